@@ -1,0 +1,429 @@
+/*
+ * gca_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 CPU oracle for the Galerkin matrix of the Laplace
+ * single-layer operator with piecewise-constant basis functions on flat
+ * triangles:
+ *
+ *     g_ij = int_{t_i} int_{t_j} g(x,y) dy dx,   g(x,y) = 1 / (4 pi |x - y|)
+ *
+ * (Section 1: the fundamental solution and Eq. G_def, with phi_i the indicator
+ * function of triangle t_i; Section 2 fixes one basis function per triangle.)
+ *
+ * Only the test-suite, the smoke check and the bench's CPU-baseline leg may
+ * load this library.  It shares no code with the HIP library.
+ *
+ * Quadrature (Section 8: one rule per Sauter case -- identical triangles,
+ * common edge, common vertex, disjoint -- citing Sauter and Sauter-Schwab):
+ *   - the case is decided combinatorially from vertex indices;
+ *   - disjoint pairs use a tensor Gauss rule on each triangle (order q_r, or
+ *     q_nr for "near-regular" pairs whose triangles contain two vertices
+ *     joined by a mesh edge);
+ *   - touching pairs use the regularising 4D transformations on [0,1]^4 of
+ *     the Sauter-Schwab method (6 / 5 / 2 subregions) with a q_s-point Gauss
+ *     rule in every one of the four variables.
+ *
+ * Reference triangle:  T = { (s1,s2) : 0 <= s2 <= s1 <= 1 },
+ * parametrisation      chi(s) = P0 + s1 (P1 - P0) + s2 (P2 - P1),
+ * surface element      |(P1 - P0) x (P2 - P1)| = 2 |t|.
+ * Collapsed Gauss rule on T of order q: s1 = u_a, s2 = u_a v_b with weight
+ * w_a w_b u_a (u, v, w: Gauss-Legendre on [0,1]).
+ *
+ * Vertex order for touching pairs (so that shared vertices come first):
+ *   identical  : the mesh order (v0, v1, v2) for both copies;
+ *   common edge: shared vertices (a, b) with a < b by vertex id, then the
+ *                third vertex of each triangle;
+ *   common vertex: the shared vertex, then the other two in cyclic mesh order.
+ * Touching and regular values are computed for (min(i,j), max(i,j)) so the
+ * matrix is symmetric by construction.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+
+enum { ORC_REG = 0, ORC_NEAR = 1, ORC_VERT = 2, ORC_EDGE = 3, ORC_IDENT = 4 };
+
+#define ORC_QMAX 32
+
+typedef struct {
+    int64_t nv, nt;
+    double *xyz;     /* nv x 3 */
+    int32_t *tri;    /* nt x 3 */
+    int64_t *vadj_ptr; /* vertex -> neighbouring vertices (mesh edges), CSR */
+    int32_t *vadj;
+    int q_r, q_nr, q_s;
+    double gr_x[ORC_QMAX], gr_w[ORC_QMAX];   /* Gauss-Legendre on [0,1], order q_r */
+    double gn_x[ORC_QMAX], gn_w[ORC_QMAX];   /* order q_nr */
+    double gs_x[ORC_QMAX], gs_w[ORC_QMAX];   /* order q_s */
+} orc_ctx;
+
+/* Gauss-Legendre rule on [0,1]: nodes are the roots t of the Legendre
+ * polynomial P_q on [-1,1], found by Newton's method with P_q and P_q'
+ * from the three-term recurrence; x = (1 + t)/2 and w = 1/((1 - t^2) P_q'(t)^2)
+ * (the usual weight 2/((1 - t^2) P_q'(t)^2) halved for the interval length).
+ * Nodes are returned in ascending order. */
+static void legendre_eval(int q, double t, double *p, double *dp)
+{
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= q; ++k) {
+        double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    /* P_q' from (t^2 - 1) P_q' = q (t P_q - P_{q-1}) */
+    *p = p1;
+    *dp = q * (t * p1 - p0) / (t * t - 1.0);
+}
+
+void orc_gauss01(int q, double *x, double *w)
+{
+    for (int i = 0; i < q; ++i) {
+        /* initial guess for the i-th largest root */
+        double t = cos(ORC_PI * (i + 0.75) / (q + 0.5));
+        double p, dp;
+        for (int it = 0; it < 100; ++it) {
+            legendre_eval(q, t, &p, &dp);
+            double dt = p / dp;
+            t -= dt;
+            if (fabs(dt) <= 1e-16 * fabs(t) + 1e-300) break;
+        }
+        legendre_eval(q, t, &p, &dp);
+        x[q - 1 - i] = 0.5 * (1.0 + t);
+        w[q - 1 - i] = 1.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+void orc_destroy(void *p)
+{
+    orc_ctx *c = (orc_ctx *)p;
+    if (!c) return;
+    free(c->xyz); free(c->tri); free(c->vadj_ptr); free(c->vadj);
+    free(c);
+}
+
+void *orc_create(int64_t nv, int64_t nt, const double *xyz, const int32_t *tri,
+                 int q_r, int q_nr, int q_s)
+{
+    if (q_r < 1 || q_nr < 1 || q_s < 1 || q_r > ORC_QMAX || q_nr > ORC_QMAX || q_s > ORC_QMAX)
+        return NULL;
+    orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    c->nv = nv; c->nt = nt;
+    c->xyz = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
+    c->tri = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)nt);
+    memcpy(c->xyz, xyz, sizeof(double) * 3 * (size_t)nv);
+    memcpy(c->tri, tri, sizeof(int32_t) * 3 * (size_t)nt);
+    c->q_r = q_r; c->q_nr = q_nr; c->q_s = q_s;
+    orc_gauss01(q_r, c->gr_x, c->gr_w);
+    orc_gauss01(q_nr, c->gn_x, c->gn_w);
+    orc_gauss01(q_s, c->gs_x, c->gs_w);
+
+    /* vertex adjacency through mesh edges: every triangle contributes its 3 edges
+     * in both directions; duplicates removed after sorting */
+    int64_t *cnt = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) cnt[tri[3 * t + k] + 1] += 2;
+    for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)cnt[nv]);
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)nv);
+    for (int64_t v = 0; v < nv; ++v) fill[v] = cnt[v];
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            int32_t a = tri[3 * t + k], b = tri[3 * t + (k + 1) % 3], d = tri[3 * t + (k + 2) % 3];
+            tmp[fill[a]++] = b;
+            tmp[fill[a]++] = d;
+        }
+    c->vadj_ptr = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    c->vadj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cnt[nv] > 0 ? cnt[nv] : 1));
+    int64_t o = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+        int64_t b = cnt[v], e = cnt[v + 1];
+        qsort(tmp + b, (size_t)(e - b), sizeof(int32_t), cmp_i32);
+        c->vadj_ptr[v] = o;
+        for (int64_t k = b; k < e; ++k)
+            if (k == b || tmp[k] != tmp[k - 1]) c->vadj[o++] = tmp[k];
+    }
+    c->vadj_ptr[nv] = o;
+    free(cnt); free(tmp); free(fill);
+    return c;
+}
+
+static int is_edge(const orc_ctx *c, int32_t a, int32_t b)
+{
+    for (int64_t k = c->vadj_ptr[a]; k < c->vadj_ptr[a + 1]; ++k)
+        if (c->vadj[k] == b) return 1;
+    return 0;
+}
+
+/* Pair class decided from vertex indices only. */
+int orc_classify(void *p, int64_t i, int64_t j)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    const int32_t *ti = c->tri + 3 * i, *tj = c->tri + 3 * j;
+    int shared = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (ti[a] == tj[b]) ++shared;
+    if (shared == 3) return ORC_IDENT;
+    if (shared == 2) return ORC_EDGE;
+    if (shared == 1) return ORC_VERT;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (is_edge(c, ti[a], tj[b])) return ORC_NEAR;
+    return ORC_REG;
+}
+
+static void vload(const orc_ctx *c, int32_t v, double *out)
+{
+    out[0] = c->xyz[3 * v]; out[1] = c->xyz[3 * v + 1]; out[2] = c->xyz[3 * v + 2];
+}
+
+/* chi(s) - P0 = s1 (P1 - P0) + s2 (P2 - P1) for a triangle given by vertices P */
+static void chi_rel(const double P[3][3], double s1, double s2, double *out)
+{
+    for (int d = 0; d < 3; ++d)
+        out[d] = s1 * (P[1][d] - P[0][d]) + s2 * (P[2][d] - P[1][d]);
+}
+
+static double surf_elem(const double P[3][3])
+{
+    double a[3], b[3];
+    for (int d = 0; d < 3; ++d) { a[d] = P[1][d] - P[0][d]; b[d] = P[2][d] - P[1][d]; }
+    double cx = a[1] * b[2] - a[2] * b[1];
+    double cy = a[2] * b[0] - a[0] * b[2];
+    double cz = a[0] * b[1] - a[1] * b[0];
+    return sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+/* Regular rule: tensor collapsed Gauss of order q on both triangles. */
+static double entry_regular(const double P[3][3], const double Q[3][3], int q,
+                            const double *gx, const double *gw)
+{
+    double Jp = surf_elem(P), Jq = surf_elem(Q);
+    double sum = 0.0;
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b) {
+            double s1 = gx[a], s2 = gx[a] * gx[b], ws = gw[a] * gw[b] * gx[a];
+            double x[3];
+            chi_rel(P, s1, s2, x);
+            for (int d = 0; d < 3; ++d) x[d] += P[0][d];
+            for (int e = 0; e < q; ++e)
+                for (int f = 0; f < q; ++f) {
+                    double u1 = gx[e], u2 = gx[e] * gx[f], wu = gw[e] * gw[f] * gx[e];
+                    double y[3];
+                    chi_rel(Q, u1, u2, y);
+                    for (int d = 0; d < 3; ++d) y[d] += Q[0][d];
+                    double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+                    sum += ws * wu / sqrt(dx * dx + dy * dy + dz * dz);
+                }
+        }
+    return sum * Jp * Jq / (4.0 * ORC_PI);
+}
+
+/* Sauter-Schwab regularising maps of [0,1]^4 onto T x T for the three touching
+ * cases.  Returns the Jacobian; (x1,x2) in the first, (y1,y2) in the second
+ * triangle's reference coordinates.  The singular set (x = y, the shared edge
+ * x2 = y2 = 0, x1 = y1, or the shared vertex x = y = 0) is mapped to the faces
+ * xi = 0 / eta1 = 0 where the Jacobian vanishes to the order that cancels the
+ * 1/|x - y| singularity. */
+static double ss_map(int kase, int region, double xi, double e1, double e2, double e3,
+                     double *x1, double *x2, double *y1, double *y2)
+{
+    if (kase == ORC_IDENT) {
+        double J = xi * xi * xi * e1 * e1 * e2;
+        switch (region) {
+        case 0: *x1 = xi; *x2 = xi * (1 - e1 + e1 * e2); *y1 = xi * (1 - e1 * e2 * e3); *y2 = xi * (1 - e1); break;
+        case 1: *x1 = xi * (1 - e1 * e2 * e3); *x2 = xi * (1 - e1); *y1 = xi; *y2 = xi * (1 - e1 + e1 * e2); break;
+        case 2: *x1 = xi; *x2 = xi * e1 * (1 - e2 + e2 * e3); *y1 = xi * (1 - e1 * e2); *y2 = xi * e1 * (1 - e2); break;
+        case 3: *x1 = xi * (1 - e1 * e2); *x2 = xi * e1 * (1 - e2); *y1 = xi; *y2 = xi * e1 * (1 - e2 + e2 * e3); break;
+        case 4: *x1 = xi * (1 - e1 * e2 * e3); *x2 = xi * e1 * (1 - e2 * e3); *y1 = xi; *y2 = xi * e1 * (1 - e2); break;
+        default: *x1 = xi; *x2 = xi * e1 * (1 - e2); *y1 = xi * (1 - e1 * e2 * e3); *y2 = xi * e1 * (1 - e2 * e3); break;
+        }
+        return J;
+    }
+    if (kase == ORC_EDGE) {
+        switch (region) {
+        case 0: *x1 = xi; *x2 = xi * e1 * e3; *y1 = xi * (1 - e1 * e2); *y2 = xi * e1 * (1 - e2);
+            return xi * xi * xi * e1 * e1;
+        case 1: *x1 = xi; *x2 = xi * e1; *y1 = xi * (1 - e1 * e2 * e3); *y2 = xi * e1 * e2 * (1 - e3); break;
+        case 2: *x1 = xi * (1 - e1 * e2); *x2 = xi * e1 * (1 - e2); *y1 = xi; *y2 = xi * e1 * e2 * e3; break;
+        case 3: *x1 = xi * (1 - e1 * e2 * e3); *x2 = xi * e1 * e2 * (1 - e3); *y1 = xi; *y2 = xi * e1; break;
+        default: *x1 = xi * (1 - e1 * e2 * e3); *x2 = xi * e1 * (1 - e2 * e3); *y1 = xi; *y2 = xi * e1 * e2; break;
+        }
+        return xi * xi * xi * e1 * e1 * e2;
+    }
+    /* common vertex */
+    if (region == 0) { *x1 = xi; *x2 = xi * e1; *y1 = xi * e2; *y2 = xi * e2 * e3; }
+    else             { *x1 = xi * e2; *x2 = xi * e2 * e3; *y1 = xi; *y2 = xi * e1; }
+    return xi * xi * xi * e2;
+}
+
+static int ss_regions(int kase) { return kase == ORC_IDENT ? 6 : (kase == ORC_EDGE ? 5 : 2); }
+
+/* Integral over T x T of a function of the two reference points, by the
+ * Sauter-Schwab maps with a q-point Gauss rule in each of the four variables.
+ * P and Q share their first vertex (edge case: first two), so
+ * chi_P(x) - chi_Q(y) = (chi_P(x) - P0) - (chi_Q(y) - Q0). */
+static double entry_touching(int kase, const double P[3][3], const double Q[3][3],
+                             int q, const double *gx, const double *gw)
+{
+    double Jp = surf_elem(P), Jq = surf_elem(Q);
+    int nreg = ss_regions(kase);
+    double sum = 0.0;
+    for (int r = 0; r < nreg; ++r)
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+                for (int e = 0; e < q; ++e)
+                    for (int f = 0; f < q; ++f) {
+                        double x1, x2, y1, y2;
+                        double jac = ss_map(kase, r, gx[a], gx[b], gx[e], gx[f], &x1, &x2, &y1, &y2);
+                        double w = gw[a] * gw[b] * gw[e] * gw[f] * jac;
+                        double X[3], Y[3];
+                        chi_rel(P, x1, x2, X);
+                        chi_rel(Q, y1, y2, Y);
+                        double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
+                        sum += w / sqrt(dx * dx + dy * dy + dz * dz);
+                    }
+    return sum * Jp * Jq / (4.0 * ORC_PI);
+}
+
+/* Moments of the Sauter-Schwab maps: sum of weights times x1^a x2^b y1^c y2^d.
+ * Equals int_T int_T x1^a x2^b y1^c y2^d exactly when the maps tile T x T. */
+double orc_ss_moment(int kase, int q, int pa, int pb, int pc, int pd)
+{
+    double gx[ORC_QMAX], gw[ORC_QMAX];
+    if (q < 1 || q > ORC_QMAX) return NAN;
+    orc_gauss01(q, gx, gw);
+    double sum = 0.0;
+    for (int r = 0; r < ss_regions(kase); ++r)
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+                for (int e = 0; e < q; ++e)
+                    for (int f = 0; f < q; ++f) {
+                        double x1, x2, y1, y2;
+                        double jac = ss_map(kase, r, gx[a], gx[b], gx[e], gx[f], &x1, &x2, &y1, &y2);
+                        sum += gw[a] * gw[b] * gw[e] * gw[f] * jac *
+                               pow(x1, pa) * pow(x2, pb) * pow(y1, pc) * pow(y2, pd);
+                    }
+    return sum;
+}
+
+/* Orders the vertices of the pair (i, j), i <= j, for the touching rules. */
+static void touching_vertices(const orc_ctx *c, int kase, int64_t i, int64_t j,
+                              double P[3][3], double Q[3][3])
+{
+    const int32_t *ti = c->tri + 3 * i, *tj = c->tri + 3 * j;
+    int32_t pi[3], pj[3];
+    if (kase == ORC_IDENT) {
+        for (int k = 0; k < 3; ++k) { pi[k] = ti[k]; pj[k] = ti[k]; }
+    } else if (kase == ORC_EDGE) {
+        int32_t sh[2]; int ns = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (ti[a] == tj[b]) sh[ns++] = ti[a];
+        int32_t lo = sh[0] < sh[1] ? sh[0] : sh[1];
+        int32_t hi = sh[0] < sh[1] ? sh[1] : sh[0];
+        int32_t oi = -1, oj = -1;
+        for (int a = 0; a < 3; ++a) if (ti[a] != lo && ti[a] != hi) oi = ti[a];
+        for (int b = 0; b < 3; ++b) if (tj[b] != lo && tj[b] != hi) oj = tj[b];
+        pi[0] = lo; pi[1] = hi; pi[2] = oi;
+        pj[0] = lo; pj[1] = hi; pj[2] = oj;
+    } else {
+        int ka = 0, kb = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (ti[a] == tj[b]) { ka = a; kb = b; }
+        for (int k = 0; k < 3; ++k) { pi[k] = ti[(ka + k) % 3]; pj[k] = tj[(kb + k) % 3]; }
+    }
+    for (int k = 0; k < 3; ++k) { vload(c, pi[k], P[k]); vload(c, pj[k], Q[k]); }
+}
+
+double orc_entry(void *p, int64_t i, int64_t j)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    if (i > j) { int64_t t = i; i = j; j = t; }
+    int kase = orc_classify(p, i, j);
+    double P[3][3], Q[3][3];
+    if (kase == ORC_IDENT || kase == ORC_EDGE || kase == ORC_VERT) {
+        touching_vertices(c, kase, i, j, P, Q);
+        return entry_touching(kase, P, Q, c->q_s, c->gs_x, c->gs_w);
+    }
+    for (int k = 0; k < 3; ++k) { vload(c, c->tri[3 * i + k], P[k]); vload(c, c->tri[3 * j + k], Q[k]); }
+    if (kase == ORC_NEAR) return entry_regular(P, Q, c->q_nr, c->gn_x, c->gn_w);
+    return entry_regular(P, Q, c->q_r, c->gr_x, c->gr_w);
+}
+
+void orc_entries(void *p, int64_t m, const int64_t *I, const int64_t *J, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < m; ++k) out[k] = orc_entry(p, I[k], J[k]);
+}
+
+void orc_classify_many(void *p, int64_t m, const int64_t *I, const int64_t *J, int32_t *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) out[k] = orc_classify(p, I[k], J[k]);
+}
+
+/* Dense G, row-major n x n (upper triangle computed, mirrored). */
+void orc_dense(void *p, double *G)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    int64_t n = c->nt;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i; j < n; ++j) {
+            double v = orc_entry(p, i, j);
+            G[i * n + j] = v;
+            G[j * n + i] = v;
+        }
+}
+
+/* y[r, :] = sum_j g_{rows[r], j} x[j, :] for the requested rows, without storing G.
+ * x is n x nrhs row-major, y is nrows x nrhs row-major. */
+void orc_matvec_rows(void *p, int64_t nrows, const int64_t *rows, const double *x,
+                     int64_t nrhs, double *y)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    int64_t n = c->nt;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        double *yr = y + r * nrhs;
+        for (int64_t k = 0; k < nrhs; ++k) yr[k] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double g = orc_entry(p, rows[r], j);
+            for (int64_t k = 0; k < nrhs; ++k) yr[k] += g * x[j * nrhs + k];
+        }
+    }
+}
+
+/* Triangle quadrature points of the collapsed rule of order q (for the
+ * Green-quadrature factor entries): pts (nt*q*q x 3), weights incl. surface
+ * element (nt*q*q). */
+void orc_triangle_points(void *p, int q, double *pts, double *wts)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    double gx[ORC_QMAX], gw[ORC_QMAX];
+    orc_gauss01(q, gx, gw);
+    for (int64_t t = 0; t < c->nt; ++t) {
+        double P[3][3];
+        for (int k = 0; k < 3; ++k) vload(c, c->tri[3 * t + k], P[k]);
+        double J = surf_elem(P);
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b) {
+                int64_t o = (t * q + a) * q + b;
+                double x[3];
+                chi_rel(P, gx[a], gx[a] * gx[b], x);
+                for (int d = 0; d < 3; ++d) pts[3 * o + d] = x[d] + P[0][d];
+                wts[o] = gw[a] * gw[b] * gx[a] * J;
+            }
+    }
+}
