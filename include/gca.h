@@ -1,0 +1,187 @@
+/*
+ * gca.h -- C-ABI of libgca: Green cross approximation (GCA) H^2-matrix
+ * compression of the Laplace single-layer Galerkin matrix on MI355X (gfx950).
+ *
+ * The operator (Section 1, Eq. G_def) is
+ *     g_ij = int_{t_i} int_{t_j} 1 / (4 pi |x - y|) dy dx
+ * for piecewise-constant basis functions, one per flat triangle t_i
+ * (Section 2).  The library builds the GCA-H^2 approximation of Sections 2-4
+ * (Green quadrature on the boundary of a box around each cluster, cross
+ * approximation of the resulting thin factor, nested bases with transfer
+ * matrices) and applies it with coupling and nearfield blocks recomputed on
+ * the fly by triangle-pair quadrature (one list per Sauter case, Section 8).
+ *
+ * Conventions for every call:
+ *   - return value: GCA_OK (0) or a negative gca_status; nothing throws or
+ *     aborts; gca_last_error() gives a thread-local message for the last
+ *     non-OK status;
+ *   - arguments are validated before any device work is queued;
+ *   - "host" pointers are plain CPU memory, read during the call only;
+ *     "device" pointers are HIP device memory owned by the caller;
+ *   - stream arguments are hipStream_t (NULL = the default stream); calls that
+ *     take a stream queue their work on it and return without synchronising
+ *     unless stated otherwise;
+ *   - vectors are indexed in the ORIGINAL triangle order of the mesh.
+ */
+#ifndef GCA_H
+#define GCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GCA_OK = 0,
+    GCA_EINVAL = -1,     /* invalid argument */
+    GCA_ENOMEM = -2,     /* device or host allocation failed */
+    GCA_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+    GCA_EMESH = -4,      /* invalid mesh (index out of range, zero-area or
+                            duplicate triangle, non-manifold edge) */
+    GCA_ENOTSPD = -5,    /* CG met a non-positive curvature p^T G p <= 0 */
+    GCA_ENOCONV = -6,    /* iterative solve did not reach its tolerance */
+    GCA_EINTERNAL = -7
+} gca_status;
+
+/* Arithmetic of a matrix-vector product.
+ * GCA_FP64 : every quadrature, transfer and accumulation in FP64.
+ * GCA_MIXED: regular-pair quadrature (nearfield and coupling), kernel
+ *            evaluation and basis transfers in FP32 with FP32 accumulation;
+ *            touching pairs (Sauter-Schwab) in FP64. */
+typedef enum { GCA_FP64 = 0, GCA_MIXED = 1 } gca_precision;
+
+/* Flat triangle mesh (host memory).  xyz: nv x 3 vertex coordinates (FP64,
+ * row-major); tri: nt x 3 vertex indices (0-based, row-major).  Copied during
+ * the call that receives it. */
+typedef struct {
+    int64_t nv, nt;
+    const double *xyz;
+    const int32_t *tri;
+} gca_mesh;
+
+/* Parameters of the approximation (Section 2: admissibility parameter eta;
+ * Green quadrature order; Section 3: cross-approximation tolerance). */
+typedef struct {
+    double eta;          /* admissible iff max(diam t, diam s) <= 2 eta dist(t, s) */
+    double eps;          /* ACA stop: ||R||_F <= eps ||A||_F                       */
+    double omega_scale;  /* omega = cluster box enlarged by omega_scale*diam/eta per side */
+    int32_t green_m;     /* Gauss points per direction on each box face (k = 6 m^2) */
+    int32_t q_A;         /* triangle rule order of the Green factor A            */
+    int32_t q_r;         /* regular pair rule order (per triangle: q_r^2 points)  */
+    int32_t q_nr;        /* order for near-regular pairs (vertices joined by an edge) */
+    int32_t q_s;         /* Sauter-Schwab order (>= 2) for touching pairs         */
+    int32_t reserved[3]; /* must be zero */
+} gca_params;
+
+typedef struct gca_tree_s *gca_tree;   /* host object; gca_tree_destroy */
+typedef struct gca_h2_s *gca_h2;       /* owns its device memory; gca_destroy */
+
+/* Statistics of a built approximation (gca_stats). */
+typedef struct {
+    int64_t n, nv, n_clusters, n_leaves, depth;
+    int64_t n_far, n_near;               /* admissible / inadmissible leaf blocks, both orders */
+    int64_t n_far_sym, n_near_sym;       /* the halves computed (t < s, t <= s) */
+    int64_t n_ident, n_edge, n_vert, n_nearreg;   /* pair lists (unordered) */
+    int64_t coupling_entries;            /* sum over t < s admissible of |t~| |s~| */
+    int64_t near_pairs;                  /* ordered regular pairs in near blocks, computed once per unordered pair */
+    int64_t rank_min, rank_max;
+    double rank_mean;
+    int64_t basis_bytes_fp64;            /* leaf V + transfers E, FP64 */
+    double build_ms;                     /* wall time of gca_build (host + device, synchronised) */
+    double phase_ms[8];                  /* last matvec, per phase (HIP events):
+                                            0 forward, 1 coupling, 2 backward+gather,
+                                            3 nearfield regular, 4 near-regular list,
+                                            5 touching, 6 permute in, 7 total */
+} gca_stats_t;
+
+/* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
+ * q_r 3, q_nr 5, q_s 4. */
+void gca_params_default(gca_params *p);
+
+/* Cluster tree over the triangles (Section 4's binary subdivision of index
+ * sets into disjoint sons).  Splitting rule: the bounding box of the triangle
+ * centroids ((v0+v1)+v2)/3 is cut along its longest axis (lowest axis on
+ * ties) at the median: triangles sorted by that centroid coordinate (ties by
+ * original id), the first floor(#/2) form the first son.  Clusters with at
+ * most leaf_size triangles are leaves.  Each cluster has the axis-parallel
+ * bounding box of all vertices of its triangles (Section 2).  Host only.
+ * Errors: GCA_EINVAL (null pointers, leaf_size < 1), GCA_EMESH. */
+gca_status gca_tree_build(const gca_mesh *mesh, int32_t leaf_size, gca_tree *out);
+
+/* Sizes of a tree: number of clusters (pre-order numbering, root 0) and depth. */
+gca_status gca_tree_info(gca_tree t, int64_t *n_clusters, int64_t *depth);
+
+/* Copies the tree to host arrays (any pointer may be NULL):
+ * perm[nt]            cluster order -> original triangle id;
+ * nodes[5*nc]         begin, end, son0, son1, level (sons -1 for leaves);
+ * boxes[7*nc]         lo xyz, hi xyz, diam. */
+gca_status gca_tree_export(gca_tree t, int32_t *perm, int32_t *nodes, double *boxes);
+
+void gca_tree_destroy(gca_tree t);
+
+/* Block partition of I x I for admissibility parameter eta (Section 2):
+ * admissible iff dist(t, s) > 0 and max(diam t, diam s) <= 2 eta dist(t, s)
+ * (axis-parallel boxes); otherwise split every non-leaf member, and keep
+ * inadmissible pairs of leaves as nearfield blocks.  Returns the symmetric
+ * halves: admissible blocks with t < s and inadmissible leaf blocks with
+ * t <= s (each stands for itself and its transpose).  Host only.
+ * far / near: host arrays of 2 x capacity int32 (t[0..n), s[0..n)), or NULL
+ * to query the counts; n_far / n_near receive the counts.  If a capacity is
+ * too small nothing is written to that array and GCA_EINVAL is returned. */
+gca_status gca_block_tree(gca_tree t, double eta, int64_t far_capacity, int32_t *far, int64_t *n_far,
+                          int64_t near_capacity, int32_t *near, int64_t *n_near);
+
+/* Builds the GCA-H^2 approximation (Sections 2-4, Section 8's three tasks):
+ * block tree by admissibility, Green points per cluster, the factor A of
+ * Section 2 at the leaves and at the sons' pivots for every parent,
+ * full-pivot cross approximation (FP64) giving tau~, leaf bases V and
+ * transfer matrices E, and the per-case pair lists for the nearfield.
+ * The mesh must be the one the tree was built from.  Synchronises `stream`
+ * before returning (one small read-back per tree level).
+ * Errors: GCA_EINVAL (parameters), GCA_EMESH, GCA_ENOMEM, GCA_EHIP. */
+gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p,
+                     void *stream, gca_h2 *out);
+
+/* y = G~ x (Section 4's H^2 representation applied by forward transform,
+ * coupling with entries G|t~ x s~ recomputed, backward transform, and
+ * nearfield blocks G|t^ x s^ recomputed).  x, y: device, FP64, nt x nrhs,
+ * column-major with leading dimension ld >= nt; y is overwritten; x and y
+ * must not overlap.  precision: gca_precision.
+ * Errors: GCA_EINVAL (null handle or pointers, nrhs < 1, ld < nt, aliasing,
+ * unknown precision), GCA_EHIP. */
+gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t ld,
+                     int32_t precision, void *stream);
+
+/* Galerkin entries g_{I[k], J[k]} (Eq. G_def) for m pairs, computed by the
+ * same device quadrature the matrix-vector product uses (the pair's Sauter
+ * case decides the rule).  I, J: device int32 original triangle ids;
+ * out: device FP64, m values.  Errors: GCA_EINVAL, GCA_EHIP. */
+gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m,
+                       double *out, int32_t precision, void *stream);
+
+/* Copies the nested basis to host arrays for inspection (any may be NULL):
+ * ranks[nc]                   |tau~| per cluster (pre-order numbering);
+ * pivots[sum ranks]           original triangle ids of tau~, clusters in
+ *                             pre-order, each in pivot order;
+ * basis[sum over leaves |tau^| * rank + sum over non-root clusters rank(son) *
+ *       rank(parent)]        leaf V (rows in cluster order, row-major) then
+ *                             transfer matrices E (row-major), clusters in
+ *                             pre-order.  Synchronises the device. */
+gca_status gca_basis_export(gca_h2 h, int32_t *ranks, int32_t *pivots, double *basis);
+
+/* Sizes for gca_basis_export: total pivots and total basis entries. */
+gca_status gca_basis_sizes(gca_h2 h, int64_t *n_pivots, int64_t *n_basis);
+
+gca_status gca_stats(gca_h2 h, gca_stats_t *out);
+
+void gca_destroy(gca_h2 h);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char *gca_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCA_H */

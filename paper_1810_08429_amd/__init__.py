@@ -1,0 +1,246 @@
+"""Python binding of libgca (argument marshalling only; every step of the
+compression and of the matrix-vector product runs in the HIP library).
+
+    import paper_1810_08429_amd as gca
+    tree = gca.Tree(verts, tris, leaf=64)
+    H = gca.H2(verts, tris, tree, gca.Params(eta=2.0, eps=1e-4))
+    y = H.matvec(x)                       # x: torch cuda float64, original order
+    y = H.matvec(x, precision=gca.MIXED)
+
+PyTorch supplies device memory (tensors) and the stream
+(torch.cuda.current_stream()).  The library must be built first
+(python -m paper_1810_08429_amd.build); importing never falls back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgca.so")
+
+FP64, MIXED = 0, 1
+STATUS = {0: "GCA_OK", -1: "GCA_EINVAL", -2: "GCA_ENOMEM", -3: "GCA_EHIP", -4: "GCA_EMESH",
+          -5: "GCA_ENOTSPD", -6: "GCA_ENOCONV", -7: "GCA_EINTERNAL"}
+
+EXPORTED = [
+    "gca_params_default", "gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_tree_destroy",
+    "gca_block_tree",
+    "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
+    "gca_destroy", "gca_last_error",
+]
+
+
+class Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("nt", ctypes.c_int64),
+                ("xyz", ctypes.c_void_p), ("tri", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("eps", ctypes.c_double), ("omega_scale", ctypes.c_double),
+                ("green_m", ctypes.c_int32), ("q_A", ctypes.c_int32), ("q_r", ctypes.c_int32),
+                ("q_nr", ctypes.c_int32), ("q_s", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "n", "nv", "n_clusters", "n_leaves", "depth", "n_far", "n_near", "n_far_sym", "n_near_sym",
+        "n_ident", "n_edge", "n_vert", "n_nearreg", "coupling_entries", "near_pairs", "rank_min",
+        "rank_max")] + [("rank_mean", ctypes.c_double), ("basis_bytes_fp64", ctypes.c_int64),
+                        ("build_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 8)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libgca.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1810_08429_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.gca_params_default.argtypes = [P]
+    L.gca_params_default.restype = None
+    L.gca_tree_build.argtypes = [P, I32, P]
+    L.gca_tree_info.argtypes = [P, P, P]
+    L.gca_tree_export.argtypes = [P, P, P, P]
+    L.gca_block_tree.argtypes = [P, D, I64, P, P, I64, P, P]
+    L.gca_tree_destroy.argtypes = [P]
+    L.gca_tree_destroy.restype = None
+    L.gca_build.argtypes = [P, P, P, P, P]
+    L.h2_matvec.argtypes = [P, P, P, I64, I64, I32, P]
+    L.gca_entries.argtypes = [P, P, P, I64, P, I32, P]
+    L.gca_basis_sizes.argtypes = [P, P, P]
+    L.gca_basis_export.argtypes = [P, P, P, P]
+    L.gca_stats.argtypes = [P, P]
+    L.gca_destroy.argtypes = [P]
+    L.gca_destroy.restype = None
+    L.gca_last_error.argtypes = []
+    L.gca_last_error.restype = ctypes.c_char_p
+    for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
+                 "h2_matvec",
+                 "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != 0:
+        raise Error(code, lib().gca_last_error().decode())
+
+
+@dataclass
+class Params:
+    eta: float = 2.0
+    eps: float = 1e-6
+    omega_scale: float = 0.25
+    green_m: int = 3
+    q_A: int = 3
+    q_r: int = 3
+    q_nr: int = 5
+    q_s: int = 4
+
+    def _c(self):
+        p = _Params()
+        p.eta, p.eps, p.omega_scale = self.eta, self.eps, self.omega_scale
+        p.green_m, p.q_A, p.q_r, p.q_nr, p.q_s = self.green_m, self.q_A, self.q_r, self.q_nr, self.q_s
+        return p
+
+
+class _MeshArrays:
+    def __init__(self, verts, tris):
+        self.xyz = np.ascontiguousarray(verts, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tris, dtype=np.int32)
+        self.c = _Mesh(self.xyz.shape[0], self.tri.shape[0], self.xyz.ctypes.data, self.tri.ctypes.data)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Tree:
+    """Cluster tree (gca_tree_build); host only."""
+
+    def __init__(self, verts, tris, leaf=64):
+        self._m = _MeshArrays(verts, tris)
+        self.h = ctypes.c_void_p()
+        _check(lib().gca_tree_build(ctypes.byref(self._m.c), int(leaf), ctypes.byref(self.h)))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().gca_tree_destroy(self.h)
+            self.h = None
+
+    def export(self):
+        nc, depth = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gca_tree_info(self.h, ctypes.byref(nc), ctypes.byref(depth)))
+        perm = np.zeros(self._m.tri.shape[0], dtype=np.int32)
+        nodes = np.zeros((nc.value, 5), dtype=np.int32)
+        boxes = np.zeros((nc.value, 7))
+        _check(lib().gca_tree_export(self.h, perm.ctypes.data, nodes.ctypes.data, boxes.ctypes.data))
+        return perm, nodes, boxes
+
+
+    def blocks(self, eta):
+        """Admissible (t < s) and inadmissible leaf (t <= s) blocks as (k, 2) arrays."""
+        nf, nn = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gca_block_tree(self.h, float(eta), 0, None, ctypes.byref(nf), 0, None, ctypes.byref(nn)))
+        far = np.zeros(2 * max(nf.value, 1), dtype=np.int32)
+        near = np.zeros(2 * max(nn.value, 1), dtype=np.int32)
+        _check(lib().gca_block_tree(self.h, float(eta), nf.value, far.ctypes.data, ctypes.byref(nf),
+                                    nn.value, near.ctypes.data, ctypes.byref(nn)))
+        far = np.stack([far[:nf.value], far[nf.value:2 * nf.value]], axis=1)
+        near = np.stack([near[:nn.value], near[nn.value:2 * nn.value]], axis=1)
+        return far, near
+
+
+class H2:
+    """GCA-H^2 approximation (gca_build) on the current HIP device."""
+
+    def __init__(self, verts, tris, tree: Tree, params: Params = None, stream=None):
+        self._m = _MeshArrays(verts, tris)
+        self.params = params or Params()
+        self.n = self._m.tri.shape[0]
+        self.h = ctypes.c_void_p()
+        p = self.params._c()
+        _check(lib().gca_build(ctypes.byref(self._m.c), tree.h, ctypes.byref(p), _stream_ptr(stream),
+                               ctypes.byref(self.h)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gca_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def matvec_into(self, x, y, precision=FP64, stream=None):
+        """y = G~ x for torch cuda float64 tensors (n,) or (n, nrhs) column-major
+        (x.T contiguous); raw call of h2_matvec."""
+        import torch
+        assert x.dtype == torch.float64 and y.dtype == torch.float64 and x.is_cuda and y.is_cuda
+        if x.dim() == 1:
+            nrhs, ld = 1, x.shape[0]
+        else:
+            nrhs, ld = x.shape[1], x.stride(1)
+            assert x.stride(0) == 1 and y.stride(0) == 1 and y.stride(1) == ld
+        _check(lib().h2_matvec(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                               nrhs, ld, int(precision), _stream_ptr(stream)))
+        return y
+
+    def matvec(self, x, precision=FP64, stream=None):
+        import torch
+        if x.dim() == 1:
+            xx = x.contiguous()
+            y = torch.empty_like(xx)
+        else:
+            xx = x.t().contiguous().t()
+            y = torch.empty_like(xx.t()).t()
+        return self.matvec_into(xx, y, precision, stream)
+
+    def entries(self, I, J, precision=FP64, stream=None):
+        import torch
+        I = torch.as_tensor(I, dtype=torch.int32).cuda().contiguous()
+        J = torch.as_tensor(J, dtype=torch.int32).cuda().contiguous()
+        out = torch.empty(I.shape[0], dtype=torch.float64, device=I.device)
+        _check(lib().gca_entries(self.h, ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                                 I.shape[0], ctypes.c_void_p(out.data_ptr()), int(precision),
+                                 _stream_ptr(stream)))
+        return out
+
+    def basis(self):
+        """ranks per cluster, pivots (original ids, per cluster in pivot order),
+        leaf V and transfer E entries (flat, see include/gca.h)."""
+        npv, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gca_basis_sizes(self.h, ctypes.byref(npv), ctypes.byref(nb)))
+        st = self.stats()
+        ranks = np.zeros(st["n_clusters"], dtype=np.int32)
+        piv = np.zeros(npv.value, dtype=np.int32)
+        basis = np.zeros(nb.value)
+        _check(lib().gca_basis_export(self.h, ranks.ctypes.data, piv.ctypes.data, basis.ctypes.data))
+        return ranks, piv, basis
+
+    def stats(self):
+        s = _Stats()
+        _check(lib().gca_stats(self.h, ctypes.byref(s)))
+        out = {k: getattr(s, k) for k, _ in _Stats._fields_ if k != "phase_ms"}
+        out["phase_ms"] = list(s.phase_ms)
+        return out

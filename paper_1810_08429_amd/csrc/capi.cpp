@@ -1,0 +1,818 @@
+// C-ABI of libgca (include/gca.h): argument checks, device memory, the
+// level-wise basis construction (Sections 2-4) and the matrix-vector product.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <unordered_set>
+
+#include "gca_internal.h"
+
+using namespace gca;
+
+namespace {
+
+template <typename T>
+gca_status dalloc(gca_h2_s *h, T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess)
+        return set_error(GCA_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                         " bytes failed: " + hipGetErrorString(e));
+    h->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return GCA_OK;
+}
+
+template <typename T>
+gca_status upload(T *dst, const std::vector<T> &src, hipStream_t s)
+{
+    if (src.empty()) return GCA_OK;
+    GCA_HIP_TRY(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+    return GCA_OK;
+}
+
+template <typename T>
+gca_status upload_new(gca_h2_s *h, T **dst, const std::vector<T> &src, hipStream_t s)
+{
+    GCA_TRY(dalloc(h, dst, src.size()));
+    return upload(*dst, src, s);
+}
+
+void free_all(gca_h2_s *h)
+{
+    for (void *p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+    if (h->events)
+        for (auto &e : h->ev) (void)hipEventDestroy(e);
+    h->events = false;
+}
+
+gca_status check_params(const gca_params *p)
+{
+    if (!p) return set_error(GCA_EINVAL, "params is NULL");
+    if (!(p->eta > 0) || !std::isfinite(p->eta)) return set_error(GCA_EINVAL, "eta must be positive and finite");
+    if (!(p->eps >= 0) || !(p->eps < 1)) return set_error(GCA_EINVAL, "eps must be in [0, 1)");
+    if (!(p->omega_scale > 0) || !std::isfinite(p->omega_scale))
+        return set_error(GCA_EINVAL, "omega_scale must be positive and finite");
+    if (p->green_m < 1 || p->green_m > 6) return set_error(GCA_EINVAL, "green_m must be in [1, 6]");
+    if (p->q_A < 1 || p->q_A > 6) return set_error(GCA_EINVAL, "q_A must be in [1, 6]");
+    if (p->q_r < 1 || p->q_r > 6) return set_error(GCA_EINVAL, "q_r must be in [1, 6]");
+    if (p->q_nr < 1 || p->q_nr > 7) return set_error(GCA_EINVAL, "q_nr must be in [1, 7]");
+    if (p->q_s < 2 || p->q_s > 32) return set_error(GCA_EINVAL, "q_s must be in [2, 32]");
+    if (p->reserved[0] || p->reserved[1] || p->reserved[2])
+        return set_error(GCA_EINVAL, "reserved fields must be zero");
+    return GCA_OK;
+}
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Basis construction, one tree level at a time from the leaves to the root.
+gca_status build_basis(gca_h2_s *h, hipStream_t s)
+{
+    const gca_params &p = h->prm;
+    const int k = 6 * p.green_m * p.green_m, cols = 2 * k;
+    const int PA = p.q_A * p.q_A;
+    const auto &nodes = h->tree.nodes;
+    const int nc = (int)h->nc;
+    std::vector<std::vector<int32_t>> piv(nc);   // pivot positions per cluster
+    h->rank.assign(nc, 0);
+
+    struct LevelWs {
+        double *V = nullptr;                // rows x min(rows, cols) per cluster
+        std::vector<int64_t> u_off;         // per batch entry
+        std::vector<int32_t> rows, rstride;
+    };
+    std::vector<LevelWs> lw(h->level_clusters.size());
+    std::vector<void *> temp;
+    auto tmp_alloc = [&](void **q, size_t bytes) -> gca_status {
+        *q = nullptr;
+        hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 8));
+        if (e != hipSuccess) return set_error(GCA_ENOMEM, "hipMalloc (basis workspace) failed");
+        temp.push_back(*q);
+        return GCA_OK;
+    };
+    auto cleanup = [&]() {
+        for (void *q : temp) (void)hipFree(q);
+        temp.clear();
+    };
+    gca_status st = GCA_OK;
+    for (int l = (int)h->level_clusters.size() - 1; l >= 0 && st == GCA_OK; --l) {
+        const auto &cl = h->level_clusters[l];
+        const int nb = (int)cl.size();
+        if (!nb) continue;
+        std::vector<int32_t> row_tri, row_cl, rows(nb);
+        std::vector<int64_t> row_out, a_off(nb), u_off(nb);
+        int64_t atot = 0, utot = 0;
+        for (int bi = 0; bi < nb; ++bi) {
+            const Node &nd = nodes[cl[bi]];
+            std::vector<int32_t> rr;
+            if (nd.son[0] < 0) {
+                for (int32_t q = nd.begin; q < nd.end; ++q) rr.push_back(q);
+            } else {
+                rr = piv[nd.son[0]];
+                rr.insert(rr.end(), piv[nd.son[1]].begin(), piv[nd.son[1]].end());
+            }
+            rows[bi] = (int32_t)rr.size();
+            a_off[bi] = atot;
+            u_off[bi] = utot;
+            for (size_t r = 0; r < rr.size(); ++r) {
+                row_tri.push_back(rr[r]);
+                row_cl.push_back(cl[bi]);
+                row_out.push_back(atot + (int64_t)r * cols);
+            }
+            atot += (int64_t)rr.size() * cols;
+            utot += (int64_t)rr.size() * std::min<int64_t>((int64_t)rr.size(), cols);
+            piv[cl[bi]] = rr;   // row list for now; replaced by the pivots below
+        }
+        double *dA, *dU, *dV;
+        int32_t *d_rows, *d_rowtri, *d_rowcl, *d_rank, *d_pivl;
+        int64_t *d_rowout, *d_aoff, *d_uoff;
+        if ((st = tmp_alloc((void **)&dA, atot * sizeof(double))) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&dU, utot * sizeof(double))) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&dV, utot * sizeof(double))) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_rows, nb * 4)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_rowtri, row_tri.size() * 4)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_rowcl, row_cl.size() * 4)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_rank, nb * 4)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_pivl, (size_t)nb * cols * 4)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_rowout, row_out.size() * 8)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_aoff, nb * 8)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_uoff, nb * 8)) != GCA_OK) break;
+        if ((st = upload(d_rows, rows, s)) != GCA_OK) break;
+        if ((st = upload(d_rowtri, row_tri, s)) != GCA_OK) break;
+        if ((st = upload(d_rowcl, row_cl, s)) != GCA_OK) break;
+        if ((st = upload(d_rowout, row_out, s)) != GCA_OK) break;
+        if ((st = upload(d_aoff, a_off, s)) != GCA_OK) break;
+        if ((st = upload(d_uoff, u_off, s)) != GCA_OK) break;
+        hipError_t e = launch_green_A(h->d_qA, PA, h->d_box, d_rowtri, d_rowcl, d_rowout, (int64_t)row_tri.size(),
+                                      p.green_m, h->gl_x, h->gl_w, p.eta, p.omega_scale, dA, s);
+        if (e == hipSuccess)
+            e = launch_aca(dA, dU, dV, d_aoff, d_uoff, d_rows, cols, nb, p.eps, cols, d_rank, d_pivl, s);
+        if (e != hipSuccess) {
+            st = set_error(GCA_EHIP, std::string("basis kernels: ") + hipGetErrorString(e));
+            break;
+        }
+        std::vector<int32_t> rk(nb), pl((size_t)nb * cols);
+        e = hipMemcpyAsync(rk.data(), d_rank, nb * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(pl.data(), d_pivl, (size_t)nb * cols * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            st = set_error(GCA_EHIP, std::string("basis read-back: ") + hipGetErrorString(e));
+            break;
+        }
+        for (int bi = 0; bi < nb; ++bi) {
+            const int c = cl[bi];
+            std::vector<int32_t> rr = piv[c], pv(rk[bi]);
+            for (int r = 0; r < rk[bi]; ++r) pv[r] = rr[pl[(size_t)bi * cols + r]];
+            piv[c] = pv;
+            h->rank[c] = rk[bi];
+        }
+        lw[l].V = dV;
+        lw[l].u_off = u_off;
+        lw[l].rows = rows;
+        lw[l].rstride.resize(nb);
+        for (int bi = 0; bi < nb; ++bi) lw[l].rstride[bi] = std::min(rows[bi], cols);
+    }
+    if (st != GCA_OK) {
+        cleanup();
+        return st;
+    }
+    // final layouts: pivots, leaf V, transfers E
+    h->piv_off.assign(nc, 0);
+    h->pivots.clear();
+    for (int c = 0; c < nc; ++c) {
+        h->piv_off[c] = (int64_t)h->pivots.size();
+        h->pivots.insert(h->pivots.end(), piv[c].begin(), piv[c].end());
+    }
+    h->n_piv = (int64_t)h->pivots.size();
+    h->v_off.assign(nc, 0);
+    h->e_off.assign(nc, 0);
+    int64_t nv_ = 0, ne_ = 0;
+    for (int c = 0; c < nc; ++c) {
+        const Node &nd = nodes[c];
+        if (nd.son[0] < 0) {
+            h->v_off[c] = nv_;
+            nv_ += (int64_t)(nd.end - nd.begin) * h->rank[c];
+        }
+        if (nd.parent >= 0) {
+            h->e_off[c] = ne_;
+            ne_ += (int64_t)h->rank[c] * h->rank[nd.parent];
+        }
+    }
+    h->n_v = nv_;
+    h->n_e = ne_;
+    h->max_rank = 0;
+    for (int c = 0; c < nc; ++c) h->max_rank = std::max(h->max_rank, h->rank[c]);
+    GCA_TRY(dalloc(h, &h->d_V, nv_));
+    GCA_TRY(dalloc(h, &h->d_Vt, nv_));
+    GCA_TRY(dalloc(h, &h->d_Vf, nv_));
+    GCA_TRY(dalloc(h, &h->d_Vtf, nv_));
+    GCA_TRY(dalloc(h, &h->d_E, ne_));
+    GCA_TRY(dalloc(h, &h->d_Et, ne_));
+    GCA_TRY(dalloc(h, &h->d_Ef, ne_));
+    GCA_TRY(dalloc(h, &h->d_Etf, ne_));
+    for (int l = 0; l < (int)h->level_clusters.size(); ++l) {
+        const auto &cl = h->level_clusters[l];
+        std::vector<int64_t> vjobs, ejobs;   // 6 per job
+        for (size_t bi = 0; bi < cl.size(); ++bi) {
+            const int c = cl[bi];
+            const Node &nd = nodes[c];
+            const int64_t so = lw[l].u_off[bi], ld = lw[l].rstride[bi];
+            if (nd.son[0] < 0) {
+                vjobs.insert(vjobs.end(), {so, ld, 0, (int64_t)lw[l].rows[bi], (int64_t)h->rank[c], h->v_off[c]});
+            } else {
+                const int s0 = nd.son[0], s1 = nd.son[1];
+                ejobs.insert(ejobs.end(), {so, ld, 0, (int64_t)h->rank[s0], (int64_t)h->rank[c], h->e_off[s0]});
+                ejobs.insert(ejobs.end(),
+                             {so, ld, (int64_t)h->rank[s0], (int64_t)h->rank[s1], (int64_t)h->rank[c], h->e_off[s1]});
+            }
+        }
+        for (int which = 0; which < 2; ++which) {
+            const auto &jobs = which ? ejobs : vjobs;
+            if (jobs.empty()) continue;
+            int64_t *dj;
+            if ((st = tmp_alloc((void **)&dj, jobs.size() * 8)) != GCA_OK) break;
+            if ((st = upload(dj, jobs, s)) != GCA_OK) break;
+            hipError_t e = which ? launch_copy_jobs(dj, (int)(jobs.size() / 6), lw[l].V, h->d_E, h->d_Et, h->d_Ef,
+                                                    h->d_Etf, s)
+                                 : launch_copy_jobs(dj, (int)(jobs.size() / 6), lw[l].V, h->d_V, h->d_Vt, h->d_Vf,
+                                                    h->d_Vtf, s);
+            if (e != hipSuccess) {
+                st = set_error(GCA_EHIP, std::string("basis copy: ") + hipGetErrorString(e));
+                break;
+            }
+        }
+        if (st != GCA_OK) break;
+    }
+    if (st == GCA_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = set_error(GCA_EHIP, std::string("basis copy sync: ") + hipGetErrorString(e));
+    }
+    cleanup();
+    return st;
+}
+
+gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, hipStream_t s, gca_h2_s *h)
+{
+    const double t0 = now_ms();
+    GCA_TRY(check_params(p));
+    h->prm = *p;
+    GCA_TRY(mesh_copy_validate(mesh, h->mesh));
+    if (tree->nt != h->mesh.nt || tree->nv != h->mesh.nv || tree->mesh_xyz != h->mesh.xyz ||
+        tree->mesh_tri != h->mesh.tri)
+        return set_error(GCA_EINVAL, "the tree was built from a different mesh");
+    if (tree->leaf > 64) return set_error(GCA_EINVAL, "leaf_size must be <= 64 (one wavefront per leaf row set)");
+    h->tree = *tree;
+    h->n = h->mesh.nt;
+    h->nv = h->mesh.nv;
+    h->nc = (int64_t)h->tree.nodes.size();
+    h->depth = h->tree.depth;
+    const auto &nodes = h->tree.nodes;
+    const int nc = (int)h->nc;
+    const int64_t n = h->n;
+
+    GCA_TRY(build_adjacency(h->mesh, h->adj));
+    GCA_TRY(build_pair_lists(h->mesh, h->adj, h->tree, h->pl));
+    block_tree(h->tree, p->eta, h->blk);
+
+    // clusters by level, leaves, leaf of each position
+    h->level_clusters.assign(h->depth + 1, {});
+    h->leaves.clear();
+    std::vector<int32_t> leaf_of(n, -1), leaf_index(nc, -1);
+    h->max_leaf = 0;
+    for (int c = 0; c < nc; ++c) {
+        h->level_clusters[nodes[c].level].push_back(c);
+        if (nodes[c].son[0] < 0) {
+            leaf_index[c] = (int32_t)h->leaves.size();
+            h->leaves.push_back(c);
+            for (int32_t q = nodes[c].begin; q < nodes[c].end; ++q) leaf_of[q] = c;
+            h->max_leaf = std::max(h->max_leaf, nodes[c].end - nodes[c].begin);
+        }
+    }
+    // every non-regular pair must lie in an inadmissible leaf block
+    {
+        std::unordered_set<int64_t> nb;
+        for (size_t b = 0; b < h->blk.near_t.size(); ++b)
+            nb.insert((int64_t)h->blk.near_t[b] * nc + h->blk.near_s[b]);
+        for (size_t q = 0; q < h->pl.a.size(); ++q) {
+            int32_t la = leaf_of[h->pl.a[q]], lb = leaf_of[h->pl.b[q]];
+            if (!nb.count((int64_t)std::min(la, lb) * nc + std::max(la, lb)))
+                return set_error(GCA_EINVAL, "a touching or near-regular pair lies in an admissible block "
+                                             "(eta too large for this mesh)");
+        }
+    }
+
+    gauss_legendre01(p->green_m, h->gl_x, h->gl_w);
+    gauss_legendre01(p->q_s, h->gs_x, h->gs_w);
+
+    // geometry
+    std::vector<int32_t> tv(3 * n), perm(n), iperm(n);
+    for (int64_t q = 0; q < n; ++q) {
+        int32_t t = h->tree.perm[q];
+        perm[q] = t;
+        iperm[t] = (int32_t)q;
+        for (int k = 0; k < 3; ++k) tv[3 * q + k] = h->mesh.tri[3 * (int64_t)t + k];
+    }
+    GCA_TRY(upload_new(h, &h->d_xyz, h->mesh.xyz, s));
+    GCA_TRY(upload_new(h, &h->d_tv, tv, s));
+    GCA_TRY(upload_new(h, &h->d_perm, perm, s));
+    GCA_TRY(upload_new(h, &h->d_iperm, iperm, s));
+    std::vector<double> box(8 * (size_t)nc);
+    std::vector<int32_t> nodearr(5 * (size_t)nc);
+    for (int c = 0; c < nc; ++c) {
+        for (int d = 0; d < 3; ++d) {
+            box[8 * c + d] = nodes[c].lo[d];
+            box[8 * c + 3 + d] = nodes[c].hi[d];
+        }
+        box[8 * c + 6] = nodes[c].diam;
+        nodearr[5 * c + 0] = nodes[c].begin;
+        nodearr[5 * c + 1] = nodes[c].end;
+        nodearr[5 * c + 2] = nodes[c].son[0];
+        nodearr[5 * c + 3] = nodes[c].son[1];
+        nodearr[5 * c + 4] = nodes[c].parent;
+    }
+    GCA_TRY(upload_new(h, &h->d_box, box, s));
+    GCA_TRY(upload_new(h, &h->d_node, nodearr, s));
+    GCA_TRY(upload_new(h, &h->d_leaves, h->leaves, s));
+    h->d_level_clusters.assign(h->level_clusters.size(), nullptr);
+    for (size_t l = 0; l < h->level_clusters.size(); ++l)
+        GCA_TRY(upload_new(h, &h->d_level_clusters[l], h->level_clusters[l], s));
+
+    // triangle quadrature points
+    auto tri_pts = [&](int q, double **out) -> gca_status {
+        double gx[32], gw[32];
+        gauss_legendre01(q, gx, gw);
+        GCA_TRY(dalloc(h, out, (size_t)n * q * q * 4));
+        GCA_HIP_TRY(launch_tri_points(h->d_xyz, h->d_tv, n, q, gx, gw, *out, s));
+        return GCA_OK;
+    };
+    GCA_TRY(tri_pts(p->q_r, &h->d_qr));
+    GCA_TRY(tri_pts(p->q_nr, &h->d_qnr));
+    if (p->q_A == p->q_r)
+        h->d_qA = h->d_qr;
+    else
+        GCA_TRY(tri_pts(p->q_A, &h->d_qA));
+
+    // nested basis (Green factor + cross approximation, level by level)
+    GCA_TRY(build_basis(h, s));
+    GCA_TRY(upload_new(h, &h->d_piv, h->pivots, s));
+    GCA_TRY(upload_new(h, &h->d_piv_off, h->piv_off, s));
+    GCA_TRY(upload_new(h, &h->d_rank, h->rank, s));
+    GCA_TRY(upload_new(h, &h->d_v_off, h->v_off, s));
+    GCA_TRY(upload_new(h, &h->d_e_off, h->e_off, s));
+
+    // coupling blocks and their partial slots
+    {
+        const size_t nb = h->blk.far_t.size();
+        std::vector<int32_t> far(2 * nb);
+        std::vector<int64_t> slot(2 * nb);
+        std::vector<std::vector<int64_t>> per(nc);
+        int64_t off = 0;
+        for (size_t b = 0; b < nb; ++b) {
+            const int t = h->blk.far_t[b], u = h->blk.far_s[b];
+            far[b] = t;
+            far[nb + b] = u;
+            slot[2 * b] = off;
+            per[t].push_back(off);
+            off += h->rank[t];
+            slot[2 * b + 1] = off;
+            per[u].push_back(off);
+            off += h->rank[u];
+        }
+        h->n_cslot_total = off;
+        std::vector<int64_t> ptr(nc + 1, 0), flat;
+        for (int c = 0; c < nc; ++c) {
+            ptr[c + 1] = ptr[c] + (int64_t)per[c].size();
+            flat.insert(flat.end(), per[c].begin(), per[c].end());
+        }
+        GCA_TRY(upload_new(h, &h->d_far, far, s));
+        GCA_TRY(upload_new(h, &h->d_far_slot, slot, s));
+        GCA_TRY(upload_new(h, &h->d_cslot_ptr, ptr, s));
+        GCA_TRY(upload_new(h, &h->d_cslot, flat, s));
+    }
+    // near blocks and their partial slots
+    {
+        const size_t nb = h->blk.near_t.size();
+        std::vector<int32_t> nearv(2 * nb);
+        std::vector<int64_t> slot(2 * nb);
+        std::vector<std::vector<int64_t>> per(h->leaves.size());
+        int64_t off = 0;
+        for (size_t b = 0; b < nb; ++b) {
+            const int t = h->blk.near_t[b], u = h->blk.near_s[b];
+            nearv[b] = t;
+            nearv[nb + b] = u;
+            slot[2 * b] = off;
+            per[leaf_index[t]].push_back(off);
+            off += nodes[t].end - nodes[t].begin;
+            if (t != u) {
+                slot[2 * b + 1] = off;
+                per[leaf_index[u]].push_back(off);
+                off += nodes[u].end - nodes[u].begin;
+            } else {
+                slot[2 * b + 1] = -1;
+            }
+        }
+        h->n_nslot_total = off;
+        std::vector<int64_t> ptr(h->leaves.size() + 1, 0), flat;
+        for (size_t c = 0; c < h->leaves.size(); ++c) {
+            ptr[c + 1] = ptr[c] + (int64_t)per[c].size();
+            flat.insert(flat.end(), per[c].begin(), per[c].end());
+        }
+        GCA_TRY(upload_new(h, &h->d_near, nearv, s));
+        GCA_TRY(upload_new(h, &h->d_near_slot, slot, s));
+        GCA_TRY(upload_new(h, &h->d_nslot_ptr, ptr, s));
+        GCA_TRY(upload_new(h, &h->d_nslot, flat, s));
+    }
+    // pair lists
+    GCA_TRY(upload_new(h, &h->d_pa, h->pl.a, s));
+    GCA_TRY(upload_new(h, &h->d_pb, h->pl.b, s));
+    GCA_TRY(upload_new(h, &h->d_pcode, h->pl.code, s));
+    GCA_TRY(upload_new(h, &h->d_prow_ptr, h->pl.row_ptr, s));
+    GCA_TRY(upload_new(h, &h->d_prow_other, h->pl.row_other, s));
+    GCA_TRY(upload_new(h, &h->d_prow_pair, h->pl.row_pair, s));
+    const int64_t npairs = (int64_t)h->pl.a.size();
+    GCA_TRY(dalloc(h, &h->d_pval, npairs));
+    GCA_TRY(dalloc(h, &h->d_pvalf, h->pl.off[4] - h->pl.off[3]));
+
+    // workspaces of the matrix-vector product
+    GCA_TRY(dalloc(h, &h->d_xp, n));
+    GCA_TRY(dalloc(h, &h->d_xpf, n));
+    GCA_TRY(dalloc(h, &h->d_xh, h->n_piv));
+    GCA_TRY(dalloc(h, &h->d_yh, h->n_piv));
+    GCA_TRY(dalloc(h, &h->d_xhf, h->n_piv));
+    GCA_TRY(dalloc(h, &h->d_yhf, h->n_piv));
+    GCA_TRY(dalloc(h, &h->d_cpart, h->n_cslot_total));
+    GCA_TRY(dalloc(h, &h->d_cpartf, h->n_cslot_total));
+    GCA_TRY(dalloc(h, &h->d_npart, h->n_nslot_total));
+    GCA_TRY(dalloc(h, &h->d_npartf, h->n_nslot_total));
+    for (auto &e : h->ev) GCA_HIP_TRY(hipEventCreate(&e));
+    h->events = true;
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+
+    // statistics
+    gca_stats_t &st = h->st;
+    st = gca_stats_t{};
+    st.n = n;
+    st.nv = h->nv;
+    st.n_clusters = nc;
+    st.n_leaves = (int64_t)h->leaves.size();
+    st.depth = h->depth;
+    st.n_far = h->blk.n_far_full;
+    st.n_near = h->blk.n_near_full;
+    st.n_far_sym = (int64_t)h->blk.far_t.size();
+    st.n_near_sym = (int64_t)h->blk.near_t.size();
+    st.n_ident = h->pl.off[1] - h->pl.off[0];
+    st.n_edge = h->pl.off[2] - h->pl.off[1];
+    st.n_vert = h->pl.off[3] - h->pl.off[2];
+    st.n_nearreg = h->pl.off[4] - h->pl.off[3];
+    for (size_t b = 0; b < h->blk.far_t.size(); ++b)
+        st.coupling_entries += (int64_t)h->rank[h->blk.far_t[b]] * h->rank[h->blk.far_s[b]];
+    for (size_t b = 0; b < h->blk.near_t.size(); ++b) {
+        const Node &a = nodes[h->blk.near_t[b]], &c = nodes[h->blk.near_s[b]];
+        st.near_pairs += (int64_t)(a.end - a.begin) * (c.end - c.begin);
+    }
+    st.rank_min = INT64_MAX;
+    double rs = 0;
+    for (int c = 0; c < nc; ++c) {
+        st.rank_min = std::min<int64_t>(st.rank_min, h->rank[c]);
+        st.rank_max = std::max<int64_t>(st.rank_max, h->rank[c]);
+        rs += h->rank[c];
+    }
+    st.rank_mean = rs / nc;
+    st.basis_bytes_fp64 = 8 * (h->n_v + h->n_e);
+    st.build_ms = now_ms() - t0;
+    return GCA_OK;
+}
+
+template <typename T>
+hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipStream_t s)
+{
+    const bool f32 = std::is_same<T, float>::value;
+    T *xp = f32 ? (T *)h->d_xpf : (T *)h->d_xp;
+    T *xh = f32 ? (T *)h->d_xhf : (T *)h->d_xh;
+    T *yh = f32 ? (T *)h->d_yhf : (T *)h->d_yh;
+    T *cpart = f32 ? (T *)h->d_cpartf : (T *)h->d_cpart;
+    T *npart = f32 ? (T *)h->d_npartf : (T *)h->d_npart;
+    T *pnr = f32 ? (T *)h->d_pvalf : (T *)(h->d_pval + h->pl.off[3]);
+    hipError_t e;
+    if (h->events) (void)hipEventRecord(h->ev[0], s);
+    if ((e = launch_permute_in<T>(x, h->d_perm, h->n, xp, f32 ? h->d_xp : nullptr, s)) != hipSuccess) return e;
+    if (h->events) (void)hipEventRecord(h->ev[1], s);
+    if ((e = launch_forward<T>(h, xp, xh, s)) != hipSuccess) return e;
+    if (h->events) (void)hipEventRecord(h->ev[2], s);
+    if ((e = launch_coupling<T>(h, xh, cpart, yh, s)) != hipSuccess) return e;
+    if (h->events) (void)hipEventRecord(h->ev[3], s);
+    if ((e = launch_backward<T>(h, yh, s)) != hipSuccess) return e;
+    if (h->events) (void)hipEventRecord(h->ev[4], s);
+    if ((e = launch_near<T>(h, xp, npart, s)) != hipSuccess) return e;
+    if (h->events) (void)hipEventRecord(h->ev[5], s);
+    if (first) {
+        if ((e = launch_nearreg<T>(h, pnr, s)) != hipSuccess) return e;
+    }
+    if (h->events) (void)hipEventRecord(h->ev[6], s);
+    if (first) {
+        if ((e = launch_touching(h, h->d_pval, s)) != hipSuccess) return e;
+    }
+    if (h->events) (void)hipEventRecord(h->ev[7], s);
+    if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, pnr, y, s)) != hipSuccess) return e;
+    if (h->events) {
+        (void)hipEventRecord(h->ev[8], s);
+        h->timed = true;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gca_params_default(gca_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eta = 2.0;
+    p->eps = 1e-6;
+    p->omega_scale = 0.25;
+    p->green_m = 3;
+    p->q_A = 3;
+    p->q_r = 3;
+    p->q_nr = 5;
+    p->q_s = 4;
+}
+
+const char *gca_last_error(void) { return last_error_cstr(); }
+
+gca_status gca_tree_build(const gca_mesh *mesh, int32_t leaf_size, gca_tree *out)
+{
+    clear_error();
+    if (!out) return set_error(GCA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (leaf_size < 1) return set_error(GCA_EINVAL, "leaf_size must be >= 1");
+    Mesh m;
+    GCA_TRY(mesh_copy_validate(mesh, m));
+    auto *t = new (std::nothrow) gca_tree_s;
+    if (!t) return set_error(GCA_ENOMEM, "out of host memory");
+    gca_status st = tree_build(m, leaf_size, *t);
+    if (st != GCA_OK) {
+        delete t;
+        return st;
+    }
+    *out = t;
+    return GCA_OK;
+}
+
+gca_status gca_tree_info(gca_tree t, int64_t *n_clusters, int64_t *depth)
+{
+    clear_error();
+    if (!t) return set_error(GCA_EINVAL, "tree is NULL");
+    if (n_clusters) *n_clusters = (int64_t)t->nodes.size();
+    if (depth) *depth = t->depth;
+    return GCA_OK;
+}
+
+gca_status gca_tree_export(gca_tree t, int32_t *perm, int32_t *nodes, double *boxes)
+{
+    clear_error();
+    if (!t) return set_error(GCA_EINVAL, "tree is NULL");
+    if (perm) std::copy(t->perm.begin(), t->perm.end(), perm);
+    for (size_t c = 0; c < t->nodes.size(); ++c) {
+        const Node &nd = t->nodes[c];
+        if (nodes) {
+            nodes[5 * c + 0] = nd.begin;
+            nodes[5 * c + 1] = nd.end;
+            nodes[5 * c + 2] = nd.son[0];
+            nodes[5 * c + 3] = nd.son[1];
+            nodes[5 * c + 4] = nd.level;
+        }
+        if (boxes) {
+            for (int d = 0; d < 3; ++d) {
+                boxes[7 * c + d] = nd.lo[d];
+                boxes[7 * c + 3 + d] = nd.hi[d];
+            }
+            boxes[7 * c + 6] = nd.diam;
+        }
+    }
+    return GCA_OK;
+}
+
+void gca_tree_destroy(gca_tree t) { delete t; }
+
+gca_status gca_block_tree(gca_tree t, double eta, int64_t far_capacity, int32_t *far, int64_t *n_far,
+                          int64_t near_capacity, int32_t *near, int64_t *n_near)
+{
+    clear_error();
+    if (!t) return set_error(GCA_EINVAL, "tree is NULL");
+    if (!(eta > 0) || !std::isfinite(eta)) return set_error(GCA_EINVAL, "eta must be positive and finite");
+    Blocks b;
+    block_tree(*t, eta, b);
+    const int64_t nf = (int64_t)b.far_t.size(), nn = (int64_t)b.near_t.size();
+    if (n_far) *n_far = nf;
+    if (n_near) *n_near = nn;
+    gca_status st = GCA_OK;
+    if (far) {
+        if (far_capacity < nf) {
+            st = set_error(GCA_EINVAL, "far capacity too small");
+        } else {
+            std::copy(b.far_t.begin(), b.far_t.end(), far);
+            std::copy(b.far_s.begin(), b.far_s.end(), far + nf);
+        }
+    }
+    if (near) {
+        if (near_capacity < nn) {
+            st = set_error(GCA_EINVAL, "near capacity too small");
+        } else {
+            std::copy(b.near_t.begin(), b.near_t.end(), near);
+            std::copy(b.near_s.begin(), b.near_s.end(), near + nn);
+        }
+    }
+    return st;
+}
+
+gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p, void *stream, gca_h2 *out)
+{
+    clear_error();
+    if (!out) return set_error(GCA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!tree) return set_error(GCA_EINVAL, "tree is NULL");
+    auto *h = new (std::nothrow) gca_h2_s;
+    if (!h) return set_error(GCA_ENOMEM, "out of host memory");
+    gca_status st = build_impl(mesh, tree, p, (hipStream_t)stream, h);
+    if (st != GCA_OK) {
+        free_all(h);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return GCA_OK;
+}
+
+gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t ld, int32_t precision,
+                     void *stream)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (!x || !y) return set_error(GCA_EINVAL, "x or y is NULL");
+    if (nrhs < 1) return set_error(GCA_EINVAL, "nrhs must be >= 1");
+    if (ld < h->n) return set_error(GCA_EINVAL, "ld must be >= n");
+    if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
+    {
+        const char *xb = (const char *)x, *xe = (const char *)(x + (nrhs - 1) * ld + h->n);
+        const char *yb = (const char *)y, *ye = (const char *)(y + (nrhs - 1) * ld + h->n);
+        if (xb < ye && yb < xe) return set_error(GCA_EINVAL, "x and y overlap");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t k = 0; k < nrhs; ++k) {
+        hipError_t e = precision == GCA_FP64 ? matvec_one<double>(h, x + k * ld, y + k * ld, k == 0, s)
+                                             : matvec_one<float>(h, x + k * ld, y + k * ld, k == 0, s);
+        if (e != hipSuccess) return set_error(GCA_EHIP, std::string("matvec launch: ") + hipGetErrorString(e));
+    }
+    return GCA_OK;
+}
+
+gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, double *out, int32_t precision,
+                       void *stream)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (m < 0) return set_error(GCA_EINVAL, "m must be >= 0");
+    if (m == 0) return GCA_OK;
+    if (!I || !J || !out) return set_error(GCA_EINVAL, "NULL pointer");
+    if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> hi(m), hj(m);
+    GCA_HIP_TRY(hipMemcpyAsync(hi.data(), I, m * 4, hipMemcpyDeviceToHost, s));
+    GCA_HIP_TRY(hipMemcpyAsync(hj.data(), J, m * 4, hipMemcpyDeviceToHost, s));
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> cls[5], codes[5], idx[5], fa[5], fb[5];
+    std::vector<int32_t> iperm(h->n);
+    for (int64_t q = 0; q < h->n; ++q) iperm[h->tree.perm[q]] = (int32_t)q;
+    for (int64_t k = 0; k < m; ++k) {
+        int32_t a = hi[k], b = hj[k];
+        if (a < 0 || a >= h->n || b < 0 || b >= h->n) return set_error(GCA_EINVAL, "triangle id out of range");
+        if (a > b) std::swap(a, b);
+        int32_t code = 0;
+        int kind = classify_pair(h->mesh, h->adj, a, b, &code);
+        int slot = kind;   // 0 ident, 1 edge, 2 vert, 3 near-regular, 4 regular
+        fa[slot].push_back(iperm[a]);
+        fb[slot].push_back(iperm[b]);
+        codes[slot].push_back(code);
+        idx[slot].push_back((int32_t)k);
+    }
+    std::vector<int32_t> pa, pb, pc, order;
+    EntryJobs j{};
+    for (int c = 0; c < 5; ++c) {
+        j.off[c] = (int64_t)pa.size();
+        pa.insert(pa.end(), fa[c].begin(), fa[c].end());
+        pb.insert(pb.end(), fb[c].begin(), fb[c].end());
+        pc.insert(pc.end(), codes[c].begin(), codes[c].end());
+        order.insert(order.end(), idx[c].begin(), idx[c].end());
+    }
+    j.off[5] = (int64_t)pa.size();
+    int32_t *dpa = nullptr, *dpb = nullptr, *dpc = nullptr;
+    double *t64 = nullptr;
+    float *t32 = nullptr;
+    gca_status st = GCA_OK;
+    auto fail = [&](hipError_t e, const char *what) {
+        st = set_error(GCA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    hipError_t e = hipMalloc(&dpa, m * 4);
+    if (e == hipSuccess) e = hipMalloc(&dpb, m * 4);
+    if (e == hipSuccess) e = hipMalloc(&dpc, m * 4);
+    if (e == hipSuccess) e = hipMalloc(&t64, m * 8);
+    if (e == hipSuccess) e = hipMalloc(&t32, m * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(dpa, pa.data(), m * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dpb, pb.data(), m * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dpc, pc.data(), m * 4, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) fail(e, "entries setup");
+    std::vector<double> r64(m);
+    std::vector<float> r32(m);
+    if (st == GCA_OK) {
+        j.pa = dpa;
+        j.pb = dpb;
+        j.code = dpc;
+        e = launch_entry_jobs(h, j, t64, t32, precision, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(r64.data(), t64, m * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(r32.data(), t32, m * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) fail(e, "entries kernels");
+    }
+    if (st == GCA_OK) {
+        std::vector<double> res(m);
+        for (int64_t q = 0; q < m; ++q) {
+            bool f32 = precision == GCA_MIXED && q >= j.off[3];
+            res[order[q]] = f32 ? (double)r32[q] : r64[q];
+        }
+        e = hipMemcpyAsync(out, res.data(), m * 8, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) fail(e, "entries result");
+    }
+    (void)hipFree(dpa);
+    (void)hipFree(dpb);
+    (void)hipFree(dpc);
+    (void)hipFree(t64);
+    (void)hipFree(t32);
+    return st;
+}
+
+gca_status gca_basis_sizes(gca_h2 h, int64_t *n_pivots, int64_t *n_basis)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (n_pivots) *n_pivots = h->n_piv;
+    if (n_basis) *n_basis = h->n_v + h->n_e;
+    return GCA_OK;
+}
+
+gca_status gca_basis_export(gca_h2 h, int32_t *ranks, int32_t *pivots, double *basis)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (ranks) std::copy(h->rank.begin(), h->rank.end(), ranks);
+    if (pivots)
+        for (int64_t q = 0; q < h->n_piv; ++q) pivots[q] = h->tree.perm[h->pivots[q]];
+    if (basis) {
+        GCA_HIP_TRY(hipDeviceSynchronize());
+        if (h->n_v) GCA_HIP_TRY(hipMemcpy(basis, h->d_V, h->n_v * 8, hipMemcpyDeviceToHost));
+        if (h->n_e) GCA_HIP_TRY(hipMemcpy(basis + h->n_v, h->d_E, h->n_e * 8, hipMemcpyDeviceToHost));
+    }
+    return GCA_OK;
+}
+
+gca_status gca_stats(gca_h2 h, gca_stats_t *out)
+{
+    clear_error();
+    if (!h || !out) return set_error(GCA_EINVAL, "NULL argument");
+    *out = h->st;
+    if (h->events && h->timed) {
+        // the phase events of the last matrix-vector product
+        GCA_HIP_TRY(hipEventSynchronize(h->ev[8]));
+        float ms;
+        const int idx[8][2] = {{1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {0, 1}, {0, 8}};
+        for (int k = 0; k < 8; ++k) {
+            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[idx[k][0]], h->ev[idx[k][1]]));
+            out->phase_ms[k] = ms;
+        }
+        GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[7], h->ev[8]));   // gather belongs to phase 2
+        out->phase_ms[2] += ms;
+    }
+    return GCA_OK;
+}
+
+void gca_destroy(gca_h2 h)
+{
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    free_all(h);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// Internal declarations of libgca (host structures, device buffers, kernel
+// launchers).  Not part of the public interface (include/gca.h).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gca.h"
+
+namespace gca {
+
+// ---------------------------------------------------------------- errors --
+gca_status set_error(gca_status s, const std::string &msg);
+void clear_error();
+
+#define GCA_HIP_TRY(expr)                                                        \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess)                                                    \
+            return ::gca::set_error(GCA_EHIP, std::string(#expr " failed: ") +   \
+                                                  hipGetErrorString(e_));        \
+    } while (0)
+
+#define GCA_TRY(expr)                                                            \
+    do {                                                                         \
+        gca_status s_ = (expr);                                                  \
+        if (s_ != GCA_OK) return s_;                                             \
+    } while (0)
+
+// --------------------------------------------------------------- geometry --
+struct Mesh {
+    int64_t nv = 0, nt = 0;
+    std::vector<double> xyz;    // nv x 3
+    std::vector<int32_t> tri;   // nt x 3
+};
+
+gca_status mesh_copy_validate(const gca_mesh *m, Mesh &out);
+
+// Adjacency needed for the pair classes (Section 8: identical / common edge /
+// common vertex / disjoint, plus "near-regular" disjoint pairs that contain a
+// mesh edge between them).
+struct Adjacency {
+    std::vector<int64_t> vt_ptr;   // vertex -> triangles
+    std::vector<int32_t> vt;
+    std::vector<int64_t> vv_ptr;   // vertex -> vertices joined by an edge
+    std::vector<int32_t> vv;
+};
+gca_status build_adjacency(const Mesh &m, Adjacency &adj);
+
+// -------------------------------------------------------------- clustering --
+struct Node {
+    int32_t begin, end, son[2], parent, level;
+    double lo[3], hi[3], diam;
+};
+
+}  // namespace gca
+
+struct gca_tree_s {
+    int64_t nt = 0, nv = 0;
+    int32_t leaf = 0;
+    std::vector<int32_t> perm;      // cluster position -> original triangle id
+    std::vector<gca::Node> nodes;   // pre-order
+    int32_t depth = 0;
+    std::vector<double> mesh_xyz;   // the mesh the tree was built from (to check gca_build)
+    std::vector<int32_t> mesh_tri;
+};
+
+namespace gca {
+
+gca_status tree_build(const Mesh &m, int32_t leaf, gca_tree_s &t);
+
+// Block partition (Section 2 admissibility) as symmetric halves.
+struct Blocks {
+    std::vector<int32_t> far_t, far_s;     // admissible, t < s
+    std::vector<int32_t> near_t, near_s;   // inadmissible leaf pairs, t <= s
+    int64_t n_far_full = 0, n_near_full = 0;
+};
+void block_tree(const gca_tree_s &t, double eta, Blocks &b);
+
+// Pairs that the regular rule does not handle, in cluster positions.
+// kind: 0 identical, 1 common edge, 2 common vertex, 3 near-regular.
+// The first triangle is the one with the smaller ORIGINAL id; for touching
+// pairs `code` packs the vertex orders (see kernels) of first | second << 4.
+struct PairLists {
+    std::vector<int32_t> a, b, code;   // positions of first / second, order code
+    int64_t off[5] = {0, 0, 0, 0, 0};  // class ranges in the concatenated list
+    // row CSR over positions: for position i, entries (other position, pair id)
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> row_other, row_pair;
+};
+gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t,
+                            PairLists &pl);
+int classify_pair(const Mesh &m, const Adjacency &adj, int32_t i, int32_t j, int32_t *code);
+const char *last_error_cstr();
+
+// Gauss-Legendre on [0,1] (ascending nodes).
+void gauss_legendre01(int q, double *x, double *w);
+
+// ------------------------------------------------------------- device data --
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace gca
+
+struct gca_h2_s {
+    gca_params prm{};
+    int64_t n = 0, nv = 0, nc = 0;
+    int32_t depth = 0;
+    gca_tree_s tree;                 // private copy
+    gca::Mesh mesh;
+    gca::Adjacency adj;
+    gca::Blocks blk;
+    gca::PairLists pl;
+
+    // host copies of the basis structure
+    std::vector<int32_t> rank;       // per cluster
+    std::vector<int64_t> piv_off;    // per cluster offset into pivots / xhat
+    std::vector<int32_t> pivots;     // positions, per cluster in pivot order
+    std::vector<int64_t> v_off;      // leaf V offsets (entries)
+    std::vector<int64_t> e_off;      // E offsets for non-root clusters (entries)
+    int64_t n_piv = 0, n_v = 0, n_e = 0;
+
+    // device memory (all owned)
+    std::vector<void *> allocs;
+    double *d_xyz = nullptr;         // nv x 3
+    int32_t *d_tv = nullptr;         // n x 3 vertex ids, cluster order
+    int32_t *d_perm = nullptr;       // position -> original id
+    int32_t *d_iperm = nullptr;      // original id -> position
+    double *d_qr = nullptr;          // n x Pr x 4 (x, y, z, w*J), regular rule
+    double *d_qnr = nullptr;         // n x Pnr x 4, near-regular rule
+    double *d_qA = nullptr;          // n x PA x 4 (may alias d_qr)
+    double *d_box = nullptr;         // nc x 8: lo, hi, diam, 0
+
+    int32_t *d_piv = nullptr;        // pivot positions
+    int64_t *d_piv_off = nullptr;    // nc
+    int32_t *d_rank = nullptr;       // nc
+    double *d_V = nullptr;           // leaf bases, row-major |t^| x r   (FP64)
+    double *d_Vt = nullptr;          // leaf bases, column-major        (FP64)
+    double *d_E = nullptr;           // transfers, row-major r' x r     (FP64)
+    double *d_Et = nullptr;          // transfers, column-major         (FP64)
+    float *d_Vf = nullptr, *d_Vtf = nullptr, *d_Ef = nullptr, *d_Etf = nullptr;
+    int64_t *d_v_off = nullptr, *d_e_off = nullptr;
+
+    // clusters by level (for the level-wise transfer launches)
+    std::vector<std::vector<int32_t>> level_clusters;
+    std::vector<int32_t *> d_level_clusters;
+    std::vector<int32_t> leaves;
+    int32_t *d_leaves = nullptr;
+    int32_t *d_node = nullptr;       // nc x 5: begin, end, son0, son1, parent
+
+    // coupling blocks (t < s)
+    int32_t *d_far = nullptr;        // 2 x n_far_sym
+    int64_t *d_far_slot = nullptr;   // 2 x n_far_sym: partial-slot offsets (row, col)
+    int64_t *d_cslot_ptr = nullptr;  // nc + 1: per cluster CSR of partial slots
+    int64_t *d_cslot = nullptr;
+    int64_t n_cslot_total = 0;       // size of the coupling partial buffer
+    int32_t max_rank = 0;
+
+    // near blocks (t <= s)
+    int32_t *d_near = nullptr;       // 2 x n_near_sym
+    int64_t *d_near_slot = nullptr;  // 2 x n_near_sym (col slot -1 on diagonal)
+    int64_t *d_nslot_ptr = nullptr;  // n_leaves + 1 (leaf index order)
+    int64_t *d_nslot = nullptr;
+    int64_t n_nslot_total = 0;
+    int32_t max_leaf = 0;
+
+    // pair lists
+    int32_t *d_pa = nullptr, *d_pb = nullptr, *d_pcode = nullptr;
+    int64_t *d_prow_ptr = nullptr;
+    int32_t *d_prow_other = nullptr, *d_prow_pair = nullptr;
+    double *d_pval = nullptr;        // pair values (FP64)
+    float *d_pvalf = nullptr;        // near-regular values in the mixed path
+
+    // per-matvec workspaces
+    double *d_xp = nullptr;          // permuted input (FP64) n
+    float *d_xpf = nullptr;
+    double *d_xh = nullptr, *d_yh = nullptr;       // n_piv
+    float *d_xhf = nullptr, *d_yhf = nullptr;
+    double *d_cpart = nullptr;       // coupling partials
+    float *d_cpartf = nullptr;
+    double *d_npart = nullptr;       // near partials
+    float *d_npartf = nullptr;
+
+    // Green rule (m points per direction on a face)
+    double gl_x[32], gl_w[32];
+    double gs_x[32], gs_w[32];       // Sauter-Schwab order q_s
+
+    hipEvent_t ev[9] = {};
+    bool events = false;
+    bool timed = false;              // phase events hold a recorded product
+    gca_stats_t st{};
+};
+
+namespace gca {
+
+// ---------------------------------------------------------- kernel launchers --
+// All launchers enqueue on `s` and return the launch status.
+hipError_t launch_tri_points(const double *xyz, const int32_t *tv, int64_t n, int q, const double *gx,
+                             const double *gw, double *out, hipStream_t s);
+hipError_t launch_green_A(const double *qA, int PA, const double *box, const int32_t *row_tri,
+                          const int32_t *row_cl, const int64_t *row_out, int64_t nrows, int m, const double *glx,
+                          const double *glw, double eta, double omega_scale, double *A, hipStream_t s);
+hipError_t launch_aca(double *R, double *U, double *V, const int64_t *a_off, const int64_t *u_off,
+                      const int32_t *rows, int cols, int nbatch, double eps, int maxr_cap, int32_t *rank_out,
+                      int32_t *piv_out, hipStream_t s);
+hipError_t launch_copy_jobs(const int64_t *jobs, int njobs, const double *src, double *dr, double *dc, float *fr,
+                            float *fc, hipStream_t s);
+
+template <typename T>
+hipError_t launch_permute_in(const double *x, const int32_t *perm, int64_t n, T *xp, double *xp64, hipStream_t s);
+template <typename T>
+hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s);
+template <typename T>
+hipError_t launch_coupling(gca_h2_s *h, const T *xh, T *cpart, T *yh, hipStream_t s);
+template <typename T>
+hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s);
+template <typename T>
+hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s);
+hipError_t launch_touching(gca_h2_s *h, double *pval, hipStream_t s);
+template <typename T>
+hipError_t launch_nearreg(gca_h2_s *h, T *pval, hipStream_t s);
+template <typename T>
+hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *yh, const T *npart,
+                         const T *pval_nr, double *y, hipStream_t s);
+
+// Entries for pairs sorted by class on the host (gca_entries).
+struct EntryJobs {
+    const int32_t *pa, *pb, *code;
+    int64_t off[6];   // 0 identical, 1 edge, 2 vertex, 3 near-regular, 4 regular, 5 end
+};
+hipError_t launch_entry_jobs(gca_h2_s *h, const EntryJobs &j, double *tmp64, float *tmp32, int precision,
+                             hipStream_t s);
+
+}  // namespace gca

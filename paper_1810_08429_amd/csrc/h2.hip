@@ -1,0 +1,206 @@
+// The four phases of the H^2 matrix-vector product (Section 4's
+// representation G|t^ x s^ ~ V_t G|t~ x s~ V_s^* with nested bases
+// V_t = [V_t1 E_t1; V_t2 E_t2]):
+//   forward : xh_t = V_t^T x|t^ at leaves, xh_t = sum_sons E_t'^T xh_t' above;
+//   coupling: yh_t = sum_s G|t~ x s~ xh_s (entries recomputed, quad.hip);
+//   backward: yh_t' += E_t' yh_t downwards, y|t^ += V_t yh_t at the leaves;
+//   nearfield: y|t^ += G|t^ x s^ x|s^ (quad.hip) plus the per-case pair lists.
+// Transfers are level-wise launches, one workgroup per cluster; all sums are
+// in a fixed order (no atomics), so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "gca_internal.h"
+
+namespace gca {
+
+template <typename T>
+__global__ void k_permute_in(const double *x, const int32_t *perm, int64_t n, T *xp, double *xp64)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = x[perm[i]];
+    xp[i] = (T)v;
+    if (xp64) xp64[i] = v;
+}
+
+template <typename T>
+hipError_t launch_permute_in(const double *x, const int32_t *perm, int64_t n, T *xp, double *xp64, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_permute_in<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, perm, n, xp, xp64);
+    return hipGetLastError();
+}
+template hipError_t launch_permute_in<float>(const double *, const int32_t *, int64_t, float *, double *,
+                                             hipStream_t);
+template hipError_t launch_permute_in<double>(const double *, const int32_t *, int64_t, double *, double *,
+                                              hipStream_t);
+
+// forward transform for the clusters of one level (workgroup per cluster,
+// thread per basis column k).  Leaf: V row-major |t^| x r.  Parent: E_son
+// row-major r_son x r.
+template <typename T>
+__global__ void __launch_bounds__(128) k_forward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
+                                                 const int64_t *piv_off, const int64_t *v_off, const int64_t *e_off,
+                                                 const T *V, const T *E, const T *xp, T *xh)
+{
+    const int c = clusters[blockIdx.x];
+    const int r = rank[c];
+    const int s0 = node[5 * c + 2], s1 = node[5 * c + 3];
+    T *out = xh + piv_off[c];
+    if (s0 < 0) {
+        const int b = node[5 * c], nr = node[5 * c + 1] - b;
+        const T *Vc = V + v_off[c];
+        for (int k = threadIdx.x; k < r; k += blockDim.x) {
+            T acc = 0;
+            for (int i = 0; i < nr; ++i) acc += Vc[(int64_t)i * r + k] * xp[b + i];
+            out[k] = acc;
+        }
+    } else {
+        for (int k = threadIdx.x; k < r; k += blockDim.x) {
+            T acc = 0;
+            for (int sidx = 0; sidx < 2; ++sidx) {
+                const int so = sidx ? s1 : s0;
+                const int rs = rank[so];
+                const T *Es = E + e_off[so];
+                const T *xs = xh + piv_off[so];
+                for (int j = 0; j < rs; ++j) acc += Es[(int64_t)j * r + k] * xs[j];
+            }
+            out[k] = acc;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s)
+{
+    const T *V = std::is_same<T, float>::value ? (const T *)h->d_Vf : (const T *)h->d_V;
+    const T *E = std::is_same<T, float>::value ? (const T *)h->d_Ef : (const T *)h->d_E;
+    for (int l = (int)h->level_clusters.size() - 1; l >= 0; --l) {
+        int nc = (int)h->level_clusters[l].size();
+        if (!nc) continue;
+        hipLaunchKernelGGL(k_forward<T>, dim3(nc), dim3(128), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
+                           h->d_piv_off, h->d_v_off, h->d_e_off, V, E, xp, xh);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+template hipError_t launch_forward<float>(gca_h2_s *, const float *, float *, hipStream_t);
+template hipError_t launch_forward<double>(gca_h2_s *, const double *, double *, hipStream_t);
+
+// yh_c = sum over the cluster's partial slots (fixed order)
+template <typename T>
+__global__ void k_coupling_reduce(const int32_t *rank, const int64_t *piv_off, const int64_t *slot_ptr,
+                                  const int64_t *slots, const T *part, T *yh)
+{
+    const int c = blockIdx.x;
+    const int r = rank[c];
+    const int64_t b = slot_ptr[c], e = slot_ptr[c + 1];
+    for (int k = threadIdx.x; k < r; k += blockDim.x) {
+        T acc = 0;
+        for (int64_t q = b; q < e; ++q) acc += part[slots[q] + k];
+        yh[piv_off[c] + k] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s);
+
+template <typename T>
+hipError_t launch_coupling(gca_h2_s *h, const T *xh, T *cpart, T *yh, hipStream_t s)
+{
+    hipError_t e = launch_far_blocks<T>(h, xh, cpart, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_coupling_reduce<T>, dim3((unsigned)h->nc), dim3(128), 0, s, h->d_rank, h->d_piv_off,
+                       h->d_cslot_ptr, h->d_cslot, cpart, yh);
+    return hipGetLastError();
+}
+template hipError_t launch_coupling<float>(gca_h2_s *, const float *, float *, float *, hipStream_t);
+template hipError_t launch_coupling<double>(gca_h2_s *, const double *, double *, double *, hipStream_t);
+
+// backward transform for the clusters of one level below the root:
+// yh_c += E_c yh_parent (E_c column-major: Et[k * r_c + j])
+template <typename T>
+__global__ void __launch_bounds__(128) k_backward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
+                                                  const int64_t *piv_off, const int64_t *e_off, const T *Et, T *yh)
+{
+    const int c = clusters[blockIdx.x];
+    const int par = node[5 * c + 4];
+    const int rc = rank[c], rp = rank[par];
+    const T *Ec = Et + e_off[c];
+    const T *yp = yh + piv_off[par];
+    T *yc = yh + piv_off[c];
+    for (int j = threadIdx.x; j < rc; j += blockDim.x) {
+        T acc = yc[j];
+        for (int k = 0; k < rp; ++k) acc += Ec[(int64_t)k * rc + j] * yp[k];
+        yc[j] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s)
+{
+    const T *Et = std::is_same<T, float>::value ? (const T *)h->d_Etf : (const T *)h->d_Et;
+    for (int l = 1; l < (int)h->level_clusters.size(); ++l) {
+        int nc = (int)h->level_clusters[l].size();
+        if (!nc) continue;
+        hipLaunchKernelGGL(k_backward<T>, dim3(nc), dim3(128), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
+                           h->d_piv_off, h->d_e_off, Et, yh);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+template hipError_t launch_backward<float>(gca_h2_s *, float *, hipStream_t);
+template hipError_t launch_backward<double>(gca_h2_s *, double *, hipStream_t);
+
+// Per leaf, thread per row: y|t^ = V_t yh_t + near partials + pair lists;
+// written back in the original triangle order.
+template <typename T>
+__global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int32_t *node, const int32_t *rank,
+                                               const int64_t *piv_off, const int64_t *v_off, const T *Vt,
+                                               const T *yh, const int64_t *nslot_ptr, const int64_t *nslot,
+                                               const T *npart, const int64_t *prow_ptr, const int32_t *prow_other,
+                                               const int32_t *prow_pair, int64_t off_nr, const double *pval,
+                                               const T *pval_nr, const T *xp, const double *xp64,
+                                               const int32_t *perm, double *y)
+{
+    const int li = blockIdx.x;
+    const int c = leaves[li];
+    const int b = node[5 * c], nr = node[5 * c + 1] - b;
+    const int r = rank[c];
+    const T *Vc = Vt + v_off[c];
+    const T *yc = yh + piv_off[c];
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+        T acc = 0;
+        for (int k = 0; k < r; ++k) acc += Vc[(int64_t)k * nr + i] * yc[k];
+        for (int64_t q = nslot_ptr[li]; q < nslot_ptr[li + 1]; ++q) acc += npart[nslot[q] + i];
+        const int pos = b + i;
+        double acc64 = 0;
+        for (int64_t q = prow_ptr[pos]; q < prow_ptr[pos + 1]; ++q) {
+            const int p = prow_pair[q], o = prow_other[q];
+            if (p < off_nr)
+                acc64 += pval[p] * xp64[o];
+            else
+                acc += pval_nr[p - off_nr] * xp[o];
+        }
+        y[perm[pos]] = (double)acc + acc64;
+    }
+}
+
+template <typename T>
+hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *yh, const T *npart,
+                         const T *pval_nr, double *y, hipStream_t s)
+{
+    const T *Vt = std::is_same<T, float>::value ? (const T *)h->d_Vtf : (const T *)h->d_Vt;
+    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)h->leaves.size()), dim3(64), 0, s, h->d_leaves, h->d_node,
+                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_nslot_ptr, h->d_nslot, npart,
+                       h->d_prow_ptr, h->d_prow_other, h->d_prow_pair, h->pl.off[3], h->d_pval, pval_nr, xp, xp64,
+                       h->d_perm, y);
+    return hipGetLastError();
+}
+template hipError_t launch_gather<float>(gca_h2_s *, const float *, const double *, const float *, const float *,
+                                         const float *, double *, hipStream_t);
+template hipError_t launch_gather<double>(gca_h2_s *, const double *, const double *, const double *,
+                                          const double *, const double *, double *, hipStream_t);
+
+}  // namespace gca

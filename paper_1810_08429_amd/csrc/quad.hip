@@ -1,0 +1,580 @@
+// Triangle-pair quadrature on gfx950: the Galerkin entries
+//     g_ij = int_{t_i} int_{t_j} 1 / (4 pi |x - y|) dy dx          (Eq. G_def)
+// for piecewise-constant bases, evaluated in bulk for
+//   - inadmissible leaf blocks G|t^ x s^ and coupling blocks G|t~ x s~
+//     (one LDS-tiled kernel; entries are recomputed and immediately
+//     multiplied, Section 8's second and third task), and
+//   - one list per Sauter case (identical, common edge, common vertex) plus
+//     a list of near-regular disjoint pairs (Section 8: one list per case so
+//     that a wavefront never diverges between rules).
+//
+// Reference triangle T = {0 <= s2 <= s1 <= 1}, chi(s) = P0 + s1 (P1 - P0) +
+// s2 (P2 - P1).  Regular pairs use a collapsed Gauss rule of order q on each
+// triangle (precomputed per triangle as points and weights times 2|t|).
+// Touching pairs use the Sauter-Schwab regularising maps of [0,1]^4 with the
+// factors that are polynomial in the variables integrated exactly: for a flat
+// pair and the 1/r kernel the integrand of every region is xi^2 eta1 (or
+// xi^2 eta1 eta2) times a function of the remaining variables, so the
+// identical case reduces to three 1D integrals, the common-edge case to five
+// 2D and the common-vertex case to two 3D integrals (Gauss order q_s >= 2
+// integrates the removed polynomial factors exactly, so the values equal the
+// full 4D tensor rule up to rounding).
+#include <hip/hip_runtime.h>
+
+#include "gca_internal.h"
+
+namespace gca {
+
+#define INV4PI 0.07957747154594766788
+
+template <typename T>
+__device__ __forceinline__ T rsq(T x);
+template <>
+__device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double rsq<double>(double x) { return rsqrt(x); }
+
+struct GaussQ {
+    double x[32], w[32];
+    int q;
+};
+
+// ------------------------------------------------------ block kernel -------
+// One workgroup (256 threads) per block (t, s).
+//   NEAR: rows = positions of leaf t, cols = positions of leaf s; entries of
+//         pairs that are not regular (touching or near-regular, from the
+//         per-row pair CSR) are masked to zero -- the list kernels own them.
+//   FAR : rows = pivots t~, cols = pivots s~ (coupling matrix G|t~ x s~).
+// Coordinates are taken relative to the centre of t's box in FP64 and then
+// rounded to T, so FP32 keeps the relative accuracy of short distances.
+// The block writes the row partial  sum_j g_ij x_j  to part[slot_row + i] and,
+// for t != s, the column partial sum_i g_ij x_i  to part[slot_col + j].
+// Deterministic: no atomics; every partial has exactly one writer.
+constexpr int BLK_THREADS = 256;
+
+template <typename T>
+struct BlkArgs {
+    const int32_t *bt, *bs;
+    const int32_t *node;      // nc x 5
+    const double *box;        // nc x 8
+    const double *q;          // n x P x 4
+    const int32_t *piv;       // FAR
+    const int64_t *piv_off;   // FAR
+    const int32_t *rank;      // FAR
+    const int64_t *prow_ptr;  // NEAR
+    const int32_t *prow_other;
+    const T *xv;              // NEAR: permuted x; FAR: xhat
+    const int64_t *slot;      // 2 x nblk
+    T *part;
+    int nblk;
+    int rmax;                 // capacity of the row arrays
+    int cw;                   // column chunk width
+};
+
+// LDS layout of the block kernel (byte offsets, 16-byte aligned sections):
+// mask[rmax] u64 | rowp[rmax][P][4] | colp[P][4][CW] | S[rmax][CW] | xr[rmax] | xc[CW]
+__host__ __device__ constexpr size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+template <typename T>
+struct BlkLayout {
+    size_t mask, rowp, colp, S, xr, xc, total;
+    __host__ __device__ BlkLayout(int rmax, int P, int CW)
+    {
+        mask = 0;
+        rowp = mask + al16((size_t)rmax * 8);
+        colp = rowp + al16((size_t)rmax * P * 4 * sizeof(T));
+        S = colp + al16((size_t)P * 4 * CW * sizeof(T));
+        xr = S + al16((size_t)rmax * CW * sizeof(T));
+        xc = xr + al16((size_t)rmax * sizeof(T));
+        total = xc + al16((size_t)CW * sizeof(T));
+    }
+};
+
+template <typename T, int P, bool NEAR>
+__global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int t = a.bt[b], s = a.bs[b];
+    const int rmax = a.rmax, CW = a.cw;
+    const BlkLayout<T> L(rmax, P, CW);
+    uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
+    T *rowp = reinterpret_cast<T *>(smem + L.rowp);
+    T *colp = reinterpret_cast<T *>(smem + L.colp);
+    T *S = reinterpret_cast<T *>(smem + L.S);
+    T *xr = reinterpret_cast<T *>(smem + L.xr);
+    T *xc = reinterpret_cast<T *>(smem + L.xc);
+
+    int nr, nc;
+    int rb = 0, cb = 0;                 // NEAR: first positions
+    const int32_t *rl = nullptr, *cl = nullptr;   // FAR: pivot lists
+    int64_t xro = 0, xco = 0;           // FAR: xhat offsets
+    if (NEAR) {
+        rb = a.node[5 * t + 0];
+        nr = a.node[5 * t + 1] - rb;
+        cb = a.node[5 * s + 0];
+        nc = a.node[5 * s + 1] - cb;
+    } else {
+        nr = a.rank[t];
+        nc = a.rank[s];
+        xro = a.piv_off[t];
+        xco = a.piv_off[s];
+        rl = a.piv + xro;
+        cl = a.piv + xco;
+    }
+    const bool emit_col = (t != s);
+    const int64_t slot_r = a.slot[2 * b], slot_c = a.slot[2 * b + 1];
+    const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
+    const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
+    const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+
+    // stage row points (relative to the reference point) and row x values
+    for (int e = tid; e < nr * P; e += BLK_THREADS) {
+        int i = e / P, p = e - i * P;
+        int pos = NEAR ? rb + i : rl[i];
+        const double *src = a.q + ((size_t)pos * P + p) * 4;
+        T *dst = rowp + ((size_t)i * P + p) * 4;
+        dst[0] = (T)(src[0] - cx);
+        dst[1] = (T)(src[1] - cy);
+        dst[2] = (T)(src[2] - cz);
+        dst[3] = (T)src[3];
+    }
+    for (int i = tid; i < nr; i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + i] : a.xv[xro + i];
+    if (NEAR) {
+        for (int i = tid; i < nr; i += BLK_THREADS) {
+            uint64_t m = 0;
+            const int pos = rb + i;
+            for (int64_t k = a.prow_ptr[pos]; k < a.prow_ptr[pos + 1]; ++k) {
+                int o = a.prow_other[k] - cb;
+                if (o >= 0 && o < nc) m |= (uint64_t)1 << o;
+            }
+            mask[i] = m;
+        }
+    }
+    T racc = 0;
+    for (int c0 = 0; c0 < nc; c0 += CW) {
+        const int cw = min(CW, nc - c0);
+        __syncthreads();
+        for (int e = tid; e < cw * P; e += BLK_THREADS) {
+            int j = e / P, p = e - j * P;
+            int pos = NEAR ? cb + c0 + j : cl[c0 + j];
+            const double *src = a.q + ((size_t)pos * P + p) * 4;
+            colp[(p * 4 + 0) * CW + j] = (T)(src[0] - cx);
+            colp[(p * 4 + 1) * CW + j] = (T)(src[1] - cy);
+            colp[(p * 4 + 2) * CW + j] = (T)(src[2] - cz);
+            colp[(p * 4 + 3) * CW + j] = (T)src[3];
+        }
+        for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = NEAR ? a.xv[cb + c0 + j] : a.xv[xco + c0 + j];
+        __syncthreads();
+        for (int e = tid; e < nr * cw; e += BLK_THREADS) {
+            const int i = e / cw, j = e - i * cw;
+            T g = 0;
+            bool skip = NEAR && ((mask[i] >> (c0 + j)) & 1);
+            if (!skip) {
+                const T *rp = rowp + (size_t)i * P * 4;
+                T acc = 0;
+#pragma unroll
+                for (int pb = 0; pb < P; ++pb) {
+                    const T yx = colp[(pb * 4 + 0) * CW + j];
+                    const T yy = colp[(pb * 4 + 1) * CW + j];
+                    const T yz = colp[(pb * 4 + 2) * CW + j];
+                    const T yw = colp[(pb * 4 + 3) * CW + j];
+                    T inner = 0;
+#pragma unroll
+                    for (int pa = 0; pa < P; ++pa) {
+                        const T dx = rp[4 * pa + 0] - yx;
+                        const T dy = rp[4 * pa + 1] - yy;
+                        const T dz = rp[4 * pa + 2] - yz;
+                        const T r2 = dx * dx + dy * dy + dz * dz;
+                        inner += rp[4 * pa + 3] * rsq<T>(r2);
+                    }
+                    acc += yw * inner;
+                }
+                g = acc * (T)INV4PI;
+            }
+            S[(size_t)i * CW + j] = g;
+        }
+        __syncthreads();
+        if (tid < nr) {
+            T r = 0;
+            for (int j = 0; j < cw; ++j) r += S[(size_t)tid * CW + j] * xc[j];
+            racc += r;
+        }
+        if (emit_col && tid < cw) {
+            T c = 0;
+            for (int i = 0; i < nr; ++i) c += S[(size_t)i * CW + tid] * xr[i];
+            a.part[slot_c + c0 + tid] = c;
+        }
+    }
+    if (tid < nr) a.part[slot_r + tid] = racc;
+}
+
+template <typename T>
+static size_t blk_smem(int rmax, int P, int cw)
+{
+    return BlkLayout<T>(rmax, P, cw).total;
+}
+
+template <typename T, bool NEAR>
+static hipError_t launch_blocks_P(int P, const BlkArgs<T> &a, hipStream_t s)
+{
+    size_t sm = blk_smem<T>(a.rmax, P, a.cw);
+    dim3 g(a.nblk), blk(BLK_THREADS);
+    switch (P) {
+#define CASE(PP)                                                                              \
+    case PP:                                                                                  \
+        hipLaunchKernelGGL((k_blocks<T, PP, NEAR>), g, blk, sm, s, a);                          \
+        break;
+        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static int blk_cw(int rmax, int P)
+{
+    // widest column chunk (multiple of 8, at most 64) whose tiles fit 60 KB of LDS
+    for (int cw = 64; cw >= 8; cw -= 8)
+        if (blk_smem<T>(rmax, P, cw) <= 60 * 1024) return cw;
+    return 0;
+}
+
+template <typename T>
+hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
+{
+    const int nb = (int)h->blk.near_t.size();
+    if (nb == 0) return hipSuccess;
+    const int P = h->prm.q_r * h->prm.q_r;
+    BlkArgs<T> a{};
+    a.bt = h->d_near;
+    a.bs = h->d_near + nb;
+    a.node = h->d_node;
+    a.box = h->d_box;
+    a.q = h->d_qr;
+    a.prow_ptr = h->d_prow_ptr;
+    a.prow_other = h->d_prow_other;
+    a.xv = xp;
+    a.slot = h->d_near_slot;
+    a.part = npart;
+    a.nblk = nb;
+    a.rmax = h->max_leaf;
+    a.cw = blk_cw<T>(a.rmax, P);
+    if (a.cw == 0) return hipErrorInvalidValue;
+    return launch_blocks_P<T, true>(P, a, s);
+}
+
+template <typename T>
+hipError_t launch_coupling(gca_h2_s *h, const T *xh, T *cpart, T *yh, hipStream_t s);
+
+template <typename T>
+hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
+{
+    const int nb = (int)h->blk.far_t.size();
+    if (nb == 0) return hipSuccess;
+    const int P = h->prm.q_r * h->prm.q_r;
+    BlkArgs<T> a{};
+    a.bt = h->d_far;
+    a.bs = h->d_far + nb;
+    a.node = h->d_node;
+    a.box = h->d_box;
+    a.q = h->d_qr;
+    a.piv = h->d_piv;
+    a.piv_off = h->d_piv_off;
+    a.rank = h->d_rank;
+    a.xv = xh;
+    a.slot = h->d_far_slot;
+    a.part = cpart;
+    a.nblk = nb;
+    a.rmax = std::max(1, h->max_rank);
+    a.cw = blk_cw<T>(a.rmax, P);
+    if (a.cw == 0) return hipErrorInvalidValue;
+    return launch_blocks_P<T, false>(P, a, s);
+}
+
+template hipError_t launch_near<float>(gca_h2_s *, const float *, float *, hipStream_t);
+template hipError_t launch_near<double>(gca_h2_s *, const double *, double *, hipStream_t);
+template hipError_t launch_far_blocks<float>(gca_h2_s *, const float *, float *, hipStream_t);
+template hipError_t launch_far_blocks<double>(gca_h2_s *, const double *, double *, hipStream_t);
+
+// -------------------------------------------------- touching pairs (FP64) --
+
+__constant__ int c_perm[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}, {2, 1, 0}};
+
+struct V3 {
+    double x, y, z;
+};
+__device__ __forceinline__ V3 vsub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double vnorm(V3 a) { return sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
+__device__ __forceinline__ double vrnorm(double x, double y, double z) { return rsqrt(x * x + y * y + z * z); }
+__device__ __forceinline__ double cross_norm(V3 a, V3 b)
+{
+    double cx = a.y * b.z - a.z * b.y, cy = a.z * b.x - a.x * b.z, cz = a.x * b.y - a.y * b.x;
+    return sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+__device__ __forceinline__ V3 ldv(const double *xyz, int v)
+{
+    return {xyz[3 * (size_t)v], xyz[3 * (size_t)v + 1], xyz[3 * (size_t)v + 2]};
+}
+
+// Ordered vertices of a triangle: code indexes c_perm.
+__device__ __forceinline__ void tri_vertices(const double *xyz, const int32_t *tv, int pos, int code, V3 P[3])
+{
+    const int32_t *v = tv + 3 * (size_t)pos;
+    P[0] = ldv(xyz, v[c_perm[code][0]]);
+    P[1] = ldv(xyz, v[c_perm[code][1]]);
+    P[2] = ldv(xyz, v[c_perm[code][2]]);
+}
+
+// identical triangles: J^2/(4 pi) * (1/3) * sum_d w_d [ 1/|eta e1 + e2| + 1/|e1 + eta e2| + 1/|-eta e1 + (1-eta) e2| ]
+__device__ double ss_identical(const V3 P[3], const GaussQ &g)
+{
+    V3 e1 = vsub(P[1], P[0]), e2 = vsub(P[2], P[1]);
+    double J = cross_norm(e1, e2);
+    double s = 0;
+    for (int d = 0; d < g.q; ++d) {
+        double t = g.x[d];
+        double a = vrnorm(t * e1.x + e2.x, t * e1.y + e2.y, t * e1.z + e2.z);
+        double b = vrnorm(e1.x + t * e2.x, e1.y + t * e2.y, e1.z + t * e2.z);
+        double c = vrnorm(-t * e1.x + (1 - t) * e2.x, -t * e1.y + (1 - t) * e2.y, -t * e1.z + (1 - t) * e2.z);
+        s += g.w[d] * (a + b + c);
+    }
+    return J * J * INV4PI * s * (1.0 / 3.0);
+}
+
+// common edge P0 P1 (same parametrisation on both triangles): five 2D integrals
+__device__ double ss_edge(const V3 P[3], const V3 Q[3], const GaussQ &g)
+{
+    V3 e1 = vsub(P[1], P[0]), et = vsub(P[2], P[1]), es = vsub(Q[2], Q[1]);
+    double Jt = cross_norm(e1, et), Js = cross_norm(e1, es);
+    double s = 0;
+    for (int ia = 0; ia < g.q; ++ia) {
+        const double h2 = g.x[ia];
+        double sb = 0;
+        for (int ib = 0; ib < g.q; ++ib) {
+            const double h3 = g.x[ib];
+            // region 1 (no eta2 factor)
+            double r1 = vrnorm(h2 * e1.x + h3 * et.x - (1 - h2) * es.x, h2 * e1.y + h3 * et.y - (1 - h2) * es.y,
+                               h2 * e1.z + h3 * et.z - (1 - h2) * es.z);
+            double r2 = vrnorm(h2 * h3 * e1.x + et.x - h2 * (1 - h3) * es.x,
+                               h2 * h3 * e1.y + et.y - h2 * (1 - h3) * es.y,
+                               h2 * h3 * e1.z + et.z - h2 * (1 - h3) * es.z);
+            double r3 = vrnorm(-h2 * e1.x + (1 - h2) * et.x - h2 * h3 * es.x,
+                               -h2 * e1.y + (1 - h2) * et.y - h2 * h3 * es.y,
+                               -h2 * e1.z + (1 - h2) * et.z - h2 * h3 * es.z);
+            double r4 = vrnorm(-h2 * h3 * e1.x + h2 * (1 - h3) * et.x - es.x,
+                               -h2 * h3 * e1.y + h2 * (1 - h3) * et.y - es.y,
+                               -h2 * h3 * e1.z + h2 * (1 - h3) * et.z - es.z);
+            double r5 = vrnorm(-h2 * h3 * e1.x + (1 - h2 * h3) * et.x - h2 * es.x,
+                               -h2 * h3 * e1.y + (1 - h2 * h3) * et.y - h2 * es.y,
+                               -h2 * h3 * e1.z + (1 - h2 * h3) * et.z - h2 * es.z);
+            sb += g.w[ib] * (r1 + h2 * (r2 + r3 + r4 + r5));
+        }
+        s += g.w[ia] * sb;
+    }
+    return Jt * Js * INV4PI * s * (1.0 / 6.0);
+}
+
+// common vertex P0 = Q0: two 3D integrals
+__device__ double ss_vertex(const V3 P[3], const V3 Q[3], const GaussQ &g)
+{
+    V3 e1t = vsub(P[1], P[0]), e2t = vsub(P[2], P[1]);
+    V3 e1s = vsub(Q[1], Q[0]), e2s = vsub(Q[2], Q[1]);
+    double Jt = cross_norm(e1t, e2t), Js = cross_norm(e1s, e2s);
+    double s = 0;
+    for (int ia = 0; ia < g.q; ++ia) {
+        const double h1 = g.x[ia];
+        // x-side points (1, eta1) and y-side points (1, eta1)
+        const double ax = e1t.x + h1 * e2t.x, ay = e1t.y + h1 * e2t.y, az = e1t.z + h1 * e2t.z;
+        const double bx = e1s.x + h1 * e2s.x, by = e1s.y + h1 * e2s.y, bz = e1s.z + h1 * e2s.z;
+        double sa = 0;
+        for (int ib = 0; ib < g.q; ++ib) {
+            const double h2 = g.x[ib];
+            double sb = 0;
+            for (int ic = 0; ic < g.q; ++ic) {
+                const double h3 = g.x[ic];
+                const double cx = e1s.x + h3 * e2s.x, cy = e1s.y + h3 * e2s.y, cz = e1s.z + h3 * e2s.z;
+                const double dx = e1t.x + h3 * e2t.x, dy = e1t.y + h3 * e2t.y, dz = e1t.z + h3 * e2t.z;
+                double r1 = vrnorm(ax - h2 * cx, ay - h2 * cy, az - h2 * cz);
+                double r2 = vrnorm(h2 * dx - bx, h2 * dy - by, h2 * dz - bz);
+                sb += g.w[ic] * (r1 + r2);
+            }
+            sa += g.w[ib] * h2 * sb;
+        }
+        s += g.w[ia] * sa;
+    }
+    return Jt * Js * INV4PI * s * (1.0 / 3.0);
+}
+
+template <int KIND>
+__device__ double touching_value(const double *xyz, const int32_t *tv, int pa, int pb, int code, const GaussQ &g)
+{
+    V3 P[3], Q[3];
+    tri_vertices(xyz, tv, pa, code & 15, P);
+    if (KIND == 0) return ss_identical(P, g);
+    tri_vertices(xyz, tv, pb, (code >> 4) & 15, Q);
+    if (KIND == 1) return ss_edge(P, Q, g);
+    return ss_vertex(P, Q, g);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_touching(const double *xyz, const int32_t *tv, const int32_t *pa,
+                                                  const int32_t *pb, const int32_t *code, int64_t np,
+                                                  GaussQ g, double *out)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    out[p] = touching_value<KIND>(xyz, tv, pa[p], pb[p], code[p], g);
+}
+
+static GaussQ make_gq(const double *x, const double *w, int q)
+{
+    GaussQ g{};
+    g.q = q;
+    for (int i = 0; i < q; ++i) {
+        g.x[i] = x[i];
+        g.w[i] = w[i];
+    }
+    return g;
+}
+
+hipError_t launch_touching(gca_h2_s *h, double *pval, hipStream_t s)
+{
+    GaussQ g = make_gq(h->gs_x, h->gs_w, h->prm.q_s);
+    for (int kind = 0; kind < 3; ++kind) {
+        int64_t b = h->pl.off[kind], e = h->pl.off[kind + 1];
+        int64_t np = e - b;
+        if (np == 0) continue;
+        dim3 grid((unsigned)((np + 255) / 256)), blk(256);
+        if (kind == 0)
+            hipLaunchKernelGGL(k_touching<0>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
+                               h->d_pcode + b, np, g, pval + b);
+        else if (kind == 1)
+            hipLaunchKernelGGL(k_touching<1>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
+                               h->d_pcode + b, np, g, pval + b);
+        else
+            hipLaunchKernelGGL(k_touching<2>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
+                               h->d_pcode + b, np, g, pval + b);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------ near-regular pairs --
+// Disjoint pairs joined by a mesh edge get the regular rule of order q_nr.
+// Points relative to the first point of the first triangle (FP64), then T.
+template <typename T, int P>
+__device__ T regular_pair(const double *q, int pa, int pb)
+{
+    const double *A = q + (size_t)pa * P * 4;
+    const double *B = q + (size_t)pb * P * 4;
+    const double ox = A[0], oy = A[1], oz = A[2];
+    T ax[P], ay[P], az[P], aw[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        ax[i] = (T)(A[4 * i] - ox);
+        ay[i] = (T)(A[4 * i + 1] - oy);
+        az[i] = (T)(A[4 * i + 2] - oz);
+        aw[i] = (T)A[4 * i + 3];
+    }
+    T acc = 0;
+    for (int j = 0; j < P; ++j) {
+        const T bx = (T)(B[4 * j] - ox), by = (T)(B[4 * j + 1] - oy), bz = (T)(B[4 * j + 2] - oz);
+        const T bw = (T)B[4 * j + 3];
+        T inner = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const T dx = ax[i] - bx, dy = ay[i] - by, dz = az[i] - bz;
+            inner += aw[i] * rsq<T>(dx * dx + dy * dy + dz * dz);
+        }
+        acc += bw * inner;
+    }
+    return acc * (T)INV4PI;
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_nearreg(const double *q, const int32_t *pa, const int32_t *pb, int64_t np,
+                                                 T *out)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    out[p] = regular_pair<T, P>(q, pa[p], pb[p]);
+}
+
+template <typename T>
+static hipError_t launch_regular_list(int P, const double *q, const int32_t *pa, const int32_t *pb, int64_t np,
+                                      T *out, hipStream_t s)
+{
+    if (np == 0) return hipSuccess;
+    dim3 grid((unsigned)((np + 255) / 256)), blk(256);
+    switch (P) {
+#define CASE(PP)                                                                              \
+    case PP:                                                                                  \
+        hipLaunchKernelGGL((k_nearreg<T, PP>), grid, blk, 0, s, q, pa, pb, np, out);           \
+        break;
+        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36) CASE(49)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_nearreg(gca_h2_s *h, T *pval, hipStream_t s)
+{
+    int64_t b = h->pl.off[3], e = h->pl.off[4];
+    return launch_regular_list<T>(h->prm.q_nr * h->prm.q_nr, h->d_qnr, h->d_pa + b, h->d_pb + b, e - b, pval,
+                                  s);
+}
+
+template hipError_t launch_nearreg<float>(gca_h2_s *, float *, hipStream_t);
+template hipError_t launch_nearreg<double>(gca_h2_s *, double *, hipStream_t);
+
+// ---------------------------------------------------- single entries ------
+// Entries for a list of pairs already sorted into classes by the host:
+// touching (codes), near-regular and regular pairs go through the same
+// device functions as the matrix-vector product.
+hipError_t launch_entry_jobs(gca_h2_s *h, const EntryJobs &j, double *tmp64, float *tmp32, int precision,
+                             hipStream_t s)
+{
+    GaussQ g = make_gq(h->gs_x, h->gs_w, h->prm.q_s);
+    for (int kind = 0; kind < 3; ++kind) {
+        int64_t b = j.off[kind], np = j.off[kind + 1] - b;
+        if (!np) continue;
+        dim3 grid((unsigned)((np + 255) / 256)), blk(256);
+        if (kind == 0)
+            hipLaunchKernelGGL(k_touching<0>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
+                               np, g, tmp64 + b);
+        else if (kind == 1)
+            hipLaunchKernelGGL(k_touching<1>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
+                               np, g, tmp64 + b);
+        else
+            hipLaunchKernelGGL(k_touching<2>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
+                               np, g, tmp64 + b);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int Pnr = h->prm.q_nr * h->prm.q_nr, Pr = h->prm.q_r * h->prm.q_r;
+    if (precision == GCA_FP64) {
+        err = launch_regular_list<double>(Pnr, h->d_qnr, j.pa + j.off[3], j.pb + j.off[3], j.off[4] - j.off[3],
+                                          tmp64 + j.off[3], s);
+        if (err != hipSuccess) return err;
+        err = launch_regular_list<double>(Pr, h->d_qr, j.pa + j.off[4], j.pb + j.off[4], j.off[5] - j.off[4],
+                                          tmp64 + j.off[4], s);
+    } else {
+        err = launch_regular_list<float>(Pnr, h->d_qnr, j.pa + j.off[3], j.pb + j.off[3], j.off[4] - j.off[3],
+                                         tmp32 + j.off[3], s);
+        if (err != hipSuccess) return err;
+        err = launch_regular_list<float>(Pr, h->d_qr, j.pa + j.off[4], j.pb + j.off[4], j.off[5] - j.off[4],
+                                         tmp32 + j.off[4], s);
+    }
+    return err;
+}
+
+}  // namespace gca

@@ -1,0 +1,194 @@
+"""Parity of the HIP path with the CPU oracle (runs on an MI355X).
+
+Tolerances (FP64 path): entries and the nearfield-only operator to 1e-12
+relative (same rules, only rounding order differs); the H^2 product to the
+compression tolerance against the dense matrix and to 1e-10 against the
+oracle's step-by-step GCA-H^2 when both select the same pivots.
+Mixed path: FP32 regular-pair quadrature with cluster-local coordinates,
+tolerance 1e-5 relative (FP32 rounding of a sum of O(100) terms).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def gca():
+    import paper_1810_08429_amd as g
+    g.lib()
+    return g
+
+
+@pytest.fixture(scope="module")
+def c1(orc):
+    m = synth.icosphere(3)
+    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    G = ent.dense()
+    return m, ent, G
+
+
+def build(gca, m, leaf, **kw):
+    tree = gca.Tree(m.verts, m.tris, leaf)
+    return gca.H2(m.verts, m.tris, tree, gca.Params(**kw))
+
+
+def class_samples(orc, ent, n, rng, per_class=1500):
+    I = rng.integers(0, n, 60000)
+    J = rng.integers(0, n, 60000)
+    I = np.concatenate([I, np.arange(n)])
+    J = np.concatenate([J, np.arange(n)])
+    c = ent.classify(I, J)
+    out = {}
+    for k in range(5):
+        sel = np.nonzero(c == k)[0][:per_class]
+        out[k] = (I[sel], J[sel])
+    # all touching pairs of a few rows, both orders
+    rows = rng.choice(n, 40, replace=False)
+    for r in rows:
+        cc = ent.classify(np.full(n, r), np.arange(n))
+        for k in (orc.EDGE, orc.VERT):
+            js = np.nonzero(cc == k)[0]
+            out[k] = (np.concatenate([out[k][0], np.full(js.size, r), js]),
+                      np.concatenate([out[k][1], js, np.full(js.size, r)]))
+    return out
+
+
+def test_entries_fp64_match_oracle_per_class(torch, gca, orc, c1):
+    m, ent, G = c1
+    H = build(gca, m, 32, eta=2.0, eps=1e-6)
+    rng = np.random.default_rng(0)
+    for k, (I, J) in class_samples(orc, ent, m.nt, rng).items():
+        assert I.size > 0, k
+        got = H.entries(I, J).cpu().numpy()
+        ref = G[I, J]
+        err = np.max(np.abs(got - ref) / np.abs(ref))
+        assert err < 1e-12, (k, err)
+
+
+def test_entries_mixed_match_oracle(torch, gca, orc, c1):
+    m, ent, G = c1
+    H = build(gca, m, 32, eta=2.0, eps=1e-6)
+    rng = np.random.default_rng(1)
+    for k, (I, J) in class_samples(orc, ent, m.nt, rng).items():
+        got = H.entries(I, J, precision=gca.MIXED).cpu().numpy()
+        ref = G[I, J]
+        err = np.max(np.abs(got - ref) / np.abs(ref))
+        tol = 1e-12 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6
+        assert err < tol, (k, err)
+
+
+def test_nearfield_only_operator_equals_dense(torch, gca, c1):
+    """eta -> 0: no admissible block, the H^2 operator is the plain Galerkin
+    matrix assembled by the block kernel and the per-case lists."""
+    m, ent, G = c1
+    H = build(gca, m, 32, eta=1e-6, eps=1e-6)
+    st = H.stats()
+    assert st["n_far_sym"] == 0
+    X = synth.rhs_normal(m.nt, 3, seed=0)
+    ref = G @ X
+    x = torch.tensor(X, device="cuda")
+    y = H.matvec(x).cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() < 1e-12 * scale
+    ym = H.matvec(x, precision=gca.MIXED).cpu().numpy()
+    assert np.abs(ym - ref).max() < 1e-5 * scale
+
+
+def test_h2_fp64_matches_dense_within_tolerance(torch, gca, orc, c1):
+    m, ent, G = c1
+    for eps in (1e-4, 1e-6):
+        H = build(gca, m, 32, eta=2.0, eps=eps)
+        assert H.stats()["n_far_sym"] > 0
+        x = synth.rhs_normal(m.nt, 1, seed=0)
+        ref = G @ x
+        y = H.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+        rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        assert rel < 10 * eps, (eps, rel)
+        ym = H.matvec(torch.tensor(x, device="cuda"), precision=gca.MIXED).cpu().numpy()
+        relm = np.linalg.norm(ym - ref) / np.linalg.norm(ref)
+        assert relm < 10 * eps + 1e-5, (eps, relm)
+
+
+def test_h2_matches_oracle_step_by_step_on_jittered_mesh(torch, gca, orc):
+    """Off the symmetric sphere the pivot choice is unique: the GPU pivots,
+    ranks and bases equal the oracle's, and so does the product."""
+    base = synth.icosphere(3)
+    m = synth.jitter(base, 0.02 * synth.mean_edge_length(base), seed=7)
+    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    ho = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, m=3, eps=1e-5, ent=ent)
+    H = build(gca, m, 32, eta=2.0, eps=1e-5)
+    ranks, piv, basis = H.basis()
+    nc = len(ho.tree.nodes)
+    assert ranks.shape[0] == nc
+    o = 0
+    for c in range(nc):
+        r = ranks[c]
+        assert r == len(ho.pivots[c]), c
+        assert np.array_equal(piv[o:o + r], ho.pivots[c]), c
+        o += r
+    x = synth.rhs_normal(m.nt, 1, seed=0)
+    yo = orc.h2_matvec(ho, x)
+    y = H.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) < 1e-10
+    # leaf bases and transfers
+    nv_ = 0
+    for c in range(nc):
+        nd = ho.tree.nodes[c]
+        if not nd.sons:
+            V = basis[nv_:nv_ + (nd.end - nd.begin) * ranks[c]].reshape(nd.end - nd.begin, ranks[c])
+            np.testing.assert_allclose(V, ho.V[c], rtol=0, atol=1e-9 * max(1.0, np.abs(ho.V[c]).max()))
+            nv_ += V.size
+
+
+def test_matvec_is_deterministic_and_multi_rhs_consistent(torch, gca, c1):
+    m, ent, G = c1
+    H = build(gca, m, 32, eta=2.0, eps=1e-6)
+    X = torch.tensor(synth.rhs_normal(m.nt, 4, seed=3), device="cuda")
+    for prec in (gca.FP64, gca.MIXED):
+        Y1 = H.matvec(X, precision=prec)
+        Y2 = H.matvec(X, precision=prec)
+        assert torch.equal(Y1, Y2)
+        for k in range(4):
+            yk = H.matvec(X[:, k].contiguous(), precision=prec)
+            assert torch.equal(yk, Y1[:, k])
+
+
+def test_sphere_constant_potential_on_gpu(torch, gca, orc):
+    """P3 through the whole H^2 product: (G~ 1)_i / |t_i| -> r = 1."""
+    m = synth.icosphere(4)
+    H = build(gca, m, 32, eta=2.0, eps=1e-6)
+    T = m.verts[m.tris]
+    area = 0.5 * np.linalg.norm(np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]), axis=1)
+    y = H.matvec(torch.ones(m.nt, dtype=torch.float64, device="cuda")).cpu().numpy() / area
+    assert np.abs(y - 1).max() < 2e-3
+    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    rows = np.arange(0, m.nt, 97)
+    ref = ent.matvec_rows(rows, np.ones(m.nt)) / area[rows]
+    assert np.abs(y[rows] - ref).max() < 1e-5
+
+
+def test_larger_sphere_sampled_rows(torch, gca, orc):
+    """n = 20480 (leaf 64, eps 1e-5, 16 right-hand sides): sampled rows of
+    the H^2 product against the oracle's dense rows."""
+    m = synth.icosphere(5)
+    H = build(gca, m, 64, eta=2.0, eps=1e-5)
+    X = synth.rhs_normal(m.nt, 16, seed=0)
+    Y = H.matvec(torch.tensor(X, device="cuda")).cpu().numpy()
+    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    rows = np.random.default_rng(2).choice(m.nt, 48, replace=False)
+    ref = ent.matvec_rows(rows, X)
+    rel = np.linalg.norm(Y[rows] - ref) / np.linalg.norm(ref)
+    assert rel < 1e-4, rel
+    Ym = H.matvec(torch.tensor(X, device="cuda"), precision=gca.MIXED).cpu().numpy()
+    relm = np.linalg.norm(Ym[rows] - ref) / np.linalg.norm(ref)
+    assert relm < 1e-4, relm

@@ -1,0 +1,152 @@
+"""Host-side checks of libgca that need no GPU: the C-ABI exports every
+declared entry point, the cluster tree and block partition equal the
+oracle's (integer and FP64 values bit for bit), and invalid input is rejected
+with the documented status before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gca():
+    import paper_1810_08429_amd as g
+    if not os.path.exists(g.LIB_PATH):
+        from paper_1810_08429_amd import build
+        build.build()
+    g.lib()
+    return g
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gca.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:gca_status|void|const char \*)\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(gca):
+    names = declared_functions()
+    assert "gca_build" in names and "h2_matvec" in names and len(names) >= 14
+    L = ctypes.CDLL(gca.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(gca.EXPORTED) <= set(names)
+
+
+@pytest.mark.parametrize("level,leaf", [(3, 32), (4, 16), (5, 64)])
+def test_tree_equals_oracle(gca, orc, level, leaf):
+    m = synth.icosphere(level)
+    perm, nodes, boxes = gca.Tree(m.verts, m.tris, leaf).export()
+    ot = orc.cluster_tree(m.verts, m.tris, leaf)
+    assert np.array_equal(perm, ot.perm)
+    assert nodes.shape[0] == len(ot.nodes)
+    for c, nd in enumerate(ot.nodes):
+        assert (nodes[c, 0], nodes[c, 1], nodes[c, 4]) == (nd.begin, nd.end, nd.level)
+        assert list(nodes[c, 2:4]) == (nd.sons or [-1, -1])
+        assert np.array_equal(boxes[c, :3], nd.lo) and np.array_equal(boxes[c, 3:6], nd.hi)
+        assert boxes[c, 6] == nd.diam
+
+
+def test_tree_equals_oracle_jittered_ellipsoid(gca, orc):
+    m = synth.jitter(synth.ellipsoid(4), 1e-3 * 0.05, seed=1)
+    perm, nodes, boxes = gca.Tree(m.verts, m.tris, 32).export()
+    ot = orc.cluster_tree(m.verts, m.tris, 32)
+    assert np.array_equal(perm, ot.perm)
+    assert np.array_equal(boxes[:, 6], np.array([nd.diam for nd in ot.nodes]))
+
+
+@pytest.mark.parametrize("level,leaf,eta", [(3, 32, 2.0), (4, 32, 1.0), (5, 64, 2.0), (3, 32, 1e-6)])
+def test_block_tree_equals_oracle(gca, orc, level, leaf, eta):
+    m = synth.icosphere(level)
+    far, near = gca.Tree(m.verts, m.tris, leaf).blocks(eta)
+    ot = orc.cluster_tree(m.verts, m.tris, leaf)
+    of, on = orc.block_tree(ot, eta)
+    assert sorted(map(tuple, far.tolist())) == sorted((t, s) for (t, s) in of if t < s)
+    assert sorted(map(tuple, near.tolist())) == sorted((t, s) for (t, s) in on if t <= s)
+    assert all(t != s for (t, s) in of)
+
+
+def _mesh(m):
+    return m.verts.copy(), m.tris.copy()
+
+
+def test_invalid_meshes_are_rejected(gca):
+    m = synth.icosphere(1)
+    v, t = _mesh(m)
+    bad = t.copy()
+    bad[3, 1] = m.nv + 5
+    with pytest.raises(gca.Error) as e:
+        gca.Tree(v, bad, 8)
+    assert e.value.code == -4
+    dup = np.concatenate([t, t[:1]])
+    with pytest.raises(gca.Error) as e:
+        gca.Tree(v, dup, 8)
+    assert e.value.code == -4
+    v2 = v.copy()
+    v2[t[0, 2]] = v2[t[0, 0]]          # collapse a triangle
+    with pytest.raises(gca.Error) as e:
+        gca.Tree(v2, t, 8)
+    assert e.value.code == -4
+    vn = v.copy()
+    vn[0, 0] = np.nan
+    with pytest.raises(gca.Error) as e:
+        gca.Tree(vn, t, 8)
+    assert e.value.code == -1
+    # a fourth triangle on one edge: non-manifold
+    a, b = t[0, 0], t[0, 1]
+    v3 = np.concatenate([v, [[5.0, 5.0, 5.0]]])
+    t3 = np.concatenate([t, [[a, b, m.nv]]]).astype(np.int32)
+    t3 = np.concatenate([t3, [[b, a, m.nv]]]).astype(np.int32)
+    with pytest.raises(gca.Error) as e:
+        gca.Tree(v3, t3, 8)
+    assert e.value.code == -4
+    with pytest.raises(gca.Error) as e:
+        gca.Tree(v, t, 0)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("field,value", [("eta", 0.0), ("eta", float("inf")), ("eps", -1.0), ("eps", 1.0),
+                                         ("green_m", 0), ("green_m", 7), ("q_s", 1), ("q_r", 0),
+                                         ("q_nr", 8), ("omega_scale", 0.0)])
+def test_invalid_parameters_are_rejected_before_device_work(gca, field, value):
+    m = synth.icosphere(1)
+    tree = gca.Tree(m.verts, m.tris, 8)
+    p = gca.Params()
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    mesh = gca._MeshArrays(m.verts, m.tris)
+    pc = p._c()
+    code = gca.lib().gca_build(ctypes.byref(mesh.c), tree.h, ctypes.byref(pc), None, ctypes.byref(h))
+    assert code == -1, gca.lib().gca_last_error()
+    assert not h.value
+
+
+def test_build_rejects_other_mesh_and_large_leaves(gca):
+    m = synth.icosphere(1)
+    tree = gca.Tree(m.verts, m.tris, 8)
+    h = ctypes.c_void_p()
+    other = gca._MeshArrays(m.verts * 1.5, m.tris)
+    pc = gca.Params()._c()
+    assert gca.lib().gca_build(ctypes.byref(other.c), tree.h, ctypes.byref(pc), None, ctypes.byref(h)) == -1
+    m2 = synth.icosphere(3)
+    big = gca.Tree(m2.verts, m2.tris, 128)
+    mesh = gca._MeshArrays(m2.verts, m2.tris)
+    assert gca.lib().gca_build(ctypes.byref(mesh.c), big.h, ctypes.byref(pc), None, ctypes.byref(h)) == -1
+    assert b"leaf" in gca.lib().gca_last_error()
+
+
+def test_null_arguments(gca):
+    L = gca.lib()
+    assert L.h2_matvec(None, None, None, 1, 1, 0, None) == -1
+    assert L.gca_entries(None, None, None, 1, None, 0, None) == -1
+    assert L.gca_stats(None, None) == -1
+    assert L.gca_tree_build(None, 8, None) == -1
+    L.gca_destroy(None)
+    L.gca_tree_destroy(None)
