@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the GCA-H^2 matrix-vector product on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere_l8]
+
+One step = one H^2 product y = G~ x (forward transform, coupling blocks and
+nearfield blocks recomputed by pair quadrature, backward transform, touching
+and near-regular pair lists) for one right-hand side, inputs resident in HBM.
+`value` is DoF/s = n / (seconds per product) of the mixed-precision path
+(FP32 regular-pair quadrature and transfers, FP64 touching pairs); the FP64
+path is measured on the same H^2 approximation alongside.  Setup seconds
+cover tree construction and gca_build (synchronised wall time).
+
+The roofline object describes the dominant kernel of the mixed product, timed
+with the library's per-product HIP events over the timed steps.  The CPU
+baseline is the plain FP64 oracle computing sampled rows of G x on the host
+cores; the same rows give the relative error of both GPU paths.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "H² matvec DoF/s + setup s at 1e-4 rel err: mixed vs FP64 plain, % roofline"
+
+# ALU ceiling of one FP32 kernel evaluation w / |x - y| accumulated into a sum
+# (derivation in the design doc): 7 VALU lane-ops (3 sub, 1 mul, 2 fma for |x-y|^2,
+# 1 fma to accumulate) + 1 v_rsq_f32.  The published FP32 vector peak, 157.3
+# TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes per clock, gives 7.86e13 lane-ops/s;
+# transcendentals run at a quarter of that.  Algorithmic work is counted as 10
+# flops per evaluation.
+VALU_LANE_OPS_PER_S = 256 * 128 * 2.4e9
+TRANS_LANE_OPS_PER_S = VALU_LANE_OPS_PER_S / 4
+FLOPS_PER_EVAL = 10
+EVALS_PER_S_F32 = 1.0 / (7.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
+ALU_PEAK_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sphere_l8")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target wall time of the oracle CPU baseline sample (0 disables it)")
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--eps", type=float, default=None, help="override the workload's ACA tolerance")
+    ap.add_argument("--q-nr", type=int, default=None, help="override the near-regular pair order")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)")
+    import torch
+    import synth
+    import paper_1810_08429_amd as gca
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    mesh, cfg = synth.workload(a.workload)
+    n = mesh.nt
+    print(f"[bench] workload {a.workload}: n={n} leaf={cfg['leaf']} eta={cfg['eta']} eps={cfg['eps']}",
+          file=sys.stderr, flush=True)
+    if a.eps is not None:
+        cfg["eps"] = a.eps
+    params = gca.Params(eta=cfg["eta"], eps=cfg["eps"], green_m=cfg["green_m"])
+    if a.q_nr is not None:
+        params.q_nr = a.q_nr
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree = gca.Tree(mesh.verts, mesh.tris, cfg["leaf"])
+    H = gca.H2(mesh.verts, mesh.tris, tree, params)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    st = H.stats()
+    print(f"[bench] setup {setup_s:.2f} s (gca_build {st['build_ms'] / 1e3:.2f} s)", file=sys.stderr, flush=True)
+
+    x_host = synth.rhs_normal(n, 1, seed=0)
+    x = torch.tensor(x_host, device=dev)
+    y = torch.empty_like(x)
+
+    def run(prec, steps, warmup):
+        for _ in range(warmup):
+            H.matvec_into(x, y, precision=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            H.matvec_into(x, y, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        ph = H.phase_times(steps)
+        return dt, ph, y.clone()
+
+    dt_mixed, ph_mixed, y_mixed = run(gca.MIXED, a.steps, a.warmup)
+    print(f"[bench] mixed: {dt_mixed * 1e3:.3f} ms/product", file=sys.stderr, flush=True)
+    fsteps = a.fp64_steps if a.fp64_steps is not None else max(3, a.steps // 2)
+    dt_fp64, ph_fp64, y_fp64 = run(gca.FP64, fsteps, 1)
+    print(f"[bench] fp64 : {dt_fp64 * 1e3:.3f} ms/product", file=sys.stderr, flush=True)
+
+    phases = gca.PHASES
+    mean_mixed = dict(zip(phases, ph_mixed.mean(axis=0).tolist()))
+    mean_fp64 = dict(zip(phases, ph_fp64.mean(axis=0).tolist()))
+
+    # dominant kernel of the mixed product: coupling-block or nearfield-block quadrature
+    P = params.q_r * params.q_r
+    work = {"coupling_blocks": st["coupling_entries"] * P * P * FLOPS_PER_EVAL,
+            "near_blocks": st["near_regular_pairs"] * P * P * FLOPS_PER_EVAL}
+    dom = max(work, key=lambda k: mean_mixed[k])
+    dur = mean_mixed[dom] * 1e-3
+    achieved = work[dom] / dur / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": None,
+                "kernel": "k_blocks<float,%d,%s>" % (P, "false" if dom == "coupling_blocks" else "true"),
+                "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom]}
+
+    # CPU oracle on a bounded sample of rows (also the accuracy check)
+    cpu = None
+    rel = {}
+    if a.cpu_seconds > 0:
+        import oracle
+        ent = oracle.Entries(mesh.verts, mesh.tris, params.q_r, params.q_nr, params.q_s)
+        rng = np.random.default_rng(12345)
+        rows = rng.choice(n, oracle.num_threads(), replace=False)
+        t = time.perf_counter()
+        ref = ent.matvec_rows(rows, x_host)
+        t1 = time.perf_counter() - t
+        more = int(min(4096, max(0, (a.cpu_seconds - t1) / max(t1, 1e-6) * len(rows))))
+        if more > 0:
+            rows2 = rng.choice(np.setdiff1d(np.arange(n), rows), more, replace=False)
+            t = time.perf_counter()
+            ref2 = ent.matvec_rows(rows2, x_host)
+            t2 = time.perf_counter() - t
+            rows = np.concatenate([rows, rows2])
+            ref = np.concatenate([ref, ref2])
+            t1 += t2
+        cpu = {"value": len(rows) / t1, "unit": "DoF/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{len(rows)} rows of the dense FP64 product G x (same quadrature orders), "
+                         f"{t1:.1f} s; a full product is n rows, so DoF/s = rows/s"}
+        ym = y_mixed.cpu().numpy()[rows]
+        yd = y_fp64.cpu().numpy()[rows]
+        rel = {"mixed": float(np.linalg.norm(ym - ref) / np.linalg.norm(ref)),
+               "fp64": float(np.linalg.norm(yd - ref) / np.linalg.norm(ref)),
+               "rows": int(len(rows))}
+        print(f"[bench] oracle rows {len(rows)} in {t1:.1f} s; rel err mixed {rel['mixed']:.2e} "
+              f"fp64 {rel['fp64']:.2e}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": n / dt_mixed,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: unit icosphere, {n} flat triangles, piecewise-constant basis, "
+                               f"leaf {cfg['leaf']}, eta {cfg['eta']}, Green order {cfg['green_m']}, "
+                               f"ACA eps {cfg['eps']}, 1 RHS x ~ N(0,1) seed 0",
+                   "n": n, "nrhs": 1, "precision": "mixed: FP32 regular-pair quadrature + transfers, "
+                                                   "FP64 Sauter-Schwab touching pairs"},
+        "setup_s": setup_s,
+        "fp64": {"value": n / dt_fp64, "unit": "DoF/s", "ms_per_step": dt_fp64 * 1e3, "steps": fsteps},
+        "mixed_over_fp64": dt_fp64 / dt_mixed,
+        "rel_err_sampled_rows": rel,
+        "phases_ms": {"mixed": mean_mixed, "fp64": mean_fp64},
+        "structure": {k: st[k] for k in ("n_clusters", "n_leaves", "depth", "n_far_sym", "n_near_sym",
+                                         "n_ident", "n_edge", "n_vert", "n_nearreg", "coupling_entries",
+                                         "near_regular_pairs", "rank_min", "rank_max", "rank_mean",
+                                         "basis_bytes_fp64")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    H.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -74,6 +74,8 @@ typedef struct {
     int32_t reserved[3]; /* must be zero */
 } gca_params;
 
+#define GCA_NPHASE 9
+
 typedef struct gca_tree_s *gca_tree;   /* host object; gca_tree_destroy */
 typedef struct gca_h2_s *gca_h2;       /* owns its device memory; gca_destroy */
 
@@ -84,19 +86,22 @@ typedef struct {
     int64_t n_far_sym, n_near_sym;       /* the halves computed (t < s, t <= s) */
     int64_t n_ident, n_edge, n_vert, n_nearreg;   /* pair lists (unordered) */
     int64_t coupling_entries;            /* sum over t < s admissible of |t~| |s~| */
-    int64_t near_pairs;                  /* ordered regular pairs in near blocks, computed once per unordered pair */
+    int64_t near_pairs;                  /* pairs evaluated by the nearfield-block kernel (t <= s blocks, full tiles) */
+    int64_t near_regular_pairs;          /* unordered regular pairs inside near blocks (algorithmic count) */
     int64_t rank_min, rank_max;
     double rank_mean;
     int64_t basis_bytes_fp64;            /* leaf V + transfers E, FP64 */
     double build_ms;                     /* wall time of gca_build (host + device, synchronised) */
-    double phase_ms[8];                  /* last matvec, per phase (HIP events):
-                                            0 forward, 1 coupling, 2 backward+gather,
-                                            3 nearfield regular, 4 near-regular list,
-                                            5 touching, 6 permute in, 7 total */
+    double phase_ms[GCA_NPHASE + 1];     /* last product's last right-hand side, HIP events on
+                                            its stream: 0 permute in, 1 forward transform,
+                                            2 coupling-block quadrature, 3 coupling reduction,
+                                            4 backward transform, 5 nearfield-block quadrature,
+                                            6 near-regular list, 7 touching lists (both only for
+                                            the first right-hand side), 8 gather, 9 total */
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
- * q_r 3, q_nr 5, q_s 4. */
+ * q_r 3, q_nr 4, q_s 4. */
 void gca_params_default(gca_params *p);
 
 /* Cluster tree over the triangles (Section 4's binary subdivision of index
@@ -174,6 +179,12 @@ gca_status gca_basis_export(gca_h2 h, int32_t *ranks, int32_t *pivots, double *b
 gca_status gca_basis_sizes(gca_h2 h, int64_t *n_pivots, int64_t *n_basis);
 
 gca_status gca_stats(gca_h2 h, gca_stats_t *out);
+
+/* Phase times (ms, HIP events on the stream of each product) of the last
+ * min(max_products, 64, products so far) single-right-hand-side products,
+ * oldest first: out[q * (GCA_NPHASE + 1) + k], k as in gca_stats_t.phase_ms.
+ * out may be NULL to query *count.  Synchronises with the last product. */
+gca_status gca_phase_times(gca_h2 h, int64_t max_products, double *out, int64_t *count);
 
 void gca_destroy(gca_h2 h);
 

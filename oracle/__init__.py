@@ -74,6 +74,8 @@ def _load():
     lib.orc_matvec_rows.argtypes = [P, I64, P, P, I64, P]
     lib.orc_triangle_points.argtypes = [P, I32, P, P]
     lib.orc_gauss01.argtypes = [I32, P, P]
+    lib.orc_num_threads.restype = I32
+    lib.orc_num_threads.argtypes = []
     lib.orc_ss_moment.restype = D
     lib.orc_ss_moment.argtypes = [I32, I32, I32, I32, I32, I32]
     _lib = lib
@@ -91,6 +93,11 @@ def gauss01(q: int):
     w = np.zeros(q)
     lib.orc_gauss01(q, _ptr(x), _ptr(w))
     return x, w
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(_load().orc_num_threads())
 
 
 def ss_moment(kase: int, q: int, a: int, b: int, c: int, d: int) -> float:

@@ -38,6 +38,7 @@
  * matrix is symmetric by construction.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -95,6 +96,9 @@ void orc_gauss01(int q, double *x, double *w)
         w[q - 1 - i] = 1.0 / ((1.0 - t * t) * dp * dp);
     }
 }
+
+/* Number of OpenMP threads the parallel loops use. */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 static int cmp_i32(const void *a, const void *b)
 {

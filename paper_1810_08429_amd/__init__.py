@@ -24,6 +24,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgca.so")
 
 FP64, MIXED = 0, 1
+PHASES = ["permute", "forward", "coupling_blocks", "coupling_reduce", "backward", "near_blocks",
+          "near_regular", "touching", "gather", "total"]
 STATUS = {0: "GCA_OK", -1: "GCA_EINVAL", -2: "GCA_ENOMEM", -3: "GCA_EHIP", -4: "GCA_EMESH",
           -5: "GCA_ENOTSPD", -6: "GCA_ENOCONV", -7: "GCA_EINTERNAL"}
 
@@ -31,7 +33,7 @@ EXPORTED = [
     "gca_params_default", "gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_tree_destroy",
     "gca_block_tree",
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
-    "gca_destroy", "gca_last_error",
+    "gca_destroy", "gca_last_error", "gca_phase_times",
 ]
 
 
@@ -56,9 +58,10 @@ class _Params(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "n", "nv", "n_clusters", "n_leaves", "depth", "n_far", "n_near", "n_far_sym", "n_near_sym",
-        "n_ident", "n_edge", "n_vert", "n_nearreg", "coupling_entries", "near_pairs", "rank_min",
+        "n_ident", "n_edge", "n_vert", "n_nearreg", "coupling_entries", "near_pairs", "near_regular_pairs",
+        "rank_min",
         "rank_max")] + [("rank_mean", ctypes.c_double), ("basis_bytes_fp64", ctypes.c_int64),
-                        ("build_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 8)]
+                        ("build_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 10)]
 
 
 _lib = None
@@ -87,13 +90,14 @@ def lib():
     L.gca_basis_sizes.argtypes = [P, P, P]
     L.gca_basis_export.argtypes = [P, P, P, P]
     L.gca_stats.argtypes = [P, P]
+    L.gca_phase_times.argtypes = [P, I64, P, P]
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
     L.gca_last_error.argtypes = []
     L.gca_last_error.restype = ctypes.c_char_p
     for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
                  "h2_matvec",
-                 "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats"):
+                 "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -112,7 +116,7 @@ class Params:
     green_m: int = 3
     q_A: int = 3
     q_r: int = 3
-    q_nr: int = 5
+    q_nr: int = 4
     q_s: int = 4
 
     def _c(self):
@@ -242,5 +246,13 @@ class H2:
         s = _Stats()
         _check(lib().gca_stats(self.h, ctypes.byref(s)))
         out = {k: getattr(s, k) for k, _ in _Stats._fields_ if k != "phase_ms"}
-        out["phase_ms"] = list(s.phase_ms)
+        out["phase_ms"] = dict(zip(PHASES, list(s.phase_ms)))
         return out
+
+    def phase_times(self, max_products=64):
+        """Per-product phase times (ms) of the last products, shape (count, 10)."""
+        cnt = ctypes.c_int64()
+        _check(lib().gca_phase_times(self.h, int(max_products), None, ctypes.byref(cnt)))
+        out = np.zeros((max(cnt.value, 1), len(PHASES)))
+        _check(lib().gca_phase_times(self.h, int(max_products), out.ctypes.data, ctypes.byref(cnt)))
+        return out[:cnt.value]

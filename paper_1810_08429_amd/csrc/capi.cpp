@@ -49,7 +49,8 @@ void free_all(gca_h2_s *h)
     for (void *p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
     if (h->events)
-        for (auto &e : h->ev) (void)hipEventDestroy(e);
+        for (auto &r : h->ev)
+            for (auto &e : r) (void)hipEventDestroy(e);
     h->events = false;
 }
 
@@ -454,7 +455,8 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     GCA_TRY(dalloc(h, &h->d_cpartf, h->n_cslot_total));
     GCA_TRY(dalloc(h, &h->d_npart, h->n_nslot_total));
     GCA_TRY(dalloc(h, &h->d_npartf, h->n_nslot_total));
-    for (auto &e : h->ev) GCA_HIP_TRY(hipEventCreate(&e));
+    for (auto &r : h->ev)
+        for (auto &e : r) GCA_HIP_TRY(hipEventCreate(&e));
     h->events = true;
     GCA_HIP_TRY(hipStreamSynchronize(s));
 
@@ -476,10 +478,15 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     st.n_nearreg = h->pl.off[4] - h->pl.off[3];
     for (size_t b = 0; b < h->blk.far_t.size(); ++b)
         st.coupling_entries += (int64_t)h->rank[h->blk.far_t[b]] * h->rank[h->blk.far_s[b]];
+    int64_t unordered = 0;
     for (size_t b = 0; b < h->blk.near_t.size(); ++b) {
         const Node &a = nodes[h->blk.near_t[b]], &c = nodes[h->blk.near_s[b]];
-        st.near_pairs += (int64_t)(a.end - a.begin) * (c.end - c.begin);
+        const int64_t na = a.end - a.begin, ncc = c.end - c.begin;
+        st.near_pairs += na * ncc;
+        unordered += (h->blk.near_t[b] == h->blk.near_s[b]) ? na * (na + 1) / 2 : na * ncc;
     }
+    // every non-regular pair (touching or near-regular) lies in a near block
+    st.near_regular_pairs = unordered - (int64_t)h->pl.a.size();
     st.rank_min = INT64_MAX;
     double rs = 0;
     for (int c = 0; c < nc; ++c) {
@@ -504,30 +511,32 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     T *npart = f32 ? (T *)h->d_npartf : (T *)h->d_npart;
     T *pnr = f32 ? (T *)h->d_pvalf : (T *)(h->d_pval + h->pl.off[3]);
     hipError_t e;
-    if (h->events) (void)hipEventRecord(h->ev[0], s);
+    // phase events: ev[slot][k] before phase k, ev[slot][GCA_NPHASE] after the last one
+    const int slot = (int)(h->n_products % gca_h2_s::RING);
+    auto mark = [&](int k) {
+        if (h->events) (void)hipEventRecord(h->ev[slot][k], s);
+    };
+    mark(0);
     if ((e = launch_permute_in<T>(x, h->d_perm, h->n, xp, f32 ? h->d_xp : nullptr, s)) != hipSuccess) return e;
-    if (h->events) (void)hipEventRecord(h->ev[1], s);
+    mark(1);
     if ((e = launch_forward<T>(h, xp, xh, s)) != hipSuccess) return e;
-    if (h->events) (void)hipEventRecord(h->ev[2], s);
-    if ((e = launch_coupling<T>(h, xh, cpart, yh, s)) != hipSuccess) return e;
-    if (h->events) (void)hipEventRecord(h->ev[3], s);
+    mark(2);
+    if ((e = launch_far_blocks<T>(h, xh, cpart, s)) != hipSuccess) return e;
+    mark(3);
+    if ((e = launch_coupling_reduce<T>(h, cpart, yh, s)) != hipSuccess) return e;
+    mark(4);
     if ((e = launch_backward<T>(h, yh, s)) != hipSuccess) return e;
-    if (h->events) (void)hipEventRecord(h->ev[4], s);
+    mark(5);
     if ((e = launch_near<T>(h, xp, npart, s)) != hipSuccess) return e;
-    if (h->events) (void)hipEventRecord(h->ev[5], s);
-    if (first) {
-        if ((e = launch_nearreg<T>(h, pnr, s)) != hipSuccess) return e;
-    }
-    if (h->events) (void)hipEventRecord(h->ev[6], s);
-    if (first) {
-        if ((e = launch_touching(h, h->d_pval, s)) != hipSuccess) return e;
-    }
-    if (h->events) (void)hipEventRecord(h->ev[7], s);
+    mark(6);
+    if (first && (e = launch_nearreg<T>(h, pnr, s)) != hipSuccess) return e;
+    mark(7);
+    if (first && (e = launch_touching(h, h->d_pval, s)) != hipSuccess) return e;
+    mark(8);
     if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, pnr, y, s)) != hipSuccess) return e;
-    if (h->events) {
-        (void)hipEventRecord(h->ev[8], s);
-        h->timed = true;
-    }
+    mark(9);
+    h->timed = h->events;
+    h->n_products++;
     return hipSuccess;
 }
 
@@ -545,7 +554,7 @@ void gca_params_default(gca_params *p)
     p->green_m = 3;
     p->q_A = 3;
     p->q_r = 3;
-    p->q_nr = 5;
+    p->q_nr = 4;
     p->q_s = 4;
 }
 
@@ -793,16 +802,37 @@ gca_status gca_stats(gca_h2 h, gca_stats_t *out)
     if (!h || !out) return set_error(GCA_EINVAL, "NULL argument");
     *out = h->st;
     if (h->events && h->timed) {
-        // the phase events of the last matrix-vector product
-        GCA_HIP_TRY(hipEventSynchronize(h->ev[8]));
+        const int slot = (int)((h->n_products - 1) % gca_h2_s::RING);
+        GCA_HIP_TRY(hipEventSynchronize(h->ev[slot][GCA_NPHASE]));
         float ms;
-        const int idx[8][2] = {{1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {0, 1}, {0, 8}};
-        for (int k = 0; k < 8; ++k) {
-            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[idx[k][0]], h->ev[idx[k][1]]));
+        for (int k = 0; k < GCA_NPHASE; ++k) {
+            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][k], h->ev[slot][k + 1]));
             out->phase_ms[k] = ms;
         }
-        GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[7], h->ev[8]));   // gather belongs to phase 2
-        out->phase_ms[2] += ms;
+        GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][0], h->ev[slot][GCA_NPHASE]));
+        out->phase_ms[GCA_NPHASE] = ms;
+    }
+    return GCA_OK;
+}
+
+gca_status gca_phase_times(gca_h2 h, int64_t max_products, double *out, int64_t *count)
+{
+    clear_error();
+    if (!h || !count) return set_error(GCA_EINVAL, "NULL argument");
+    int64_t c = std::min<int64_t>({h->n_products, (int64_t)gca_h2_s::RING, std::max<int64_t>(max_products, 0)});
+    *count = c;
+    if (!c || !out) return GCA_OK;
+    const int last = (int)((h->n_products - 1) % gca_h2_s::RING);
+    GCA_HIP_TRY(hipEventSynchronize(h->ev[last][GCA_NPHASE]));
+    for (int64_t q = 0; q < c; ++q) {
+        const int slot = (int)((h->n_products - c + q) % gca_h2_s::RING);
+        float ms;
+        for (int k = 0; k < GCA_NPHASE; ++k) {
+            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][k], h->ev[slot][k + 1]));
+            out[q * (GCA_NPHASE + 1) + k] = ms;
+        }
+        GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][0], h->ev[slot][GCA_NPHASE]));
+        out[q * (GCA_NPHASE + 1) + GCA_NPHASE] = ms;
     }
     return GCA_OK;
 }

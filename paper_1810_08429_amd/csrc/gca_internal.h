@@ -191,7 +191,9 @@ struct gca_h2_s {
     double gl_x[32], gl_w[32];
     double gs_x[32], gs_w[32];       // Sauter-Schwab order q_s
 
-    hipEvent_t ev[9] = {};
+    static constexpr int RING = 64;  // products whose phase events are retained
+    hipEvent_t ev[RING][GCA_NPHASE + 1] = {};
+    int64_t n_products = 0;
     bool events = false;
     bool timed = false;              // phase events hold a recorded product
     gca_stats_t st{};
@@ -217,7 +219,9 @@ hipError_t launch_permute_in(const double *x, const int32_t *perm, int64_t n, T 
 template <typename T>
 hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s);
 template <typename T>
-hipError_t launch_coupling(gca_h2_s *h, const T *xh, T *cpart, T *yh, hipStream_t s);
+hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s);
+template <typename T>
+hipError_t launch_coupling_reduce(gca_h2_s *h, const T *cpart, T *yh, hipStream_t s);
 template <typename T>
 hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s);
 template <typename T>

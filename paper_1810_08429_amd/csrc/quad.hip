@@ -268,9 +268,6 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
 }
 
 template <typename T>
-hipError_t launch_coupling(gca_h2_s *h, const T *xh, T *cpart, T *yh, hipStream_t s);
-
-template <typename T>
 hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
 {
     const int nb = (int)h->blk.far_t.size();

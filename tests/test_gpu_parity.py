@@ -29,10 +29,15 @@ def gca():
     return g
 
 
+def orders(gca):
+    p = gca.Params()
+    return (p.q_r, p.q_nr, p.q_s)
+
+
 @pytest.fixture(scope="module")
-def c1(orc):
+def c1(orc, gca):
     m = synth.icosphere(3)
-    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    ent = orc.Entries(m.verts, m.tris, *orders(gca))
     G = ent.dense()
     return m, ent, G
 
@@ -124,7 +129,7 @@ def test_h2_matches_oracle_step_by_step_on_jittered_mesh(torch, gca, orc):
     ranks and bases equal the oracle's, and so does the product."""
     base = synth.icosphere(3)
     m = synth.jitter(base, 0.02 * synth.mean_edge_length(base), seed=7)
-    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    ent = orc.Entries(m.verts, m.tris, *orders(gca))
     ho = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, m=3, eps=1e-5, ent=ent)
     H = build(gca, m, 32, eta=2.0, eps=1e-5)
     ranks, piv, basis = H.basis()
@@ -171,7 +176,7 @@ def test_sphere_constant_potential_on_gpu(torch, gca, orc):
     area = 0.5 * np.linalg.norm(np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]), axis=1)
     y = H.matvec(torch.ones(m.nt, dtype=torch.float64, device="cuda")).cpu().numpy() / area
     assert np.abs(y - 1).max() < 2e-3
-    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    ent = orc.Entries(m.verts, m.tris, *orders(gca))
     rows = np.arange(0, m.nt, 97)
     ref = ent.matvec_rows(rows, np.ones(m.nt)) / area[rows]
     assert np.abs(y[rows] - ref).max() < 1e-5
@@ -184,7 +189,7 @@ def test_larger_sphere_sampled_rows(torch, gca, orc):
     H = build(gca, m, 64, eta=2.0, eps=1e-5)
     X = synth.rhs_normal(m.nt, 16, seed=0)
     Y = H.matvec(torch.tensor(X, device="cuda")).cpu().numpy()
-    ent = orc.Entries(m.verts, m.tris, 3, 5, 4)
+    ent = orc.Entries(m.verts, m.tris, *orders(gca))
     rows = np.random.default_rng(2).choice(m.nt, 48, replace=False)
     ref = ent.matvec_rows(rows, X)
     rel = np.linalg.norm(Y[rows] - ref) / np.linalg.norm(ref)
