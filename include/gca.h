@@ -92,6 +92,11 @@ typedef struct {
     double rank_mean;
     int64_t basis_bytes_fp64;            /* leaf V + transfers E, FP64 */
     double build_ms;                     /* wall time of gca_build (host + device, synchronised) */
+    double setup_ms[8];                  /* parts of build_ms: 0 mesh checks + adjacency,
+                                            1 pair lists, 2 block tree + list checks,
+                                            3 geometry upload + quadrature points,
+                                            4 nested basis (Green factor + ACA, all levels),
+                                            5 block slots, lists and workspaces, 6-7 unused */
     double phase_ms[GCA_NPHASE + 1];     /* last product's last right-hand side, HIP events on
                                             its stream: 0 permute in, 1 forward transform,
                                             2 coupling-block quadrature, 3 coupling reduction,
@@ -157,6 +162,25 @@ gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p,
  * unknown precision), GCA_EHIP. */
 gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t ld,
                      int32_t precision, void *stream);
+
+/* Solves G~ u = f by conjugate gradients on the mixed-precision product
+ * (inner iterations, stopped when the inner residual falls below
+ * inner_rtol times its start) inside FP64 iterative refinement: each outer
+ * step forms r = f - G~ u with the FP64 product and adds the inner
+ * correction.  Stops when ||f - G~ u||_2 <= rtol ||f||_2 (FP64 product).
+ * The solved equation is the one the paper's boundary element method leads
+ * to (Section 1; the single-layer system for exterior electrostatics).
+ * f, u: device FP64, n entries, original triangle order; u is overwritten
+ * (the start is u = 0); f and u must not overlap.
+ * iters_out (host, may be NULL): [0] outer refinement steps, [1] inner CG
+ * iterations in total.  relres_out (host, may be NULL): final relative
+ * FP64 residual.  Synchronises the stream once per iteration.
+ * Errors: GCA_EINVAL; GCA_ENOTSPD if CG meets p^T G~ p <= 0; GCA_ENOCONV if
+ * max_outer steps do not reach rtol (u then holds the last iterate);
+ * GCA_ENOMEM; GCA_EHIP. */
+gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, int32_t max_outer,
+                             double inner_rtol, int32_t max_inner, int32_t *iters_out, double *relres_out,
+                             void *stream);
 
 /* Galerkin entries g_{I[k], J[k]} (Eq. G_def) for m pairs, computed by the
  * same device quadrature the matrix-vector product uses (the pair's Sauter

@@ -33,7 +33,7 @@ EXPORTED = [
     "gca_params_default", "gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_tree_destroy",
     "gca_block_tree",
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
-    "gca_destroy", "gca_last_error", "gca_phase_times",
+    "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined",
 ]
 
 
@@ -61,7 +61,8 @@ class _Stats(ctypes.Structure):
         "n_ident", "n_edge", "n_vert", "n_nearreg", "coupling_entries", "near_pairs", "near_regular_pairs",
         "rank_min",
         "rank_max")] + [("rank_mean", ctypes.c_double), ("basis_bytes_fp64", ctypes.c_int64),
-                        ("build_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 10)]
+                        ("build_ms", ctypes.c_double), ("setup_ms", ctypes.c_double * 8),
+                        ("phase_ms", ctypes.c_double * 10)]
 
 
 _lib = None
@@ -90,6 +91,7 @@ def lib():
     L.gca_basis_sizes.argtypes = [P, P, P]
     L.gca_basis_export.argtypes = [P, P, P, P]
     L.gca_stats.argtypes = [P, P]
+    L.gca_solve_refined.argtypes = [P, P, P, D, I32, D, I32, P, P, P]
     L.gca_phase_times.argtypes = [P, I64, P, P]
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
@@ -97,7 +99,8 @@ def lib():
     L.gca_last_error.restype = ctypes.c_char_p
     for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
                  "h2_matvec",
-                 "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times"):
+                 "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
+                 "gca_solve_refined"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -149,9 +152,12 @@ class Tree:
         _check(lib().gca_tree_build(ctypes.byref(self._m.c), int(leaf), ctypes.byref(self.h)))
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().gca_tree_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().gca_tree_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
 
     def export(self):
         nc, depth = ctypes.c_int64(), ctypes.c_int64()
@@ -194,7 +200,10 @@ class H2:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def matvec_into(self, x, y, precision=FP64, stream=None):
         """y = G~ x for torch cuda float64 tensors (n,) or (n, nrhs) column-major
@@ -219,6 +228,20 @@ class H2:
             xx = x.t().contiguous().t()
             y = torch.empty_like(xx.t()).t()
         return self.matvec_into(xx, y, precision, stream)
+
+    def solve(self, f, rtol=1e-8, max_outer=20, inner_rtol=1e-3, max_inner=500, stream=None):
+        """u with ||f - G~ u|| <= rtol ||f|| (mixed CG inside FP64 refinement).
+        Returns (u, outer steps, inner iterations, relative residual)."""
+        import torch
+        f = f.contiguous()
+        assert f.dtype == torch.float64 and f.is_cuda and f.shape == (self.n,)
+        u = torch.empty_like(f)
+        it = (ctypes.c_int32 * 2)()
+        rel = ctypes.c_double()
+        _check(lib().gca_solve_refined(self.h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                       float(rtol), int(max_outer), float(inner_rtol), int(max_inner), it,
+                                       ctypes.byref(rel), _stream_ptr(stream)))
+        return u, it[0], it[1], rel.value
 
     def entries(self, I, J, precision=FP64, stream=None):
         import torch
@@ -245,7 +268,9 @@ class H2:
     def stats(self):
         s = _Stats()
         _check(lib().gca_stats(self.h, ctypes.byref(s)))
-        out = {k: getattr(s, k) for k, _ in _Stats._fields_ if k != "phase_ms"}
+        out = {k: getattr(s, k) for k, _ in _Stats._fields_ if k not in ("phase_ms", "setup_ms")}
+        out["setup_ms"] = dict(zip(["mesh_adjacency", "pair_lists", "block_tree", "geometry", "basis",
+                                    "slots_lists"], list(s.setup_ms)[:6]))
         out["phase_ms"] = dict(zip(PHASES, list(s.phase_ms)))
         return out
 

@@ -281,8 +281,17 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     const int nc = (int)h->nc;
     const int64_t n = h->n;
 
+    double tm[8] = {0};
+    double tl = now_ms();
+    auto lap = [&](int k) {
+        double t = now_ms();
+        tm[k] += t - tl;
+        tl = t;
+    };
     GCA_TRY(build_adjacency(h->mesh, h->adj));
+    lap(0);
     GCA_TRY(build_pair_lists(h->mesh, h->adj, h->tree, h->pl));
+    lap(1);
     block_tree(h->tree, p->eta, h->blk);
 
     // clusters by level, leaves, leaf of each position
@@ -301,16 +310,25 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     }
     // every non-regular pair must lie in an inadmissible leaf block
     {
-        std::unordered_set<int64_t> nb;
+        const size_t nl = h->leaves.size();
+        std::vector<int64_t> ptr(nl + 1, 0);
+        for (size_t b = 0; b < h->blk.near_t.size(); ++b) ptr[leaf_index[h->blk.near_t[b]] + 1]++;
+        for (size_t l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
+        std::vector<int32_t> partner(ptr[nl]);
+        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
         for (size_t b = 0; b < h->blk.near_t.size(); ++b)
-            nb.insert((int64_t)h->blk.near_t[b] * nc + h->blk.near_s[b]);
+            partner[fill[leaf_index[h->blk.near_t[b]]]++] = h->blk.near_s[b];
+        for (size_t l = 0; l < nl; ++l) std::sort(partner.begin() + ptr[l], partner.begin() + ptr[l + 1]);
         for (size_t q = 0; q < h->pl.a.size(); ++q) {
             int32_t la = leaf_of[h->pl.a[q]], lb = leaf_of[h->pl.b[q]];
-            if (!nb.count((int64_t)std::min(la, lb) * nc + std::max(la, lb)))
+            int32_t t = std::min(la, lb), u = std::max(la, lb);
+            const int32_t li = leaf_index[t];
+            if (!std::binary_search(partner.begin() + ptr[li], partner.begin() + ptr[li + 1], u))
                 return set_error(GCA_EINVAL, "a touching or near-regular pair lies in an admissible block "
                                              "(eta too large for this mesh)");
         }
     }
+    lap(2);
 
     gauss_legendre01(p->green_m, h->gl_x, h->gl_w);
     gauss_legendre01(p->q_s, h->gs_x, h->gs_w);
@@ -363,8 +381,11 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     else
         GCA_TRY(tri_pts(p->q_A, &h->d_qA));
 
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+    lap(3);
     // nested basis (Green factor + cross approximation, level by level)
     GCA_TRY(build_basis(h, s));
+    lap(4);
     GCA_TRY(upload_new(h, &h->d_piv, h->pivots, s));
     GCA_TRY(upload_new(h, &h->d_piv_off, h->piv_off, s));
     GCA_TRY(upload_new(h, &h->d_rank, h->rank, s));
@@ -439,10 +460,15 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     GCA_TRY(upload_new(h, &h->d_pcode, h->pl.code, s));
     GCA_TRY(upload_new(h, &h->d_prow_ptr, h->pl.row_ptr, s));
     GCA_TRY(upload_new(h, &h->d_prow_other, h->pl.row_other, s));
-    GCA_TRY(upload_new(h, &h->d_prow_pair, h->pl.row_pair, s));
-    const int64_t npairs = (int64_t)h->pl.a.size();
-    GCA_TRY(dalloc(h, &h->d_pval, npairs));
-    GCA_TRY(dalloc(h, &h->d_pvalf, h->pl.off[4] - h->pl.off[3]));
+    GCA_TRY(upload_new(h, &h->d_tptr, h->pl.t_ptr, s));
+    GCA_TRY(upload_new(h, &h->d_nptr, h->pl.n_ptr, s));
+    GCA_TRY(upload_new(h, &h->d_tother, h->pl.t_other, s));
+    GCA_TRY(upload_new(h, &h->d_nother, h->pl.n_other, s));
+    GCA_TRY(upload_new(h, &h->d_slot_a, h->pl.slot_a, s));
+    GCA_TRY(upload_new(h, &h->d_slot_b, h->pl.slot_b, s));
+    GCA_TRY(dalloc(h, &h->d_tval, h->pl.t_other.size()));
+    GCA_TRY(dalloc(h, &h->d_nval, h->pl.n_other.size()));
+    GCA_TRY(dalloc(h, &h->d_nvalf, h->pl.n_other.size()));
 
     // workspaces of the matrix-vector product
     GCA_TRY(dalloc(h, &h->d_xp, n));
@@ -459,6 +485,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         for (auto &e : r) GCA_HIP_TRY(hipEventCreate(&e));
     h->events = true;
     GCA_HIP_TRY(hipStreamSynchronize(s));
+    lap(5);
 
     // statistics
     gca_stats_t &st = h->st;
@@ -497,6 +524,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     st.rank_mean = rs / nc;
     st.basis_bytes_fp64 = 8 * (h->n_v + h->n_e);
     st.build_ms = now_ms() - t0;
+    for (int k = 0; k < 8; ++k) st.setup_ms[k] = tm[k];
     return GCA_OK;
 }
 
@@ -509,7 +537,7 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     T *yh = f32 ? (T *)h->d_yhf : (T *)h->d_yh;
     T *cpart = f32 ? (T *)h->d_cpartf : (T *)h->d_cpart;
     T *npart = f32 ? (T *)h->d_npartf : (T *)h->d_npart;
-    T *pnr = f32 ? (T *)h->d_pvalf : (T *)(h->d_pval + h->pl.off[3]);
+    T *nval = f32 ? (T *)h->d_nvalf : (T *)h->d_nval;
     hipError_t e;
     // phase events: ev[slot][k] before phase k, ev[slot][GCA_NPHASE] after the last one
     const int slot = (int)(h->n_products % gca_h2_s::RING);
@@ -529,11 +557,11 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     mark(5);
     if ((e = launch_near<T>(h, xp, npart, s)) != hipSuccess) return e;
     mark(6);
-    if (first && (e = launch_nearreg<T>(h, pnr, s)) != hipSuccess) return e;
+    if (first && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
     mark(7);
-    if (first && (e = launch_touching(h, h->d_pval, s)) != hipSuccess) return e;
+    if (first && (e = launch_touching(h, h->d_tval, s)) != hipSuccess) return e;
     mark(8);
-    if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, pnr, y, s)) != hipSuccess) return e;
+    if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, nval, y, s)) != hipSuccess) return e;
     mark(9);
     h->timed = h->events;
     h->n_products++;
@@ -770,6 +798,90 @@ gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, 
     (void)hipFree(t64);
     (void)hipFree(t32);
     return st;
+}
+
+gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, int32_t max_outer,
+                             double inner_rtol, int32_t max_inner, int32_t *iters_out, double *relres_out,
+                             void *stream)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (!f || !u) return set_error(GCA_EINVAL, "f or u is NULL");
+    if (!(rtol > 0 && rtol < 1) || !(inner_rtol > 0 && inner_rtol < 1))
+        return set_error(GCA_EINVAL, "tolerances must be in (0, 1)");
+    if (max_outer < 1 || max_inner < 1) return set_error(GCA_EINVAL, "iteration limits must be >= 1");
+    const int64_t n = h->n;
+    {
+        const char *fb = (const char *)f, *fe = (const char *)(f + n);
+        const char *ub = (const char *)u, *ue = (const char *)(u + n);
+        if (fb < ue && ub < fe) return set_error(GCA_EINVAL, "f and u overlap");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!h->d_sv) {
+        GCA_TRY(dalloc(h, &h->d_sv, 5 * (size_t)n));
+        GCA_TRY(dalloc(h, &h->d_dotp, 1025));
+    }
+    double *r = h->d_sv, *d = r + n, *res = d + n, *p = res + n, *q = p + n;
+    double *dres = h->d_dotp + 1024;
+    auto dot = [&](const double *a, const double *b, double *out) -> gca_status {
+        GCA_HIP_TRY(launch_dot(a, b, n, h->d_dotp, dres, s));
+        GCA_HIP_TRY(hipMemcpyAsync(out, dres, sizeof(double), hipMemcpyDeviceToHost, s));
+        GCA_HIP_TRY(hipStreamSynchronize(s));
+        return GCA_OK;
+    };
+    auto product = [&](const double *x, double *y, int prec) -> gca_status {
+        hipError_t e = prec == GCA_FP64 ? matvec_one<double>(h, x, y, true, s) : matvec_one<float>(h, x, y, true, s);
+        if (e != hipSuccess) return set_error(GCA_EHIP, std::string("product in solve: ") + hipGetErrorString(e));
+        return GCA_OK;
+    };
+    double ff;
+    GCA_TRY(dot(f, f, &ff));
+    const double nf = std::sqrt(ff);
+    GCA_HIP_TRY(launch_fill(u, 0.0, n, s));
+    int32_t outer = 0, inner = 0;
+    double relres = nf > 0 ? 1.0 : 0.0;
+    if (nf > 0) {
+        for (;;) {
+            // FP64 refinement residual r = f - G~ u
+            GCA_TRY(product(u, q, GCA_FP64));
+            GCA_HIP_TRY(launch_sub(f, q, r, n, s));
+            double rr;
+            GCA_TRY(dot(r, r, &rr));
+            relres = std::sqrt(rr) / nf;
+            if (relres <= rtol || outer >= max_outer) break;
+            ++outer;
+            // inner CG on the mixed-precision operator: G~_mixed d = r
+            GCA_HIP_TRY(launch_fill(d, 0.0, n, s));
+            GCA_HIP_TRY(hipMemcpyAsync(res, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            GCA_HIP_TRY(hipMemcpyAsync(p, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            double rho = rr;
+            const double stop = inner_rtol * std::sqrt(rr);
+            for (int it = 0; it < max_inner; ++it) {
+                GCA_TRY(product(p, q, GCA_MIXED));
+                double pq;
+                GCA_TRY(dot(p, q, &pq));
+                ++inner;
+                if (!(pq > 0))
+                    return set_error(GCA_ENOTSPD, "conjugate gradients met p^T G p <= 0 (operator not positive definite)");
+                const double alpha = rho / pq;
+                GCA_HIP_TRY(launch_cg_update(alpha, p, q, d, res, n, s));
+                double rho_new;
+                GCA_TRY(dot(res, res, &rho_new));
+                if (std::sqrt(rho_new) <= stop) break;
+                GCA_HIP_TRY(launch_axpby(1.0, res, rho_new / rho, p, n, s));
+                rho = rho_new;
+            }
+            GCA_HIP_TRY(launch_axpby(1.0, d, 1.0, u, n, s));
+        }
+    }
+    if (iters_out) {
+        iters_out[0] = outer;
+        iters_out[1] = inner;
+    }
+    if (relres_out) *relres_out = relres;
+    if (relres > rtol)
+        return set_error(GCA_ENOCONV, "refinement stopped at relative residual " + std::to_string(relres));
+    return GCA_OK;
 }
 
 gca_status gca_basis_sizes(gca_h2 h, int64_t *n_pivots, int64_t *n_basis)

@@ -91,6 +91,13 @@ struct PairLists {
     // row CSR over positions: for position i, entries (other position, pair id)
     std::vector<int64_t> row_ptr;
     std::vector<int32_t> row_other, row_pair;
+    // value CSRs used by the product: touching pairs (classes 0-2) and
+    // near-regular pairs (class 3) separately; pair p writes its value to
+    // slot_a[p] (row of its first triangle) and slot_b[p] (row of the second,
+    // -1 for identical pairs)
+    std::vector<int64_t> t_ptr, n_ptr;
+    std::vector<int32_t> t_other, n_other;
+    std::vector<int32_t> slot_a, slot_b;
 };
 gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t,
                             PairLists &pl);
@@ -173,9 +180,17 @@ struct gca_h2_s {
     // pair lists
     int32_t *d_pa = nullptr, *d_pb = nullptr, *d_pcode = nullptr;
     int64_t *d_prow_ptr = nullptr;
-    int32_t *d_prow_other = nullptr, *d_prow_pair = nullptr;
-    double *d_pval = nullptr;        // pair values (FP64)
-    float *d_pvalf = nullptr;        // near-regular values in the mixed path
+    int32_t *d_prow_other = nullptr;
+    int64_t *d_tptr = nullptr, *d_nptr = nullptr;
+    int32_t *d_tother = nullptr, *d_nother = nullptr;
+    int32_t *d_slot_a = nullptr, *d_slot_b = nullptr;
+    double *d_tval = nullptr;        // touching values, row CSR (FP64)
+    double *d_nval = nullptr;        // near-regular values, row CSR (FP64 path)
+    float *d_nvalf = nullptr;        // near-regular values, row CSR (mixed path)
+
+    // solver workspaces (allocated by the first solve)
+    double *d_sv = nullptr;          // 5 x n: r, d, res, p, q
+    double *d_dotp = nullptr;        // dot partials (1024) + result
 
     // per-matvec workspaces
     double *d_xp = nullptr;          // permuted input (FP64) n
@@ -226,12 +241,20 @@ template <typename T>
 hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s);
 template <typename T>
 hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s);
-hipError_t launch_touching(gca_h2_s *h, double *pval, hipStream_t s);
+hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s);
 template <typename T>
-hipError_t launch_nearreg(gca_h2_s *h, T *pval, hipStream_t s);
+hipError_t launch_nearreg(gca_h2_s *h, T *nval, hipStream_t s);
 template <typename T>
 hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *yh, const T *npart,
-                         const T *pval_nr, double *y, hipStream_t s);
+                         const T *nval, double *y, hipStream_t s);
+
+// vector kernels of the solver (solve.hip)
+hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t s);
+hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
+hipError_t launch_cg_update(double alpha, const double *p, const double *q, double *d, double *r, int64_t n,
+                            hipStream_t s);
+hipError_t launch_sub(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
+hipError_t launch_fill(double *y, double v, int64_t n, hipStream_t s);
 
 // Entries for pairs sorted by class on the host (gca_entries).
 struct EntryJobs {

@@ -149,14 +149,16 @@ template hipError_t launch_backward<float>(gca_h2_s *, float *, hipStream_t);
 template hipError_t launch_backward<double>(gca_h2_s *, double *, hipStream_t);
 
 // Per leaf, thread per row: y|t^ = V_t yh_t + near partials + pair lists;
-// written back in the original triangle order.
+// written back in the original triangle order.  The touching values (FP64)
+// and near-regular values (T) are stored in row CSRs aligned with their
+// column indices, so each row streams its own entries.
 template <typename T>
 __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int32_t *node, const int32_t *rank,
                                                const int64_t *piv_off, const int64_t *v_off, const T *Vt,
                                                const T *yh, const int64_t *nslot_ptr, const int64_t *nslot,
-                                               const T *npart, const int64_t *prow_ptr, const int32_t *prow_other,
-                                               const int32_t *prow_pair, int64_t off_nr, const double *pval,
-                                               const T *pval_nr, const T *xp, const double *xp64,
+                                               const T *npart, const int64_t *tptr, const int32_t *tother,
+                                               const double *tval, const int64_t *nptr, const int32_t *nother,
+                                               const T *nval, const T *xp, const double *xp64,
                                                const int32_t *perm, double *y)
 {
     const int li = blockIdx.x;
@@ -170,27 +172,21 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
         for (int k = 0; k < r; ++k) acc += Vc[(int64_t)k * nr + i] * yc[k];
         for (int64_t q = nslot_ptr[li]; q < nslot_ptr[li + 1]; ++q) acc += npart[nslot[q] + i];
         const int pos = b + i;
+        for (int64_t q = nptr[pos]; q < nptr[pos + 1]; ++q) acc += nval[q] * xp[nother[q]];
         double acc64 = 0;
-        for (int64_t q = prow_ptr[pos]; q < prow_ptr[pos + 1]; ++q) {
-            const int p = prow_pair[q], o = prow_other[q];
-            if (p < off_nr)
-                acc64 += pval[p] * xp64[o];
-            else
-                acc += pval_nr[p - off_nr] * xp[o];
-        }
+        for (int64_t q = tptr[pos]; q < tptr[pos + 1]; ++q) acc64 += tval[q] * xp64[tother[q]];
         y[perm[pos]] = (double)acc + acc64;
     }
 }
 
 template <typename T>
 hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *yh, const T *npart,
-                         const T *pval_nr, double *y, hipStream_t s)
+                         const T *nval, double *y, hipStream_t s)
 {
     const T *Vt = std::is_same<T, float>::value ? (const T *)h->d_Vtf : (const T *)h->d_Vt;
     hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)h->leaves.size()), dim3(64), 0, s, h->d_leaves, h->d_node,
-                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_nslot_ptr, h->d_nslot, npart,
-                       h->d_prow_ptr, h->d_prow_other, h->d_prow_pair, h->pl.off[3], h->d_pval, pval_nr, xp, xp64,
-                       h->d_perm, y);
+                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_nslot_ptr, h->d_nslot, npart, h->d_tptr,
+                       h->d_tother, h->d_tval, h->d_nptr, h->d_nother, nval, xp, xp64, h->d_perm, y);
     return hipGetLastError();
 }
 template hipError_t launch_gather<float>(gca_h2_s *, const float *, const double *, const float *, const float *,

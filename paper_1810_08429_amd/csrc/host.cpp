@@ -3,7 +3,9 @@
 // diameters and distances are rounded exactly as written (the admissibility
 // test of Section 2 is a comparison of such values).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <cstring>
 #include <numeric>
 #include <utility>
@@ -161,7 +163,6 @@ struct TreeBuilder {
             nd.son[0] = nd.son[1] = -1;
             nd.parent = parent;
             nd.level = level;
-            box_of(b, e, nd);
         }
         t.depth = std::max(t.depth, level);
         if (e - b <= leaf) return me;
@@ -180,12 +181,18 @@ struct TreeBuilder {
                 axis = d;
             }
         const double *cc = cent.data();
-        std::sort(t.perm.begin() + b, t.perm.begin() + e, [cc, axis](int32_t x, int32_t y) {
+        auto less = [cc, axis](int32_t x, int32_t y) {
             double kx = cc[3 * (int64_t)x + axis], ky = cc[3 * (int64_t)y + axis];
             if (kx != ky) return kx < ky;
             return x < y;
-        });
+        };
+        // Same result as sorting the whole range by (coordinate, id) and cutting
+        // at the median: the partition needs only nth_element; a son that is a
+        // leaf keeps the sorted order, a son that is split sorts its own range.
         int32_t mid = b + (e - b) / 2;
+        std::nth_element(t.perm.begin() + b, t.perm.begin() + mid, t.perm.begin() + e, less);
+        if (mid - b <= leaf) std::sort(t.perm.begin() + b, t.perm.begin() + mid, less);
+        if (e - mid <= leaf) std::sort(t.perm.begin() + mid, t.perm.begin() + e, less);
         int32_t s0 = rec(b, mid, level + 1, me);
         int32_t s1 = rec(mid, e, level + 1, me);
         t.nodes[me].son[0] = s0;
@@ -217,6 +224,22 @@ gca_status tree_build(const Mesh &m, int32_t leaf, gca_tree_s &t)
             tb.cent[3 * i + d] = ((v0 + v1) + v2) / 3.0;
         }
     tb.rec(0, (int32_t)m.nt, 0, -1);
+    // boxes of the supports: leaves from their vertices, parents as the union of
+    // their sons' boxes (min / max are exact, so this equals a direct scan)
+    for (int64_t c = (int64_t)t.nodes.size() - 1; c >= 0; --c) {
+        Node &nd = t.nodes[c];
+        if (nd.son[0] < 0) {
+            tb.box_of(nd.begin, nd.end, nd);
+        } else {
+            const Node &a = t.nodes[nd.son[0]], &b = t.nodes[nd.son[1]];
+            for (int d = 0; d < 3; ++d) {
+                nd.lo[d] = std::min(a.lo[d], b.lo[d]);
+                nd.hi[d] = std::max(a.hi[d], b.hi[d]);
+            }
+            double e0 = nd.hi[0] - nd.lo[0], e1 = nd.hi[1] - nd.lo[1], e2 = nd.hi[2] - nd.lo[2];
+            nd.diam = std::sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+        }
+    }
     t.mesh_xyz = m.xyz;
     t.mesh_tri = m.tri;
     return GCA_OK;
@@ -344,32 +367,61 @@ gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_
     std::vector<int32_t> iperm(nt);
     for (int64_t p = 0; p < nt; ++p) iperm[t.perm[p]] = (int32_t)p;
 
-    // per class: (first original id, second original id, code), first < second
+    // per class: (first original id, second original id, code), first < second.
+    // Triangles are processed in contiguous chunks on several threads; the
+    // chunks are concatenated in order, so the lists do not depend on the
+    // thread count.
     struct P { int32_t i, j, code; };
-    std::vector<P> cls[4];
-    std::vector<int32_t> cand;
-    for (int64_t i = 0; i < nt; ++i) {
-        const int32_t *ti = &m.tri[3 * i];
-        cls[0].push_back(P{(int32_t)i, (int32_t)i, 0});
-        // candidates: triangles around the vertices of t_i and around their
-        // edge neighbours (covers touching and near-regular pairs)
-        cand.clear();
-        for (int k = 0; k < 3; ++k) {
-            for (int64_t q = adj.vt_ptr[ti[k]]; q < adj.vt_ptr[ti[k] + 1]; ++q) cand.push_back(adj.vt[q]);
-            for (int64_t e = adj.vv_ptr[ti[k]]; e < adj.vv_ptr[ti[k] + 1]; ++e) {
-                int32_t v = adj.vv[e];
-                for (int64_t q = adj.vt_ptr[v]; q < adj.vt_ptr[v + 1]; ++q) cand.push_back(adj.vt[q]);
+    const int nthr = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+    const int nchunk = (int)std::min<int64_t>(nt, 4 * nthr);
+    std::vector<std::array<std::vector<P>, 4>> part(nchunk);
+    std::atomic<int> next{0};
+    std::atomic<bool> dup{false};
+    auto worker = [&]() {
+        std::vector<int32_t> cand;
+        for (;;) {
+            const int c = next.fetch_add(1);
+            if (c >= nchunk) break;
+            const int64_t i0 = nt * c / nchunk, i1 = nt * (c + 1) / nchunk;
+            auto &cls = part[c];
+            for (int64_t i = i0; i < i1; ++i) {
+                const int32_t *ti = &m.tri[3 * i];
+                cls[0].push_back(P{(int32_t)i, (int32_t)i, 0});
+                // candidates: triangles around the vertices of t_i and around
+                // their edge neighbours (covers touching and near-regular pairs)
+                cand.clear();
+                for (int k = 0; k < 3; ++k) {
+                    for (int64_t q = adj.vt_ptr[ti[k]]; q < adj.vt_ptr[ti[k] + 1]; ++q) cand.push_back(adj.vt[q]);
+                    for (int64_t e = adj.vv_ptr[ti[k]]; e < adj.vv_ptr[ti[k] + 1]; ++e) {
+                        int32_t v = adj.vv[e];
+                        for (int64_t q = adj.vt_ptr[v]; q < adj.vt_ptr[v + 1]; ++q) cand.push_back(adj.vt[q]);
+                    }
+                }
+                std::sort(cand.begin(), cand.end());
+                cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+                for (int32_t j : cand) {
+                    if (j <= i) continue;
+                    int32_t code;
+                    int k = classify_pair(m, adj, (int32_t)i, j, &code);
+                    if (k == 0) dup = true;
+                    if (k >= 1 && k <= 3) cls[k].push_back(P{(int32_t)i, j, code});
+                }
             }
         }
-        std::sort(cand.begin(), cand.end());
-        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-        for (int32_t j : cand) {
-            if (j <= i) continue;
-            int32_t code;
-            int k = classify_pair(m, adj, (int32_t)i, j, &code);
-            if (k == 0) return set_error(GCA_EMESH, "duplicate triangle");
-            if (k <= 3) cls[k].push_back(P{(int32_t)i, j, code});
-        }
+    };
+    {
+        std::vector<std::thread> th;
+        for (int t = 1; t < nthr; ++t) th.emplace_back(worker);
+        worker();
+        for (auto &x : th) x.join();
+    }
+    if (dup) return set_error(GCA_EMESH, "duplicate triangle");
+    std::vector<P> cls[4];
+    for (int k = 0; k < 4; ++k) {
+        size_t tot = 0;
+        for (auto &pc : part) tot += pc[k].size();
+        cls[k].reserve(tot);
+        for (auto &pc : part) cls[k].insert(cls[k].end(), pc[k].begin(), pc[k].end());
     }
     pl.a.clear();
     pl.b.clear();
@@ -401,6 +453,38 @@ gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_
         if (a != b) {
             pl.row_other[fill[b]] = a;
             pl.row_pair[fill[b]++] = (int32_t)p;
+        }
+    }
+    // value CSRs (touching, near-regular): row entries in pair order
+    {
+        const int64_t nts = pl.off[3];   // touching pairs are classes 0..2
+        if (2 * np >= INT32_MAX) return set_error(GCA_EINVAL, "too many pairs for 32-bit slots");
+        pl.t_ptr.assign(nt + 1, 0);
+        pl.n_ptr.assign(nt + 1, 0);
+        for (int64_t p = 0; p < np; ++p) {
+            auto &ptr = p < nts ? pl.t_ptr : pl.n_ptr;
+            ptr[pl.a[p] + 1]++;
+            if (pl.a[p] != pl.b[p]) ptr[pl.b[p] + 1]++;
+        }
+        for (int64_t i = 0; i < nt; ++i) {
+            pl.t_ptr[i + 1] += pl.t_ptr[i];
+            pl.n_ptr[i + 1] += pl.n_ptr[i];
+        }
+        pl.t_other.assign(pl.t_ptr[nt], 0);
+        pl.n_other.assign(pl.n_ptr[nt], 0);
+        pl.slot_a.assign(np, -1);
+        pl.slot_b.assign(np, -1);
+        std::vector<int64_t> ft(pl.t_ptr.begin(), pl.t_ptr.end() - 1), fn(pl.n_ptr.begin(), pl.n_ptr.end() - 1);
+        for (int64_t p = 0; p < np; ++p) {
+            auto &f = p < nts ? ft : fn;
+            auto &other = p < nts ? pl.t_other : pl.n_other;
+            const int32_t a = pl.a[p], b = pl.b[p];
+            pl.slot_a[p] = (int32_t)f[a];
+            other[f[a]++] = b;
+            if (a != b) {
+                pl.slot_b[p] = (int32_t)f[b];
+                other[f[b]++] = a;
+            }
         }
     }
     // sort each row by the other position (the nearfield kernel builds masks from it)

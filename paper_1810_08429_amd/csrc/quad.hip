@@ -418,14 +418,22 @@ __device__ double touching_value(const double *xyz, const int32_t *tv, int pa, i
     return ss_vertex(P, Q, g);
 }
 
+// Value of pair p goes to out[sa[p]] and out[sb[p]] (sb < 0: none) when slot
+// maps are given (row CSR of the product), else to out[p].
 template <int KIND>
 __global__ void __launch_bounds__(256) k_touching(const double *xyz, const int32_t *tv, const int32_t *pa,
                                                   const int32_t *pb, const int32_t *code, int64_t np,
-                                                  GaussQ g, double *out)
+                                                  GaussQ g, const int32_t *sa, const int32_t *sb, double *out)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    out[p] = touching_value<KIND>(xyz, tv, pa[p], pb[p], code[p], g);
+    const double v = touching_value<KIND>(xyz, tv, pa[p], pb[p], code[p], g);
+    if (sa) {
+        out[sa[p]] = v;
+        if (sb[p] >= 0) out[sb[p]] = v;
+    } else {
+        out[p] = v;
+    }
 }
 
 static GaussQ make_gq(const double *x, const double *w, int q)
@@ -439,7 +447,7 @@ static GaussQ make_gq(const double *x, const double *w, int q)
     return g;
 }
 
-hipError_t launch_touching(gca_h2_s *h, double *pval, hipStream_t s)
+hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s)
 {
     GaussQ g = make_gq(h->gs_x, h->gs_w, h->prm.q_s);
     for (int kind = 0; kind < 3; ++kind) {
@@ -449,13 +457,13 @@ hipError_t launch_touching(gca_h2_s *h, double *pval, hipStream_t s)
         dim3 grid((unsigned)((np + 255) / 256)), blk(256);
         if (kind == 0)
             hipLaunchKernelGGL(k_touching<0>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
-                               h->d_pcode + b, np, g, pval + b);
+                               h->d_pcode + b, np, g, h->d_slot_a + b, h->d_slot_b + b, tval);
         else if (kind == 1)
             hipLaunchKernelGGL(k_touching<1>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
-                               h->d_pcode + b, np, g, pval + b);
+                               h->d_pcode + b, np, g, h->d_slot_a + b, h->d_slot_b + b, tval);
         else
             hipLaunchKernelGGL(k_touching<2>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
-                               h->d_pcode + b, np, g, pval + b);
+                               h->d_pcode + b, np, g, h->d_slot_a + b, h->d_slot_b + b, tval);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -496,23 +504,29 @@ __device__ T regular_pair(const double *q, int pa, int pb)
 
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_nearreg(const double *q, const int32_t *pa, const int32_t *pb, int64_t np,
-                                                 T *out)
+                                                 const int32_t *sa, const int32_t *sb, T *out)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    out[p] = regular_pair<T, P>(q, pa[p], pb[p]);
+    const T v = regular_pair<T, P>(q, pa[p], pb[p]);
+    if (sa) {
+        out[sa[p]] = v;
+        if (sb[p] >= 0) out[sb[p]] = v;
+    } else {
+        out[p] = v;
+    }
 }
 
 template <typename T>
 static hipError_t launch_regular_list(int P, const double *q, const int32_t *pa, const int32_t *pb, int64_t np,
-                                      T *out, hipStream_t s)
+                                      const int32_t *sa, const int32_t *sb, T *out, hipStream_t s)
 {
     if (np == 0) return hipSuccess;
     dim3 grid((unsigned)((np + 255) / 256)), blk(256);
     switch (P) {
 #define CASE(PP)                                                                              \
     case PP:                                                                                  \
-        hipLaunchKernelGGL((k_nearreg<T, PP>), grid, blk, 0, s, q, pa, pb, np, out);           \
+        hipLaunchKernelGGL((k_nearreg<T, PP>), grid, blk, 0, s, q, pa, pb, np, sa, sb, out);   \
         break;
         CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36) CASE(49)
 #undef CASE
@@ -523,11 +537,11 @@ static hipError_t launch_regular_list(int P, const double *q, const int32_t *pa,
 }
 
 template <typename T>
-hipError_t launch_nearreg(gca_h2_s *h, T *pval, hipStream_t s)
+hipError_t launch_nearreg(gca_h2_s *h, T *nval, hipStream_t s)
 {
     int64_t b = h->pl.off[3], e = h->pl.off[4];
-    return launch_regular_list<T>(h->prm.q_nr * h->prm.q_nr, h->d_qnr, h->d_pa + b, h->d_pb + b, e - b, pval,
-                                  s);
+    return launch_regular_list<T>(h->prm.q_nr * h->prm.q_nr, h->d_qnr, h->d_pa + b, h->d_pb + b, e - b,
+                                  h->d_slot_a + b, h->d_slot_b + b, nval, s);
 }
 
 template hipError_t launch_nearreg<float>(gca_h2_s *, float *, hipStream_t);
@@ -547,29 +561,29 @@ hipError_t launch_entry_jobs(gca_h2_s *h, const EntryJobs &j, double *tmp64, flo
         dim3 grid((unsigned)((np + 255) / 256)), blk(256);
         if (kind == 0)
             hipLaunchKernelGGL(k_touching<0>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
-                               np, g, tmp64 + b);
+                               np, g, nullptr, nullptr, tmp64 + b);
         else if (kind == 1)
             hipLaunchKernelGGL(k_touching<1>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
-                               np, g, tmp64 + b);
+                               np, g, nullptr, nullptr, tmp64 + b);
         else
             hipLaunchKernelGGL(k_touching<2>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
-                               np, g, tmp64 + b);
+                               np, g, nullptr, nullptr, tmp64 + b);
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int Pnr = h->prm.q_nr * h->prm.q_nr, Pr = h->prm.q_r * h->prm.q_r;
     if (precision == GCA_FP64) {
         err = launch_regular_list<double>(Pnr, h->d_qnr, j.pa + j.off[3], j.pb + j.off[3], j.off[4] - j.off[3],
-                                          tmp64 + j.off[3], s);
+                                          nullptr, nullptr, tmp64 + j.off[3], s);
         if (err != hipSuccess) return err;
         err = launch_regular_list<double>(Pr, h->d_qr, j.pa + j.off[4], j.pb + j.off[4], j.off[5] - j.off[4],
-                                          tmp64 + j.off[4], s);
+                                          nullptr, nullptr, tmp64 + j.off[4], s);
     } else {
         err = launch_regular_list<float>(Pnr, h->d_qnr, j.pa + j.off[3], j.pb + j.off[3], j.off[4] - j.off[3],
-                                         tmp32 + j.off[3], s);
+                                         nullptr, nullptr, tmp32 + j.off[3], s);
         if (err != hipSuccess) return err;
         err = launch_regular_list<float>(Pr, h->d_qr, j.pa + j.off[4], j.pb + j.off[4], j.off[5] - j.off[4],
-                                         tmp32 + j.off[4], s);
+                                         nullptr, nullptr, tmp32 + j.off[4], s);
     }
     return err;
 }
