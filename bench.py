@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--eps", type=float, default=None, help="override the workload's ACA tolerance")
     ap.add_argument("--q-nr", type=int, default=None, help="override the near-regular pair order")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
 
 
@@ -77,7 +79,8 @@ def main():
           file=sys.stderr, flush=True)
     if a.eps is not None:
         cfg["eps"] = a.eps
-    params = gca.Params(eta=cfg["eta"], eps=cfg["eps"], green_m=cfg["green_m"])
+    params = gca.Params(eta=cfg["eta"], eps=cfg["eps"], green_m=cfg["green_m"],
+                        omega_scale=cfg.get("omega_scale", 0.25))
     if a.q_nr is not None:
         params.q_nr = a.q_nr
 
@@ -105,6 +108,15 @@ def main():
         dt = (time.perf_counter() - t) / steps
         ph = H.phase_times(steps)
         return dt, ph, y.clone()
+
+    if a.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy probe: 1 GiB read + 1 GiB written", file=sys.stderr, flush=True)
+        del src, dst
 
     dt_mixed, ph_mixed, y_mixed = run(gca.MIXED, a.steps, a.warmup)
     print(f"[bench] mixed: {dt_mixed * 1e3:.3f} ms/product", file=sys.stderr, flush=True)
@@ -174,7 +186,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: unit icosphere, {n} flat triangles, piecewise-constant basis, "
                                f"leaf {cfg['leaf']}, eta {cfg['eta']}, Green order {cfg['green_m']}, "
-                               f"ACA eps {cfg['eps']}, 1 RHS x ~ N(0,1) seed 0",
+                               f"omega margin {params.omega_scale} diam/eta, ACA eps {cfg['eps']}, "
+                               f"1 RHS x ~ N(0,1) seed 0",
                    "n": n, "nrhs": 1, "precision": "mixed: FP32 regular-pair quadrature + transfers, "
                                                    "FP64 Sauter-Schwab touching pairs"},
         "setup_s": setup_s,

@@ -182,6 +182,35 @@ gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, 
                              double inner_rtol, int32_t max_inner, int32_t *iters_out, double *relres_out,
                              void *stream);
 
+/* Moves the vertices to xyz (host, nv x 3, same mesh topology) keeping the
+ * structure of the approximation frozen: cluster tree, block partition,
+ * boxes omega, Green points, and every cluster's pivot rows I and Green
+ * columns J.  Leaf bases and transfer matrices are recomputed as
+ * V^ = A^[:, J] A^[I, J]^{-1} from the Green factor of Section 2 at the new
+ * triangle positions (equal to the cross-approximation basis when xyz is the
+ * mesh of gca_build).  The energy and product of the frozen approximation are
+ * then smooth functions of xyz, which is what h2_bilinear_grad
+ * differentiates.  Synchronises the stream.  Errors: GCA_EINVAL, GCA_ENOMEM,
+ * GCA_EHIP. */
+gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream);
+
+/* Adjoint of the product with respect to the vertex coordinates:
+ *     dxyz += alpha * d(a^T G~(X) b) / dX
+ * with the structure frozen (tree, blocks, boxes, Green points, pivot rows I
+ * and Green columns J of every cluster; the bases are the functions
+ * V^ = A^[:, J] A^[I, J]^{-1} of the vertex positions that gca_update_geometry
+ * evaluates).  Terms: derivatives of every nearfield and coupling entry
+ * (recomputed, not stored), of the touching pairs' Sauter-Schwab rules, and of
+ * the Green factor rows through the interpolation chain of Sections 3-4.
+ * For the energy E = 1/2 u^T G~ u pass a = b = u, alpha = 1/2.
+ * a, b: device FP64, n entries, original triangle order; dxyz: device FP64,
+ * nv x 3 row-major, accumulated.  precision: GCA_FP64, or GCA_MIXED (FP32
+ * nearfield / coupling derivatives and transfers; touching pairs and bases in
+ * FP64).  Stream-ordered, no synchronisation after the first call.
+ * Errors: GCA_EINVAL, GCA_ENOMEM, GCA_EHIP. */
+gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double alpha, double *dxyz,
+                            int32_t precision, void *stream);
+
 /* Galerkin entries g_{I[k], J[k]} (Eq. G_def) for m pairs, computed by the
  * same device quadrature the matrix-vector product uses (the pair's Sauter
  * case decides the rule).  I, J: device int32 original triangle ids;

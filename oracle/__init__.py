@@ -74,6 +74,8 @@ def _load():
     lib.orc_matvec_rows.argtypes = [P, I64, P, P, I64, P]
     lib.orc_triangle_points.argtypes = [P, I32, P, P]
     lib.orc_gauss01.argtypes = [I32, P, P]
+    lib.orc_entry_grad.argtypes = [P, I64, I64, P]
+    lib.orc_energy_grad_vertices.argtypes = [P, P, I64, P, P]
     lib.orc_num_threads.restype = I32
     lib.orc_num_threads.argtypes = []
     lib.orc_ss_moment.restype = D
@@ -167,6 +169,22 @@ class Entries:
         Y = np.zeros((rows.size, X.shape[1]))
         self.lib.orc_matvec_rows(self.h, rows.size, _ptr(rows), _ptr(X), X.shape[1], _ptr(Y))
         return Y[:, 0] if one else Y
+
+    def entry_grad(self, i, j):
+        """d g_ij / d(coordinates of t_i's and t_j's vertices), shape (2, 3, 3):
+        [side][vertex slot in mesh order][coordinate]; for i == j the whole
+        derivative is in side 0."""
+        out = np.zeros(18)
+        self.lib.orc_entry_grad(self.h, int(i), int(j), _ptr(out))
+        return out.reshape(2, 3, 3)
+
+    def energy_grad_vertices(self, u, vsel):
+        """dE/dX_v, E = 1/2 u^T G u, for the selected vertices (k, 3)."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        vsel = np.ascontiguousarray(vsel, dtype=np.int32)
+        out = np.zeros((vsel.size, 3))
+        self.lib.orc_energy_grad_vertices(self.h, _ptr(u), vsel.size, _ptr(vsel), _ptr(out))
+        return out
 
     def triangle_points(self, q):
         """Collapsed Gauss points of order q on every triangle and their weights

@@ -322,7 +322,7 @@ double orc_ss_moment(int kase, int q, int pa, int pb, int pc, int pd)
 
 /* Orders the vertices of the pair (i, j), i <= j, for the touching rules. */
 static void touching_vertices(const orc_ctx *c, int kase, int64_t i, int64_t j,
-                              double P[3][3], double Q[3][3])
+                              double P[3][3], double Q[3][3], int32_t *pid, int32_t *qid)
 {
     const int32_t *ti = c->tri + 3 * i, *tj = c->tri + 3 * j;
     int32_t pi[3], pj[3];
@@ -348,6 +348,7 @@ static void touching_vertices(const orc_ctx *c, int kase, int64_t i, int64_t j,
         for (int k = 0; k < 3; ++k) { pi[k] = ti[(ka + k) % 3]; pj[k] = tj[(kb + k) % 3]; }
     }
     for (int k = 0; k < 3; ++k) { vload(c, pi[k], P[k]); vload(c, pj[k], Q[k]); }
+    if (pid) for (int k = 0; k < 3; ++k) { pid[k] = pi[k]; qid[k] = pj[k]; }
 }
 
 double orc_entry(void *p, int64_t i, int64_t j)
@@ -357,7 +358,7 @@ double orc_entry(void *p, int64_t i, int64_t j)
     int kase = orc_classify(p, i, j);
     double P[3][3], Q[3][3];
     if (kase == ORC_IDENT || kase == ORC_EDGE || kase == ORC_VERT) {
-        touching_vertices(c, kase, i, j, P, Q);
+        touching_vertices(c, kase, i, j, P, Q, NULL, NULL);
         return entry_touching(kase, P, Q, c->q_s, c->gs_x, c->gs_w);
     }
     for (int k = 0; k < 3; ++k) { vload(c, c->tri[3 * i + k], P[k]); vload(c, c->tri[3 * j + k], Q[k]); }
@@ -429,5 +430,173 @@ void orc_triangle_points(void *p, int q, double *pts, double *wts)
                 for (int d = 0; d < 3; ++d) pts[3 * o + d] = x[d] + P[0][d];
                 wts[o] = gw[a] * gw[b] * gx[a] * J;
             }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Derivatives of the entries with respect to the vertex coordinates (for the
+ * energy E = 1/2 u^T G u and the adjoint of the H^2 product).
+ *
+ * Every rule above integrates F = w J_P J_Q / (4 pi |X - Y|) at fixed
+ * reference points, with X = b0 P0 + b1 P1 + b2 P2, (b0, b1, b2) =
+ * (1 - s1, s1 - s2, s2), J = |(P1 - P0) x (P2 - P1)|.  The derivative of F with
+ * respect to a vertex copy P_k is therefore
+ *     w [ dJ_P/dP_k J_Q / r - J_P J_Q (X - Y) b_k / r^3 ] / (4 pi),
+ * and likewise for Q_k with the opposite sign of the second term.  Shared
+ * vertices appear once in each triangle; their two partial derivatives add.
+ * ------------------------------------------------------------------------ */
+
+/* dJ/dP_k for J = |(P1 - P0) x (P2 - P1)|: with e1 = P1 - P0, e2 = P2 - P1,
+ * c = e1 x e2, dJ/de1 = e2 x c/|c|, dJ/de2 = c/|c| x e1. */
+static void surf_elem_grad(const double P[3][3], double g[3][3])
+{
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) { e1[d] = P[1][d] - P[0][d]; e2[d] = P[2][d] - P[1][d]; }
+    double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double J = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    for (int d = 0; d < 3; ++d) c[d] /= J;
+    double a[3] = {e2[1] * c[2] - e2[2] * c[1], e2[2] * c[0] - e2[0] * c[2], e2[0] * c[1] - e2[1] * c[0]};  /* dJ/de1 */
+    double b[3] = {c[1] * e1[2] - c[2] * e1[1], c[2] * e1[0] - c[0] * e1[2], c[0] * e1[1] - c[1] * e1[0]};  /* dJ/de2 */
+    for (int d = 0; d < 3; ++d) {
+        g[0][d] = -a[d];
+        g[1][d] = a[d] - b[d];
+        g[2][d] = b[d];
+    }
+}
+
+/* One quadrature point pair: adds to GP (d/dP_k) and GQ (d/dQ_k). */
+static void grad_point(const double P[3][3], const double Q[3][3], double JP, double JQ,
+                       const double gJP[3][3], const double gJQ[3][3],
+                       double s1, double s2, double u1, double u2, double w,
+                       const double *XmY, double GP[3][3], double GQ[3][3])
+{
+    double r2 = XmY[0] * XmY[0] + XmY[1] * XmY[1] + XmY[2] * XmY[2];
+    double r = sqrt(r2);
+    double bp[3] = {1.0 - s1, s1 - s2, s2}, bq[3] = {1.0 - u1, u1 - u2, u2};
+    double f = w / r, h = w * JP * JQ / (r2 * r);
+    (void)P; (void)Q;
+    for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) {
+            GP[k][d] += f * gJP[k][d] * JQ - h * XmY[d] * bp[k];
+            GQ[k][d] += f * JP * gJQ[k][d] + h * XmY[d] * bq[k];
+        }
+}
+
+static void grad_regular(const double P[3][3], const double Q[3][3], int q, const double *gx, const double *gw,
+                         double GP[3][3], double GQ[3][3])
+{
+    double JP = surf_elem(P), JQ = surf_elem(Q);
+    double gJP[3][3], gJQ[3][3];
+    surf_elem_grad(P, gJP);
+    surf_elem_grad(Q, gJQ);
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b) {
+            double s1 = gx[a], s2 = gx[a] * gx[b], ws = gw[a] * gw[b] * gx[a];
+            double x[3];
+            chi_rel(P, s1, s2, x);
+            for (int d = 0; d < 3; ++d) x[d] += P[0][d];
+            for (int e = 0; e < q; ++e)
+                for (int f = 0; f < q; ++f) {
+                    double u1 = gx[e], u2 = gx[e] * gx[f], wu = gw[e] * gw[f] * gx[e];
+                    double y[3], XmY[3];
+                    chi_rel(Q, u1, u2, y);
+                    for (int d = 0; d < 3; ++d) XmY[d] = x[d] - (y[d] + Q[0][d]);
+                    grad_point(P, Q, JP, JQ, gJP, gJQ, s1, s2, u1, u2, ws * wu, XmY, GP, GQ);
+                }
+        }
+}
+
+static void grad_touching(int kase, const double P[3][3], const double Q[3][3], int q, const double *gx,
+                          const double *gw, double GP[3][3], double GQ[3][3])
+{
+    double JP = surf_elem(P), JQ = surf_elem(Q);
+    double gJP[3][3], gJQ[3][3];
+    surf_elem_grad(P, gJP);
+    surf_elem_grad(Q, gJQ);
+    int nreg = ss_regions(kase);
+    for (int r = 0; r < nreg; ++r)
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+                for (int e = 0; e < q; ++e)
+                    for (int f = 0; f < q; ++f) {
+                        double x1, x2, y1, y2;
+                        double jac = ss_map(kase, r, gx[a], gx[b], gx[e], gx[f], &x1, &x2, &y1, &y2);
+                        double w = gw[a] * gw[b] * gw[e] * gw[f] * jac;
+                        double X[3], Y[3], XmY[3];
+                        chi_rel(P, x1, x2, X);
+                        chi_rel(Q, y1, y2, Y);
+                        /* P0 and Q0 are the same vertex: X - Y = (P0 - Q0) + ... = rel. parts */
+                        for (int d = 0; d < 3; ++d) XmY[d] = (P[0][d] - Q[0][d]) + X[d] - Y[d];
+                        grad_point(P, Q, JP, JQ, gJP, gJQ, x1, x2, y1, y2, w, XmY, GP, GQ);
+                    }
+}
+
+/* local slot of vertex id v in triangle t */
+static int local_slot(const orc_ctx *c, int64_t t, int32_t v)
+{
+    for (int k = 0; k < 3; ++k)
+        if (c->tri[3 * t + k] == v) return k;
+    return -1;
+}
+
+/* out[0..8]: d g_ij / d(vertex slot m of t_i, coordinate d) at 3 m + d;
+ * out[9..17]: the same for t_j.  For i == j the whole derivative of g_ii is in
+ * out[0..8] and out[9..17] is zero. */
+void orc_entry_grad(void *p, int64_t i, int64_t j, double *out)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    for (int k = 0; k < 18; ++k) out[k] = 0.0;
+    int swapped = 0;
+    if (i > j) { int64_t t = i; i = j; j = t; swapped = 1; }
+    int kase = orc_classify(p, i, j);
+    double P[3][3], Q[3][3], GP[3][3] = {{0}}, GQ[3][3] = {{0}};
+    int32_t pid[3], qid[3];
+    if (kase == ORC_IDENT || kase == ORC_EDGE || kase == ORC_VERT) {
+        touching_vertices(c, kase, i, j, P, Q, pid, qid);
+        grad_touching(kase, P, Q, c->q_s, c->gs_x, c->gs_w, GP, GQ);
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            pid[k] = c->tri[3 * i + k];
+            qid[k] = c->tri[3 * j + k];
+            vload(c, pid[k], P[k]);
+            vload(c, qid[k], Q[k]);
+        }
+        if (kase == ORC_NEAR) grad_regular(P, Q, c->q_nr, c->gn_x, c->gn_w, GP, GQ);
+        else grad_regular(P, Q, c->q_r, c->gr_x, c->gr_w, GP, GQ);
+    }
+    double *oi = out + (swapped ? 9 : 0), *oj = out + (swapped ? 0 : 9);
+    if (i == j) { oi = out; oj = out; }
+    for (int k = 0; k < 3; ++k) {
+        int si = local_slot(c, i, pid[k]), sj = local_slot(c, j, qid[k]);
+        for (int d = 0; d < 3; ++d) {
+            oi[3 * si + d] += GP[k][d] / (4.0 * ORC_PI);
+            oj[3 * sj + d] += GQ[k][d] / (4.0 * ORC_PI);
+        }
+    }
+}
+
+/* dE/dX for E = 1/2 u^T G u at the selected vertices (nsel x 3, row-major):
+ * dE/dX_v = sum over triangles t containing v of u_t sum_j u_j d_t g_tj (the
+ * t-side partial derivative; the identical pair contributes half of its full
+ * derivative, as both copies of t lie in t). */
+void orc_energy_grad_vertices(void *p, const double *u, int64_t nsel, const int32_t *vsel, double *out)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    const int64_t n = c->nt;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < nsel; ++s) {
+        const int32_t v = vsel[s];
+        double acc[3] = {0, 0, 0};
+        for (int64_t t = 0; t < n; ++t) {
+            int slot = local_slot(c, t, v);
+            if (slot < 0) continue;
+            for (int64_t j = 0; j < n; ++j) {
+                double g[18];
+                orc_entry_grad(p, t, j, g);
+                double wgt = u[t] * u[j] * (j == t ? 0.5 : 1.0);
+                for (int d = 0; d < 3; ++d) acc[d] += wgt * g[3 * slot + d];
+            }
+        }
+        for (int d = 0; d < 3; ++d) out[3 * s + d] = acc[d];
     }
 }

@@ -33,7 +33,8 @@ EXPORTED = [
     "gca_params_default", "gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_tree_destroy",
     "gca_block_tree",
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
-    "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined",
+    "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
+    "h2_bilinear_grad",
 ]
 
 
@@ -91,6 +92,8 @@ def lib():
     L.gca_basis_sizes.argtypes = [P, P, P]
     L.gca_basis_export.argtypes = [P, P, P, P]
     L.gca_stats.argtypes = [P, P]
+    L.gca_update_geometry.argtypes = [P, P, P]
+    L.h2_bilinear_grad.argtypes = [P, P, P, D, P, I32, P]
     L.gca_solve_refined.argtypes = [P, P, P, D, I32, D, I32, P, P, P]
     L.gca_phase_times.argtypes = [P, I64, P, P]
     L.gca_destroy.argtypes = [P]
@@ -100,7 +103,7 @@ def lib():
     for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
-                 "gca_solve_refined"):
+                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -242,6 +245,25 @@ class H2:
                                        float(rtol), int(max_outer), float(inner_rtol), int(max_inner), it,
                                        ctypes.byref(rel), _stream_ptr(stream)))
         return u, it[0], it[1], rel.value
+
+    def update_geometry(self, verts, stream=None):
+        """Move the vertices keeping tree, blocks, boxes, Green points and pivots
+        (frozen structure); bases are recomputed from the Green factor."""
+        v = np.ascontiguousarray(verts, dtype=np.float64)
+        assert v.shape == self._m.xyz.shape
+        _check(lib().gca_update_geometry(self.h, v.ctypes.data, _stream_ptr(stream)))
+
+    def bilinear_grad(self, a, b, alpha=1.0, dxyz=None, precision=FP64, stream=None):
+        """dxyz += alpha * d(a^T G~ b)/dX (frozen structure); returns dxyz (nv, 3)."""
+        import torch
+        a = a.contiguous()
+        b = b.contiguous()
+        if dxyz is None:
+            dxyz = torch.zeros((self._m.xyz.shape[0], 3), dtype=torch.float64, device=a.device)
+        _check(lib().h2_bilinear_grad(self.h, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                      float(alpha), ctypes.c_void_p(dxyz.data_ptr()), int(precision),
+                                      _stream_ptr(stream)))
+        return dxyz
 
     def entries(self, I, J, precision=FP64, stream=None):
         import torch

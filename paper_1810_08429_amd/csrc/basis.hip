@@ -207,12 +207,13 @@ __device__ void block_reduce(double &s, double &mv, int64_t &mi, double *sh_s, d
 
 __global__ void __launch_bounds__(ACA_THREADS) k_aca(double *Rall, double *Uall, double *Vall, const int64_t *a_off,
                                                      const int64_t *u_off, const int32_t *rows_arr, int cols,
-                                                     double eps, int maxr_cap, int32_t *rank_out, int32_t *piv_out)
+                                                     double eps, int maxr_cap, int32_t *rank_out, int32_t *piv_out,
+                                                     int32_t *pivc_out)
 {
     __shared__ double sh_s[ACA_THREADS / 64], sh_v[ACA_THREADS / 64];
     __shared__ int64_t sh_i[ACA_THREADS / 64];
     __shared__ double vrow[ACA_MAXCOLS];
-    __shared__ int32_t pivr[ACA_MAXCOLS];
+    __shared__ int32_t pivr[ACA_MAXCOLS], pivc[ACA_MAXCOLS];
     const int c = blockIdx.x, tid = threadIdx.x;
     const int rows = rows_arr[c];
     const int rmax = min(rows, cols);
@@ -244,7 +245,10 @@ __global__ void __launch_bounds__(ACA_THREADS) k_aca(double *Rall, double *Uall,
         // u = R[:, q] -> U[:, r];  v = R[p, :] / piv
         for (int i = tid; i < rows; i += ACA_THREADS) U[(int64_t)i * rmax + r] = R[(int64_t)i * cols + q];
         for (int j = tid; j < cols; j += ACA_THREADS) vrow[j] = R[(int64_t)p * cols + j] / piv;
-        if (tid == 0) pivr[r] = p;
+        if (tid == 0) {
+            pivr[r] = p;
+            pivc[r] = q;
+        }
         __syncthreads();
         s = 0;
         mv = -1.0;
@@ -269,7 +273,10 @@ __global__ void __launch_bounds__(ACA_THREADS) k_aca(double *Rall, double *Uall,
         ++r;
     }
     if (tid == 0) rank_out[c] = r;
-    for (int k = tid; k < r; k += ACA_THREADS) piv_out[(int64_t)c * maxr_cap + k] = pivr[k];
+    for (int k = tid; k < r; k += ACA_THREADS) {
+        piv_out[(int64_t)c * maxr_cap + k] = pivr[k];
+        pivc_out[(int64_t)c * maxr_cap + k] = pivc[k];
+    }
     __syncthreads();
     // V = U L^{-1}, L[j][k] = U[piv_j][k] (lower triangular): back substitution per row
     for (int i = tid; i < rows; i += ACA_THREADS) {
@@ -291,12 +298,12 @@ __global__ void __launch_bounds__(ACA_THREADS) k_aca(double *Rall, double *Uall,
 
 hipError_t launch_aca(double *R, double *U, double *V, const int64_t *a_off, const int64_t *u_off,
                       const int32_t *rows, int cols, int nbatch, double eps, int maxr_cap, int32_t *rank_out,
-                      int32_t *piv_out, hipStream_t s)
+                      int32_t *piv_out, int32_t *pivc_out, hipStream_t s)
 {
     if (nbatch == 0) return hipSuccess;
     if (cols > ACA_MAXCOLS || maxr_cap > ACA_MAXCOLS) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_aca, dim3(nbatch), dim3(ACA_THREADS), 0, s, R, U, V, a_off, u_off, rows, cols, eps,
-                       maxr_cap, rank_out, piv_out);
+                       maxr_cap, rank_out, piv_out, pivc_out);
     return hipGetLastError();
 }
 

@@ -85,6 +85,7 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
     const auto &nodes = h->tree.nodes;
     const int nc = (int)h->nc;
     std::vector<std::vector<int32_t>> piv(nc);   // pivot positions per cluster
+    std::vector<std::vector<int32_t>> arows_c(nc), prow_c(nc), pcol_c(nc);
     h->rank.assign(nc, 0);
 
     struct LevelWs {
@@ -135,7 +136,7 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
             piv[cl[bi]] = rr;   // row list for now; replaced by the pivots below
         }
         double *dA, *dU, *dV;
-        int32_t *d_rows, *d_rowtri, *d_rowcl, *d_rank, *d_pivl;
+        int32_t *d_rows, *d_rowtri, *d_rowcl, *d_rank, *d_pivl, *d_pivc;
         int64_t *d_rowout, *d_aoff, *d_uoff;
         if ((st = tmp_alloc((void **)&dA, atot * sizeof(double))) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&dU, utot * sizeof(double))) != GCA_OK) break;
@@ -145,6 +146,7 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
         if ((st = tmp_alloc((void **)&d_rowcl, row_cl.size() * 4)) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&d_rank, nb * 4)) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&d_pivl, (size_t)nb * cols * 4)) != GCA_OK) break;
+        if ((st = tmp_alloc((void **)&d_pivc, (size_t)nb * cols * 4)) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&d_rowout, row_out.size() * 8)) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&d_aoff, nb * 8)) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&d_uoff, nb * 8)) != GCA_OK) break;
@@ -157,14 +159,15 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
         hipError_t e = launch_green_A(h->d_qA, PA, h->d_box, d_rowtri, d_rowcl, d_rowout, (int64_t)row_tri.size(),
                                       p.green_m, h->gl_x, h->gl_w, p.eta, p.omega_scale, dA, s);
         if (e == hipSuccess)
-            e = launch_aca(dA, dU, dV, d_aoff, d_uoff, d_rows, cols, nb, p.eps, cols, d_rank, d_pivl, s);
+            e = launch_aca(dA, dU, dV, d_aoff, d_uoff, d_rows, cols, nb, p.eps, cols, d_rank, d_pivl, d_pivc, s);
         if (e != hipSuccess) {
             st = set_error(GCA_EHIP, std::string("basis kernels: ") + hipGetErrorString(e));
             break;
         }
-        std::vector<int32_t> rk(nb), pl((size_t)nb * cols);
+        std::vector<int32_t> rk(nb), pl((size_t)nb * cols), pc((size_t)nb * cols);
         e = hipMemcpyAsync(rk.data(), d_rank, nb * 4, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(pl.data(), d_pivl, (size_t)nb * cols * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(pc.data(), d_pivc, (size_t)nb * cols * 4, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             st = set_error(GCA_EHIP, std::string("basis read-back: ") + hipGetErrorString(e));
@@ -174,6 +177,9 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
             const int c = cl[bi];
             std::vector<int32_t> rr = piv[c], pv(rk[bi]);
             for (int r = 0; r < rk[bi]; ++r) pv[r] = rr[pl[(size_t)bi * cols + r]];
+            arows_c[c] = rr;
+            prow_c[c].assign(pl.begin() + (size_t)bi * cols, pl.begin() + (size_t)bi * cols + rk[bi]);
+            pcol_c[c].assign(pc.begin() + (size_t)bi * cols, pc.begin() + (size_t)bi * cols + rk[bi]);
             piv[c] = pv;
             h->rank[c] = rk[bi];
         }
@@ -195,6 +201,17 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
         h->pivots.insert(h->pivots.end(), piv[c].begin(), piv[c].end());
     }
     h->n_piv = (int64_t)h->pivots.size();
+    h->pivrow.clear();
+    h->pivcol.clear();
+    h->arow_off.assign(nc + 1, 0);
+    h->arows.clear();
+    for (int c = 0; c < nc; ++c) {
+        h->pivrow.insert(h->pivrow.end(), prow_c[c].begin(), prow_c[c].end());
+        h->pivcol.insert(h->pivcol.end(), pcol_c[c].begin(), pcol_c[c].end());
+        h->arow_off[c] = (int64_t)h->arows.size();
+        h->arows.insert(h->arows.end(), arows_c[c].begin(), arows_c[c].end());
+    }
+    h->arow_off[nc] = (int64_t)h->arows.size();
     h->v_off.assign(nc, 0);
     h->e_off.assign(nc, 0);
     int64_t nv_ = 0, ne_ = 0;
@@ -568,6 +585,159 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     return hipSuccess;
 }
 
+// Device data of the frozen-structure basis, built on first use.
+gca_status frozen_setup(gca_h2_s *h, hipStream_t s)
+{
+    Frozen &fz = h->fz;
+    if (fz.ready) return GCA_OK;
+    const int nc = (int)h->nc;
+    std::vector<int32_t> batch(nc);
+    for (int c = 0; c < nc; ++c) batch[c] = c;
+    fz.aj_off.assign(nc, 0);
+    fz.c_off.assign(nc, 0);
+    int64_t aj = 0, cc = 0;
+    for (int c = 0; c < nc; ++c) {
+        const int64_t m = h->arow_off[c + 1] - h->arow_off[c];
+        fz.aj_off[c] = aj;
+        fz.c_off[c] = cc;
+        aj += m * h->rank[c];
+        cc += (int64_t)h->rank[c] * h->rank[c];
+    }
+    fz.n_aj = aj;
+    fz.n_c = cc;
+    GCA_TRY(upload_new(h, &fz.d_batch, batch, s));
+    GCA_TRY(upload_new(h, &fz.d_pivrow, h->pivrow, s));
+    GCA_TRY(upload_new(h, &fz.d_pivcol, h->pivcol, s));
+    GCA_TRY(upload_new(h, &fz.d_arow_off, h->arow_off, s));
+    GCA_TRY(upload_new(h, &fz.d_arows, h->arows, s));
+    GCA_TRY(upload_new(h, &fz.d_aj_off, fz.aj_off, s));
+    GCA_TRY(upload_new(h, &fz.d_c_off, fz.c_off, s));
+    GCA_TRY(dalloc(h, &fz.d_AJ, aj));
+    GCA_TRY(dalloc(h, &fz.d_Vh, aj));
+    GCA_TRY(dalloc(h, &fz.d_tmp, aj));
+    GCA_TRY(dalloc(h, &fz.d_Vbar, aj));
+    GCA_TRY(dalloc(h, &fz.d_Z, aj));
+    GCA_TRY(dalloc(h, &fz.d_LU, cc));
+    GCA_TRY(dalloc(h, &fz.d_perm, h->n_piv));
+    // copies of V^ into the leaf bases and transfer matrices
+    std::vector<int64_t> vj, ej;
+    for (int c = 0; c < nc; ++c) {
+        const Node &nd = h->tree.nodes[c];
+        const int64_t r = h->rank[c];
+        if (nd.son[0] < 0) {
+            vj.insert(vj.end(), {fz.aj_off[c], r, 0, (int64_t)(nd.end - nd.begin), r, h->v_off[c]});
+        } else {
+            const int s0 = nd.son[0], s1 = nd.son[1];
+            ej.insert(ej.end(), {fz.aj_off[c], r, 0, (int64_t)h->rank[s0], r, h->e_off[s0]});
+            ej.insert(ej.end(), {fz.aj_off[c], r, (int64_t)h->rank[s0], (int64_t)h->rank[s1], r, h->e_off[s1]});
+        }
+    }
+    fz.n_vjobs = (int32_t)(vj.size() / 6);
+    fz.n_ejobs = (int32_t)(ej.size() / 6);
+    vj.insert(vj.end(), ej.begin(), ej.end());
+    GCA_TRY(upload_new(h, &fz.d_copy_jobs, vj, s));
+    fz.ready = true;
+    return GCA_OK;
+}
+
+// Workspaces and index maps of the adjoint, built on first use.
+gca_status grad_setup(gca_h2_s *h, hipStream_t s)
+{
+    GradWs &w = h->gw;
+    if (w.ready) return GCA_OK;
+    const int64_t n = h->n, nv = h->nv;
+    const int nc = (int)h->nc;
+    GCA_TRY(dalloc(h, &w.ap, n));
+    GCA_TRY(dalloc(h, &w.bp, n));
+    GCA_TRY(dalloc(h, &w.apf, n));
+    GCA_TRY(dalloc(h, &w.bpf, n));
+    double *tmp;
+    GCA_TRY(dalloc(h, &tmp, h->n_piv));
+    w.xa = tmp;
+    GCA_TRY(dalloc(h, &tmp, h->n_piv));
+    w.xb = tmp;
+    GCA_TRY(dalloc(h, &tmp, h->n_piv));
+    w.ya = tmp;
+    GCA_TRY(dalloc(h, &tmp, h->n_piv));
+    w.yb = tmp;
+    GCA_TRY(dalloc(h, &tmp, h->n_cslot_total));
+    w.cpart = tmp;
+    GCA_TRY(dalloc(h, &w.gnear, 9 * (size_t)h->n_nslot_total));
+    GCA_TRY(dalloc(h, &w.gfar, 9 * (size_t)h->n_cslot_total));
+    GCA_TRY(dalloc(h, &w.gt, 9 * h->pl.t_other.size()));
+    GCA_TRY(dalloc(h, &w.gn, 9 * h->pl.n_other.size()));
+    GCA_TRY(dalloc(h, &w.gb, 9 * h->arows.size()));
+    GCA_TRY(dalloc(h, &w.dT, 9 * (size_t)n));
+    const auto &nodes = h->tree.nodes;
+    std::vector<int32_t> leaf_of(n), leaf_index(nc, -1);
+    for (size_t li = 0; li < h->leaves.size(); ++li) {
+        const int c = h->leaves[li];
+        leaf_index[c] = (int32_t)li;
+        for (int32_t q = nodes[c].begin; q < nodes[c].end; ++q) leaf_of[q] = c;
+    }
+    GCA_TRY(upload_new(h, &w.leaf_of, leaf_of, s));
+    GCA_TRY(upload_new(h, &w.leaf_index, leaf_index, s));
+    auto csr = [&](const std::vector<int32_t> &key, int64_t nkey, std::vector<int64_t> &ptr,
+                   std::vector<int32_t> &val) {
+        ptr.assign(nkey + 1, 0);
+        for (int32_t k : key) ptr[k + 1]++;
+        for (int64_t i = 0; i < nkey; ++i) ptr[i + 1] += ptr[i];
+        val.assign(key.size(), 0);
+        std::vector<int64_t> f(ptr.begin(), ptr.end() - 1);
+        for (size_t q = 0; q < key.size(); ++q) val[f[key[q]]++] = (int32_t)q;
+    };
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> val;
+    csr(h->pivots, n, ptr, val);
+    GCA_TRY(upload_new(h, &w.pocc_ptr, ptr, s));
+    GCA_TRY(upload_new(h, &w.pocc, val, s));
+    std::vector<int32_t> pc(h->n_piv);
+    for (int c = 0; c < nc; ++c)
+        for (int k = 0; k < h->rank[c]; ++k) pc[h->piv_off[c] + k] = c;
+    GCA_TRY(upload_new(h, &w.piv_cluster, pc, s));
+    csr(h->arows, n, ptr, val);
+    GCA_TRY(upload_new(h, &w.rocc_ptr, ptr, s));
+    GCA_TRY(upload_new(h, &w.rocc, val, s));
+    // vertex -> (position, slot)
+    std::vector<int32_t> vkey(3 * n);
+    for (int64_t q = 0; q < n; ++q)
+        for (int k = 0; k < 3; ++k) vkey[3 * q + k] = h->mesh.tri[3 * (int64_t)h->tree.perm[q] + k];
+    csr(vkey, nv, ptr, val);
+    std::vector<int32_t> vpos(val.size()), vslot(val.size());
+    for (size_t q = 0; q < val.size(); ++q) {
+        vpos[q] = val[q] / 3;
+        vslot[q] = val[q] % 3;
+    }
+    GCA_TRY(upload_new(h, &w.vptr, ptr, s));
+    GCA_TRY(upload_new(h, &w.vpos, vpos, s));
+    GCA_TRY(upload_new(h, &w.vslot, vslot, s));
+    w.ready = true;
+    return GCA_OK;
+}
+
+template <typename T>
+hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alpha, double *dxyz, hipStream_t s)
+{
+    GradWs &w = h->gw;
+    const bool f32 = std::is_same<T, float>::value;
+    T *ap = f32 ? (T *)w.apf : (T *)w.ap, *bp = f32 ? (T *)w.bpf : (T *)w.bp;
+    T *xa = (T *)w.xa, *xb = (T *)w.xb, *ya = (T *)w.ya, *yb = (T *)w.yb, *cp = (T *)w.cpart;
+    hipError_t e;
+    if ((e = launch_frozen_basis(h, s)) != hipSuccess) return e;
+    if ((e = launch_permute_in<T>(a, h->d_perm, h->n, ap, f32 ? w.ap : nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_permute_in<T>(b, h->d_perm, h->n, bp, f32 ? w.bp : nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_forward<T>(h, ap, xa, s)) != hipSuccess) return e;
+    if ((e = launch_forward<T>(h, bp, xb, s)) != hipSuccess) return e;
+    if ((e = launch_far_blocks<T>(h, xa, cp, s)) != hipSuccess) return e;
+    if ((e = launch_coupling_reduce<T>(h, cp, ya, s)) != hipSuccess) return e;
+    if ((e = launch_far_blocks<T>(h, xb, cp, s)) != hipSuccess) return e;
+    if ((e = launch_coupling_reduce<T>(h, cp, yb, s)) != hipSuccess) return e;
+    if ((e = launch_backward<T>(h, ya, s)) != hipSuccess) return e;
+    if ((e = launch_backward<T>(h, yb, s)) != hipSuccess) return e;
+    if ((e = launch_bilinear_grad<T>(h, w, s)) != hipSuccess) return e;
+    return launch_vertex_gather(h, w, alpha, dxyz, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -881,6 +1051,51 @@ gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, 
     if (relres_out) *relres_out = relres;
     if (relres > rtol)
         return set_error(GCA_ENOCONV, "refinement stopped at relative residual " + std::to_string(relres));
+    return GCA_OK;
+}
+
+gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
+{
+    clear_error();
+    if (!h || !xyz) return set_error(GCA_EINVAL, "NULL argument");
+    for (int64_t k = 0; k < 3 * h->nv; ++k)
+        if (!std::isfinite(xyz[k])) return set_error(GCA_EINVAL, "non-finite vertex coordinate");
+    hipStream_t s = (hipStream_t)stream;
+    GCA_TRY(frozen_setup(h, s));
+    std::copy(xyz, xyz + 3 * h->nv, h->mesh.xyz.begin());
+    GCA_TRY(upload(h->d_xyz, h->mesh.xyz, s));
+    auto tri_pts = [&](int q, double *out) -> gca_status {
+        double gx[32], gw[32];
+        gauss_legendre01(q, gx, gw);
+        GCA_HIP_TRY(launch_tri_points(h->d_xyz, h->d_tv, h->n, q, gx, gw, out, s));
+        return GCA_OK;
+    };
+    GCA_TRY(tri_pts(h->prm.q_r, h->d_qr));
+    GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
+    if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, h->d_qA));
+    GCA_HIP_TRY(launch_frozen_basis(h, s));
+    Frozen &fz = h->fz;
+    GCA_HIP_TRY(launch_copy_jobs(fz.d_copy_jobs, fz.n_vjobs, fz.d_Vh, h->d_V, h->d_Vt, h->d_Vf, h->d_Vtf, s));
+    GCA_HIP_TRY(launch_copy_jobs(fz.d_copy_jobs + 6 * (int64_t)fz.n_vjobs, fz.n_ejobs, fz.d_Vh, h->d_E, h->d_Et,
+                                 h->d_Ef, h->d_Etf, s));
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+    return GCA_OK;
+}
+
+gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double alpha, double *dxyz,
+                            int32_t precision, void *stream)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (!a || !b || !dxyz) return set_error(GCA_EINVAL, "NULL vector");
+    if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
+    if (!std::isfinite(alpha)) return set_error(GCA_EINVAL, "alpha must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    GCA_TRY(frozen_setup(h, s));
+    GCA_TRY(grad_setup(h, s));
+    hipError_t e = precision == GCA_FP64 ? grad_device<double>(h, a, b, alpha, dxyz, s)
+                                         : grad_device<float>(h, a, b, alpha, dxyz, s);
+    if (e != hipSuccess) return set_error(GCA_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
     return GCA_OK;
 }
 

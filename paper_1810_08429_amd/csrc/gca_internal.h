@@ -115,8 +115,52 @@ struct DevBuf {
 
 }  // namespace gca
 
+namespace gca {
+// Frozen-structure basis data (pivot rows / columns fixed): device copies of
+// the per-cluster row lists and workspaces of the refresh and the adjoint.
+struct Frozen {
+    bool ready = false;
+    int32_t *d_batch = nullptr;      // cluster ids 0..nc-1
+    int32_t *d_pivrow = nullptr, *d_pivcol = nullptr;
+    int64_t *d_arow_off = nullptr;
+    int32_t *d_arows = nullptr;
+    int64_t *d_aj_off = nullptr, *d_c_off = nullptr;
+    std::vector<int64_t> aj_off, c_off;
+    int64_t n_aj = 0, n_c = 0;
+    double *d_AJ = nullptr, *d_Vh = nullptr, *d_tmp = nullptr, *d_LU = nullptr;
+    double *d_Vbar = nullptr, *d_Z = nullptr;
+    int32_t *d_perm = nullptr;
+    int64_t *d_copy_jobs = nullptr;  // V / E copies from d_Vh
+    int32_t n_vjobs = 0, n_ejobs = 0;
+};
+}  // namespace gca
+
+namespace gca {
+// Workspaces and index maps of h2_bilinear_grad (allocated by its first call).
+struct GradWs {
+    bool ready = false;
+    double *ap = nullptr, *bp = nullptr;        // permuted a, b (FP64)
+    float *apf = nullptr, *bpf = nullptr;       // permuted a, b (mixed)
+    void *xa = nullptr, *xb = nullptr, *ya = nullptr, *yb = nullptr;   // n_piv of T (sized for FP64)
+    void *cpart = nullptr;                      // coupling partials (sized for FP64)
+    double *gnear = nullptr, *gfar = nullptr;   // 9 per near / coupling slot entry
+    double *gt = nullptr, *gn = nullptr;        // 9 per pair-CSR entry
+    double *gb = nullptr;                       // 9 per row of every cluster's A^
+    double *dT = nullptr;                       // 9 per triangle position
+    int32_t *leaf_of = nullptr, *leaf_index = nullptr;
+    int64_t *pocc_ptr = nullptr;                // position -> occurrences as a pivot
+    int32_t *pocc = nullptr, *piv_cluster = nullptr;
+    int64_t *rocc_ptr = nullptr;                // position -> occurrences as a row of some A^
+    int32_t *rocc = nullptr;
+    int64_t *vptr = nullptr;                    // vertex -> (position, local slot)
+    int32_t *vpos = nullptr, *vslot = nullptr;
+};
+}  // namespace gca
+
 struct gca_h2_s {
     gca_params prm{};
+    gca::Frozen fz;
+    gca::GradWs gw;
     int64_t n = 0, nv = 0, nc = 0;
     int32_t depth = 0;
     gca_tree_s tree;                 // private copy
@@ -129,6 +173,10 @@ struct gca_h2_s {
     std::vector<int32_t> rank;       // per cluster
     std::vector<int64_t> piv_off;    // per cluster offset into pivots / xhat
     std::vector<int32_t> pivots;     // positions, per cluster in pivot order
+    std::vector<int32_t> pivrow;     // per pivot: local row index in the cluster's A (pivot order)
+    std::vector<int32_t> pivcol;     // per pivot: Green column of the factor A (pivot order)
+    std::vector<int64_t> arow_off;   // per cluster: offset of its row list in arows
+    std::vector<int32_t> arows;      // rows of each cluster's A (leaf: its triangles; parent: sons' pivots)
     std::vector<int64_t> v_off;      // leaf V offsets (entries)
     std::vector<int64_t> e_off;      // E offsets for non-root clusters (entries)
     int64_t n_piv = 0, n_v = 0, n_e = 0;
@@ -225,7 +273,7 @@ hipError_t launch_green_A(const double *qA, int PA, const double *box, const int
                           const double *glw, double eta, double omega_scale, double *A, hipStream_t s);
 hipError_t launch_aca(double *R, double *U, double *V, const int64_t *a_off, const int64_t *u_off,
                       const int32_t *rows, int cols, int nbatch, double eps, int maxr_cap, int32_t *rank_out,
-                      int32_t *piv_out, hipStream_t s);
+                      int32_t *piv_out, int32_t *pivc_out, hipStream_t s);
 hipError_t launch_copy_jobs(const int64_t *jobs, int njobs, const double *src, double *dr, double *dc, float *fr,
                             float *fc, hipStream_t s);
 
@@ -255,6 +303,15 @@ hipError_t launch_cg_update(double alpha, const double *p, const double *q, doub
                             hipStream_t s);
 hipError_t launch_sub(const double *a, const double *b, double *out, int64_t n, hipStream_t s);
 hipError_t launch_fill(double *y, double v, int64_t n, hipStream_t s);
+
+// frozen-structure basis (adjoint.hip)
+hipError_t launch_frozen_basis(gca_h2_s *h, hipStream_t s);
+hipError_t launch_frozen_adjoint_solve(gca_h2_s *h, hipStream_t s);
+
+// adjoint (grad.hip)
+template <typename T>
+hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s);
+hipError_t launch_vertex_gather(gca_h2_s *h, const GradWs &w, double alpha, double *dxyz, hipStream_t s);
 
 // Entries for pairs sorted by class on the host (gca_entries).
 struct EntryJobs {

@@ -129,8 +129,8 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
     const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
     const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
 
-    // stage row points (relative to the reference point) and row x values
-    for (int e = tid; e < nr * P; e += BLK_THREADS) {
+    // stage the first chunk of row points (relative to the reference point)
+    for (int e = tid; e < min(nr, rmax) * P; e += BLK_THREADS) {
         int i = e / P, p = e - i * P;
         int pos = NEAR ? rb + i : rl[i];
         const double *src = a.q + ((size_t)pos * P + p) * 4;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
         dst[2] = (T)(src[2] - cz);
         dst[3] = (T)src[3];
     }
-    for (int i = tid; i < nr; i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + i] : a.xv[xro + i];
+    for (int i = tid; i < min(nr, rmax); i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + i] : a.xv[xro + i];
     if (NEAR) {
         for (int i = tid; i < nr; i += BLK_THREADS) {
             uint64_t m = 0;
@@ -152,62 +152,85 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
             mask[i] = m;
         }
     }
-    T racc = 0;
-    for (int c0 = 0; c0 < nc; c0 += CW) {
-        const int cw = min(CW, nc - c0);
-        __syncthreads();
-        for (int e = tid; e < cw * P; e += BLK_THREADS) {
-            int j = e / P, p = e - j * P;
-            int pos = NEAR ? cb + c0 + j : cl[c0 + j];
-            const double *src = a.q + ((size_t)pos * P + p) * 4;
-            colp[(p * 4 + 0) * CW + j] = (T)(src[0] - cx);
-            colp[(p * 4 + 1) * CW + j] = (T)(src[1] - cy);
-            colp[(p * 4 + 2) * CW + j] = (T)(src[2] - cz);
-            colp[(p * 4 + 3) * CW + j] = (T)src[3];
-        }
-        for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = NEAR ? a.xv[cb + c0 + j] : a.xv[xco + c0 + j];
-        __syncthreads();
-        for (int e = tid; e < nr * cw; e += BLK_THREADS) {
-            const int i = e / cw, j = e - i * cw;
-            T g = 0;
-            bool skip = NEAR && ((mask[i] >> (c0 + j)) & 1);
-            if (!skip) {
-                const T *rp = rowp + (size_t)i * P * 4;
-                T acc = 0;
-#pragma unroll
-                for (int pb = 0; pb < P; ++pb) {
-                    const T yx = colp[(pb * 4 + 0) * CW + j];
-                    const T yy = colp[(pb * 4 + 1) * CW + j];
-                    const T yz = colp[(pb * 4 + 2) * CW + j];
-                    const T yw = colp[(pb * 4 + 3) * CW + j];
-                    T inner = 0;
-#pragma unroll
-                    for (int pa = 0; pa < P; ++pa) {
-                        const T dx = rp[4 * pa + 0] - yx;
-                        const T dy = rp[4 * pa + 1] - yy;
-                        const T dz = rp[4 * pa + 2] - yz;
-                        const T r2 = dx * dx + dy * dy + dz * dz;
-                        inner += rp[4 * pa + 3] * rsq<T>(r2);
-                    }
-                    acc += yw * inner;
-                }
-                g = acc * (T)INV4PI;
+    // rows are processed in chunks of rmax (the LDS row tile); the column
+    // partials of later row chunks are added to what earlier chunks wrote
+    // (same thread, same address: deterministic)
+    for (int r0 = 0; r0 < nr; r0 += rmax) {
+        const int rw = min(rmax, nr - r0);
+        if (r0 > 0) {
+            __syncthreads();
+            for (int e = tid; e < rw * P; e += BLK_THREADS) {
+                int i = e / P, p = e - i * P;
+                int pos = NEAR ? rb + r0 + i : rl[r0 + i];
+                const double *src = a.q + ((size_t)pos * P + p) * 4;
+                T *dst = rowp + ((size_t)i * P + p) * 4;
+                dst[0] = (T)(src[0] - cx);
+                dst[1] = (T)(src[1] - cy);
+                dst[2] = (T)(src[2] - cz);
+                dst[3] = (T)src[3];
             }
-            S[(size_t)i * CW + j] = g;
+            for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + r0 + i] : a.xv[xro + r0 + i];
         }
-        __syncthreads();
-        if (tid < nr) {
-            T r = 0;
-            for (int j = 0; j < cw; ++j) r += S[(size_t)tid * CW + j] * xc[j];
-            racc += r;
+        T racc = 0;
+        for (int c0 = 0; c0 < nc; c0 += CW) {
+            const int cw = min(CW, nc - c0);
+            __syncthreads();
+            for (int e = tid; e < cw * P; e += BLK_THREADS) {
+                int j = e / P, p = e - j * P;
+                int pos = NEAR ? cb + c0 + j : cl[c0 + j];
+                const double *src = a.q + ((size_t)pos * P + p) * 4;
+                colp[(p * 4 + 0) * CW + j] = (T)(src[0] - cx);
+                colp[(p * 4 + 1) * CW + j] = (T)(src[1] - cy);
+                colp[(p * 4 + 2) * CW + j] = (T)(src[2] - cz);
+                colp[(p * 4 + 3) * CW + j] = (T)src[3];
+            }
+            for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = NEAR ? a.xv[cb + c0 + j] : a.xv[xco + c0 + j];
+            __syncthreads();
+            for (int e = tid; e < rw * cw; e += BLK_THREADS) {
+                const int i = e / cw, j = e - i * cw;
+                T g = 0;
+                bool skip = NEAR && ((mask[i] >> (c0 + j)) & 1);
+                if (!skip) {
+                    const T *rp = rowp + (size_t)i * P * 4;
+                    T acc = 0;
+#pragma unroll
+                    for (int pb = 0; pb < P; ++pb) {
+                        const T yx = colp[(pb * 4 + 0) * CW + j];
+                        const T yy = colp[(pb * 4 + 1) * CW + j];
+                        const T yz = colp[(pb * 4 + 2) * CW + j];
+                        const T yw = colp[(pb * 4 + 3) * CW + j];
+                        T inner = 0;
+#pragma unroll
+                        for (int pa = 0; pa < P; ++pa) {
+                            const T dx = rp[4 * pa + 0] - yx;
+                            const T dy = rp[4 * pa + 1] - yy;
+                            const T dz = rp[4 * pa + 2] - yz;
+                            const T r2 = dx * dx + dy * dy + dz * dz;
+                            inner += rp[4 * pa + 3] * rsq<T>(r2);
+                        }
+                        acc += yw * inner;
+                    }
+                    g = acc * (T)INV4PI;
+                }
+                S[(size_t)i * CW + j] = g;
+            }
+            __syncthreads();
+            if (tid < rw) {
+                T r = 0;
+                for (int j = 0; j < cw; ++j) r += S[(size_t)tid * CW + j] * xc[j];
+                racc += r;
+            }
+            if (emit_col && tid < cw) {
+                T c = 0;
+                for (int i = 0; i < rw; ++i) c += S[(size_t)i * CW + tid] * xr[i];
+                if (r0 == 0)
+                    a.part[slot_c + c0 + tid] = c;
+                else
+                    a.part[slot_c + c0 + tid] += c;
+            }
         }
-        if (emit_col && tid < cw) {
-            T c = 0;
-            for (int i = 0; i < nr; ++i) c += S[(size_t)i * CW + tid] * xr[i];
-            a.part[slot_c + c0 + tid] = c;
-        }
+        if (tid < rw) a.part[slot_r + r0 + tid] = racc;
     }
-    if (tid < nr) a.part[slot_r + tid] = racc;
 }
 
 template <typename T>
@@ -286,7 +309,7 @@ hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
     a.slot = h->d_far_slot;
     a.part = cpart;
     a.nblk = nb;
-    a.rmax = std::max(1, h->max_rank);
+    a.rmax = std::max(1, std::min(64, h->max_rank));
     a.cw = blk_cw<T>(a.rmax, P);
     if (a.cw == 0) return hipErrorInvalidValue;
     return launch_blocks_P<T, false>(P, a, s);

@@ -1,0 +1,118 @@
+"""Frozen-structure geometry updates and the adjoint of the H^2 product with
+respect to vertex coordinates (runs on an MI355X)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def gca():
+    import paper_1810_08429_amd as g
+    g.lib()
+    return g
+
+
+def jittered(level, rel=0.02, seed=7):
+    base = synth.icosphere(level)
+    return synth.jitter(base, rel * synth.mean_edge_length(base), seed=seed)
+
+
+def test_refresh_at_same_geometry_reproduces_the_basis(torch, gca):
+    """V^ = A^[:, J] A^[I, J]^{-1} with the build's pivots equals the cross-
+    approximation basis U L^{-1} (same matrix in exact arithmetic)."""
+    m = jittered(3)
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, 32), gca.Params(eta=2.0, eps=1e-6))
+    r0, p0, b0 = H.basis()
+    x = torch.tensor(synth.rhs_normal(m.nt, 1, seed=0), device="cuda")
+    y0 = H.matvec(x).cpu().numpy()
+    H.update_geometry(m.verts)
+    r1, p1, b1 = H.basis()
+    assert np.array_equal(r0, r1) and np.array_equal(p0, p1)
+    assert np.abs(b1 - b0).max() < 1e-8 * max(1.0, np.abs(b0).max())
+    y1 = H.matvec(x).cpu().numpy()
+    assert np.linalg.norm(y1 - y0) / np.linalg.norm(y0) < 1e-10
+
+
+def test_refresh_tracks_a_rigid_translation(torch, gca, orc):
+    """After moving every vertex the frozen approximation still reproduces the
+    Galerkin matrix of the moved mesh to the compression tolerance."""
+    m = jittered(3)
+    p = gca.Params(eta=2.0, eps=1e-6)
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, 32), p)
+    moved = m.verts * 1.001 + np.array([1e-3, -2e-3, 5e-4])
+    H.update_geometry(moved)
+    G = orc.Entries(moved, m.tris, p.q_r, p.q_nr, p.q_s).dense()
+    x = synth.rhs_normal(m.nt, 1, seed=1)
+    y = H.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = G @ x
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-5
+
+
+def frozen_energy(H, torch, u):
+    y = H.matvec(u)
+    return 0.5 * float(torch.dot(u, y))
+
+
+def test_adjoint_matches_central_differences(torch, gca):
+    """dE/dX of E = 1/2 u^T G~(X) u with the structure frozen, against central
+    differences of the same frozen approximation (step 1e-6)."""
+    m = jittered(3, seed=11)
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, 32), gca.Params(eta=2.0, eps=1e-6))
+    u = torch.tensor(synth.rhs_normal(m.nt, 1, seed=5), device="cuda")
+    g = H.bilinear_grad(u, u, alpha=0.5).cpu().numpy()
+    rng = np.random.default_rng(3)
+    verts = rng.choice(m.nv, 12, replace=False)
+    h = 1e-6
+    scale = np.abs(g).max()
+    for v in verts:
+        for d in range(3):
+            xp, xm = m.verts.copy(), m.verts.copy()
+            xp[v, d] += h
+            xm[v, d] -= h
+            H.update_geometry(xp)
+            ep = frozen_energy(H, torch, u)
+            H.update_geometry(xm)
+            em = frozen_energy(H, torch, u)
+            fd = (ep - em) / (2 * h)
+            assert abs(fd - g[v, d]) <= 1e-6 * abs(g[v, d]) + 1e-7 * scale, (v, d, fd, g[v, d])
+    H.update_geometry(m.verts)
+
+
+def test_adjoint_close_to_dense_gradient(torch, gca, orc):
+    """The frozen-structure H^2 gradient approximates the gradient of the exact
+    Galerkin energy (oracle, all pairs) to the compression tolerance."""
+    m = jittered(3, seed=12)
+    p = gca.Params(eta=2.0, eps=1e-8)
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, 32), p)
+    uh = synth.rhs_normal(m.nt, 1, seed=6)
+    u = torch.tensor(uh, device="cuda")
+    g = H.bilinear_grad(u, u, alpha=0.5).cpu().numpy()
+    vs = np.random.default_rng(1).choice(m.nv, 24, replace=False)
+    ref = orc.Entries(m.verts, m.tris, p.q_r, p.q_nr, p.q_s).energy_grad_vertices(uh, vs)
+    err = np.abs(g[vs] - ref).max() / np.abs(ref).max()
+    assert err < 1e-4, err
+    gm = H.bilinear_grad(u, u, alpha=0.5, precision=gca.MIXED).cpu().numpy()
+    assert np.abs(gm - g).max() / np.abs(g).max() < 1e-4
+
+
+def test_adjoint_without_admissible_blocks_equals_dense_gradient(torch, gca, orc):
+    """eta -> 0: only nearfield and pair-list derivatives; equal to the oracle's
+    dense gradient to rounding."""
+    m = jittered(2, seed=13)
+    p = gca.Params(eta=1e-6, eps=1e-6)
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, 16), p)
+    uh = synth.rhs_normal(m.nt, 1, seed=7)
+    u = torch.tensor(uh, device="cuda")
+    g = H.bilinear_grad(u, u, alpha=0.5).cpu().numpy()
+    ref = orc.Entries(m.verts, m.tris, p.q_r, p.q_nr, p.q_s).energy_grad_vertices(uh, np.arange(m.nv))
+    assert np.abs(g - ref).max() < 1e-11 * np.abs(ref).max()

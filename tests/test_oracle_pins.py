@@ -497,3 +497,49 @@ def test_mesh_generator_counts():
         assert np.all(s > 0)
         edges = {tuple(sorted((int(t[a]), int(t[(a + 1) % 3])))) for t in m.tris for a in range(3)}
         assert m.nv - len(edges) + m.nt == 2
+
+
+# ------------------------------------------------------------- gradients --
+
+def test_entry_gradients_match_central_differences(orc):
+    """The analytic pair derivatives (chain rule through the fixed reference
+    points and the surface elements) against central differences of the
+    oracle's own entries, for every pair class."""
+    m = synth.jitter(synth.icosphere(2), 0.01, seed=3)
+    e0 = orc.Entries(m.verts, m.tris, 3, 4, 4)
+    found = {}
+    for j in range(m.nt):
+        found.setdefault(int(e0.classify(5, j)[0]), j)
+    assert set(found) == {orc.REG, orc.NEAR, orc.VERT, orc.EDGE, orc.IDENT}
+    h = 1e-6
+    for cls, j in found.items():
+        g = e0.entry_grad(5, j)
+        scale = np.abs(g).max()
+        tris = [5] if j == 5 else [5, j]
+        for t in tris:
+            for k in range(3):
+                v = m.tris[t][k]
+                for d in range(3):
+                    vp, vm = m.verts.copy(), m.verts.copy()
+                    vp[v, d] += h
+                    vm[v, d] -= h
+                    fd = (orc.Entries(vp, m.tris, 3, 4, 4).entries(5, j)[0]
+                          - orc.Entries(vm, m.tris, 3, 4, 4).entries(5, j)[0]) / (2 * h)
+                    an = sum(g[side, kk, d] for side, tt in enumerate([5, j]) if not (j == 5 and side == 1)
+                             for kk in range(3) if m.tris[tt][kk] == v)
+                    assert abs(fd - an) <= 1e-7 * scale, (cls, t, k, d, fd, an)
+
+
+def test_energy_gradient_invariants(orc):
+    """P13 for the dense energy E = 1/2 u^T G u: translation invariance
+    (sum of gradients 0), Euler homogeneity of degree 3 (sum X.grad = 3E) and
+    rotation invariance (sum X x grad = 0)."""
+    m = synth.jitter(synth.icosphere(2), 0.01, seed=4)
+    e = orc.Entries(m.verts, m.tris, 3, 4, 4)
+    u = synth.rhs_normal(m.nt, 1, seed=2)
+    grad = e.energy_grad_vertices(u, np.arange(m.nv))
+    E = 0.5 * u @ (e.dense() @ u)
+    scale = np.abs(grad).sum() * np.abs(m.verts).max()
+    assert np.abs(grad.sum(axis=0)).max() < 1e-12 * np.abs(grad).sum()
+    assert abs(np.sum(m.verts * grad) - 3 * E) < 1e-12 * scale
+    assert np.abs(np.cross(m.verts, grad).sum(axis=0)).max() < 1e-12 * scale
