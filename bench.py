@@ -19,6 +19,7 @@ cores; the same rows give the relative error of both GPU paths.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -43,6 +44,23 @@ TRANS_LANE_OPS_PER_S = VALU_LANE_OPS_PER_S / 4
 FLOPS_PER_EVAL = 10
 EVALS_PER_S_F32 = 1.0 / (7.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
 ALU_PEAK_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (profiles/pmc_traffic_sphere_l8.md), or None when the kernel's source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_sphere_l8.md")
+    src = os.path.join(ROOT, "paper_1810_08429_amd", "csrc", "quad.hip")
+    try:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for line in open(path):
+            f = line.split()
+            if line.startswith("machine-readable: traffic_bytes") and f[2] == kernel and f[-1] == digest:
+                return float(f[3])
+    except OSError:
+        pass
+    return None
 
 
 def parse():
@@ -135,9 +153,10 @@ def main():
     dom = max(work, key=lambda k: mean_mixed[k])
     dur = mean_mixed[dom] * 1e-3
     achieved = work[dom] / dur / 1e12
+    kname = "k_blocks<float,%d,%s>" % (P, "false" if dom == "coupling_blocks" else "true")
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": None,
-                "kernel": "k_blocks<float,%d,%s>" % (P, "false" if dom == "coupling_blocks" else "true"),
+                "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": measured_traffic(kname),
+                "kernel": kname,
                 "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom]}
 
     # CPU oracle on a bounded sample of rows (also the accuracy check)
@@ -191,6 +210,7 @@ def main():
                    "n": n, "nrhs": 1, "precision": "mixed: FP32 regular-pair quadrature + transfers, "
                                                    "FP64 Sauter-Schwab touching pairs"},
         "setup_s": setup_s,
+        "setup_ms": {"tree": (setup_s * 1e3 - st["build_ms"]), **st["setup_ms"]},
         "fp64": {"value": n / dt_fp64, "unit": "DoF/s", "ms_per_step": dt_fp64 * 1e3, "steps": fsteps},
         "mixed_over_fp64": dt_fp64 / dt_mixed,
         "rel_err_sampled_rows": rel,
