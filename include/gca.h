@@ -106,7 +106,9 @@ typedef struct {
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
- * q_r 3, q_nr 4, q_s 4. */
+ * q_r 3, q_nr 3, q_s 4.  With q_nr == q_r near-regular pairs are
+ * integrated by the regular rule inside the nearfield blocks (no separate
+ * list). */
 void gca_params_default(gca_params *p);
 
 /* Cluster tree over the triangles (Section 4's binary subdivision of index

@@ -122,7 +122,7 @@ class Params:
     green_m: int = 3
     q_A: int = 3
     q_r: int = 3
-    q_nr: int = 4
+    q_nr: int = 3
     q_s: int = 4
 
     def _c(self):

@@ -39,21 +39,25 @@ def _compile(args):
     return src
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 4, out: str = None, defines=()) -> str:
+    """Compile and link libgca.so (to `out`, default the package directory);
+    `defines` are extra -D flags for tuning variants."""
     hipcc = _hipcc()
-    os.makedirs(BUILD, exist_ok=True)
+    out = out or OUT
+    build_dir = BUILD if out == OUT else out + "_build"
+    os.makedirs(build_dir, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
-              "-I" + os.path.join(HERE, "..", "include")]
+              "-I" + os.path.join(HERE, "..", "include")] + ["-D" + d for d in defines]
     hip_flags = ["-x", "hip", "--offload-arch=gfx950",
                  "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
     tasks = []
     objs = []
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
+        obj = os.path.join(build_dir, src + ".o")
         tasks.append(([hipcc, *common, *hip_flags, "-c", os.path.join(CSRC, src), "-o", obj], src))
         objs.append(obj)
     for src in HOST_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
+        obj = os.path.join(build_dir, src + ".o")
         extra = ["-ffp-contract=off"] if src == "host.cpp" else []
         tasks.append(([hipcc, *common, *extra, "-c", os.path.join(CSRC, src), "-o", obj], src))
         objs.append(obj)
@@ -61,14 +65,16 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         for src in ex.map(_compile, tasks):
             if verbose:
                 print("compiled", src, flush=True)
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     link = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(link)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT, flush=True)
+        print("built", out, flush=True)
+    if out != OUT:
+        return out
     # ALU probe used to check the roofline ceiling of the quadrature kernels
     probe_src = os.path.join(HERE, "probe", "alu_probe.hip")
     probe_bin = os.path.join(HERE, "probe", "alu_probe")

@@ -307,7 +307,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     };
     GCA_TRY(build_adjacency(h->mesh, h->adj));
     lap(0);
-    GCA_TRY(build_pair_lists(h->mesh, h->adj, h->tree, h->pl));
+    GCA_TRY(build_pair_lists(h->mesh, h->adj, h->tree, p->q_nr != p->q_r, h->pl));
     lap(1);
     block_tree(h->tree, p->eta, h->blk);
 
@@ -392,7 +392,10 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         return GCA_OK;
     };
     GCA_TRY(tri_pts(p->q_r, &h->d_qr));
-    GCA_TRY(tri_pts(p->q_nr, &h->d_qnr));
+    if (p->q_nr == p->q_r)
+        h->d_qnr = h->d_qr;
+    else
+        GCA_TRY(tri_pts(p->q_nr, &h->d_qnr));
     if (p->q_A == p->q_r)
         h->d_qA = h->d_qr;
     else
@@ -752,7 +755,7 @@ void gca_params_default(gca_params *p)
     p->green_m = 3;
     p->q_A = 3;
     p->q_r = 3;
-    p->q_nr = 4;
+    p->q_nr = 3;
     p->q_s = 4;
 }
 
@@ -1071,7 +1074,7 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
         return GCA_OK;
     };
     GCA_TRY(tri_pts(h->prm.q_r, h->d_qr));
-    GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
+    if (h->d_qnr != h->d_qr) GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
     if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, h->d_qA));
     GCA_HIP_TRY(launch_frozen_basis(h, s));
     Frozen &fz = h->fz;

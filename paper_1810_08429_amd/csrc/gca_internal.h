@@ -99,7 +99,9 @@ struct PairLists {
     std::vector<int32_t> t_other, n_other;
     std::vector<int32_t> slot_a, slot_b;
 };
-gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t,
+// with_nearreg = false: near-regular pairs use the regular rule (q_nr == q_r)
+// and stay in the nearfield blocks, so no list is built for them.
+gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t, bool with_nearreg,
                             PairLists &pl);
 int classify_pair(const Mesh &m, const Adjacency &adj, int32_t i, int32_t j, int32_t *code);
 const char *last_error_cstr();

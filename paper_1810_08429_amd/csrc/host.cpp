@@ -361,7 +361,8 @@ int classify_pair(const Mesh &m, const Adjacency &adj, int32_t i, int32_t j, int
     return 4;
 }
 
-gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t, PairLists &pl)
+gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t, bool with_nearreg,
+                            PairLists &pl)
 {
     const int64_t nt = m.nt;
     std::vector<int32_t> iperm(nt);
@@ -404,7 +405,8 @@ gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_
                     int32_t code;
                     int k = classify_pair(m, adj, (int32_t)i, j, &code);
                     if (k == 0) dup = true;
-                    if (k >= 1 && k <= 3) cls[k].push_back(P{(int32_t)i, j, code});
+                    if (k >= 1 && k <= 2) cls[k].push_back(P{(int32_t)i, j, code});
+                    if (k == 3 && with_nearreg) cls[k].push_back(P{(int32_t)i, j, code});
                 }
             }
         }

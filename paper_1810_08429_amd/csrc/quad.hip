@@ -75,10 +75,11 @@ struct BlkArgs {
 // mask[rmax] u64 | rowp[rmax][P][4] | colp[P][4][CW] | S[rmax][CW] | xr[rmax] | xc[CW]
 __host__ __device__ constexpr size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
 
+// | rown[rmax][P] | coln[P][CW]   (squared norms, expanded-distance path only)
 template <typename T>
 struct BlkLayout {
-    size_t mask, rowp, colp, S, xr, xc, total;
-    __host__ __device__ BlkLayout(int rmax, int P, int CW)
+    size_t mask, rowp, colp, S, xr, xc, rown, coln, total;
+    __host__ __device__ BlkLayout(int rmax, int P, int CW, bool exp)
     {
         mask = 0;
         rowp = mask + al16((size_t)rmax * 8);
@@ -86,7 +87,9 @@ struct BlkLayout {
         S = colp + al16((size_t)P * 4 * CW * sizeof(T));
         xr = S + al16((size_t)rmax * CW * sizeof(T));
         xc = xr + al16((size_t)rmax * sizeof(T));
-        total = xc + al16((size_t)CW * sizeof(T));
+        rown = xc + al16((size_t)CW * sizeof(T));
+        coln = rown + (exp ? al16((size_t)rmax * P * sizeof(T)) : 0);
+        total = coln + (exp ? al16((size_t)P * CW * sizeof(T)) : 0);
     }
 };
 
@@ -98,13 +101,21 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
     const int tid = threadIdx.x;
     const int t = a.bt[b], s = a.bs[b];
     const int rmax = a.rmax, CW = a.cw;
-    const BlkLayout<T> L(rmax, P, CW);
+    const BlkLayout<T> L(rmax, P, CW, !NEAR && sizeof(T) == 4);
     uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
     T *rowp = reinterpret_cast<T *>(smem + L.rowp);
     T *colp = reinterpret_cast<T *>(smem + L.colp);
     T *S = reinterpret_cast<T *>(smem + L.S);
     T *xr = reinterpret_cast<T *>(smem + L.xr);
     T *xc = reinterpret_cast<T *>(smem + L.xc);
+    // FP32 coupling blocks evaluate |x - y|^2 = |x|^2 + |y|^2 - 2 x.y (one add and
+    // three FMAs instead of three subtractions, a multiply and two FMAs) with
+    // coordinates relative to the midpoint of the two clusters' centres;
+    // admissibility keeps |x - y| >= dist >= diam / (2 eta), so the relative
+    // cancellation error stays below ~50 FP32 ulps of |x - y|^2.
+    constexpr bool EXP = !NEAR && sizeof(T) == 4;
+    T *rown = reinterpret_cast<T *>(smem + L.rown);
+    T *coln = reinterpret_cast<T *>(smem + L.coln);
 
     int nr, nc;
     int rb = 0, cb = 0;                 // NEAR: first positions
@@ -125,21 +136,31 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
     }
     const bool emit_col = (t != s);
     const int64_t slot_r = a.slot[2 * b], slot_c = a.slot[2 * b + 1];
-    const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
-    const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
-    const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+    double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
+    double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
+    double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+    if (!NEAR) {
+        cx = 0.5 * (cx + 0.5 * (a.box[8 * s + 0] + a.box[8 * s + 3]));
+        cy = 0.5 * (cy + 0.5 * (a.box[8 * s + 1] + a.box[8 * s + 4]));
+        cz = 0.5 * (cz + 0.5 * (a.box[8 * s + 2] + a.box[8 * s + 5]));
+    }
+    auto stage_rows = [&](int r0, int rw) {
+        for (int e = tid; e < rw * P; e += BLK_THREADS) {
+            int i = e / P, p = e - i * P;
+            int pos = NEAR ? rb + r0 + i : rl[r0 + i];
+            const double *src = a.q + ((size_t)pos * P + p) * 4;
+            T *dst = rowp + ((size_t)i * P + p) * 4;
+            const T x0 = (T)(src[0] - cx), x1 = (T)(src[1] - cy), x2 = (T)(src[2] - cz);
+            dst[0] = x0;
+            dst[1] = x1;
+            dst[2] = x2;
+            dst[3] = (T)src[3];
+            if (EXP) rown[(size_t)i * P + p] = x0 * x0 + x1 * x1 + x2 * x2;
+        }
+    };
 
     // stage the first chunk of row points (relative to the reference point)
-    for (int e = tid; e < min(nr, rmax) * P; e += BLK_THREADS) {
-        int i = e / P, p = e - i * P;
-        int pos = NEAR ? rb + i : rl[i];
-        const double *src = a.q + ((size_t)pos * P + p) * 4;
-        T *dst = rowp + ((size_t)i * P + p) * 4;
-        dst[0] = (T)(src[0] - cx);
-        dst[1] = (T)(src[1] - cy);
-        dst[2] = (T)(src[2] - cz);
-        dst[3] = (T)src[3];
-    }
+    stage_rows(0, min(nr, rmax));
     for (int i = tid; i < min(nr, rmax); i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + i] : a.xv[xro + i];
     if (NEAR) {
         for (int i = tid; i < nr; i += BLK_THREADS) {
@@ -159,16 +180,7 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
         const int rw = min(rmax, nr - r0);
         if (r0 > 0) {
             __syncthreads();
-            for (int e = tid; e < rw * P; e += BLK_THREADS) {
-                int i = e / P, p = e - i * P;
-                int pos = NEAR ? rb + r0 + i : rl[r0 + i];
-                const double *src = a.q + ((size_t)pos * P + p) * 4;
-                T *dst = rowp + ((size_t)i * P + p) * 4;
-                dst[0] = (T)(src[0] - cx);
-                dst[1] = (T)(src[1] - cy);
-                dst[2] = (T)(src[2] - cz);
-                dst[3] = (T)src[3];
-            }
+            stage_rows(r0, rw);
             for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + r0 + i] : a.xv[xro + r0 + i];
         }
         T racc = 0;
@@ -179,9 +191,17 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
                 int j = e / P, p = e - j * P;
                 int pos = NEAR ? cb + c0 + j : cl[c0 + j];
                 const double *src = a.q + ((size_t)pos * P + p) * 4;
-                colp[(p * 4 + 0) * CW + j] = (T)(src[0] - cx);
-                colp[(p * 4 + 1) * CW + j] = (T)(src[1] - cy);
-                colp[(p * 4 + 2) * CW + j] = (T)(src[2] - cz);
+                const T y0 = (T)(src[0] - cx), y1 = (T)(src[1] - cy), y2 = (T)(src[2] - cz);
+                if (EXP) {
+                    colp[(p * 4 + 0) * CW + j] = -2 * y0;
+                    colp[(p * 4 + 1) * CW + j] = -2 * y1;
+                    colp[(p * 4 + 2) * CW + j] = -2 * y2;
+                    coln[p * CW + j] = y0 * y0 + y1 * y1 + y2 * y2;
+                } else {
+                    colp[(p * 4 + 0) * CW + j] = y0;
+                    colp[(p * 4 + 1) * CW + j] = y1;
+                    colp[(p * 4 + 2) * CW + j] = y2;
+                }
                 colp[(p * 4 + 3) * CW + j] = (T)src[3];
             }
             for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = NEAR ? a.xv[cb + c0 + j] : a.xv[xco + c0 + j];
@@ -193,22 +213,44 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
                 if (!skip) {
                     const T *rp = rowp + (size_t)i * P * 4;
                     T acc = 0;
+                    if (EXP) {
+                        const T *rn = rown + (size_t)i * P;
 #pragma unroll
-                    for (int pb = 0; pb < P; ++pb) {
-                        const T yx = colp[(pb * 4 + 0) * CW + j];
-                        const T yy = colp[(pb * 4 + 1) * CW + j];
-                        const T yz = colp[(pb * 4 + 2) * CW + j];
-                        const T yw = colp[(pb * 4 + 3) * CW + j];
-                        T inner = 0;
+                        for (int pb = 0; pb < P; ++pb) {
+                            const T mx = colp[(pb * 4 + 0) * CW + j];
+                            const T my = colp[(pb * 4 + 1) * CW + j];
+                            const T mz = colp[(pb * 4 + 2) * CW + j];
+                            const T yw = colp[(pb * 4 + 3) * CW + j];
+                            const T ny = coln[pb * CW + j];
+                            T inner = 0;
 #pragma unroll
-                        for (int pa = 0; pa < P; ++pa) {
-                            const T dx = rp[4 * pa + 0] - yx;
-                            const T dy = rp[4 * pa + 1] - yy;
-                            const T dz = rp[4 * pa + 2] - yz;
-                            const T r2 = dx * dx + dy * dy + dz * dz;
-                            inner += rp[4 * pa + 3] * rsq<T>(r2);
+                            for (int pa = 0; pa < P; ++pa) {
+                                T r2 = rn[pa] + ny;
+                                r2 = fmaf(rp[4 * pa + 2], mz, r2);
+                                r2 = fmaf(rp[4 * pa + 1], my, r2);
+                                r2 = fmaf(rp[4 * pa + 0], mx, r2);
+                                inner += rp[4 * pa + 3] * rsq<T>(r2);
+                            }
+                            acc += yw * inner;
                         }
-                        acc += yw * inner;
+                    } else {
+#pragma unroll
+                        for (int pb = 0; pb < P; ++pb) {
+                            const T yx = colp[(pb * 4 + 0) * CW + j];
+                            const T yy = colp[(pb * 4 + 1) * CW + j];
+                            const T yz = colp[(pb * 4 + 2) * CW + j];
+                            const T yw = colp[(pb * 4 + 3) * CW + j];
+                            T inner = 0;
+#pragma unroll
+                            for (int pa = 0; pa < P; ++pa) {
+                                const T dx = rp[4 * pa + 0] - yx;
+                                const T dy = rp[4 * pa + 1] - yy;
+                                const T dz = rp[4 * pa + 2] - yz;
+                                const T r2 = dx * dx + dy * dy + dz * dz;
+                                inner += rp[4 * pa + 3] * rsq<T>(r2);
+                            }
+                            acc += yw * inner;
+                        }
                     }
                     g = acc * (T)INV4PI;
                 }
@@ -234,15 +276,15 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
 }
 
 template <typename T>
-static size_t blk_smem(int rmax, int P, int cw)
+static size_t blk_smem(int rmax, int P, int cw, bool exp)
 {
-    return BlkLayout<T>(rmax, P, cw).total;
+    return BlkLayout<T>(rmax, P, cw, exp).total;
 }
 
 template <typename T, bool NEAR>
 static hipError_t launch_blocks_P(int P, const BlkArgs<T> &a, hipStream_t s)
 {
-    size_t sm = blk_smem<T>(a.rmax, P, a.cw);
+    size_t sm = blk_smem<T>(a.rmax, P, a.cw, !NEAR && sizeof(T) == 4);
     dim3 g(a.nblk), blk(BLK_THREADS);
     switch (P) {
 #define CASE(PP)                                                                              \
@@ -257,12 +299,19 @@ static hipError_t launch_blocks_P(int P, const BlkArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// LDS budget per workgroup of the block kernel: the widest column chunk
+// (multiple of 8, at most 64) whose tiles fit it.  The budget trades fewer
+// chunks against more resident workgroups per CU (160 KB of LDS each).
+#ifndef GCA_BLK_LDS_KB
+#define GCA_BLK_LDS_KB 60
+#endif
 template <typename T>
-static int blk_cw(int rmax, int P)
+static int blk_cw(int rmax, int P, bool exp)
 {
-    // widest column chunk (multiple of 8, at most 64) whose tiles fit 60 KB of LDS
     for (int cw = 64; cw >= 8; cw -= 8)
-        if (blk_smem<T>(rmax, P, cw) <= 60 * 1024) return cw;
+        if (blk_smem<T>(rmax, P, cw, exp) <= GCA_BLK_LDS_KB * 1024) return cw;
+    for (int cw = 64; cw >= 8; cw -= 8)
+        if (blk_smem<T>(rmax, P, cw, exp) <= 64 * 1024) return cw;
     return 0;
 }
 
@@ -285,7 +334,7 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
     a.part = npart;
     a.nblk = nb;
     a.rmax = h->max_leaf;
-    a.cw = blk_cw<T>(a.rmax, P);
+    a.cw = blk_cw<T>(a.rmax, P, false);
     if (a.cw == 0) return hipErrorInvalidValue;
     return launch_blocks_P<T, true>(P, a, s);
 }
@@ -310,7 +359,7 @@ hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
     a.part = cpart;
     a.nblk = nb;
     a.rmax = std::max(1, std::min(64, h->max_rank));
-    a.cw = blk_cw<T>(a.rmax, P);
+    a.cw = blk_cw<T>(a.rmax, P, sizeof(T) == 4);
     if (a.cw == 0) return hipErrorInvalidValue;
     return launch_blocks_P<T, false>(P, a, s);
 }
