@@ -40,17 +40,30 @@ struct GaussQ {
 };
 
 // ------------------------------------------------------ block kernel -------
-// One workgroup (256 threads) per block (t, s).
+// One workgroup (256 threads = 4 wavefronts) per block (t, s).
 //   NEAR: rows = positions of leaf t, cols = positions of leaf s; entries of
-//         pairs that are not regular (touching or near-regular, from the
-//         per-row pair CSR) are masked to zero -- the list kernels own them.
+//         the pairs in the per-row pair CSR (touching pairs, and near-regular
+//         pairs when their order differs from the regular one) are masked to
+//         zero -- the list kernels own them.
 //   FAR : rows = pivots t~, cols = pivots s~ (coupling matrix G|t~ x s~).
-// Coordinates are taken relative to the centre of t's box in FP64 and then
-// rounded to T, so FP32 keeps the relative accuracy of short distances.
-// The block writes the row partial  sum_j g_ij x_j  to part[slot_row + i] and,
-// for t != s, the column partial sum_i g_ij x_i  to part[slot_col + j].
-// Deterministic: no atomics; every partial has exactly one writer.
+// Point sets are staged in LDS relative to a reference point (FP64 subtract,
+// then rounding to T), so FP32 keeps the relative accuracy of short distances.
+// Entries are computed in wavefront tiles of R x C = 64 lanes (C = 4 .. 64,
+// chosen per chunk to waste the fewest lanes on ragged edges) and multiplied
+// at once: g_ij x_j is summed over the C lanes of a tile row and g_ij x_i over
+// the R lanes of a tile column by cross-lane shuffles, then added to row and
+// column accumulators that each wavefront owns in LDS.  The block writes the
+// row partial  sum_j g_ij x_j  to part[slot_row + i] and, for t != s, the
+// column partial  sum_i g_ij x_i  to part[slot_col + j].  Deterministic: a
+// fixed tile order per wavefront, fixed reduction orders, no atomics, one
+// writer per partial.
 constexpr int BLK_THREADS = 256;
+constexpr int BLK_WAVES = BLK_THREADS / 64;
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+    T x, y, z, w;
+};
 
 template <typename T>
 struct BlkArgs {
@@ -71,51 +84,101 @@ struct BlkArgs {
     int cw;                   // column chunk width
 };
 
-// LDS layout of the block kernel (byte offsets, 16-byte aligned sections):
-// mask[rmax] u64 | rowp[rmax][P][4] | colp[P][4][CW] | S[rmax][CW] | xr[rmax] | xc[CW]
 __host__ __device__ constexpr size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
 
-// | rown[rmax][P] | coln[P][CW]   (squared norms, expanded-distance path only)
+// LDS layout of the block kernel (byte offsets, 16-byte aligned sections):
+//   mask[rmax] u64 (NEAR) | rowp[rmax][P] Q4 | rown[rmax][P] (EXP) |
+//   colp[CW][P] Q4 | coln[CW][P] (EXP) | xr[rmax] | xc[CW] |
+//   racc[4][rmax] | cacc[4][CW]
+// EXP (the FP32 coupling blocks) stores squared norms for the expanded
+// distance |x - y|^2 = |x|^2 + |y|^2 - 2 x.y.
 template <typename T>
 struct BlkLayout {
-    size_t mask, rowp, colp, S, xr, xc, rown, coln, total;
-    __host__ __device__ BlkLayout(int rmax, int P, int CW, bool exp)
+    size_t mask, rowp, rown, colp, coln, xr, xc, racc, cacc, total;
+    __host__ __device__ BlkLayout(int rmax, int P, int CW, bool near, bool exp)
     {
         mask = 0;
-        rowp = mask + al16((size_t)rmax * 8);
-        colp = rowp + al16((size_t)rmax * P * 4 * sizeof(T));
-        S = colp + al16((size_t)P * 4 * CW * sizeof(T));
-        xr = S + al16((size_t)rmax * CW * sizeof(T));
+        rowp = mask + (near ? al16((size_t)rmax * 8) : 0);
+        rown = rowp + al16((size_t)rmax * P * sizeof(Q4<T>));
+        colp = rown + (exp ? al16((size_t)rmax * P * sizeof(T)) : 0);
+        coln = colp + al16((size_t)CW * P * sizeof(Q4<T>));
+        xr = coln + (exp ? al16((size_t)CW * P * sizeof(T)) : 0);
         xc = xr + al16((size_t)rmax * sizeof(T));
-        rown = xc + al16((size_t)CW * sizeof(T));
-        coln = rown + (exp ? al16((size_t)rmax * P * sizeof(T)) : 0);
-        total = coln + (exp ? al16((size_t)P * CW * sizeof(T)) : 0);
+        racc = xc + al16((size_t)CW * sizeof(T));
+        cacc = racc + al16((size_t)BLK_WAVES * rmax * sizeof(T));
+        total = cacc + al16((size_t)BLK_WAVES * CW * sizeof(T));
     }
 };
 
+template <typename T>
+__device__ __forceinline__ T fmat(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fmat<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fmat<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// sum over the collapsed rules of both triangles of w_a w_b / |x_a - y_b|,
+// row points in registers, column points from LDS
+template <typename T, int P, bool EXP>
+__device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[EXP ? P : 1], const Q4<T> *cp,
+                                        const T *cn)
+{
+    T acc = 0;
+#pragma unroll
+    for (int pb = 0; pb < P; ++pb) {
+        const Q4<T> c = cp[pb];
+        T inner = 0;
+        if (EXP) {
+            const T ny = cn[pb];
+#pragma unroll
+            for (int pa = 0; pa < P; ++pa) {
+                T r2 = rn[EXP ? pa : 0] + ny;
+                r2 = fmat(rp[pa].z, c.z, r2);
+                r2 = fmat(rp[pa].y, c.y, r2);
+                r2 = fmat(rp[pa].x, c.x, r2);
+                inner = fmat(rp[pa].w, rsq<T>(r2), inner);
+            }
+        } else {
+#pragma unroll
+            for (int pa = 0; pa < P; ++pa) {
+                const T dx = rp[pa].x - c.x, dy = rp[pa].y - c.y, dz = rp[pa].z - c.z;
+                const T r2 = fmat(dz, dz, fmat(dy, dy, dx * dx));
+                inner = fmat(rp[pa].w, rsq<T>(r2), inner);
+            }
+        }
+        acc = fmat(c.w, inner, acc);
+    }
+    return acc;
+}
+
+#ifdef GCA_BLK_WAVES_PER_EU
+#define GCA_BLK_ATTR __attribute__((amdgpu_waves_per_eu(GCA_BLK_WAVES_PER_EU)))
+#else
+#define GCA_BLK_ATTR
+#endif
 template <typename T, int P, bool NEAR>
-__global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
+#ifndef GCA_BLK_FP64_WAVES
+#define GCA_BLK_FP64_WAVES 4
+#endif
+__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAVES : 1) GCA_BLK_ATTR
+    k_blocks(BlkArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr bool EXP = !NEAR && sizeof(T) == 4;
     const int b = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int t = a.bt[b], s = a.bs[b];
     const int rmax = a.rmax, CW = a.cw;
-    const BlkLayout<T> L(rmax, P, CW, !NEAR && sizeof(T) == 4);
+    const BlkLayout<T> L(rmax, P, CW, NEAR, EXP);
     uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
-    T *rowp = reinterpret_cast<T *>(smem + L.rowp);
-    T *colp = reinterpret_cast<T *>(smem + L.colp);
-    T *S = reinterpret_cast<T *>(smem + L.S);
+    Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
+    T *rown = reinterpret_cast<T *>(smem + L.rown);
+    Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
+    T *coln = reinterpret_cast<T *>(smem + L.coln);
     T *xr = reinterpret_cast<T *>(smem + L.xr);
     T *xc = reinterpret_cast<T *>(smem + L.xc);
-    // FP32 coupling blocks evaluate |x - y|^2 = |x|^2 + |y|^2 - 2 x.y (one add and
-    // three FMAs instead of three subtractions, a multiply and two FMAs) with
-    // coordinates relative to the midpoint of the two clusters' centres;
-    // admissibility keeps |x - y| >= dist >= diam / (2 eta), so the relative
-    // cancellation error stays below ~50 FP32 ulps of |x - y|^2.
-    constexpr bool EXP = !NEAR && sizeof(T) == 4;
-    T *rown = reinterpret_cast<T *>(smem + L.rown);
-    T *coln = reinterpret_cast<T *>(smem + L.coln);
+    T *racc = reinterpret_cast<T *>(smem + L.racc);
+    T *cacc = reinterpret_cast<T *>(smem + L.cacc);
 
     int nr, nc;
     int rb = 0, cb = 0;                 // NEAR: first positions
@@ -136,6 +199,7 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
     }
     const bool emit_col = (t != s);
     const int64_t slot_r = a.slot[2 * b], slot_c = a.slot[2 * b + 1];
+    // reference point: centre of t's box (NEAR), midpoint of both centres (FAR)
     double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
     double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
     double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
@@ -144,24 +208,9 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
         cy = 0.5 * (cy + 0.5 * (a.box[8 * s + 1] + a.box[8 * s + 4]));
         cz = 0.5 * (cz + 0.5 * (a.box[8 * s + 2] + a.box[8 * s + 5]));
     }
-    auto stage_rows = [&](int r0, int rw) {
-        for (int e = tid; e < rw * P; e += BLK_THREADS) {
-            int i = e / P, p = e - i * P;
-            int pos = NEAR ? rb + r0 + i : rl[r0 + i];
-            const double *src = a.q + ((size_t)pos * P + p) * 4;
-            T *dst = rowp + ((size_t)i * P + p) * 4;
-            const T x0 = (T)(src[0] - cx), x1 = (T)(src[1] - cy), x2 = (T)(src[2] - cz);
-            dst[0] = x0;
-            dst[1] = x1;
-            dst[2] = x2;
-            dst[3] = (T)src[3];
-            if (EXP) rown[(size_t)i * P + p] = x0 * x0 + x1 * x1 + x2 * x2;
-        }
-    };
 
-    // stage the first chunk of row points (relative to the reference point)
-    stage_rows(0, min(nr, rmax));
-    for (int i = tid; i < min(nr, rmax); i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + i] : a.xv[xro + i];
+    for (int e = tid; e < BLK_WAVES * rmax; e += BLK_THREADS) racc[e] = 0;
+    for (int e = tid; e < BLK_WAVES * CW; e += BLK_THREADS) cacc[e] = 0;
     if (NEAR) {
         for (int i = tid; i < nr; i += BLK_THREADS) {
             uint64_t m = 0;
@@ -173,118 +222,123 @@ __global__ void __launch_bounds__(BLK_THREADS) k_blocks(BlkArgs<T> a)
             mask[i] = m;
         }
     }
-    // rows are processed in chunks of rmax (the LDS row tile); the column
-    // partials of later row chunks are added to what earlier chunks wrote
-    // (same thread, same address: deterministic)
+    // rows in chunks of rmax, columns in chunks of CW; the column partials of
+    // later row chunks are added to what earlier chunks wrote (same thread,
+    // same address: deterministic)
     for (int r0 = 0; r0 < nr; r0 += rmax) {
         const int rw = min(rmax, nr - r0);
-        if (r0 > 0) {
-            __syncthreads();
-            stage_rows(r0, rw);
-            for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + r0 + i] : a.xv[xro + r0 + i];
+        if (r0 > 0) __syncthreads();
+        for (int e = tid; e < rw * P; e += BLK_THREADS) {
+            const int i = e / P, p = e - i * P;
+            const int pos = NEAR ? rb + r0 + i : rl[r0 + i];
+            const double *src = a.q + ((size_t)pos * P + p) * 4;
+            const T x0 = (T)(src[0] - cx), x1 = (T)(src[1] - cy), x2 = (T)(src[2] - cz);
+            rowp[e] = Q4<T>{x0, x1, x2, (T)src[3]};
+            if (EXP) rown[e] = x0 * x0 + x1 * x1 + x2 * x2;
         }
-        T racc = 0;
+        for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + r0 + i] : a.xv[xro + r0 + i];
         for (int c0 = 0; c0 < nc; c0 += CW) {
             const int cw = min(CW, nc - c0);
             __syncthreads();
             for (int e = tid; e < cw * P; e += BLK_THREADS) {
-                int j = e / P, p = e - j * P;
-                int pos = NEAR ? cb + c0 + j : cl[c0 + j];
+                const int j = e / P, p = e - j * P;
+                const int pos = NEAR ? cb + c0 + j : cl[c0 + j];
                 const double *src = a.q + ((size_t)pos * P + p) * 4;
                 const T y0 = (T)(src[0] - cx), y1 = (T)(src[1] - cy), y2 = (T)(src[2] - cz);
                 if (EXP) {
-                    colp[(p * 4 + 0) * CW + j] = -2 * y0;
-                    colp[(p * 4 + 1) * CW + j] = -2 * y1;
-                    colp[(p * 4 + 2) * CW + j] = -2 * y2;
-                    coln[p * CW + j] = y0 * y0 + y1 * y1 + y2 * y2;
+                    colp[e] = Q4<T>{-2 * y0, -2 * y1, -2 * y2, (T)src[3]};
+                    coln[e] = y0 * y0 + y1 * y1 + y2 * y2;
                 } else {
-                    colp[(p * 4 + 0) * CW + j] = y0;
-                    colp[(p * 4 + 1) * CW + j] = y1;
-                    colp[(p * 4 + 2) * CW + j] = y2;
+                    colp[e] = Q4<T>{y0, y1, y2, (T)src[3]};
                 }
-                colp[(p * 4 + 3) * CW + j] = (T)src[3];
             }
             for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = NEAR ? a.xv[cb + c0 + j] : a.xv[xco + c0 + j];
             __syncthreads();
-            for (int e = tid; e < rw * cw; e += BLK_THREADS) {
-                const int i = e / cw, j = e - i * cw;
-                T g = 0;
-                bool skip = NEAR && ((mask[i] >> (c0 + j)) & 1);
-                if (!skip) {
-                    const T *rp = rowp + (size_t)i * P * 4;
-                    T acc = 0;
-                    if (EXP) {
-                        const T *rn = rown + (size_t)i * P;
-#pragma unroll
-                        for (int pb = 0; pb < P; ++pb) {
-                            const T mx = colp[(pb * 4 + 0) * CW + j];
-                            const T my = colp[(pb * 4 + 1) * CW + j];
-                            const T mz = colp[(pb * 4 + 2) * CW + j];
-                            const T yw = colp[(pb * 4 + 3) * CW + j];
-                            const T ny = coln[pb * CW + j];
-                            T inner = 0;
-#pragma unroll
-                            for (int pa = 0; pa < P; ++pa) {
-                                T r2 = rn[pa] + ny;
-                                r2 = fmaf(rp[4 * pa + 2], mz, r2);
-                                r2 = fmaf(rp[4 * pa + 1], my, r2);
-                                r2 = fmaf(rp[4 * pa + 0], mx, r2);
-                                inner += rp[4 * pa + 3] * rsq<T>(r2);
-                            }
-                            acc += yw * inner;
-                        }
-                    } else {
-#pragma unroll
-                        for (int pb = 0; pb < P; ++pb) {
-                            const T yx = colp[(pb * 4 + 0) * CW + j];
-                            const T yy = colp[(pb * 4 + 1) * CW + j];
-                            const T yz = colp[(pb * 4 + 2) * CW + j];
-                            const T yw = colp[(pb * 4 + 3) * CW + j];
-                            T inner = 0;
-#pragma unroll
-                            for (int pa = 0; pa < P; ++pa) {
-                                const T dx = rp[4 * pa + 0] - yx;
-                                const T dy = rp[4 * pa + 1] - yy;
-                                const T dz = rp[4 * pa + 2] - yz;
-                                const T r2 = dx * dx + dy * dy + dz * dz;
-                                inner += rp[4 * pa + 3] * rsq<T>(r2);
-                            }
-                            acc += yw * inner;
-                        }
-                    }
-                    g = acc * (T)INV4PI;
+            // tile shape: fewest tile rounds over the 4 wavefronts, then fewest tiles
+            int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
+            for (int l = 2; l <= 6; ++l) {
+                const int R = 64 >> l;
+                const int n = ((rw + R - 1) / R) * ((cw + (1 << l) - 1) >> l);
+                const int rounds = (n + BLK_WAVES - 1) / BLK_WAVES;
+                if (rounds < best_r || (rounds == best_r && n < best_n)) {
+                    best_r = rounds;
+                    best_n = n;
+                    lc = l;
                 }
-                S[(size_t)i * CW + j] = g;
+            }
+            const int C = 1 << lc, R = 64 >> lc;
+            const int ii = lane >> lc, jj = lane & (C - 1);
+            const int nct = (cw + C - 1) >> lc;
+            // each wavefront takes a contiguous run of the row-major tile list,
+            // so consecutive tiles mostly share their rows: the row points stay
+            // in registers until the tile row changes
+            const int k0 = (wv * best_n) / BLK_WAVES, k1 = ((wv + 1) * best_n) / BLK_WAVES;
+            Q4<T> rr[P];
+            T rq[EXP ? P : 1];
+            int cur_tr = -1;
+            for (int k = k0; k < k1; ++k) {
+                const int tr = k / nct, tc = k - tr * nct;
+                const int i = tr * R + ii, j = tc * C + jj;
+                if (tr != cur_tr) {
+                    cur_tr = tr;
+                    const int il = min(i, rw - 1);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        rr[p] = rowp[(size_t)il * P + p];
+                        if (EXP) rq[EXP ? p : 0] = rown[(size_t)il * P + p];
+                    }
+                }
+                const bool valid = i < rw && j < cw;
+                T v = 0, u = 0;
+                if (valid && !(NEAR && ((mask[i] >> (c0 + j)) & 1))) {
+                    const T g = block_entry<T, P, EXP>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) *
+                                (T)INV4PI;
+                    v = g * xc[j];
+                    u = g * xr[i];
+                }
+                for (int o = 1; o < C; o <<= 1) v += __shfl_xor(v, o, 64);
+                for (int o = C; o < 64; o <<= 1) u += __shfl_xor(u, o, 64);
+                if (jj == 0 && i < rw) racc[wv * rmax + i] += v;
+                if (ii == 0 && j < cw) cacc[wv * CW + j] += u;
             }
             __syncthreads();
-            if (tid < rw) {
-                T r = 0;
-                for (int j = 0; j < cw; ++j) r += S[(size_t)tid * CW + j] * xc[j];
-                racc += r;
-            }
-            if (emit_col && tid < cw) {
+            for (int j = tid; j < cw; j += BLK_THREADS) {
                 T c = 0;
-                for (int i = 0; i < rw; ++i) c += S[(size_t)i * CW + tid] * xr[i];
-                if (r0 == 0)
-                    a.part[slot_c + c0 + tid] = c;
-                else
-                    a.part[slot_c + c0 + tid] += c;
+#pragma unroll
+                for (int w = 0; w < BLK_WAVES; ++w) {
+                    c += cacc[w * CW + j];
+                    cacc[w * CW + j] = 0;
+                }
+                if (emit_col) {
+                    if (r0 == 0)
+                        a.part[slot_c + c0 + j] = c;
+                    else
+                        a.part[slot_c + c0 + j] += c;
+                }
             }
         }
-        if (tid < rw) a.part[slot_r + r0 + tid] = racc;
+        for (int i = tid; i < rw; i += BLK_THREADS) {
+            T r = 0;
+#pragma unroll
+            for (int w = 0; w < BLK_WAVES; ++w) {
+                r += racc[w * rmax + i];
+                racc[w * rmax + i] = 0;
+            }
+            a.part[slot_r + r0 + i] = r;
+        }
     }
 }
 
 template <typename T>
-static size_t blk_smem(int rmax, int P, int cw, bool exp)
+static size_t blk_smem(int rmax, int P, int cw, bool near, bool exp)
 {
-    return BlkLayout<T>(rmax, P, cw, exp).total;
+    return BlkLayout<T>(rmax, P, cw, near, exp).total;
 }
 
 template <typename T, bool NEAR>
 static hipError_t launch_blocks_P(int P, const BlkArgs<T> &a, hipStream_t s)
 {
-    size_t sm = blk_smem<T>(a.rmax, P, a.cw, !NEAR && sizeof(T) == 4);
+    size_t sm = blk_smem<T>(a.rmax, P, a.cw, NEAR, !NEAR && sizeof(T) == 4);
     dim3 g(a.nblk), blk(BLK_THREADS);
     switch (P) {
 #define CASE(PP)                                                                              \
@@ -300,18 +354,18 @@ static hipError_t launch_blocks_P(int P, const BlkArgs<T> &a, hipStream_t s)
 }
 
 // LDS budget per workgroup of the block kernel: the widest column chunk
-// (multiple of 8, at most 64) whose tiles fit it.  The budget trades fewer
+// (multiple of 8, at most 128) whose arrays fit it.  The budget trades fewer
 // chunks against more resident workgroups per CU (160 KB of LDS each).
 #ifndef GCA_BLK_LDS_KB
-#define GCA_BLK_LDS_KB 60
+#define GCA_BLK_LDS_KB 40
 #endif
 template <typename T>
-static int blk_cw(int rmax, int P, bool exp)
+static int blk_cw(int rmax, int P, bool near, bool exp)
 {
+    for (int cw = 128; cw >= 8; cw -= 8)
+        if (blk_smem<T>(rmax, P, cw, near, exp) <= GCA_BLK_LDS_KB * 1024) return cw;
     for (int cw = 64; cw >= 8; cw -= 8)
-        if (blk_smem<T>(rmax, P, cw, exp) <= GCA_BLK_LDS_KB * 1024) return cw;
-    for (int cw = 64; cw >= 8; cw -= 8)
-        if (blk_smem<T>(rmax, P, cw, exp) <= 64 * 1024) return cw;
+        if (blk_smem<T>(rmax, P, cw, near, exp) <= 64 * 1024) return cw;
     return 0;
 }
 
@@ -334,7 +388,7 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
     a.part = npart;
     a.nblk = nb;
     a.rmax = h->max_leaf;
-    a.cw = blk_cw<T>(a.rmax, P, false);
+    a.cw = std::min(a.rmax, blk_cw<T>(a.rmax, P, true, false));
     if (a.cw == 0) return hipErrorInvalidValue;
     return launch_blocks_P<T, true>(P, a, s);
 }
@@ -359,7 +413,7 @@ hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
     a.part = cpart;
     a.nblk = nb;
     a.rmax = std::max(1, std::min(64, h->max_rank));
-    a.cw = blk_cw<T>(a.rmax, P, sizeof(T) == 4);
+    a.cw = std::min(std::max(8, h->max_rank), blk_cw<T>(a.rmax, P, false, sizeof(T) == 4));
     if (a.cw == 0) return hipErrorInvalidValue;
     return launch_blocks_P<T, false>(P, a, s);
 }
