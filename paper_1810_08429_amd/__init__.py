@@ -303,3 +303,84 @@ class H2:
         out = np.zeros((max(cnt.value, 1), len(PHASES)))
         _check(lib().gca_phase_times(self.h, int(max_products), out.ctypes.data, ctypes.byref(cnt)))
         return out[:cnt.value]
+
+
+# ------------------------------------------------------------- autograd ----
+# torch.autograd glue around h2_matvec and h2_bilinear_grad (marshalling only).
+# The operator G~(X) is symmetric, so the vector-Jacobian product of
+# y = G~ x with respect to x is G~ y_bar; with respect to the vertex
+# coordinates X it is d(y_bar^T G~ x)/dX at frozen structure.  The vertex
+# tensor passed in must hold the coordinates the operator was built or last
+# updated at (H2.update_geometry); it only routes the gradient.
+
+_autograd_fns = None
+
+
+def _fns():
+    global _autograd_fns
+    if _autograd_fns is not None:
+        return _autograd_fns
+    import torch
+
+    class _Matvec(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, verts, H, precision):
+            ctx.H, ctx.precision = H, precision
+            ctx.save_for_backward(x)
+            return H.matvec(x, precision)
+
+        @staticmethod
+        def backward(ctx, gy):
+            (x,) = ctx.saved_tensors
+            H, prec = ctx.H, ctx.precision
+            gx = gv = None
+            if ctx.needs_input_grad[0]:
+                gx = H.matvec(gy, prec)
+            if ctx.needs_input_grad[1]:
+                gv = torch.zeros((H._m.xyz.shape[0], 3), dtype=torch.float64, device=x.device)
+                if x.dim() == 1:
+                    H.bilinear_grad(gy, x, 1.0, gv, prec)
+                else:
+                    for k in range(x.shape[1]):
+                        H.bilinear_grad(gy[:, k], x[:, k], 1.0, gv, prec)
+            return gx, gv, None, None
+
+    class _Energy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, u, verts, H, precision):
+            ctx.H, ctx.precision = H, precision
+            gu = H.matvec(u, precision)
+            ctx.save_for_backward(u, gu)
+            return 0.5 * torch.dot(u, gu)
+
+        @staticmethod
+        def backward(ctx, ge):
+            u, gu = ctx.saved_tensors
+            H, prec = ctx.H, ctx.precision
+            du = dv = None
+            if ctx.needs_input_grad[0]:
+                du = ge * gu
+            if ctx.needs_input_grad[1]:
+                dv = torch.zeros((H._m.xyz.shape[0], 3), dtype=torch.float64, device=u.device)
+                H.bilinear_grad(u, u, 0.5 * float(ge), dv, prec)
+            return du, dv, None, None
+
+    _autograd_fns = (_Matvec, _Energy)
+    return _autograd_fns
+
+
+def matvec(H: "H2", x, verts=None, precision=FP64):
+    """Differentiable y = G~ x: gradients flow to x and, if given, to the
+    vertex tensor verts (nv x 3, float64, on x's device)."""
+    import torch
+    if verts is None:
+        verts = torch.zeros((0,), dtype=torch.float64, device=x.device)
+    return _fns()[0].apply(x, verts, H, precision)
+
+
+def energy(H: "H2", u, verts=None, precision=FP64):
+    """Differentiable E = 1/2 u^T G~ u (u: (n,) float64 cuda)."""
+    import torch
+    if verts is None:
+        verts = torch.zeros((0,), dtype=torch.float64, device=u.device)
+    return _fns()[1].apply(u, verts, H, precision)

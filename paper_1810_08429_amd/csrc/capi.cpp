@@ -441,6 +441,74 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         GCA_TRY(upload_new(h, &h->d_cslot_ptr, ptr, s));
         GCA_TRY(upload_new(h, &h->d_cslot, flat, s));
     }
+    // block rows of the coupling half for the product: blocks grouped by row
+    // cluster, groups launched in decreasing order of work
+    {
+        const size_t nb = h->blk.far_t.size();
+        std::vector<std::vector<int32_t>> cols_of(nc);
+        for (size_t b = 0; b < nb; ++b) cols_of[h->blk.far_t[b]].push_back(h->blk.far_s[b]);
+        std::vector<int32_t> gt;
+        std::vector<int64_t> work;
+        for (int c = 0; c < nc; ++c)
+            if (!cols_of[c].empty()) {
+                int64_t w = 0;
+                for (int u : cols_of[c]) w += (int64_t)h->rank[c] * h->rank[u];
+                gt.push_back(c);
+                work.push_back(w);
+            }
+        std::vector<int32_t> order(gt.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+        const size_t ng = gt.size();
+        std::vector<int32_t> fg_t(ng), col_e, col_s;
+        std::vector<int64_t> fg_ptr(ng + 1, 0), fg_rslot(ng), col_out;
+        std::vector<std::vector<int64_t>> per(nc);
+        int64_t off = 0;
+        for (size_t k = 0; k < ng; ++k) {
+            const int t = gt[order[k]];
+            fg_t[k] = t;
+            fg_rslot[k] = off;
+            per[t].push_back(off);
+            off += h->rank[t];
+            for (int u : cols_of[t]) {
+                per[u].push_back(off);
+                for (int j = 0; j < h->rank[u]; ++j) {
+                    col_e.push_back((int32_t)(h->piv_off[u] + j));
+                    col_s.push_back(u);
+                    col_out.push_back(off + j);
+                }
+                off += h->rank[u];
+            }
+            fg_ptr[k + 1] = (int64_t)col_e.size();
+        }
+        h->n_gslot_total = off;
+        h->n_far_groups = (int32_t)ng;
+        std::vector<int64_t> ptr(nc + 1, 0), flat;
+        for (int c = 0; c < nc; ++c) {
+            ptr[c + 1] = ptr[c] + (int64_t)per[c].size();
+            flat.insert(flat.end(), per[c].begin(), per[c].end());
+        }
+        if (ng > 0) {
+            GCA_TRY(upload_new(h, &h->d_fg_t, fg_t, s));
+            GCA_TRY(upload_new(h, &h->d_fg_ptr, fg_ptr, s));
+            GCA_TRY(upload_new(h, &h->d_fg_rslot, fg_rslot, s));
+            GCA_TRY(upload_new(h, &h->d_fcol_e, col_e, s));
+            GCA_TRY(upload_new(h, &h->d_fcol_s, col_s, s));
+            GCA_TRY(upload_new(h, &h->d_fcol_out, col_out, s));
+        }
+        GCA_TRY(upload_new(h, &h->d_gslot_ptr, ptr, s));
+        GCA_TRY(upload_new(h, &h->d_gslot, flat, s));
+        // FP32 pivot points relative to their cluster's centre
+        h->n_piv_total = h->n_piv;
+        std::vector<int32_t> pc((size_t)h->n_piv_total);
+        for (int c = 0; c < nc; ++c)
+            for (int64_t k = h->piv_off[c]; k < h->piv_off[c] + h->rank[c]; ++k) pc[(size_t)k] = c;
+        if (h->n_piv_total > 0) {
+            GCA_TRY(upload_new(h, &h->d_piv_cluster, pc, s));
+            GCA_TRY(dalloc(h, &h->d_pq32, (size_t)h->n_piv_total * p->q_r * p->q_r * 4));
+            GCA_HIP_TRY(launch_pivot_points(h, s));
+        }
+    }
     // near blocks and their partial slots
     {
         const size_t nb = h->blk.near_t.size();
@@ -497,8 +565,8 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     GCA_TRY(dalloc(h, &h->d_yh, h->n_piv));
     GCA_TRY(dalloc(h, &h->d_xhf, h->n_piv));
     GCA_TRY(dalloc(h, &h->d_yhf, h->n_piv));
-    GCA_TRY(dalloc(h, &h->d_cpart, h->n_cslot_total));
-    GCA_TRY(dalloc(h, &h->d_cpartf, h->n_cslot_total));
+    GCA_TRY(dalloc(h, &h->d_cpart, h->n_gslot_total));
+    GCA_TRY(dalloc(h, &h->d_cpartf, h->n_gslot_total));
     GCA_TRY(dalloc(h, &h->d_npart, h->n_nslot_total));
     GCA_TRY(dalloc(h, &h->d_npartf, h->n_nslot_total));
     for (auto &r : h->ev)
@@ -571,7 +639,7 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     mark(2);
     if ((e = launch_far_blocks<T>(h, xh, cpart, s)) != hipSuccess) return e;
     mark(3);
-    if ((e = launch_coupling_reduce<T>(h, cpart, yh, s)) != hipSuccess) return e;
+    if ((e = launch_coupling_reduce<T>(h, h->d_gslot_ptr, h->d_gslot, cpart, yh, s)) != hipSuccess) return e;
     mark(4);
     if ((e = launch_backward<T>(h, yh, s)) != hipSuccess) return e;
     mark(5);
@@ -663,7 +731,7 @@ gca_status grad_setup(gca_h2_s *h, hipStream_t s)
     w.ya = tmp;
     GCA_TRY(dalloc(h, &tmp, h->n_piv));
     w.yb = tmp;
-    GCA_TRY(dalloc(h, &tmp, h->n_cslot_total));
+    GCA_TRY(dalloc(h, &tmp, h->n_gslot_total));
     w.cpart = tmp;
     GCA_TRY(dalloc(h, &w.gnear, 9 * (size_t)h->n_nslot_total));
     GCA_TRY(dalloc(h, &w.gfar, 9 * (size_t)h->n_cslot_total));
@@ -732,9 +800,9 @@ hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alp
     if ((e = launch_forward<T>(h, ap, xa, s)) != hipSuccess) return e;
     if ((e = launch_forward<T>(h, bp, xb, s)) != hipSuccess) return e;
     if ((e = launch_far_blocks<T>(h, xa, cp, s)) != hipSuccess) return e;
-    if ((e = launch_coupling_reduce<T>(h, cp, ya, s)) != hipSuccess) return e;
+    if ((e = launch_coupling_reduce<T>(h, h->d_gslot_ptr, h->d_gslot, cp, ya, s)) != hipSuccess) return e;
     if ((e = launch_far_blocks<T>(h, xb, cp, s)) != hipSuccess) return e;
-    if ((e = launch_coupling_reduce<T>(h, cp, yb, s)) != hipSuccess) return e;
+    if ((e = launch_coupling_reduce<T>(h, h->d_gslot_ptr, h->d_gslot, cp, yb, s)) != hipSuccess) return e;
     if ((e = launch_backward<T>(h, ya, s)) != hipSuccess) return e;
     if ((e = launch_backward<T>(h, yb, s)) != hipSuccess) return e;
     if ((e = launch_bilinear_grad<T>(h, w, s)) != hipSuccess) return e;
@@ -1076,6 +1144,7 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
     GCA_TRY(tri_pts(h->prm.q_r, h->d_qr));
     if (h->d_qnr != h->d_qr) GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
     if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, h->d_qA));
+    if (h->n_piv_total > 0) GCA_HIP_TRY(launch_pivot_points(h, s));
     GCA_HIP_TRY(launch_frozen_basis(h, s));
     Frozen &fz = h->fz;
     GCA_HIP_TRY(launch_copy_jobs(fz.d_copy_jobs, fz.n_vjobs, fz.d_Vh, h->d_V, h->d_Vt, h->d_Vf, h->d_Vtf, s));

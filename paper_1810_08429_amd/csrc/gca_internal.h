@@ -219,6 +219,22 @@ struct gca_h2_s {
     int64_t n_cslot_total = 0;       // size of the coupling partial buffer
     int32_t max_rank = 0;
 
+    // coupling block rows (product path): one group per row cluster t with
+    // blocks (t, s); the columns of its blocks are concatenated
+    int32_t n_far_groups = 0;
+    int32_t *d_fg_t = nullptr;       // ng: row cluster
+    int64_t *d_fg_ptr = nullptr;     // ng + 1: column ranges
+    int64_t *d_fg_rslot = nullptr;   // ng: row-partial slot
+    int32_t *d_fcol_e = nullptr;     // per column: pivot entry piv_off[s] + j
+    int32_t *d_fcol_s = nullptr;     // per column: cluster s
+    int64_t *d_fcol_out = nullptr;   // per column: column-partial slot
+    int64_t *d_gslot_ptr = nullptr;  // nc + 1: per cluster CSR of partial slots
+    int64_t *d_gslot = nullptr;
+    int64_t n_gslot_total = 0;
+    int64_t n_piv_total = 0;         // sum of ranks
+    int32_t *d_piv_cluster = nullptr;   // per pivot entry: its cluster
+    float *d_pq32 = nullptr;         // per pivot entry: Pr x (x, y, z, w) relative to its cluster's centre
+
     // near blocks (t <= s)
     int32_t *d_near = nullptr;       // 2 x n_near_sym
     int64_t *d_near_slot = nullptr;  // 2 x n_near_sym (col slot -1 on diagonal)
@@ -286,7 +302,9 @@ hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s);
 template <typename T>
 hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s);
 template <typename T>
-hipError_t launch_coupling_reduce(gca_h2_s *h, const T *cpart, T *yh, hipStream_t s);
+hipError_t launch_coupling_reduce(gca_h2_s *h, const int64_t *slot_ptr, const int64_t *slots, const T *cpart,
+                                  T *yh, hipStream_t s);
+hipError_t launch_pivot_points(gca_h2_s *h, hipStream_t s);
 template <typename T>
 hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s);
 template <typename T>

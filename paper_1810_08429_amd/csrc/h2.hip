@@ -103,14 +103,17 @@ __global__ void k_coupling_reduce(const int32_t *rank, const int64_t *piv_off, c
 }
 
 template <typename T>
-hipError_t launch_coupling_reduce(gca_h2_s *h, const T *cpart, T *yh, hipStream_t s)
+hipError_t launch_coupling_reduce(gca_h2_s *h, const int64_t *slot_ptr, const int64_t *slots, const T *cpart,
+                                  T *yh, hipStream_t s)
 {
     hipLaunchKernelGGL(k_coupling_reduce<T>, dim3((unsigned)h->nc), dim3(128), 0, s, h->d_rank, h->d_piv_off,
-                       h->d_cslot_ptr, h->d_cslot, cpart, yh);
+                       slot_ptr, slots, cpart, yh);
     return hipGetLastError();
 }
-template hipError_t launch_coupling_reduce<float>(gca_h2_s *, const float *, float *, hipStream_t);
-template hipError_t launch_coupling_reduce<double>(gca_h2_s *, const double *, double *, hipStream_t);
+template hipError_t launch_coupling_reduce<float>(gca_h2_s *, const int64_t *, const int64_t *, const float *,
+                                                  float *, hipStream_t);
+template hipError_t launch_coupling_reduce<double>(gca_h2_s *, const int64_t *, const int64_t *, const double *,
+                                                   double *, hipStream_t);
 
 // backward transform for the clusters of one level below the root:
 // yh_c += E_c yh_parent (E_c column-major: Et[k * r_c + j])

@@ -151,6 +151,65 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[EXP
     return acc;
 }
 
+// One pass over the entries of an rw x cw chunk (rows in rowp/rown, columns
+// in colp/coln, both in LDS): tiles of R x C = 64 lanes (C = 4 .. 64 picked
+// for the fewest tile rounds over the 4 wavefronts, then the fewest tiles).
+// Each wavefront takes a contiguous run of the row-major tile list, so its
+// consecutive tiles mostly share their rows, which stay in registers until
+// the tile row changes.  Entry g_ij contributes g_ij x_j to racc[i] (summed
+// over the C lanes of a tile row by shuffles) and g_ij x_i to cacc[j] (over
+// the R lanes of a tile column); racc and cacc belong to the calling
+// wavefront.  MASK skips the pairs whose bit c0 + j is set in mask[i].
+template <typename T, int P, bool EXP, bool MASK>
+__device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *rowp, const T *rown,
+                                          const Q4<T> *colp, const T *coln, const T *xr, const T *xc,
+                                          const uint64_t *mask, T *racc, T *cacc)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
+    for (int l = 2; l <= 6; ++l) {
+        const int R = 64 >> l;
+        const int n = ((rw + R - 1) / R) * ((cw + (1 << l) - 1) >> l);
+        const int rounds = (n + BLK_WAVES - 1) / BLK_WAVES;
+        if (rounds < best_r || (rounds == best_r && n < best_n)) {
+            best_r = rounds;
+            best_n = n;
+            lc = l;
+        }
+    }
+    const int C = 1 << lc, R = 64 >> lc;
+    const int ii = lane >> lc, jj = lane & (C - 1);
+    const int nct = (cw + C - 1) >> lc;
+    const int k0 = (wv * best_n) / BLK_WAVES, k1 = ((wv + 1) * best_n) / BLK_WAVES;
+    Q4<T> rr[P];
+    T rq[EXP ? P : 1];
+    int cur_tr = -1;
+    for (int k = k0; k < k1; ++k) {
+        const int tr = k / nct, tc = k - tr * nct;
+        const int i = tr * R + ii, j = tc * C + jj;
+        if (tr != cur_tr) {
+            cur_tr = tr;
+            const int il = min(i, rw - 1);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                rr[p] = rowp[(size_t)il * P + p];
+                if (EXP) rq[EXP ? p : 0] = rown[(size_t)il * P + p];
+            }
+        }
+        const bool valid = i < rw && j < cw;
+        T v = 0, u = 0;
+        if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1))) {
+            const T g = block_entry<T, P, EXP>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
+            v = g * xc[j];
+            u = g * xr[i];
+        }
+        for (int o = 1; o < C; o <<= 1) v += __shfl_xor(v, o, 64);
+        for (int o = C; o < 64; o <<= 1) u += __shfl_xor(u, o, 64);
+        if (jj == 0 && i < rw) racc[i] += v;
+        if (ii == 0 && j < cw) cacc[j] += u;
+    }
+}
+
 #ifdef GCA_BLK_WAVES_PER_EU
 #define GCA_BLK_ATTR __attribute__((amdgpu_waves_per_eu(GCA_BLK_WAVES_PER_EU)))
 #else
@@ -254,53 +313,8 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAV
             }
             for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = NEAR ? a.xv[cb + c0 + j] : a.xv[xco + c0 + j];
             __syncthreads();
-            // tile shape: fewest tile rounds over the 4 wavefronts, then fewest tiles
-            int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
-            for (int l = 2; l <= 6; ++l) {
-                const int R = 64 >> l;
-                const int n = ((rw + R - 1) / R) * ((cw + (1 << l) - 1) >> l);
-                const int rounds = (n + BLK_WAVES - 1) / BLK_WAVES;
-                if (rounds < best_r || (rounds == best_r && n < best_n)) {
-                    best_r = rounds;
-                    best_n = n;
-                    lc = l;
-                }
-            }
-            const int C = 1 << lc, R = 64 >> lc;
-            const int ii = lane >> lc, jj = lane & (C - 1);
-            const int nct = (cw + C - 1) >> lc;
-            // each wavefront takes a contiguous run of the row-major tile list,
-            // so consecutive tiles mostly share their rows: the row points stay
-            // in registers until the tile row changes
-            const int k0 = (wv * best_n) / BLK_WAVES, k1 = ((wv + 1) * best_n) / BLK_WAVES;
-            Q4<T> rr[P];
-            T rq[EXP ? P : 1];
-            int cur_tr = -1;
-            for (int k = k0; k < k1; ++k) {
-                const int tr = k / nct, tc = k - tr * nct;
-                const int i = tr * R + ii, j = tc * C + jj;
-                if (tr != cur_tr) {
-                    cur_tr = tr;
-                    const int il = min(i, rw - 1);
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        rr[p] = rowp[(size_t)il * P + p];
-                        if (EXP) rq[EXP ? p : 0] = rown[(size_t)il * P + p];
-                    }
-                }
-                const bool valid = i < rw && j < cw;
-                T v = 0, u = 0;
-                if (valid && !(NEAR && ((mask[i] >> (c0 + j)) & 1))) {
-                    const T g = block_entry<T, P, EXP>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) *
-                                (T)INV4PI;
-                    v = g * xc[j];
-                    u = g * xr[i];
-                }
-                for (int o = 1; o < C; o <<= 1) v += __shfl_xor(v, o, 64);
-                for (int o = C; o < 64; o <<= 1) u += __shfl_xor(u, o, 64);
-                if (jj == 0 && i < rw) racc[wv * rmax + i] += v;
-                if (ii == 0 && j < cw) cacc[wv * CW + j] += u;
-            }
+            tile_pass<T, P, EXP, NEAR>(rw, cw, c0, rowp, rown, colp, coln, xr, xc, mask, racc + wv * rmax,
+                                       cacc + wv * CW);
             __syncthreads();
             for (int j = tid; j < cw; j += BLK_THREADS) {
                 T c = 0;
@@ -327,6 +341,167 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAV
             a.part[slot_r + r0 + i] = r;
         }
     }
+}
+
+// ------------------------------------------------ coupling block rows ------
+// One workgroup per row cluster t with coupling blocks (t, s), t < s (a block
+// row of the symmetric half).  The columns of all its blocks are concatenated
+// -- column k is pivot entry col_e[k] of cluster col_s[k] -- so the row points
+// are staged once and the tiles of the whole block row are balanced over the
+// workgroup.  Row partials  sum_k g_ik x_k  go to part[g_rslot + i], the
+// column partial of column k to part[col_out[k]] (one writer each).
+// Coordinates are taken relative to the centre c_t of t's box.  The FP32 path
+// (EXP) reads the pivots' points from pq32, stored relative to their own
+// cluster's centre, and shifts the columns by c_s - c_t (FP64 difference,
+// rounded once); admissibility keeps |x - y| >= dist(t, s) >= diam / (2 eta),
+// so the cancellation in |x|^2 + |y|^2 - 2 x.y stays within a few dozen FP32
+// ulps of |x - y|^2.
+template <typename T>
+struct FarArgs {
+    const int32_t *g_t;       // ng: row cluster of each group
+    const int64_t *g_ptr;     // ng + 1: column range of each group
+    const int64_t *g_rslot;   // ng: first row-partial slot
+    const int32_t *col_e;     // pivot entry (piv_off[s] + j) of each column
+    const int32_t *col_s;     // cluster of each column
+    const int64_t *col_out;   // column-partial slot of each column
+    const int32_t *rank;
+    const int64_t *piv_off;
+    const int32_t *piv;       // FP64 path: pivot positions
+    const double *box;        // nc x 8
+    const double *q;          // FP64 path: n x P x 4
+    const float *pq32;        // FP32 path: sum(rank) x P x 4
+    const T *xh;
+    T *part;
+    int ng;
+    int rmax;
+    int cw;
+};
+
+template <typename T, int P>
+__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAVES : 1) GCA_BLK_ATTR
+    k_far_rows(FarArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr bool EXP = sizeof(T) == 4;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const int t = a.g_t[g];
+    const int64_t kb = a.g_ptr[g];
+    const int nc = (int)(a.g_ptr[g + 1] - kb);
+    const int nr = a.rank[t];
+    const int64_t xro = a.piv_off[t];
+    const int64_t rslot = a.g_rslot[g];
+    const int rmax = a.rmax, CW = a.cw;
+    const BlkLayout<T> L(rmax, P, CW, false, EXP);
+    Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
+    T *rown = reinterpret_cast<T *>(smem + L.rown);
+    Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
+    T *coln = reinterpret_cast<T *>(smem + L.coln);
+    T *xr = reinterpret_cast<T *>(smem + L.xr);
+    T *xc = reinterpret_cast<T *>(smem + L.xc);
+    T *racc = reinterpret_cast<T *>(smem + L.racc);
+    T *cacc = reinterpret_cast<T *>(smem + L.cacc);
+    const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
+    const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
+    const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+
+    for (int e = tid; e < BLK_WAVES * rmax; e += BLK_THREADS) racc[e] = 0;
+    for (int e = tid; e < BLK_WAVES * CW; e += BLK_THREADS) cacc[e] = 0;
+    for (int r0 = 0; r0 < nr; r0 += rmax) {
+        const int rw = min(rmax, nr - r0);
+        if (r0 > 0) __syncthreads();
+        for (int e = tid; e < rw * P; e += BLK_THREADS) {
+            const int i = e / P, p = e - i * P;
+            if (EXP) {
+                const float4 v = reinterpret_cast<const float4 *>(a.pq32)[(size_t)(xro + r0 + i) * P + p];
+                rowp[e] = Q4<T>{(T)v.x, (T)v.y, (T)v.z, (T)v.w};
+                rown[e] = (T)(v.x * v.x + v.y * v.y + v.z * v.z);
+            } else {
+                const double *src = a.q + ((size_t)a.piv[xro + r0 + i] * P + p) * 4;
+                rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+            }
+        }
+        for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = a.xh[xro + r0 + i];
+        for (int c0 = 0; c0 < nc; c0 += CW) {
+            const int cw = min(CW, nc - c0);
+            __syncthreads();
+            for (int e = tid; e < cw * P; e += BLK_THREADS) {
+                const int j = e / P, p = e - j * P;
+                const int64_t k = kb + c0 + j;
+                const int ce = a.col_e[k];
+                if (EXP) {
+                    const int cs = a.col_s[k];
+                    const float ox = (float)(0.5 * (a.box[8 * cs + 0] + a.box[8 * cs + 3]) - cx);
+                    const float oy = (float)(0.5 * (a.box[8 * cs + 1] + a.box[8 * cs + 4]) - cy);
+                    const float oz = (float)(0.5 * (a.box[8 * cs + 2] + a.box[8 * cs + 5]) - cz);
+                    const float4 v = reinterpret_cast<const float4 *>(a.pq32)[(size_t)ce * P + p];
+                    const float y0 = v.x + ox, y1 = v.y + oy, y2 = v.z + oz;
+                    colp[e] = Q4<T>{(T)(-2 * y0), (T)(-2 * y1), (T)(-2 * y2), (T)v.w};
+                    coln[e] = (T)(y0 * y0 + y1 * y1 + y2 * y2);
+                } else {
+                    const double *src = a.q + ((size_t)a.piv[ce] * P + p) * 4;
+                    colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+                }
+            }
+            for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xh[a.col_e[kb + c0 + j]];
+            __syncthreads();
+            tile_pass<T, P, EXP, false>(rw, cw, 0, rowp, rown, colp, coln, xr, xc, nullptr, racc + wv * rmax,
+                                        cacc + wv * CW);
+            __syncthreads();
+            for (int j = tid; j < cw; j += BLK_THREADS) {
+                T c = 0;
+#pragma unroll
+                for (int w = 0; w < BLK_WAVES; ++w) {
+                    c += cacc[w * CW + j];
+                    cacc[w * CW + j] = 0;
+                }
+                const int64_t o = a.col_out[kb + c0 + j];
+                if (r0 == 0)
+                    a.part[o] = c;
+                else
+                    a.part[o] += c;
+            }
+        }
+        for (int i = tid; i < rw; i += BLK_THREADS) {
+            T r = 0;
+#pragma unroll
+            for (int w = 0; w < BLK_WAVES; ++w) {
+                r += racc[w * rmax + i];
+                racc[w * rmax + i] = 0;
+            }
+            a.part[rslot + r0 + i] = r;
+        }
+    }
+}
+
+// FP32 copies of the pivots' quadrature points relative to their cluster's
+// centre (FP64 subtract, one rounding): entry e = piv_off[c] + k of cluster c.
+__global__ void k_pivot_points(const int32_t *piv_cluster, const int32_t *piv, const double *box, const double *q,
+                               int P, int64_t n_entries, float *out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_entries * P) return;
+    const int64_t k = e / P;
+    const int p = (int)(e - k * P);
+    const int c = piv_cluster[k];
+    const double *src = q + ((size_t)piv[k] * P + p) * 4;
+    float4 v;
+    v.x = (float)(src[0] - 0.5 * (box[8 * c + 0] + box[8 * c + 3]));
+    v.y = (float)(src[1] - 0.5 * (box[8 * c + 1] + box[8 * c + 4]));
+    v.z = (float)(src[2] - 0.5 * (box[8 * c + 2] + box[8 * c + 5]));
+    v.w = (float)src[3];
+    reinterpret_cast<float4 *>(out)[e] = v;
+}
+
+hipError_t launch_pivot_points(gca_h2_s *h, hipStream_t s)
+{
+    const int P = h->prm.q_r * h->prm.q_r;
+    const int64_t ne = h->n_piv_total;
+    if (ne == 0) return hipSuccess;
+    const int64_t total = ne * P;
+    hipLaunchKernelGGL(k_pivot_points, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, h->d_piv_cluster,
+                       h->d_piv, h->d_box, h->d_qr, P, ne, h->d_pq32);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -396,26 +571,41 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
 template <typename T>
 hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
 {
-    const int nb = (int)h->blk.far_t.size();
-    if (nb == 0) return hipSuccess;
+    const int ng = h->n_far_groups;
+    if (ng == 0) return hipSuccess;
     const int P = h->prm.q_r * h->prm.q_r;
-    BlkArgs<T> a{};
-    a.bt = h->d_far;
-    a.bs = h->d_far + nb;
-    a.node = h->d_node;
+    constexpr bool EXP = sizeof(T) == 4;
+    FarArgs<T> a{};
+    a.g_t = h->d_fg_t;
+    a.g_ptr = h->d_fg_ptr;
+    a.g_rslot = h->d_fg_rslot;
+    a.col_e = h->d_fcol_e;
+    a.col_s = h->d_fcol_s;
+    a.col_out = h->d_fcol_out;
+    a.rank = h->d_rank;
+    a.piv_off = h->d_piv_off;
+    a.piv = h->d_piv;
     a.box = h->d_box;
     a.q = h->d_qr;
-    a.piv = h->d_piv;
-    a.piv_off = h->d_piv_off;
-    a.rank = h->d_rank;
-    a.xv = xh;
-    a.slot = h->d_far_slot;
+    a.pq32 = h->d_pq32;
+    a.xh = xh;
     a.part = cpart;
-    a.nblk = nb;
+    a.ng = ng;
     a.rmax = std::max(1, std::min(64, h->max_rank));
-    a.cw = std::min(std::max(8, h->max_rank), blk_cw<T>(a.rmax, P, false, sizeof(T) == 4));
+    a.cw = blk_cw<T>(a.rmax, P, false, EXP);
     if (a.cw == 0) return hipErrorInvalidValue;
-    return launch_blocks_P<T, false>(P, a, s);
+    const size_t sm = blk_smem<T>(a.rmax, P, a.cw, false, EXP);
+    switch (P) {
+#define CASE(PP)                                                                              \
+    case PP:                                                                                  \
+        hipLaunchKernelGGL((k_far_rows<T, PP>), dim3(ng), dim3(BLK_THREADS), sm, s, a);        \
+        break;
+        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template hipError_t launch_near<float>(gca_h2_s *, const float *, float *, hipStream_t);
