@@ -153,7 +153,7 @@ def main():
     dom = max(work, key=lambda k: mean_mixed[k])
     dur = mean_mixed[dom] * 1e-3
     achieved = work[dom] / dur / 1e12
-    kname = ("k_far_rows<float,%d>" % P) if dom == "coupling_blocks" else ("k_blocks<float,%d,true>" % P)
+    kname = ("k_far_rows<float,%d>" % P) if dom == "coupling_blocks" else ("k_near_rows<float,%d>" % P)
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": measured_traffic(kname),
                 "kernel": kname,

@@ -542,6 +542,96 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         GCA_TRY(upload_new(h, &h->d_nslot_ptr, ptr, s));
         GCA_TRY(upload_new(h, &h->d_nslot, flat, s));
     }
+    // block rows of the nearfield half for the product: the blocks (t, s),
+    // t <= s, of each leaf t with the diagonal block first; the columns of a
+    // row are the concatenated positions of its leaves s.  Pairs of the row
+    // CSR (touching, and near-regular when they have their own order) are
+    // masked per row and chunk of NEAR_CW columns.
+    {
+        const size_t nb = h->blk.near_t.size();
+        std::vector<std::vector<int32_t>> cols_of(nc);
+        for (size_t b = 0; b < nb; ++b) {
+            const int t = h->blk.near_t[b], u = h->blk.near_s[b];
+            if (t == u)
+                cols_of[t].insert(cols_of[t].begin(), u);
+            else
+                cols_of[t].push_back(u);
+        }
+        std::vector<int32_t> gt;
+        std::vector<int64_t> work;
+        for (int c = 0; c < nc; ++c)
+            if (!cols_of[c].empty()) {
+                int64_t w = 0;
+                for (int u : cols_of[c])
+                    w += (int64_t)(nodes[c].end - nodes[c].begin) * (nodes[u].end - nodes[u].begin);
+                gt.push_back(c);
+                work.push_back(w);
+            }
+        std::vector<int32_t> order(gt.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+        const size_t ng = gt.size();
+        std::vector<int32_t> g_t(ng), col_pos;
+        std::vector<int64_t> g_ptr(ng + 1, 0), g_rslot(ng), g_moff(ng + 1, 0), col_out;
+        std::vector<uint64_t> masks;
+        std::vector<std::vector<int64_t>> per(h->leaves.size());
+        int64_t off = 0;
+        for (size_t k = 0; k < ng; ++k) {
+            const int t = gt[order[k]];
+            const int rb = nodes[t].begin, nr = nodes[t].end - rb;
+            g_t[k] = t;
+            g_rslot[k] = off;
+            per[leaf_index[t]].push_back(off);
+            off += nr;
+            const int64_t k0 = (int64_t)col_pos.size();
+            std::vector<std::array<int64_t, 3>> segs;   // (first position, count, first column)
+            for (int u : cols_of[t]) {
+                const int cb = nodes[u].begin, cn = nodes[u].end - cb;
+                segs.push_back({cb, cn, (int64_t)col_pos.size() - k0});
+                if (u != t) per[leaf_index[u]].push_back(off);
+                for (int j = 0; j < cn; ++j) {
+                    col_pos.push_back(cb + j);
+                    col_out.push_back(u != t ? off + j : -1);
+                }
+                if (u != t) off += cn;
+            }
+            const int64_t ncols = (int64_t)col_pos.size() - k0;
+            const int64_t nch = (ncols + NEAR_CW - 1) / NEAR_CW;
+            const size_t m0 = masks.size();
+            masks.resize(m0 + (size_t)(nch * nr), 0);
+            for (int i = 0; i < nr; ++i) {
+                const int pos = rb + i;
+                for (int64_t q = h->pl.row_ptr[pos]; q < h->pl.row_ptr[pos + 1]; ++q) {
+                    const int o = h->pl.row_other[q];
+                    for (const auto &sg : segs)
+                        if (o >= sg[0] && o < sg[0] + sg[1]) {
+                            const int64_t col = sg[2] + (o - sg[0]);
+                            masks[m0 + (size_t)((col / NEAR_CW) * nr + i)] |= (uint64_t)1 << (col % NEAR_CW);
+                        }
+                }
+            }
+            g_ptr[k + 1] = (int64_t)col_pos.size();
+            g_moff[k + 1] = (int64_t)masks.size();
+        }
+        h->n_gnslot_total = off;
+        h->n_near_groups = (int32_t)ng;
+        std::vector<int64_t> ptr(h->leaves.size() + 1, 0), flat;
+        for (size_t c = 0; c < h->leaves.size(); ++c) {
+            ptr[c + 1] = ptr[c] + (int64_t)per[c].size();
+            flat.insert(flat.end(), per[c].begin(), per[c].end());
+        }
+        if (ng > 0) {
+            GCA_TRY(upload_new(h, &h->d_ng_t, g_t, s));
+            GCA_TRY(upload_new(h, &h->d_ng_ptr, g_ptr, s));
+            GCA_TRY(upload_new(h, &h->d_ng_rslot, g_rslot, s));
+            GCA_TRY(upload_new(h, &h->d_ng_moff, g_moff, s));
+            GCA_TRY(upload_new(h, &h->d_ncol_pos, col_pos, s));
+            GCA_TRY(upload_new(h, &h->d_ncol_out, col_out, s));
+            GCA_TRY(upload_new(h, &h->d_nmask, masks, s));
+        }
+        GCA_TRY(upload_new(h, &h->d_gnslot_ptr, ptr, s));
+        GCA_TRY(upload_new(h, &h->d_gnslot, flat, s));
+    }
     // pair lists
     GCA_TRY(upload_new(h, &h->d_pa, h->pl.a, s));
     GCA_TRY(upload_new(h, &h->d_pb, h->pl.b, s));
@@ -567,8 +657,8 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     GCA_TRY(dalloc(h, &h->d_yhf, h->n_piv));
     GCA_TRY(dalloc(h, &h->d_cpart, h->n_gslot_total));
     GCA_TRY(dalloc(h, &h->d_cpartf, h->n_gslot_total));
-    GCA_TRY(dalloc(h, &h->d_npart, h->n_nslot_total));
-    GCA_TRY(dalloc(h, &h->d_npartf, h->n_nslot_total));
+    GCA_TRY(dalloc(h, &h->d_npart, h->n_gnslot_total));
+    GCA_TRY(dalloc(h, &h->d_npartf, h->n_gnslot_total));
     for (auto &r : h->ev)
         for (auto &e : r) GCA_HIP_TRY(hipEventCreate(&e));
     h->events = true;

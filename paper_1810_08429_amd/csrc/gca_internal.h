@@ -243,6 +243,20 @@ struct gca_h2_s {
     int64_t n_nslot_total = 0;
     int32_t max_leaf = 0;
 
+    // nearfield block rows (product path): one group per leaf t with its
+    // blocks (t, s), t <= s, diagonal first; columns concatenated
+    int32_t n_near_groups = 0;
+    int32_t *d_ng_t = nullptr;       // ng: row leaf
+    int64_t *d_ng_ptr = nullptr;     // ng + 1: column ranges
+    int64_t *d_ng_rslot = nullptr;   // ng: row-partial slot
+    int64_t *d_ng_moff = nullptr;    // ng + 1: mask ranges (chunk-major, one word per row)
+    int32_t *d_ncol_pos = nullptr;   // per column: position
+    int64_t *d_ncol_out = nullptr;   // per column: column-partial slot (-1: diagonal block)
+    uint64_t *d_nmask = nullptr;     // per (group, chunk, row): pairs owned by the list kernels
+    int64_t *d_gnslot_ptr = nullptr; // n_leaves + 1 (leaf index order)
+    int64_t *d_gnslot = nullptr;
+    int64_t n_gnslot_total = 0;
+
     // pair lists
     int32_t *d_pa = nullptr, *d_pb = nullptr, *d_pcode = nullptr;
     int64_t *d_prow_ptr = nullptr;
@@ -281,6 +295,8 @@ struct gca_h2_s {
 };
 
 namespace gca {
+
+constexpr int NEAR_CW = 64;          // column chunk of the nearfield block rows (one mask word)
 
 // ---------------------------------------------------------- kernel launchers --
 // All launchers enqueue on `s` and return the launch status.

@@ -34,13 +34,35 @@ template hipError_t launch_permute_in<float>(const double *, const int32_t *, in
 template hipError_t launch_permute_in<double>(const double *, const int32_t *, int64_t, double *, double *,
                                               hipStream_t);
 
-// forward transform for the clusters of one level (workgroup per cluster,
-// thread per basis column k).  Leaf: V row-major |t^| x r.  Parent: E_son
-// row-major r_son x r.
+// sum_i M[i * ld + k] v[i] for i < m: rows are fetched sixteen at a time into
+// registers before they are used, so their loads are in flight together
+// (v is read at the same address by the whole wavefront); four partial sums
 template <typename T>
-__global__ void __launch_bounds__(128) k_forward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
-                                                 const int64_t *piv_off, const int64_t *v_off, const int64_t *e_off,
-                                                 const T *V, const T *E, const T *xp, T *xh)
+__device__ __forceinline__ T col_dot(const T *M, int64_t ld, int m, const T *v, int k)
+{
+    constexpr int U = 16;
+    T acc[4] = {0, 0, 0, 0};
+    for (int i0 = 0; i0 < m; i0 += U) {
+        T mv[U], vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            mv[u] = i < m ? M[(int64_t)i * ld + k] : (T)0;
+            vv[u] = i < m ? v[i] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u & 3] += mv[u] * vv[u];
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// forward transform for the clusters of one level (one wavefront per
+// cluster, lane per basis column k).  Leaf: V row-major |t^| x r.  Parent:
+// E_son row-major r_son x r.
+template <typename T>
+__global__ void __launch_bounds__(64) k_forward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
+                                                const int64_t *piv_off, const int64_t *v_off, const int64_t *e_off,
+                                                const T *V, const T *E, const T *xp, T *xh)
 {
     const int c = clusters[blockIdx.x];
     const int r = rank[c];
@@ -49,23 +71,12 @@ __global__ void __launch_bounds__(128) k_forward(const int32_t *clusters, const 
     if (s0 < 0) {
         const int b = node[5 * c], nr = node[5 * c + 1] - b;
         const T *Vc = V + v_off[c];
-        for (int k = threadIdx.x; k < r; k += blockDim.x) {
-            T acc = 0;
-            for (int i = 0; i < nr; ++i) acc += Vc[(int64_t)i * r + k] * xp[b + i];
-            out[k] = acc;
-        }
+        for (int k = threadIdx.x; k < r; k += 64) out[k] = col_dot(Vc, r, nr, xp + b, k);
     } else {
-        for (int k = threadIdx.x; k < r; k += blockDim.x) {
-            T acc = 0;
-            for (int sidx = 0; sidx < 2; ++sidx) {
-                const int so = sidx ? s1 : s0;
-                const int rs = rank[so];
-                const T *Es = E + e_off[so];
-                const T *xs = xh + piv_off[so];
-                for (int j = 0; j < rs; ++j) acc += Es[(int64_t)j * r + k] * xs[j];
-            }
-            out[k] = acc;
-        }
+        const int r0 = rank[s0], r1 = rank[s1];
+        const T *E0 = E + e_off[s0], *E1 = E + e_off[s1];
+        const T *x0 = xh + piv_off[s0], *x1 = xh + piv_off[s1];
+        for (int k = threadIdx.x; k < r; k += 64) out[k] = col_dot(E0, r, r0, x0, k) + col_dot(E1, r, r1, x1, k);
     }
 }
 
@@ -77,7 +88,7 @@ hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s)
     for (int l = (int)h->level_clusters.size() - 1; l >= 0; --l) {
         int nc = (int)h->level_clusters[l].size();
         if (!nc) continue;
-        hipLaunchKernelGGL(k_forward<T>, dim3(nc), dim3(128), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
+        hipLaunchKernelGGL(k_forward<T>, dim3(nc), dim3(64), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
                            h->d_piv_off, h->d_v_off, h->d_e_off, V, E, xp, xh);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -116,10 +127,11 @@ template hipError_t launch_coupling_reduce<double>(gca_h2_s *, const int64_t *, 
                                                    double *, hipStream_t);
 
 // backward transform for the clusters of one level below the root:
-// yh_c += E_c yh_parent (E_c column-major: Et[k * r_c + j])
+// yh_c += E_c yh_parent (E_c column-major: Et[k * r_c + j]); one wavefront
+// per cluster, lane per basis column j
 template <typename T>
-__global__ void __launch_bounds__(128) k_backward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
-                                                  const int64_t *piv_off, const int64_t *e_off, const T *Et, T *yh)
+__global__ void __launch_bounds__(64) k_backward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
+                                                 const int64_t *piv_off, const int64_t *e_off, const T *Et, T *yh)
 {
     const int c = clusters[blockIdx.x];
     const int par = node[5 * c + 4];
@@ -127,11 +139,7 @@ __global__ void __launch_bounds__(128) k_backward(const int32_t *clusters, const
     const T *Ec = Et + e_off[c];
     const T *yp = yh + piv_off[par];
     T *yc = yh + piv_off[c];
-    for (int j = threadIdx.x; j < rc; j += blockDim.x) {
-        T acc = yc[j];
-        for (int k = 0; k < rp; ++k) acc += Ec[(int64_t)k * rc + j] * yp[k];
-        yc[j] = acc;
-    }
+    for (int j = threadIdx.x; j < rc; j += 64) yc[j] += col_dot(Ec, rc, rp, yp, j);
 }
 
 template <typename T>
@@ -141,7 +149,7 @@ hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s)
     for (int l = 1; l < (int)h->level_clusters.size(); ++l) {
         int nc = (int)h->level_clusters[l].size();
         if (!nc) continue;
-        hipLaunchKernelGGL(k_backward<T>, dim3(nc), dim3(128), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
+        hipLaunchKernelGGL(k_backward<T>, dim3(nc), dim3(64), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
                            h->d_piv_off, h->d_e_off, Et, yh);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -171,8 +179,7 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
     const T *Vc = Vt + v_off[c];
     const T *yc = yh + piv_off[c];
     for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-        T acc = 0;
-        for (int k = 0; k < r; ++k) acc += Vc[(int64_t)k * nr + i] * yc[k];
+        T acc = col_dot(Vc, nr, r, yc, i);
         for (int64_t q = nslot_ptr[li]; q < nslot_ptr[li + 1]; ++q) acc += npart[nslot[q] + i];
         const int pos = b + i;
         for (int64_t q = nptr[pos]; q < nptr[pos + 1]; ++q) acc += nval[q] * xp[nother[q]];
@@ -188,7 +195,7 @@ hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *
 {
     const T *Vt = std::is_same<T, float>::value ? (const T *)h->d_Vtf : (const T *)h->d_Vt;
     hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)h->leaves.size()), dim3(64), 0, s, h->d_leaves, h->d_node,
-                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_nslot_ptr, h->d_nslot, npart, h->d_tptr,
+                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_gnslot_ptr, h->d_gnslot, npart, h->d_tptr,
                        h->d_tother, h->d_tval, h->d_nptr, h->d_nother, nval, xp, xp64, h->d_perm, y);
     return hipGetLastError();
 }

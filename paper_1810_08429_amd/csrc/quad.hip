@@ -2,11 +2,11 @@
 //     g_ij = int_{t_i} int_{t_j} 1 / (4 pi |x - y|) dy dx          (Eq. G_def)
 // for piecewise-constant bases, evaluated in bulk for
 //   - inadmissible leaf blocks G|t^ x s^ and coupling blocks G|t~ x s~
-//     (one LDS-tiled kernel; entries are recomputed and immediately
+//     (LDS-tiled block-row kernels; entries are recomputed and immediately
 //     multiplied, Section 8's second and third task), and
-//   - one list per Sauter case (identical, common edge, common vertex) plus
-//     a list of near-regular disjoint pairs (Section 8: one list per case so
-//     that a wavefront never diverges between rules).
+//   - one list per Sauter case (identical, common edge, common vertex) plus,
+//     when near-regular pairs get their own order, a list of those (Section
+//     8: one list per case so that a wavefront never diverges between rules).
 //
 // Reference triangle T = {0 <= s2 <= s1 <= 1}, chi(s) = P0 + s1 (P1 - P0) +
 // s2 (P2 - P1).  Regular pairs use a collapsed Gauss rule of order q on each
@@ -39,24 +39,19 @@ struct GaussQ {
     int q;
 };
 
-// ------------------------------------------------------ block kernel -------
-// One workgroup (256 threads = 4 wavefronts) per block (t, s).
-//   NEAR: rows = positions of leaf t, cols = positions of leaf s; entries of
-//         the pairs in the per-row pair CSR (touching pairs, and near-regular
-//         pairs when their order differs from the regular one) are masked to
-//         zero -- the list kernels own them.
-//   FAR : rows = pivots t~, cols = pivots s~ (coupling matrix G|t~ x s~).
-// Point sets are staged in LDS relative to a reference point (FP64 subtract,
-// then rounding to T), so FP32 keeps the relative accuracy of short distances.
-// Entries are computed in wavefront tiles of R x C = 64 lanes (C = 4 .. 64,
-// chosen per chunk to waste the fewest lanes on ragged edges) and multiplied
-// at once: g_ij x_j is summed over the C lanes of a tile row and g_ij x_i over
-// the R lanes of a tile column by cross-lane shuffles, then added to row and
-// column accumulators that each wavefront owns in LDS.  The block writes the
-// row partial  sum_j g_ij x_j  to part[slot_row + i] and, for t != s, the
-// column partial  sum_i g_ij x_i  to part[slot_col + j].  Deterministic: a
-// fixed tile order per wavefront, fixed reduction orders, no atomics, one
-// writer per partial.
+// ------------------------------------------------------ block kernels ------
+// Nearfield blocks G|t^ x s^ and coupling blocks G|t~ x s~ are recomputed in
+// every product and multiplied at once (Section 8's second and third task).
+// A workgroup (256 threads = 4 wavefronts) takes one block row: a row
+// cluster and the concatenated columns of all its blocks of the symmetric
+// half.  Point sets are staged in LDS relative to a reference point (FP64
+// subtract, then rounding to T), so FP32 keeps the relative accuracy of short
+// distances.  Entries are computed in wavefront tiles of R x C = 64 lanes and
+// multiplied at once: g_ij x_j is summed over the C lanes of a tile row and
+// g_ij x_i over the R lanes of a tile column by cross-lane shuffles, then
+// added to row and column accumulators that each wavefront owns in LDS.
+// Deterministic: a fixed tile order per wavefront, fixed reduction orders, no
+// atomics, one writer per partial.
 constexpr int BLK_THREADS = 256;
 constexpr int BLK_WAVES = BLK_THREADS / 64;
 
@@ -65,24 +60,6 @@ struct alignas(4 * sizeof(T)) Q4 {
     T x, y, z, w;
 };
 
-template <typename T>
-struct BlkArgs {
-    const int32_t *bt, *bs;
-    const int32_t *node;      // nc x 5
-    const double *box;        // nc x 8
-    const double *q;          // n x P x 4
-    const int32_t *piv;       // FAR
-    const int64_t *piv_off;   // FAR
-    const int32_t *rank;      // FAR
-    const int64_t *prow_ptr;  // NEAR
-    const int32_t *prow_other;
-    const T *xv;              // NEAR: permuted x; FAR: xhat
-    const int64_t *slot;      // 2 x nblk
-    T *part;
-    int nblk;
-    int rmax;                 // capacity of the row arrays
-    int cw;                   // column chunk width
-};
 
 __host__ __device__ constexpr size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
 
@@ -215,133 +192,9 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
 #else
 #define GCA_BLK_ATTR
 #endif
-template <typename T, int P, bool NEAR>
 #ifndef GCA_BLK_FP64_WAVES
 #define GCA_BLK_FP64_WAVES 4
 #endif
-__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAVES : 1) GCA_BLK_ATTR
-    k_blocks(BlkArgs<T> a)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    constexpr bool EXP = !NEAR && sizeof(T) == 4;
-    const int b = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int t = a.bt[b], s = a.bs[b];
-    const int rmax = a.rmax, CW = a.cw;
-    const BlkLayout<T> L(rmax, P, CW, NEAR, EXP);
-    uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
-    Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
-    T *rown = reinterpret_cast<T *>(smem + L.rown);
-    Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
-    T *coln = reinterpret_cast<T *>(smem + L.coln);
-    T *xr = reinterpret_cast<T *>(smem + L.xr);
-    T *xc = reinterpret_cast<T *>(smem + L.xc);
-    T *racc = reinterpret_cast<T *>(smem + L.racc);
-    T *cacc = reinterpret_cast<T *>(smem + L.cacc);
-
-    int nr, nc;
-    int rb = 0, cb = 0;                 // NEAR: first positions
-    const int32_t *rl = nullptr, *cl = nullptr;   // FAR: pivot lists
-    int64_t xro = 0, xco = 0;           // FAR: xhat offsets
-    if (NEAR) {
-        rb = a.node[5 * t + 0];
-        nr = a.node[5 * t + 1] - rb;
-        cb = a.node[5 * s + 0];
-        nc = a.node[5 * s + 1] - cb;
-    } else {
-        nr = a.rank[t];
-        nc = a.rank[s];
-        xro = a.piv_off[t];
-        xco = a.piv_off[s];
-        rl = a.piv + xro;
-        cl = a.piv + xco;
-    }
-    const bool emit_col = (t != s);
-    const int64_t slot_r = a.slot[2 * b], slot_c = a.slot[2 * b + 1];
-    // reference point: centre of t's box (NEAR), midpoint of both centres (FAR)
-    double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
-    double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
-    double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
-    if (!NEAR) {
-        cx = 0.5 * (cx + 0.5 * (a.box[8 * s + 0] + a.box[8 * s + 3]));
-        cy = 0.5 * (cy + 0.5 * (a.box[8 * s + 1] + a.box[8 * s + 4]));
-        cz = 0.5 * (cz + 0.5 * (a.box[8 * s + 2] + a.box[8 * s + 5]));
-    }
-
-    for (int e = tid; e < BLK_WAVES * rmax; e += BLK_THREADS) racc[e] = 0;
-    for (int e = tid; e < BLK_WAVES * CW; e += BLK_THREADS) cacc[e] = 0;
-    if (NEAR) {
-        for (int i = tid; i < nr; i += BLK_THREADS) {
-            uint64_t m = 0;
-            const int pos = rb + i;
-            for (int64_t k = a.prow_ptr[pos]; k < a.prow_ptr[pos + 1]; ++k) {
-                int o = a.prow_other[k] - cb;
-                if (o >= 0 && o < nc) m |= (uint64_t)1 << o;
-            }
-            mask[i] = m;
-        }
-    }
-    // rows in chunks of rmax, columns in chunks of CW; the column partials of
-    // later row chunks are added to what earlier chunks wrote (same thread,
-    // same address: deterministic)
-    for (int r0 = 0; r0 < nr; r0 += rmax) {
-        const int rw = min(rmax, nr - r0);
-        if (r0 > 0) __syncthreads();
-        for (int e = tid; e < rw * P; e += BLK_THREADS) {
-            const int i = e / P, p = e - i * P;
-            const int pos = NEAR ? rb + r0 + i : rl[r0 + i];
-            const double *src = a.q + ((size_t)pos * P + p) * 4;
-            const T x0 = (T)(src[0] - cx), x1 = (T)(src[1] - cy), x2 = (T)(src[2] - cz);
-            rowp[e] = Q4<T>{x0, x1, x2, (T)src[3]};
-            if (EXP) rown[e] = x0 * x0 + x1 * x1 + x2 * x2;
-        }
-        for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = NEAR ? a.xv[rb + r0 + i] : a.xv[xro + r0 + i];
-        for (int c0 = 0; c0 < nc; c0 += CW) {
-            const int cw = min(CW, nc - c0);
-            __syncthreads();
-            for (int e = tid; e < cw * P; e += BLK_THREADS) {
-                const int j = e / P, p = e - j * P;
-                const int pos = NEAR ? cb + c0 + j : cl[c0 + j];
-                const double *src = a.q + ((size_t)pos * P + p) * 4;
-                const T y0 = (T)(src[0] - cx), y1 = (T)(src[1] - cy), y2 = (T)(src[2] - cz);
-                if (EXP) {
-                    colp[e] = Q4<T>{-2 * y0, -2 * y1, -2 * y2, (T)src[3]};
-                    coln[e] = y0 * y0 + y1 * y1 + y2 * y2;
-                } else {
-                    colp[e] = Q4<T>{y0, y1, y2, (T)src[3]};
-                }
-            }
-            for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = NEAR ? a.xv[cb + c0 + j] : a.xv[xco + c0 + j];
-            __syncthreads();
-            tile_pass<T, P, EXP, NEAR>(rw, cw, c0, rowp, rown, colp, coln, xr, xc, mask, racc + wv * rmax,
-                                       cacc + wv * CW);
-            __syncthreads();
-            for (int j = tid; j < cw; j += BLK_THREADS) {
-                T c = 0;
-#pragma unroll
-                for (int w = 0; w < BLK_WAVES; ++w) {
-                    c += cacc[w * CW + j];
-                    cacc[w * CW + j] = 0;
-                }
-                if (emit_col) {
-                    if (r0 == 0)
-                        a.part[slot_c + c0 + j] = c;
-                    else
-                        a.part[slot_c + c0 + j] += c;
-                }
-            }
-        }
-        for (int i = tid; i < rw; i += BLK_THREADS) {
-            T r = 0;
-#pragma unroll
-            for (int w = 0; w < BLK_WAVES; ++w) {
-                r += racc[w * rmax + i];
-                racc[w * rmax + i] = 0;
-            }
-            a.part[slot_r + r0 + i] = r;
-        }
-    }
-}
 
 // ------------------------------------------------ coupling block rows ------
 // One workgroup per row cluster t with coupling blocks (t, s), t < s (a block
@@ -474,6 +327,104 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAV
     }
 }
 
+// ------------------------------------------------ nearfield block rows -----
+// One workgroup per leaf t with nearfield blocks (t, s), t <= s: the columns of
+// all its blocks are concatenated (diagonal block first), the row points are
+// staged once and the tiles of the whole block row are balanced over the
+// workgroup.  Pairs listed in the row CSR (touching pairs, and near-regular
+// pairs when they have their own order) are skipped by a precomputed mask,
+// one word per row and chunk of NEAR_CW columns.  Row partials go to
+// part[g_rslot + i], the column partial of column k to part[col_out[k]]
+// (none for the diagonal block).  Coordinates relative to the centre of t's
+// box (FP64 subtract, then rounding to T).
+template <typename T>
+struct NearArgs {
+    const int32_t *g_t;
+    const int64_t *g_ptr;
+    const int64_t *g_rslot;
+    const int64_t *g_moff;
+    const int32_t *col_pos;
+    const int64_t *col_out;
+    const uint64_t *mask;
+    const int32_t *node;      // nc x 5
+    const double *box;        // nc x 8
+    const double *q;          // n x P x 4
+    const T *xp;              // permuted x
+    T *part;
+    int ng;
+    int rmax;                 // >= largest leaf
+    int cw;                   // column sub-chunk (divides NEAR_CW)
+};
+
+template <typename T, int P>
+__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAVES : 1) GCA_BLK_ATTR
+    k_near_rows(NearArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int CW = a.cw;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const int t = a.g_t[g];
+    const int64_t kb = a.g_ptr[g];
+    const int nc = (int)(a.g_ptr[g + 1] - kb);
+    const int rb = a.node[5 * t + 0], nr = a.node[5 * t + 1] - rb;
+    const int64_t rslot = a.g_rslot[g];
+    const uint64_t *gm = a.mask + a.g_moff[g];
+    const int rmax = a.rmax;
+    const BlkLayout<T> L(rmax, P, CW, true, false);
+    uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
+    Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
+    Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
+    T *xr = reinterpret_cast<T *>(smem + L.xr);
+    T *xc = reinterpret_cast<T *>(smem + L.xc);
+    T *racc = reinterpret_cast<T *>(smem + L.racc);
+    T *cacc = reinterpret_cast<T *>(smem + L.cacc);
+    const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
+    const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
+    const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+
+    for (int e = tid; e < BLK_WAVES * rmax; e += BLK_THREADS) racc[e] = 0;
+    for (int e = tid; e < BLK_WAVES * CW; e += BLK_THREADS) cacc[e] = 0;
+    for (int e = tid; e < nr * P; e += BLK_THREADS) {
+        const int i = e / P, p = e - i * P;
+        const double *src = a.q + ((size_t)(rb + i) * P + p) * 4;
+        rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+    }
+    for (int i = tid; i < nr; i += BLK_THREADS) xr[i] = a.xp[rb + i];
+    for (int c0 = 0; c0 < nc; c0 += CW) {
+        const int cw = min(CW, nc - c0);
+        const int ch = c0 / NEAR_CW, cb = c0 - ch * NEAR_CW;   // mask word and bit offset
+        __syncthreads();
+        for (int e = tid; e < cw * P; e += BLK_THREADS) {
+            const int j = e / P, p = e - j * P;
+            const double *src = a.q + ((size_t)a.col_pos[kb + c0 + j] * P + p) * 4;
+            colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+        }
+        for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xp[a.col_pos[kb + c0 + j]];
+        for (int i = tid; i < nr; i += BLK_THREADS) mask[i] = gm[(size_t)ch * nr + i];
+        __syncthreads();
+        tile_pass<T, P, false, true>(nr, cw, cb, rowp, nullptr, colp, nullptr, xr, xc, mask, racc + wv * rmax,
+                                     cacc + wv * CW);
+        __syncthreads();
+        for (int j = tid; j < cw; j += BLK_THREADS) {
+            T c = 0;
+#pragma unroll
+            for (int w = 0; w < BLK_WAVES; ++w) {
+                c += cacc[w * CW + j];
+                cacc[w * CW + j] = 0;
+            }
+            const int64_t o = a.col_out[kb + c0 + j];
+            if (o >= 0) a.part[o] = c;
+        }
+    }
+    for (int i = tid; i < nr; i += BLK_THREADS) {
+        T r = 0;
+#pragma unroll
+        for (int w = 0; w < BLK_WAVES; ++w) r += racc[w * rmax + i];
+        a.part[rslot + i] = r;
+    }
+}
+
 // FP32 copies of the pivots' quadrature points relative to their cluster's
 // centre (FP64 subtract, one rounding): entry e = piv_off[c] + k of cluster c.
 __global__ void k_pivot_points(const int32_t *piv_cluster, const int32_t *piv, const double *box, const double *q,
@@ -510,24 +461,6 @@ static size_t blk_smem(int rmax, int P, int cw, bool near, bool exp)
     return BlkLayout<T>(rmax, P, cw, near, exp).total;
 }
 
-template <typename T, bool NEAR>
-static hipError_t launch_blocks_P(int P, const BlkArgs<T> &a, hipStream_t s)
-{
-    size_t sm = blk_smem<T>(a.rmax, P, a.cw, NEAR, !NEAR && sizeof(T) == 4);
-    dim3 g(a.nblk), blk(BLK_THREADS);
-    switch (P) {
-#define CASE(PP)                                                                              \
-    case PP:                                                                                  \
-        hipLaunchKernelGGL((k_blocks<T, PP, NEAR>), g, blk, sm, s, a);                          \
-        break;
-        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
-#undef CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 // LDS budget per workgroup of the block kernel: the widest column chunk
 // (multiple of 8, at most 128) whose arrays fit it.  The budget trades fewer
 // chunks against more resident workgroups per CU (160 KB of LDS each).
@@ -547,25 +480,40 @@ static int blk_cw(int rmax, int P, bool near, bool exp)
 template <typename T>
 hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
 {
-    const int nb = (int)h->blk.near_t.size();
-    if (nb == 0) return hipSuccess;
+    const int ng = h->n_near_groups;
+    if (ng == 0) return hipSuccess;
     const int P = h->prm.q_r * h->prm.q_r;
-    BlkArgs<T> a{};
-    a.bt = h->d_near;
-    a.bs = h->d_near + nb;
+    NearArgs<T> a{};
+    a.g_t = h->d_ng_t;
+    a.g_ptr = h->d_ng_ptr;
+    a.g_rslot = h->d_ng_rslot;
+    a.g_moff = h->d_ng_moff;
+    a.col_pos = h->d_ncol_pos;
+    a.col_out = h->d_ncol_out;
+    a.mask = h->d_nmask;
     a.node = h->d_node;
     a.box = h->d_box;
     a.q = h->d_qr;
-    a.prow_ptr = h->d_prow_ptr;
-    a.prow_other = h->d_prow_other;
-    a.xv = xp;
-    a.slot = h->d_near_slot;
+    a.xp = xp;
     a.part = npart;
-    a.nblk = nb;
+    a.ng = ng;
     a.rmax = h->max_leaf;
-    a.cw = std::min(a.rmax, blk_cw<T>(a.rmax, P, true, false));
-    if (a.cw == 0) return hipErrorInvalidValue;
-    return launch_blocks_P<T, true>(P, a, s);
+    if (a.rmax > 64) return hipErrorInvalidValue;
+    a.cw = NEAR_CW;
+    while (a.cw > 8 && blk_smem<T>(a.rmax, P, a.cw, true, false) > 64 * 1024) a.cw /= 2;
+    const size_t sm = blk_smem<T>(a.rmax, P, a.cw, true, false);
+    if (sm > 64 * 1024) return hipErrorInvalidValue;
+    switch (P) {
+#define CASE(PP)                                                                              \
+    case PP:                                                                                  \
+        hipLaunchKernelGGL((k_near_rows<T, PP>), dim3(ng), dim3(BLK_THREADS), sm, s, a);       \
+        break;
+        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T>
