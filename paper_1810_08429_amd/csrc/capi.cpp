@@ -545,8 +545,9 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     // block rows of the nearfield half for the product: the blocks (t, s),
     // t <= s, of each leaf t with the diagonal block first; the columns of a
     // row are the concatenated positions of its leaves s.  Pairs of the row
-    // CSR (touching, and near-regular when they have their own order) are
-    // masked per row and chunk of NEAR_CW columns.
+    // CSR (touching, and near-regular when they have their own order) and the
+    // lower triangle of the diagonal block are masked per row and chunk of
+    // NEAR_CW columns.
     {
         const size_t nb = h->blk.near_t.size();
         std::vector<std::vector<int32_t>> cols_of(nc);
@@ -588,12 +589,12 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             for (int u : cols_of[t]) {
                 const int cb = nodes[u].begin, cn = nodes[u].end - cb;
                 segs.push_back({cb, cn, (int64_t)col_pos.size() - k0});
-                if (u != t) per[leaf_index[u]].push_back(off);
+                per[leaf_index[u]].push_back(off);
                 for (int j = 0; j < cn; ++j) {
                     col_pos.push_back(cb + j);
-                    col_out.push_back(u != t ? off + j : -1);
+                    col_out.push_back(off + j);
                 }
-                if (u != t) off += cn;
+                off += cn;
             }
             const int64_t ncols = (int64_t)col_pos.size() - k0;
             const int64_t nch = (ncols + NEAR_CW - 1) / NEAR_CW;
@@ -601,6 +602,11 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             masks.resize(m0 + (size_t)(nch * nr), 0);
             for (int i = 0; i < nr; ++i) {
                 const int pos = rb + i;
+                // diagonal block (first segment): each unordered pair once, j > i;
+                // its column partial is the mirrored entry's row contribution
+                if (cols_of[t][0] == t)
+                    for (int j = 0; j <= i; ++j)
+                        masks[m0 + (size_t)((j / NEAR_CW) * nr + i)] |= (uint64_t)1 << (j % NEAR_CW);
                 for (int64_t q = h->pl.row_ptr[pos]; q < h->pl.row_ptr[pos + 1]; ++q) {
                     const int o = h->pl.row_other[q];
                     for (const auto &sg : segs)

@@ -251,7 +251,7 @@ struct gca_h2_s {
     int64_t *d_ng_rslot = nullptr;   // ng: row-partial slot
     int64_t *d_ng_moff = nullptr;    // ng + 1: mask ranges (chunk-major, one word per row)
     int32_t *d_ncol_pos = nullptr;   // per column: position
-    int64_t *d_ncol_out = nullptr;   // per column: column-partial slot (-1: diagonal block)
+    int64_t *d_ncol_out = nullptr;   // per column: column-partial slot
     uint64_t *d_nmask = nullptr;     // per (group, chunk, row): pairs owned by the list kernels
     int64_t *d_gnslot_ptr = nullptr; // n_leaves + 1 (leaf index order)
     int64_t *d_gnslot = nullptr;

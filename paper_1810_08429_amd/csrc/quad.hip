@@ -131,9 +131,9 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[EXP
 // One pass over the entries of an rw x cw chunk (rows in rowp/rown, columns
 // in colp/coln, both in LDS): tiles of R x C = 64 lanes (C = 4 .. 64 picked
 // for the fewest tile rounds over the 4 wavefronts, then the fewest tiles).
-// Each wavefront takes a contiguous run of the row-major tile list, so its
-// consecutive tiles mostly share their rows, which stay in registers until
-// the tile row changes.  Entry g_ij contributes g_ij x_j to racc[i] (summed
+// Without a mask each wavefront takes a contiguous run of the row-major tile
+// list, so its consecutive tiles mostly share their rows, which stay in
+// registers until the tile row changes.  Entry g_ij contributes g_ij x_j to racc[i] (summed
 // over the C lanes of a tile row by shuffles) and g_ij x_i to cacc[j] (over
 // the R lanes of a tile column); racc and cacc belong to the calling
 // wavefront.  MASK skips the pairs whose bit c0 + j is set in mask[i].
@@ -157,11 +157,15 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
     const int C = 1 << lc, R = 64 >> lc;
     const int ii = lane >> lc, jj = lane & (C - 1);
     const int nct = (cw + C - 1) >> lc;
-    const int k0 = (wv * best_n) / BLK_WAVES, k1 = ((wv + 1) * best_n) / BLK_WAVES;
+    // masked passes interleave the tiles over the wavefronts instead, so that
+    // fully masked tiles (skipped at no cost) are spread evenly
+    const int k0 = MASK ? wv : (wv * best_n) / BLK_WAVES;
+    const int k1 = MASK ? best_n : ((wv + 1) * best_n) / BLK_WAVES;
+    const int kstep = MASK ? BLK_WAVES : 1;
     Q4<T> rr[P];
     T rq[EXP ? P : 1];
     int cur_tr = -1;
-    for (int k = k0; k < k1; ++k) {
+    for (int k = k0; k < k1; k += kstep) {
         const int tr = k / nct, tc = k - tr * nct;
         const int i = tr * R + ii, j = tc * C + jj;
         if (tr != cur_tr) {
@@ -332,11 +336,12 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAV
 // all its blocks are concatenated (diagonal block first), the row points are
 // staged once and the tiles of the whole block row are balanced over the
 // workgroup.  Pairs listed in the row CSR (touching pairs, and near-regular
-// pairs when they have their own order) are skipped by a precomputed mask,
-// one word per row and chunk of NEAR_CW columns.  Row partials go to
-// part[g_rslot + i], the column partial of column k to part[col_out[k]]
-// (none for the diagonal block).  Coordinates relative to the centre of t's
-// box (FP64 subtract, then rounding to T).
+// pairs when they have their own order) and the lower triangle of the
+// diagonal block are skipped by a precomputed mask, one word per row and
+// chunk of NEAR_CW columns, so every unordered pair is evaluated once.  Row
+// partials go to part[g_rslot + i], the column partial of column k to
+// part[col_out[k]].  Coordinates relative to the centre of t's box (FP64
+// subtract, then rounding to T).
 template <typename T>
 struct NearArgs {
     const int32_t *g_t;
@@ -413,8 +418,7 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAV
                 c += cacc[w * CW + j];
                 cacc[w * CW + j] = 0;
             }
-            const int64_t o = a.col_out[kb + c0 + j];
-            if (o >= 0) a.part[o] = c;
+            a.part[a.col_out[kb + c0 + j]] = c;
         }
     }
     for (int i = tid; i < nr; i += BLK_THREADS) {
