@@ -284,7 +284,8 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     const double t0 = now_ms();
     GCA_TRY(check_params(p));
     h->prm = *p;
-    GCA_TRY(mesh_copy_validate(mesh, h->mesh));
+    // the topology checks ran when the tree was built from this same mesh
+    GCA_TRY(mesh_copy_validate(mesh, h->mesh, false));
     if (tree->nt != h->mesh.nt || tree->nv != h->mesh.nv || tree->mesh_xyz != h->mesh.xyz ||
         tree->mesh_tri != h->mesh.tri)
         return set_error(GCA_EINVAL, "the tree was built from a different mesh");
@@ -336,14 +337,18 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         for (size_t b = 0; b < h->blk.near_t.size(); ++b)
             partner[fill[leaf_index[h->blk.near_t[b]]]++] = h->blk.near_s[b];
         for (size_t l = 0; l < nl; ++l) std::sort(partner.begin() + ptr[l], partner.begin() + ptr[l + 1]);
-        for (size_t q = 0; q < h->pl.a.size(); ++q) {
-            int32_t la = leaf_of[h->pl.a[q]], lb = leaf_of[h->pl.b[q]];
-            int32_t t = std::min(la, lb), u = std::max(la, lb);
-            const int32_t li = leaf_index[t];
-            if (!std::binary_search(partner.begin() + ptr[li], partner.begin() + ptr[li + 1], u))
-                return set_error(GCA_EINVAL, "a touching or near-regular pair lies in an admissible block "
-                                             "(eta too large for this mesh)");
-        }
+        std::atomic<bool> bad{false};
+        parallel_for((int64_t)h->pl.a.size(), [&](int64_t q0, int64_t q1) {
+            for (int64_t q = q0; q < q1; ++q) {
+                int32_t la = leaf_of[h->pl.a[q]], lb = leaf_of[h->pl.b[q]];
+                int32_t t = std::min(la, lb), u = std::max(la, lb);
+                const int32_t li = leaf_index[t];
+                if (!std::binary_search(partner.begin() + ptr[li], partner.begin() + ptr[li + 1], u)) bad = true;
+            }
+        });
+        if (bad)
+            return set_error(GCA_EINVAL, "a touching or near-regular pair lies in an admissible block "
+                                         "(eta too large for this mesh)");
     }
     lap(2);
 
@@ -445,14 +450,20 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     // cluster, groups launched in decreasing order of work
     {
         const size_t nb = h->blk.far_t.size();
-        std::vector<std::vector<int32_t>> cols_of(nc);
-        for (size_t b = 0; b < nb; ++b) cols_of[h->blk.far_t[b]].push_back(h->blk.far_s[b]);
+        std::vector<int64_t> bptr(nc + 1, 0);
+        for (size_t b = 0; b < nb; ++b) bptr[h->blk.far_t[b] + 1]++;
+        for (int c = 0; c < nc; ++c) bptr[c + 1] += bptr[c];
+        std::vector<int32_t> bcol(nb);
+        {
+            std::vector<int64_t> fill(bptr.begin(), bptr.end() - 1);
+            for (size_t b = 0; b < nb; ++b) bcol[fill[h->blk.far_t[b]]++] = h->blk.far_s[b];
+        }
         std::vector<int32_t> gt;
         std::vector<int64_t> work;
         for (int c = 0; c < nc; ++c)
-            if (!cols_of[c].empty()) {
+            if (bptr[c + 1] > bptr[c]) {
                 int64_t w = 0;
-                for (int u : cols_of[c]) w += (int64_t)h->rank[c] * h->rank[u];
+                for (int64_t q = bptr[c]; q < bptr[c + 1]; ++q) w += (int64_t)h->rank[c] * h->rank[bcol[q]];
                 gt.push_back(c);
                 work.push_back(w);
             }
@@ -460,33 +471,59 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
         const size_t ng = gt.size();
-        std::vector<int32_t> fg_t(ng), col_e, col_s;
-        std::vector<int64_t> fg_ptr(ng + 1, 0), fg_rslot(ng), col_out;
-        std::vector<std::vector<int64_t>> per(nc);
+        // offsets (serial), then the column arrays (parallel over groups)
+        std::vector<int32_t> fg_t(ng);
+        std::vector<int64_t> fg_ptr(ng + 1, 0), fg_rslot(ng), fg_cslot(ng);
         int64_t off = 0;
         for (size_t k = 0; k < ng; ++k) {
             const int t = gt[order[k]];
             fg_t[k] = t;
             fg_rslot[k] = off;
-            per[t].push_back(off);
             off += h->rank[t];
-            for (int u : cols_of[t]) {
-                per[u].push_back(off);
-                for (int j = 0; j < h->rank[u]; ++j) {
-                    col_e.push_back((int32_t)(h->piv_off[u] + j));
-                    col_s.push_back(u);
-                    col_out.push_back(off + j);
-                }
-                off += h->rank[u];
-            }
-            fg_ptr[k + 1] = (int64_t)col_e.size();
+            int64_t cols = 0;
+            for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) cols += h->rank[bcol[q]];
+            fg_cslot[k] = off;
+            off += cols;
+            fg_ptr[k + 1] = fg_ptr[k] + cols;
         }
         h->n_gslot_total = off;
         h->n_far_groups = (int32_t)ng;
-        std::vector<int64_t> ptr(nc + 1, 0), flat;
-        for (int c = 0; c < nc; ++c) {
-            ptr[c + 1] = ptr[c] + (int64_t)per[c].size();
-            flat.insert(flat.end(), per[c].begin(), per[c].end());
+        std::vector<int32_t> col_e(fg_ptr[ng]), col_s(fg_ptr[ng]);
+        std::vector<int64_t> col_out(fg_ptr[ng]);
+        parallel_for((int64_t)ng, [&](int64_t k0, int64_t k1) {
+            for (int64_t k = k0; k < k1; ++k) {
+                const int t = fg_t[k];
+                int64_t kk = fg_ptr[k];
+                for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) {
+                    const int u = bcol[q];
+                    for (int j = 0; j < h->rank[u]; ++j, ++kk) {
+                        col_e[kk] = (int32_t)(h->piv_off[u] + j);
+                        col_s[kk] = u;
+                        col_out[kk] = fg_cslot[k] + (kk - fg_ptr[k]);
+                    }
+                }
+            }
+        }, 64);
+        // per cluster: its row slot (as a row cluster) and its column slots
+        std::vector<int64_t> ptr(nc + 1, 0);
+        for (size_t k = 0; k < ng; ++k) {
+            const int t = fg_t[k];
+            ptr[t + 1]++;
+            for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) ptr[bcol[q] + 1]++;
+        }
+        for (int c = 0; c < nc; ++c) ptr[c + 1] += ptr[c];
+        std::vector<int64_t> flat(ptr[nc]);
+        {
+            std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+            for (size_t k = 0; k < ng; ++k) {
+                const int t = fg_t[k];
+                flat[fill[t]++] = fg_rslot[k];
+                int64_t o = fg_cslot[k];
+                for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) {
+                    flat[fill[bcol[q]]++] = o;
+                    o += h->rank[bcol[q]];
+                }
+            }
         }
         if (ng > 0) {
             GCA_TRY(upload_new(h, &h->d_fg_t, fg_t, s));
@@ -550,21 +587,28 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     // NEAR_CW columns.
     {
         const size_t nb = h->blk.near_t.size();
-        std::vector<std::vector<int32_t>> cols_of(nc);
-        for (size_t b = 0; b < nb; ++b) {
-            const int t = h->blk.near_t[b], u = h->blk.near_s[b];
-            if (t == u)
-                cols_of[t].insert(cols_of[t].begin(), u);
-            else
-                cols_of[t].push_back(u);
+        std::vector<int64_t> bptr(nc + 1, 0);
+        for (size_t b = 0; b < nb; ++b) bptr[h->blk.near_t[b] + 1]++;
+        for (int c = 0; c < nc; ++c) bptr[c + 1] += bptr[c];
+        std::vector<int32_t> bcol(nb);
+        {
+            std::vector<int64_t> fill(bptr.begin(), bptr.end() - 1);
+            for (size_t b = 0; b < nb; ++b) bcol[fill[h->blk.near_t[b]]++] = h->blk.near_s[b];
+            // diagonal block first, the others in ascending order
+            for (int c = 0; c < nc; ++c)
+                std::sort(bcol.begin() + bptr[c], bcol.begin() + bptr[c + 1], [c](int32_t x, int32_t y) {
+                    if ((x == c) != (y == c)) return x == c;
+                    return x < y;
+                });
         }
+        auto rows_of = [&](int c) { return nodes[c].end - nodes[c].begin; };
         std::vector<int32_t> gt;
         std::vector<int64_t> work;
         for (int c = 0; c < nc; ++c)
-            if (!cols_of[c].empty()) {
+            if (bptr[c + 1] > bptr[c]) {
+                if (bcol[bptr[c]] != c) return set_error(GCA_EINTERNAL, "leaf without its diagonal nearfield block");
                 int64_t w = 0;
-                for (int u : cols_of[c])
-                    w += (int64_t)(nodes[c].end - nodes[c].begin) * (nodes[u].end - nodes[u].begin);
+                for (int64_t q = bptr[c]; q < bptr[c + 1]; ++q) w += (int64_t)rows_of(c) * rows_of(bcol[q]);
                 gt.push_back(c);
                 work.push_back(w);
             }
@@ -572,59 +616,81 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
         const size_t ng = gt.size();
-        std::vector<int32_t> g_t(ng), col_pos;
-        std::vector<int64_t> g_ptr(ng + 1, 0), g_rslot(ng), g_moff(ng + 1, 0), col_out;
-        std::vector<uint64_t> masks;
-        std::vector<std::vector<int64_t>> per(h->leaves.size());
+        std::vector<int32_t> g_t(ng);
+        std::vector<int64_t> g_ptr(ng + 1, 0), g_rslot(ng), g_cslot(ng), g_moff(ng + 1, 0);
         int64_t off = 0;
         for (size_t k = 0; k < ng; ++k) {
             const int t = gt[order[k]];
-            const int rb = nodes[t].begin, nr = nodes[t].end - rb;
             g_t[k] = t;
             g_rslot[k] = off;
-            per[leaf_index[t]].push_back(off);
-            off += nr;
-            const int64_t k0 = (int64_t)col_pos.size();
-            std::vector<std::array<int64_t, 3>> segs;   // (first position, count, first column)
-            for (int u : cols_of[t]) {
-                const int cb = nodes[u].begin, cn = nodes[u].end - cb;
-                segs.push_back({cb, cn, (int64_t)col_pos.size() - k0});
-                per[leaf_index[u]].push_back(off);
-                for (int j = 0; j < cn; ++j) {
-                    col_pos.push_back(cb + j);
-                    col_out.push_back(off + j);
-                }
-                off += cn;
-            }
-            const int64_t ncols = (int64_t)col_pos.size() - k0;
-            const int64_t nch = (ncols + NEAR_CW - 1) / NEAR_CW;
-            const size_t m0 = masks.size();
-            masks.resize(m0 + (size_t)(nch * nr), 0);
-            for (int i = 0; i < nr; ++i) {
-                const int pos = rb + i;
-                // diagonal block (first segment): each unordered pair once, j > i;
-                // its column partial is the mirrored entry's row contribution
-                if (cols_of[t][0] == t)
-                    for (int j = 0; j <= i; ++j)
-                        masks[m0 + (size_t)((j / NEAR_CW) * nr + i)] |= (uint64_t)1 << (j % NEAR_CW);
-                for (int64_t q = h->pl.row_ptr[pos]; q < h->pl.row_ptr[pos + 1]; ++q) {
-                    const int o = h->pl.row_other[q];
-                    for (const auto &sg : segs)
-                        if (o >= sg[0] && o < sg[0] + sg[1]) {
-                            const int64_t col = sg[2] + (o - sg[0]);
-                            masks[m0 + (size_t)((col / NEAR_CW) * nr + i)] |= (uint64_t)1 << (col % NEAR_CW);
-                        }
-                }
-            }
-            g_ptr[k + 1] = (int64_t)col_pos.size();
-            g_moff[k + 1] = (int64_t)masks.size();
+            off += rows_of(t);
+            int64_t cols = 0;
+            for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) cols += rows_of(bcol[q]);
+            g_cslot[k] = off;
+            off += cols;
+            g_ptr[k + 1] = g_ptr[k] + cols;
+            g_moff[k + 1] = g_moff[k] + ((cols + NEAR_CW - 1) / NEAR_CW) * rows_of(t);
         }
         h->n_gnslot_total = off;
         h->n_near_groups = (int32_t)ng;
-        std::vector<int64_t> ptr(h->leaves.size() + 1, 0), flat;
-        for (size_t c = 0; c < h->leaves.size(); ++c) {
-            ptr[c + 1] = ptr[c] + (int64_t)per[c].size();
-            flat.insert(flat.end(), per[c].begin(), per[c].end());
+        std::vector<int32_t> col_pos(g_ptr[ng]);
+        std::vector<int64_t> col_out(g_ptr[ng]);
+        std::vector<uint64_t> masks(g_moff[ng], 0);
+        parallel_for((int64_t)ng, [&](int64_t k0, int64_t k1) {
+            for (int64_t k = k0; k < k1; ++k) {
+                const int t = g_t[k];
+                const int rb = nodes[t].begin, nr = rows_of(t);
+                int64_t kk = g_ptr[k];
+                for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) {
+                    const int u = bcol[q];
+                    for (int32_t pos = nodes[u].begin; pos < nodes[u].end; ++pos, ++kk) {
+                        col_pos[kk] = pos;
+                        col_out[kk] = g_cslot[k] + (kk - g_ptr[k]);
+                    }
+                }
+                uint64_t *m = masks.data() + g_moff[k];
+                for (int i = 0; i < nr; ++i) {
+                    // diagonal block (first segment): each unordered pair once, j > i;
+                    // its column partial is the mirrored entry's row contribution
+                    for (int j = 0; j <= i; ++j) m[(size_t)((j / NEAR_CW) * nr + i)] |= (uint64_t)1 << (j % NEAR_CW);
+                    const int pos = rb + i;
+                    for (int64_t e = h->pl.row_ptr[pos]; e < h->pl.row_ptr[pos + 1]; ++e) {
+                        const int o = h->pl.row_other[e];
+                        int64_t col0 = 0;
+                        for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) {
+                            const Node &nu = nodes[bcol[q]];
+                            if (o >= nu.begin && o < nu.end) {
+                                const int64_t col = col0 + (o - nu.begin);
+                                m[(size_t)((col / NEAR_CW) * nr + i)] |= (uint64_t)1 << (col % NEAR_CW);
+                                break;
+                            }
+                            col0 += nu.end - nu.begin;
+                        }
+                    }
+                }
+            }
+        }, 64);
+        // per leaf: its row slot and its column slots (leaf index order)
+        const size_t nl = h->leaves.size();
+        std::vector<int64_t> ptr(nl + 1, 0);
+        for (size_t k = 0; k < ng; ++k) {
+            const int t = g_t[k];
+            ptr[leaf_index[t] + 1]++;
+            for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) ptr[leaf_index[bcol[q]] + 1]++;
+        }
+        for (size_t l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
+        std::vector<int64_t> flat(ptr[nl]);
+        {
+            std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+            for (size_t k = 0; k < ng; ++k) {
+                const int t = g_t[k];
+                flat[fill[leaf_index[t]]++] = g_rslot[k];
+                int64_t o = g_cslot[k];
+                for (int64_t q = bptr[t]; q < bptr[t + 1]; ++q) {
+                    flat[fill[leaf_index[bcol[q]]]++] = o;
+                    o += rows_of(bcol[q]);
+                }
+            }
         }
         if (ng > 0) {
             GCA_TRY(upload_new(h, &h->d_ng_t, g_t, s));

@@ -4,14 +4,50 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/gca.h"
 
 namespace gca {
+
+// ------------------------------------------------------- host threading --
+// Host worker count: the hardware threads, at most 16.
+inline int host_threads()
+{
+    return (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+}
+
+// f(i0, i1) over [0, n) in contiguous chunks on host_threads() threads.
+// Results must not depend on which thread runs which chunk.
+template <class F>
+void parallel_for(int64_t n, F &&f, int64_t min_chunk = 1024)
+{
+    if (n <= 0) return;
+    const int nthr = host_threads();
+    const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(4 * nthr, (n + min_chunk - 1) / min_chunk));
+    if (nchunk == 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            const int64_t c = next.fetch_add(1);
+            if (c >= nchunk) break;
+            f(n * c / nchunk, n * (c + 1) / nchunk);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < std::min<int64_t>(nthr, nchunk); ++t) th.emplace_back(worker);
+    worker();
+    for (auto &x : th) x.join();
+}
 
 // ---------------------------------------------------------------- errors --
 gca_status set_error(gca_status s, const std::string &msg);
@@ -38,7 +74,9 @@ struct Mesh {
     std::vector<int32_t> tri;   // nt x 3
 };
 
-gca_status mesh_copy_validate(const gca_mesh *m, Mesh &out);
+// Copies the mesh and checks coordinates, indices and areas; with topology
+// also duplicate triangles and non-manifold edges.
+gca_status mesh_copy_validate(const gca_mesh *m, Mesh &out, bool topology = true);
 
 // Adjacency needed for the pair classes (Section 8: identical / common edge /
 // common vertex / disjoint, plus "near-regular" disjoint pairs that contain a

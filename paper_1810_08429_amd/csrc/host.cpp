@@ -28,7 +28,7 @@ const char *last_error_cstr() { return g_err.c_str(); }
 
 // ------------------------------------------------------------------- mesh --
 
-gca_status mesh_copy_validate(const gca_mesh *m, Mesh &out)
+gca_status mesh_copy_validate(const gca_mesh *m, Mesh &out, bool topology)
 {
     if (!m) return set_error(GCA_EINVAL, "mesh is NULL");
     if (m->nt < 1 || m->nv < 3) return set_error(GCA_EINVAL, "mesh needs nt >= 1 and nv >= 3");
@@ -39,52 +39,80 @@ gca_status mesh_copy_validate(const gca_mesh *m, Mesh &out)
     out.nt = m->nt;
     out.xyz.assign(m->xyz, m->xyz + 3 * m->nv);
     out.tri.assign(m->tri, m->tri + 3 * m->nt);
-    for (double v : out.xyz)
-        if (!std::isfinite(v)) return set_error(GCA_EINVAL, "non-finite vertex coordinate");
-    for (int64_t t = 0; t < m->nt; ++t) {
-        const int32_t *v = &out.tri[3 * t];
-        for (int k = 0; k < 3; ++k)
-            if (v[k] < 0 || v[k] >= m->nv)
-                return set_error(GCA_EMESH, "triangle " + std::to_string(t) + ": vertex index out of range");
-        if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2])
-            return set_error(GCA_EMESH, "triangle " + std::to_string(t) + ": repeated vertex");
-        const double *a = &out.xyz[3 * v[0]], *b = &out.xyz[3 * v[1]], *c = &out.xyz[3 * v[2]];
-        double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-        double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
-        double cx = e1[1] * e2[2] - e1[2] * e2[1];
-        double cy = e1[2] * e2[0] - e1[0] * e2[2];
-        double cz = e1[0] * e2[1] - e1[1] * e2[0];
-        if (!(cx * cx + cy * cy + cz * cz > 0.0))
-            return set_error(GCA_EMESH, "triangle " + std::to_string(t) + ": zero area");
+    std::atomic<bool> bad_xyz{false};
+    parallel_for(3 * m->nv, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            if (!std::isfinite(out.xyz[i])) bad_xyz = true;
+    });
+    if (bad_xyz) return set_error(GCA_EINVAL, "non-finite vertex coordinate");
+    // first failing triangle (lowest index) and its reason
+    std::atomic<int64_t> first_bad{INT64_MAX};
+    std::vector<int8_t> why((size_t)m->nt, 0);
+    parallel_for(m->nt, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            const int32_t *v = &out.tri[3 * t];
+            int8_t r = 0;
+            for (int k = 0; k < 3; ++k)
+                if (v[k] < 0 || v[k] >= m->nv) r = 1;
+            if (!r && (v[0] == v[1] || v[1] == v[2] || v[0] == v[2])) r = 2;
+            if (!r) {
+                const double *a = &out.xyz[3 * v[0]], *b = &out.xyz[3 * v[1]], *c = &out.xyz[3 * v[2]];
+                double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+                double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+                double cx = e1[1] * e2[2] - e1[2] * e2[1];
+                double cy = e1[2] * e2[0] - e1[0] * e2[2];
+                double cz = e1[0] * e2[1] - e1[1] * e2[0];
+                if (!(cx * cx + cy * cy + cz * cz > 0.0)) r = 3;
+            }
+            if (r) {
+                why[t] = r;
+                int64_t cur = first_bad.load();
+                while (t < cur && !first_bad.compare_exchange_weak(cur, t)) {
+                }
+            }
+        }
+    });
+    if (first_bad.load() != INT64_MAX) {
+        const int64_t t = first_bad.load();
+        const char *msg[4] = {"", ": vertex index out of range", ": repeated vertex", ": zero area"};
+        return set_error(GCA_EMESH, "triangle " + std::to_string(t) + msg[why[t]]);
     }
-    // duplicate triangles and non-manifold edges
+    if (!topology) return GCA_OK;
+    // duplicate triangles and non-manifold edges, through the triangles
+    // around each vertex
+    std::vector<int64_t> ptr(m->nv + 1, 0);
+    for (int64_t i = 0; i < 3 * m->nt; ++i) ptr[out.tri[i] + 1]++;
+    for (int64_t v = 0; v < m->nv; ++v) ptr[v + 1] += ptr[v];
+    std::vector<int32_t> vt(ptr[m->nv]);
     {
-        std::vector<std::array<int32_t, 3>> s(m->nt);
-        for (int64_t t = 0; t < m->nt; ++t) {
-            std::array<int32_t, 3> k = {out.tri[3 * t], out.tri[3 * t + 1], out.tri[3 * t + 2]};
-            std::sort(k.begin(), k.end());
-            s[t] = k;
-        }
-        std::sort(s.begin(), s.end());
-        for (size_t i = 1; i < s.size(); ++i)
-            if (s[i] == s[i - 1]) return set_error(GCA_EMESH, "duplicate triangle");
-        std::vector<std::pair<int32_t, int32_t>> e;
-        e.reserve(3 * m->nt);
+        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
         for (int64_t t = 0; t < m->nt; ++t)
+            for (int k = 0; k < 3; ++k) vt[fill[out.tri[3 * t + k]]++] = (int32_t)t;
+    }
+    std::atomic<bool> dup{false}, nonman{false};
+    parallel_for(m->nt, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            const int32_t *v = &out.tri[3 * t];
+            std::array<int32_t, 3> key = {v[0], v[1], v[2]};
+            std::sort(key.begin(), key.end());
             for (int k = 0; k < 3; ++k) {
-                int32_t a = out.tri[3 * t + k], b = out.tri[3 * t + (k + 1) % 3];
-                e.emplace_back(std::min(a, b), std::max(a, b));
-            }
-        std::sort(e.begin(), e.end());
-        size_t run = 1;
-        for (size_t i = 1; i <= e.size(); ++i) {
-            if (i < e.size() && e[i] == e[i - 1]) {
-                if (++run > 2) return set_error(GCA_EMESH, "non-manifold edge (more than two triangles)");
-            } else {
-                run = 1;
+                const int32_t a = v[k], b = v[(k + 1) % 3];
+                int cnt = 0;
+                for (int64_t q = ptr[a]; q < ptr[a + 1]; ++q) {
+                    const int32_t *w = &out.tri[3 * (int64_t)vt[q]];
+                    if (w[0] == b || w[1] == b || w[2] == b) ++cnt;
+                    if (k == 0 && vt[q] != t) {
+                        std::array<int32_t, 3> k2 = {w[0], w[1], w[2]};
+                        std::sort(k2.begin(), k2.end());
+                        if (k2 == key) dup = true;
+                    }
+                }
+                if (cnt > 2) nonman = true;
             }
         }
-    }
+    });
+    if (dup) return set_error(GCA_EMESH, "duplicate triangle");
+    if (nonman) return set_error(GCA_EMESH, "non-manifold edge (more than two triangles)");
     return GCA_OK;
 }
 
@@ -101,23 +129,31 @@ gca_status build_adjacency(const Mesh &m, Adjacency &adj)
         for (int64_t t = 0; t < nt; ++t)
             for (int k = 0; k < 3; ++k) adj.vt[fill[m.tri[3 * t + k]]++] = (int32_t)t;
     }
-    // vertex neighbours through edges
-    std::vector<std::vector<int32_t>> nb(nv);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int k = 0; k < 3; ++k) {
-            int32_t a = m.tri[3 * t + k], b = m.tri[3 * t + (k + 1) % 3];
-            nb[a].push_back(b);
-            nb[b].push_back(a);
+    // vertex neighbours through edges: the other vertices of the triangles
+    // around v, sorted and unique (parallel over vertices)
+    std::vector<int32_t> cnt(nv, 0);
+    std::vector<int32_t> tmp(2 * adj.vt_ptr[nv]);
+    parallel_for(nv, [&](int64_t v0, int64_t v1) {
+        for (int64_t v = v0; v < v1; ++v) {
+            int32_t *l = tmp.data() + 2 * adj.vt_ptr[v];
+            int n = 0;
+            for (int64_t q = adj.vt_ptr[v]; q < adj.vt_ptr[v + 1]; ++q) {
+                const int32_t *w = &m.tri[3 * (int64_t)adj.vt[q]];
+                for (int k = 0; k < 3; ++k)
+                    if (w[k] != v) l[n++] = w[k];
+            }
+            std::sort(l, l + n);
+            cnt[v] = (int32_t)(std::unique(l, l + n) - l);
         }
+    });
     adj.vv_ptr.assign(nv + 1, 0);
-    for (int64_t v = 0; v < nv; ++v) {
-        auto &l = nb[v];
-        std::sort(l.begin(), l.end());
-        l.erase(std::unique(l.begin(), l.end()), l.end());
-        adj.vv_ptr[v + 1] = adj.vv_ptr[v] + (int64_t)l.size();
-    }
+    for (int64_t v = 0; v < nv; ++v) adj.vv_ptr[v + 1] = adj.vv_ptr[v] + cnt[v];
     adj.vv.resize(adj.vv_ptr[nv]);
-    for (int64_t v = 0; v < nv; ++v) std::copy(nb[v].begin(), nb[v].end(), adj.vv.begin() + adj.vv_ptr[v]);
+    parallel_for(nv, [&](int64_t v0, int64_t v1) {
+        for (int64_t v = v0; v < v1; ++v)
+            std::copy(tmp.begin() + 2 * adj.vt_ptr[v], tmp.begin() + 2 * adj.vt_ptr[v] + cnt[v],
+                      adj.vv.begin() + adj.vv_ptr[v]);
+    });
     return GCA_OK;
 }
 
@@ -152,19 +188,21 @@ struct TreeBuilder {
         nd.diam = std::sqrt((e0 * e0 + e1 * e1) + e2 * e2);
     }
 
-    int32_t rec(int32_t b, int32_t e, int32_t level, int32_t parent)
+    // Splits [b, e) and appends the subtree in pre-order to `out` (indices
+    // local to `out`); the top `par` levels build their two sons on two
+    // threads and append them afterwards, which gives the same numbering.
+    int32_t rec(int32_t b, int32_t e, int32_t level, int32_t parent, int par, std::vector<Node> &out)
     {
-        int32_t me = (int32_t)t.nodes.size();
-        t.nodes.push_back(Node{});
+        int32_t me = (int32_t)out.size();
+        out.push_back(Node{});
         {
-            Node &nd = t.nodes[me];
+            Node &nd = out[me];
             nd.begin = b;
             nd.end = e;
             nd.son[0] = nd.son[1] = -1;
             nd.parent = parent;
             nd.level = level;
         }
-        t.depth = std::max(t.depth, level);
         if (e - b <= leaf) return me;
         double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int32_t p = b; p < e; ++p)
@@ -193,11 +231,35 @@ struct TreeBuilder {
         std::nth_element(t.perm.begin() + b, t.perm.begin() + mid, t.perm.begin() + e, less);
         if (mid - b <= leaf) std::sort(t.perm.begin() + b, t.perm.begin() + mid, less);
         if (e - mid <= leaf) std::sort(t.perm.begin() + mid, t.perm.begin() + e, less);
-        int32_t s0 = rec(b, mid, level + 1, me);
-        int32_t s1 = rec(mid, e, level + 1, me);
-        t.nodes[me].son[0] = s0;
-        t.nodes[me].son[1] = s1;
+        int32_t s0, s1;
+        if (par > 0) {
+            std::vector<Node> left, right;
+            std::thread th([&]() { rec(b, mid, level + 1, -1, par - 1, left); });
+            rec(mid, e, level + 1, -1, par - 1, right);
+            th.join();
+            s0 = append(out, left, me);
+            s1 = append(out, right, me);
+        } else {
+            s0 = rec(b, mid, level + 1, me, 0, out);
+            s1 = rec(mid, e, level + 1, me, 0, out);
+        }
+        out[me].son[0] = s0;
+        out[me].son[1] = s1;
         return me;
+    }
+
+    // appends a subtree built with local indices; returns its root's index
+    static int32_t append(std::vector<Node> &out, const std::vector<Node> &sub, int32_t parent)
+    {
+        const int32_t base = (int32_t)out.size();
+        for (const Node &n0 : sub) {
+            Node n = n0;
+            n.parent = n.parent < 0 ? parent : n.parent + base;
+            if (n.son[0] >= 0) n.son[0] += base;
+            if (n.son[1] >= 0) n.son[1] += base;
+            out.push_back(n);
+        }
+        return base;
     }
 };
 
@@ -216,20 +278,29 @@ gca_status tree_build(const Mesh &m, int32_t leaf, gca_tree_s &t)
     t.depth = 0;
     TreeBuilder tb{m, leaf, t, {}, {}};
     tb.cent.resize(3 * m.nt);
-    for (int64_t i = 0; i < m.nt; ++i)
-        for (int d = 0; d < 3; ++d) {
-            double v0 = m.xyz[3 * (int64_t)m.tri[3 * i] + d];
-            double v1 = m.xyz[3 * (int64_t)m.tri[3 * i + 1] + d];
-            double v2 = m.xyz[3 * (int64_t)m.tri[3 * i + 2] + d];
-            tb.cent[3 * i + d] = ((v0 + v1) + v2) / 3.0;
-        }
-    tb.rec(0, (int32_t)m.nt, 0, -1);
+    parallel_for(m.nt, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double v0 = m.xyz[3 * (int64_t)m.tri[3 * i] + d];
+                double v1 = m.xyz[3 * (int64_t)m.tri[3 * i + 1] + d];
+                double v2 = m.xyz[3 * (int64_t)m.tri[3 * i + 2] + d];
+                tb.cent[3 * i + d] = ((v0 + v1) + v2) / 3.0;
+            }
+    });
+    int par = 0;
+    while (par < 4 && (1 << (par + 1)) <= host_threads() && (m.nt >> par) > 8 * (int64_t)leaf) ++par;
+    tb.rec(0, (int32_t)m.nt, 0, -1, par, t.nodes);
+    for (const Node &nd : t.nodes) t.depth = std::max(t.depth, nd.level);
     // boxes of the supports: leaves from their vertices, parents as the union of
     // their sons' boxes (min / max are exact, so this equals a direct scan)
+    parallel_for((int64_t)t.nodes.size(), [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c)
+            if (t.nodes[c].son[0] < 0) tb.box_of(t.nodes[c].begin, t.nodes[c].end, t.nodes[c]);
+    });
     for (int64_t c = (int64_t)t.nodes.size() - 1; c >= 0; --c) {
         Node &nd = t.nodes[c];
         if (nd.son[0] < 0) {
-            tb.box_of(nd.begin, nd.end, nd);
+            continue;
         } else {
             const Node &a = t.nodes[nd.son[0]], &b = t.nodes[nd.son[1]];
             for (int d = 0; d < 3; ++d) {
@@ -366,33 +437,45 @@ gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_
 {
     const int64_t nt = m.nt;
     std::vector<int32_t> iperm(nt);
-    for (int64_t p = 0; p < nt; ++p) iperm[t.perm[p]] = (int32_t)p;
+    parallel_for(nt, [&](int64_t p0, int64_t p1) {
+        for (int64_t p = p0; p < p1; ++p) iperm[t.perm[p]] = (int32_t)p;
+    });
 
-    // per class: (first original id, second original id, code), first < second.
-    // Triangles are processed in contiguous chunks on several threads; the
-    // chunks are concatenated in order, so the lists do not depend on the
-    // thread count.
-    struct P { int32_t i, j, code; };
-    const int nthr = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
-    const int nchunk = (int)std::min<int64_t>(nt, 4 * nthr);
-    std::vector<std::array<std::vector<P>, 4>> part(nchunk);
-    std::atomic<int> next{0};
+    // Rows in position order, built in contiguous chunks of positions on
+    // several threads.  The row of position r (triangle i = perm[r]) lists
+    // every listed partner (touching, and near-regular if with_nearreg) by
+    // its position, ascending.  A pair belongs to the row of its smaller
+    // position; its class and order code are those of (lower original id,
+    // higher original id).  Pair ids: class by class, and within a class in
+    // the order of the owning rows, so nothing depends on the thread count.
+    struct E {
+        int32_t other;   // position of the partner
+        int32_t cc;      // owned: class << 8 | code; else -1
+    };
+    const int nthr = host_threads();
+    const int64_t nchunk = std::min<int64_t>(nt, 8 * nthr);
+    std::vector<std::vector<E>> ent(nchunk);
+    std::vector<std::array<int64_t, 4>> ccount(nchunk);
+    std::vector<int32_t> rowlen(nt);
     std::atomic<bool> dup{false};
-    auto worker = [&]() {
+    parallel_for(nchunk, [&](int64_t c0, int64_t c1) {
         std::vector<int32_t> cand;
-        for (;;) {
-            const int c = next.fetch_add(1);
-            if (c >= nchunk) break;
-            const int64_t i0 = nt * c / nchunk, i1 = nt * (c + 1) / nchunk;
-            auto &cls = part[c];
-            for (int64_t i = i0; i < i1; ++i) {
-                const int32_t *ti = &m.tri[3 * i];
-                cls[0].push_back(P{(int32_t)i, (int32_t)i, 0});
-                // candidates: triangles around the vertices of t_i and around
-                // their edge neighbours (covers touching and near-regular pairs)
+        std::vector<E> row;
+        for (int64_t c = c0; c < c1; ++c) {
+            const int64_t r0 = nt * c / nchunk, r1 = nt * (c + 1) / nchunk;
+            auto &out = ent[c];
+            auto &cnt = ccount[c];
+            cnt = {0, 0, 0, 0};
+            for (int64_t r = r0; r < r1; ++r) {
+                const int32_t i = t.perm[r];
+                const int32_t *ti = &m.tri[3 * (int64_t)i];
+                // candidates: triangles around the vertices of t_i (touching
+                // pairs) and, when near-regular pairs are listed, around their
+                // edge neighbours too
                 cand.clear();
                 for (int k = 0; k < 3; ++k) {
                     for (int64_t q = adj.vt_ptr[ti[k]]; q < adj.vt_ptr[ti[k] + 1]; ++q) cand.push_back(adj.vt[q]);
+                    if (!with_nearreg) continue;
                     for (int64_t e = adj.vv_ptr[ti[k]]; e < adj.vv_ptr[ti[k] + 1]; ++e) {
                         int32_t v = adj.vv[e];
                         for (int64_t q = adj.vt_ptr[v]; q < adj.vt_ptr[v + 1]; ++q) cand.push_back(adj.vt[q]);
@@ -400,74 +483,104 @@ gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_
                 }
                 std::sort(cand.begin(), cand.end());
                 cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+                row.clear();
                 for (int32_t j : cand) {
-                    if (j <= i) continue;
-                    int32_t code;
-                    int k = classify_pair(m, adj, (int32_t)i, j, &code);
-                    if (k == 0) dup = true;
-                    if (k >= 1 && k <= 2) cls[k].push_back(P{(int32_t)i, j, code});
-                    if (k == 3 && with_nearreg) cls[k].push_back(P{(int32_t)i, j, code});
+                    const int32_t pj = iperm[j];
+                    int kls, code = 0;
+                    if (j == i) {
+                        kls = 0;
+                    } else {
+                        kls = classify_pair(m, adj, std::min(i, j), std::max(i, j), &code);
+                        if (kls == 0) {
+                            dup = true;
+                            continue;
+                        }
+                        if (kls > 3 || (kls == 3 && !with_nearreg)) continue;
+                    }
+                    const bool own = pj >= r;
+                    row.push_back(E{pj, own ? (kls << 8 | code) : -1});
+                    if (own) cnt[kls]++;
                 }
+                std::sort(row.begin(), row.end(), [](const E &x, const E &y) { return x.other < y.other; });
+                out.insert(out.end(), row.begin(), row.end());
+                rowlen[r] = (int32_t)row.size();
             }
         }
-    };
-    {
-        std::vector<std::thread> th;
-        for (int t = 1; t < nthr; ++t) th.emplace_back(worker);
-        worker();
-        for (auto &x : th) x.join();
-    }
+    }, 1);
     if (dup) return set_error(GCA_EMESH, "duplicate triangle");
-    std::vector<P> cls[4];
-    for (int k = 0; k < 4; ++k) {
-        size_t tot = 0;
-        for (auto &pc : part) tot += pc[k].size();
-        cls[k].reserve(tot);
-        for (auto &pc : part) cls[k].insert(cls[k].end(), pc[k].begin(), pc[k].end());
-    }
-    pl.a.clear();
-    pl.b.clear();
-    pl.code.clear();
-    pl.off[0] = 0;
-    for (int c = 0; c < 4; ++c) {
-        for (const P &p : cls[c]) {
-            pl.a.push_back(iperm[p.i]);
-            pl.b.push_back(iperm[p.j]);
-            pl.code.push_back(p.code);
-        }
-        pl.off[c + 1] = (int64_t)pl.a.size();
-    }
-    // row CSR over positions (identical pairs once, others in both rows)
-    const int64_t np = (int64_t)pl.a.size();
     pl.row_ptr.assign(nt + 1, 0);
-    for (int64_t p = 0; p < np; ++p) {
-        pl.row_ptr[pl.a[p] + 1]++;
-        if (pl.a[p] != pl.b[p]) pl.row_ptr[pl.b[p] + 1]++;
+    for (int64_t r = 0; r < nt; ++r) pl.row_ptr[r + 1] = pl.row_ptr[r] + rowlen[r];
+    // pair ids: class offsets, then per chunk
+    pl.off[0] = 0;
+    for (int k = 0; k < 4; ++k) {
+        int64_t tot = 0;
+        for (int64_t c = 0; c < nchunk; ++c) tot += ccount[c][k];
+        pl.off[k + 1] = pl.off[k] + tot;
     }
-    for (int64_t i = 0; i < nt; ++i) pl.row_ptr[i + 1] += pl.row_ptr[i];
-    pl.row_other.assign(pl.row_ptr[nt], 0);
-    pl.row_pair.assign(pl.row_ptr[nt], 0);
-    std::vector<int64_t> fill(pl.row_ptr.begin(), pl.row_ptr.end() - 1);
-    for (int64_t p = 0; p < np; ++p) {
-        int32_t a = pl.a[p], b = pl.b[p];
-        pl.row_other[fill[a]] = b;
-        pl.row_pair[fill[a]++] = (int32_t)p;
-        if (a != b) {
-            pl.row_other[fill[b]] = a;
-            pl.row_pair[fill[b]++] = (int32_t)p;
-        }
-    }
-    // value CSRs (touching, near-regular): row entries in pair order
+    const int64_t np = pl.off[4];
+    if (2 * np >= INT32_MAX) return set_error(GCA_EINVAL, "too many pairs for 32-bit slots");
+    std::vector<std::array<int64_t, 4>> cbase(nchunk);
     {
-        const int64_t nts = pl.off[3];   // touching pairs are classes 0..2
-        if (2 * np >= INT32_MAX) return set_error(GCA_EINVAL, "too many pairs for 32-bit slots");
+        std::array<int64_t, 4> run = {pl.off[0], pl.off[1], pl.off[2], pl.off[3]};
+        for (int64_t c = 0; c < nchunk; ++c)
+            for (int k = 0; k < 4; ++k) {
+                cbase[c][k] = run[k];
+                run[k] += ccount[c][k];
+            }
+    }
+    pl.a.assign(np, 0);
+    pl.b.assign(np, 0);
+    pl.code.assign(np, 0);
+    pl.row_other.assign(pl.row_ptr[nt], 0);
+    pl.row_pair.assign(pl.row_ptr[nt], -1);
+    parallel_for(nchunk, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            const int64_t r0 = nt * c / nchunk, r1 = nt * (c + 1) / nchunk;
+            std::array<int64_t, 4> id = cbase[c];
+            int64_t k = pl.row_ptr[r0];
+            const E *e = ent[c].data();
+            for (int64_t r = r0; r < r1; ++r)
+                for (int64_t q = pl.row_ptr[r]; q < pl.row_ptr[r + 1]; ++q, ++k, ++e) {
+                    pl.row_other[q] = e->other;
+                    if (e->cc < 0) continue;
+                    const int kls = e->cc >> 8;
+                    const int64_t p = id[kls]++;
+                    const int32_t i = t.perm[r], j = t.perm[e->other];
+                    pl.a[p] = i < j ? (int32_t)r : e->other;
+                    pl.b[p] = i < j ? e->other : (int32_t)r;
+                    pl.code[p] = e->cc & 0xff;
+                    pl.row_pair[q] = (int32_t)p;
+                }
+            std::vector<E>().swap(ent[c]);
+        }
+    }, 1);
+    // entries owned by the other row: find this row in the partner's row
+    parallel_for(nt, [&](int64_t r0, int64_t r1) {
+        for (int64_t r = r0; r < r1; ++r)
+            for (int64_t q = pl.row_ptr[r]; q < pl.row_ptr[r + 1]; ++q) {
+                if (pl.row_pair[q] >= 0) continue;
+                const int32_t o = pl.row_other[q];
+                const int32_t *b0 = pl.row_other.data() + pl.row_ptr[o], *b1 = pl.row_other.data() + pl.row_ptr[o + 1];
+                const int32_t *f = std::lower_bound(b0, b1, (int32_t)r);
+                pl.row_pair[q] = pl.row_pair[pl.row_ptr[o] + (f - b0)];
+            }
+    });
+    // value CSRs used by the product: the row CSR split into touching pairs
+    // (classes 0-2) and near-regular pairs (class 3), same order; slot_a[p] /
+    // slot_b[p] is the entry of pair p in the row of its first / second
+    // triangle
+    {
+        const int64_t nts = pl.off[3];
         pl.t_ptr.assign(nt + 1, 0);
         pl.n_ptr.assign(nt + 1, 0);
-        for (int64_t p = 0; p < np; ++p) {
-            auto &ptr = p < nts ? pl.t_ptr : pl.n_ptr;
-            ptr[pl.a[p] + 1]++;
-            if (pl.a[p] != pl.b[p]) ptr[pl.b[p] + 1]++;
-        }
+        parallel_for(nt, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                int64_t ct = 0;
+                for (int64_t k = pl.row_ptr[i]; k < pl.row_ptr[i + 1]; ++k) ct += pl.row_pair[k] < nts;
+                pl.t_ptr[i + 1] = ct;
+                pl.n_ptr[i + 1] = (pl.row_ptr[i + 1] - pl.row_ptr[i]) - ct;
+            }
+        });
         for (int64_t i = 0; i < nt; ++i) {
             pl.t_ptr[i + 1] += pl.t_ptr[i];
             pl.n_ptr[i + 1] += pl.n_ptr[i];
@@ -476,29 +589,21 @@ gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_
         pl.n_other.assign(pl.n_ptr[nt], 0);
         pl.slot_a.assign(np, -1);
         pl.slot_b.assign(np, -1);
-        std::vector<int64_t> ft(pl.t_ptr.begin(), pl.t_ptr.end() - 1), fn(pl.n_ptr.begin(), pl.n_ptr.end() - 1);
-        for (int64_t p = 0; p < np; ++p) {
-            auto &f = p < nts ? ft : fn;
-            auto &other = p < nts ? pl.t_other : pl.n_other;
-            const int32_t a = pl.a[p], b = pl.b[p];
-            pl.slot_a[p] = (int32_t)f[a];
-            other[f[a]++] = b;
-            if (a != b) {
-                pl.slot_b[p] = (int32_t)f[b];
-                other[f[b]++] = a;
+        parallel_for(nt, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                int64_t ft = pl.t_ptr[i], fn = pl.n_ptr[i];
+                for (int64_t k = pl.row_ptr[i]; k < pl.row_ptr[i + 1]; ++k) {
+                    const int32_t p = pl.row_pair[k];
+                    const bool touch = p < nts;
+                    const int64_t q = touch ? ft++ : fn++;
+                    (touch ? pl.t_other : pl.n_other)[q] = pl.row_other[k];
+                    if (pl.a[p] == i)
+                        pl.slot_a[p] = (int32_t)q;
+                    else
+                        pl.slot_b[p] = (int32_t)q;
+                }
             }
-        }
-    }
-    // sort each row by the other position (the nearfield kernel builds masks from it)
-    for (int64_t i = 0; i < nt; ++i) {
-        int64_t b = pl.row_ptr[i], e = pl.row_ptr[i + 1];
-        std::vector<std::pair<int32_t, int32_t>> tmp(e - b);
-        for (int64_t k = b; k < e; ++k) tmp[k - b] = {pl.row_other[k], pl.row_pair[k]};
-        std::sort(tmp.begin(), tmp.end());
-        for (int64_t k = b; k < e; ++k) {
-            pl.row_other[k] = tmp[k - b].first;
-            pl.row_pair[k] = tmp[k - b].second;
-        }
+        });
     }
     return GCA_OK;
 }
