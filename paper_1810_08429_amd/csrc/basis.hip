@@ -296,12 +296,236 @@ __global__ void __launch_bounds__(ACA_THREADS) k_aca(double *Rall, double *Uall,
     }
 }
 
+// The same cross approximation with the residual held in registers: the
+// threads form TR = ACA_RT / cols row groups of cols threads; thread (g, j)
+// owns column j of rows g + k TR (k < K).  Each step writes the pivot row and
+// column to LDS, then updates the owned entries; the arithmetic (and so the
+// pivots) equals k_aca's.
+constexpr int ACA_RT = 1024;
+constexpr int ACA_RMAXROWS = 1024;   // row groups x K (rows beyond the matrix are zero)
+constexpr int ACA_BS_MAXR = 64;      // largest rank of the parallel back substitution
+
+__device__ __forceinline__ bool better32(double v, int i, double bv, int bi)
+{
+    return v > bv || (v == bv && i < bi);
+}
+
+__device__ void block_reduce_rt(double &s, double &mv, int &mi, double *sh_s, double *sh_v, int *sh_i)
+{
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) {
+        double os = __shfl_xor(s, off, 64);
+        double ov = __shfl_xor(mv, off, 64);
+        int oi = __shfl_xor(mi, off, 64);
+        s += os;
+        if (better32(ov, oi, mv, mi)) {
+            mv = ov;
+            mi = oi;
+        }
+    }
+    const int w = tid >> 6, l = tid & 63;
+    if (l == 0) {
+        sh_s[w] = s;
+        sh_v[w] = mv;
+        sh_i[w] = mi;
+    }
+    __syncthreads();
+    double ts = 0, tv = -1.0;
+    int ti = INT32_MAX;
+    for (int k = 0; k < ACA_RT / 64; ++k) {
+        ts += sh_s[k];
+        if (better32(sh_v[k], sh_i[k], tv, ti)) {
+            tv = sh_v[k];
+            ti = sh_i[k];
+        }
+    }
+    s = ts;
+    mv = tv;
+    mi = ti;
+    // no trailing barrier: the partials are rewritten only after the next
+    // barrier of the caller (the pivot row/column barrier)
+}
+
+template <int K>
+__global__ void __launch_bounds__(ACA_RT) k_aca_reg(const double *Rall, double *Uall, double *Vall,
+                                                    const int64_t *a_off, const int64_t *u_off,
+                                                    const int32_t *rows_arr, int cols, double eps, int maxr_cap,
+                                                    int32_t *rank_out, int32_t *piv_out, int32_t *pivc_out)
+{
+    __shared__ double sh_s[ACA_RT / 64], sh_v[ACA_RT / 64];
+    __shared__ int sh_i[ACA_RT / 64];
+    __shared__ double vrow[ACA_MAXCOLS], vq[ACA_MAXCOLS], ucol[ACA_RMAXROWS];
+    __shared__ int32_t pivr[ACA_MAXCOLS], pivc[ACA_MAXCOLS];
+    __shared__ double Lsh[ACA_BS_MAXR * ACA_BS_MAXR];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int rows = rows_arr[c];
+    const int rmax = min(rows, cols);
+    const double *R = Rall + a_off[c];
+    double *U = Uall + u_off[c];
+    double *V = Vall + u_off[c];
+    const int TR = ACA_RT / cols;
+    const int g = tid / cols, j = tid - g * cols;
+    const bool act = g < TR;
+
+    // rows g + k TR beyond the matrix (and inactive threads) hold zeros and
+    // never win the pivot search: their index is past every real entry
+    for (int i = tid; i < ACA_RMAXROWS; i += ACA_RT) ucol[i] = 0.0;
+    const int big = INT32_MAX / 2;
+    double x[K];
+    double s = 0, mv = -1.0;
+    int mi = INT32_MAX;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = g + k * TR;
+        const bool ok = act && i < rows;
+        x[k] = ok ? R[i * cols + j] : 0.0;
+        s += x[k] * x[k];
+        const int e = ok ? i * cols + j : big;
+        if (better32(fabs(x[k]), e, mv, mi)) {
+            mv = fabs(x[k]);
+            mi = e;
+        }
+    }
+    block_reduce_rt(s, mv, mi, sh_s, sh_v, sh_i);
+    const double tol2 = eps * eps * s;
+    double nR2 = s;
+    int r = 0;
+    // two barriers per step: after the pivot row and column reach LDS, and
+    // inside the reduction of the updated residual
+    while (r < rmax && r < maxr_cap && nR2 > tol2) {
+        const int p = mi / cols, q = mi - p * cols;
+        // the row-group index is made opaque to the compiler here so that the
+        // per-entry indices are recomputed in each step instead of being kept
+        // live across steps (they would double the registers per entry)
+        int gs = g;
+        asm volatile("" : "+v"(gs));
+        // pivot row and column to LDS
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = gs + k * TR;
+                if (i == p) vrow[j] = x[k];
+                if (j == q) ucol[i] = x[k];
+            }
+        }
+        __syncthreads();
+        const double piv = vrow[q];
+        if (piv == 0.0) break;
+        for (int i = tid; i < rows; i += ACA_RT) U[(int64_t)i * rmax + r] = ucol[i];
+        if (tid == 0) {
+            pivr[r] = p;
+            pivc[r] = q;
+        }
+        s = 0;
+        mv = -1.0;
+        mi = INT32_MAX;
+        const double vj = act ? vrow[j] / piv : 0.0;
+        const bool colq = j == q;
+        // the pivot row and column are read before the reduction's barrier,
+        // so the next step may overwrite them after it
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = gs + k * TR;
+            const double v = (i == p || colq) ? 0.0 : x[k] - ucol[i] * vj;
+            x[k] = v;
+            s += v * v;
+            const int e = (act && i < rows) ? i * cols + j : big;
+            if (better32(fabs(v), e, mv, mi)) {
+                mv = fabs(v);
+                mi = e;
+            }
+        }
+        block_reduce_rt(s, mv, mi, sh_s, sh_v, sh_i);
+        nR2 = s;
+        ++r;
+    }
+    if (tid == 0) rank_out[c] = r;
+    for (int k = tid; k < r; k += ACA_RT) {
+        piv_out[(int64_t)c * maxr_cap + k] = pivr[k];
+        pivc_out[(int64_t)c * maxr_cap + k] = pivc[k];
+    }
+    __syncthreads();
+    // V = U L^{-1}, L[j][k] = U[piv_j][k] (lower triangular): back substitution
+    // per row, k = r-1 .. 0.  Eight threads share a row: thread t holds
+    // columns t + 8 s of u_i and v_i in registers, the sum over j > k is
+    // split over the eight and combined by shuffles; L is staged in LDS.
+    if (r <= ACA_BS_MAXR) {
+        for (int e = tid; e < r * r; e += ACA_RT) {
+            const int jr = e / r, kc = e - jr * r;
+            Lsh[e] = U[(int64_t)pivr[jr] * rmax + kc];
+        }
+        __syncthreads();
+        const int t8 = tid & 7;
+        for (int i = tid >> 3; i < rows; i += ACA_RT / 8) {
+            double u[ACA_BS_MAXR / 8], v[ACA_BS_MAXR / 8];
+#pragma unroll
+            for (int sl = 0; sl < ACA_BS_MAXR / 8; ++sl) {
+                const int j = t8 + 8 * sl;
+                u[sl] = j < r ? U[(int64_t)i * rmax + j] : 0.0;
+                v[sl] = 0.0;
+            }
+            for (int k = r - 1; k >= 0; --k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int sl = 0; sl < ACA_BS_MAXR / 8; ++sl) {
+                    const int j = t8 + 8 * sl;
+                    if (j > k && j < r) acc += v[sl] * Lsh[j * r + k];
+                }
+                acc += __shfl_xor(acc, 1, 8);
+                acc += __shfl_xor(acc, 2, 8);
+                acc += __shfl_xor(acc, 4, 8);
+                const int sk = k >> 3;
+                if (t8 == (k & 7)) {
+#pragma unroll
+                    for (int sl = 0; sl < ACA_BS_MAXR / 8; ++sl)
+                        if (sl == sk) v[sl] = (u[sl] - acc) / Lsh[k * r + k];
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < ACA_BS_MAXR / 8; ++sl) {
+                const int j = t8 + 8 * sl;
+                if (j < r) V[(int64_t)i * rmax + j] = v[sl];
+            }
+        }
+    } else {
+        for (int i = tid; i < rows; i += ACA_RT) {
+            double *vi = V + (int64_t)i * rmax;
+            const double *ui = U + (int64_t)i * rmax;
+            for (int k = r - 1; k >= 0; --k) {
+                double acc = ui[k];
+                for (int jj = k + 1; jj < r; ++jj) acc -= vi[jj] * U[(int64_t)pivr[jj] * rmax + k];
+                vi[k] = acc / U[(int64_t)pivr[k] * rmax + k];
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < r; k += ACA_RT) {
+        double *vi = V + (int64_t)pivr[k] * rmax;
+        for (int jj = 0; jj < r; ++jj) vi[jj] = (jj == k) ? 1.0 : 0.0;
+    }
+}
+
 hipError_t launch_aca(double *R, double *U, double *V, const int64_t *a_off, const int64_t *u_off,
                       const int32_t *rows, int cols, int nbatch, double eps, int maxr_cap, int32_t *rank_out,
-                      int32_t *piv_out, int32_t *pivc_out, hipStream_t s)
+                      int32_t *piv_out, int32_t *pivc_out, int max_rows, hipStream_t s)
 {
     if (nbatch == 0) return hipSuccess;
     if (cols > ACA_MAXCOLS || maxr_cap > ACA_MAXCOLS) return hipErrorInvalidValue;
+    // register-resident variant when every row group fits K rows
+    const int TR = ACA_RT / cols;
+    const int need = TR > 0 ? (max_rows + TR - 1) / TR : 1 << 30;
+#define ACA_REG(KK)                                                                                   \
+    if (need <= KK && KK * TR <= ACA_RMAXROWS) {                                                     \
+        hipLaunchKernelGGL(k_aca_reg<KK>, dim3(nbatch), dim3(ACA_RT), 0, s, R, U, V, a_off, u_off, rows, \
+                           cols, eps, maxr_cap, rank_out, piv_out, pivc_out);                        \
+        return hipGetLastError();                                                                    \
+    }
+    ACA_REG(8)
+    ACA_REG(16)
+    ACA_REG(24)
+    ACA_REG(32)
+    ACA_REG(48)
+#undef ACA_REG
     hipLaunchKernelGGL(k_aca, dim3(nbatch), dim3(ACA_THREADS), 0, s, R, U, V, a_off, u_off, rows, cols, eps,
                        maxr_cap, rank_out, piv_out, pivc_out);
     return hipGetLastError();

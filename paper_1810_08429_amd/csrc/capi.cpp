@@ -106,6 +106,20 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
         for (void *q : temp) (void)hipFree(q);
         temp.clear();
     };
+    // workspaces shared by the levels (the leaf level is the largest): the
+    // Green factor A and the cross-approximation columns U
+    struct Grow {
+        void *p = nullptr;
+        size_t cap = 0;
+    } wA, wU;
+    auto grow = [&](Grow &g, size_t bytes) -> gca_status {
+        if (bytes <= g.cap) return GCA_OK;
+        void *q = nullptr;
+        GCA_TRY(tmp_alloc(&q, bytes));
+        g.p = q;
+        g.cap = bytes;
+        return GCA_OK;
+    };
     gca_status st = GCA_OK;
     for (int l = (int)h->level_clusters.size() - 1; l >= 0 && st == GCA_OK; --l) {
         const auto &cl = h->level_clusters[l];
@@ -138,8 +152,10 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
         double *dA, *dU, *dV;
         int32_t *d_rows, *d_rowtri, *d_rowcl, *d_rank, *d_pivl, *d_pivc;
         int64_t *d_rowout, *d_aoff, *d_uoff;
-        if ((st = tmp_alloc((void **)&dA, atot * sizeof(double))) != GCA_OK) break;
-        if ((st = tmp_alloc((void **)&dU, utot * sizeof(double))) != GCA_OK) break;
+        if ((st = grow(wA, atot * sizeof(double))) != GCA_OK) break;
+        if ((st = grow(wU, utot * sizeof(double))) != GCA_OK) break;
+        dA = (double *)wA.p;
+        dU = (double *)wU.p;
         if ((st = tmp_alloc((void **)&dV, utot * sizeof(double))) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&d_rows, nb * 4)) != GCA_OK) break;
         if ((st = tmp_alloc((void **)&d_rowtri, row_tri.size() * 4)) != GCA_OK) break;
@@ -159,7 +175,8 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
         hipError_t e = launch_green_A(h->d_qA, PA, h->d_box, d_rowtri, d_rowcl, d_rowout, (int64_t)row_tri.size(),
                                       p.green_m, h->gl_x, h->gl_w, p.eta, p.omega_scale, dA, s);
         if (e == hipSuccess)
-            e = launch_aca(dA, dU, dV, d_aoff, d_uoff, d_rows, cols, nb, p.eps, cols, d_rank, d_pivl, d_pivc, s);
+            e = launch_aca(dA, dU, dV, d_aoff, d_uoff, d_rows, cols, nb, p.eps, cols, d_rank, d_pivl, d_pivc,
+                           *std::max_element(rows.begin(), rows.end()), s);
         if (e != hipSuccess) {
             st = set_error(GCA_EHIP, std::string("basis kernels: ") + hipGetErrorString(e));
             break;

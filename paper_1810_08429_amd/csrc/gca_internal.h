@@ -345,7 +345,7 @@ hipError_t launch_green_A(const double *qA, int PA, const double *box, const int
                           const double *glw, double eta, double omega_scale, double *A, hipStream_t s);
 hipError_t launch_aca(double *R, double *U, double *V, const int64_t *a_off, const int64_t *u_off,
                       const int32_t *rows, int cols, int nbatch, double eps, int maxr_cap, int32_t *rank_out,
-                      int32_t *piv_out, int32_t *pivc_out, hipStream_t s);
+                      int32_t *piv_out, int32_t *pivc_out, int max_rows, hipStream_t s);
 hipError_t launch_copy_jobs(const int64_t *jobs, int njobs, const double *src, double *dr, double *dc, float *fr,
                             float *fc, hipStream_t s);
 
