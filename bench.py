@@ -5,11 +5,13 @@
 
 One step = one H^2 product y = G~ x (forward transform, coupling blocks and
 nearfield blocks recomputed by pair quadrature, backward transform, touching
-and near-regular pair lists) for one right-hand side, inputs resident in HBM.
-`value` is DoF/s = n / (seconds per product) of the mixed-precision path
-(FP32 regular-pair quadrature and transfers, FP64 touching pairs); the FP64
-path is measured on the same H^2 approximation alongside.  Setup seconds
-cover tree construction and gca_build (synchronised wall time).
+pairs) for one right-hand side, inputs resident in HBM.  `value` is
+DoF/s = n / (seconds per product) of the mixed-precision path (FP32
+regular-pair quadrature and transfers, FP64 touching pairs); the FP64 path is
+measured on the same H^2 approximation alongside.  Setup seconds cover tree
+construction and gca_build (synchronised wall time).  The adjoint of the
+energy with respect to the vertex coordinates is timed in both precisions
+after the products (`energy_gradient`).
 
 The roofline object describes the dominant kernel of the mixed product, timed
 with the library's per-product HIP events over the timed steps.  The CPU
@@ -74,6 +76,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--eps", type=float, default=None, help="override the workload's ACA tolerance")
     ap.add_argument("--q-nr", type=int, default=None, help="override the near-regular pair order")
+    ap.add_argument("--grad-steps", type=int, default=3,
+                    help="timed calls of the energy gradient per precision (0 disables it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
@@ -141,6 +145,24 @@ def main():
     fsteps = a.fp64_steps if a.fp64_steps is not None else max(3, a.steps // 2)
     dt_fp64, ph_fp64, y_fp64 = run(gca.FP64, fsteps, 1)
     print(f"[bench] fp64 : {dt_fp64 * 1e3:.3f} ms/product", file=sys.stderr, flush=True)
+
+    # adjoint of the energy E = 1/2 x^T G~ x w.r.t. the vertex coordinates
+    # (h2_bilinear_grad, frozen structure), mixed and FP64; the first call of
+    # each precision sets up the adjoint's index maps and is not timed
+    grad = {}
+    if a.grad_steps > 0:
+        dxyz = torch.zeros((mesh.nv, 3), dtype=torch.float64, device=dev)
+        for prec, name in ((gca.MIXED, "mixed"), (gca.FP64, "fp64")):
+            H.bilinear_grad(x, x, 0.5, dxyz, prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(a.grad_steps):
+                H.bilinear_grad(x, x, 0.5, dxyz, prec)
+            torch.cuda.synchronize()
+            grad[name] = {"ms_per_step": (time.perf_counter() - t) / a.grad_steps * 1e3, "steps": a.grad_steps}
+            print(f"[bench] energy gradient {name}: {grad[name]['ms_per_step']:.3f} ms", file=sys.stderr,
+                  flush=True)
+        del dxyz
 
     phases = gca.PHASES
     mean_mixed = dict(zip(phases, ph_mixed.mean(axis=0).tolist()))
@@ -212,6 +234,7 @@ def main():
         "setup_s": setup_s,
         "setup_ms": {"tree": (setup_s * 1e3 - st["build_ms"]), **st["setup_ms"]},
         "fp64": {"value": n / dt_fp64, "unit": "DoF/s", "ms_per_step": dt_fp64 * 1e3, "steps": fsteps},
+        "energy_gradient": grad,
         "mixed_over_fp64": dt_fp64 / dt_mixed,
         "rel_err_sampled_rows": rel,
         "phases_ms": {"mixed": mean_mixed, "fp64": mean_fp64},
