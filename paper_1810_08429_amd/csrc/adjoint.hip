@@ -210,6 +210,203 @@ __global__ void __launch_bounds__(256) k_row_solve(ClusterArgs ca, const double 
     }
 }
 
+// The same factorisation and solves with C staged in LDS, for ranks up to
+// FZ_MAXR: k_lu_lds factors in LDS (one workgroup per cluster); in
+// k_row_solve_lds eight threads share a row and hold its entries q = t + 8 s
+// in registers, the sums over q are split over the eight and combined by
+// shuffles.  Same operations as k_lu / k_row_solve, different summation order.
+constexpr int FZ_MAXR = 64;
+
+__global__ void __launch_bounds__(256) k_lu_lds(ClusterArgs ca, const double *AJ, double *LU, int32_t *perm,
+                                                const int64_t *perm_off)
+{
+    __shared__ double A[FZ_MAXR * FZ_MAXR];
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    __shared__ int pmv[FZ_MAXR];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int c = ca.clusters[b];
+    const int r = ca.rank[c];
+    const double *src = AJ + ca.aj_off[b];
+    const int32_t *I = ca.pivrow + ca.piv_off[c];
+    for (int e = tid; e < r * r; e += blockDim.x) {
+        const int i = e / r, j = e - i * r;
+        A[e] = src[(int64_t)I[i] * r + j];
+    }
+    for (int i = tid; i < r; i += blockDim.x) pmv[i] = i;
+    __syncthreads();
+    for (int kk = 0; kk < r; ++kk) {
+        double best = -1.0;
+        int bi = kk;
+        for (int i = kk + tid; i < r; i += blockDim.x) {
+            const double v = fabs(A[i * r + kk]);
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        // wavefront argmax (ties: smallest row), then across the 4 wavefronts
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > best || (ov == best && oi < bi)) {
+                best = ov;
+                bi = oi;
+            }
+        }
+        if ((tid & 63) == 0) {
+            sv[tid >> 6] = best;
+            si[tid >> 6] = bi;
+        }
+        __syncthreads();
+        double bv = -1.0;
+        int pr = kk;
+        for (int w = 0; w < (int)blockDim.x / 64; ++w)
+            if (sv[w] > bv || (sv[w] == bv && si[w] < pr)) {
+                bv = sv[w];
+                pr = si[w];
+            }
+        if (pr != kk) {
+            for (int j = tid; j < r; j += blockDim.x) {
+                const double t = A[kk * r + j];
+                A[kk * r + j] = A[pr * r + j];
+                A[pr * r + j] = t;
+            }
+            if (tid == 0) {
+                const int t = pmv[kk];
+                pmv[kk] = pmv[pr];
+                pmv[pr] = t;
+            }
+        }
+        __syncthreads();
+        const double piv = A[kk * r + kk];
+        for (int i = kk + 1 + tid; i < r; i += blockDim.x) A[i * r + kk] /= piv;
+        __syncthreads();
+        const int rem = r - kk - 1;
+        for (int e = tid; e < rem * rem; e += blockDim.x) {
+            const int i = kk + 1 + e / rem, j = kk + 1 + e % rem;
+            A[i * r + j] -= A[i * r + kk] * A[kk * r + j];
+        }
+        __syncthreads();
+    }
+    double *out = LU + ca.c_off[b];
+    for (int e = tid; e < r * r; e += blockDim.x) out[e] = A[e];
+    int32_t *pm = perm + perm_off[b];
+    for (int i = tid; i < r; i += blockDim.x) pm[i] = pmv[i];
+}
+
+__global__ void __launch_bounds__(256) k_row_solve_lds(ClusterArgs ca, const double *LU, const int32_t *perm,
+                                                       const int64_t *perm_off, const double *in, double *out,
+                                                       int mode)
+{
+    constexpr int NS = FZ_MAXR / 8;
+    __shared__ double A[FZ_MAXR * FZ_MAXR];
+    __shared__ int pmv[FZ_MAXR];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int c = ca.clusters[b];
+    const int r = ca.rank[c];
+    const int m = (int)(ca.arow_off[c + 1] - ca.arow_off[c]);
+    const double *LUb = LU + ca.c_off[b];
+    for (int e = tid; e < r * r; e += blockDim.x) A[e] = LUb[e];
+    for (int i = tid; i < r; i += blockDim.x) pmv[i] = perm[perm_off[b] + i];
+    __syncthreads();
+    const int t8 = tid & 7;
+    for (int i = tid >> 3; i < m; i += blockDim.x / 8) {
+        const double *a = in + ca.aj_off[b] + (int64_t)i * r;
+        double *v = out + ca.aj_off[b] + (int64_t)i * r;
+        double t[NS], av[NS];
+        // the right-hand side entries this thread consumes, fetched up front
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const int q = t8 + 8 * sl;
+            av[sl] = q < r ? a[mode == 0 ? q : pmv[q]] : 0.0;
+        }
+        if (mode == 0) {
+            // v P^T L U = a: t U = a (forward over columns), w L = t (backward), v = w P
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
+            for (int j = 0; j < r; ++j) {
+                double acc = 0.0;
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl) {
+                    const int q = t8 + 8 * sl;
+                    if (q < j) acc += t[sl] * A[q * r + j];
+                }
+                acc += __shfl_xor(acc, 1, 8);
+                acc += __shfl_xor(acc, 2, 8);
+                acc += __shfl_xor(acc, 4, 8);
+                if (t8 == (j & 7)) {
+#pragma unroll
+                    for (int sl = 0; sl < NS; ++sl)
+                        if (sl == (j >> 3)) t[sl] = (av[sl] - acc) / A[j * r + j];
+                }
+            }
+            for (int j = r - 1; j >= 0; --j) {
+                double acc = 0.0;
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl) {
+                    const int q = t8 + 8 * sl;
+                    if (q > j && q < r) acc += t[sl] * A[q * r + j];
+                }
+                acc += __shfl_xor(acc, 1, 8);
+                acc += __shfl_xor(acc, 2, 8);
+                acc += __shfl_xor(acc, 4, 8);
+                if (t8 == (j & 7)) {
+#pragma unroll
+                    for (int sl = 0; sl < NS; ++sl)
+                        if (sl == (j >> 3)) t[sl] -= acc;
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) {
+                const int q = t8 + 8 * sl;
+                if (q < r) v[pmv[q]] = t[sl];
+            }
+        } else {
+            // P^T L U z = vbar: L y = P vbar (forward), U z = y (backward)
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
+            for (int j = 0; j < r; ++j) {
+                double acc = 0.0;
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl) {
+                    const int q = t8 + 8 * sl;
+                    if (q < j) acc += A[j * r + q] * t[sl];
+                }
+                acc += __shfl_xor(acc, 1, 8);
+                acc += __shfl_xor(acc, 2, 8);
+                acc += __shfl_xor(acc, 4, 8);
+                if (t8 == (j & 7)) {
+#pragma unroll
+                    for (int sl = 0; sl < NS; ++sl)
+                        if (sl == (j >> 3)) t[sl] = av[sl] - acc;
+                }
+            }
+            for (int j = r - 1; j >= 0; --j) {
+                double acc = 0.0;
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl) {
+                    const int q = t8 + 8 * sl;
+                    if (q > j && q < r) acc += A[j * r + q] * t[sl];
+                }
+                acc += __shfl_xor(acc, 1, 8);
+                acc += __shfl_xor(acc, 2, 8);
+                acc += __shfl_xor(acc, 4, 8);
+                if (t8 == (j & 7)) {
+#pragma unroll
+                    for (int sl = 0; sl < NS; ++sl)
+                        if (sl == (j >> 3)) t[sl] = (t[sl] - acc) / A[j * r + j];
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) {
+                const int q = t8 + 8 * sl;
+                if (q < r) v[q] = t[sl];
+            }
+        }
+    }
+}
+
 // rows I of V^ are the unit vectors (interpolation property)
 __global__ void k_unit_rows(ClusterArgs ca, double *V)
 {
@@ -271,9 +468,16 @@ hipError_t launch_frozen_basis(gca_h2_s *h, hipStream_t s)
     default:
         return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_lu, dim3(nc), dim3(256), 0, s, ca, h->fz.d_AJ, h->fz.d_LU, h->fz.d_perm, h->d_piv_off);
-    hipLaunchKernelGGL(k_row_solve, dim3(nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm, h->d_piv_off,
-                       h->fz.d_AJ, h->fz.d_Vh, h->fz.d_tmp, 0);
+    if (h->max_rank <= FZ_MAXR) {
+        hipLaunchKernelGGL(k_lu_lds, dim3(nc), dim3(256), 0, s, ca, h->fz.d_AJ, h->fz.d_LU, h->fz.d_perm,
+                           h->d_piv_off);
+        hipLaunchKernelGGL(k_row_solve_lds, dim3(nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm, h->d_piv_off,
+                           h->fz.d_AJ, h->fz.d_Vh, 0);
+    } else {
+        hipLaunchKernelGGL(k_lu, dim3(nc), dim3(256), 0, s, ca, h->fz.d_AJ, h->fz.d_LU, h->fz.d_perm, h->d_piv_off);
+        hipLaunchKernelGGL(k_row_solve, dim3(nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm, h->d_piv_off,
+                           h->fz.d_AJ, h->fz.d_Vh, h->fz.d_tmp, 0);
+    }
     hipLaunchKernelGGL(k_unit_rows, dim3(nc), dim3(256), 0, s, ca, h->fz.d_Vh);
     return hipGetLastError();
 }
@@ -282,8 +486,12 @@ hipError_t launch_frozen_basis(gca_h2_s *h, hipStream_t s)
 hipError_t launch_frozen_adjoint_solve(gca_h2_s *h, hipStream_t s)
 {
     ClusterArgs ca = cluster_args(h);
-    hipLaunchKernelGGL(k_row_solve, dim3((unsigned)h->nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm,
-                       h->d_piv_off, h->fz.d_Vbar, h->fz.d_Z, h->fz.d_tmp, 1);
+    if (h->max_rank <= FZ_MAXR)
+        hipLaunchKernelGGL(k_row_solve_lds, dim3((unsigned)h->nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm,
+                           h->d_piv_off, h->fz.d_Vbar, h->fz.d_Z, 1);
+    else
+        hipLaunchKernelGGL(k_row_solve, dim3((unsigned)h->nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm,
+                           h->d_piv_off, h->fz.d_Vbar, h->fz.d_Z, h->fz.d_tmp, 1);
     return hipGetLastError();
 }
 

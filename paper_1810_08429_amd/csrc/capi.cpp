@@ -973,7 +973,12 @@ hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alp
     T *ap = f32 ? (T *)w.apf : (T *)w.ap, *bp = f32 ? (T *)w.bpf : (T *)w.bp;
     T *xa = (T *)w.xa, *xb = (T *)w.xb, *ya = (T *)w.ya, *yb = (T *)w.yb, *cp = (T *)w.cpart;
     hipError_t e;
-    if ((e = launch_frozen_basis(h, s)) != hipSuccess) return e;
+    // the factors of C = A^[I, J] and V^ depend only on the geometry: computed
+    // by the first gradient after a build, and by every geometry update
+    if (!h->fz.basis_current) {
+        if ((e = launch_frozen_basis(h, s)) != hipSuccess) return e;
+        h->fz.basis_current = true;
+    }
     if ((e = launch_permute_in<T>(a, h->d_perm, h->n, ap, f32 ? w.ap : nullptr, s)) != hipSuccess) return e;
     if ((e = launch_permute_in<T>(b, h->d_perm, h->n, bp, f32 ? w.bp : nullptr, s)) != hipSuccess) return e;
     if ((e = launch_forward<T>(h, ap, xa, s)) != hipSuccess) return e;
@@ -1324,7 +1329,9 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
     if (h->d_qnr != h->d_qr) GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
     if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, h->d_qA));
     if (h->n_piv_total > 0) GCA_HIP_TRY(launch_pivot_points(h, s));
+    h->fz.basis_current = false;
     GCA_HIP_TRY(launch_frozen_basis(h, s));
+    h->fz.basis_current = true;
     Frozen &fz = h->fz;
     GCA_HIP_TRY(launch_copy_jobs(fz.d_copy_jobs, fz.n_vjobs, fz.d_Vh, h->d_V, h->d_Vt, h->d_Vf, h->d_Vtf, s));
     GCA_HIP_TRY(launch_copy_jobs(fz.d_copy_jobs + 6 * (int64_t)fz.n_vjobs, fz.n_ejobs, fz.d_Vh, h->d_E, h->d_Et,

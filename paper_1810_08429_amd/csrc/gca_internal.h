@@ -160,6 +160,7 @@ namespace gca {
 // the per-cluster row lists and workspaces of the refresh and the adjoint.
 struct Frozen {
     bool ready = false;
+    bool basis_current = false;      // LU factors and V^ hold for the current geometry
     int32_t *d_batch = nullptr;      // cluster ids 0..nc-1
     int32_t *d_pivrow = nullptr, *d_pivcol = nullptr;
     int64_t *d_arow_off = nullptr;
