@@ -191,14 +191,10 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
     }
 }
 
-#ifdef GCA_BLK_WAVES_PER_EU
-#define GCA_BLK_ATTR __attribute__((amdgpu_waves_per_eu(GCA_BLK_WAVES_PER_EU)))
-#else
-#define GCA_BLK_ATTR
-#endif
-#ifndef GCA_BLK_FP64_WAVES
-#define GCA_BLK_FP64_WAVES 4
-#endif
+// FP64 block kernels: at least 4 wavefronts per SIMD (128 VGPRs); the FP32
+// ones keep the compiler's register choice (measured: forcing 6 wavefronts,
+// or two entries per lane, is slower)
+constexpr int BLK_FP64_WAVES = 4;
 
 // ------------------------------------------------ coupling block rows ------
 // One workgroup per row cluster t with coupling blocks (t, s), t < s (a block
@@ -235,7 +231,7 @@ struct FarArgs {
 };
 
 template <typename T, int P>
-__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAVES : 1) GCA_BLK_ATTR
+__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : 1)
     k_far_rows(FarArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -362,7 +358,7 @@ struct NearArgs {
 };
 
 template <typename T, int P>
-__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? GCA_BLK_FP64_WAVES : 1) GCA_BLK_ATTR
+__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : 1)
     k_near_rows(NearArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -468,14 +464,12 @@ static size_t blk_smem(int rmax, int P, int cw, bool near, bool exp)
 // LDS budget per workgroup of the block kernel: the widest column chunk
 // (multiple of 8, at most 128) whose arrays fit it.  The budget trades fewer
 // chunks against more resident workgroups per CU (160 KB of LDS each).
-#ifndef GCA_BLK_LDS_KB
-#define GCA_BLK_LDS_KB 40
-#endif
+constexpr int BLK_LDS_KB = 40;
 template <typename T>
 static int blk_cw(int rmax, int P, bool near, bool exp)
 {
     for (int cw = 128; cw >= 8; cw -= 8)
-        if (blk_smem<T>(rmax, P, cw, near, exp) <= GCA_BLK_LDS_KB * 1024) return cw;
+        if (blk_smem<T>(rmax, P, cw, near, exp) <= BLK_LDS_KB * 1024) return cw;
     for (int cw = 64; cw >= 8; cw -= 8)
         if (blk_smem<T>(rmax, P, cw, near, exp) <= 64 * 1024) return cw;
     return 0;
