@@ -11,7 +11,8 @@ regular-pair quadrature and transfers, FP64 touching pairs); the FP64 path is
 measured on the same H^2 approximation alongside.  Setup seconds cover tree
 construction and gca_build (synchronised wall time).  The adjoint of the
 energy with respect to the vertex coordinates is timed in both precisions
-after the products (`energy_gradient`).
+after the products (`energy_gradient`), and so is the stored-block mode
+(`stored_blocks`: block rows computed once, products read them).
 
 The roofline object describes the dominant kernel of the mixed product, timed
 with the library's per-product HIP events over the timed steps.  The CPU
@@ -76,6 +77,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--eps", type=float, default=None, help="override the workload's ACA tolerance")
     ap.add_argument("--q-nr", type=int, default=None, help="override the near-regular pair order")
+    ap.add_argument("--stored-steps", type=int, default=10,
+                    help="timed products per precision in stored-block mode (0 disables it)")
     ap.add_argument("--grad-steps", type=int, default=3,
                     help="timed calls of the energy gradient per precision (0 disables it)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -164,6 +167,32 @@ def main():
                   flush=True)
         del dxyz
 
+    # stored-block mode: the block rows computed once (gca_store_blocks), then
+    # products that read them; reported beside the recomputing product
+    stored = {}
+    if a.stored_steps > 0:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        H.store_blocks(fp64=True, mixed=True)
+        torch.cuda.synchronize()
+        t_store = time.perf_counter() - t
+        st2 = H.stats()
+        entries = st2["store_entries_far"] + st2["store_entries_near"]
+        stored = {"store_s": t_store, "entries": entries,
+                  "bytes": {"mixed": 4 * entries, "fp64": 8 * entries}}
+        for prec, name, yref in ((gca.MIXED, "mixed", y_mixed), (gca.FP64, "fp64", y_fp64)):
+            dt, ph, ys = run(prec, a.stored_steps, 2)
+            pm = dict(zip(gca.PHASES, ph.mean(axis=0).tolist()))
+            blk_ms = pm["coupling_blocks"] + pm["near_blocks"]
+            stored[name] = {"value": n / dt, "unit": "DoF/s", "ms_per_step": dt * 1e3,
+                            "block_rows_ms": blk_ms,
+                            "block_rows_GBps": stored["bytes"][name] / (blk_ms * 1e-3) / 1e9,
+                            "rel_diff_vs_recomputed": float(torch.linalg.norm(ys - yref) / torch.linalg.norm(yref)),
+                            "phases_ms": pm}
+            print(f"[bench] stored blocks {name}: {dt * 1e3:.3f} ms/product, block rows "
+                  f"{stored[name]['block_rows_GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+        H.store_blocks(False, False)
+
     phases = gca.PHASES
     mean_mixed = dict(zip(phases, ph_mixed.mean(axis=0).tolist()))
     mean_fp64 = dict(zip(phases, ph_fp64.mean(axis=0).tolist()))
@@ -235,6 +264,7 @@ def main():
         "setup_ms": {"tree": (setup_s * 1e3 - st["build_ms"]), **st["setup_ms"]},
         "fp64": {"value": n / dt_fp64, "unit": "DoF/s", "ms_per_step": dt_fp64 * 1e3, "steps": fsteps},
         "energy_gradient": grad,
+        "stored_blocks": stored,
         "mixed_over_fp64": dt_fp64 / dt_mixed,
         "rel_err_sampled_rows": rel,
         "phases_ms": {"mixed": mean_mixed, "fp64": mean_fp64},

@@ -103,6 +103,10 @@ typedef struct {
                                             4 backward transform, 5 nearfield-block quadrature,
                                             6 near-regular list, 7 touching lists (both only for
                                             the first right-hand side), 8 gather, 9 total */
+    int64_t store_entries_far;           /* entries of the stored coupling block rows */
+    int64_t store_entries_near;          /* entries of the stored nearfield block rows (masked pairs as zeros) */
+    int32_t stored_mask;                 /* precisions with stored block rows (gca_store_blocks) */
+    int32_t reserved_i;
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
@@ -164,6 +168,22 @@ gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p,
  * unknown precision), GCA_EHIP. */
 gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t ld,
                      int32_t precision, void *stream);
+
+/* Stored-block mode (the paper's GPU setup computes and keeps the coupling
+ * matrices G|t~ x s~ and the nearfield blocks G|t^ x s^, Section 8's second
+ * and third task): computes the entries of every coupling and nearfield block
+ * row of the symmetric halves once, with the same quadrature as the
+ * recomputing product, and keeps them in device memory for the precisions
+ * whose bit is set in `which` (bit GCA_FP64 = 1, bit GCA_MIXED = 2; FP32
+ * entries for the mixed product).  Products in a stored precision then read
+ * the entries (one pass over (store_entries_far + store_entries_near) x 4 or 8
+ * bytes) instead of recomputing them, and reuse the touching and
+ * near-regular list values computed here.  which = 0 releases the storage.
+ * gca_update_geometry recomputes stored entries; h2_bilinear_grad always
+ * recomputes.  Synchronises the stream.
+ * Errors: GCA_EINVAL (null handle, unknown bits), GCA_ENOMEM (nothing is
+ * stored then), GCA_EHIP. */
+gca_status gca_store_blocks(gca_h2 h, int32_t which, void *stream);
 
 /* Solves G~ u = f by conjugate gradients on the mixed-precision product
  * (inner iterations, stopped when the inner residual falls below

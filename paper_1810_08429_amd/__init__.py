@@ -34,7 +34,7 @@ EXPORTED = [
     "gca_block_tree",
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
     "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
-    "h2_bilinear_grad",
+    "h2_bilinear_grad", "gca_store_blocks",
 ]
 
 
@@ -63,7 +63,9 @@ class _Stats(ctypes.Structure):
         "rank_min",
         "rank_max")] + [("rank_mean", ctypes.c_double), ("basis_bytes_fp64", ctypes.c_int64),
                         ("build_ms", ctypes.c_double), ("setup_ms", ctypes.c_double * 8),
-                        ("phase_ms", ctypes.c_double * 10)]
+                        ("phase_ms", ctypes.c_double * 10), ("store_entries_far", ctypes.c_int64),
+                        ("store_entries_near", ctypes.c_int64), ("stored_mask", ctypes.c_int32),
+                        ("reserved_i", ctypes.c_int32)]
 
 
 _lib = None
@@ -96,6 +98,7 @@ def lib():
     L.h2_bilinear_grad.argtypes = [P, P, P, D, P, I32, P]
     L.gca_solve_refined.argtypes = [P, P, P, D, I32, D, I32, P, P, P]
     L.gca_phase_times.argtypes = [P, I64, P, P]
+    L.gca_store_blocks.argtypes = [P, I32, P]
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
     L.gca_last_error.argtypes = []
@@ -103,7 +106,7 @@ def lib():
     for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
-                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad"):
+                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -246,6 +249,13 @@ class H2:
                                        ctypes.byref(rel), _stream_ptr(stream)))
         return u, it[0], it[1], rel.value
 
+    def store_blocks(self, fp64=True, mixed=True, stream=None):
+        """Compute the coupling and nearfield block rows once and keep them
+        (gca_store_blocks); products in a stored precision read them.
+        store_blocks(False, False) releases the storage."""
+        which = (1 << FP64 if fp64 else 0) | (1 << MIXED if mixed else 0)
+        _check(lib().gca_store_blocks(self.h, which, _stream_ptr(stream)))
+
     def update_geometry(self, verts, stream=None):
         """Move the vertices keeping tree, blocks, boxes, Green points and pivots
         (frozen structure); bases are recomputed from the Green factor."""
@@ -290,7 +300,7 @@ class H2:
     def stats(self):
         s = _Stats()
         _check(lib().gca_stats(self.h, ctypes.byref(s)))
-        out = {k: getattr(s, k) for k, _ in _Stats._fields_ if k not in ("phase_ms", "setup_ms")}
+        out = {k: getattr(s, k) for k, _ in _Stats._fields_ if k not in ("phase_ms", "setup_ms", "reserved_i")}
         out["setup_ms"] = dict(zip(["mesh_adjacency", "pair_lists", "block_tree", "geometry", "basis",
                                     "slots_lists"], list(s.setup_ms)[:6]))
         out["phase_ms"] = dict(zip(PHASES, list(s.phase_ms)))

@@ -44,8 +44,18 @@ gca_status upload_new(gca_h2_s *h, T **dst, const std::vector<T> &src, hipStream
     return upload(*dst, src, s);
 }
 
+void free_stored(gca_h2_s *h)
+{
+    for (void **p : {(void **)&h->d_far_g64, (void **)&h->d_near_g64, (void **)&h->d_far_g32,
+                     (void **)&h->d_near_g32}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+}
+
 void free_all(gca_h2_s *h)
 {
+    free_stored(h);
     for (void *p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
     if (h->events)
@@ -505,6 +515,12 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         }
         h->n_gslot_total = off;
         h->n_far_groups = (int32_t)ng;
+        std::vector<int64_t> fg_soff(ng);
+        h->n_far_store = 0;
+        for (size_t k = 0; k < ng; ++k) {
+            fg_soff[k] = h->n_far_store;
+            h->n_far_store += (int64_t)h->rank[fg_t[k]] * (fg_ptr[k + 1] - fg_ptr[k]);
+        }
         std::vector<int32_t> col_e(fg_ptr[ng]), col_s(fg_ptr[ng]);
         std::vector<int64_t> col_out(fg_ptr[ng]);
         parallel_for((int64_t)ng, [&](int64_t k0, int64_t k1) {
@@ -549,6 +565,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             GCA_TRY(upload_new(h, &h->d_fcol_e, col_e, s));
             GCA_TRY(upload_new(h, &h->d_fcol_s, col_s, s));
             GCA_TRY(upload_new(h, &h->d_fcol_out, col_out, s));
+            GCA_TRY(upload_new(h, &h->d_fg_soff, fg_soff, s));
         }
         GCA_TRY(upload_new(h, &h->d_gslot_ptr, ptr, s));
         GCA_TRY(upload_new(h, &h->d_gslot, flat, s));
@@ -650,6 +667,12 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         }
         h->n_gnslot_total = off;
         h->n_near_groups = (int32_t)ng;
+        std::vector<int64_t> g_soff(ng);
+        h->n_near_store = 0;
+        for (size_t k = 0; k < ng; ++k) {
+            g_soff[k] = h->n_near_store;
+            h->n_near_store += (int64_t)rows_of(g_t[k]) * (g_ptr[k + 1] - g_ptr[k]);
+        }
         std::vector<int32_t> col_pos(g_ptr[ng]);
         std::vector<int64_t> col_out(g_ptr[ng]);
         std::vector<uint64_t> masks(g_moff[ng], 0);
@@ -717,6 +740,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             GCA_TRY(upload_new(h, &h->d_ncol_pos, col_pos, s));
             GCA_TRY(upload_new(h, &h->d_ncol_out, col_out, s));
             GCA_TRY(upload_new(h, &h->d_nmask, masks, s));
+            GCA_TRY(upload_new(h, &h->d_ng_soff, g_soff, s));
         }
         GCA_TRY(upload_new(h, &h->d_gnslot_ptr, ptr, s));
         GCA_TRY(upload_new(h, &h->d_gnslot, flat, s));
@@ -816,17 +840,29 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     mark(1);
     if ((e = launch_forward<T>(h, xp, xh, s)) != hipSuccess) return e;
     mark(2);
-    if ((e = launch_far_blocks<T>(h, xh, cpart, s)) != hipSuccess) return e;
+    const T *far_g = f32 ? (const T *)h->d_far_g32 : (const T *)h->d_far_g64;
+    const T *near_g = f32 ? (const T *)h->d_near_g32 : (const T *)h->d_near_g64;
+    const bool stored = far_g != nullptr;
+    if (stored) {
+        if ((e = launch_apply_stored<T>(h, false, xh, far_g, cpart, s)) != hipSuccess) return e;
+    } else if ((e = launch_far_blocks<T>(h, xh, cpart, s)) != hipSuccess) {
+        return e;
+    }
     mark(3);
     if ((e = launch_coupling_reduce<T>(h, h->d_gslot_ptr, h->d_gslot, cpart, yh, s)) != hipSuccess) return e;
     mark(4);
     if ((e = launch_backward<T>(h, yh, s)) != hipSuccess) return e;
     mark(5);
-    if ((e = launch_near<T>(h, xp, npart, s)) != hipSuccess) return e;
+    if (stored) {
+        if ((e = launch_apply_stored<T>(h, true, xp, near_g, npart, s)) != hipSuccess) return e;
+    } else if ((e = launch_near<T>(h, xp, npart, s)) != hipSuccess) {
+        return e;
+    }
     mark(6);
-    if (first && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
+    // stored mode: the list values were computed with the blocks
+    if (first && !stored && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
     mark(7);
-    if (first && (e = launch_touching(h, h->d_tval, s)) != hipSuccess) return e;
+    if (first && !stored && (e = launch_touching(h, h->d_tval, s)) != hipSuccess) return e;
     mark(8);
     if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, nval, y, s)) != hipSuccess) return e;
     mark(9);
@@ -993,9 +1029,61 @@ hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alp
     return launch_vertex_gather(h, w, alpha, dxyz, s);
 }
 
+// Computes and stores the coupling and nearfield block rows (and the list
+// values) for the precisions in `which` (bit GCA_FP64, bit GCA_MIXED).
+gca_status store_impl(gca_h2_s *h, int32_t which, hipStream_t s)
+{
+    free_stored(h);
+    if (which == 0) return GCA_OK;
+    auto alloc = [&](void **p, size_t bytes) -> gca_status {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
+        if (e != hipSuccess) {
+            *p = nullptr;
+            free_stored(h);
+            return set_error(GCA_ENOMEM, "hipMalloc of stored blocks (" + std::to_string(bytes) +
+                                             " bytes) failed: " + hipGetErrorString(e));
+        }
+        return GCA_OK;
+    };
+    double *f64 = nullptr, *n64 = nullptr;
+    float *f32 = nullptr, *n32 = nullptr;
+    if (which & (1 << GCA_FP64)) {
+        GCA_TRY(alloc((void **)&f64, (size_t)h->n_far_store * 8));
+        h->d_far_g64 = f64;
+        GCA_TRY(alloc((void **)&n64, (size_t)h->n_near_store * 8));
+        h->d_near_g64 = n64;
+        GCA_HIP_TRY(launch_store_blocks<double>(h, f64, n64, s));
+    }
+    if (which & (1 << GCA_MIXED)) {
+        GCA_TRY(alloc((void **)&f32, (size_t)h->n_far_store * 4));
+        h->d_far_g32 = f32;
+        GCA_TRY(alloc((void **)&n32, (size_t)h->n_near_store * 4));
+        h->d_near_g32 = n32;
+        GCA_HIP_TRY(launch_store_blocks<float>(h, f32, n32, s));
+    }
+    GCA_HIP_TRY(launch_touching(h, h->d_tval, s));
+    if (h->d_qnr != h->d_qr) {
+        GCA_HIP_TRY(launch_nearreg<double>(h, h->d_nval, s));
+        GCA_HIP_TRY(launch_nearreg<float>(h, h->d_nvalf, s));
+    }
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+    return GCA_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+gca_status gca_store_blocks(gca_h2 h, int32_t which, void *stream)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (which & ~((1 << GCA_FP64) | (1 << GCA_MIXED))) return set_error(GCA_EINVAL, "unknown precision bits");
+    gca_status st = store_impl(h, which, (hipStream_t)stream);
+    h->stored_mask = st == GCA_OK ? which : 0;
+    return st;
+}
+
 
 void gca_params_default(gca_params *p)
 {
@@ -1332,6 +1420,7 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
     h->fz.basis_current = false;
     GCA_HIP_TRY(launch_frozen_basis(h, s));
     h->fz.basis_current = true;
+    if (h->stored_mask) GCA_TRY(store_impl(h, h->stored_mask, s));
     Frozen &fz = h->fz;
     GCA_HIP_TRY(launch_copy_jobs(fz.d_copy_jobs, fz.n_vjobs, fz.d_Vh, h->d_V, h->d_Vt, h->d_Vf, h->d_Vtf, s));
     GCA_HIP_TRY(launch_copy_jobs(fz.d_copy_jobs + 6 * (int64_t)fz.n_vjobs, fz.n_ejobs, fz.d_Vh, h->d_E, h->d_Et,
@@ -1386,6 +1475,10 @@ gca_status gca_stats(gca_h2 h, gca_stats_t *out)
     clear_error();
     if (!h || !out) return set_error(GCA_EINVAL, "NULL argument");
     *out = h->st;
+    out->store_entries_far = h->n_far_store;
+    out->store_entries_near = h->n_near_store;
+    out->stored_mask = h->stored_mask;
+    out->reserved_i = 0;
     if (h->events && h->timed) {
         const int slot = (int)((h->n_products - 1) % gca_h2_s::RING);
         GCA_HIP_TRY(hipEventSynchronize(h->ev[slot][GCA_NPHASE]));

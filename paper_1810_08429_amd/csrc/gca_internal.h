@@ -267,6 +267,8 @@ struct gca_h2_s {
     int32_t *d_fcol_e = nullptr;     // per column: pivot entry piv_off[s] + j
     int32_t *d_fcol_s = nullptr;     // per column: cluster s
     int64_t *d_fcol_out = nullptr;   // per column: column-partial slot
+    int64_t *d_fg_soff = nullptr;    // ng: offset of the group's stored entries (rank_t x columns)
+    int64_t n_far_store = 0;         // stored coupling entries
     int64_t *d_gslot_ptr = nullptr;  // nc + 1: per cluster CSR of partial slots
     int64_t *d_gslot = nullptr;
     int64_t n_gslot_total = 0;
@@ -292,6 +294,8 @@ struct gca_h2_s {
     int32_t *d_ncol_pos = nullptr;   // per column: position
     int64_t *d_ncol_out = nullptr;   // per column: column-partial slot
     uint64_t *d_nmask = nullptr;     // per (group, chunk, row): pairs owned by the list kernels
+    int64_t *d_ng_soff = nullptr;    // ng: offset of the group's stored entries (rows x columns)
+    int64_t n_near_store = 0;        // stored nearfield entries (masked pairs as zeros)
     int64_t *d_gnslot_ptr = nullptr; // n_leaves + 1 (leaf index order)
     int64_t *d_gnslot = nullptr;
     int64_t n_gnslot_total = 0;
@@ -306,6 +310,12 @@ struct gca_h2_s {
     double *d_tval = nullptr;        // touching values, row CSR (FP64)
     double *d_nval = nullptr;        // near-regular values, row CSR (FP64 path)
     float *d_nvalf = nullptr;        // near-regular values, row CSR (mixed path)
+
+    // stored block rows (gca_store_blocks): entries of the coupling and the
+    // nearfield block rows per precision; the product then reads them
+    double *d_far_g64 = nullptr, *d_near_g64 = nullptr;
+    float *d_far_g32 = nullptr, *d_near_g32 = nullptr;
+    int32_t stored_mask = 0;         // bits GCA_FP64 / GCA_MIXED
 
     // solver workspaces (allocated by the first solve)
     double *d_sv = nullptr;          // 5 x n: r, d, res, p, q
@@ -362,6 +372,10 @@ hipError_t launch_coupling_reduce(gca_h2_s *h, const int64_t *slot_ptr, const in
 hipError_t launch_pivot_points(gca_h2_s *h, hipStream_t s);
 template <typename T>
 hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s);
+template <typename T>
+hipError_t launch_store_blocks(gca_h2_s *h, T *far_store, T *near_store, hipStream_t s);
+template <typename T>
+hipError_t launch_apply_stored(gca_h2_s *h, bool nearfield, const T *x, const T *G, T *part, hipStream_t s);
 template <typename T>
 hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s);
 hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s);

@@ -137,10 +137,10 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[EXP
 // over the C lanes of a tile row by shuffles) and g_ij x_i to cacc[j] (over
 // the R lanes of a tile column); racc and cacc belong to the calling
 // wavefront.  MASK skips the pairs whose bit c0 + j is set in mask[i].
-template <typename T, int P, bool EXP, bool MASK>
+template <typename T, int P, bool EXP, bool MASK, bool STORE>
 __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *rowp, const T *rown,
                                           const Q4<T> *colp, const T *coln, const T *xr, const T *xc,
-                                          const uint64_t *mask, T *racc, T *cacc)
+                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
@@ -178,6 +178,14 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
             }
         }
         const bool valid = i < rw && j < cw;
+        if (STORE) {
+            // entries go to memory (masked ones as zeros) instead of into products
+            T g = 0;
+            if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1)))
+                g = block_entry<T, P, EXP>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
+            if (valid) st[(int64_t)i * ld + j] = g;
+            continue;
+        }
         T v = 0, u = 0;
         if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1))) {
             const T g = block_entry<T, P, EXP>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
@@ -225,12 +233,14 @@ struct FarArgs {
     const float *pq32;        // FP32 path: sum(rank) x P x 4
     const T *xh;
     T *part;
+    T *store;                 // STORE: entries, row-major per group at g_soff
+    const int64_t *g_soff;
     int ng;
     int rmax;
     int cw;
 };
 
-template <typename T, int P>
+template <typename T, int P, bool STORE>
 __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : 1)
     k_far_rows(FarArgs<T> a)
 {
@@ -274,7 +284,9 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
                 rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
             }
         }
-        for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = a.xh[xro + r0 + i];
+        // the store variant gets no vectors (xh is null there)
+        if (!STORE)
+            for (int i = tid; i < rw; i += BLK_THREADS) xr[i] = a.xh[xro + r0 + i];
         for (int c0 = 0; c0 < nc; c0 += CW) {
             const int cw = min(CW, nc - c0);
             __syncthreads();
@@ -296,11 +308,14 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
                     colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
                 }
             }
-            for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xh[a.col_e[kb + c0 + j]];
+            if (!STORE)
+                for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xh[a.col_e[kb + c0 + j]];
             __syncthreads();
-            tile_pass<T, P, EXP, false>(rw, cw, 0, rowp, rown, colp, coln, xr, xc, nullptr, racc + wv * rmax,
-                                        cacc + wv * CW);
+            tile_pass<T, P, EXP, false, STORE>(rw, cw, 0, rowp, rown, colp, coln, xr, xc, nullptr, racc + wv * rmax,
+                                               cacc + wv * CW,
+                                               STORE ? a.store + a.g_soff[g] + (int64_t)r0 * nc + c0 : nullptr, nc);
             __syncthreads();
+            if (STORE) continue;
             for (int j = tid; j < cw; j += BLK_THREADS) {
                 T c = 0;
 #pragma unroll
@@ -315,6 +330,7 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
                     a.part[o] += c;
             }
         }
+        if (STORE) continue;
         for (int i = tid; i < rw; i += BLK_THREADS) {
             T r = 0;
 #pragma unroll
@@ -352,12 +368,14 @@ struct NearArgs {
     const double *q;          // n x P x 4
     const T *xp;              // permuted x
     T *part;
+    T *store;                 // STORE: entries, row-major per group at g_soff
+    const int64_t *g_soff;
     int ng;
     int rmax;                 // >= largest leaf
     int cw;                   // column sub-chunk (divides NEAR_CW)
 };
 
-template <typename T, int P>
+template <typename T, int P, bool STORE>
 __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : 1)
     k_near_rows(NearArgs<T> a)
 {
@@ -391,7 +409,9 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
         const double *src = a.q + ((size_t)(rb + i) * P + p) * 4;
         rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
     }
-    for (int i = tid; i < nr; i += BLK_THREADS) xr[i] = a.xp[rb + i];
+    // the store variant gets no vectors (xp is null there)
+    if (!STORE)
+        for (int i = tid; i < nr; i += BLK_THREADS) xr[i] = a.xp[rb + i];
     for (int c0 = 0; c0 < nc; c0 += CW) {
         const int cw = min(CW, nc - c0);
         const int ch = c0 / NEAR_CW, cb = c0 - ch * NEAR_CW;   // mask word and bit offset
@@ -401,12 +421,15 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
             const double *src = a.q + ((size_t)a.col_pos[kb + c0 + j] * P + p) * 4;
             colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
         }
-        for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xp[a.col_pos[kb + c0 + j]];
+        if (!STORE)
+            for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xp[a.col_pos[kb + c0 + j]];
         for (int i = tid; i < nr; i += BLK_THREADS) mask[i] = gm[(size_t)ch * nr + i];
         __syncthreads();
-        tile_pass<T, P, false, true>(nr, cw, cb, rowp, nullptr, colp, nullptr, xr, xc, mask, racc + wv * rmax,
-                                     cacc + wv * CW);
+        tile_pass<T, P, false, true, STORE>(nr, cw, cb, rowp, nullptr, colp, nullptr, xr, xc, mask,
+                                            racc + wv * rmax, cacc + wv * CW,
+                                            STORE ? a.store + a.g_soff[g] + c0 : nullptr, nc);
         __syncthreads();
+        if (STORE) continue;
         for (int j = tid; j < cw; j += BLK_THREADS) {
             T c = 0;
 #pragma unroll
@@ -417,6 +440,7 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
             a.part[a.col_out[kb + c0 + j]] = c;
         }
     }
+    if (STORE) return;
     for (int i = tid; i < nr; i += BLK_THREADS) {
         T r = 0;
 #pragma unroll
@@ -475,11 +499,12 @@ static int blk_cw(int rmax, int P, bool near, bool exp)
     return 0;
 }
 
-template <typename T>
-hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
+template <typename T, bool STORE>
+static hipError_t near_rows(gca_h2_s *h, const T *xp, T *npart, T *store, hipStream_t s)
 {
     const int ng = h->n_near_groups;
     if (ng == 0) return hipSuccess;
+    if (STORE ? store == nullptr : (xp == nullptr || npart == nullptr)) return hipErrorInvalidValue;
     const int P = h->prm.q_r * h->prm.q_r;
     NearArgs<T> a{};
     a.g_t = h->d_ng_t;
@@ -494,6 +519,8 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
     a.q = h->d_qr;
     a.xp = xp;
     a.part = npart;
+    a.store = store;
+    a.g_soff = h->d_ng_soff;
     a.ng = ng;
     a.rmax = h->max_leaf;
     if (a.rmax > 64) return hipErrorInvalidValue;
@@ -504,7 +531,7 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
     switch (P) {
 #define CASE(PP)                                                                              \
     case PP:                                                                                  \
-        hipLaunchKernelGGL((k_near_rows<T, PP>), dim3(ng), dim3(BLK_THREADS), sm, s, a);       \
+        hipLaunchKernelGGL((k_near_rows<T, PP, STORE>), dim3(ng), dim3(BLK_THREADS), sm, s, a); \
         break;
         CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
 #undef CASE
@@ -514,11 +541,12 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
+template <typename T, bool STORE>
+static hipError_t far_rows(gca_h2_s *h, const T *xh, T *cpart, T *store, hipStream_t s)
 {
     const int ng = h->n_far_groups;
     if (ng == 0) return hipSuccess;
+    if (STORE ? store == nullptr : (xh == nullptr || cpart == nullptr)) return hipErrorInvalidValue;
     const int P = h->prm.q_r * h->prm.q_r;
     constexpr bool EXP = sizeof(T) == 4;
     FarArgs<T> a{};
@@ -536,6 +564,8 @@ hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
     a.pq32 = h->d_pq32;
     a.xh = xh;
     a.part = cpart;
+    a.store = store;
+    a.g_soff = h->d_fg_soff;
     a.ng = ng;
     a.rmax = std::max(1, std::min(64, h->max_rank));
     a.cw = blk_cw<T>(a.rmax, P, false, EXP);
@@ -544,7 +574,7 @@ hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
     switch (P) {
 #define CASE(PP)                                                                              \
     case PP:                                                                                  \
-        hipLaunchKernelGGL((k_far_rows<T, PP>), dim3(ng), dim3(BLK_THREADS), sm, s, a);        \
+        hipLaunchKernelGGL((k_far_rows<T, PP, STORE>), dim3(ng), dim3(BLK_THREADS), sm, s, a);  \
         break;
         CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
 #undef CASE
@@ -554,10 +584,167 @@ hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
+{
+    return near_rows<T, false>(h, xp, npart, nullptr, s);
+}
+
+template <typename T>
+hipError_t launch_far_blocks(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
+{
+    return far_rows<T, false>(h, xh, cpart, nullptr, s);
+}
+
+template <typename T>
+hipError_t launch_store_blocks(gca_h2_s *h, T *far_store, T *near_store, hipStream_t s)
+{
+    hipError_t e = far_rows<T, true>(h, nullptr, nullptr, far_store, s);
+    if (e != hipSuccess) return e;
+    return near_rows<T, true>(h, nullptr, nullptr, near_store, s);
+}
+
+// ----------------------------------------------------- stored block rows ---
+// Product with block rows stored by the STORE kernels: G_g (nr x nc,
+// row-major at g_soff) gives the row partials G_g x_cols and the column
+// partials G_g^T x_rows from one read of every entry.  A wavefront takes
+// column tiles of 16 columns; its lanes cover 4 rows x 16 columns, keep the
+// column sums over the row tiles and the row sums over the column tiles in
+// registers, and combine them by shuffles once per column tile and once per
+// row chunk of 64.  The partial slots are those of the quadrature kernels.
+template <typename T>
+struct ApplyArgs {
+    const int32_t *g_t;
+    const int64_t *g_ptr;
+    const int64_t *g_rslot;
+    const int64_t *g_soff;
+    const int32_t *col_idx;   // coupling: pivot entry (into xh); nearfield: position (into xp)
+    const int64_t *col_out;
+    const int32_t *node;
+    const int32_t *rank;
+    const int64_t *piv_off;
+    const T *x;               // coupling: xh; nearfield: permuted x
+    const T *G;
+    T *part;
+};
+
+template <typename T, bool NEARG>
+__global__ void __launch_bounds__(BLK_THREADS) k_rows_apply(ApplyArgs<T> a)
+{
+    __shared__ T xr[64];
+    __shared__ T racc[BLK_WAVES][64];
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ii = lane >> 4, jj = lane & 15;
+    const int t = a.g_t[g];
+    const int64_t kb = a.g_ptr[g];
+    const int nc = (int)(a.g_ptr[g + 1] - kb);
+    int nr;
+    const T *xrow;
+    if (NEARG) {
+        const int rb = a.node[5 * t];
+        nr = a.node[5 * t + 1] - rb;
+        xrow = a.x + rb;
+    } else {
+        nr = a.rank[t];
+        xrow = a.x + a.piv_off[t];
+    }
+    const T *G = a.G + a.g_soff[g];
+    const int64_t rslot = a.g_rslot[g];
+    for (int r0 = 0; r0 < nr; r0 += 64) {
+        const int rw = min(64, nr - r0);
+        if (r0 > 0) __syncthreads();
+        for (int i = tid; i < 64; i += BLK_THREADS) xr[i] = i < rw ? xrow[r0 + i] : (T)0;
+        __syncthreads();
+        T rowacc[16];
+#pragma unroll
+        for (int rt = 0; rt < 16; ++rt) rowacc[rt] = 0;
+        for (int ct = wv; ct * 16 < nc; ct += BLK_WAVES) {
+            const int j = ct * 16 + jj;
+            const bool vj = j < nc;
+            const T xj = vj ? a.x[a.col_idx[kb + j]] : (T)0;
+            T colacc = 0;
+#pragma unroll
+            for (int rt = 0; rt < 16; ++rt) {
+                const int i = rt * 4 + ii;
+                if (vj && i < rw) {
+                    const T gv = G[(int64_t)(r0 + i) * nc + j];
+                    colacc += gv * xr[i];
+                    rowacc[rt] += gv * xj;
+                }
+            }
+            colacc += __shfl_xor(colacc, 16, 64);
+            colacc += __shfl_xor(colacc, 32, 64);
+            if (ii == 0 && vj) {
+                const int64_t o = a.col_out[kb + j];
+                if (r0 == 0)
+                    a.part[o] = colacc;
+                else
+                    a.part[o] += colacc;
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 16; ++rt) {
+            T v = rowacc[rt];
+            for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+            if (jj == 0) racc[wv][rt * 4 + ii] = v;
+        }
+        __syncthreads();
+        for (int i = tid; i < rw; i += BLK_THREADS) {
+            T r = 0;
+#pragma unroll
+            for (int w = 0; w < BLK_WAVES; ++w) r += racc[w][i];
+            a.part[rslot + r0 + i] = r;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_apply_stored(gca_h2_s *h, bool nearfield, const T *x, const T *G, T *part, hipStream_t s)
+{
+    ApplyArgs<T> a{};
+    a.node = h->d_node;
+    a.rank = h->d_rank;
+    a.piv_off = h->d_piv_off;
+    a.x = x;
+    a.G = G;
+    a.part = part;
+    int ng;
+    if (nearfield) {
+        ng = h->n_near_groups;
+        a.g_t = h->d_ng_t;
+        a.g_ptr = h->d_ng_ptr;
+        a.g_rslot = h->d_ng_rslot;
+        a.g_soff = h->d_ng_soff;
+        a.col_idx = h->d_ncol_pos;
+        a.col_out = h->d_ncol_out;
+    } else {
+        ng = h->n_far_groups;
+        a.g_t = h->d_fg_t;
+        a.g_ptr = h->d_fg_ptr;
+        a.g_rslot = h->d_fg_rslot;
+        a.g_soff = h->d_fg_soff;
+        a.col_idx = h->d_fcol_e;
+        a.col_out = h->d_fcol_out;
+    }
+    if (ng == 0) return hipSuccess;
+    if (nearfield)
+        hipLaunchKernelGGL((k_rows_apply<T, true>), dim3(ng), dim3(BLK_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_rows_apply<T, false>), dim3(ng), dim3(BLK_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
 template hipError_t launch_near<float>(gca_h2_s *, const float *, float *, hipStream_t);
 template hipError_t launch_near<double>(gca_h2_s *, const double *, double *, hipStream_t);
 template hipError_t launch_far_blocks<float>(gca_h2_s *, const float *, float *, hipStream_t);
 template hipError_t launch_far_blocks<double>(gca_h2_s *, const double *, double *, hipStream_t);
+template hipError_t launch_store_blocks<float>(gca_h2_s *, float *, float *, hipStream_t);
+template hipError_t launch_store_blocks<double>(gca_h2_s *, double *, double *, hipStream_t);
+template hipError_t launch_apply_stored<float>(gca_h2_s *, bool, const float *, const float *, float *,
+                                               hipStream_t);
+template hipError_t launch_apply_stored<double>(gca_h2_s *, bool, const double *, const double *, double *,
+                                                hipStream_t);
 
 // -------------------------------------------------- touching pairs (FP64) --
 
