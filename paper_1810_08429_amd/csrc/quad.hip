@@ -607,11 +607,16 @@ hipError_t launch_store_blocks(gca_h2_s *h, T *far_store, T *near_store, hipStre
 // ----------------------------------------------------- stored block rows ---
 // Product with block rows stored by the STORE kernels: G_g (nr x nc,
 // row-major at g_soff) gives the row partials G_g x_cols and the column
-// partials G_g^T x_rows from one read of every entry.  A wavefront takes
-// column tiles of 16 columns; its lanes cover 4 rows x 16 columns, keep the
-// column sums over the row tiles and the row sums over the column tiles in
-// registers, and combine them by shuffles once per column tile and once per
-// row chunk of 64.  The partial slots are those of the quadrature kernels.
+// partials G_g^T x_rows from one read of every entry.  Wavefront w streams
+// the rows i = w mod 4 (each a contiguous run of nc entries, lanes over
+// columns): the row sum is reduced across the wavefront by shuffles, the
+// column sums stay in registers (up to APPLY_CB columns at a time) and are
+// combined over the four wavefronts in LDS.  One writer per partial slot.
+constexpr int APPLY_K = 4;                 // column registers per lane
+constexpr int APPLY_CB = 64 * APPLY_K;     // columns per pass
+template <typename T>
+constexpr int apply_rows() { return sizeof(T) == 4 ? 4 : 2; }   // rows per wavefront step
+
 template <typename T>
 struct ApplyArgs {
     const int32_t *g_t;
@@ -631,11 +636,9 @@ struct ApplyArgs {
 template <typename T, bool NEARG>
 __global__ void __launch_bounds__(BLK_THREADS) k_rows_apply(ApplyArgs<T> a)
 {
-    __shared__ T xr[64];
-    __shared__ T racc[BLK_WAVES][64];
+    __shared__ T cacc[BLK_WAVES][APPLY_CB];
     const int g = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int ii = lane >> 4, jj = lane & 15;
     const int t = a.g_t[g];
     const int64_t kb = a.g_ptr[g];
     const int nc = (int)(a.g_ptr[g + 1] - kb);
@@ -651,51 +654,59 @@ __global__ void __launch_bounds__(BLK_THREADS) k_rows_apply(ApplyArgs<T> a)
     }
     const T *G = a.G + a.g_soff[g];
     const int64_t rslot = a.g_rslot[g];
-    for (int r0 = 0; r0 < nr; r0 += 64) {
-        const int rw = min(64, nr - r0);
-        if (r0 > 0) __syncthreads();
-        for (int i = tid; i < 64; i += BLK_THREADS) xr[i] = i < rw ? xrow[r0 + i] : (T)0;
-        __syncthreads();
-        T rowacc[16];
+    for (int cb = 0; cb < nc; cb += APPLY_CB) {
+        const int cw = min(APPLY_CB, nc - cb);
+        T xc[APPLY_K], ca[APPLY_K];
 #pragma unroll
-        for (int rt = 0; rt < 16; ++rt) rowacc[rt] = 0;
-        for (int ct = wv; ct * 16 < nc; ct += BLK_WAVES) {
-            const int j = ct * 16 + jj;
-            const bool vj = j < nc;
-            const T xj = vj ? a.x[a.col_idx[kb + j]] : (T)0;
-            T colacc = 0;
+        for (int k = 0; k < APPLY_K; ++k) {
+            const int j = lane + 64 * k;
+            xc[k] = j < cw ? a.x[a.col_idx[kb + cb + j]] : (T)0;
+            ca[k] = 0;
+        }
+        // APPLY_R rows per step so that their loads are in flight together
+        constexpr int APPLY_R = apply_rows<T>();
+        for (int i0 = wv; i0 < nr; i0 += APPLY_R * BLK_WAVES) {
+            T gr[APPLY_R][APPLY_K], xi[APPLY_R];
 #pragma unroll
-            for (int rt = 0; rt < 16; ++rt) {
-                const int i = rt * 4 + ii;
-                if (vj && i < rw) {
-                    const T gv = G[(int64_t)(r0 + i) * nc + j];
-                    colacc += gv * xr[i];
-                    rowacc[rt] += gv * xj;
+            for (int q = 0; q < APPLY_R; ++q) {
+                const int i = i0 + q * BLK_WAVES;
+                const bool ok = i < nr;
+                xi[q] = ok ? xrow[i] : (T)0;
+                const T *Gi = G + (int64_t)(ok ? i : i0) * nc + cb;
+#pragma unroll
+                for (int k = 0; k < APPLY_K; ++k) {
+                    const int j = lane + 64 * k;
+                    gr[q][k] = (ok && j < cw) ? Gi[j] : (T)0;
                 }
             }
-            colacc += __shfl_xor(colacc, 16, 64);
-            colacc += __shfl_xor(colacc, 32, 64);
-            if (ii == 0 && vj) {
-                const int64_t o = a.col_out[kb + j];
-                if (r0 == 0)
-                    a.part[o] = colacc;
-                else
-                    a.part[o] += colacc;
+#pragma unroll
+            for (int q = 0; q < APPLY_R; ++q) {
+                T v = 0;
+#pragma unroll
+                for (int k = 0; k < APPLY_K; ++k) {
+                    v += gr[q][k] * xc[k];
+                    ca[k] += gr[q][k] * xi[q];
+                }
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                const int i = i0 + q * BLK_WAVES;
+                if (lane == 0 && i < nr) {
+                    if (cb == 0)
+                        a.part[rslot + i] = v;
+                    else
+                        a.part[rslot + i] += v;
+                }
             }
         }
 #pragma unroll
-        for (int rt = 0; rt < 16; ++rt) {
-            T v = rowacc[rt];
-            for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
-            if (jj == 0) racc[wv][rt * 4 + ii] = v;
+        for (int k = 0; k < APPLY_K; ++k) cacc[wv][lane + 64 * k] = ca[k];
+        __syncthreads();
+        for (int j = tid; j < cw; j += BLK_THREADS) {
+            T c = 0;
+#pragma unroll
+            for (int w = 0; w < BLK_WAVES; ++w) c += cacc[w][j];
+            a.part[a.col_out[kb + cb + j]] = c;
         }
         __syncthreads();
-        for (int i = tid; i < rw; i += BLK_THREADS) {
-            T r = 0;
-#pragma unroll
-            for (int w = 0; w < BLK_WAVES; ++w) r += racc[w][i];
-            a.part[rslot + r0 + i] = r;
-        }
     }
 }
 
