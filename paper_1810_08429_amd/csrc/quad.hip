@@ -775,7 +775,9 @@ struct V3 {
 };
 __device__ __forceinline__ V3 vsub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ double vnorm(V3 a) { return sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
-__device__ __forceinline__ double vrnorm(double x, double y, double z) { return rsqrt(x * x + y * y + z * z); }
+// the Sauter-Schwab integrands are evaluated at interior Gauss points, where
+// the squared distances are positive and finite
+__device__ __forceinline__ double vrnorm(double x, double y, double z) { return rsq<double>(x * x + y * y + z * z); }
 __device__ __forceinline__ double cross_norm(V3 a, V3 b)
 {
     double cx = a.y * b.z - a.z * b.y, cy = a.z * b.x - a.x * b.z, cz = a.x * b.y - a.y * b.x;
