@@ -163,6 +163,15 @@ template hipError_t launch_backward<double>(gca_h2_s *, double *, hipStream_t);
 // written back in the original triangle order.  The touching values (FP64)
 // and near-regular values (T) are stored in row CSRs aligned with their
 // column indices, so each row streams its own entries.
+// Workgroups are dealt to the 8 XCDs of the chip round-robin by id; this
+// bijection gives each XCD a contiguous range of leaves, so the neighbouring
+// positions a leaf's touching pairs read stay in that XCD's L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int nb)
+{
+    const int q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + min(x, r) + b / 8;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int32_t *node, const int32_t *rank,
                                                const int64_t *piv_off, const int64_t *v_off, const T *Vt,
@@ -172,7 +181,7 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
                                                const T *nval, const T *xp, const double *xp64,
                                                const int32_t *perm, double *y)
 {
-    const int li = blockIdx.x;
+    const int li = xcd_contiguous(blockIdx.x, gridDim.x);
     const int c = leaves[li];
     const int b = node[5 * c], nr = node[5 * c + 1] - b;
     const int r = rank[c];
