@@ -424,6 +424,9 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         return GCA_OK;
     };
     GCA_TRY(tri_pts(p->q_r, &h->d_qr));
+    GCA_TRY(dalloc(h, &h->d_cent, (size_t)n * 4));
+    GCA_TRY(dalloc(h, &h->d_qloc32, (size_t)n * p->q_r * p->q_r * 4));
+    GCA_HIP_TRY(launch_local_points(h, s));
     if (p->q_nr == p->q_r)
         h->d_qnr = h->d_qr;
     else
@@ -1414,6 +1417,7 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
         return GCA_OK;
     };
     GCA_TRY(tri_pts(h->prm.q_r, h->d_qr));
+    GCA_HIP_TRY(launch_local_points(h, s));
     if (h->d_qnr != h->d_qr) GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
     if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, h->d_qA));
     if (h->n_piv_total > 0) GCA_HIP_TRY(launch_pivot_points(h, s));

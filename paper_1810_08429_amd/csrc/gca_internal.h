@@ -231,6 +231,8 @@ struct gca_h2_s {
     double *d_qr = nullptr;          // n x Pr x 4 (x, y, z, w*J), regular rule
     double *d_qnr = nullptr;         // n x Pnr x 4, near-regular rule
     double *d_qA = nullptr;          // n x PA x 4 (may alias d_qr)
+    double *d_cent = nullptr;        // n x 4: reference point per triangle (mean of its d_qr points)
+    float *d_qloc32 = nullptr;       // n x Pr x 4: d_qr points relative to it (FP32), weights
     double *d_box = nullptr;         // nc x 8: lo, hi, diam, 0
 
     int32_t *d_piv = nullptr;        // pivot positions
@@ -370,6 +372,7 @@ template <typename T>
 hipError_t launch_coupling_reduce(gca_h2_s *h, const int64_t *slot_ptr, const int64_t *slots, const T *cpart,
                                   T *yh, hipStream_t s);
 hipError_t launch_pivot_points(gca_h2_s *h, hipStream_t s);
+hipError_t launch_local_points(gca_h2_s *h, hipStream_t s);
 template <typename T>
 hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s);
 template <typename T>

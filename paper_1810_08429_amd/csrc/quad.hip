@@ -80,8 +80,9 @@ __host__ __device__ constexpr size_t al16(size_t b) { return (b + 15) & ~(size_t
 // distance |x - y|^2 = |x|^2 + |y|^2 - 2 x.y.
 template <typename T>
 struct BlkLayout {
-    size_t mask, rowp, rown, colp, coln, xr, xc, racc, cacc, total;
-    __host__ __device__ BlkLayout(int rmax, int P, int CW, bool near, bool exp)
+    size_t mask, rowp, rown, colp, coln, xr, xc, racc, cacc, rowc, colc, total;
+    // loc: per-triangle reference points rowc[rmax], colc[CW] (Q4) as well
+    __host__ __device__ BlkLayout(int rmax, int P, int CW, bool near, bool exp, bool loc = false)
     {
         mask = 0;
         rowp = mask + (near ? al16((size_t)rmax * 8) : 0);
@@ -92,7 +93,9 @@ struct BlkLayout {
         xc = xr + al16((size_t)rmax * sizeof(T));
         racc = xc + al16((size_t)CW * sizeof(T));
         cacc = racc + al16((size_t)BLK_WAVES * rmax * sizeof(T));
-        total = cacc + al16((size_t)BLK_WAVES * CW * sizeof(T));
+        rowc = cacc + al16((size_t)BLK_WAVES * CW * sizeof(T));
+        colc = rowc + (loc ? al16((size_t)rmax * sizeof(Q4<T>)) : 0);
+        total = colc + (loc ? al16((size_t)CW * sizeof(Q4<T>)) : 0);
     }
 };
 
@@ -137,6 +140,54 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[EXP
     return acc;
 }
 
+// Entry with per-triangle reference points (FP32 nearfield): x_a = c_i + a,
+// y_b = c_j + b, d = c_i - c_j, m = -2 b:
+//     |x_a - y_b|^2 = |d + a|^2 + (|b|^2 + m.d) + a.m
+// The first two terms are formed once per entry (9 + 9 values), the last
+// costs three FMAs per evaluation; all magnitudes are those of the pair's
+// own geometry, so the cancellation stays that of the pair's distance.
+template <int P>
+__device__ __forceinline__ float entry_loc(const Q4<float> (&rp)[P], const float (&rn)[P], const Q4<float> ci,
+                                           const Q4<float> *cp, const float *cn, const Q4<float> cj)
+{
+    const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+    const float dd = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float ex = 2 * dx, ey = 2 * dy, ez = 2 * dz;
+    float al[P];
+#pragma unroll
+    for (int pa = 0; pa < P; ++pa)
+        al[pa] = __builtin_fmaf(ex, rp[pa].x, __builtin_fmaf(ey, rp[pa].y, __builtin_fmaf(ez, rp[pa].z, rn[pa] + dd)));
+    float acc = 0;
+#pragma unroll
+    for (int pb = 0; pb < P; ++pb) {
+        const Q4<float> c = cp[pb];
+        const float be = __builtin_fmaf(c.x, dx, __builtin_fmaf(c.y, dy, __builtin_fmaf(c.z, dz, cn[pb])));
+        float inner = 0;
+#pragma unroll
+        for (int pa = 0; pa < P; ++pa) {
+            float r2 = al[pa] + be;
+            r2 = __builtin_fmaf(rp[pa].z, c.z, r2);
+            r2 = __builtin_fmaf(rp[pa].y, c.y, r2);
+            r2 = __builtin_fmaf(rp[pa].x, c.x, r2);
+            inner = __builtin_fmaf(rp[pa].w, rsq<float>(r2), inner);
+        }
+        acc = __builtin_fmaf(c.w, inner, acc);
+    }
+    return acc;
+}
+
+template <typename T, int P, bool EXP, bool LOC>
+__device__ __forceinline__ T entry_dispatch(const Q4<T> (&rr)[P], const T (&rq)[(EXP || LOC) ? P : 1], const Q4<T> rc,
+                                            const Q4<T> *colp, const T *coln, const Q4<T> *colc, int j)
+{
+    if constexpr (LOC) {
+        return entry_loc<P>(rr, rq, rc, colp + (size_t)j * P, coln + (size_t)j * P, colc[j]);
+    } else {
+        return block_entry<T, P, EXP>(rr, reinterpret_cast<const T(&)[EXP ? P : 1]>(rq), colp + (size_t)j * P,
+                                      coln + (size_t)j * P);
+    }
+}
+
 // One pass over the entries of an rw x cw chunk (rows in rowp/rown, columns
 // in colp/coln, both in LDS): tiles of R x C = 64 lanes (C = 4 .. 64 picked
 // for the fewest tile rounds over the 4 wavefronts, then the fewest tiles).
@@ -146,10 +197,11 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[EXP
 // over the C lanes of a tile row by shuffles) and g_ij x_i to cacc[j] (over
 // the R lanes of a tile column); racc and cacc belong to the calling
 // wavefront.  MASK skips the pairs whose bit c0 + j is set in mask[i].
-template <typename T, int P, bool EXP, bool MASK, bool STORE>
+template <typename T, int P, bool EXP, bool MASK, bool STORE, bool LOC = false>
 __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *rowp, const T *rown,
                                           const Q4<T> *colp, const T *coln, const T *xr, const T *xc,
-                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld)
+                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld,
+                                          const Q4<T> *rowc = nullptr, const Q4<T> *colc = nullptr)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
@@ -172,7 +224,8 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
     const int k1 = MASK ? best_n : ((wv + 1) * best_n) / BLK_WAVES;
     const int kstep = MASK ? BLK_WAVES : 1;
     Q4<T> rr[P];
-    T rq[EXP ? P : 1];
+    T rq[(EXP || LOC) ? P : 1];
+    Q4<T> rc{};
     int cur_tr = -1;
     for (int k = k0; k < k1; k += kstep) {
         const int tr = k / nct, tc = k - tr * nct;
@@ -183,21 +236,22 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 rr[p] = rowp[(size_t)il * P + p];
-                if (EXP) rq[EXP ? p : 0] = rown[(size_t)il * P + p];
+                if (EXP || LOC) rq[(EXP || LOC) ? p : 0] = rown[(size_t)il * P + p];
             }
+            if (LOC) rc = rowc[il];
         }
         const bool valid = i < rw && j < cw;
         if (STORE) {
             // entries go to memory (masked ones as zeros) instead of into products
             T g = 0;
             if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1)))
-                g = block_entry<T, P, EXP>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
+                g = entry_dispatch<T, P, EXP, LOC>(rr, rq, rc, colp, coln, colc, j) * (T)INV4PI;
             if (valid) st[(int64_t)i * ld + j] = g;
             continue;
         }
         T v = 0, u = 0;
         if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1))) {
-            const T g = block_entry<T, P, EXP>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
+            const T g = entry_dispatch<T, P, EXP, LOC>(rr, rq, rc, colp, coln, colc, j) * (T)INV4PI;
             v = g * xc[j];
             u = g * xr[i];
         }
@@ -374,7 +428,9 @@ struct NearArgs {
     const uint64_t *mask;
     const int32_t *node;      // nc x 5
     const double *box;        // nc x 8
-    const double *q;          // n x P x 4
+    const double *q;          // n x P x 4 (FP64 path)
+    const double *cent;       // FP32 path: n x 4, reference point of each triangle
+    const float *qloc;        // FP32 path: n x P x 4, points relative to it (x, y, z, w)
     const T *xp;              // permuted x
     T *part;
     T *store;                 // STORE: entries, row-major per group at g_soff
@@ -399,24 +455,42 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
     const int64_t rslot = a.g_rslot[g];
     const uint64_t *gm = a.mask + a.g_moff[g];
     const int rmax = a.rmax;
-    const BlkLayout<T> L(rmax, P, CW, true, false);
+    // FP32: per-triangle reference points (entry_loc); FP64: direct differences
+    constexpr bool LOC = sizeof(T) == 4;
+    const BlkLayout<T> L(rmax, P, CW, true, LOC, LOC);
     uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
     Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
+    T *rown = reinterpret_cast<T *>(smem + L.rown);
     Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
+    T *coln = reinterpret_cast<T *>(smem + L.coln);
     T *xr = reinterpret_cast<T *>(smem + L.xr);
     T *xc = reinterpret_cast<T *>(smem + L.xc);
     T *racc = reinterpret_cast<T *>(smem + L.racc);
     T *cacc = reinterpret_cast<T *>(smem + L.cacc);
+    Q4<T> *rowc = reinterpret_cast<Q4<T> *>(smem + L.rowc);
+    Q4<T> *colc = reinterpret_cast<Q4<T> *>(smem + L.colc);
     const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
     const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
     const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+    // reference point of triangle `pos` relative to t's box centre
+    auto refpt = [&](int pos) {
+        const double *c = a.cent + 4 * (size_t)pos;
+        return Q4<T>{(T)(c[0] - cx), (T)(c[1] - cy), (T)(c[2] - cz), (T)0};
+    };
 
     for (int e = tid; e < BLK_WAVES * rmax; e += BLK_THREADS) racc[e] = 0;
     for (int e = tid; e < BLK_WAVES * CW; e += BLK_THREADS) cacc[e] = 0;
     for (int e = tid; e < nr * P; e += BLK_THREADS) {
         const int i = e / P, p = e - i * P;
-        const double *src = a.q + ((size_t)(rb + i) * P + p) * 4;
-        rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+        if (LOC) {
+            const float4 v = reinterpret_cast<const float4 *>(a.qloc)[(size_t)(rb + i) * P + p];
+            rowp[e] = Q4<T>{(T)v.x, (T)v.y, (T)v.z, (T)v.w};
+            rown[e] = (T)(v.x * v.x + v.y * v.y + v.z * v.z);
+            if (p == 0) rowc[i] = refpt(rb + i);
+        } else {
+            const double *src = a.q + ((size_t)(rb + i) * P + p) * 4;
+            rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+        }
     }
     // the store variant gets no vectors (xp is null there)
     if (!STORE)
@@ -427,16 +501,24 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
         __syncthreads();
         for (int e = tid; e < cw * P; e += BLK_THREADS) {
             const int j = e / P, p = e - j * P;
-            const double *src = a.q + ((size_t)a.col_pos[kb + c0 + j] * P + p) * 4;
-            colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+            const int pos = a.col_pos[kb + c0 + j];
+            if (LOC) {
+                const float4 v = reinterpret_cast<const float4 *>(a.qloc)[(size_t)pos * P + p];
+                colp[e] = Q4<T>{(T)(-2 * v.x), (T)(-2 * v.y), (T)(-2 * v.z), (T)v.w};
+                coln[e] = (T)(v.x * v.x + v.y * v.y + v.z * v.z);
+                if (p == 0) colc[j] = refpt(pos);
+            } else {
+                const double *src = a.q + ((size_t)pos * P + p) * 4;
+                colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+            }
         }
         if (!STORE)
             for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xp[a.col_pos[kb + c0 + j]];
         for (int i = tid; i < nr; i += BLK_THREADS) mask[i] = gm[(size_t)ch * nr + i];
         __syncthreads();
-        tile_pass<T, P, false, true, STORE>(nr, cw, cb, rowp, nullptr, colp, nullptr, xr, xc, mask,
-                                            racc + wv * rmax, cacc + wv * CW,
-                                            STORE ? a.store + a.g_soff[g] + c0 : nullptr, nc);
+        tile_pass<T, P, false, true, STORE, LOC>(nr, cw, cb, rowp, rown, colp, coln, xr, xc, mask,
+                                                 racc + wv * rmax, cacc + wv * CW,
+                                                 STORE ? a.store + a.g_soff[g] + c0 : nullptr, nc, rowc, colc);
         __syncthreads();
         if (STORE) continue;
         for (int j = tid; j < cw; j += BLK_THREADS) {
@@ -456,6 +538,38 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
         for (int w = 0; w < BLK_WAVES; ++w) r += racc[w * rmax + i];
         a.part[rslot + i] = r;
     }
+}
+
+// Reference point of every triangle (the mean of its regular-rule points, FP64)
+// and the points relative to it (FP64 subtract, one rounding to FP32), for
+// the FP32 nearfield blocks.
+__global__ void k_local_points(const double *q, int P, int64_t n, double *cent, float *qloc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *src = q + (size_t)i * P * 4;
+    double c[3] = {0, 0, 0};
+    for (int p = 0; p < P; ++p)
+        for (int d = 0; d < 3; ++d) c[d] += src[4 * p + d];
+    for (int d = 0; d < 3; ++d) c[d] /= P;
+    for (int d = 0; d < 3; ++d) cent[4 * i + d] = c[d];
+    cent[4 * i + 3] = 0;
+    for (int p = 0; p < P; ++p) {
+        float4 v;
+        v.x = (float)(src[4 * p + 0] - c[0]);
+        v.y = (float)(src[4 * p + 1] - c[1]);
+        v.z = (float)(src[4 * p + 2] - c[2]);
+        v.w = (float)src[4 * p + 3];
+        reinterpret_cast<float4 *>(qloc)[(size_t)i * P + p] = v;
+    }
+}
+
+hipError_t launch_local_points(gca_h2_s *h, hipStream_t s)
+{
+    const int P = h->prm.q_r * h->prm.q_r;
+    hipLaunchKernelGGL(k_local_points, dim3((unsigned)((h->n + 127) / 128)), dim3(128), 0, s, h->d_qr, P, h->n,
+                       h->d_cent, h->d_qloc32);
+    return hipGetLastError();
 }
 
 // FP32 copies of the pivots' quadrature points relative to their cluster's
@@ -526,6 +640,8 @@ static hipError_t near_rows(gca_h2_s *h, const T *xp, T *npart, T *store, hipStr
     a.node = h->d_node;
     a.box = h->d_box;
     a.q = h->d_qr;
+    a.cent = h->d_cent;
+    a.qloc = h->d_qloc32;
     a.xp = xp;
     a.part = npart;
     a.store = store;
@@ -533,9 +649,10 @@ static hipError_t near_rows(gca_h2_s *h, const T *xp, T *npart, T *store, hipStr
     a.ng = ng;
     a.rmax = h->max_leaf;
     if (a.rmax > 64) return hipErrorInvalidValue;
+    constexpr bool LOC = sizeof(T) == 4;
     a.cw = NEAR_CW;
-    while (a.cw > 8 && blk_smem<T>(a.rmax, P, a.cw, true, false) > 64 * 1024) a.cw /= 2;
-    const size_t sm = blk_smem<T>(a.rmax, P, a.cw, true, false);
+    while (a.cw > 8 && BlkLayout<T>(a.rmax, P, a.cw, true, LOC, LOC).total > 64 * 1024) a.cw /= 2;
+    const size_t sm = BlkLayout<T>(a.rmax, P, a.cw, true, LOC, LOC).total;
     if (sm > 64 * 1024) return hipErrorInvalidValue;
     switch (P) {
 #define CASE(PP)                                                                              \
