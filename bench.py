@@ -37,15 +37,16 @@ if ROOT not in sys.path:
 METRIC = "H² matvec DoF/s + setup s at 1e-4 rel err: mixed vs FP64 plain, % roofline"
 
 # ALU ceiling of one FP32 kernel evaluation w / |x - y| accumulated into a sum
-# (derivation in the design doc): 7 VALU lane-ops (3 sub, 1 mul, 2 fma for |x-y|^2,
-# 1 fma to accumulate) + 1 v_rsq_f32.  The published FP32 vector peak, 157.3
-# TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes per clock, gives 7.86e13 lane-ops/s;
+# (derivation in the design doc): with the squared distance expanded around
+# reference points, 5 VALU lane-ops (1 add + 3 fma for |x - y|^2, 1 fma to
+# accumulate) + 1 v_rsq_f32.  The published FP32 vector peak, 157.3 TFLOP/s =
+# 256 CUs x 2.4 GHz x 128 FMA lanes per clock, gives 7.86e13 lane-ops/s;
 # transcendentals run at a quarter of that.  Algorithmic work is counted as 10
 # flops per evaluation.
 VALU_LANE_OPS_PER_S = 256 * 128 * 2.4e9
 TRANS_LANE_OPS_PER_S = VALU_LANE_OPS_PER_S / 4
 FLOPS_PER_EVAL = 10
-EVALS_PER_S_F32 = 1.0 / (7.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
+EVALS_PER_S_F32 = 1.0 / (5.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
 ALU_PEAK_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
 
 
