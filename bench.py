@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--eps", type=float, default=None, help="override the workload's ACA tolerance")
     ap.add_argument("--q-nr", type=int, default=None, help="override the near-regular pair order")
+    ap.add_argument("--q-c", type=int, default=None, help="override the coupling-entry rule order")
     ap.add_argument("--stored-steps", type=int, default=10,
                     help="timed products per precision in stored-block mode (0 disables it)")
     ap.add_argument("--grad-steps", type=int, default=3,
@@ -107,6 +108,10 @@ def main():
         cfg["eps"] = a.eps
     params = gca.Params(eta=cfg["eta"], eps=cfg["eps"], green_m=cfg["green_m"],
                         omega_scale=cfg.get("omega_scale", 0.25))
+    if a.q_c is not None:
+        params.q_c = a.q_c
+    elif "q_c" in cfg:
+        params.q_c = cfg["q_c"]
     if a.q_nr is not None:
         params.q_nr = a.q_nr
 
@@ -200,12 +205,13 @@ def main():
 
     # dominant kernel of the mixed product: coupling-block or nearfield-block quadrature
     P = params.q_r * params.q_r
-    work = {"coupling_blocks": st["coupling_entries"] * P * P * FLOPS_PER_EVAL,
+    Pc = params.q_c * params.q_c
+    work = {"coupling_blocks": st["coupling_entries"] * Pc * Pc * FLOPS_PER_EVAL,
             "near_blocks": st["near_regular_pairs"] * P * P * FLOPS_PER_EVAL}
     dom = max(work, key=lambda k: mean_mixed[k])
     dur = mean_mixed[dom] * 1e-3
     achieved = work[dom] / dur / 1e12
-    kname = ("k_far_rows<float,%d>" % P) if dom == "coupling_blocks" else ("k_near_rows<float,%d>" % P)
+    kname = ("k_far_rows<float,%d>" % Pc) if dom == "coupling_blocks" else ("k_near_rows<float,%d>" % P)
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": measured_traffic(kname),
                 "kernel": kname,
@@ -258,6 +264,8 @@ def main():
         "config": {"workload": f"{a.workload}: unit icosphere, {n} flat triangles, piecewise-constant basis, "
                                f"leaf {cfg['leaf']}, eta {cfg['eta']}, Green order {cfg['green_m']}, "
                                f"omega margin {params.omega_scale} diam/eta, ACA eps {cfg['eps']}, "
+                               f"Gauss orders regular {params.q_r} / coupling {params.q_c} / "
+                               f"near {params.q_nr} / Sauter-Schwab {params.q_s}, "
                                f"1 RHS x ~ N(0,1) seed 0",
                    "n": n, "nrhs": 1, "precision": "mixed: FP32 regular-pair quadrature + transfers, "
                                                    "FP64 Sauter-Schwab touching pairs"},

@@ -71,7 +71,9 @@ typedef struct {
     int32_t q_r;         /* regular pair rule order (per triangle: q_r^2 points)  */
     int32_t q_nr;        /* order for near-regular pairs (vertices joined by an edge) */
     int32_t q_s;         /* Sauter-Schwab order (>= 2) for touching pairs         */
-    int32_t reserved[3]; /* must be zero */
+    int32_t q_c;         /* regular rule order for the coupling entries G|t~ x s~
+                            (admissible blocks); 0 means q_c = q_r              */
+    int32_t reserved[2]; /* must be zero */
 } gca_params;
 
 #define GCA_NPHASE 9
@@ -110,7 +112,7 @@ typedef struct {
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
- * q_r 3, q_nr 3, q_s 4.  With q_nr == q_r near-regular pairs are
+ * q_r 3, q_nr 3, q_s 4, q_c 3.  With q_nr == q_r near-regular pairs are
  * integrated by the regular rule inside the nearfield blocks (no separate
  * list). */
 void gca_params_default(gca_params *p);

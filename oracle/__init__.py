@@ -393,11 +393,13 @@ class H2:
     E: dict            # non-root cluster -> E_tau (|tau~| x |parent~|)
     ent: Entries
     blocks: dict = field(default_factory=dict)   # entries of coupling / near blocks, filled on first use
+    ent_c: Entries = None                        # rule of the coupling entries (default: ent)
 
     def coupling(self, t, s):
         key = ("far", t, s)
         if key not in self.blocks:
-            self.blocks[key] = self.ent.block(self.pivots[t], self.pivots[s])
+            e = self.ent_c if self.ent_c is not None else self.ent
+            self.blocks[key] = e.block(self.pivots[t], self.pivots[s])
         return self.blocks[key]
 
     def nearblock(self, t, s):
@@ -408,8 +410,11 @@ class H2:
 
 
 def gca_h2(verts, tris, leaf=32, eta=2.0, m=3, eps=1e-6, q_A=3, q=(3, 5, 4),
-           omega_scale=0.25, ent=None):
-    """Build the GCA-H^2 approximation step by step (Sections 2-4)."""
+           omega_scale=0.25, ent=None, q_c=None):
+    """Build the GCA-H^2 approximation step by step (Sections 2-4).  q_c: order
+    of the regular rule for the coupling entries G|t~ x s~ (default q[0]); the
+    coupling matrices are Galerkin entries of well-separated pairs, whose
+    rule order is a parameter of the method like the others."""
     tree = cluster_tree(verts, tris, leaf)
     far, near = block_tree(tree, eta)
     if ent is None:
@@ -435,7 +440,10 @@ def gca_h2(verts, tris, leaf=32, eta=2.0, m=3, eps=1e-6, q_A=3, q=(3, 5, 4),
                 r = len(pivots[s])
                 E[s] = Vh[o:o + r, :]
                 o += r
-    return H2(tree, far, near, pivots, V, E, ent)
+    ent_c = None
+    if q_c is not None and q_c != q[0]:
+        ent_c = Entries(verts, tris, q_c, q[1], q[2])
+    return H2(tree, far, near, pivots, V, E, ent, ent_c=ent_c)
 
 
 def h2_matvec(h: H2, x):

@@ -53,7 +53,8 @@ class _Mesh(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("eps", ctypes.c_double), ("omega_scale", ctypes.c_double),
                 ("green_m", ctypes.c_int32), ("q_A", ctypes.c_int32), ("q_r", ctypes.c_int32),
-                ("q_nr", ctypes.c_int32), ("q_s", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("q_nr", ctypes.c_int32), ("q_s", ctypes.c_int32), ("q_c", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class _Stats(ctypes.Structure):
@@ -127,11 +128,13 @@ class Params:
     q_r: int = 3
     q_nr: int = 3
     q_s: int = 4
+    q_c: int = 3
 
     def _c(self):
         p = _Params()
         p.eta, p.eps, p.omega_scale = self.eta, self.eps, self.omega_scale
         p.green_m, p.q_A, p.q_r, p.q_nr, p.q_s = self.green_m, self.q_A, self.q_r, self.q_nr, self.q_s
+        p.q_c = self.q_c
         return p
 
 

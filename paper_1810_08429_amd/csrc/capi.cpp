@@ -76,8 +76,8 @@ gca_status check_params(const gca_params *p)
     if (p->q_r < 1 || p->q_r > 6) return set_error(GCA_EINVAL, "q_r must be in [1, 6]");
     if (p->q_nr < 1 || p->q_nr > 7) return set_error(GCA_EINVAL, "q_nr must be in [1, 7]");
     if (p->q_s < 2 || p->q_s > 32) return set_error(GCA_EINVAL, "q_s must be in [2, 32]");
-    if (p->reserved[0] || p->reserved[1] || p->reserved[2])
-        return set_error(GCA_EINVAL, "reserved fields must be zero");
+    if (p->reserved[0] || p->reserved[1]) return set_error(GCA_EINVAL, "reserved fields must be zero");
+    if (p->q_c < 0 || p->q_c > 6) return set_error(GCA_EINVAL, "q_c must be in 1..6 (0: same as q_r)");
     return GCA_OK;
 }
 
@@ -311,6 +311,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     const double t0 = now_ms();
     GCA_TRY(check_params(p));
     h->prm = *p;
+    if (h->prm.q_c == 0) h->prm.q_c = h->prm.q_r;
     // the topology checks ran when the tree was built from this same mesh
     GCA_TRY(mesh_copy_validate(mesh, h->mesh, false));
     if (tree->nt != h->mesh.nt || tree->nv != h->mesh.nv || tree->mesh_xyz != h->mesh.xyz ||
@@ -435,6 +436,10 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
         h->d_qA = h->d_qr;
     else
         GCA_TRY(tri_pts(p->q_A, &h->d_qA));
+    if (h->prm.q_c == p->q_r)
+        h->d_qc = h->d_qr;
+    else
+        GCA_TRY(tri_pts(h->prm.q_c, &h->d_qc));
 
     GCA_HIP_TRY(hipStreamSynchronize(s));
     lap(3);
@@ -579,7 +584,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             for (int64_t k = h->piv_off[c]; k < h->piv_off[c] + h->rank[c]; ++k) pc[(size_t)k] = c;
         if (h->n_piv_total > 0) {
             GCA_TRY(upload_new(h, &h->d_piv_cluster, pc, s));
-            GCA_TRY(dalloc(h, &h->d_pq32, (size_t)h->n_piv_total * p->q_r * p->q_r * 4));
+            GCA_TRY(dalloc(h, &h->d_pq32, (size_t)h->n_piv_total * h->prm.q_c * h->prm.q_c * 4));
             GCA_HIP_TRY(launch_pivot_points(h, s));
         }
     }
@@ -1100,6 +1105,7 @@ void gca_params_default(gca_params *p)
     p->q_r = 3;
     p->q_nr = 3;
     p->q_s = 4;
+    p->q_c = 3;
 }
 
 const char *gca_last_error(void) { return last_error_cstr(); }
@@ -1420,6 +1426,7 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
     GCA_HIP_TRY(launch_local_points(h, s));
     if (h->d_qnr != h->d_qr) GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
     if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, h->d_qA));
+    if (h->d_qc != h->d_qr) GCA_TRY(tri_pts(h->prm.q_c, h->d_qc));
     if (h->n_piv_total > 0) GCA_HIP_TRY(launch_pivot_points(h, s));
     h->fz.basis_current = false;
     GCA_HIP_TRY(launch_frozen_basis(h, s));

@@ -231,6 +231,7 @@ struct gca_h2_s {
     double *d_qr = nullptr;          // n x Pr x 4 (x, y, z, w*J), regular rule
     double *d_qnr = nullptr;         // n x Pnr x 4, near-regular rule
     double *d_qA = nullptr;          // n x PA x 4 (may alias d_qr)
+    double *d_qc = nullptr;          // n x Pc x 4, coupling rule (may alias d_qr)
     double *d_cent = nullptr;        // n x 4: reference point per triangle (mean of its d_qr points)
     float *d_qloc32 = nullptr;       // n x Pr x 4: d_qr points relative to it (FP32), weights
     double *d_box = nullptr;         // nc x 8: lo, hi, diam, 0

@@ -654,7 +654,10 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
     const Rule RA = make_rule(gx, gw, h->prm.q_A);
     const Rule Rs = make_rule(h->gs_x, h->gs_w, h->prm.q_s);
     const Rule Rg = make_rule(h->gl_x, h->gl_w, h->prm.green_m);
+    gauss_legendre01(h->prm.q_c, gx, gw);
+    const Rule Rc = make_rule(gx, gw, h->prm.q_c);
     const int Pr = h->prm.q_r * h->prm.q_r;
+    const int Pc = h->prm.q_c * h->prm.q_c;
     hipError_t e;
     // (i) nearfield blocks, both orientations
     {
@@ -687,7 +690,7 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
         a.slot = h->d_far_slot;
         a.node = h->d_node;
         a.box = h->d_box;
-        a.q = h->d_qr;
+        a.q = h->d_qc;
         a.xyz = h->d_xyz;
         a.tv = h->d_tv;
         a.piv = h->d_piv;
@@ -697,9 +700,9 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
         a.cb = xb;
         a.nblk = nb;
         a.cw = 64;
-        a.R = Rr;
+        a.R = Rc;
         a.gout = w.gfar;
-        if ((e = launch_grad_blocks_P<T, false>(Pr, a, s)) != hipSuccess) return e;
+        if ((e = launch_grad_blocks_P<T, false>(Pc, a, s)) != hipSuccess) return e;
     }
     // touching and near-regular lists (FP64)
     for (int kind = 0; kind < 3; ++kind) {

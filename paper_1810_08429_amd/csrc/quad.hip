@@ -593,12 +593,12 @@ __global__ void k_pivot_points(const int32_t *piv_cluster, const int32_t *piv, c
 
 hipError_t launch_pivot_points(gca_h2_s *h, hipStream_t s)
 {
-    const int P = h->prm.q_r * h->prm.q_r;
+    const int P = h->prm.q_c * h->prm.q_c;
     const int64_t ne = h->n_piv_total;
     if (ne == 0) return hipSuccess;
     const int64_t total = ne * P;
     hipLaunchKernelGGL(k_pivot_points, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, h->d_piv_cluster,
-                       h->d_piv, h->d_box, h->d_qr, P, ne, h->d_pq32);
+                       h->d_piv, h->d_box, h->d_qc, P, ne, h->d_pq32);
     return hipGetLastError();
 }
 
@@ -673,7 +673,7 @@ static hipError_t far_rows(gca_h2_s *h, const T *xh, T *cpart, T *store, hipStre
     const int ng = h->n_far_groups;
     if (ng == 0) return hipSuccess;
     if (STORE ? store == nullptr : (xh == nullptr || cpart == nullptr)) return hipErrorInvalidValue;
-    const int P = h->prm.q_r * h->prm.q_r;
+    const int P = h->prm.q_c * h->prm.q_c;   // the coupling rule
     constexpr bool EXP = sizeof(T) == 4;
     FarArgs<T> a{};
     a.g_t = h->d_fg_t;
@@ -686,7 +686,7 @@ static hipError_t far_rows(gca_h2_s *h, const T *xh, T *cpart, T *store, hipStre
     a.piv_off = h->d_piv_off;
     a.piv = h->d_piv;
     a.box = h->d_box;
-    a.q = h->d_qr;
+    a.q = h->d_qc;
     a.pq32 = h->d_pq32;
     a.xh = xh;
     a.part = cpart;

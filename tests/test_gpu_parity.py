@@ -197,3 +197,30 @@ def test_larger_sphere_sampled_rows(torch, gca, orc):
     Ym = H.matvec(torch.tensor(X, device="cuda"), precision=gca.MIXED).cpu().numpy()
     relm = np.linalg.norm(Ym[rows] - ref) / np.linalg.norm(ref)
     assert relm < 1e-4, relm
+
+
+def test_coupling_rule_order_matches_oracle(torch, gca, orc):
+    """A lower-order regular rule for the coupling entries G|t~ x s~ only
+    (q_c = 2): the GPU product equals the oracle's GCA-H^2 built with the same
+    coupling rule, and stays within the compression tolerance of the dense
+    matrix on this mesh."""
+    base = synth.icosphere(3)
+    m = synth.jitter(base, 0.02 * synth.mean_edge_length(base), seed=7)
+    ent = orc.Entries(m.verts, m.tris, *orders(gca))
+    ho = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, m=3, eps=1e-5, ent=ent,
+                    q=orders(gca), q_c=2)
+    x = synth.rhs_normal(m.nt, 1, seed=3)
+    yo = orc.h2_matvec(ho, x)
+    for qc in (2,):
+        H = build(gca, m, 32, eta=2.0, eps=1e-5, q_c=qc)
+        y = H.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert np.linalg.norm(y - yo) / np.linalg.norm(yo) < 1e-10
+        ym = H.matvec(torch.tensor(x, device="cuda"), precision=gca.MIXED).cpu().numpy()
+        assert np.linalg.norm(ym - yo) / np.linalg.norm(yo) < 2e-5
+    yd = ent.dense() @ x
+    assert np.linalg.norm(yo - yd) / np.linalg.norm(yd) < 1e-3
+    # q_c = 0 means "the regular order": identical to the default build
+    H0 = build(gca, m, 32, eta=2.0, eps=1e-5, q_c=0)
+    H3 = build(gca, m, 32, eta=2.0, eps=1e-5, q_c=orders(gca)[0])
+    xt = torch.tensor(x, device="cuda")
+    assert torch.equal(H0.matvec(xt), H3.matvec(xt))

@@ -114,7 +114,7 @@ def test_invalid_meshes_are_rejected(gca):
 
 @pytest.mark.parametrize("field,value", [("eta", 0.0), ("eta", float("inf")), ("eps", -1.0), ("eps", 1.0),
                                          ("green_m", 0), ("green_m", 7), ("q_s", 1), ("q_r", 0),
-                                         ("q_nr", 8), ("omega_scale", 0.0)])
+                                         ("q_nr", 8), ("omega_scale", 0.0), ("q_c", 7), ("q_c", -1)])
 def test_invalid_parameters_are_rejected_before_device_work(gca, field, value):
     m = synth.icosphere(1)
     tree = gca.Tree(m.verts, m.tris, 8)

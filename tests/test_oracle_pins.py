@@ -469,6 +469,38 @@ def test_h2_error_follows_tolerance(orc, sphere3_dense):
     assert h.far
 
 
+def test_coupling_rule_order_changes_only_admissible_blocks(orc, sphere3_dense):
+    """The coupling matrices G|t~ x s~ (Section 4) are Galerkin entries of
+    well-separated pairs; evaluating them with a lower regular order q_c = 2
+    changes the assembled matrix on admissible blocks only, by no more than the
+    quadrature error of such pairs, and q_c equal to the regular order is the
+    default build."""
+    m, e, G = sphere3_dense
+    h3 = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, eps=1e-6, ent=e)
+    hs = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, eps=1e-6, ent=e, q_c=3)
+    assert hs.ent_c is None
+    h2 = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, eps=1e-6, ent=e, q_c=2)
+    D3, D2 = orc.h2_dense(h3), orc.h2_dense(h2)
+    tree = h3.tree
+    for (t, s) in h3.near:
+        ix = np.ix_(tree.indices(t), tree.indices(s))
+        assert np.array_equal(D3[ix], D2[ix])
+    changed = 0.0
+    for (t, s) in h3.far:
+        ix = np.ix_(tree.indices(t), tree.indices(s))
+        # an order-6 rule stands in for the exact integral of a separated pair
+        changed = max(changed, np.abs(D3[ix] - D2[ix]).max())
+    assert changed > 0
+    e6 = orc.Entries(m.verts, m.tris, 6, 5, 4)
+    t, s = h3.far[0]
+    Pt, Ps = h2.pivots[t], h2.pivots[s]
+    Bx = e6.block(Pt, Ps)
+    assert np.abs(h2.coupling(t, s) - Bx).max() < 1e-3 * np.abs(Bx).max()
+    assert np.abs(h3.coupling(t, s) - Bx).max() < np.abs(h2.coupling(t, s) - Bx).max()
+    nG = np.linalg.norm(G)
+    assert np.linalg.norm(D2 - G) < 1e-3 * nG
+
+
 def test_h2_nested_basis_matches_direct_interpolation(orc, sphere3_dense):
     """Section 4: V_tau = diag(V_tau1, V_tau2) V^_tau, so the expanded basis is
     the identity on the pivot rows tau~ and V_tau G|tau~ x sigma^ approximates
