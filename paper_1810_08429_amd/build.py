@@ -39,6 +39,12 @@ def _compile(args):
     return src
 
 
+# MFMA results and accumulators in ordinary VGPRs: the point-pair kernels
+# feed every MFMA result straight into VALU work, which AGPR results would
+# first have to be copied out for
+MFMA_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+
+
 def build(verbose: bool = False, jobs: int = 4, out: str = None, defines=()) -> str:
     """Compile and link libgca.so (to `out`, default the package directory);
     `defines` are extra -D flags for tuning variants."""
@@ -49,7 +55,7 @@ def build(verbose: bool = False, jobs: int = 4, out: str = None, defines=()) -> 
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
               "-I" + os.path.join(HERE, "..", "include")] + ["-D" + d for d in defines]
     hip_flags = ["-x", "hip", "--offload-arch=gfx950",
-                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *MFMA_FLAGS]
     tasks = []
     objs = []
     for src in HIP_SOURCES:
@@ -79,7 +85,7 @@ def build(verbose: bool = False, jobs: int = 4, out: str = None, defines=()) -> 
     probe_src = os.path.join(HERE, "probe", "alu_probe.hip")
     probe_bin = os.path.join(HERE, "probe", "alu_probe")
     r = subprocess.run([hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",
-                        "-Xclang", "-packed-fp32-ops", probe_src, "-o", probe_bin + ".tmp"],
+                        "-Xclang", "-packed-fp32-ops", *MFMA_FLAGS, probe_src, "-o", probe_bin + ".tmp"],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"building the ALU probe failed:\n{r.stderr}")

@@ -73,29 +73,26 @@ struct alignas(4 * sizeof(T)) Q4 {
 __host__ __device__ constexpr size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 // LDS layout of the block kernel (byte offsets, 16-byte aligned sections):
-//   mask[rmax] u64 (NEAR) | rowp[rmax][P] Q4 | rown[rmax][P] (EXP) |
-//   colp[CW][P] Q4 | coln[CW][P] (EXP) | xr[rmax] | xc[CW] |
+//   mask[rmax] u64 (NEAR) | rowp[rmax][P] Q4 | rown[rmax][P] |
+//   colp[CW][P] Q4 | coln[CW][P] | xr[rmax] | xc[CW] |
 //   racc[4][rmax] | cacc[4][CW]
-// EXP (the FP32 coupling blocks) stores squared norms for the expanded
-// distance |x - y|^2 = |x|^2 + |y|^2 - 2 x.y.
+// rown / coln are the squared norms of the expanded distance
+// |x - y|^2 = |x|^2 + |y|^2 - 2 x.y.
 template <typename T>
 struct BlkLayout {
-    size_t mask, rowp, rown, colp, coln, xr, xc, racc, cacc, rowc, colc, total;
-    // loc: per-triangle reference points rowc[rmax], colc[CW] (Q4) as well
-    __host__ __device__ BlkLayout(int rmax, int P, int CW, bool near, bool exp, bool loc = false)
+    size_t mask, rowp, rown, colp, coln, xr, xc, racc, cacc, total;
+    __host__ __device__ BlkLayout(int rmax, int P, int CW, bool near)
     {
         mask = 0;
         rowp = mask + (near ? al16((size_t)rmax * 8) : 0);
         rown = rowp + al16((size_t)rmax * P * sizeof(Q4<T>));
-        colp = rown + (exp ? al16((size_t)rmax * P * sizeof(T)) : 0);
+        colp = rown + al16((size_t)rmax * P * sizeof(T));
         coln = colp + al16((size_t)CW * P * sizeof(Q4<T>));
-        xr = coln + (exp ? al16((size_t)CW * P * sizeof(T)) : 0);
+        xr = coln + al16((size_t)CW * P * sizeof(T));
         xc = xr + al16((size_t)rmax * sizeof(T));
         racc = xc + al16((size_t)CW * sizeof(T));
         cacc = racc + al16((size_t)BLK_WAVES * rmax * sizeof(T));
-        rowc = cacc + al16((size_t)BLK_WAVES * CW * sizeof(T));
-        colc = rowc + (loc ? al16((size_t)rmax * sizeof(Q4<T>)) : 0);
-        total = colc + (loc ? al16((size_t)CW * sizeof(Q4<T>)) : 0);
+        total = cacc + al16((size_t)BLK_WAVES * CW * sizeof(T));
     }
 };
 
@@ -107,85 +104,33 @@ template <>
 __device__ __forceinline__ double fmat<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // sum over the collapsed rules of both triangles of w_a w_b / |x_a - y_b|,
-// row points in registers, column points from LDS
-template <typename T, int P, bool EXP>
-__device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[EXP ? P : 1], const Q4<T> *cp,
-                                        const T *cn)
+// row points and their squared norms in registers, column points (scaled by
+// -2) and their squared norms from LDS:
+//     |x_a - y_b|^2 = (|x_a|^2 + |y_b|^2) + x_a . (-2 y_b)
+// one add and three FMAs per point pair.  All coordinates are relative to
+// the row cluster's box centre, so the cancellation is bounded by
+// (|x|^2 + |y|^2) / |x - y|^2, a few hundred at most for the regular pairs of
+// nearfield blocks and far less for admissible ones.
+template <typename T, int P>
+__device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[P], const Q4<T> *cp, const T *cn)
 {
     T acc = 0;
 #pragma unroll
     for (int pb = 0; pb < P; ++pb) {
         const Q4<T> c = cp[pb];
+        const T ny = cn[pb];
         T inner = 0;
-        if (EXP) {
-            const T ny = cn[pb];
 #pragma unroll
-            for (int pa = 0; pa < P; ++pa) {
-                T r2 = rn[EXP ? pa : 0] + ny;
-                r2 = fmat(rp[pa].z, c.z, r2);
-                r2 = fmat(rp[pa].y, c.y, r2);
-                r2 = fmat(rp[pa].x, c.x, r2);
-                inner = fmat(rp[pa].w, rsq<T>(r2), inner);
-            }
-        } else {
-#pragma unroll
-            for (int pa = 0; pa < P; ++pa) {
-                const T dx = rp[pa].x - c.x, dy = rp[pa].y - c.y, dz = rp[pa].z - c.z;
-                const T r2 = fmat(dz, dz, fmat(dy, dy, dx * dx));
-                inner = fmat(rp[pa].w, rsq<T>(r2), inner);
-            }
+        for (int pa = 0; pa < P; ++pa) {
+            T r2 = rn[pa] + ny;
+            r2 = fmat(rp[pa].z, c.z, r2);
+            r2 = fmat(rp[pa].y, c.y, r2);
+            r2 = fmat(rp[pa].x, c.x, r2);
+            inner = fmat(rp[pa].w, rsq<T>(r2), inner);
         }
         acc = fmat(c.w, inner, acc);
     }
     return acc;
-}
-
-// Entry with per-triangle reference points (FP32 nearfield): x_a = c_i + a,
-// y_b = c_j + b, d = c_i - c_j, m = -2 b:
-//     |x_a - y_b|^2 = |d + a|^2 + (|b|^2 + m.d) + a.m
-// The first two terms are formed once per entry (9 + 9 values), the last
-// costs three FMAs per evaluation; all magnitudes are those of the pair's
-// own geometry, so the cancellation stays that of the pair's distance.
-template <int P>
-__device__ __forceinline__ float entry_loc(const Q4<float> (&rp)[P], const float (&rn)[P], const Q4<float> ci,
-                                           const Q4<float> *cp, const float *cn, const Q4<float> cj)
-{
-    const float dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-    const float dd = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-    const float ex = 2 * dx, ey = 2 * dy, ez = 2 * dz;
-    float al[P];
-#pragma unroll
-    for (int pa = 0; pa < P; ++pa)
-        al[pa] = __builtin_fmaf(ex, rp[pa].x, __builtin_fmaf(ey, rp[pa].y, __builtin_fmaf(ez, rp[pa].z, rn[pa] + dd)));
-    float acc = 0;
-#pragma unroll
-    for (int pb = 0; pb < P; ++pb) {
-        const Q4<float> c = cp[pb];
-        const float be = __builtin_fmaf(c.x, dx, __builtin_fmaf(c.y, dy, __builtin_fmaf(c.z, dz, cn[pb])));
-        float inner = 0;
-#pragma unroll
-        for (int pa = 0; pa < P; ++pa) {
-            float r2 = al[pa] + be;
-            r2 = __builtin_fmaf(rp[pa].z, c.z, r2);
-            r2 = __builtin_fmaf(rp[pa].y, c.y, r2);
-            r2 = __builtin_fmaf(rp[pa].x, c.x, r2);
-            inner = __builtin_fmaf(rp[pa].w, rsq<float>(r2), inner);
-        }
-        acc = __builtin_fmaf(c.w, inner, acc);
-    }
-    return acc;
-}
-
-template <typename T, int P, bool EXP, bool LOC>
-__device__ __forceinline__ T entry_dispatch(const Q4<T> (&rr)[P], const T (&rq)[(EXP || LOC) ? P : 1], const Q4<T> rc,
-                                            const Q4<T> *colp, const T *coln, const Q4<T> *colc, int j)
-{
-    if constexpr (LOC) {
-        return entry_loc<P>(rr, rq, rc, colp + (size_t)j * P, coln + (size_t)j * P, colc[j]);
-    } else {
-        return block_entry<T, P, EXP>(rr, reinterpret_cast<const T(&)[EXP ? P : 1]>(rq), colp + (size_t)j * P,
-                                      coln + (size_t)j * P);
-    }
 }
 
 // One pass over the entries of an rw x cw chunk (rows in rowp/rown, columns
@@ -197,11 +142,10 @@ __device__ __forceinline__ T entry_dispatch(const Q4<T> (&rr)[P], const T (&rq)[
 // over the C lanes of a tile row by shuffles) and g_ij x_i to cacc[j] (over
 // the R lanes of a tile column); racc and cacc belong to the calling
 // wavefront.  MASK skips the pairs whose bit c0 + j is set in mask[i].
-template <typename T, int P, bool EXP, bool MASK, bool STORE, bool LOC = false>
+template <typename T, int P, bool MASK, bool STORE>
 __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *rowp, const T *rown,
                                           const Q4<T> *colp, const T *coln, const T *xr, const T *xc,
-                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld,
-                                          const Q4<T> *rowc = nullptr, const Q4<T> *colc = nullptr)
+                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
@@ -224,8 +168,7 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
     const int k1 = MASK ? best_n : ((wv + 1) * best_n) / BLK_WAVES;
     const int kstep = MASK ? BLK_WAVES : 1;
     Q4<T> rr[P];
-    T rq[(EXP || LOC) ? P : 1];
-    Q4<T> rc{};
+    T rq[P];
     int cur_tr = -1;
     for (int k = k0; k < k1; k += kstep) {
         const int tr = k / nct, tc = k - tr * nct;
@@ -236,22 +179,21 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 rr[p] = rowp[(size_t)il * P + p];
-                if (EXP || LOC) rq[(EXP || LOC) ? p : 0] = rown[(size_t)il * P + p];
+                rq[p] = rown[(size_t)il * P + p];
             }
-            if (LOC) rc = rowc[il];
         }
         const bool valid = i < rw && j < cw;
         if (STORE) {
             // entries go to memory (masked ones as zeros) instead of into products
             T g = 0;
             if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1)))
-                g = entry_dispatch<T, P, EXP, LOC>(rr, rq, rc, colp, coln, colc, j) * (T)INV4PI;
+                g = block_entry<T, P>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
             if (valid) st[(int64_t)i * ld + j] = g;
             continue;
         }
         T v = 0, u = 0;
         if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1))) {
-            const T g = entry_dispatch<T, P, EXP, LOC>(rr, rq, rc, colp, coln, colc, j) * (T)INV4PI;
+            const T g = block_entry<T, P>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
             v = g * xc[j];
             u = g * xr[i];
         }
@@ -275,7 +217,7 @@ constexpr int BLK_FP64_WAVES = 4;
 // workgroup.  Row partials  sum_k g_ik x_k  go to part[g_rslot + i], the
 // column partial of column k to part[col_out[k]] (one writer each).
 // Coordinates are taken relative to the centre c_t of t's box.  The FP32 path
-// (EXP) reads the pivots' points from pq32, stored relative to their own
+// reads the pivots' points from pq32, stored relative to their own
 // cluster's centre, and shifts the columns by c_s - c_t (FP64 difference,
 // rounded once); admissibility keeps |x - y| >= dist(t, s) >= diam / (2 eta),
 // so the cancellation in |x|^2 + |y|^2 - 2 x.y stays within a few dozen FP32
@@ -308,7 +250,7 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
     k_far_rows(FarArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr bool EXP = sizeof(T) == 4;
+    constexpr bool F32 = sizeof(T) == 4;
     const int g = blockIdx.x;
     const int tid = threadIdx.x, wv = tid >> 6;
     const int t = a.g_t[g];
@@ -318,7 +260,7 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
     const int64_t xro = a.piv_off[t];
     const int64_t rslot = a.g_rslot[g];
     const int rmax = a.rmax, CW = a.cw;
-    const BlkLayout<T> L(rmax, P, CW, false, EXP);
+    const BlkLayout<T> L(rmax, P, CW, false);
     Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
     T *rown = reinterpret_cast<T *>(smem + L.rown);
     Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
@@ -338,13 +280,15 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
         if (r0 > 0) __syncthreads();
         for (int e = tid; e < rw * P; e += BLK_THREADS) {
             const int i = e / P, p = e - i * P;
-            if (EXP) {
+            if (F32) {
                 const float4 v = reinterpret_cast<const float4 *>(a.pq32)[(size_t)(xro + r0 + i) * P + p];
                 rowp[e] = Q4<T>{(T)v.x, (T)v.y, (T)v.z, (T)v.w};
                 rown[e] = (T)(v.x * v.x + v.y * v.y + v.z * v.z);
             } else {
                 const double *src = a.q + ((size_t)a.piv[xro + r0 + i] * P + p) * 4;
-                rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+                const T x = (T)(src[0] - cx), y = (T)(src[1] - cy), z = (T)(src[2] - cz);
+                rowp[e] = Q4<T>{x, y, z, (T)src[3]};
+                rown[e] = x * x + y * y + z * z;
             }
         }
         // the store variant gets no vectors (xh is null there)
@@ -357,7 +301,7 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
                 const int j = e / P, p = e - j * P;
                 const int64_t k = kb + c0 + j;
                 const int ce = a.col_e[k];
-                if (EXP) {
+                if (F32) {
                     const int cs = a.col_s[k];
                     const float ox = (float)(0.5 * (a.box[8 * cs + 0] + a.box[8 * cs + 3]) - cx);
                     const float oy = (float)(0.5 * (a.box[8 * cs + 1] + a.box[8 * cs + 4]) - cy);
@@ -368,13 +312,15 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
                     coln[e] = (T)(y0 * y0 + y1 * y1 + y2 * y2);
                 } else {
                     const double *src = a.q + ((size_t)a.piv[ce] * P + p) * 4;
-                    colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
+                    const T y0 = (T)(src[0] - cx), y1 = (T)(src[1] - cy), y2 = (T)(src[2] - cz);
+                    colp[e] = Q4<T>{-2 * y0, -2 * y1, -2 * y2, (T)src[3]};
+                    coln[e] = y0 * y0 + y1 * y1 + y2 * y2;
                 }
             }
             if (!STORE)
                 for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xh[a.col_e[kb + c0 + j]];
             __syncthreads();
-            tile_pass<T, P, EXP, false, STORE>(rw, cw, 0, rowp, rown, colp, coln, xr, xc, nullptr, racc + wv * rmax,
+            tile_pass<T, P, false, STORE>(rw, cw, 0, rowp, rown, colp, coln, xr, xc, nullptr, racc + wv * rmax,
                                                cacc + wv * CW,
                                                STORE ? a.store + a.g_soff[g] + (int64_t)r0 * nc + c0 : nullptr, nc);
             __syncthreads();
@@ -455,9 +401,10 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
     const int64_t rslot = a.g_rslot[g];
     const uint64_t *gm = a.mask + a.g_moff[g];
     const int rmax = a.rmax;
-    // FP32: per-triangle reference points (entry_loc); FP64: direct differences
-    constexpr bool LOC = sizeof(T) == 4;
-    const BlkLayout<T> L(rmax, P, CW, true, LOC, LOC);
+    // expanded distances around t's box centre in both precisions; the FP32
+    // points are formed from each triangle's reference point (FP64 offset to
+    // the centre, rounded once) plus its FP32 local points
+    const BlkLayout<T> L(rmax, P, CW, true);
     uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
     Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
     T *rown = reinterpret_cast<T *>(smem + L.rown);
@@ -467,30 +414,28 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
     T *xc = reinterpret_cast<T *>(smem + L.xc);
     T *racc = reinterpret_cast<T *>(smem + L.racc);
     T *cacc = reinterpret_cast<T *>(smem + L.cacc);
-    Q4<T> *rowc = reinterpret_cast<Q4<T> *>(smem + L.rowc);
-    Q4<T> *colc = reinterpret_cast<Q4<T> *>(smem + L.colc);
     const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
     const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
     const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
-    // reference point of triangle `pos` relative to t's box centre
-    auto refpt = [&](int pos) {
-        const double *c = a.cent + 4 * (size_t)pos;
-        return Q4<T>{(T)(c[0] - cx), (T)(c[1] - cy), (T)(c[2] - cz), (T)0};
+    // point p of triangle `pos` relative to t's box centre, and its weight
+    auto point = [&](int pos, int p) {
+        if constexpr (sizeof(T) == 4) {
+            const double *c = a.cent + 4 * (size_t)pos;
+            const float4 v = reinterpret_cast<const float4 *>(a.qloc)[(size_t)pos * P + p];
+            return Q4<T>{(T)(c[0] - cx) + v.x, (T)(c[1] - cy) + v.y, (T)(c[2] - cz) + v.z, v.w};
+        } else {
+            const double *src = a.q + ((size_t)pos * P + p) * 4;
+            return Q4<T>{src[0] - cx, src[1] - cy, src[2] - cz, src[3]};
+        }
     };
 
     for (int e = tid; e < BLK_WAVES * rmax; e += BLK_THREADS) racc[e] = 0;
     for (int e = tid; e < BLK_WAVES * CW; e += BLK_THREADS) cacc[e] = 0;
     for (int e = tid; e < nr * P; e += BLK_THREADS) {
         const int i = e / P, p = e - i * P;
-        if (LOC) {
-            const float4 v = reinterpret_cast<const float4 *>(a.qloc)[(size_t)(rb + i) * P + p];
-            rowp[e] = Q4<T>{(T)v.x, (T)v.y, (T)v.z, (T)v.w};
-            rown[e] = (T)(v.x * v.x + v.y * v.y + v.z * v.z);
-            if (p == 0) rowc[i] = refpt(rb + i);
-        } else {
-            const double *src = a.q + ((size_t)(rb + i) * P + p) * 4;
-            rowp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
-        }
+        const Q4<T> v = point(rb + i, p);
+        rowp[e] = v;
+        rown[e] = v.x * v.x + v.y * v.y + v.z * v.z;
     }
     // the store variant gets no vectors (xp is null there)
     if (!STORE)
@@ -501,24 +446,16 @@ __global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES :
         __syncthreads();
         for (int e = tid; e < cw * P; e += BLK_THREADS) {
             const int j = e / P, p = e - j * P;
-            const int pos = a.col_pos[kb + c0 + j];
-            if (LOC) {
-                const float4 v = reinterpret_cast<const float4 *>(a.qloc)[(size_t)pos * P + p];
-                colp[e] = Q4<T>{(T)(-2 * v.x), (T)(-2 * v.y), (T)(-2 * v.z), (T)v.w};
-                coln[e] = (T)(v.x * v.x + v.y * v.y + v.z * v.z);
-                if (p == 0) colc[j] = refpt(pos);
-            } else {
-                const double *src = a.q + ((size_t)pos * P + p) * 4;
-                colp[e] = Q4<T>{(T)(src[0] - cx), (T)(src[1] - cy), (T)(src[2] - cz), (T)src[3]};
-            }
+            const Q4<T> v = point(a.col_pos[kb + c0 + j], p);
+            colp[e] = Q4<T>{-2 * v.x, -2 * v.y, -2 * v.z, v.w};
+            coln[e] = v.x * v.x + v.y * v.y + v.z * v.z;
         }
         if (!STORE)
             for (int j = tid; j < cw; j += BLK_THREADS) xc[j] = a.xp[a.col_pos[kb + c0 + j]];
         for (int i = tid; i < nr; i += BLK_THREADS) mask[i] = gm[(size_t)ch * nr + i];
         __syncthreads();
-        tile_pass<T, P, false, true, STORE, LOC>(nr, cw, cb, rowp, rown, colp, coln, xr, xc, mask,
-                                                 racc + wv * rmax, cacc + wv * CW,
-                                                 STORE ? a.store + a.g_soff[g] + c0 : nullptr, nc, rowc, colc);
+        tile_pass<T, P, true, STORE>(nr, cw, cb, rowp, rown, colp, coln, xr, xc, mask, racc + wv * rmax,
+                                           cacc + wv * CW, STORE ? a.store + a.g_soff[g] + c0 : nullptr, nc);
         __syncthreads();
         if (STORE) continue;
         for (int j = tid; j < cw; j += BLK_THREADS) {
@@ -603,9 +540,9 @@ hipError_t launch_pivot_points(gca_h2_s *h, hipStream_t s)
 }
 
 template <typename T>
-static size_t blk_smem(int rmax, int P, int cw, bool near, bool exp)
+static size_t blk_smem(int rmax, int P, int cw, bool near)
 {
-    return BlkLayout<T>(rmax, P, cw, near, exp).total;
+    return BlkLayout<T>(rmax, P, cw, near).total;
 }
 
 // LDS budget per workgroup of the block kernel: the widest column chunk
@@ -613,12 +550,12 @@ static size_t blk_smem(int rmax, int P, int cw, bool near, bool exp)
 // chunks against more resident workgroups per CU (160 KB of LDS each).
 constexpr int BLK_LDS_KB = 40;
 template <typename T>
-static int blk_cw(int rmax, int P, bool near, bool exp)
+static int blk_cw(int rmax, int P, bool near)
 {
     for (int cw = 128; cw >= 8; cw -= 8)
-        if (blk_smem<T>(rmax, P, cw, near, exp) <= BLK_LDS_KB * 1024) return cw;
+        if (blk_smem<T>(rmax, P, cw, near) <= BLK_LDS_KB * 1024) return cw;
     for (int cw = 64; cw >= 8; cw -= 8)
-        if (blk_smem<T>(rmax, P, cw, near, exp) <= 64 * 1024) return cw;
+        if (blk_smem<T>(rmax, P, cw, near) <= 64 * 1024) return cw;
     return 0;
 }
 
@@ -649,10 +586,9 @@ static hipError_t near_rows(gca_h2_s *h, const T *xp, T *npart, T *store, hipStr
     a.ng = ng;
     a.rmax = h->max_leaf;
     if (a.rmax > 64) return hipErrorInvalidValue;
-    constexpr bool LOC = sizeof(T) == 4;
     a.cw = NEAR_CW;
-    while (a.cw > 8 && BlkLayout<T>(a.rmax, P, a.cw, true, LOC, LOC).total > 64 * 1024) a.cw /= 2;
-    const size_t sm = BlkLayout<T>(a.rmax, P, a.cw, true, LOC, LOC).total;
+    while (a.cw > 8 && BlkLayout<T>(a.rmax, P, a.cw, true).total > 64 * 1024) a.cw /= 2;
+    const size_t sm = BlkLayout<T>(a.rmax, P, a.cw, true).total;
     if (sm > 64 * 1024) return hipErrorInvalidValue;
     switch (P) {
 #define CASE(PP)                                                                              \
@@ -674,7 +610,6 @@ static hipError_t far_rows(gca_h2_s *h, const T *xh, T *cpart, T *store, hipStre
     if (ng == 0) return hipSuccess;
     if (STORE ? store == nullptr : (xh == nullptr || cpart == nullptr)) return hipErrorInvalidValue;
     const int P = h->prm.q_c * h->prm.q_c;   // the coupling rule
-    constexpr bool EXP = sizeof(T) == 4;
     FarArgs<T> a{};
     a.g_t = h->d_fg_t;
     a.g_ptr = h->d_fg_ptr;
@@ -694,9 +629,9 @@ static hipError_t far_rows(gca_h2_s *h, const T *xh, T *cpart, T *store, hipStre
     a.g_soff = h->d_fg_soff;
     a.ng = ng;
     a.rmax = std::max(1, std::min(64, h->max_rank));
-    a.cw = blk_cw<T>(a.rmax, P, false, EXP);
+    a.cw = blk_cw<T>(a.rmax, P, false);
     if (a.cw == 0) return hipErrorInvalidValue;
-    const size_t sm = blk_smem<T>(a.rmax, P, a.cw, false, EXP);
+    const size_t sm = blk_smem<T>(a.rmax, P, a.cw, false);
     switch (P) {
 #define CASE(PP)                                                                              \
     case PP:                                                                                  \
