@@ -115,8 +115,7 @@ template <typename T, int P>
 __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[P], const Q4<T> *cp, const T *cn)
 {
     T acc = 0;
-#pragma unroll
-    for (int pb = 0; pb < P; ++pb) {
+    auto column_point = [&](int pb) {
         const Q4<T> c = cp[pb];
         const T ny = cn[pb];
         T inner = 0;
@@ -129,51 +128,128 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[P],
             inner = fmat(rp[pa].w, rsq<T>(r2), inner);
         }
         acc = fmat(c.w, inner, acc);
+    };
+    // rules up to 3 x 3 points fully unrolled; larger ones keep the column
+    // loop (code size)
+    if constexpr (P <= 9) {
+#pragma unroll
+        for (int pb = 0; pb < P; ++pb) column_point(pb);
+    } else {
+#pragma unroll 1
+        for (int pb = 0; pb < P; ++pb) column_point(pb);
     }
     return acc;
 }
 
-// One pass over the entries of an rw x cw chunk (rows in rowp/rown, columns
-// in colp/coln, both in LDS): tiles of R x C = 64 lanes (C = 4 .. 64 picked
-// for the fewest tile rounds over the 4 wavefronts, then the fewest tiles).
-// Without a mask each wavefront takes a contiguous run of the row-major tile
-// list, so its consecutive tiles mostly share their rows, which stay in
-// registers until the tile row changes.  Entry g_ij contributes g_ij x_j to racc[i] (summed
-// over the C lanes of a tile row by shuffles) and g_ij x_i to cacc[j] (over
-// the R lanes of a tile column); racc and cacc belong to the calling
-// wavefront.  MASK skips the pairs whose bit c0 + j is set in mask[i].
-template <typename T, int P, bool MASK, bool STORE>
-__device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *rowp, const T *rown,
-                                          const Q4<T> *colp, const T *coln, const T *xr, const T *xc,
-                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld)
+// Cross-lane moves for the tile reductions: DPP within a row of 16 lanes, an
+// LDS swizzle for lane ^ 16 and a permute for lane ^ 32 (64-bit values move
+// as two 32-bit halves).  Every lane of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
-    for (int l = 2; l <= 6; ++l) {
-        const int R = 64 >> l;
-        const int n = ((rw + R - 1) / R) * ((cw + (1 << l) - 1) >> l);
-        const int rounds = (n + BLK_WAVES - 1) / BLK_WAVES;
-        if (rounds < best_r || (rounds == best_r && n < best_n)) {
-            best_r = rounds;
-            best_n = n;
-            lc = l;
-        }
-    }
-    const int C = 1 << lc, R = 64 >> lc;
-    const int ii = lane >> lc, jj = lane & (C - 1);
-    const int nct = (cw + C - 1) >> lc;
-    // masked passes interleave the tiles over the wavefronts instead, so that
-    // fully masked tiles (skipped at no cost) are spread evenly
-    const int k0 = MASK ? wv : (wv * best_n) / BLK_WAVES;
-    const int k1 = MASK ? best_n : ((wv + 1) * best_n) / BLK_WAVES;
-    const int kstep = MASK ? BLK_WAVES : 1;
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const int2 h = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, int2{__builtin_amdgcn_update_dpp(0, h.x, CTRL, 0xF, 0xF, false),
+                                           __builtin_amdgcn_update_dpp(0, h.y, CTRL, 0xF, 0xF, false)});
+}
+__device__ __forceinline__ float xor16_mov(float v)
+{   // ds_swizzle bit mode within 32 lanes: and 0x1f, or 0, xor 0x10
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+__device__ __forceinline__ double xor16_mov(double v)
+{
+    const int2 h = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, int2{__builtin_amdgcn_ds_swizzle(h.x, 0x401F),
+                                           __builtin_amdgcn_ds_swizzle(h.y, 0x401F)});
+}
+__device__ __forceinline__ float xor32_mov(float v, int addr)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double xor32_mov(double v, int addr)
+{
+    const int2 h = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, int2{__builtin_amdgcn_ds_bpermute(addr, h.x),
+                                           __builtin_amdgcn_ds_bpermute(addr, h.y)});
+}
+
+// Sum over the N consecutive lanes of each aligned group (N = 1 .. 16); every
+// lane of the group receives the sum.  DPP: lane ^ 1, lane ^ 2, mirror in 8,
+// mirror in 16 -- each step pairs the two halves of the next larger group.
+template <int N, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+    if constexpr (N >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    if constexpr (N >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    if constexpr (N >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+    if constexpr (N >= 16) v += dpp_mov<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Sum over the lanes congruent modulo S (S = 1 .. 32); every lane receives
+// the sum of its class.  Within a row of 16 the class is rotated through
+// (row_ror by 8, 4, .., S), then lane ^ 16 and lane ^ 32 join the rows.
+template <int S, typename T>
+__device__ __forceinline__ T class_sum(T v, int lane)
+{
+    if constexpr (S <= 8) v += dpp_mov<0x128>(v);   // row_ror:8
+    if constexpr (S <= 4) v += dpp_mov<0x124>(v);   // row_ror:4
+    if constexpr (S <= 2) v += dpp_mov<0x122>(v);   // row_ror:2
+    if constexpr (S <= 1) v += dpp_mov<0x121>(v);   // row_ror:1
+    if constexpr (S <= 16) v += xor16_mov(v);
+    v += xor32_mov(v, (lane ^ 32) << 2);
+    return v;
+}
+
+// One pass over the entries of an rw x cw chunk (rows in rowp/rown, columns
+// in colp/coln, both in LDS): tiles of R rows x C columns = 64 lanes (C = 8
+// or 16 picked for the fewest tile rounds over the 4 wavefronts, then the
+// fewest tiles).  Without a mask each wavefront takes a contiguous run of the
+// row-major tile list; masked passes interleave the tiles over the
+// wavefronts, so that fully masked tiles (skipped at no cost) are spread
+// evenly.  Either way consecutive tiles of a wavefront mostly share their
+// rows, which stay in registers until the tile row changes.
+//
+// The lanes of a tile column are R consecutive lanes (row ii = lane % R):
+// entry g_ij adds g_ij x_i to the column sum, reduced over those lanes by
+// DPP and added to cacc[j] once per tile, and g_ij x_j to a per-lane row sum
+// that stays in a register while the tile row is unchanged and is reduced
+// over the C lanes of the row (lanes congruent modulo R) into racc[i] when it
+// changes.  racc and cacc belong to the calling wavefront.  MASK skips the
+// pairs whose bit c0 + j is set in mask[i].  STORE writes the entries
+// (masked ones as zeros) to st[i * ld + j] instead, with the columns on
+// consecutive lanes.
+template <typename T, int P, bool MASK, bool STORE, int LC>
+__device__ __forceinline__ void tile_loop(int rw, int cw, int c0, const Q4<T> *rowp, const T *rown,
+                                          const Q4<T> *colp, const T *coln, const T *xr, const T *xc,
+                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld, int k0,
+                                          int k1, int kstep)
+{
+    constexpr int C = 1 << LC, R = 64 >> LC;
+    const int lane = threadIdx.x & 63;
+    const int ii = STORE ? lane >> LC : lane & (R - 1);
+    const int jj = STORE ? lane & (C - 1) : lane >> (6 - LC);
+    const int nct = (cw + C - 1) >> LC;
     Q4<T> rr[P];
     T rq[P];
+    T vacc = 0;
     int cur_tr = -1;
+    // tile coordinates are wavefront-uniform
+    int tr = k0 / nct, tc = k0 - tr * nct;
+    auto flush_rows = [&]() {
+        const T v = class_sum<R>(vacc, lane);
+        const int i = cur_tr * R + ii;
+        if (jj == 0 && i < rw) racc[i] += v;
+    };
     for (int k = k0; k < k1; k += kstep) {
-        const int tr = k / nct, tc = k - tr * nct;
         const int i = tr * R + ii, j = tc * C + jj;
         if (tr != cur_tr) {
+            if (!STORE && cur_tr >= 0) flush_rows();
+            vacc = 0;
             cur_tr = tr;
             const int il = min(i, rw - 1);
 #pragma unroll
@@ -184,23 +260,59 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
         }
         const bool valid = i < rw && j < cw;
         if (STORE) {
-            // entries go to memory (masked ones as zeros) instead of into products
             T g = 0;
             if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1)))
                 g = block_entry<T, P>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
             if (valid) st[(int64_t)i * ld + j] = g;
-            continue;
+        } else {
+            T u = 0;
+            if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1))) {
+                const T g = block_entry<T, P>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
+                vacc = fmat(g, xc[j], vacc);
+                u = g * xr[i];
+            }
+            u = group_sum<R>(u);
+            if (ii == 0 && j < cw) cacc[j] += u;
         }
-        T v = 0, u = 0;
-        if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1))) {
-            const T g = block_entry<T, P>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
-            v = g * xc[j];
-            u = g * xr[i];
+        tc += kstep;
+        while (tc >= nct) {
+            tc -= nct;
+            ++tr;
         }
-        for (int o = 1; o < C; o <<= 1) v += __shfl_xor(v, o, 64);
-        for (int o = C; o < 64; o <<= 1) u += __shfl_xor(u, o, 64);
-        if (jj == 0 && i < rw) racc[i] += v;
-        if (ii == 0 && j < cw) cacc[j] += u;
+    }
+    if (!STORE && cur_tr >= 0) flush_rows();
+}
+
+template <typename T, int P, bool MASK, bool STORE>
+__device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *rowp, const T *rown,
+                                          const Q4<T> *colp, const T *coln, const T *xr, const T *xc,
+                                          const uint64_t *mask, T *racc, T *cacc, T *st, int64_t ld)
+{
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int lc = 0, best_r = 1 << 30, best_n = 1 << 30;
+    for (int l = 3; l <= 4; ++l) {
+        const int R = 64 >> l;
+        const int n = ((rw + R - 1) / R) * ((cw + (1 << l) - 1) >> l);
+        const int rounds = (n + BLK_WAVES - 1) / BLK_WAVES;
+        if (rounds < best_r || (rounds == best_r && n < best_n)) {
+            best_r = rounds;
+            best_n = n;
+            lc = l;
+        }
+    }
+    const int k0 = MASK ? wv : (wv * best_n) / BLK_WAVES;
+    const int k1 = MASK ? best_n : ((wv + 1) * best_n) / BLK_WAVES;
+    const int kstep = MASK ? BLK_WAVES : 1;
+    // C = 8 or 16 (R = 8 or 4): the two shapes cover the leaf and rank sizes
+    // of the block rows; narrower or wider tiles are not instantiated
+    switch (lc) {
+#define TL(L)                                                                                                  \
+    case L:                                                                                                   \
+        tile_loop<T, P, MASK, STORE, L>(rw, cw, c0, rowp, rown, colp, coln, xr, xc, mask, racc, cacc, st, ld, k0, \
+                                        k1, kstep);                                                           \
+        break;
+        TL(3) TL(4)
+#undef TL
     }
 }
 
