@@ -316,10 +316,12 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
     }
 }
 
-// FP64 block kernels: at least 4 wavefronts per SIMD (128 VGPRs); the FP32
-// ones keep the compiler's register choice (measured: forcing 6 wavefronts,
-// or two entries per lane, is slower)
+// Wavefronts per SIMD the block kernels are compiled for: FP64 4 (128
+// VGPRs), FP32 5 (96 VGPRs; measured on the level-8 sphere: nearfield
+// 3.98 ms with the compiler's own choice of 103 VGPRs, 3.46 ms at 5,
+// 3.79 ms at 6)
 constexpr int BLK_FP64_WAVES = 4;
+constexpr int BLK_FP32_WAVES = 5;
 
 // ------------------------------------------------ coupling block rows ------
 // One workgroup per row cluster t with coupling blocks (t, s), t < s (a block
@@ -358,7 +360,7 @@ struct FarArgs {
 };
 
 template <typename T, int P, bool STORE>
-__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : 1)
+__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : BLK_FP32_WAVES)
     k_far_rows(FarArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -499,7 +501,7 @@ struct NearArgs {
 };
 
 template <typename T, int P, bool STORE>
-__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : 1)
+__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : BLK_FP32_WAVES)
     k_near_rows(NearArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
