@@ -298,6 +298,18 @@ struct GradBlkArgs {
     Rule R;
 };
 
+// Threads per row: blocks with at most 32 (64) rows give each row 4 (2)
+// threads that take every 4th (2nd) column and sum their accumulators in LDS
+// at the end, so small leaves and ranks keep the 128 threads busy.
+template <int P>
+constexpr int grad_max_split() { return P <= 9 ? 4 : 1; }
+
+template <typename T, int P>
+constexpr size_t grad_blk_smem(int cw)
+{
+    return ((size_t)P * 4 * cw + 2 * cw + (size_t)(grad_max_split<P>() - 1) * 32 * 4 * P) * sizeof(T) + 16;
+}
+
 template <typename T, int P, bool NEAR>
 __global__ void __launch_bounds__(128) k_grad_blocks(GradBlkArgs<T> g)
 {
@@ -315,6 +327,7 @@ __global__ void __launch_bounds__(128) k_grad_blocks(GradBlkArgs<T> g)
     T *colp = reinterpret_cast<T *>(smem);   // P x 4 x CW (SoA)
     T *cca = colp + (size_t)P * 4 * CW;     // CW
     T *ccb = cca + CW;
+    T *red = ccb + CW;                       // (split - 1) x RW x 4P partial accumulators
     int nr, nc, rb = 0, cb = 0;
     const int32_t *rl = nullptr, *cl = nullptr;
     int64_t ro = 0, co = 0;
@@ -331,11 +344,15 @@ __global__ void __launch_bounds__(128) k_grad_blocks(GradBlkArgs<T> g)
         rl = g.piv + ro;
         cl = g.piv + co;
     }
+    constexpr int MAXG = grad_max_split<P>();
+    const int G = (MAXG >= 4 && nr <= 32) ? 4 : (MAXG >= 2 && nr <= 64) ? 2 : 1;
+    const int RW = (int)blockDim.x / G;
+    const int gi = tid / RW, rt = tid - gi * RW;
     const double cx = 0.5 * (g.box[8 * t + 0] + g.box[8 * t + 3]);
     const double cy = 0.5 * (g.box[8 * t + 1] + g.box[8 * t + 4]);
     const double cz = 0.5 * (g.box[8 * t + 2] + g.box[8 * t + 5]);
-  for (int r0 = 0; r0 < nr; r0 += blockDim.x) {
-    const int row = r0 + tid;
+  for (int r0 = 0; r0 < nr; r0 += RW) {
+    const int row = r0 + rt;
     const bool active = row < nr;
     const int pos = active ? (NEAR ? rb + row : rl[row]) : 0;
     T xr[P][3], wr[P];
@@ -380,7 +397,7 @@ __global__ void __launch_bounds__(128) k_grad_blocks(GradBlkArgs<T> g)
         }
         __syncthreads();
         if (!active) continue;
-        for (int j = 0; j < cw; ++j) {
+        for (int j = gi; j < cw; j += G) {
             if (NEAR && ((mask >> (c0 + j)) & 1)) continue;
             const T coef = ra * ccb[j] + rbv * cca[j];
             for (int pb = 0; pb < P; ++pb) {
@@ -401,7 +418,31 @@ __global__ void __launch_bounds__(128) k_grad_blocks(GradBlkArgs<T> g)
             }
         }
     }
-    if (active) {
+    if (G > 1) {
+        // the column groups of a row add their sums into group 0 (fixed order)
+        __syncthreads();
+        if (gi > 0 && active) {
+            T *o = red + ((size_t)(gi - 1) * RW + rt) * 4 * P;
+            for (int p = 0; p < P; ++p) {
+                o[4 * p] = Ga[p];
+                o[4 * p + 1] = Ha[p][0];
+                o[4 * p + 2] = Ha[p][1];
+                o[4 * p + 3] = Ha[p][2];
+            }
+        }
+        __syncthreads();
+        if (gi == 0 && active)
+            for (int q = 1; q < G; ++q) {
+                const T *o = red + ((size_t)(q - 1) * RW + rt) * 4 * P;
+                for (int p = 0; p < P; ++p) {
+                    Ga[p] += o[4 * p];
+                    Ha[p][0] += o[4 * p + 1];
+                    Ha[p][1] += o[4 * p + 2];
+                    Ha[p][2] += o[4 * p + 3];
+                }
+            }
+    }
+    if (active && gi == 0) {
         double S = 0;
         for (int p = 0; p < P; ++p) S += (double)wr[p] * (double)Ga[p];
         const int32_t *v = g.tv + 3 * (size_t)pos;
@@ -621,13 +662,13 @@ template <typename T, bool NEAR>
 static hipError_t launch_grad_blocks_P(int P, GradBlkArgs<T> a, hipStream_t s)
 {
     if (a.nblk == 0) return hipSuccess;
-    size_t sm = ((size_t)P * 4 * a.cw + 2 * a.cw) * sizeof(T) + 16;
     switch (P) {
 #define CASE(PP)                                                                                        \
     case PP:                                                                                            \
         for (int o = 0; o < 2; ++o) {                                                                   \
             a.orient = o;                                                                               \
-            hipLaunchKernelGGL((k_grad_blocks<T, PP, NEAR>), dim3(a.nblk), dim3(128), sm, s, a);          \
+            hipLaunchKernelGGL((k_grad_blocks<T, PP, NEAR>), dim3(a.nblk), dim3(128),                     \
+                               (grad_blk_smem<T, PP>(a.cw)), s, a);                                      \
         }                                                                                               \
         break;
         CASE(1) CASE(4) CASE(9) CASE(16)
