@@ -316,12 +316,22 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
     }
 }
 
-// Wavefronts per SIMD the block kernels are compiled for: FP64 4 (128
-// VGPRs), FP32 5 (96 VGPRs; measured on the level-8 sphere: nearfield
-// 3.98 ms with the compiler's own choice of 103 VGPRs, 3.46 ms at 5,
-// 3.79 ms at 6)
-constexpr int BLK_FP64_WAVES = 4;
-constexpr int BLK_FP32_WAVES = 5;
+// Wavefronts per SIMD the block kernels are compiled for: as many as the
+// registers of a tile allow without spilling (the row points of a lane take
+// 5 P values; 512 / waves VGPRs per lane), at most 5 (FP32) or 3 (FP64).
+// Measured on the level-8 sphere: FP32 nearfield 3.98 ms with the
+// compiler's own choice (103 VGPRs), 3.46 ms at 5, 3.79 ms at 6; FP64
+// nearfield 9.15 ms at 4 (88 bytes of spills), 8.91 ms at 3, 8.82 ms at 2.
+constexpr int blk_waves(int word_bytes, int P, int base, int cap)
+{
+    const int need = 5 * P * (word_bytes / 4) + base;
+    const int w = 512 / need;
+    return w < 1 ? 1 : (w > cap ? cap : w);
+}
+template <typename T, int P>
+constexpr int near_waves() { return blk_waves((int)sizeof(T), P, 48, sizeof(T) == 8 ? 3 : 5); }
+template <typename T, int P>
+constexpr int far_waves() { return blk_waves((int)sizeof(T), P, 64, sizeof(T) == 8 ? 3 : 5); }
 
 // ------------------------------------------------ coupling block rows ------
 // One workgroup per row cluster t with coupling blocks (t, s), t < s (a block
@@ -360,7 +370,7 @@ struct FarArgs {
 };
 
 template <typename T, int P, bool STORE>
-__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : BLK_FP32_WAVES)
+__global__ void __launch_bounds__(BLK_THREADS, (far_waves<T, P>()))
     k_far_rows(FarArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -501,7 +511,7 @@ struct NearArgs {
 };
 
 template <typename T, int P, bool STORE>
-__global__ void __launch_bounds__(BLK_THREADS, sizeof(T) == 8 ? BLK_FP64_WAVES : BLK_FP32_WAVES)
+__global__ void __launch_bounds__(BLK_THREADS, (near_waves<T, P>()))
     k_near_rows(NearArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
