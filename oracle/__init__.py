@@ -62,7 +62,7 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.orc_create.restype = P
-    lib.orc_create.argtypes = [I64, I64, P, P, I32, I32, I32]
+    lib.orc_create.argtypes = [I64, I64, P, P, I32, I32, I32, I32]
     lib.orc_destroy.argtypes = [P]
     lib.orc_classify.restype = I32
     lib.orc_classify.argtypes = [P, I64, I64]
@@ -74,6 +74,8 @@ def _load():
     lib.orc_matvec_rows.argtypes = [P, I64, P, P, I64, P]
     lib.orc_triangle_points.argtypes = [P, I32, P, P]
     lib.orc_gauss01.argtypes = [I32, P, P]
+    lib.orc_tri_rule.restype = I32
+    lib.orc_tri_rule.argtypes = [I32, I32, P, P, P]
     lib.orc_entry_grad.argtypes = [P, I64, I64, P]
     lib.orc_energy_grad_vertices.argtypes = [P, P, I64, P, P]
     lib.orc_num_threads.restype = I32
@@ -97,6 +99,17 @@ def gauss01(q: int):
     return x, w
 
 
+def tri_rule(q: int, sym: bool = False):
+    """The oracle's rule on the reference triangle {0 <= s2 <= s1 <= 1} used
+    by the disjoint classes: (s1, s2, w), weights summing to 1/2."""
+    n = 1024
+    s1, s2, w = np.zeros(n), np.zeros(n), np.zeros(n)
+    k = _load().orc_tri_rule(q, int(sym), _ptr(s1), _ptr(s2), _ptr(w))
+    if k == 0:
+        raise ValueError("unsupported rule")
+    return s1[:k], s2[:k], w[:k]
+
+
 def num_threads() -> int:
     """OpenMP threads used by the oracle's parallel loops."""
     return int(_load().orc_num_threads())
@@ -111,17 +124,21 @@ class Entries:
     """Galerkin entries g_ij of Eq. G_def by the oracle's quadrature rules.
 
     Orders: q_r (disjoint), q_nr (near-regular disjoint), q_s (touching,
-    Gauss points per variable of the 4D Sauter-Schwab rules).
+    Gauss points per variable of the 4D Sauter-Schwab rules).  sym: the
+    disjoint classes use the fully symmetric triangle rule of the same
+    polynomial degree as the collapsed rule of their order (q = 2: 3 points,
+    q = 3: 6 points) instead of the collapsed rule.
     """
 
-    def __init__(self, verts, tris, q_r=3, q_nr=5, q_s=4):
+    def __init__(self, verts, tris, q_r=3, q_nr=5, q_s=4, sym=False):
         self.lib = _load()
         self.verts = np.ascontiguousarray(verts, dtype=np.float64)
         self.tris = np.ascontiguousarray(tris, dtype=np.int32)
         self.n = int(self.tris.shape[0])
         self.q = (q_r, q_nr, q_s)
+        self.sym = bool(sym)
         self.h = self.lib.orc_create(self.verts.shape[0], self.n, _ptr(self.verts),
-                                     _ptr(self.tris), q_r, q_nr, q_s)
+                                     _ptr(self.tris), q_r, q_nr, q_s, int(self.sym))
         if not self.h:
             raise ValueError("invalid quadrature orders")
 
@@ -442,7 +459,7 @@ def gca_h2(verts, tris, leaf=32, eta=2.0, m=3, eps=1e-6, q_A=3, q=(3, 5, 4),
                 o += r
     ent_c = None
     if q_c is not None and q_c != q[0]:
-        ent_c = Entries(verts, tris, q_c, q[1], q[2])
+        ent_c = Entries(verts, tris, q_c, q_c if ent.sym else q[1], q[2], sym=ent.sym)
     return H2(tree, far, near, pivots, V, E, ent, ent_c=ent_c)
 
 

@@ -27,7 +27,12 @@
  * parametrisation      chi(s) = P0 + s1 (P1 - P0) + s2 (P2 - P1),
  * surface element      |(P1 - P0) x (P2 - P1)| = 2 |t|.
  * Collapsed Gauss rule on T of order q: s1 = u_a, s2 = u_a v_b with weight
- * w_a w_b u_a (u, v, w: Gauss-Legendre on [0,1]).
+ * w_a w_b u_a (u, v, w: Gauss-Legendre on [0,1]).  Optional family for the
+ * regular classes ("sym"): the fully symmetric triangle rules of polynomial
+ * degree 2q - 2, the same degree as the collapsed rule of order q -- 3 points
+ * (degree 2, q = 2) and 6 points (degree 4, q = 3; Strang-Fix / Dunavant),
+ * given by barycentric orbits (l0, l1, l2) with s1 = l1 + l2, s2 = l2 and
+ * weight w / 2 on T (the weights w sum to one).
  *
  * Vertex order for touching pairs (so that shared vertices come first):
  *   identical  : the mesh order (v0, v1, v2) for both copies;
@@ -48,6 +53,13 @@
 enum { ORC_REG = 0, ORC_NEAR = 1, ORC_VERT = 2, ORC_EDGE = 3, ORC_IDENT = 4 };
 
 #define ORC_QMAX 32
+#define ORC_TMAX (ORC_QMAX * ORC_QMAX)
+
+/* A rule on the reference triangle T: points (s1, s2), weights summing to |T| = 1/2. */
+typedef struct {
+    int np;
+    double s1[ORC_TMAX], s2[ORC_TMAX], w[ORC_TMAX];
+} orc_trirule;
 
 typedef struct {
     int64_t nv, nt;
@@ -55,9 +67,8 @@ typedef struct {
     int32_t *tri;    /* nt x 3 */
     int64_t *vadj_ptr; /* vertex -> neighbouring vertices (mesh edges), CSR */
     int32_t *vadj;
-    int q_r, q_nr, q_s;
-    double gr_x[ORC_QMAX], gr_w[ORC_QMAX];   /* Gauss-Legendre on [0,1], order q_r */
-    double gn_x[ORC_QMAX], gn_w[ORC_QMAX];   /* order q_nr */
+    int q_r, q_nr, q_s, sym;
+    orc_trirule rr, rn;                      /* the regular and near-regular triangle rules */
     double gs_x[ORC_QMAX], gs_w[ORC_QMAX];   /* order q_s */
 } orc_ctx;
 
@@ -114,20 +125,90 @@ void orc_destroy(void *p)
     free(c);
 }
 
+/* Collapsed Gauss rule of order q on T (see the header). */
+static void rule_collapsed(int q, orc_trirule *r)
+{
+    double x[ORC_QMAX], w[ORC_QMAX];
+    orc_gauss01(q, x, w);
+    r->np = 0;
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b) {
+            r->s1[r->np] = x[a];
+            r->s2[r->np] = x[a] * x[b];
+            r->w[r->np] = w[a] * w[b] * x[a];
+            r->np++;
+        }
+}
+
+/* Fully symmetric rule from barycentric orbits: every orbit (a, a, 1 - 2a)
+ * contributes its three permutations with barycentric weight w each. */
+static void add_orbit(orc_trirule *r, double a, double w)
+{
+    const double b = 1.0 - 2.0 * a;
+    const double l[3][3] = {{b, a, a}, {a, b, a}, {a, a, b}};
+    for (int k = 0; k < 3; ++k) {
+        r->s1[r->np] = l[k][1] + l[k][2];
+        r->s2[r->np] = l[k][2];
+        r->w[r->np] = 0.5 * w;
+        r->np++;
+    }
+}
+
+/* Symmetric rule of degree 2q - 2: q = 2 -> 3 points (orbit a = 1/6, weights
+ * 1/3, degree 2); q = 3 -> 6 points (orbits a = 0.445948490915965 with weight
+ * 0.223381589678011 and a = 0.091576213509771 with weight 0.109951743655322,
+ * degree 4).  Returns 0 for other orders. */
+static int rule_symmetric(int q, orc_trirule *r)
+{
+    r->np = 0;
+    if (q == 2) {
+        add_orbit(r, 1.0 / 6.0, 1.0 / 3.0);
+        return 1;
+    }
+    if (q == 3) {
+        add_orbit(r, 0.445948490915965, 0.223381589678011);
+        add_orbit(r, 0.091576213509771, 0.109951743655322);
+        return 1;
+    }
+    return 0;
+}
+
+/* The triangle rule the regular classes use (for tests): writes np points
+ * (s1, s2) and weights, returns np, or 0 for an unsupported order. */
+int orc_tri_rule(int q, int sym, double *s1, double *s2, double *w)
+{
+    orc_trirule r;
+    if (q < 1 || q > ORC_QMAX) return 0;
+    if (sym) {
+        if (!rule_symmetric(q, &r)) return 0;
+    } else {
+        rule_collapsed(q, &r);
+    }
+    for (int k = 0; k < r.np; ++k) { s1[k] = r.s1[k]; s2[k] = r.s2[k]; w[k] = r.w[k]; }
+    return r.np;
+}
+
 void *orc_create(int64_t nv, int64_t nt, const double *xyz, const int32_t *tri,
-                 int q_r, int q_nr, int q_s)
+                 int q_r, int q_nr, int q_s, int sym)
 {
     if (q_r < 1 || q_nr < 1 || q_s < 1 || q_r > ORC_QMAX || q_nr > ORC_QMAX || q_s > ORC_QMAX)
         return NULL;
+    if (sym && ((q_r != 2 && q_r != 3) || (q_nr != 2 && q_nr != 3))) return NULL;
     orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    c->sym = sym;
+    if (sym) {
+        rule_symmetric(q_r, &c->rr);
+        rule_symmetric(q_nr, &c->rn);
+    } else {
+        rule_collapsed(q_r, &c->rr);
+        rule_collapsed(q_nr, &c->rn);
+    }
     c->nv = nv; c->nt = nt;
     c->xyz = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
     c->tri = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)nt);
     memcpy(c->xyz, xyz, sizeof(double) * 3 * (size_t)nv);
     memcpy(c->tri, tri, sizeof(int32_t) * 3 * (size_t)nt);
     c->q_r = q_r; c->q_nr = q_nr; c->q_s = q_s;
-    orc_gauss01(q_r, c->gr_x, c->gr_w);
-    orc_gauss01(q_nr, c->gn_x, c->gn_w);
     orc_gauss01(q_s, c->gs_x, c->gs_w);
 
     /* vertex adjacency through mesh edges: every triangle contributes its 3 edges
@@ -207,28 +288,23 @@ static double surf_elem(const double P[3][3])
     return sqrt(cx * cx + cy * cy + cz * cz);
 }
 
-/* Regular rule: tensor collapsed Gauss of order q on both triangles. */
-static double entry_regular(const double P[3][3], const double Q[3][3], int q,
-                            const double *gx, const double *gw)
+/* Regular rule: the triangle rule r on both triangles. */
+static double entry_regular(const double P[3][3], const double Q[3][3], const orc_trirule *r)
 {
     double Jp = surf_elem(P), Jq = surf_elem(Q);
     double sum = 0.0;
-    for (int a = 0; a < q; ++a)
-        for (int b = 0; b < q; ++b) {
-            double s1 = gx[a], s2 = gx[a] * gx[b], ws = gw[a] * gw[b] * gx[a];
-            double x[3];
-            chi_rel(P, s1, s2, x);
-            for (int d = 0; d < 3; ++d) x[d] += P[0][d];
-            for (int e = 0; e < q; ++e)
-                for (int f = 0; f < q; ++f) {
-                    double u1 = gx[e], u2 = gx[e] * gx[f], wu = gw[e] * gw[f] * gx[e];
-                    double y[3];
-                    chi_rel(Q, u1, u2, y);
-                    for (int d = 0; d < 3; ++d) y[d] += Q[0][d];
-                    double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-                    sum += ws * wu / sqrt(dx * dx + dy * dy + dz * dz);
-                }
+    for (int a = 0; a < r->np; ++a) {
+        double x[3];
+        chi_rel(P, r->s1[a], r->s2[a], x);
+        for (int d = 0; d < 3; ++d) x[d] += P[0][d];
+        for (int b = 0; b < r->np; ++b) {
+            double y[3];
+            chi_rel(Q, r->s1[b], r->s2[b], y);
+            for (int d = 0; d < 3; ++d) y[d] += Q[0][d];
+            double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+            sum += r->w[a] * r->w[b] / sqrt(dx * dx + dy * dy + dz * dz);
         }
+    }
     return sum * Jp * Jq / (4.0 * ORC_PI);
 }
 
@@ -362,8 +438,8 @@ double orc_entry(void *p, int64_t i, int64_t j)
         return entry_touching(kase, P, Q, c->q_s, c->gs_x, c->gs_w);
     }
     for (int k = 0; k < 3; ++k) { vload(c, c->tri[3 * i + k], P[k]); vload(c, c->tri[3 * j + k], Q[k]); }
-    if (kase == ORC_NEAR) return entry_regular(P, Q, c->q_nr, c->gn_x, c->gn_w);
-    return entry_regular(P, Q, c->q_r, c->gr_x, c->gr_w);
+    if (kase == ORC_NEAR) return entry_regular(P, Q, &c->rn);
+    return entry_regular(P, Q, &c->rr);
 }
 
 void orc_entries(void *p, int64_t m, const int64_t *I, const int64_t *J, double *out)
@@ -482,28 +558,26 @@ static void grad_point(const double P[3][3], const double Q[3][3], double JP, do
         }
 }
 
-static void grad_regular(const double P[3][3], const double Q[3][3], int q, const double *gx, const double *gw,
-                         double GP[3][3], double GQ[3][3])
+static void grad_regular(const double P[3][3], const double Q[3][3], const orc_trirule *r, double GP[3][3],
+                         double GQ[3][3])
 {
     double JP = surf_elem(P), JQ = surf_elem(Q);
     double gJP[3][3], gJQ[3][3];
     surf_elem_grad(P, gJP);
     surf_elem_grad(Q, gJQ);
-    for (int a = 0; a < q; ++a)
-        for (int b = 0; b < q; ++b) {
-            double s1 = gx[a], s2 = gx[a] * gx[b], ws = gw[a] * gw[b] * gx[a];
-            double x[3];
-            chi_rel(P, s1, s2, x);
-            for (int d = 0; d < 3; ++d) x[d] += P[0][d];
-            for (int e = 0; e < q; ++e)
-                for (int f = 0; f < q; ++f) {
-                    double u1 = gx[e], u2 = gx[e] * gx[f], wu = gw[e] * gw[f] * gx[e];
-                    double y[3], XmY[3];
-                    chi_rel(Q, u1, u2, y);
-                    for (int d = 0; d < 3; ++d) XmY[d] = x[d] - (y[d] + Q[0][d]);
-                    grad_point(P, Q, JP, JQ, gJP, gJQ, s1, s2, u1, u2, ws * wu, XmY, GP, GQ);
-                }
+    for (int a = 0; a < r->np; ++a) {
+        const double s1 = r->s1[a], s2 = r->s2[a];
+        double x[3];
+        chi_rel(P, s1, s2, x);
+        for (int d = 0; d < 3; ++d) x[d] += P[0][d];
+        for (int b = 0; b < r->np; ++b) {
+            const double u1 = r->s1[b], u2 = r->s2[b];
+            double y[3], XmY[3];
+            chi_rel(Q, u1, u2, y);
+            for (int d = 0; d < 3; ++d) XmY[d] = x[d] - (y[d] + Q[0][d]);
+            grad_point(P, Q, JP, JQ, gJP, gJQ, s1, s2, u1, u2, r->w[a] * r->w[b], XmY, GP, GQ);
         }
+    }
 }
 
 static void grad_touching(int kase, const double P[3][3], const double Q[3][3], int q, const double *gx,
@@ -561,8 +635,8 @@ void orc_entry_grad(void *p, int64_t i, int64_t j, double *out)
             vload(c, pid[k], P[k]);
             vload(c, qid[k], Q[k]);
         }
-        if (kase == ORC_NEAR) grad_regular(P, Q, c->q_nr, c->gn_x, c->gn_w, GP, GQ);
-        else grad_regular(P, Q, c->q_r, c->gr_x, c->gr_w, GP, GQ);
+        if (kase == ORC_NEAR) grad_regular(P, Q, &c->rn, GP, GQ);
+        else grad_regular(P, Q, &c->rr, GP, GQ);
     }
     double *oi = out + (swapped ? 9 : 0), *oj = out + (swapped ? 0 : 9);
     if (i == j) { oi = out; oj = out; }

@@ -51,6 +51,80 @@ def test_gauss_legendre_matches_library_and_is_exact(orc, q):
         assert abs(np.sum(w * x ** d) - 1.0 / (d + 1)) < 1e-14
 
 
+def _tri_moment(a, b):
+    # int_T s1^a s2^b over T = {0 <= s2 <= s1 <= 1}
+    return 1.0 / ((b + 1) * (a + b + 2))
+
+
+@pytest.mark.parametrize("q,sym", [(2, False), (3, False), (4, False), (2, True), (3, True)])
+def test_triangle_rules_integrate_polynomials_of_their_degree(orc, q, sym):
+    """Both rule families of the disjoint classes are exact for every
+    polynomial in (s1, s2) of total degree <= 2q - 2 on the reference triangle
+    (the collapsed rule: Gauss-Legendre exact to degree 2q - 1 in s1 after the
+    factor s1 of the collapse; the symmetric rules by construction), and the
+    symmetric ones are not exact one degree higher (so the degree is the
+    stated one, not an accident of the test).  Exactness to rounding pins the
+    printed orbit constants."""
+    s1, s2, w = orc.tri_rule(q, sym)
+    assert len(w) == (q * q if not sym else {2: 3, 3: 6}[q])
+    assert np.all(w > 0)
+    assert np.all((s2 >= 0) & (s2 <= s1) & (s1 <= 1))
+    deg = 2 * q - 2
+    for a in range(deg + 1):
+        for b in range(deg + 1 - a):
+            assert abs(np.sum(w * s1 ** a * s2 ** b) - _tri_moment(a, b)) < 2e-15, (a, b)
+    if sym:
+        worst = max(abs(np.sum(w * s1 ** a * s2 ** (deg + 1 - a)) - _tri_moment(a, deg + 1 - a))
+                    for a in range(deg + 2))
+        assert worst > 1e-6
+
+
+def test_symmetric_rule_entries_are_invariant_under_vertex_rotation(orc):
+    """The symmetric rules are invariant under the permutations of a
+    triangle's vertices, so rotating the vertex order of every triangle leaves
+    their regular entries unchanged (to rounding); the collapsed rule is not
+    invariant (it distinguishes P0), which the same test shows."""
+    m = synth.icosphere(2)
+    rot = np.ascontiguousarray(m.tris[:, [1, 2, 0]])
+    a = orc.Entries(m.verts, m.tris, 3, 3, 4, sym=True)
+    b = orc.Entries(m.verts, rot, 3, 3, 4, sym=True)
+    c0 = orc.Entries(m.verts, m.tris, 3, 3, 4)
+    c1 = orc.Entries(m.verts, rot, 3, 3, 4)
+    I = np.arange(m.nt)
+    J = (I * 37 + 11) % m.nt
+    reg = a.classify(I, J) == orc.REG
+    I, J = I[reg], J[reg]
+    ga, gb = a.entries(I, J), b.entries(I, J)
+    np.testing.assert_allclose(ga, gb, rtol=1e-13, atol=0)
+    assert np.max(np.abs(c0.entries(I, J) - c1.entries(I, J)) / np.abs(c0.entries(I, J))) > 1e-9
+
+
+def test_symmetric_rule_converges_like_the_collapsed_rule(orc):
+    """Disjoint pairs of the level-3 sphere: against an order-8 collapsed
+    reference, the symmetric rule of degree 4 (6 points) is as accurate as
+    the collapsed rule of the same degree (9 points) -- within a factor 3 --
+    and far more accurate than the degree-2 rules; near-regular pairs use the
+    same family."""
+    m = synth.icosphere(3)
+    ref = orc.Entries(m.verts, m.tris, 8, 8, 4)
+    rng = np.random.default_rng(3)
+    I = rng.integers(0, m.nt, 4000)
+    J = rng.integers(0, m.nt, 4000)
+    cls = ref.classify(I, J)
+    sel = (cls == orc.REG) | (cls == orc.NEAR)
+    I, J = I[sel], J[sel]
+    g = ref.entries(I, J)
+    err = {}
+    for q in (2, 3):
+        for sym in (False, True):
+            e = orc.Entries(m.verts, m.tris, q, q, 4, sym=sym)
+            err[q, sym] = np.linalg.norm(e.entries(I, J) - g) / np.linalg.norm(g)
+    assert err[3, True] < 3 * err[3, False] and err[3, False] < 3 * err[3, True]
+    assert err[3, True] < err[2, True] / 10 and err[3, True] < 1e-5
+    with pytest.raises(ValueError):
+        orc.Entries(m.verts, m.tris, 4, 4, 4, sym=True)
+
+
 @pytest.mark.parametrize("kase", ["ident", "edge", "vert"])
 def test_sauter_schwab_maps_tile_the_product_domain(orc, kase):
     """The regions' maps must cover T x T exactly once: every moment
