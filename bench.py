@@ -50,6 +50,12 @@ EVALS_PER_S_F32 = 1.0 / (5.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
 ALU_PEAK_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
 
 
+def rule_points(q, sym):
+    """Points per triangle of the rule of order q: q^2 (collapsed Gauss) or
+    the symmetric rule of the same degree (3 points for q = 2, 6 for q = 3)."""
+    return {2: 3, 3: 6}[q] if sym else q * q
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed PMC summary
     (profiles/pmc_traffic_sphere_l8.md), or None when the kernel's source has
@@ -76,9 +82,14 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the oracle CPU baseline sample (0 disables it)")
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--err-rows", type=int, default=384,
+                    help="rows of the oracle accuracy sample (fewer if they do not fit the CPU budget)")
     ap.add_argument("--eps", type=float, default=None, help="override the workload's ACA tolerance")
     ap.add_argument("--q-nr", type=int, default=None, help="override the near-regular pair order")
     ap.add_argument("--q-c", type=int, default=None, help="override the coupling-entry rule order")
+    ap.add_argument("--sym", type=int, default=None, choices=(0, 1),
+                    help="override the workload's triangle-rule family for disjoint pairs "
+                         "(0 collapsed Gauss, 1 symmetric)")
     ap.add_argument("--stored-steps", type=int, default=10,
                     help="timed products per precision in stored-block mode (0 disables it)")
     ap.add_argument("--grad-steps", type=int, default=3,
@@ -114,6 +125,7 @@ def main():
         params.q_c = cfg["q_c"]
     if a.q_nr is not None:
         params.q_nr = a.q_nr
+    params.sym_rules = a.sym if a.sym is not None else cfg.get("sym_rules", 0)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -204,8 +216,8 @@ def main():
     mean_fp64 = dict(zip(phases, ph_fp64.mean(axis=0).tolist()))
 
     # dominant kernel of the mixed product: coupling-block or nearfield-block quadrature
-    P = params.q_r * params.q_r
-    Pc = params.q_c * params.q_c
+    P = rule_points(params.q_r, params.sym_rules)
+    Pc = rule_points(params.q_c, params.sym_rules)
     work = {"coupling_blocks": st["coupling_entries"] * Pc * Pc * FLOPS_PER_EVAL,
             "near_blocks": st["near_regular_pairs"] * P * P * FLOPS_PER_EVAL}
     dom = max(work, key=lambda k: mean_mixed[k])
@@ -217,28 +229,32 @@ def main():
                 "kernel": kname,
                 "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom]}
 
-    # CPU oracle on a bounded sample of rows (also the accuracy check)
+    # CPU oracle on a bounded sample of rows (also the accuracy check): the
+    # first rows of one seeded permutation, err_rows of them unless fewer fit
+    # in about twice cpu_seconds, so runs of different configurations compare
+    # on the same rows
     cpu = None
     rel = {}
     if a.cpu_seconds > 0:
         import oracle
         ent = oracle.Entries(mesh.verts, mesh.tris, params.q_r, params.q_nr, params.q_s)
-        rng = np.random.default_rng(12345)
-        rows = rng.choice(n, oracle.num_threads(), replace=False)
+        order = np.random.default_rng(12345).permutation(n)
+        k0 = oracle.num_threads()
+        rows = order[:k0]
         t = time.perf_counter()
         ref = ent.matvec_rows(rows, x_host)
         t1 = time.perf_counter() - t
-        more = int(min(4096, max(0, (a.cpu_seconds - t1) / max(t1, 1e-6) * len(rows))))
-        if more > 0:
-            rows2 = rng.choice(np.setdiff1d(np.arange(n), rows), more, replace=False)
+        k = int(min(a.err_rows, max(k0, 2 * a.cpu_seconds / max(t1, 1e-6) * k0)))
+        if k > k0:
+            rows2 = order[k0:k]
             t = time.perf_counter()
             ref2 = ent.matvec_rows(rows2, x_host)
-            t2 = time.perf_counter() - t
-            rows = np.concatenate([rows, rows2])
+            t1 += time.perf_counter() - t
+            rows = order[:k]
             ref = np.concatenate([ref, ref2])
-            t1 += t2
         cpu = {"value": len(rows) / t1, "unit": "DoF/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"{len(rows)} rows of the dense FP64 product G x (same quadrature orders), "
+               "sample": f"{len(rows)} rows of the dense FP64 product G x (collapsed Gauss rules of the stated "
+                         f"orders, Sauter-Schwab touching pairs), "
                          f"{t1:.1f} s; a full product is n rows, so DoF/s = rows/s"}
         ym = y_mixed.cpu().numpy()[rows]
         yd = y_fp64.cpu().numpy()[rows]
@@ -266,6 +282,8 @@ def main():
                                f"omega margin {params.omega_scale} diam/eta, ACA eps {cfg['eps']}, "
                                f"Gauss orders regular {params.q_r} / coupling {params.q_c} / "
                                f"near {params.q_nr} / Sauter-Schwab {params.q_s}, "
+                               f"disjoint-pair triangle rules "
+                               f"{'symmetric' if params.sym_rules else 'collapsed Gauss'} ({P} points regular, {Pc} coupling), "
                                f"1 RHS x ~ N(0,1) seed 0",
                    "n": n, "nrhs": 1, "precision": "mixed: FP32 regular-pair quadrature + transfers, "
                                                    "FP64 Sauter-Schwab touching pairs"},

@@ -73,7 +73,14 @@ typedef struct {
     int32_t q_s;         /* Sauter-Schwab order (>= 2) for touching pairs         */
     int32_t q_c;         /* regular rule order for the coupling entries G|t~ x s~
                             (admissible blocks); 0 means q_c = q_r              */
-    int32_t reserved[2]; /* must be zero */
+    int32_t sym_rules;   /* 0: the disjoint pairs (regular, near-regular, coupling)
+                            use the collapsed Gauss rule of their order on each
+                            triangle (q^2 points, the disjoint case of Sauter's
+                            rules, Section 8); 1: the fully symmetric rule of the
+                            same polynomial degree 2q - 2 (q = 2: 3 points, q = 3:
+                            6 points), which needs q_r, q_nr, q_c in {2, 3}.  The
+                            Green factor keeps the collapsed rule of order q_A. */
+    int32_t reserved;    /* must be zero */
 } gca_params;
 
 #define GCA_NPHASE 9
@@ -112,7 +119,7 @@ typedef struct {
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
- * q_r 3, q_nr 3, q_s 4, q_c 3.  With q_nr == q_r near-regular pairs are
+ * q_r 3, q_nr 3, q_s 4, q_c 3, sym_rules 0.  With q_nr == q_r near-regular pairs are
  * integrated by the regular rule inside the nearfield blocks (no separate
  * list). */
 void gca_params_default(gca_params *p);

@@ -54,7 +54,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("eps", ctypes.c_double), ("omega_scale", ctypes.c_double),
                 ("green_m", ctypes.c_int32), ("q_A", ctypes.c_int32), ("q_r", ctypes.c_int32),
                 ("q_nr", ctypes.c_int32), ("q_s", ctypes.c_int32), ("q_c", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("sym_rules", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -129,12 +129,14 @@ class Params:
     q_nr: int = 3
     q_s: int = 4
     q_c: int = 3
+    sym_rules: int = 0   # 1: symmetric triangle rules (3 / 6 points) for the disjoint pairs
 
     def _c(self):
         p = _Params()
         p.eta, p.eps, p.omega_scale = self.eta, self.eps, self.omega_scale
         p.green_m, p.q_A, p.q_r, p.q_nr, p.q_s = self.green_m, self.q_A, self.q_r, self.q_nr, self.q_s
         p.q_c = self.q_c
+        p.sym_rules = self.sym_rules
         return p
 
 

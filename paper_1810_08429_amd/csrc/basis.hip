@@ -23,16 +23,15 @@ struct GLRule {
 };
 
 // ---------------------------------------------------------- triangle rule --
-// point (s1, s2) = (u_a, u_a v_b), weight w_a w_b u_a, mapped by
-// chi(s) = P0 + s1 (P1 - P0) + s2 (P2 - P1); weight times |(P1-P0) x (P2-P1)|.
-__global__ void k_tri_points(const double *xyz, const int32_t *tv, int64_t n, int q, GLRule g, double *out)
+// point p of the rule: chi(s) = P0 + s1 (P1 - P0) + s2 (P2 - P1), weight
+// w_p |(P1 - P0) x (P2 - P1)|; thread per (triangle, point).
+__global__ void k_tri_points(const double *xyz, const int32_t *tv, int64_t n, TriRule r, double *out)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int P = q * q;
+    const int P = r.np;
     if (e >= n * P) return;
     int64_t t = e / P;
     int p = (int)(e - t * P);
-    int a = p / q, b = p - a * q;
     const int32_t *v = tv + 3 * t;
     double P0[3], P1[3], P2[3];
     for (int d = 0; d < 3; ++d) {
@@ -47,23 +46,19 @@ __global__ void k_tri_points(const double *xyz, const int32_t *tv, int64_t n, in
     }
     double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
     double J = sqrt(cx * cx + cy * cy + cz * cz);
-    double s1 = g.x[a], s2 = g.x[a] * g.x[b];
+    const double s1 = r.s1[p], s2 = r.s2[p];
     double *o = out + 4 * e;
     for (int d = 0; d < 3; ++d) o[d] = P0[d] + s1 * e1[d] + s2 * e2[d];
-    o[3] = g.w[a] * g.w[b] * g.x[a] * J;
+    o[3] = r.w[p] * J;
 }
 
-hipError_t launch_tri_points(const double *xyz, const int32_t *tv, int64_t n, int q, const double *gx,
-                             const double *gw, double *out, hipStream_t s)
+hipError_t launch_tri_points(const double *xyz, const int32_t *tv, int64_t n, const TriRule &rule, double *out,
+                             hipStream_t s)
 {
-    GLRule g{};
-    for (int i = 0; i < q; ++i) {
-        g.x[i] = gx[i];
-        g.w[i] = gw[i];
-    }
-    int64_t tot = n * q * q;
+    if (rule.np < 1 || rule.np > 64) return hipErrorInvalidValue;
+    int64_t tot = n * rule.np;
     dim3 grid((unsigned)((tot + 255) / 256)), blk(256);
-    hipLaunchKernelGGL(k_tri_points, grid, blk, 0, s, xyz, tv, n, q, g, out);
+    hipLaunchKernelGGL(k_tri_points, grid, blk, 0, s, xyz, tv, n, rule, out);
     return hipGetLastError();
 }
 

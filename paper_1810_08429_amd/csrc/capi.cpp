@@ -76,8 +76,14 @@ gca_status check_params(const gca_params *p)
     if (p->q_r < 1 || p->q_r > 6) return set_error(GCA_EINVAL, "q_r must be in [1, 6]");
     if (p->q_nr < 1 || p->q_nr > 7) return set_error(GCA_EINVAL, "q_nr must be in [1, 7]");
     if (p->q_s < 2 || p->q_s > 32) return set_error(GCA_EINVAL, "q_s must be in [2, 32]");
-    if (p->reserved[0] || p->reserved[1]) return set_error(GCA_EINVAL, "reserved fields must be zero");
+    if (p->reserved) return set_error(GCA_EINVAL, "reserved field must be zero");
     if (p->q_c < 0 || p->q_c > 6) return set_error(GCA_EINVAL, "q_c must be in 1..6 (0: same as q_r)");
+    if (p->sym_rules != 0 && p->sym_rules != 1) return set_error(GCA_EINVAL, "sym_rules must be 0 or 1");
+    if (p->sym_rules) {
+        const int qc = p->q_c ? p->q_c : p->q_r;
+        for (int q : {p->q_r, p->q_nr, qc})
+            if (q != 2 && q != 3) return set_error(GCA_EINVAL, "sym_rules needs q_r, q_nr and q_c in {2, 3}");
+    }
     return GCA_OK;
 }
 
@@ -416,30 +422,37 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     for (size_t l = 0; l < h->level_clusters.size(); ++l)
         GCA_TRY(upload_new(h, &h->d_level_clusters[l], h->level_clusters[l], s));
 
-    // triangle quadrature points
-    auto tri_pts = [&](int q, double **out) -> gca_status {
-        double gx[32], gw[32];
-        gauss_legendre01(q, gx, gw);
-        GCA_TRY(dalloc(h, out, (size_t)n * q * q * 4));
-        GCA_HIP_TRY(launch_tri_points(h->d_xyz, h->d_tv, n, q, gx, gw, *out, s));
+    // triangle quadrature points: the regular-pair rules (collapsed Gauss or
+    // symmetric, by sym_rules) and the collapsed rule of the Green factor
+    const bool sym = p->sym_rules != 0;
+    auto tri_pts = [&](int q, bool sy, double **out, int *np) -> gca_status {
+        TriRule r;
+        if (!tri_rule(q, sy, r)) return set_error(GCA_EINVAL, "unsupported triangle rule");
+        if (np) *np = r.np;
+        GCA_TRY(dalloc(h, out, (size_t)n * r.np * 4));
+        GCA_HIP_TRY(launch_tri_points(h->d_xyz, h->d_tv, n, r, *out, s));
         return GCA_OK;
     };
-    GCA_TRY(tri_pts(p->q_r, &h->d_qr));
+    GCA_TRY(tri_pts(p->q_r, sym, &h->d_qr, &h->P_r));
     GCA_TRY(dalloc(h, &h->d_cent, (size_t)n * 4));
-    GCA_TRY(dalloc(h, &h->d_qloc32, (size_t)n * p->q_r * p->q_r * 4));
+    GCA_TRY(dalloc(h, &h->d_qloc32, (size_t)n * h->P_r * 4));
     GCA_HIP_TRY(launch_local_points(h, s));
-    if (p->q_nr == p->q_r)
+    if (p->q_nr == p->q_r) {
         h->d_qnr = h->d_qr;
-    else
-        GCA_TRY(tri_pts(p->q_nr, &h->d_qnr));
-    if (p->q_A == p->q_r)
+        h->P_nr = h->P_r;
+    } else {
+        GCA_TRY(tri_pts(p->q_nr, sym, &h->d_qnr, &h->P_nr));
+    }
+    if (p->q_A == p->q_r && !sym)
         h->d_qA = h->d_qr;
     else
-        GCA_TRY(tri_pts(p->q_A, &h->d_qA));
-    if (h->prm.q_c == p->q_r)
+        GCA_TRY(tri_pts(p->q_A, false, &h->d_qA, nullptr));
+    if (h->prm.q_c == p->q_r) {
         h->d_qc = h->d_qr;
-    else
-        GCA_TRY(tri_pts(h->prm.q_c, &h->d_qc));
+        h->P_c = h->P_r;
+    } else {
+        GCA_TRY(tri_pts(h->prm.q_c, sym, &h->d_qc, &h->P_c));
+    }
 
     GCA_HIP_TRY(hipStreamSynchronize(s));
     lap(3);
@@ -584,7 +597,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             for (int64_t k = h->piv_off[c]; k < h->piv_off[c] + h->rank[c]; ++k) pc[(size_t)k] = c;
         if (h->n_piv_total > 0) {
             GCA_TRY(upload_new(h, &h->d_piv_cluster, pc, s));
-            GCA_TRY(dalloc(h, &h->d_pq32, (size_t)h->n_piv_total * h->prm.q_c * h->prm.q_c * 4));
+            GCA_TRY(dalloc(h, &h->d_pq32, (size_t)h->n_piv_total * h->P_c * 4));
             GCA_HIP_TRY(launch_pivot_points(h, s));
         }
     }
@@ -1416,17 +1429,18 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
     GCA_TRY(frozen_setup(h, s));
     std::copy(xyz, xyz + 3 * h->nv, h->mesh.xyz.begin());
     GCA_TRY(upload(h->d_xyz, h->mesh.xyz, s));
-    auto tri_pts = [&](int q, double *out) -> gca_status {
-        double gx[32], gw[32];
-        gauss_legendre01(q, gx, gw);
-        GCA_HIP_TRY(launch_tri_points(h->d_xyz, h->d_tv, h->n, q, gx, gw, out, s));
+    const bool sym = h->prm.sym_rules != 0;
+    auto tri_pts = [&](int q, bool sy, double *out) -> gca_status {
+        TriRule r;
+        if (!tri_rule(q, sy, r)) return set_error(GCA_EINVAL, "unsupported triangle rule");
+        GCA_HIP_TRY(launch_tri_points(h->d_xyz, h->d_tv, h->n, r, out, s));
         return GCA_OK;
     };
-    GCA_TRY(tri_pts(h->prm.q_r, h->d_qr));
+    GCA_TRY(tri_pts(h->prm.q_r, sym, h->d_qr));
     GCA_HIP_TRY(launch_local_points(h, s));
-    if (h->d_qnr != h->d_qr) GCA_TRY(tri_pts(h->prm.q_nr, h->d_qnr));
-    if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, h->d_qA));
-    if (h->d_qc != h->d_qr) GCA_TRY(tri_pts(h->prm.q_c, h->d_qc));
+    if (h->d_qnr != h->d_qr) GCA_TRY(tri_pts(h->prm.q_nr, sym, h->d_qnr));
+    if (h->d_qA != h->d_qr) GCA_TRY(tri_pts(h->prm.q_A, false, h->d_qA));
+    if (h->d_qc != h->d_qr) GCA_TRY(tri_pts(h->prm.q_c, sym, h->d_qc));
     if (h->n_piv_total > 0) GCA_HIP_TRY(launch_pivot_points(h, s));
     h->fz.basis_current = false;
     GCA_HIP_TRY(launch_frozen_basis(h, s));
@@ -1535,3 +1549,50 @@ void gca_destroy(gca_h2 h)
 }
 
 }  // extern "C"
+
+namespace gca {
+
+bool tri_rule(int q, bool sym, TriRule &r)
+{
+    r = TriRule{};
+    if (!sym) {
+        if (q < 1 || q * q > 64) return false;
+        double x[32], w[32];
+        gauss_legendre01(q, x, w);
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b) {
+                r.s1[r.np] = x[a];
+                r.s2[r.np] = x[a] * x[b];
+                r.w[r.np] = w[a] * w[b] * x[a];
+                ++r.np;
+            }
+        return true;
+    }
+    // fully symmetric rules: orbits (a, a, 1 - 2a) of barycentric points with
+    // barycentric weight w each; s1 = l1 + l2, s2 = l2, weight w / 2 on the
+    // reference triangle.  Degree 2 (q = 2): a = 1/6, w = 1/3.  Degree 4
+    // (q = 3, Strang-Fix / Dunavant): a = 0.445948490915965, w =
+    // 0.223381589678011 and a = 0.091576213509771, w = 0.109951743655322.
+    auto orbit = [&](double a, double w) {
+        const double b = 1.0 - 2.0 * a;
+        const double l[3][3] = {{b, a, a}, {a, b, a}, {a, a, b}};
+        for (auto &k : l) {
+            r.s1[r.np] = k[1] + k[2];
+            r.s2[r.np] = k[2];
+            r.w[r.np] = 0.5 * w;
+            ++r.np;
+        }
+    };
+    if (q == 2) {
+        orbit(1.0 / 6.0, 1.0 / 3.0);
+        return true;
+    }
+    if (q == 3) {
+        orbit(0.445948490915965, 0.223381589678011);
+        orbit(0.091576213509771, 0.109951743655322);
+        return true;
+    }
+    return false;
+}
+
+}  // namespace gca

@@ -338,6 +338,8 @@ struct gca_h2_s {
     double gl_x[32], gl_w[32];
     double gs_x[32], gs_w[32];       // Sauter-Schwab order q_s
 
+    // points per triangle of the regular, near-regular and coupling rules
+    int P_r = 0, P_nr = 0, P_c = 0;
     static constexpr int RING = 64;  // products whose phase events are retained
     hipEvent_t ev[RING][GCA_NPHASE + 1] = {};
     int64_t n_products = 0;
@@ -352,8 +354,19 @@ constexpr int NEAR_CW = 64;          // column chunk of the nearfield block rows
 
 // ---------------------------------------------------------- kernel launchers --
 // All launchers enqueue on `s` and return the launch status.
-hipError_t launch_tri_points(const double *xyz, const int32_t *tv, int64_t n, int q, const double *gx,
-                             const double *gw, double *out, hipStream_t s);
+// A rule on the reference triangle {0 <= s2 <= s1 <= 1}: point
+// P0 + s1 (P1 - P0) + s2 (P2 - P1), weight w times |(P1 - P0) x (P2 - P1)|;
+// the weights sum to 1/2.
+struct TriRule {
+    int np;
+    double s1[64], s2[64], w[64];
+};
+// Collapsed Gauss rule of order q, or (sym) the symmetric rule of the same
+// degree 2q - 2 (q = 2: 3 points, q = 3: 6 points).  False if unsupported.
+bool tri_rule(int q, bool sym, TriRule &r);
+
+hipError_t launch_tri_points(const double *xyz, const int32_t *tv, int64_t n, const TriRule &rule,
+                             double *out, hipStream_t s);
 hipError_t launch_green_A(const double *qA, int PA, const double *box, const int32_t *row_tri,
                           const int32_t *row_cl, const int64_t *row_out, int64_t nrows, int m, const double *glx,
                           const double *glw, double eta, double omega_scale, double *A, hipStream_t s);

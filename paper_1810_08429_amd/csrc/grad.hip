@@ -209,12 +209,11 @@ __global__ void __launch_bounds__(128) k_touching_grad(const double *xyz, const 
 }
 
 // ------------------------------------------------ regular pair derivatives --
-// Triangle rule point p = (a, b) of the collapsed Gauss rule: s1 = x_a,
-// s2 = x_a x_b, barycentric weights of the vertices (1 - s1, s1 - s2, s2).
-__device__ __forceinline__ void rule_beta(const Rule &R, int p, double beta[3])
+// Point p = (s1, s2) of a triangle rule: barycentric weights of the vertices
+// (1 - s1, s1 - s2, s2).
+__device__ __forceinline__ void rule_beta(const TriRule &R, int p, double beta[3])
 {
-    const int a = p / R.q, b = p - a * R.q;
-    const double s1 = R.x[a], s2 = R.x[a] * R.x[b];
+    const double s1 = R.s1[p], s2 = R.s2[p];
     beta[0] = 1 - s1;
     beta[1] = s1 - s2;
     beta[2] = s2;
@@ -223,7 +222,7 @@ __device__ __forceinline__ void rule_beta(const Rule &R, int p, double beta[3])
 // Near-regular pair list: both sides of d g_ij, weighted a_i b_j + a_j b_i.
 template <int P>
 __global__ void __launch_bounds__(128) k_nearreg_grad(const double *xyz, const int32_t *tv, const double *q,
-                                                      const int32_t *pa, const int32_t *pb, int64_t np, Rule R,
+                                                      const int32_t *pa, const int32_t *pb, int64_t np, TriRule R,
                                                       const double *ap, const double *bp, const int32_t *sa,
                                                       const int32_t *sb, double *gout)
 {
@@ -295,7 +294,7 @@ struct GradBlkArgs {
     const T *ca, *cb;          // NEAR: permuted a, b; FAR: forward transforms of a, b
     double *gout;
     int nblk, orient, cw;
-    Rule R;
+    TriRule R;
 };
 
 // Threads per row: blocks with at most 32 (64) rows give each row 4 (2)
@@ -523,7 +522,7 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
                                                    const int32_t *pivcol, const int64_t *arow_off,
                                                    const int32_t *arows, const int64_t *aj_off, const double *box,
                                                    const double *qA, const double *xyz, const int32_t *tv, int m_green,
-                                                   double eta, double omega_scale, Rule G, Rule RA,
+                                                   double eta, double omega_scale, Rule G, TriRule RA,
                                                    const double *Abar, double *gout)
 {
     const int c = blockIdx.x;
@@ -671,7 +670,7 @@ static hipError_t launch_grad_blocks_P(int P, GradBlkArgs<T> a, hipStream_t s)
                                (grad_blk_smem<T, PP>(a.cw)), s, a);                                      \
         }                                                                                               \
         break;
-        CASE(1) CASE(4) CASE(9) CASE(16)
+        CASE(1) CASE(3) CASE(4) CASE(6) CASE(9) CASE(16)
 #undef CASE
     default:
         return hipErrorInvalidValue;
@@ -686,19 +685,15 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
     const T *ap = f32 ? (const T *)w.apf : (const T *)w.ap;
     const T *bp = f32 ? (const T *)w.bpf : (const T *)w.bp;
     const T *xa = (const T *)w.xa, *xb = (const T *)w.xb, *ya = (const T *)w.ya, *yb = (const T *)w.yb;
-    double gx[32], gw[32];
-    gauss_legendre01(h->prm.q_r, gx, gw);
-    const Rule Rr = make_rule(gx, gw, h->prm.q_r);
-    gauss_legendre01(h->prm.q_nr, gx, gw);
-    const Rule Rnr = make_rule(gx, gw, h->prm.q_nr);
-    gauss_legendre01(h->prm.q_A, gx, gw);
-    const Rule RA = make_rule(gx, gw, h->prm.q_A);
+    const bool sym = h->prm.sym_rules != 0;
+    TriRule Rr, Rnr, RA, Rc;
+    if (!tri_rule(h->prm.q_r, sym, Rr) || !tri_rule(h->prm.q_nr, sym, Rnr) || !tri_rule(h->prm.q_A, false, RA) ||
+        !tri_rule(h->prm.q_c, sym, Rc))
+        return hipErrorInvalidValue;
     const Rule Rs = make_rule(h->gs_x, h->gs_w, h->prm.q_s);
     const Rule Rg = make_rule(h->gl_x, h->gl_w, h->prm.green_m);
-    gauss_legendre01(h->prm.q_c, gx, gw);
-    const Rule Rc = make_rule(gx, gw, h->prm.q_c);
-    const int Pr = h->prm.q_r * h->prm.q_r;
-    const int Pc = h->prm.q_c * h->prm.q_c;
+    const int Pr = h->P_r;
+    const int Pc = h->P_c;
     hipError_t e;
     // (i) nearfield blocks, both orientations
     {
@@ -762,7 +757,7 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
     }
     {
         const int64_t b = h->pl.off[3], np = h->pl.off[4] - b;
-        const int Pnr = h->prm.q_nr * h->prm.q_nr;
+        const int Pnr = h->P_nr;
         if (np) {
             dim3 g((unsigned)((np + 127) / 128)), blk(128);
             switch (Pnr) {
@@ -771,7 +766,7 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
         hipLaunchKernelGGL((k_nearreg_grad<PP>), g, blk, 0, s, h->d_xyz, h->d_tv, h->d_qnr, h->d_pa + b,   \
                            h->d_pb + b, np, Rnr, w.ap, w.bp, h->d_slot_a + b, h->d_slot_b + b, w.gn);       \
         break;
-                CASE(1) CASE(4) CASE(9) CASE(16) CASE(25)
+                CASE(1) CASE(3) CASE(4) CASE(6) CASE(9) CASE(16) CASE(25)
 #undef CASE
             default:
                 return hipErrorInvalidValue;

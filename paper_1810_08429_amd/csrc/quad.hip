@@ -627,7 +627,7 @@ __global__ void k_local_points(const double *q, int P, int64_t n, double *cent, 
 
 hipError_t launch_local_points(gca_h2_s *h, hipStream_t s)
 {
-    const int P = h->prm.q_r * h->prm.q_r;
+    const int P = h->P_r;
     hipLaunchKernelGGL(k_local_points, dim3((unsigned)((h->n + 127) / 128)), dim3(128), 0, s, h->d_qr, P, h->n,
                        h->d_cent, h->d_qloc32);
     return hipGetLastError();
@@ -654,7 +654,7 @@ __global__ void k_pivot_points(const int32_t *piv_cluster, const int32_t *piv, c
 
 hipError_t launch_pivot_points(gca_h2_s *h, hipStream_t s)
 {
-    const int P = h->prm.q_c * h->prm.q_c;
+    const int P = h->P_c;
     const int64_t ne = h->n_piv_total;
     if (ne == 0) return hipSuccess;
     const int64_t total = ne * P;
@@ -689,7 +689,7 @@ static hipError_t near_rows(gca_h2_s *h, const T *xp, T *npart, T *store, hipStr
     const int ng = h->n_near_groups;
     if (ng == 0) return hipSuccess;
     if (STORE ? store == nullptr : (xp == nullptr || npart == nullptr)) return hipErrorInvalidValue;
-    const int P = h->prm.q_r * h->prm.q_r;
+    const int P = h->P_r;
     NearArgs<T> a{};
     a.g_t = h->d_ng_t;
     a.g_ptr = h->d_ng_ptr;
@@ -719,7 +719,7 @@ static hipError_t near_rows(gca_h2_s *h, const T *xp, T *npart, T *store, hipStr
     case PP:                                                                                  \
         hipLaunchKernelGGL((k_near_rows<T, PP, STORE>), dim3(ng), dim3(BLK_THREADS), sm, s, a); \
         break;
-        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
+        CASE(1) CASE(3) CASE(4) CASE(6) CASE(9) CASE(16) CASE(25) CASE(36)
 #undef CASE
     default:
         return hipErrorInvalidValue;
@@ -733,7 +733,7 @@ static hipError_t far_rows(gca_h2_s *h, const T *xh, T *cpart, T *store, hipStre
     const int ng = h->n_far_groups;
     if (ng == 0) return hipSuccess;
     if (STORE ? store == nullptr : (xh == nullptr || cpart == nullptr)) return hipErrorInvalidValue;
-    const int P = h->prm.q_c * h->prm.q_c;   // the coupling rule
+    const int P = h->P_c;   // the coupling rule
     FarArgs<T> a{};
     a.g_t = h->d_fg_t;
     a.g_ptr = h->d_fg_ptr;
@@ -761,7 +761,7 @@ static hipError_t far_rows(gca_h2_s *h, const T *xh, T *cpart, T *store, hipStre
     case PP:                                                                                  \
         hipLaunchKernelGGL((k_far_rows<T, PP, STORE>), dim3(ng), dim3(BLK_THREADS), sm, s, a);  \
         break;
-        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
+        CASE(1) CASE(3) CASE(4) CASE(6) CASE(9) CASE(16) CASE(25) CASE(36)
 #undef CASE
     default:
         return hipErrorInvalidValue;
@@ -1175,7 +1175,7 @@ static hipError_t launch_regular_list(int P, const double *q, const int32_t *pa,
     case PP:                                                                                  \
         hipLaunchKernelGGL((k_nearreg<T, PP>), grid, blk, 0, s, q, pa, pb, np, sa, sb, out);   \
         break;
-        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36) CASE(49)
+        CASE(1) CASE(3) CASE(4) CASE(6) CASE(9) CASE(16) CASE(25) CASE(36) CASE(49)
 #undef CASE
     default:
         return hipErrorInvalidValue;
@@ -1187,7 +1187,7 @@ template <typename T>
 hipError_t launch_nearreg(gca_h2_s *h, T *nval, hipStream_t s)
 {
     int64_t b = h->pl.off[3], e = h->pl.off[4];
-    return launch_regular_list<T>(h->prm.q_nr * h->prm.q_nr, h->d_qnr, h->d_pa + b, h->d_pb + b, e - b,
+    return launch_regular_list<T>(h->P_nr, h->d_qnr, h->d_pa + b, h->d_pb + b, e - b,
                                   h->d_slot_a + b, h->d_slot_b + b, nval, s);
 }
 
@@ -1218,7 +1218,7 @@ hipError_t launch_entry_jobs(gca_h2_s *h, const EntryJobs &j, double *tmp64, flo
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    const int Pnr = h->prm.q_nr * h->prm.q_nr, Pr = h->prm.q_r * h->prm.q_r;
+    const int Pnr = h->P_nr, Pr = h->P_r;
     if (precision == GCA_FP64) {
         err = launch_regular_list<double>(Pnr, h->d_qnr, j.pa + j.off[3], j.pb + j.off[3], j.off[4] - j.off[3],
                                           nullptr, nullptr, tmp64 + j.off[3], s);

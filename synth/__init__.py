@@ -143,8 +143,9 @@ def workload(name: str):
     ellip_l6   : ellipsoid (1, 0.7, 0.4), 81920 triangles, jitter N(0, (1e-3 h)^2), seed 1
     sphere_l8  : unit sphere, 1310720 triangles, leaf 64, eta 2; Green order 5,
                  omega margin 1.5 diam / eta, eps 1e-5, coupling entries with the
-                 order-2 regular rule (the cheapest setting measured at <= 1e-4
-                 relative error of the product on this mesh)
+                 order-2 regular rule, symmetric triangle rules for disjoint pairs
+                 (6 points regular, 3 coupling) -- the cheapest setting measured at
+                 <= 1e-4 relative error of the product on this mesh
     """
     if name == "sphere_l3":
         return icosphere(3), dict(leaf=32, eta=2.0, green_m=3, eps=1e-6)
@@ -157,5 +158,5 @@ def workload(name: str):
         h = mean_edge_length(m)
         return jitter(m, 1e-3 * h, seed=1), dict(leaf=64, eta=2.0, green_m=3, eps=1e-5)
     if name == "sphere_l8":
-        return icosphere(8), dict(leaf=64, eta=2.0, green_m=5, eps=1e-5, omega_scale=1.5, q_c=2)
+        return icosphere(8), dict(leaf=64, eta=2.0, green_m=5, eps=1e-5, omega_scale=1.5, q_c=2, sym_rules=1)
     raise KeyError(name)

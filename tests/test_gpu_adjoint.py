@@ -116,3 +116,17 @@ def test_adjoint_without_admissible_blocks_equals_dense_gradient(torch, gca, orc
     g = H.bilinear_grad(u, u, alpha=0.5).cpu().numpy()
     ref = orc.Entries(m.verts, m.tris, p.q_r, p.q_nr, p.q_s).energy_grad_vertices(uh, np.arange(m.nv))
     assert np.abs(g - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_adjoint_with_symmetric_rules_equals_dense_gradient(torch, gca, orc):
+    """eta -> 0 with sym_rules = 1: the derivatives through the symmetric
+    rules' points (barycentric weights of each point) equal the oracle's
+    dense gradient with the same rules."""
+    m = jittered(2, seed=17)
+    p = gca.Params(eta=1e-6, eps=1e-6, sym_rules=1)
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, 16), p)
+    uh = synth.rhs_normal(m.nt, 1, seed=8)
+    u = torch.tensor(uh, device="cuda")
+    g = H.bilinear_grad(u, u, alpha=0.5).cpu().numpy()
+    ref = orc.Entries(m.verts, m.tris, p.q_r, p.q_nr, p.q_s, sym=True).energy_grad_vertices(uh, np.arange(m.nv))
+    assert np.abs(g - ref).max() < 1e-11 * np.abs(ref).max()

@@ -224,3 +224,59 @@ def test_coupling_rule_order_matches_oracle(torch, gca, orc):
     H3 = build(gca, m, 32, eta=2.0, eps=1e-5, q_c=orders(gca)[0])
     xt = torch.tensor(x, device="cuda")
     assert torch.equal(H0.matvec(xt), H3.matvec(xt))
+
+
+@pytest.fixture(scope="module")
+def c1_sym(orc, gca):
+    m = synth.icosphere(3)
+    ent = orc.Entries(m.verts, m.tris, 3, 3, 4, sym=True)
+    return m, ent, ent.dense()
+
+
+def test_symmetric_rule_entries_and_nearfield_match_oracle(torch, gca, orc, c1_sym):
+    """sym_rules = 1 (6-point symmetric rule for the disjoint classes): every
+    class through gca_entries equals the oracle with the same rules (FP64
+    1e-12; mixed 2e-6 for the disjoint classes), and with eta -> 0 the
+    product is the oracle's dense matrix times x."""
+    m, ent, G = c1_sym
+    H = build(gca, m, 32, eta=2.0, eps=1e-6, sym_rules=1)
+    rng = np.random.default_rng(5)
+    for k, (I, J) in class_samples(orc, ent, m.nt, rng, per_class=600).items():
+        ref = G[I, J]
+        got = H.entries(I, J).cpu().numpy()
+        assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-12, k
+        gm = H.entries(I, J, precision=gca.MIXED).cpu().numpy()
+        tol = 1e-12 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6
+        assert np.max(np.abs(gm - ref) / np.abs(ref)) < tol, k
+    H0 = build(gca, m, 32, eta=1e-6, eps=1e-6, sym_rules=1)
+    X = synth.rhs_normal(m.nt, 2, seed=1)
+    ref = G @ X
+    x = torch.tensor(X, device="cuda")
+    scale = np.abs(ref).max()
+    assert np.abs(H0.matvec(x).cpu().numpy() - ref).max() < 1e-12 * scale
+    assert np.abs(H0.matvec(x, precision=gca.MIXED).cpu().numpy() - ref).max() < 1e-5 * scale
+
+
+def test_symmetric_rule_h2_matches_oracle_step_by_step(torch, gca, orc):
+    """Jittered level-3 sphere, symmetric rules for the regular pairs (6
+    points) and for the coupling entries (q_c = 2: 3 points): the GPU product
+    equals the oracle's GCA-H^2 built with the same rules, and stays within
+    the compression tolerance of the dense matrix of the collapsed rules."""
+    base = synth.icosphere(3)
+    m = synth.jitter(base, 0.02 * synth.mean_edge_length(base), seed=7)
+    ent = orc.Entries(m.verts, m.tris, 3, 3, 4, sym=True)
+    ho = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, m=3, eps=1e-5, ent=ent, q=(3, 3, 4), q_c=2)
+    x = synth.rhs_normal(m.nt, 1, seed=3)
+    yo = orc.h2_matvec(ho, x)
+    H = build(gca, m, 32, eta=2.0, eps=1e-5, sym_rules=1, q_c=2)
+    xt = torch.tensor(x, device="cuda")
+    y = H.matvec(xt).cpu().numpy()
+    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) < 1e-10
+    ym = H.matvec(xt, precision=gca.MIXED).cpu().numpy()
+    assert np.linalg.norm(ym - yo) / np.linalg.norm(yo) < 2e-5
+    yd = orc.Entries(m.verts, m.tris, *orders(gca)).dense() @ x
+    assert np.linalg.norm(yo - yd) / np.linalg.norm(yd) < 1e-3
+    # stored blocks give the recomputed product
+    H.store_blocks(fp64=True, mixed=True)
+    ys = H.matvec(xt).cpu().numpy()
+    assert np.linalg.norm(ys - y) / np.linalg.norm(y) < 1e-13

@@ -114,17 +114,35 @@ def test_invalid_meshes_are_rejected(gca):
 
 @pytest.mark.parametrize("field,value", [("eta", 0.0), ("eta", float("inf")), ("eps", -1.0), ("eps", 1.0),
                                          ("green_m", 0), ("green_m", 7), ("q_s", 1), ("q_r", 0),
-                                         ("q_nr", 8), ("omega_scale", 0.0), ("q_c", 7), ("q_c", -1)])
+                                         ("q_nr", 8), ("omega_scale", 0.0), ("q_c", 7), ("q_c", -1),
+                                         ("sym_rules", 2), ("reserved", 1)])
 def test_invalid_parameters_are_rejected_before_device_work(gca, field, value):
     m = synth.icosphere(1)
     tree = gca.Tree(m.verts, m.tris, 8)
     p = gca.Params()
-    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    mesh = gca._MeshArrays(m.verts, m.tris)
+    if field == "reserved":
+        pc = p._c()
+        pc.reserved = value
+    else:
+        setattr(p, field, value)
+        pc = p._c()
+    code = gca.lib().gca_build(ctypes.byref(mesh.c), tree.h, ctypes.byref(pc), None, ctypes.byref(h))
+    assert code == -1, gca.lib().gca_last_error()
+    assert not h.value
+
+
+@pytest.mark.parametrize("orders", [(4, 3, 3), (3, 4, 3), (3, 3, 4), (1, 3, 3)])
+def test_symmetric_rules_need_orders_two_or_three(gca, orders):
+    m = synth.icosphere(1)
+    tree = gca.Tree(m.verts, m.tris, 8)
+    p = gca.Params(q_r=orders[0], q_nr=orders[1], q_c=orders[2], sym_rules=1)
     h = ctypes.c_void_p()
     mesh = gca._MeshArrays(m.verts, m.tris)
     pc = p._c()
     code = gca.lib().gca_build(ctypes.byref(mesh.c), tree.h, ctypes.byref(pc), None, ctypes.byref(h))
-    assert code == -1, gca.lib().gca_last_error()
+    assert code == -1 and "sym_rules" in gca.lib().gca_last_error().decode()
     assert not h.value
 
 
