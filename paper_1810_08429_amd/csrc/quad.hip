@@ -318,10 +318,12 @@ __device__ __forceinline__ void tile_pass(int rw, int cw, int c0, const Q4<T> *r
 
 // Wavefronts per SIMD the block kernels are compiled for: as many as the
 // registers of a tile allow without spilling (the row points of a lane take
-// 5 P values; 512 / waves VGPRs per lane), at most 5 (FP32) or 3 (FP64).
-// Measured on the level-8 sphere: FP32 nearfield 3.98 ms with the
-// compiler's own choice (103 VGPRs), 3.46 ms at 5, 3.79 ms at 6; FP64
-// nearfield 9.15 ms at 4 (88 bytes of spills), 8.91 ms at 3, 8.82 ms at 2.
+// 5 P values; 512 / waves VGPRs per lane), at most 6 (FP32 nearfield), 5
+// (FP32 coupling; 6 spills at 4 points) or 3 (FP64).  Measured on the
+// level-8 sphere: FP32 3x3 nearfield 3.98 ms with the compiler's own choice
+// (103 VGPRs), 3.46 ms at 5, 3.79 ms at 6; FP32 6-point nearfield 1.81 ms at
+// 5, 1.70 ms at 6; FP64 3x3 nearfield 9.15 ms at 4 (88 bytes of spills),
+// 8.91 ms at 3, 8.82 ms at 2.
 constexpr int blk_waves(int word_bytes, int P, int base, int cap)
 {
     const int need = 5 * P * (word_bytes / 4) + base;
@@ -329,7 +331,7 @@ constexpr int blk_waves(int word_bytes, int P, int base, int cap)
     return w < 1 ? 1 : (w > cap ? cap : w);
 }
 template <typename T, int P>
-constexpr int near_waves() { return blk_waves((int)sizeof(T), P, 48, sizeof(T) == 8 ? 3 : 5); }
+constexpr int near_waves() { return blk_waves((int)sizeof(T), P, 48, sizeof(T) == 8 ? 3 : 6); }
 template <typename T, int P>
 constexpr int far_waves() { return blk_waves((int)sizeof(T), P, 64, sizeof(T) == 8 ? 3 : 5); }
 
