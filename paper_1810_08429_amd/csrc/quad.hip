@@ -977,12 +977,17 @@ __device__ __forceinline__ void tri_vertices(const double *xyz, const int32_t *t
 }
 
 // identical triangles: J^2/(4 pi) * (1/3) * sum_d w_d [ 1/|eta e1 + e2| + 1/|e1 + eta e2| + 1/|-eta e1 + (1-eta) e2| ]
+// NQ > 0: the Gauss order as a compile-time constant (loops unrolled, the
+// points' loop-invariant parts formed once); NQ = 0: g.q at run time.
+template <int NQ>
 __device__ double ss_identical(const V3 P[3], const GaussQ &g)
 {
     V3 e1 = vsub(P[1], P[0]), e2 = vsub(P[2], P[1]);
     double J = cross_norm(e1, e2);
     double s = 0;
-    for (int d = 0; d < g.q; ++d) {
+    const int q = NQ ? NQ : g.q;
+#pragma unroll
+    for (int d = 0; d < q; ++d) {
         double t = g.x[d];
         double a = vrnorm(t * e1.x + e2.x, t * e1.y + e2.y, t * e1.z + e2.z);
         double b = vrnorm(e1.x + t * e2.x, e1.y + t * e2.y, e1.z + t * e2.z);
@@ -993,15 +998,19 @@ __device__ double ss_identical(const V3 P[3], const GaussQ &g)
 }
 
 // common edge P0 P1 (same parametrisation on both triangles): five 2D integrals
+template <int NQ>
 __device__ double ss_edge(const V3 P[3], const V3 Q[3], const GaussQ &g)
 {
     V3 e1 = vsub(P[1], P[0]), et = vsub(P[2], P[1]), es = vsub(Q[2], Q[1]);
     double Jt = cross_norm(e1, et), Js = cross_norm(e1, es);
     double s = 0;
-    for (int ia = 0; ia < g.q; ++ia) {
+    const int q = NQ ? NQ : g.q;
+#pragma unroll
+    for (int ia = 0; ia < q; ++ia) {
         const double h2 = g.x[ia];
         double sb = 0;
-        for (int ib = 0; ib < g.q; ++ib) {
+#pragma unroll
+        for (int ib = 0; ib < q; ++ib) {
             const double h3 = g.x[ib];
             // region 1 (no eta2 factor)
             double r1 = vrnorm(h2 * e1.x + h3 * et.x - (1 - h2) * es.x, h2 * e1.y + h3 * et.y - (1 - h2) * es.y,
@@ -1026,22 +1035,27 @@ __device__ double ss_edge(const V3 P[3], const V3 Q[3], const GaussQ &g)
 }
 
 // common vertex P0 = Q0: two 3D integrals
+template <int NQ>
 __device__ double ss_vertex(const V3 P[3], const V3 Q[3], const GaussQ &g)
 {
     V3 e1t = vsub(P[1], P[0]), e2t = vsub(P[2], P[1]);
     V3 e1s = vsub(Q[1], Q[0]), e2s = vsub(Q[2], Q[1]);
     double Jt = cross_norm(e1t, e2t), Js = cross_norm(e1s, e2s);
     double s = 0;
-    for (int ia = 0; ia < g.q; ++ia) {
+    const int q = NQ ? NQ : g.q;
+#pragma unroll
+    for (int ia = 0; ia < q; ++ia) {
         const double h1 = g.x[ia];
         // x-side points (1, eta1) and y-side points (1, eta1)
         const double ax = e1t.x + h1 * e2t.x, ay = e1t.y + h1 * e2t.y, az = e1t.z + h1 * e2t.z;
         const double bx = e1s.x + h1 * e2s.x, by = e1s.y + h1 * e2s.y, bz = e1s.z + h1 * e2s.z;
         double sa = 0;
-        for (int ib = 0; ib < g.q; ++ib) {
+#pragma unroll
+        for (int ib = 0; ib < q; ++ib) {
             const double h2 = g.x[ib];
             double sb = 0;
-            for (int ic = 0; ic < g.q; ++ic) {
+#pragma unroll
+            for (int ic = 0; ic < q; ++ic) {
                 const double h3 = g.x[ic];
                 const double cx = e1s.x + h3 * e2s.x, cy = e1s.y + h3 * e2s.y, cz = e1s.z + h3 * e2s.z;
                 const double dx = e1t.x + h3 * e2t.x, dy = e1t.y + h3 * e2t.y, dz = e1t.z + h3 * e2t.z;
@@ -1056,15 +1070,15 @@ __device__ double ss_vertex(const V3 P[3], const V3 Q[3], const GaussQ &g)
     return Jt * Js * INV4PI * s * (1.0 / 3.0);
 }
 
-template <int KIND>
+template <int KIND, int NQ>
 __device__ double touching_value(const double *xyz, const int32_t *tv, int pa, int pb, int code, const GaussQ &g)
 {
     V3 P[3], Q[3];
     tri_vertices(xyz, tv, pa, code & 15, P);
-    if (KIND == 0) return ss_identical(P, g);
+    if (KIND == 0) return ss_identical<NQ>(P, g);
     tri_vertices(xyz, tv, pb, (code >> 4) & 15, Q);
-    if (KIND == 1) return ss_edge(P, Q, g);
-    return ss_vertex(P, Q, g);
+    if (KIND == 1) return ss_edge<NQ>(P, Q, g);
+    return ss_vertex<NQ>(P, Q, g);
 }
 
 // Value of pair p goes to out[sa[p]] and out[sb[p]] (sb < 0: none) when slot
@@ -1076,7 +1090,9 @@ __global__ void __launch_bounds__(256) k_touching(const double *xyz, const int32
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    const double v = touching_value<KIND>(xyz, tv, pa[p], pb[p], code[p], g);
+    // the default Sauter-Schwab order 4 with unrolled loops
+    const double v = g.q == 4 ? touching_value<KIND, 4>(xyz, tv, pa[p], pb[p], code[p], g)
+                              : touching_value<KIND, 0>(xyz, tv, pa[p], pb[p], code[p], g);
     if (sa) {
         out[sa[p]] = v;
         if (sb[p] >= 0) out[sb[p]] = v;
