@@ -310,7 +310,14 @@ struct gca_h2_s {
     int64_t *d_tptr = nullptr, *d_nptr = nullptr;
     int32_t *d_tother = nullptr, *d_nother = nullptr;
     int32_t *d_slot_a = nullptr, *d_slot_b = nullptr;
-    double *d_tval = nullptr;        // touching values, row CSR (FP64)
+    // touching values of the product (FP64) in a leaf-ELL layout: leaf li
+    // owns tell_k[li] x nr columns from tell_off[li], entry (k, i) is the k-th
+    // touching partner of its row i (padding: value 0, partner = the row);
+    // pair p writes to tslot_a[p] and tslot_b[p] (-1: identical pair)
+    double *d_tval = nullptr;
+    int64_t *d_tell_off = nullptr;
+    int32_t *d_tell_k = nullptr, *d_tell_other = nullptr;
+    int32_t *d_tslot_a = nullptr, *d_tslot_b = nullptr;
     double *d_nval = nullptr;        // near-regular values, row CSR (FP64 path)
     float *d_nvalf = nullptr;        // near-regular values, row CSR (mixed path)
 

@@ -161,8 +161,9 @@ template hipError_t launch_backward<double>(gca_h2_s *, double *, hipStream_t);
 
 // Per leaf, thread per row: y|t^ = V_t yh_t + near partials + pair lists;
 // written back in the original triangle order.  The touching values (FP64)
-// and near-regular values (T) are stored in row CSRs aligned with their
-// column indices, so each row streams its own entries.
+// are stored per leaf in ELL form (partner k of row i at k * nr + i, so the
+// rows of a leaf read consecutive addresses), the near-regular values (T) in
+// a row CSR aligned with their column indices.
 // Workgroups are dealt to the 8 XCDs of the chip round-robin by id; this
 // bijection gives each XCD a contiguous range of leaves, so the neighbouring
 // positions a leaf's touching pairs read stay in that XCD's L2.
@@ -176,8 +177,9 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int32_t *node, const int32_t *rank,
                                                const int64_t *piv_off, const int64_t *v_off, const T *Vt,
                                                const T *yh, const int64_t *nslot_ptr, const int64_t *nslot,
-                                               const T *npart, const int64_t *tptr, const int32_t *tother,
-                                               const double *tval, const int64_t *nptr, const int32_t *nother,
+                                               const T *npart, const int64_t *tell_off, const int32_t *tell_k,
+                                               const int32_t *tother, const double *tval, const int64_t *nptr,
+                                               const int32_t *nother,
                                                const T *nval, const T *xp, const double *xp64,
                                                const int32_t *perm, double *y)
 {
@@ -193,7 +195,8 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
         const int pos = b + i;
         for (int64_t q = nptr[pos]; q < nptr[pos + 1]; ++q) acc += nval[q] * xp[nother[q]];
         double acc64 = 0;
-        for (int64_t q = tptr[pos]; q < tptr[pos + 1]; ++q) acc64 += tval[q] * xp64[tother[q]];
+        const int64_t t0 = tell_off[li] + i;
+        for (int k = 0; k < tell_k[li]; ++k) acc64 += tval[t0 + (int64_t)k * nr] * xp64[tother[t0 + (int64_t)k * nr]];
         y[perm[pos]] = (double)acc + acc64;
     }
 }
@@ -204,8 +207,8 @@ hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *
 {
     const T *Vt = std::is_same<T, float>::value ? (const T *)h->d_Vtf : (const T *)h->d_Vt;
     hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)h->leaves.size()), dim3(64), 0, s, h->d_leaves, h->d_node,
-                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_gnslot_ptr, h->d_gnslot, npart, h->d_tptr,
-                       h->d_tother, h->d_tval, h->d_nptr, h->d_nother, nval, xp, xp64, h->d_perm, y);
+                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_gnslot_ptr, h->d_gnslot, npart, h->d_tell_off,
+                       h->d_tell_k, h->d_tell_other, h->d_tval, h->d_nptr, h->d_nother, nval, xp, xp64, h->d_perm, y);
     return hipGetLastError();
 }
 template hipError_t launch_gather<float>(gca_h2_s *, const float *, const double *, const float *, const float *,

@@ -1122,13 +1122,13 @@ hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s)
         dim3 grid((unsigned)((np + 255) / 256)), blk(256);
         if (kind == 0)
             hipLaunchKernelGGL(k_touching<0>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
-                               h->d_pcode + b, np, g, h->d_slot_a + b, h->d_slot_b + b, tval);
+                               h->d_pcode + b, np, g, h->d_tslot_a + b, h->d_tslot_b + b, tval);
         else if (kind == 1)
             hipLaunchKernelGGL(k_touching<1>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
-                               h->d_pcode + b, np, g, h->d_slot_a + b, h->d_slot_b + b, tval);
+                               h->d_pcode + b, np, g, h->d_tslot_a + b, h->d_tslot_b + b, tval);
         else
             hipLaunchKernelGGL(k_touching<2>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
-                               h->d_pcode + b, np, g, h->d_slot_a + b, h->d_slot_b + b, tval);
+                               h->d_pcode + b, np, g, h->d_tslot_a + b, h->d_tslot_b + b, tval);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
