@@ -50,6 +50,44 @@ EVALS_PER_S_F32 = 1.0 / (5.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
 ALU_PEAK_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
 
 
+# FP64 ceiling of one dimension-reduced Sauter-Schwab evaluation (the
+# touching kernels): about 12 FP64 VALU operations (point difference,
+# squared norm, rsqrt refinement, weighted accumulate) and one FP64 rsqrt at
+# a quarter of the VALU rate.  FP64 vector peak 78.6 TFLOP/s = 3.93e13
+# FMA lane-ops/s.
+FP64_LANE_OPS_PER_S = 78.6e12 / 2
+SS_EVALS_PER_S = 1.0 / (12.0 / FP64_LANE_OPS_PER_S + 1.0 / (FP64_LANE_OPS_PER_S / 4))
+HBM_BYTES_PER_S = 8.0e12
+
+
+def phase_rooflines(st, params, P, Pc, ms):
+    """Fraction of its bound for every phase of the mixed product (per
+    product): the quadrature phases against the FP32 ALU ceiling (10 flops
+    per evaluation), the touching lists against the FP64 evaluation ceiling,
+    the transforms and the gather against HBM with their algorithmic bytes
+    (FP32 basis entries read once, vectors read or written once)."""
+    q = params.q_s
+    nv_, ne_ = st["basis_entries_leaf"], st["basis_entries_transfer"]
+    n = st["n"]
+    out = {}
+    for ph, flops in (("near_blocks", st["near_regular_pairs"] * P * P * FLOPS_PER_EVAL),
+                      ("coupling_blocks", st["coupling_entries"] * Pc * Pc * FLOPS_PER_EVAL)):
+        a = flops / (ms[ph] * 1e-3) / 1e12
+        out[ph] = {"bound": "alu", "achieved": a, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
+                   "frac": a / ALU_PEAK_F32_TFLOPS}
+    ev = st["n_ident"] * 3 * q + st["n_edge"] * 5 * q * q + st["n_vert"] * 2 * q ** 3
+    a = ev / (ms["touching"] * 1e-3)
+    out["touching"] = {"bound": "fp64 alu", "achieved": a, "peak": SS_EVALS_PER_S, "unit": "evaluations/s",
+                       "frac": a / SS_EVALS_PER_S}
+    for ph, byts in (("forward", 4 * (nv_ + ne_) + 4 * n),
+                     ("backward", 4 * ne_),
+                     ("gather", 4 * nv_ + 2 * (st["n_edge"] + st["n_vert"]) * 12 + st["n_ident"] * 12 + 8 * n)):
+        a = byts / (ms[ph] * 1e-3)
+        out[ph] = {"bound": "hbm", "achieved": a / 1e9, "peak": HBM_BYTES_PER_S / 1e9, "unit": "GB/s",
+                   "frac": a / HBM_BYTES_PER_S, "bytes": byts}
+    return out
+
+
 def rule_points(q, sym):
     """Points per triangle of the rule of order q: q^2 (collapsed Gauss) or
     the symmetric rule of the same degree (3 points for q = 2, 6 for q = 3)."""
@@ -300,6 +338,7 @@ def main():
                                          "near_regular_pairs", "rank_min", "rank_max", "rank_mean",
                                          "basis_bytes_fp64")},
         "roofline": roofline,
+        "phases_roofline": phase_rooflines(st, params, P, Pc, mean_mixed),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -116,6 +116,8 @@ typedef struct {
     int64_t store_entries_near;          /* entries of the stored nearfield block rows (masked pairs as zeros) */
     int32_t stored_mask;                 /* precisions with stored block rows (gca_store_blocks) */
     int32_t reserved_i;
+    int64_t basis_entries_leaf;          /* entries of the leaf bases V (sum |t^| r_t) */
+    int64_t basis_entries_transfer;      /* entries of the transfer matrices E (sum r_t r_parent) */
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,

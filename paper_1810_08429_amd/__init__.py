@@ -66,7 +66,8 @@ class _Stats(ctypes.Structure):
                         ("build_ms", ctypes.c_double), ("setup_ms", ctypes.c_double * 8),
                         ("phase_ms", ctypes.c_double * 10), ("store_entries_far", ctypes.c_int64),
                         ("store_entries_near", ctypes.c_int64), ("stored_mask", ctypes.c_int32),
-                        ("reserved_i", ctypes.c_int32)]
+                        ("reserved_i", ctypes.c_int32),
+                        ("basis_entries_leaf", ctypes.c_int64), ("basis_entries_transfer", ctypes.c_int64)]
 
 
 _lib = None

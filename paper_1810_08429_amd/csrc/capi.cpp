@@ -1554,6 +1554,8 @@ gca_status gca_stats(gca_h2 h, gca_stats_t *out)
     out->store_entries_near = h->n_near_store;
     out->stored_mask = h->stored_mask;
     out->reserved_i = 0;
+    out->basis_entries_leaf = h->n_v;
+    out->basis_entries_transfer = h->n_e;
     if (h->events && h->timed) {
         const int slot = (int)((h->n_products - 1) % gca_h2_s::RING);
         GCA_HIP_TRY(hipEventSynchronize(h->ev[slot][GCA_NPHASE]));
