@@ -56,9 +56,18 @@ __device__ __forceinline__ T col_dot(const T *M, int64_t ld, int m, const T *v, 
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// sum_{i0 <= i < i1} M[i * ld + k] v[i]: col_dot over a row range
+template <typename T>
+__device__ __forceinline__ T col_dot_range(const T *M, int64_t ld, int i0, int i1, const T *v, int k)
+{
+    return col_dot(M + (int64_t)i0 * ld, ld, i1 - i0, v + i0, k);
+}
+
 // forward transform for the clusters of one level (one wavefront per
-// cluster, lane per basis column k).  Leaf: V row-major |t^| x r.  Parent:
-// E_son row-major r_son x r.
+// cluster).  Leaf: V row-major |t^| x r.  Parent: E_son row-major
+// r_son x r.  With r <= 32 the two half-wavefronts take the two halves of
+// the rows of the same column k and add their sums across lane ^ 32 (twice
+// the active lanes, half the dependent loads); else a lane per column.
 template <typename T>
 __global__ void __launch_bounds__(64) k_forward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
                                                 const int64_t *piv_off, const int64_t *v_off, const int64_t *e_off,
@@ -67,16 +76,35 @@ __global__ void __launch_bounds__(64) k_forward(const int32_t *clusters, const i
     const int c = clusters[blockIdx.x];
     const int r = rank[c];
     const int s0 = node[5 * c + 2], s1 = node[5 * c + 3];
+    const int lane = threadIdx.x;
     T *out = xh + piv_off[c];
+    if (r <= 32) {
+        const int k = lane & 31, h = lane >> 5;
+        T acc = 0;
+        if (k < r) {
+            if (s0 < 0) {
+                const int b = node[5 * c], nr = node[5 * c + 1] - b, m = (nr + 1) >> 1;
+                acc = col_dot_range(V + v_off[c], r, h ? m : 0, h ? nr : m, xp + b, k);
+            } else {
+                const int r0 = rank[s0], r1 = rank[s1];
+                // half 0: son 0, half 1: son 1
+                acc = h ? col_dot(E + e_off[s1], r, r1, xh + piv_off[s1], k)
+                        : col_dot(E + e_off[s0], r, r0, xh + piv_off[s0], k);
+            }
+        }
+        acc += __shfl_xor(acc, 32, 64);
+        if (h == 0 && k < r) out[k] = acc;
+        return;
+    }
     if (s0 < 0) {
         const int b = node[5 * c], nr = node[5 * c + 1] - b;
         const T *Vc = V + v_off[c];
-        for (int k = threadIdx.x; k < r; k += 64) out[k] = col_dot(Vc, r, nr, xp + b, k);
+        for (int k = lane; k < r; k += 64) out[k] = col_dot(Vc, r, nr, xp + b, k);
     } else {
         const int r0 = rank[s0], r1 = rank[s1];
         const T *E0 = E + e_off[s0], *E1 = E + e_off[s1];
         const T *x0 = xh + piv_off[s0], *x1 = xh + piv_off[s1];
-        for (int k = threadIdx.x; k < r; k += 64) out[k] = col_dot(E0, r, r0, x0, k) + col_dot(E1, r, r1, x1, k);
+        for (int k = lane; k < r; k += 64) out[k] = col_dot(E0, r, r0, x0, k) + col_dot(E1, r, r1, x1, k);
     }
 }
 
@@ -128,7 +156,8 @@ template hipError_t launch_coupling_reduce<double>(gca_h2_s *, const int64_t *, 
 
 // backward transform for the clusters of one level below the root:
 // yh_c += E_c yh_parent (E_c column-major: Et[k * r_c + j]); one wavefront
-// per cluster, lane per basis column j
+// per cluster, lane per basis column j (with r_c <= 32 the two
+// half-wavefronts split the parent's rows and add across lane ^ 32)
 template <typename T>
 __global__ void __launch_bounds__(64) k_backward(const int32_t *clusters, const int32_t *node, const int32_t *rank,
                                                  const int64_t *piv_off, const int64_t *e_off, const T *Et, T *yh)
@@ -139,7 +168,16 @@ __global__ void __launch_bounds__(64) k_backward(const int32_t *clusters, const 
     const T *Ec = Et + e_off[c];
     const T *yp = yh + piv_off[par];
     T *yc = yh + piv_off[c];
-    for (int j = threadIdx.x; j < rc; j += 64) yc[j] += col_dot(Ec, rc, rp, yp, j);
+    const int lane = threadIdx.x;
+    if (rc <= 32) {
+        const int j = lane & 31, h = lane >> 5, m = (rp + 1) >> 1;
+        T acc = 0;
+        if (j < rc) acc = col_dot_range(Ec, rc, h ? m : 0, h ? rp : m, yp, j);
+        acc += __shfl_xor(acc, 32, 64);
+        if (h == 0 && j < rc) yc[j] += acc;
+        return;
+    }
+    for (int j = lane; j < rc; j += 64) yc[j] += col_dot(Ec, rc, rp, yp, j);
 }
 
 template <typename T>
