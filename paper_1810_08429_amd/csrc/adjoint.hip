@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
+#include "lanes.h"
 
 namespace gca {
 
@@ -332,9 +333,7 @@ __global__ void __launch_bounds__(256) k_row_solve_lds(ClusterArgs ca, const dou
                     const int q = t8 + 8 * sl;
                     if (q < j) acc += t[sl] * A[q * r + j];
                 }
-                acc += __shfl_xor(acc, 1, 8);
-                acc += __shfl_xor(acc, 2, 8);
-                acc += __shfl_xor(acc, 4, 8);
+                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
                 if (t8 == (j & 7)) {
 #pragma unroll
                     for (int sl = 0; sl < NS; ++sl)
@@ -348,9 +347,7 @@ __global__ void __launch_bounds__(256) k_row_solve_lds(ClusterArgs ca, const dou
                     const int q = t8 + 8 * sl;
                     if (q > j && q < r) acc += t[sl] * A[q * r + j];
                 }
-                acc += __shfl_xor(acc, 1, 8);
-                acc += __shfl_xor(acc, 2, 8);
-                acc += __shfl_xor(acc, 4, 8);
+                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
                 if (t8 == (j & 7)) {
 #pragma unroll
                     for (int sl = 0; sl < NS; ++sl)
@@ -373,9 +370,7 @@ __global__ void __launch_bounds__(256) k_row_solve_lds(ClusterArgs ca, const dou
                     const int q = t8 + 8 * sl;
                     if (q < j) acc += A[j * r + q] * t[sl];
                 }
-                acc += __shfl_xor(acc, 1, 8);
-                acc += __shfl_xor(acc, 2, 8);
-                acc += __shfl_xor(acc, 4, 8);
+                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
                 if (t8 == (j & 7)) {
 #pragma unroll
                     for (int sl = 0; sl < NS; ++sl)
@@ -389,9 +384,7 @@ __global__ void __launch_bounds__(256) k_row_solve_lds(ClusterArgs ca, const dou
                     const int q = t8 + 8 * sl;
                     if (q > j && q < r) acc += A[j * r + q] * t[sl];
                 }
-                acc += __shfl_xor(acc, 1, 8);
-                acc += __shfl_xor(acc, 2, 8);
-                acc += __shfl_xor(acc, 4, 8);
+                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
                 if (t8 == (j & 7)) {
 #pragma unroll
                     for (int sl = 0; sl < NS; ++sl)

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
+#include "lanes.h"
 
 namespace gca {
 
@@ -466,9 +467,7 @@ __global__ void __launch_bounds__(ACA_RT) k_aca_reg(const double *Rall, double *
                     const int j = t8 + 8 * sl;
                     if (j > k && j < r) acc += v[sl] * Lsh[j * r + k];
                 }
-                acc += __shfl_xor(acc, 1, 8);
-                acc += __shfl_xor(acc, 2, 8);
-                acc += __shfl_xor(acc, 4, 8);
+                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
                 const int sk = k >> 3;
                 if (t8 == (k & 7)) {
 #pragma unroll

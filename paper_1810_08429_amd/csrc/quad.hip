@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
+#include "lanes.h"
 
 namespace gca {
 
@@ -141,21 +142,10 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[P],
     return acc;
 }
 
-// Cross-lane moves for the tile reductions: DPP within a row of 16 lanes, an
-// LDS swizzle for lane ^ 16 and a permute for lane ^ 32 (64-bit values move
-// as two 32-bit halves).  Every lane of the wavefront must be active.
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v)
-{
-    const int2 h = __builtin_bit_cast(int2, v);
-    return __builtin_bit_cast(double, int2{__builtin_amdgcn_update_dpp(0, h.x, CTRL, 0xF, 0xF, false),
-                                           __builtin_amdgcn_update_dpp(0, h.y, CTRL, 0xF, 0xF, false)});
-}
+// Cross-lane moves for the tile reductions: DPP (lanes.h) within a row of 16
+// lanes, an LDS swizzle for lane ^ 16 and a permute for lane ^ 32 (64-bit
+// values move as two 32-bit halves).  Every lane of the wavefront must be
+// active.
 __device__ __forceinline__ float xor16_mov(float v)
 {   // ds_swizzle bit mode within 32 lanes: and 0x1f, or 0, xor 0x10
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
@@ -175,19 +165,6 @@ __device__ __forceinline__ double xor32_mov(double v, int addr)
     const int2 h = __builtin_bit_cast(int2, v);
     return __builtin_bit_cast(double, int2{__builtin_amdgcn_ds_bpermute(addr, h.x),
                                            __builtin_amdgcn_ds_bpermute(addr, h.y)});
-}
-
-// Sum over the N consecutive lanes of each aligned group (N = 1 .. 16); every
-// lane of the group receives the sum.  DPP: lane ^ 1, lane ^ 2, mirror in 8,
-// mirror in 16 -- each step pairs the two halves of the next larger group.
-template <int N, typename T>
-__device__ __forceinline__ T group_sum(T v)
-{
-    if constexpr (N >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-    if constexpr (N >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    if constexpr (N >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
-    if constexpr (N >= 16) v += dpp_mov<0x140>(v);  // row_mirror
-    return v;
 }
 
 // Sum over the lanes congruent modulo S (S = 1 .. 32); every lane receives
