@@ -13,7 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
-#include "lanes.h"
+#include "devfn.h"
 
 namespace gca {
 

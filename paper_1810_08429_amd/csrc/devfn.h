@@ -1,9 +1,26 @@
-// Cross-lane sums inside a wavefront by DPP (no LDS round trip).
+// Device helpers shared by the kernels: reciprocal square roots and
+// cross-lane sums inside a wavefront by DPP (no LDS round trip).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace gca {
+
+template <typename T>
+__device__ __forceinline__ T rsq(T x);
+template <>
+__device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+// FP64: the hardware estimate refined by one step of the binomial series
+// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y0^2, which triples the
+// number of correct bits; valid for positive finite arguments (no
+// special-value handling).
+template <>
+__device__ __forceinline__ double rsq<double>(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = __builtin_fma(-x * y, y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
 
 // DPP move within a row of 16 lanes (64-bit values move as two 32-bit
 // halves).  The source lanes must be active.

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
+#include "devfn.h"
 
 namespace gca {
 
@@ -67,7 +68,7 @@ __device__ inline void dlnJ(D3 P0, D3 P1, D3 P2, D3 g[3])
 // f = 1/|v|: accumulate  wt * df/dv = -wt v / |v|^3  and return 1/|v|
 __device__ __forceinline__ double inv_and_grad(D3 v, double wt, D3 &acc)
 {
-    double ri = rsqrt(dot(v, v));
+    double ri = rsq<double>(dot(v, v));
     acc = acc + (-wt * ri * ri * ri) * v;
     return ri;
 }
@@ -239,7 +240,7 @@ __global__ void __launch_bounds__(128) k_nearreg_grad(const double *xyz, const i
         const double wb = B[4 * bq + 3];
         for (int aq = 0; aq < P; ++aq) {
             const D3 d = D3{A[4 * aq], A[4 * aq + 1], A[4 * aq + 2]} - y;
-            const double ri = rsqrt(dot(d, d));
+            const double ri = rsq<double>(dot(d, d));
             const double wab = A[4 * aq + 3] * wb;
             S += wab * ri;
             const D3 f = (wab * ri * ri * ri) * d;
@@ -406,7 +407,7 @@ __global__ void __launch_bounds__(128) k_grad_blocks(GradBlkArgs<T> g)
                 for (int pa = 0; pa < P; ++pa) {
                     const T dx = xr[pa][0] - yx, dy = xr[pa][1] - yy, dz = xr[pa][2] - yz;
                     const T ri = (sizeof(T) == 4) ? (T)__builtin_amdgcn_rsqf((float)(dx * dx + dy * dy + dz * dz))
-                                                  : (T)rsqrt((double)(dx * dx + dy * dy + dz * dz));
+                                                  : (T)rsq<double>((double)(dx * dx + dy * dy + dz * dz));
                     const T tt = yw * ri;
                     Ga[pa] += tt;
                     const T t3 = tt * ri * ri;
@@ -522,7 +523,7 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
                                                    const int32_t *pivcol, const int64_t *arow_off,
                                                    const int32_t *arows, const int64_t *aj_off, const double *box,
                                                    const double *qA, const double *xyz, const int32_t *tv, int m_green,
-                                                   double eta, double omega_scale, Rule G, TriRule RA,
+                                                   double eta, double omega_scale, Rule G_, TriRule RA,
                                                    const double *Abar, double *gout)
 {
     const int c = blockIdx.x;
@@ -537,34 +538,60 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
         L[d] = bx[d] - delta;
         H[d] = bx[3 + d] + delta;
     }
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        const int pos = arows[ro + i];
+    // Green column l of the cluster: point z, outward normal n, and the scale
+    // of the single-layer (> 0) or double-layer (< 0) column; staged in LDS
+    // once per cluster when the rank allows
+    auto column = [&](int l, double *o) {
+        const int col = pivcol[piv_off[c] + l];
+        const int nu = col < k ? col : col - k;
+        const int f = nu / (m_green * m_green), ij = nu - f * m_green * m_green, gi = ij / m_green,
+                  gj = ij - gi * m_green;
+        const int ax = f >> 1, b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
+        o[3] = o[4] = o[5] = 0.0;
+        o[ax] = (f & 1) ? H[ax] : L[ax];
+        o[b1] = L[b1] + G_.x[gi] * (H[b1] - L[b1]);
+        o[b2] = L[b2] + G_.x[gj] * (H[b2] - L[b2]);
+        o[3 + ax] = (f & 1) ? 1.0 : -1.0;
+        const double w = G_.w[gi] * G_.w[gj] * (H[b1] - L[b1]) * (H[b2] - L[b2]);
+        o[6] = col < k ? sqrt(w) * INV4PI_G : -diam * sqrt(w) * INV4PI_G;
+    };
+    constexpr int CMAX = 64;
+    __shared__ double colz[CMAX * 7];
+    const bool staged = r <= CMAX;
+    if (staged)
+        for (int l = threadIdx.x; l < r; l += blockDim.x) column(l, colz + 7 * l);
+    __syncthreads();
+    // rows of at most 32 (64): 4 (2) threads per row take every 4th (2nd)
+    // Green column; their sums are added in LDS in a fixed order
+    constexpr int MAXG = PA <= 9 ? 4 : 1;
+    constexpr int NV = 1 + 3 * PA;
+    __shared__ double red[(MAXG == 1 ? 1 : 96) * NV];
+    const int G = (MAXG >= 4 && m <= 32) ? 4 : (MAXG >= 2 && m <= 64) ? 2 : 1;
+    const int RW = (int)blockDim.x / G, gq = threadIdx.x / RW, rt = threadIdx.x - gq * RW;
+    for (int i0 = 0; i0 < m; i0 += RW) {
+        const int i = i0 + rt;
+        const bool active = i < m;
+        const int pos = active ? arows[ro + i] : 0;
         const double *pts = qA + (size_t)pos * PA * 4;
-        const double *ab = Abar + aj_off[c] + (int64_t)i * r;
         double S = 0;          // sum_p W_p f_p weighted (for the d ln J term)
         D3 Hp[PA];
         for (int p = 0; p < PA; ++p) Hp[p] = {0, 0, 0};
-        for (int l = 0; l < r; ++l) {
+        const double *ab = Abar + aj_off[c] + (int64_t)(active ? i : 0) * r;
+        for (int l = gq; active && l < r; l += G) {
             const double om = ab[l];
             if (om == 0.0) continue;
-            const int col = pivcol[piv_off[c] + l];
-            const int nu = col < k ? col : col - k;
-            const int f = nu / (m_green * m_green), ij = nu - f * m_green * m_green, gi = ij / m_green,
-                      gj = ij - gi * m_green;
-            const int ax = f >> 1, b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
-            double z[3], n[3] = {0, 0, 0};
-            z[ax] = (f & 1) ? H[ax] : L[ax];
-            z[b1] = L[b1] + G.x[gi] * (H[b1] - L[b1]);
-            z[b2] = L[b2] + G.x[gj] * (H[b2] - L[b2]);
-            n[ax] = (f & 1) ? 1.0 : -1.0;
-            const double w = G.w[gi] * G.w[gj] * (H[b1] - L[b1]) * (H[b2] - L[b2]);
-            const double scale = col < k ? sqrt(w) * INV4PI_G : -diam * sqrt(w) * INV4PI_G;
-            const D3 nn = {n[0], n[1], n[2]};
+            double own[7];
+            if (!staged) column(l, own);
+            const double *cz = staged ? colz + 7 * l : own;
+            const double z[3] = {cz[0], cz[1], cz[2]};
+            const double scale = cz[6];
+            const bool single = scale > 0;
+            const D3 nn = {cz[3], cz[4], cz[5]};
             for (int p = 0; p < PA; ++p) {
                 const D3 d = D3{pts[4 * p] - z[0], pts[4 * p + 1] - z[1], pts[4 * p + 2] - z[2]};
-                const double ri = rsqrt(dot(d, d)), ri3 = ri * ri * ri;
+                const double ri = rsq<double>(dot(d, d)), ri3 = ri * ri * ri;
                 const double wq = pts[4 * p + 3] * om * scale;
-                if (col < k) {
+                if (single) {
                     S += wq * ri;                               // g = ri / 4 pi
                     Hp[p] = Hp[p] + (-wq * ri3) * d;            // grad_x ri = -d ri^3
                 } else {
@@ -574,6 +601,26 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
                 }
             }
         }
+        if (G > 1) {
+            __syncthreads();
+            if (gq > 0 && active) {
+                double *o = red + ((size_t)(gq - 1) * RW + rt) * NV;
+                o[0] = S;
+                for (int p = 0; p < PA; ++p) {
+                    o[1 + 3 * p] = Hp[p].x;
+                    o[2 + 3 * p] = Hp[p].y;
+                    o[3 + 3 * p] = Hp[p].z;
+                }
+            }
+            __syncthreads();
+            if (gq == 0 && active)
+                for (int q = 1; q < G; ++q) {
+                    const double *o = red + ((size_t)(q - 1) * RW + rt) * NV;
+                    S += o[0];
+                    for (int p = 0; p < PA; ++p) Hp[p] = Hp[p] + D3{o[1 + 3 * p], o[2 + 3 * p], o[3 + 3 * p]};
+                }
+        }
+        if (gq != 0 || !active) continue;
         const int32_t *v = tv + 3 * (size_t)pos;
         D3 lj[3];
         dlnJ(ldv3(xyz, v[0]), ldv3(xyz, v[1]), ldv3(xyz, v[2]), lj);

@@ -22,27 +22,11 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
-#include "lanes.h"
+#include "devfn.h"
 
 namespace gca {
 
 #define INV4PI 0.07957747154594766788
-
-template <typename T>
-__device__ __forceinline__ T rsq(T x);
-template <>
-__device__ __forceinline__ float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-// FP64: the hardware estimate refined by one step of the binomial series
-// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y0^2, which triples the
-// number of correct bits; valid for the positive finite arguments of regular
-// pairs (no special-value handling).
-template <>
-__device__ __forceinline__ double rsq<double>(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = __builtin_fma(-x * y, y, 1.0);
-    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
-}
 
 struct GaussQ {
     double x[32], w[32];
@@ -142,7 +126,7 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[P],
     return acc;
 }
 
-// Cross-lane moves for the tile reductions: DPP (lanes.h) within a row of 16
+// Cross-lane moves for the tile reductions: DPP (devfn.h) within a row of 16
 // lanes, an LDS swizzle for lane ^ 16 and a permute for lane ^ 32 (64-bit
 // values move as two 32-bit halves).  Every lane of the wavefront must be
 // active.
