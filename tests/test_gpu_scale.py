@@ -73,3 +73,23 @@ def test_ellipsoid_energy_adjoint_central_differences(torch, gca):
         assert abs(fd - an) <= 1e-5 * abs(an) + 1e-6 * scale, (v, fd, an)
     H.update_geometry(m.verts)
     H.close()
+
+
+def test_bench_operating_point_holds_on_the_level5_sphere(torch, gca, orc):
+    """The settings of the level-8 bench workload (Green order 5, omega margin
+    1.5, eps 1e-5, coupling rule order 2, symmetric triangle rules) on the
+    level-5 sphere (n = 20480): 512 sampled rows of the mixed and FP64
+    products against the oracle's dense rows with the collapsed rules stay
+    within the 1e-4 operating point."""
+    _, prm = synth.workload("sphere_l8")
+    m = synth.icosphere(5)
+    p = gca.Params(eta=prm["eta"], eps=prm["eps"], green_m=prm["green_m"], omega_scale=prm["omega_scale"],
+                   q_c=prm["q_c"], sym_rules=prm["sym_rules"])
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, prm["leaf"]), p)
+    x = synth.rhs_normal(m.nt, 1, seed=0)
+    rows = np.random.default_rng(12345).permutation(m.nt)[:512]
+    ref = orc.Entries(m.verts, m.tris, p.q_r, p.q_nr, p.q_s).matvec_rows(rows, x)
+    xt = torch.tensor(x, device="cuda")
+    for prec in (gca.FP64, gca.MIXED):
+        y = H.matvec(xt, precision=prec).cpu().numpy()[rows]
+        assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-4, prec
