@@ -198,6 +198,7 @@ __device__ __forceinline__ void tile_loop(int rw, int cw, int c0, const Q4<T> *r
     Q4<T> rr[P];
     T rq[P];
     T vacc = 0;
+    uint64_t mrow = 0;   // MASK: the lane's row mask word, loaded with the row
     int cur_tr = -1;
     // tile coordinates are wavefront-uniform
     int tr = k0 / nct, tc = k0 - tr * nct;
@@ -218,16 +219,17 @@ __device__ __forceinline__ void tile_loop(int rw, int cw, int c0, const Q4<T> *r
                 rr[p] = rowp[(size_t)il * P + p];
                 rq[p] = rown[(size_t)il * P + p];
             }
+            if (MASK) mrow = mask[il];
         }
         const bool valid = i < rw && j < cw;
         if (STORE) {
             T g = 0;
-            if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1)))
+            if (valid && !(MASK && ((mrow >> (c0 + j)) & 1)))
                 g = block_entry<T, P>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
             if (valid) st[(int64_t)i * ld + j] = g;
         } else {
             T u = 0;
-            if (valid && !(MASK && ((mask[i] >> (c0 + j)) & 1))) {
+            if (valid && !(MASK && ((mrow >> (c0 + j)) & 1))) {
                 const T g = block_entry<T, P>(rr, rq, colp + (size_t)j * P, coln + (size_t)j * P) * (T)INV4PI;
                 vacc = fmat(g, xc[j], vacc);
                 u = g * xr[i];
