@@ -793,38 +793,22 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             ell_k[li] = kmax;
             ell_off[li + 1] = ell_off[li] + (int64_t)kmax * (nd.end - nd.begin);
         }
-        std::vector<int32_t> ell_other(std::max<int64_t>(ell_off[nl], 1));
-        std::vector<int32_t> qmap(h->pl.t_other.size());
-        parallel_for((int64_t)nl, [&](int64_t l0, int64_t l1) {
-          for (int64_t li = l0; li < l1; ++li) {
-            const Node &nd = nodes[h->leaves[li]];
-            const int64_t nr = nd.end - nd.begin;
-            for (int64_t i = 0; i < nr; ++i) {
-                const int64_t pos = nd.begin + i, q0 = h->pl.t_ptr[pos], cnt = h->pl.t_ptr[pos + 1] - q0;
-                for (int64_t k = 0; k < ell_k[li]; ++k) {
-                    const int64_t e = ell_off[li] + k * nr + i;
-                    if (k < cnt) {
-                        ell_other[e] = h->pl.t_other[q0 + k];
-                        qmap[q0 + k] = (int32_t)e;
-                    } else {
-                        ell_other[e] = (int32_t)pos;
-                    }
-                }
-            }
-          }
-        }, 64);
-        const int64_t ntouch = h->pl.off[3];
-        std::vector<int32_t> sa(std::max<int64_t>(ntouch, 1), -1), sb(std::max<int64_t>(ntouch, 1), -1);
-        for (int64_t p = 0; p < ntouch; ++p) {
-            sa[p] = qmap[h->pl.slot_a[p]];
-            if (h->pl.slot_b[p] >= 0) sb[p] = qmap[h->pl.slot_b[p]];
-        }
         if (ell_off[nl] > INT32_MAX) return set_error(GCA_EINVAL, "touching value table exceeds 2^31 entries");
+        std::vector<int32_t> pos_li(std::max<int64_t>(n, 1));
+        for (size_t li = 0; li < nl; ++li) {
+            const Node &nd = nodes[h->leaves[li]];
+            for (int64_t pos = nd.begin; pos < nd.end; ++pos) pos_li[pos] = (int32_t)li;
+        }
+        const int64_t ntouch = h->pl.off[3];
+        int32_t *d_pos_li = nullptr, *d_qmap = nullptr;
         GCA_TRY(upload_new(h, &h->d_tell_off, ell_off, s));
         GCA_TRY(upload_new(h, &h->d_tell_k, ell_k, s));
-        GCA_TRY(upload_new(h, &h->d_tell_other, ell_other, s));
-        GCA_TRY(upload_new(h, &h->d_tslot_a, sa, s));
-        GCA_TRY(upload_new(h, &h->d_tslot_b, sb, s));
+        GCA_TRY(upload_new(h, &d_pos_li, pos_li, s));
+        GCA_TRY(dalloc(h, &h->d_tell_other, (size_t)std::max<int64_t>(ell_off[nl], 1)));
+        GCA_TRY(dalloc(h, &d_qmap, std::max<size_t>(h->pl.t_other.size(), 1)));
+        GCA_TRY(dalloc(h, &h->d_tslot_a, (size_t)std::max<int64_t>(ntouch, 1)));
+        GCA_TRY(dalloc(h, &h->d_tslot_b, (size_t)std::max<int64_t>(ntouch, 1)));
+        GCA_HIP_TRY(launch_touching_ell(h, d_pos_li, d_qmap, ntouch, s));
         GCA_TRY(dalloc(h, &h->d_tval, (size_t)std::max<int64_t>(ell_off[nl], 1)));
         // padding entries stay zero
         GCA_HIP_TRY(hipMemsetAsync(h->d_tval, 0, sizeof(double) * std::max<int64_t>(ell_off[nl], 1), s));

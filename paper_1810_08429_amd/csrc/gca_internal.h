@@ -372,6 +372,11 @@ struct TriRule {
 // degree 2q - 2 (q = 2: 3 points, q = 3: 6 points).  False if unsupported.
 bool tri_rule(int q, bool sym, TriRule &r);
 
+// Fills the leaf-ELL partner table of the touching values (padding: the row
+// itself) and the ELL slot of both rows of every touching pair, from the row
+// CSR (d_tptr, d_tother, d_slot_a/b); pos_li: leaf index of every position,
+// qmap: scratch of one int32 per CSR entry.
+hipError_t launch_touching_ell(gca_h2_s *h, const int32_t *pos_li, int32_t *qmap, int64_t ntouch, hipStream_t s);
 hipError_t launch_tri_points(const double *xyz, const int32_t *tv, int64_t n, const TriRule &rule,
                              double *out, hipStream_t s);
 hipError_t launch_green_A(const double *qA, int PA, const double *box, const int32_t *row_tri,

@@ -239,6 +239,52 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
     }
 }
 
+// thread per position: its k-th touching partner (or itself as padding) at
+// ELL entry tell_off[li] + k nr + i, and the CSR -> ELL map of its entries
+__global__ void k_touching_ell(int64_t n, const int32_t *pos_li, const int32_t *leaves, const int32_t *node,
+                               const int64_t *tell_off, const int32_t *tell_k, const int64_t *tptr,
+                               const int32_t *tother, int32_t *ell_other, int32_t *qmap)
+{
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n) return;
+    const int li = pos_li[pos];
+    const int c = leaves[li];
+    const int b = node[5 * c], nr = node[5 * c + 1] - b;
+    const int64_t q0 = tptr[pos], cnt = tptr[pos + 1] - q0;
+    const int64_t base = tell_off[li] + (pos - b);
+    for (int k = 0; k < tell_k[li]; ++k) {
+        const int64_t e = base + (int64_t)k * nr;
+        if (k < cnt) {
+            ell_other[e] = tother[q0 + k];
+            qmap[q0 + k] = (int32_t)e;
+        } else {
+            ell_other[e] = (int32_t)pos;
+        }
+    }
+}
+
+// thread per touching pair: the ELL slots of its two rows (-1: identical pair)
+__global__ void k_touching_slots(int64_t np, const int32_t *slot_a, const int32_t *slot_b, const int32_t *qmap,
+                                 int32_t *tslot_a, int32_t *tslot_b)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    tslot_a[p] = qmap[slot_a[p]];
+    tslot_b[p] = slot_b[p] >= 0 ? qmap[slot_b[p]] : -1;
+}
+
+hipError_t launch_touching_ell(gca_h2_s *h, const int32_t *pos_li, int32_t *qmap, int64_t ntouch, hipStream_t s)
+{
+    if (h->n > 0)
+        hipLaunchKernelGGL(k_touching_ell, dim3((unsigned)((h->n + 255) / 256)), dim3(256), 0, s, h->n, pos_li,
+                           h->d_leaves, h->d_node, h->d_tell_off, h->d_tell_k, h->d_tptr, h->d_tother,
+                           h->d_tell_other, qmap);
+    if (ntouch > 0)
+        hipLaunchKernelGGL(k_touching_slots, dim3((unsigned)((ntouch + 255) / 256)), dim3(256), 0, s, ntouch,
+                           h->d_slot_a, h->d_slot_b, qmap, h->d_tslot_a, h->d_tslot_b);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *yh, const T *npart,
                          const T *nval, double *y, hipStream_t s)
