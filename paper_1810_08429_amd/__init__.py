@@ -35,6 +35,7 @@ EXPORTED = [
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
     "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
     "h2_bilinear_grad", "gca_store_blocks",
+    "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
 ]
 
 
@@ -101,6 +102,9 @@ def lib():
     L.gca_solve_refined.argtypes = [P, P, P, D, I32, D, I32, P, P, P]
     L.gca_phase_times.argtypes = [P, I64, P, P]
     L.gca_store_blocks.argtypes = [P, I32, P]
+    L.gca_lin_vertex_triangles.argtypes = [P, I64, I64, P, P]
+    L.gca_lin_merge.argtypes = [P, P, P, P, P, I32, I32, P, P, P, P]
+    L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, P, P, P]
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
     L.gca_last_error.argtypes = []
@@ -108,7 +112,8 @@ def lib():
     for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
-                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks"):
+                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks",
+                 "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -400,3 +405,57 @@ def energy(H: "H2", u, verts=None, precision=FP64):
     if verts is None:
         verts = torch.zeros((0,), dtype=torch.float64, device=u.device)
     return _fns()[1].apply(u, verts, H, precision)
+
+
+# ---------------------------------------------------------------------------
+# Continuous piecewise-linear nodal basis (Section 5)
+
+LIN_MAX_GATHER, LIN_MAX_SET, LIN_MAX_BLOCK_SET, LIN_MAX_TRIS, LIN_MAX_DEGREE = 2048, 1024, 64, 192, 16
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def lin_vertex_triangles(tris, nv):
+    """The sets T_i (gca_lin_vertex_triangles, host): (off[nv + 1], list[3 nt])
+    as int32 numpy arrays."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    nt = int(tris.shape[0])
+    off = np.zeros(nv + 1, dtype=np.int32)
+    lst = np.zeros(max(3 * nt, 1), dtype=np.int32)
+    _check(lib().gca_lin_vertex_triangles(tris.ctypes.data_as(ctypes.c_void_p), nt, int(nv),
+                                          off.ctypes.data_as(ctypes.c_void_p),
+                                          lst.ctypes.data_as(ctypes.c_void_p)))
+    return off, lst[:3 * nt]
+
+
+def lin_merge(vt_off, vt_list, tri, set_off, set_vtx, cap, stream=None):
+    """Merged triangle lists of vertex subsets (gca_lin_merge).  Inputs are
+    int32 CUDA tensors; returns (tri[nsets, cap], loc[nsets, cap, 3],
+    count[nsets]) as CUDA tensors (count -1 where a limit is exceeded)."""
+    import torch
+    nsets = int(set_off.numel()) - 1
+    dev = set_off.device
+    out_tri = torch.full((max(nsets, 1), cap), -1, dtype=torch.int32, device=dev)
+    out_loc = torch.full((max(nsets, 1), cap, 3), -1, dtype=torch.int32, device=dev)
+    out_count = torch.zeros(max(nsets, 1), dtype=torch.int32, device=dev)
+    _check(lib().gca_lin_merge(_vp(vt_off), _vp(vt_list), _vp(tri), _vp(set_off), _vp(set_vtx), nsets, int(cap),
+                               _vp(out_tri), _vp(out_loc), _vp(out_count), _stream_ptr(stream)))
+    return out_tri[:nsets], out_loc[:nsets], out_count[:nsets]
+
+
+def lin_blocks(xyz, tri, merged, set_off, blk_row, blk_col, ld, q, sym=False, stream=None):
+    """Dense FP64 linear-basis blocks (gca_lin_blocks) over the merged lists
+    `merged` = (tri, loc, count) of lin_merge.  Returns (out[nblk, ld],
+    status[nblk]) as CUDA tensors."""
+    import torch
+    m_tri, m_loc, m_count = merged
+    cap = int(m_tri.shape[1])
+    nblk = int(blk_row.numel())
+    out = torch.empty((max(nblk, 1), ld), dtype=torch.float64, device=xyz.device)
+    status = torch.empty(max(nblk, 1), dtype=torch.int32, device=xyz.device)
+    _check(lib().gca_lin_blocks(_vp(xyz), _vp(tri), _vp(m_tri), _vp(m_loc), _vp(m_count), cap, _vp(set_off),
+                                _vp(blk_row), _vp(blk_col), nblk, int(ld), int(q), int(bool(sym)),
+                                _vp(out), _vp(status), _stream_ptr(stream)))
+    return out[:nblk], status[:nblk]

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgca.so")
 BUILD = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["quad.hip", "basis.hip", "h2.hip", "solve.hip", "adjoint.hip", "grad.hip"]
+HIP_SOURCES = ["quad.hip", "basis.hip", "h2.hip", "solve.hip", "adjoint.hip", "grad.hip", "linear.hip"]
 HOST_SOURCES = ["host.cpp", "capi.cpp"]
 
 

@@ -25,7 +25,8 @@ def gca():
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "gca.h")).read()
+    src = "".join(open(os.path.join(ROOT, "include", h)).read()
+                  for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:gca_status|void|const char \*)\s*(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
@@ -34,6 +35,7 @@ def declared_functions():
 def test_every_declared_symbol_is_exported(gca):
     names = declared_functions()
     assert "gca_build" in names and "h2_matvec" in names and len(names) >= 14
+    assert "gca_lin_merge" in names and "gca_lin_blocks" in names
     L = ctypes.CDLL(gca.LIB_PATH)
     for n in names:
         assert hasattr(L, n), n
@@ -168,3 +170,39 @@ def test_null_arguments(gca):
     assert L.gca_tree_build(None, 8, None) == -1
     L.gca_destroy(None)
     L.gca_tree_destroy(None)
+
+
+def test_lin_vertex_triangles_host(gca):
+    # host sets T_i equal the oracle's set definition; invalid meshes are rejected
+    from oracle import linear as L
+    m = synth.icosphere(3)
+    off, lst = gca.lin_vertex_triangles(m.tris, m.nv)
+    T = L.vertex_triangles(m.tris, m.nv)
+    assert all(list(lst[off[i]:off[i + 1]]) == T[i] for i in range(m.nv))
+    for bad in ([[0, 1, 1]], [[0, 1, 3]], [[-1, 1, 2]]):
+        with pytest.raises(gca.Error):
+            gca.lin_vertex_triangles(np.array(bad), 3)
+    off, lst = gca.lin_vertex_triangles(np.zeros((0, 3), np.int32), 4)
+    assert list(off) == [0] * 5 and lst.size == 0
+
+
+def test_lin_entry_points_validate_arguments(gca):
+    # argument checks run before any device work (NULL device pointers are fine here)
+    L = ctypes.CDLL(gca.LIB_PATH)
+    L.gca_lin_merge.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int32] * 2 + [ctypes.c_void_p] * 4
+    assert L.gca_lin_merge(None, None, None, None, None, -1, 8, None, None, None, None) == -1
+    assert L.gca_lin_merge(None, None, None, None, None, 1, 0, None, None, None, None) == -1
+    assert L.gca_lin_merge(None, None, None, None, None, 1, 4096, None, None, None, None) == -1
+    assert L.gca_lin_merge(None, None, None, None, None, 0, 8, None, None, None, None) == 0
+    assert L.gca_lin_merge(None, None, None, None, None, 2, 8, None, None, None, None) == -1
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, P, P, P]
+    args = lambda nblk, q, sym, cap=8, ld=16: (None, None, None, None, None, cap, None, None, None, nblk, ld, q, sym,
+                                                None, None, None)
+    assert L.gca_lin_blocks(*args(0, 3, 0)) == 0
+    assert L.gca_lin_blocks(*args(1, 3, 0)) == -1       # NULL pointers
+    assert L.gca_lin_blocks(*args(0, 5, 0)) == -1       # 25-point rule exceeds 16 points
+    assert L.gca_lin_blocks(*args(0, 4, 1)) == -1       # no symmetric rule of order 4
+    assert L.gca_lin_blocks(*args(0, 3, 2)) == -1
+    assert L.gca_lin_blocks(*args(0, 3, 0, cap=0)) == -1
+    assert L.gca_lin_blocks(*args(-1, 3, 0)) == -1
