@@ -60,6 +60,15 @@ SS_EVALS_PER_S = 1.0 / (12.0 / FP64_LANE_OPS_PER_S + 1.0 / (FP64_LANE_OPS_PER_S 
 HBM_BYTES_PER_S = 8.0e12
 
 
+# FP64 ceiling of the linear-basis block kernel per kernel evaluation: 3 FP64
+# subtractions, 3 for |x - y|^2, 4 for the refined rsqrt and its quarter-rate
+# v_rsq_f64 (4 issue slots), 3 FMAs for the three column-corner moments, and
+# the 27 FMAs that fold the P column sums into the nine corner moments of the
+# pair, shared by its P evaluations of one row point.
+def lin_evals_per_s(P):
+    return FP64_LANE_OPS_PER_S / (13.0 + 4.0 + 27.0 / P)
+
+
 def phase_rooflines(st, params, P, Pc, ms):
     """Fraction of its bound for every phase of the mixed product (per
     product): the quadrature phases against the FP32 ALU ceiling (10 flops
@@ -132,9 +141,94 @@ def parse():
                     help="timed products per precision in stored-block mode (0 disables it)")
     ap.add_argument("--grad-steps", type=int, default=3,
                     help="timed calls of the energy gradient per precision (0 disables it)")
+    ap.add_argument("--lin-blocks", type=int, default=16384,
+                    help="linear-basis blocks (32 x 32 vertices) in the piecewise-linear leg (0 disables it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
+
+
+def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
+    """Piecewise-linear nodal basis (Section 5) on the workload's mesh: nblk
+    blocks, rows and columns each 32 vertices drawn at random from the 256
+    nearest to a random centre (a stand-in for pivot sets of 32 vertices in a
+    cluster), centres at least 0.1 apart.  Times the merge of all 2 nblk
+    subsets and the block assembly with HIP events on the current stream."""
+    from scipy.spatial import cKDTree
+    import ctypes
+    rng = np.random.default_rng(seed)
+    c = rng.integers(mesh.nv, size=2 * nblk)
+    while True:
+        d = np.linalg.norm(mesh.verts[c[0::2]] - mesh.verts[c[1::2]], axis=1)
+        bad = np.nonzero(d < 0.1)[0]
+        if bad.size == 0:
+            break
+        c[2 * bad + 1] = rng.integers(mesh.nv, size=bad.size)
+    _, nb = cKDTree(mesh.verts).query(mesh.verts[c], k=256)
+    pick = np.argsort(rng.random(nb.shape), axis=1)[:, :32]
+    sets = np.take_along_axis(nb, pick, axis=1).astype(np.int32)
+    off, lst = gca.lin_vertex_triangles(mesh.tris, mesh.nv)
+    cuda = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt).cuda()
+    xyz, tri = cuda(mesh.verts, torch.float64), cuda(mesh.tris, torch.int32)
+    vt_off, vt_list = cuda(off, torch.int32), cuda(lst, torch.int32)
+    set_off = cuda(np.arange(0, 32 * 2 * nblk + 1, 32), torch.int32)
+    set_vtx = cuda(sets.reshape(-1), torch.int32)
+    cap, ld, ns = 192, 32 * 32, 2 * nblk
+    m_tri = torch.empty((ns, cap), dtype=torch.int32, device="cuda")
+    m_loc = torch.empty((ns, cap, 3), dtype=torch.int32, device="cuda")
+    m_cnt = torch.empty(ns, dtype=torch.int32, device="cuda")
+    br = cuda(np.arange(0, ns, 2), torch.int32)
+    bc = cuda(np.arange(1, ns, 2), torch.int32)
+    out = torch.empty((nblk, ld), dtype=torch.float64, device="cuda")
+    status = torch.empty(nblk, dtype=torch.int32, device="cuda")
+    L = gca.lib()
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def merge():
+        gca._check(L.gca_lin_merge(vp(vt_off), vp(vt_list), vp(tri), vp(set_off), vp(set_vtx), ns, cap,
+                                   vp(m_tri), vp(m_loc), vp(m_cnt), sp))
+
+    def blocks():
+        gca._check(L.gca_lin_blocks(vp(xyz), vp(tri), vp(m_tri), vp(m_loc), vp(m_cnt), cap, vp(set_off), vp(br),
+                                    vp(bc), nblk, ld, q, int(sym), vp(out), vp(status), sp))
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    merge_ms = timed(merge)
+    blocks_ms = timed(blocks)
+    cnt = m_cnt.cpu().numpy().astype(np.int64)
+    st = status.cpu().numpy()
+    if (cnt < 0).any() or (st != 0).any():
+        raise RuntimeError("linear-basis workload exceeded a kernel limit or has touching blocks")
+    P = rule_points(q, sym)
+    evals = int((cnt[0::2] * cnt[1::2]).sum()) * P * P
+    ach = evals / (blocks_ms * 1e-3)
+    peak = lin_evals_per_s(P)
+    res = {"workload": f"{nblk} blocks of 32 x 32 vertices on the workload mesh ({mesh.nv} vertices), each "
+                       f"subset 32 of the 256 vertices nearest a random centre (seed {seed}), block centres >= 0.1 "
+                       f"apart; regular rule {'symmetric' if sym else 'collapsed Gauss'} order {q} "
+                       f"({P} points) on both triangles, FP64",
+           "merge_ms": merge_ms, "subsets_per_s": ns / (merge_ms * 1e-3),
+           "blocks_ms": blocks_ms, "entries_per_s": nblk * ld / (blocks_ms * 1e-3),
+           "merged_rows_mean": float(cnt.mean()), "kernel_evaluations": evals,
+           "roofline": {"bound": "fp64 alu", "achieved": ach, "peak": peak, "unit": "evaluations/s",
+                        "frac": ach / peak, "kernel": f"k_lin_blocks<{P}>"},
+           "steps": steps}
+    print(f"[bench] linear basis: merge {merge_ms:.3f} ms ({ns} subsets), blocks {blocks_ms:.3f} ms "
+          f"({nblk} blocks, {ach:.3e} evals/s = {100 * ach / peak:.1f}% of FP64 ceiling)",
+          file=sys.stderr, flush=True)
+    return res
 
 
 def main():
@@ -249,6 +343,10 @@ def main():
                   f"{stored[name]['block_rows_GBps']:.0f} GB/s", file=sys.stderr, flush=True)
         H.store_blocks(False, False)
 
+    linear = None
+    if a.lin_blocks > 0:
+        linear = linear_basis(gca, torch, mesh, a.lin_blocks, max(a.stored_steps, 3), 2)
+
     phases = gca.PHASES
     mean_mixed = dict(zip(phases, ph_mixed.mean(axis=0).tolist()))
     mean_fp64 = dict(zip(phases, ph_fp64.mean(axis=0).tolist()))
@@ -330,6 +428,7 @@ def main():
         "fp64": {"value": n / dt_fp64, "unit": "DoF/s", "ms_per_step": dt_fp64 * 1e3, "steps": fsteps},
         "energy_gradient": grad,
         "stored_blocks": stored,
+        "linear_basis": linear,
         "mixed_over_fp64": dt_fp64 / dt_mixed,
         "rel_err_sampled_rows": rel,
         "phases_ms": {"mixed": mean_mixed, "fp64": mean_fp64},

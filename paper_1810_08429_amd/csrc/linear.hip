@@ -38,8 +38,7 @@ constexpr int NSET = GCA_LIN_MAX_SET;
 constexpr int BSET = GCA_LIN_MAX_BLOCK_SET;
 constexpr int TMAX = GCA_LIN_MAX_TRIS;
 constexpr int DEG = GCA_LIN_MAX_DEGREE;
-constexpr int SCMAX = 16;                        // column triangles per chunk
-constexpr int MC = 6144;                         // FP64 moments per chunk (48 KiB)
+constexpr int MV = 3712;                         // FP64 corner moments per chunk (29 KiB)
 constexpr int EPT = BSET * BSET / LT;            // block entries per thread
 constexpr uint64_t PAD = ~0ull;
 
@@ -183,22 +182,37 @@ __device__ __forceinline__ double load_tri(const double *xyz, const int32_t *tri
     return sqrt(cx * cx + cy * cy + cz * cz);
 }
 
-// Append corner entries (row * 3 + corner) of a merged list to the per-vertex
-// lists, then sort each list so that the reduction order is fixed.  Returns
-// through *bad when a vertex has more than DEG rows.
-__device__ void vertex_lists(const int32_t *loc, int nrow, int nv, int (*vl)[DEG], int *vc, int *bad)
+// Corner numbering of a merged list: corner (row r, c) with a local vertex
+// gets the next number in (row, corner) order, -1 otherwise (map[r][c]);
+// base[r] is the first number of row r, base[nrow] the total.  Then the
+// per-vertex lists of corner numbers, ascending (the reduction order), and
+// *bad when a vertex has more than DEG corners or an index is out of range.
+__device__ void corner_lists(const int32_t *loc, int nrow, int nv, int (*map)[3], int *base, int (*vl)[DEG],
+                             int *vc, int *sh, int *bad)
 {
     const int tid = threadIdx.x;
+    const int per = (nrow + LT - 1) / LT;
+    const int r0 = min(nrow, tid * per), r1 = min(nrow, r0 + per);
+    int cnt = 0;
+    for (int r = r0; r < r1; ++r)
+        for (int c = 0; c < 3; ++c) cnt += loc[3 * r + c] >= 0;
+    int total;
+    int k = wg_exscan(cnt, sh, &total);
+    for (int r = r0; r < r1; ++r) {
+        base[r] = k;
+        for (int c = 0; c < 3; ++c) map[r][c] = loc[3 * r + c] >= 0 ? k++ : -1;
+    }
+    if (tid == 0) base[nrow] = total;
     for (int i = tid; i < nv; i += LT) vc[i] = 0;
     __syncthreads();
     for (int x = tid; x < 3 * nrow; x += LT) {
         const int l = loc[x];
-        if (l >= 0 && l < nv) {
-            const int p = atomicAdd(&vc[l], 1);
-            if (p < DEG) vl[l][p] = x;
-            else *bad = 1;
-        } else if (l >= nv) {
+        if (l >= nv) {
             *bad = 1;
+        } else if (l >= 0) {
+            const int p = atomicAdd(&vc[l], 1);
+            if (p < DEG) vl[l][p] = map[x / 3][x - 3 * (x / 3)];
+            else *bad = 1;
         }
     }
     __syncthreads();
@@ -218,18 +232,50 @@ __device__ void vertex_lists(const int32_t *loc, int nrow, int nv, int (*vl)[DEG
     __syncthreads();
 }
 
+// Stages triangle t: vertex ids, |J|, and either its P quadrature points
+// (P <= 3: 3 P doubles) or its vertices (9 doubles).
+template <int P>
+__device__ __forceinline__ void stage_tri(const LinArgs &A, int t, double *X, int *V, double *jac)
+{
+    double Y[9];
+    *jac = load_tri(A.xyz, A.tri, t, Y, V);
+    if constexpr (P <= 3) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                X[3 * p + d] = Y[d] + A.R.s1[p] * (Y[3 + d] - Y[d]) + A.R.s2[p] * (Y[6 + d] - Y[3 + d]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) X[e] = Y[e];
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void point(const LinArgs &A, const double *X, int p, double *x)
+{
+    if constexpr (P <= 3) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = X[3 * p + d];
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = X[d] + A.R.s1[p] * (X[3 + d] - X[d]) + A.R.s2[p] * (X[6 + d] - X[3 + d]);
+    }
+}
+
 template <int P>
 __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
 {
-    __shared__ double px_r[TMAX][9];
-    __shared__ double jac_r[TMAX];
-    __shared__ int tv_r[TMAX][3];
-    __shared__ double px_c[SCMAX][9];
-    __shared__ double jac_c[SCMAX];
-    __shared__ int tv_c[SCMAX][3];
+    __shared__ double px[2][TMAX][9];      // points (P <= 3) or vertices of every row / column triangle
+    __shared__ double jac[2][TMAX];
+    __shared__ int tv[2][TMAX][3];
+    __shared__ int cmap[2][TMAX][3];       // corner numbers (row corners rho, column corners kappa)
+    __shared__ int cbase[TMAX + 1];        // first column corner of each column triangle
+    __shared__ int rbase[TMAX + 1];
     __shared__ int vl[2][BSET][DEG];
     __shared__ int vc[2][BSET];
-    __shared__ double mc[MC];
+    __shared__ int sh[LT];
+    __shared__ double V[MV];               // used moments of a chunk: V[rho * kc + kappa - k0]
     __shared__ int bad, touch;
 
     const int b = blockIdx.x, tid = threadIdx.x;
@@ -248,10 +294,13 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
         touch = 0;
     }
     const int32_t *rtri = A.m_tri + (int64_t)rs * A.cap, *ctri = A.m_tri + (int64_t)cs * A.cap;
-    for (int t = tid; t < nT; t += LT) jac_r[t] = load_tri(A.xyz, A.tri, rtri[t], px_r[t], tv_r[t]);
-    __syncthreads();
-    vertex_lists(A.m_loc + (int64_t)rs * A.cap * 3, nT, n, vl[0], vc[0], &bad);
-    vertex_lists(A.m_loc + (int64_t)cs * A.cap * 3, nS, m, vl[1], vc[1], &bad);
+    for (int x = tid; x < nT + nS; x += LT) {
+        const int side = x >= nT, t = side ? x - nT : x;
+        stage_tri<P>(A, (side ? ctri : rtri)[t], px[side][t], tv[side][t], &jac[side][t]);
+    }
+    corner_lists(A.m_loc + (int64_t)rs * A.cap * 3, nT, n, cmap[0], rbase, vl[0], vc[0], sh, &bad);
+    corner_lists(A.m_loc + (int64_t)cs * A.cap * 3, nS, m, cmap[1], cbase, vl[1], vc[1], sh, &bad);
+    const int NR = rbase[nT], NC = cbase[nS];
 
     double acc[EPT];
     int cp[EPT];
@@ -260,43 +309,45 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
         acc[k] = 0.0;
         cp[k] = 0;
     }
-    const int sc_max = max(1, min(SCMAX, MC / (9 * max(nT, 1))));
+    // column corners per chunk: at least one whole triangle (NR <= 3 TMAX)
+    const int kmax = NR > 0 ? MV / NR : 3 * TMAX;
     constexpr double inv4pi = 0.07957747154594767;   // 1 / (4 pi)
-    for (int s0 = 0; s0 < nS; s0 += sc_max) {
-        const int sc = min(sc_max, nS - s0);
-        for (int sl = tid; sl < sc; sl += LT) jac_c[sl] = load_tri(A.xyz, A.tri, ctri[s0 + sl], px_c[sl], tv_c[sl]);
-        __syncthreads();
-        // pair moments of this chunk: index sl * nT + t
+    for (int s0 = 0; s0 < nS;) {
+        // last triangle s1 with cbase[s1] - cbase[s0] <= kmax (same for every thread)
+        int lo = s0 + 1, hi = nS;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cbase[mid] - cbase[s0] <= kmax) lo = mid;
+            else hi = mid - 1;
+        }
+        const int s1 = lo, sc = s1 - s0;
+        const int k0 = cbase[s0], kc = cbase[s1] - k0;
         for (int pi = tid; pi < sc * nT; pi += LT) {
-            const int sl = pi / nT, t = pi - sl * nT;
+            const int sl = pi / nT, t = pi - sl * nT, s = s0 + sl;
             bool tch = false;
 #pragma unroll
             for (int u = 0; u < 3; ++u)
 #pragma unroll
-                for (int v = 0; v < 3; ++v) tch |= tv_r[t][u] == tv_c[sl][v];
+                for (int v = 0; v < 3; ++v) tch |= tv[0][t][u] == tv[1][s][v];
             if (tch) touch = 1;
-            const double *X = px_r[t], *Y = px_c[sl];
+            const double *X = px[0][t], *Y = px[1][s];
             double y[P][3];
 #pragma unroll
-            for (int q = 0; q < P; ++q)
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    y[q][d] = Y[d] + A.R.s1[q] * (Y[3 + d] - Y[d]) + A.R.s2[q] * (Y[6 + d] - Y[3 + d]);
+            for (int q = 0; q < P; ++q) point<P>(A, Y, q, y[q]);
             double M[9];
 #pragma unroll
             for (int e = 0; e < 9; ++e) M[e] = 0.0;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 double x[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    x[d] = X[d] + A.R.s1[p] * (X[3 + d] - X[d]) + A.R.s2[p] * (X[6 + d] - X[3 + d]);
+                point<P>(A, X, p, x);
                 double u0 = 0.0, u1 = 0.0, u2 = 0.0;
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const double dx = x[0] - y[q][0], dy = x[1] - y[q][1], dz = x[2] - y[q][2];
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    const double g = tch ? 0.0 : rsq<double>(r2);
+                    // a pair with a common vertex may give inf / NaN here: its
+                    // block is reported with status 1 and written as zeros
+                    const double g = rsq<double>(dx * dx + dy * dy + dz * dz);
                     u0 += g * A.R.wl[q][0];
                     u1 += g * A.R.wl[q][1];
                     u2 += g * A.R.wl[q][2];
@@ -308,12 +359,20 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
                     M[3 * a + 2] += A.R.wl[p][a] * u2;
                 }
             }
-            const double f = jac_r[t] * jac_c[sl] * inv4pi;
+            const double f = jac[0][t] * jac[1][s] * inv4pi;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) mc[9 * pi + e] = M[e] * f;
+            for (int a = 0; a < 3; ++a) {
+                const int rho = cmap[0][t][a];
+                if (rho < 0) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int kap = cmap[1][s][c];
+                    if (kap >= 0) V[rho * kc + kap - k0] = M[3 * a + c] * f;
+                }
+            }
         }
         __syncthreads();
-        // entries: rows of column vertex j inside this chunk, in ascending order
+        // entries: column corners of vertex j inside this chunk, ascending
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             const int e = tid + k * LT;
@@ -322,21 +381,16 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
                 double a = acc[k];
                 int c = cp[k];
                 for (; c < vc[1][j]; ++c) {
-                    const int s3 = vl[1][j][c];
-                    const int s = s3 / 3 - s0;
-                    if (s >= sc) break;
-                    const int bb = s3 - 3 * (s3 / 3);
-                    for (int r = 0; r < vc[0][i]; ++r) {
-                        const int t3 = vl[0][i][r];
-                        const int t = t3 / 3, aa = t3 - 3 * t;
-                        a += mc[9 * (s * nT + t) + 3 * aa + bb];
-                    }
+                    const int kap = vl[1][j][c] - k0;
+                    if (kap >= kc) break;
+                    for (int r = 0; r < vc[0][i]; ++r) a += V[vl[0][i][r] * kc + kap];
                 }
                 acc[k] = a;
                 cp[k] = c;
             }
         }
         __syncthreads();
+        s0 = s1;
     }
     const int st = bad ? 2 : (touch ? 1 : 0);
 #pragma unroll
