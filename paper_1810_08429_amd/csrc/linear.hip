@@ -38,25 +38,26 @@ constexpr int NSET = GCA_LIN_MAX_SET;
 constexpr int BSET = GCA_LIN_MAX_BLOCK_SET;
 constexpr int TMAX = GCA_LIN_MAX_TRIS;
 constexpr int DEG = GCA_LIN_MAX_DEGREE;
-constexpr int MV = 3712;                         // FP64 corner moments per chunk (29 KiB)
-constexpr int EPT = BSET * BSET / LT;            // block entries per thread
+constexpr int MV = 3680;                         // FP64 corner moments per chunk (28.75 KiB)
+constexpr int LB = 512;                          // threads per workgroup of the block kernel
 constexpr uint64_t PAD = ~0ull;
 
-// Exclusive prefix sum over the workgroup; *total receives the sum.  Every
-// thread must call it.
+// Exclusive prefix sum over a workgroup of NT threads; *total receives the
+// sum.  Every thread must call it.
+template <int NT = LT>
 __device__ int wg_exscan(int v, int *sh, int *total)
 {
     const int tid = threadIdx.x;
     sh[tid] = v;
     __syncthreads();
-    for (int d = 1; d < LT; d <<= 1) {
+    for (int d = 1; d < NT; d <<= 1) {
         const int add = tid >= d ? sh[tid - d] : 0;
         __syncthreads();
         sh[tid] += add;
         __syncthreads();
     }
     const int incl = sh[tid];
-    *total = sh[LT - 1];
+    *total = sh[NT - 1];
     __syncthreads();
     return incl - v;
 }
@@ -191,21 +192,21 @@ __device__ void corner_lists(const int32_t *loc, int nrow, int nv, int (*map)[3]
                              int *vc, int *sh, int *bad)
 {
     const int tid = threadIdx.x;
-    const int per = (nrow + LT - 1) / LT;
+    const int per = (nrow + LB - 1) / LB;
     const int r0 = min(nrow, tid * per), r1 = min(nrow, r0 + per);
     int cnt = 0;
     for (int r = r0; r < r1; ++r)
         for (int c = 0; c < 3; ++c) cnt += loc[3 * r + c] >= 0;
     int total;
-    int k = wg_exscan(cnt, sh, &total);
+    int k = wg_exscan<LB>(cnt, sh, &total);
     for (int r = r0; r < r1; ++r) {
         base[r] = k;
         for (int c = 0; c < 3; ++c) map[r][c] = loc[3 * r + c] >= 0 ? k++ : -1;
     }
     if (tid == 0) base[nrow] = total;
-    for (int i = tid; i < nv; i += LT) vc[i] = 0;
+    for (int i = tid; i < nv; i += LB) vc[i] = 0;
     __syncthreads();
-    for (int x = tid; x < 3 * nrow; x += LT) {
+    for (int x = tid; x < 3 * nrow; x += LB) {
         const int l = loc[x];
         if (l >= nv) {
             *bad = 1;
@@ -216,7 +217,7 @@ __device__ void corner_lists(const int32_t *loc, int nrow, int nv, int (*map)[3]
         }
     }
     __syncthreads();
-    for (int i = tid; i < nv; i += LT) {
+    for (int i = tid; i < nv; i += LB) {
         const int c = min(vc[i], DEG);
         for (int a = 1; a < c; ++a) {
             const int v = vl[i][a];
@@ -263,8 +264,9 @@ __device__ __forceinline__ void point(const LinArgs &A, const double *X, int p, 
     }
 }
 
-template <int P>
-__global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
+// EPT block entries per thread (n m <= EPT LB); two workgroups per CU.
+template <int P, int EPT>
+__global__ void __launch_bounds__(LB, 2) k_lin_blocks(LinArgs A)
 {
     __shared__ double px[2][TMAX][9];      // points (P <= 3) or vertices of every row / column triangle
     __shared__ double jac[2][TMAX];
@@ -274,7 +276,7 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
     __shared__ int rbase[TMAX + 1];
     __shared__ int vl[2][BSET][DEG];
     __shared__ int vc[2][BSET];
-    __shared__ int sh[LT];
+    __shared__ int sh[LB];
     __shared__ double V[MV];               // used moments of a chunk: V[rho * kc + kappa - k0]
     __shared__ int bad, touch;
 
@@ -284,8 +286,8 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
     const int nT = A.m_count[rs], nS = A.m_count[cs];
     const int64_t nm = (int64_t)n * m;
     double *out = A.out + (int64_t)b * A.ld;
-    if (n > BSET || m > BSET || nT < 0 || nS < 0 || nT > TMAX || nS > TMAX) {
-        for (int64_t e = tid; e < nm; e += LT) out[e] = 0.0;
+    if (n > BSET || m > BSET || nm > EPT * LB || nT < 0 || nS < 0 || nT > TMAX || nS > TMAX) {
+        for (int64_t e = tid; e < nm; e += LB) out[e] = 0.0;
         if (tid == 0) A.status[b] = 2;
         return;
     }
@@ -294,7 +296,7 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
         touch = 0;
     }
     const int32_t *rtri = A.m_tri + (int64_t)rs * A.cap, *ctri = A.m_tri + (int64_t)cs * A.cap;
-    for (int x = tid; x < nT + nS; x += LT) {
+    for (int x = tid; x < nT + nS; x += LB) {
         const int side = x >= nT, t = side ? x - nT : x;
         stage_tri<P>(A, (side ? ctri : rtri)[t], px[side][t], tv[side][t], &jac[side][t]);
     }
@@ -322,7 +324,7 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
         }
         const int s1 = lo, sc = s1 - s0;
         const int k0 = cbase[s0], kc = cbase[s1] - k0;
-        for (int pi = tid; pi < sc * nT; pi += LT) {
+        for (int pi = tid; pi < sc * nT; pi += LB) {
             const int sl = pi / nT, t = pi - sl * nT, s = s0 + sl;
             bool tch = false;
 #pragma unroll
@@ -375,7 +377,7 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
         // entries: column corners of vertex j inside this chunk, ascending
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-            const int e = tid + k * LT;
+            const int e = tid + k * LB;
             if (e < nm) {
                 const int i = e / m, j = e - i * m;
                 double a = acc[k];
@@ -395,7 +397,7 @@ __global__ void __launch_bounds__(LT) k_lin_blocks(LinArgs A)
     const int st = bad ? 2 : (touch ? 1 : 0);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-        const int e = tid + k * LT;
+        const int e = tid + k * LB;
         if (e < nm) out[e] = st ? 0.0 : acc[k];
     }
     if (tid == 0) A.status[b] = st;
@@ -470,12 +472,16 @@ gca_status gca_lin_blocks(const double *xyz, const int32_t *tri, const int32_t *
         a.R.wl[p][2] = r.w[p] * r.s2[p];
     }
     hipStream_t s = (hipStream_t)stream;
-    switch (r.np) {
-#define CASE(PP)                                                                    \
-    case PP:                                                                        \
-        hipLaunchKernelGGL(k_lin_blocks<PP>, dim3(nblk), dim3(LT), 0, s, a);        \
+    // entries per thread from the caller's stride (ld >= n m of every block)
+    const int ept = ld <= 2 * LB ? 2 : (ld <= 4 * LB ? 4 : 8);
+    switch (r.np * 16 + ept) {
+#define CASE(PP, EE)                                                                    \
+    case PP * 16 + EE:                                                                  \
+        hipLaunchKernelGGL((k_lin_blocks<PP, EE>), dim3(nblk), dim3(LB), 0, s, a);      \
         break;
-        CASE(1) CASE(3) CASE(4) CASE(6) CASE(9) CASE(16)
+#define CASES(PP) CASE(PP, 2) CASE(PP, 4) CASE(PP, 8)
+        CASES(1) CASES(3) CASES(4) CASES(6) CASES(9) CASES(16)
+#undef CASES
 #undef CASE
     default:
         return set_error(GCA_EINVAL, "unsupported rule size");
