@@ -324,8 +324,15 @@ __global__ void __launch_bounds__(LB, 2) k_lin_blocks(LinArgs A)
         }
         const int s1 = lo, sc = s1 - s0;
         const int k0 = cbase[s0], kc = cbase[s1] - k0;
-        for (int pi = tid; pi < sc * nT; pi += LB) {
-            const int sl = pi / nT, t = pi - sl * nT, s = s0 + sl;
+        // pair pi = sl * nT + t, advanced by LB without a division per pair
+        const int nt1 = max(nT, 1), dsl = LB / nt1, dt = LB - dsl * nt1;
+        int sl = tid / nt1, t = tid - sl * nt1;
+        for (int pi = tid; pi < sc * nT; pi += LB, t += dt, sl += dsl) {
+            if (t >= nT) {
+                t -= nT;
+                ++sl;
+            }
+            const int s = s0 + sl;
             bool tch = false;
 #pragma unroll
             for (int u = 0; u < 3; ++u)
