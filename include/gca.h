@@ -48,7 +48,9 @@ typedef enum {
  * GCA_FP64 : every quadrature, transfer and accumulation in FP64.
  * GCA_MIXED: regular-pair quadrature (nearfield and coupling), kernel
  *            evaluation and basis transfers in FP32 with FP32 accumulation;
- *            touching pairs (Sauter-Schwab) in FP64. */
+ *            touching pairs (Sauter-Schwab): edge vectors and surface
+ *            elements in FP64, the Gauss loops of the regularised integrands
+ *            in FP32, values kept in FP64. */
 typedef enum { GCA_FP64 = 0, GCA_MIXED = 1 } gca_precision;
 
 /* Flat triangle mesh (host memory).  xyz: nv x 3 vertex coordinates (FP64,

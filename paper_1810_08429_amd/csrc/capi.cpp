@@ -917,7 +917,7 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     // stored mode: the list values were computed with the blocks
     if (first && !stored && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
     mark(7);
-    if (first && !stored && (e = launch_touching(h, h->d_tval, s)) != hipSuccess) return e;
+    if (first && !stored && (e = launch_touching(h, h->d_tval, s, sizeof(T) == 4)) != hipSuccess) return e;
     mark(8);
     if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, nval, y, s)) != hipSuccess) return e;
     mark(9);

@@ -407,7 +407,8 @@ template <typename T>
 hipError_t launch_apply_stored(gca_h2_s *h, bool nearfield, const T *x, const T *G, T *part, hipStream_t s);
 template <typename T>
 hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s);
-hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s);
+// Touching-pair values (FP64 table); fp32: the Gauss loops in FP32.
+hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s, bool fp32 = false);
 template <typename T>
 hipError_t launch_nearreg(gca_h2_s *h, T *nval, hipStream_t s);
 template <typename T>

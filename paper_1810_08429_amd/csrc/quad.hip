@@ -907,31 +907,42 @@ template hipError_t launch_apply_stored<float>(gca_h2_s *, bool, const float *, 
 template hipError_t launch_apply_stored<double>(gca_h2_s *, bool, const double *, const double *, double *,
                                                 hipStream_t);
 
-// -------------------------------------------------- touching pairs (FP64) --
+// ------------------------------------------------------- touching pairs --
+// FP64 by default.  T = float (the mixed product): vertices are read and the
+// edge vectors and surface elements formed in FP64, then the Gauss loops run
+// in FP32 -- the dimension-reduced integrands below are smooth, so FP32 only
+// adds rounding of the order of 1e-7 relative to the pair's value.
 
 __constant__ int c_perm[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}, {2, 1, 0}};
 
+template <typename T = double>
 struct V3 {
-    double x, y, z;
+    T x, y, z;
 };
-__device__ __forceinline__ V3 vsub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ double vnorm(V3 a) { return sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
+template <typename T>
+__device__ __forceinline__ V3<T> vsub(V3<double> a, V3<double> b)
+{
+    return {(T)(a.x - b.x), (T)(a.y - b.y), (T)(a.z - b.z)};
+}
 // the Sauter-Schwab integrands are evaluated at interior Gauss points, where
 // the squared distances are positive and finite
-__device__ __forceinline__ double vrnorm(double x, double y, double z) { return rsq<double>(x * x + y * y + z * z); }
-__device__ __forceinline__ double cross_norm(V3 a, V3 b)
+template <typename T>
+__device__ __forceinline__ T vrnorm(T x, T y, T z) { return rsq<T>(x * x + y * y + z * z); }
+template <typename T>
+__device__ __forceinline__ double cross_norm(V3<T> a, V3<T> b)
 {
-    double cx = a.y * b.z - a.z * b.y, cy = a.z * b.x - a.x * b.z, cz = a.x * b.y - a.y * b.x;
+    const double ax = a.x, ay = a.y, az = a.z, bx = b.x, by = b.y, bz = b.z;
+    double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
     return sqrt(cx * cx + cy * cy + cz * cz);
 }
 
-__device__ __forceinline__ V3 ldv(const double *xyz, int v)
+__device__ __forceinline__ V3<double> ldv(const double *xyz, int v)
 {
     return {xyz[3 * (size_t)v], xyz[3 * (size_t)v + 1], xyz[3 * (size_t)v + 2]};
 }
 
 // Ordered vertices of a triangle: code indexes c_perm.
-__device__ __forceinline__ void tri_vertices(const double *xyz, const int32_t *tv, int pos, int code, V3 P[3])
+__device__ __forceinline__ void tri_vertices(const double *xyz, const int32_t *tv, int pos, int code, V3<double> P[3])
 {
     const int32_t *v = tv + 3 * (size_t)pos;
     P[0] = ldv(xyz, v[c_perm[code][0]]);
@@ -942,111 +953,114 @@ __device__ __forceinline__ void tri_vertices(const double *xyz, const int32_t *t
 // identical triangles: J^2/(4 pi) * (1/3) * sum_d w_d [ 1/|eta e1 + e2| + 1/|e1 + eta e2| + 1/|-eta e1 + (1-eta) e2| ]
 // NQ > 0: the Gauss order as a compile-time constant (loops unrolled, the
 // points' loop-invariant parts formed once); NQ = 0: g.q at run time.
-template <int NQ>
-__device__ double ss_identical(const V3 P[3], const GaussQ &g)
+template <int NQ, typename T = double>
+__device__ double ss_identical(const V3<double> P[3], const GaussQ &g)
 {
-    V3 e1 = vsub(P[1], P[0]), e2 = vsub(P[2], P[1]);
-    double J = cross_norm(e1, e2);
-    double s = 0;
+    const V3<T> e1 = vsub<T>(P[1], P[0]), e2 = vsub<T>(P[2], P[1]);
+    const double J = cross_norm(vsub<double>(P[1], P[0]), vsub<double>(P[2], P[1]));
+    T s = 0;
     const int q = NQ ? NQ : g.q;
 #pragma unroll
     for (int d = 0; d < q; ++d) {
-        double t = g.x[d];
-        double a = vrnorm(t * e1.x + e2.x, t * e1.y + e2.y, t * e1.z + e2.z);
-        double b = vrnorm(e1.x + t * e2.x, e1.y + t * e2.y, e1.z + t * e2.z);
-        double c = vrnorm(-t * e1.x + (1 - t) * e2.x, -t * e1.y + (1 - t) * e2.y, -t * e1.z + (1 - t) * e2.z);
-        s += g.w[d] * (a + b + c);
+        const T t = (T)g.x[d];
+        T a = vrnorm<T>(t * e1.x + e2.x, t * e1.y + e2.y, t * e1.z + e2.z);
+        T b = vrnorm<T>(e1.x + t * e2.x, e1.y + t * e2.y, e1.z + t * e2.z);
+        T c = vrnorm<T>(-t * e1.x + (1 - t) * e2.x, -t * e1.y + (1 - t) * e2.y, -t * e1.z + (1 - t) * e2.z);
+        s += (T)g.w[d] * (a + b + c);
     }
-    return J * J * INV4PI * s * (1.0 / 3.0);
+    return J * J * INV4PI * (double)s * (1.0 / 3.0);
 }
 
 // common edge P0 P1 (same parametrisation on both triangles): five 2D integrals
-template <int NQ>
-__device__ double ss_edge(const V3 P[3], const V3 Q[3], const GaussQ &g)
+template <int NQ, typename T = double>
+__device__ double ss_edge(const V3<double> P[3], const V3<double> Q[3], const GaussQ &g)
 {
-    V3 e1 = vsub(P[1], P[0]), et = vsub(P[2], P[1]), es = vsub(Q[2], Q[1]);
-    double Jt = cross_norm(e1, et), Js = cross_norm(e1, es);
-    double s = 0;
+    const V3<T> e1 = vsub<T>(P[1], P[0]), et = vsub<T>(P[2], P[1]), es = vsub<T>(Q[2], Q[1]);
+    const V3<double> d1 = vsub<double>(P[1], P[0]);
+    const double Jt = cross_norm(d1, vsub<double>(P[2], P[1])), Js = cross_norm(d1, vsub<double>(Q[2], Q[1]));
+    T s = 0;
     const int q = NQ ? NQ : g.q;
 #pragma unroll
     for (int ia = 0; ia < q; ++ia) {
-        const double h2 = g.x[ia];
-        double sb = 0;
+        const T h2 = (T)g.x[ia];
+        T sb = 0;
 #pragma unroll
         for (int ib = 0; ib < q; ++ib) {
-            const double h3 = g.x[ib];
+            const T h3 = (T)g.x[ib];
             // region 1 (no eta2 factor)
-            double r1 = vrnorm(h2 * e1.x + h3 * et.x - (1 - h2) * es.x, h2 * e1.y + h3 * et.y - (1 - h2) * es.y,
-                               h2 * e1.z + h3 * et.z - (1 - h2) * es.z);
-            double r2 = vrnorm(h2 * h3 * e1.x + et.x - h2 * (1 - h3) * es.x,
-                               h2 * h3 * e1.y + et.y - h2 * (1 - h3) * es.y,
-                               h2 * h3 * e1.z + et.z - h2 * (1 - h3) * es.z);
-            double r3 = vrnorm(-h2 * e1.x + (1 - h2) * et.x - h2 * h3 * es.x,
-                               -h2 * e1.y + (1 - h2) * et.y - h2 * h3 * es.y,
-                               -h2 * e1.z + (1 - h2) * et.z - h2 * h3 * es.z);
-            double r4 = vrnorm(-h2 * h3 * e1.x + h2 * (1 - h3) * et.x - es.x,
-                               -h2 * h3 * e1.y + h2 * (1 - h3) * et.y - es.y,
-                               -h2 * h3 * e1.z + h2 * (1 - h3) * et.z - es.z);
-            double r5 = vrnorm(-h2 * h3 * e1.x + (1 - h2 * h3) * et.x - h2 * es.x,
-                               -h2 * h3 * e1.y + (1 - h2 * h3) * et.y - h2 * es.y,
-                               -h2 * h3 * e1.z + (1 - h2 * h3) * et.z - h2 * es.z);
-            sb += g.w[ib] * (r1 + h2 * (r2 + r3 + r4 + r5));
+            T r1 = vrnorm<T>(h2 * e1.x + h3 * et.x - (1 - h2) * es.x, h2 * e1.y + h3 * et.y - (1 - h2) * es.y,
+                             h2 * e1.z + h3 * et.z - (1 - h2) * es.z);
+            T r2 = vrnorm<T>(h2 * h3 * e1.x + et.x - h2 * (1 - h3) * es.x,
+                             h2 * h3 * e1.y + et.y - h2 * (1 - h3) * es.y,
+                             h2 * h3 * e1.z + et.z - h2 * (1 - h3) * es.z);
+            T r3 = vrnorm<T>(-h2 * e1.x + (1 - h2) * et.x - h2 * h3 * es.x,
+                             -h2 * e1.y + (1 - h2) * et.y - h2 * h3 * es.y,
+                             -h2 * e1.z + (1 - h2) * et.z - h2 * h3 * es.z);
+            T r4 = vrnorm<T>(-h2 * h3 * e1.x + h2 * (1 - h3) * et.x - es.x,
+                             -h2 * h3 * e1.y + h2 * (1 - h3) * et.y - es.y,
+                             -h2 * h3 * e1.z + h2 * (1 - h3) * et.z - es.z);
+            T r5 = vrnorm<T>(-h2 * h3 * e1.x + (1 - h2 * h3) * et.x - h2 * es.x,
+                             -h2 * h3 * e1.y + (1 - h2 * h3) * et.y - h2 * es.y,
+                             -h2 * h3 * e1.z + (1 - h2 * h3) * et.z - h2 * es.z);
+            sb += (T)g.w[ib] * (r1 + h2 * (r2 + r3 + r4 + r5));
         }
-        s += g.w[ia] * sb;
+        s += (T)g.w[ia] * sb;
     }
-    return Jt * Js * INV4PI * s * (1.0 / 6.0);
+    return Jt * Js * INV4PI * (double)s * (1.0 / 6.0);
 }
 
 // common vertex P0 = Q0: two 3D integrals
-template <int NQ>
-__device__ double ss_vertex(const V3 P[3], const V3 Q[3], const GaussQ &g)
+template <int NQ, typename T = double>
+__device__ double ss_vertex(const V3<double> P[3], const V3<double> Q[3], const GaussQ &g)
 {
-    V3 e1t = vsub(P[1], P[0]), e2t = vsub(P[2], P[1]);
-    V3 e1s = vsub(Q[1], Q[0]), e2s = vsub(Q[2], Q[1]);
-    double Jt = cross_norm(e1t, e2t), Js = cross_norm(e1s, e2s);
-    double s = 0;
+    const V3<T> e1t = vsub<T>(P[1], P[0]), e2t = vsub<T>(P[2], P[1]);
+    const V3<T> e1s = vsub<T>(Q[1], Q[0]), e2s = vsub<T>(Q[2], Q[1]);
+    const double Jt = cross_norm(vsub<double>(P[1], P[0]), vsub<double>(P[2], P[1]));
+    const double Js = cross_norm(vsub<double>(Q[1], Q[0]), vsub<double>(Q[2], Q[1]));
+    T s = 0;
     const int q = NQ ? NQ : g.q;
 #pragma unroll
     for (int ia = 0; ia < q; ++ia) {
-        const double h1 = g.x[ia];
+        const T h1 = (T)g.x[ia];
         // x-side points (1, eta1) and y-side points (1, eta1)
-        const double ax = e1t.x + h1 * e2t.x, ay = e1t.y + h1 * e2t.y, az = e1t.z + h1 * e2t.z;
-        const double bx = e1s.x + h1 * e2s.x, by = e1s.y + h1 * e2s.y, bz = e1s.z + h1 * e2s.z;
-        double sa = 0;
+        const T ax = e1t.x + h1 * e2t.x, ay = e1t.y + h1 * e2t.y, az = e1t.z + h1 * e2t.z;
+        const T bx = e1s.x + h1 * e2s.x, by = e1s.y + h1 * e2s.y, bz = e1s.z + h1 * e2s.z;
+        T sa = 0;
 #pragma unroll
         for (int ib = 0; ib < q; ++ib) {
-            const double h2 = g.x[ib];
-            double sb = 0;
+            const T h2 = (T)g.x[ib];
+            T sb = 0;
 #pragma unroll
             for (int ic = 0; ic < q; ++ic) {
-                const double h3 = g.x[ic];
-                const double cx = e1s.x + h3 * e2s.x, cy = e1s.y + h3 * e2s.y, cz = e1s.z + h3 * e2s.z;
-                const double dx = e1t.x + h3 * e2t.x, dy = e1t.y + h3 * e2t.y, dz = e1t.z + h3 * e2t.z;
-                double r1 = vrnorm(ax - h2 * cx, ay - h2 * cy, az - h2 * cz);
-                double r2 = vrnorm(h2 * dx - bx, h2 * dy - by, h2 * dz - bz);
-                sb += g.w[ic] * (r1 + r2);
+                const T h3 = (T)g.x[ic];
+                const T cx = e1s.x + h3 * e2s.x, cy = e1s.y + h3 * e2s.y, cz = e1s.z + h3 * e2s.z;
+                const T dx = e1t.x + h3 * e2t.x, dy = e1t.y + h3 * e2t.y, dz = e1t.z + h3 * e2t.z;
+                T r1 = vrnorm<T>(ax - h2 * cx, ay - h2 * cy, az - h2 * cz);
+                T r2 = vrnorm<T>(h2 * dx - bx, h2 * dy - by, h2 * dz - bz);
+                sb += (T)g.w[ic] * (r1 + r2);
             }
-            sa += g.w[ib] * h2 * sb;
+            sa += (T)g.w[ib] * h2 * sb;
         }
-        s += g.w[ia] * sa;
+        s += (T)g.w[ia] * sa;
     }
-    return Jt * Js * INV4PI * s * (1.0 / 3.0);
+    return Jt * Js * INV4PI * (double)s * (1.0 / 3.0);
 }
 
-template <int KIND, int NQ>
+template <int KIND, int NQ, typename T = double>
 __device__ double touching_value(const double *xyz, const int32_t *tv, int pa, int pb, int code, const GaussQ &g)
 {
-    V3 P[3], Q[3];
+    V3<double> P[3], Q[3];
     tri_vertices(xyz, tv, pa, code & 15, P);
-    if (KIND == 0) return ss_identical<NQ>(P, g);
+    if (KIND == 0) return ss_identical<NQ, T>(P, g);
     tri_vertices(xyz, tv, pb, (code >> 4) & 15, Q);
-    if (KIND == 1) return ss_edge<NQ>(P, Q, g);
-    return ss_vertex<NQ>(P, Q, g);
+    if (KIND == 1) return ss_edge<NQ, T>(P, Q, g);
+    return ss_vertex<NQ, T>(P, Q, g);
 }
 
 // Value of pair p goes to out[sa[p]] and out[sb[p]] (sb < 0: none) when slot
-// maps are given (row CSR of the product), else to out[p].
-template <int KIND>
+// maps are given (row CSR of the product), else to out[p].  T: the type of
+// the Gauss loops (values are stored in FP64 either way).
+template <int KIND, typename T = double>
 __global__ void __launch_bounds__(256) k_touching(const double *xyz, const int32_t *tv, const int32_t *pa,
                                                   const int32_t *pb, const int32_t *code, int64_t np,
                                                   GaussQ g, const int32_t *sa, const int32_t *sb, double *out)
@@ -1054,8 +1068,8 @@ __global__ void __launch_bounds__(256) k_touching(const double *xyz, const int32
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     // the default Sauter-Schwab order 4 with unrolled loops
-    const double v = g.q == 4 ? touching_value<KIND, 4>(xyz, tv, pa[p], pb[p], code[p], g)
-                              : touching_value<KIND, 0>(xyz, tv, pa[p], pb[p], code[p], g);
+    const double v = g.q == 4 ? touching_value<KIND, 4, T>(xyz, tv, pa[p], pb[p], code[p], g)
+                              : touching_value<KIND, 0, T>(xyz, tv, pa[p], pb[p], code[p], g);
     if (sa) {
         out[sa[p]] = v;
         if (sb[p] >= 0) out[sb[p]] = v;
@@ -1075,7 +1089,8 @@ static GaussQ make_gq(const double *x, const double *w, int q)
     return g;
 }
 
-hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s)
+template <typename T>
+static hipError_t touching_lists(gca_h2_s *h, double *tval, hipStream_t s)
 {
     GaussQ g = make_gq(h->gs_x, h->gs_w, h->prm.q_s);
     for (int kind = 0; kind < 3; ++kind) {
@@ -1084,18 +1099,23 @@ hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s)
         if (np == 0) continue;
         dim3 grid((unsigned)((np + 255) / 256)), blk(256);
         if (kind == 0)
-            hipLaunchKernelGGL(k_touching<0>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
+            hipLaunchKernelGGL((k_touching<0, T>), grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
                                h->d_pcode + b, np, g, h->d_tslot_a + b, h->d_tslot_b + b, tval);
         else if (kind == 1)
-            hipLaunchKernelGGL(k_touching<1>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
+            hipLaunchKernelGGL((k_touching<1, T>), grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
                                h->d_pcode + b, np, g, h->d_tslot_a + b, h->d_tslot_b + b, tval);
         else
-            hipLaunchKernelGGL(k_touching<2>, grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
+            hipLaunchKernelGGL((k_touching<2, T>), grid, blk, 0, s, h->d_xyz, h->d_tv, h->d_pa + b, h->d_pb + b,
                                h->d_pcode + b, np, g, h->d_tslot_a + b, h->d_tslot_b + b, tval);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
+}
+
+hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s, bool fp32)
+{
+    return fp32 ? touching_lists<float>(h, tval, s) : touching_lists<double>(h, tval, s);
 }
 
 // ------------------------------------------------------ near-regular pairs --
@@ -1183,19 +1203,26 @@ hipError_t launch_entry_jobs(gca_h2_s *h, const EntryJobs &j, double *tmp64, flo
                              hipStream_t s)
 {
     GaussQ g = make_gq(h->gs_x, h->gs_w, h->prm.q_s);
+    const bool f32 = precision != GCA_FP64;   // the mixed product's FP32 Gauss loops
     for (int kind = 0; kind < 3; ++kind) {
         int64_t b = j.off[kind], np = j.off[kind + 1] - b;
         if (!np) continue;
         dim3 grid((unsigned)((np + 255) / 256)), blk(256);
-        if (kind == 0)
-            hipLaunchKernelGGL(k_touching<0>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
-                               np, g, nullptr, nullptr, tmp64 + b);
-        else if (kind == 1)
-            hipLaunchKernelGGL(k_touching<1>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
-                               np, g, nullptr, nullptr, tmp64 + b);
-        else
-            hipLaunchKernelGGL(k_touching<2>, grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, j.code + b,
-                               np, g, nullptr, nullptr, tmp64 + b);
+#define TOUCH(K)                                                                                        \
+    if (f32)                                                                                            \
+        hipLaunchKernelGGL((k_touching<K, float>), grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, \
+                           j.code + b, np, g, nullptr, nullptr, tmp64 + b);                             \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_touching<K, double>), grid, blk, 0, s, h->d_xyz, h->d_tv, j.pa + b, j.pb + b, \
+                           j.code + b, np, g, nullptr, nullptr, tmp64 + b);
+        if (kind == 0) {
+            TOUCH(0)
+        } else if (kind == 1) {
+            TOUCH(1)
+        } else {
+            TOUCH(2)
+        }
+#undef TOUCH
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;

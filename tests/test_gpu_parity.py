@@ -88,7 +88,9 @@ def test_entries_mixed_match_oracle(torch, gca, orc, c1):
         got = H.entries(I, J, precision=gca.MIXED).cpu().numpy()
         ref = G[I, J]
         err = np.max(np.abs(got - ref) / np.abs(ref))
-        tol = 1e-12 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6
+        # mixed: the Sauter-Schwab Gauss loops run in FP32 (sums of at most 128
+        # positive terms, relative rounding < 128 x 2^-24 ~ 8e-6)
+        tol = 1e-5 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6
         assert err < tol, (k, err)
 
 
@@ -246,7 +248,7 @@ def test_symmetric_rule_entries_and_nearfield_match_oracle(torch, gca, orc, c1_s
         got = H.entries(I, J).cpu().numpy()
         assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-12, k
         gm = H.entries(I, J, precision=gca.MIXED).cpu().numpy()
-        tol = 1e-12 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6
+        tol = 1e-5 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6   # FP32 Sauter-Schwab loops
         assert np.max(np.abs(gm - ref) / np.abs(ref)) < tol, k
     H0 = build(gca, m, 32, eta=1e-6, eps=1e-6, sym_rules=1)
     X = synth.rhs_normal(m.nt, 2, seed=1)
