@@ -58,9 +58,16 @@ void free_all(gca_h2_s *h)
     free_stored(h);
     for (void *p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
-    if (h->events)
+    if (h->events) {
         for (auto &r : h->ev)
             for (auto &e : r) (void)hipEventDestroy(e);
+        for (auto &r : h->ev_side)
+            for (auto &e : r) (void)hipEventDestroy(e);
+        (void)hipEventDestroy(h->ev_fork);
+        (void)hipEventDestroy(h->ev_join);
+        (void)hipStreamDestroy(h->s_side);
+        h->s_side = nullptr;
+    }
     h->events = false;
 }
 
@@ -829,6 +836,11 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     GCA_TRY(dalloc(h, &h->d_npartf, h->n_gnslot_total));
     for (auto &r : h->ev)
         for (auto &e : r) GCA_HIP_TRY(hipEventCreate(&e));
+    for (auto &r : h->ev_side)
+        for (auto &e : r) GCA_HIP_TRY(hipEventCreate(&e));
+    GCA_HIP_TRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    GCA_HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    GCA_HIP_TRY(hipStreamCreateWithFlags(&h->s_side, hipStreamNonBlocking));
     h->events = true;
     GCA_HIP_TRY(hipStreamSynchronize(s));
     lap(5);
@@ -890,14 +902,27 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     auto mark = [&](int k) {
         if (h->events) (void)hipEventRecord(h->ev[slot][k], s);
     };
+    const T *far_g = f32 ? (const T *)h->d_far_g32 : (const T *)h->d_far_g64;
+    const T *near_g = f32 ? (const T *)h->d_near_g32 : (const T *)h->d_near_g64;
+    const bool stored = far_g != nullptr;
+    const bool side = first && !stored && h->events;
+    h->side_used[slot] = side;
     mark(0);
+    if (side) {
+        // touching values depend on the geometry only: they run beside the
+        // transforms and blocks; the fork orders them after earlier products
+        // on s (whose gathers read the same table)
+        if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(h->s_side, h->ev_fork, 0)) != hipSuccess) return e;
+        (void)hipEventRecord(h->ev_side[slot][0], h->s_side);
+        if ((e = launch_touching(h, h->d_tval, h->s_side, sizeof(T) == 4)) != hipSuccess) return e;
+        (void)hipEventRecord(h->ev_side[slot][1], h->s_side);
+        if ((e = hipEventRecord(h->ev_join, h->s_side)) != hipSuccess) return e;
+    }
     if ((e = launch_permute_in<T>(x, h->d_perm, h->n, xp, f32 ? h->d_xp : nullptr, s)) != hipSuccess) return e;
     mark(1);
     if ((e = launch_forward<T>(h, xp, xh, s)) != hipSuccess) return e;
     mark(2);
-    const T *far_g = f32 ? (const T *)h->d_far_g32 : (const T *)h->d_far_g64;
-    const T *near_g = f32 ? (const T *)h->d_near_g32 : (const T *)h->d_near_g64;
-    const bool stored = far_g != nullptr;
     if (stored) {
         if ((e = launch_apply_stored<T>(h, false, xh, far_g, cpart, s)) != hipSuccess) return e;
     } else if ((e = launch_far_blocks<T>(h, xh, cpart, s)) != hipSuccess) {
@@ -917,7 +942,11 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     // stored mode: the list values were computed with the blocks
     if (first && !stored && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
     mark(7);
-    if (first && !stored && (e = launch_touching(h, h->d_tval, s, sizeof(T) == 4)) != hipSuccess) return e;
+    if (side) {
+        if ((e = hipStreamWaitEvent(s, h->ev_join, 0)) != hipSuccess) return e;
+    } else if (first && !stored && (e = launch_touching(h, h->d_tval, s, sizeof(T) == 4)) != hipSuccess) {
+        return e;
+    }
     mark(8);
     if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, nval, y, s)) != hipSuccess) return e;
     mark(9);
@@ -1548,6 +1577,10 @@ gca_status gca_stats(gca_h2 h, gca_stats_t *out)
             GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][k], h->ev[slot][k + 1]));
             out->phase_ms[k] = ms;
         }
+        if (h->side_used[slot]) {
+            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev_side[slot][0], h->ev_side[slot][1]));
+            out->phase_ms[TOUCH_PHASE] = ms;
+        }
         GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][0], h->ev[slot][GCA_NPHASE]));
         out->phase_ms[GCA_NPHASE] = ms;
     }
@@ -1569,6 +1602,10 @@ gca_status gca_phase_times(gca_h2 h, int64_t max_products, double *out, int64_t 
         for (int k = 0; k < GCA_NPHASE; ++k) {
             GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][k], h->ev[slot][k + 1]));
             out[q * (GCA_NPHASE + 1) + k] = ms;
+        }
+        if (h->side_used[slot]) {
+            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev_side[slot][0], h->ev_side[slot][1]));
+            out[q * (GCA_NPHASE + 1) + TOUCH_PHASE] = ms;
         }
         GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][0], h->ev[slot][GCA_NPHASE]));
         out[q * (GCA_NPHASE + 1) + GCA_NPHASE] = ms;

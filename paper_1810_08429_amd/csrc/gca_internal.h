@@ -352,6 +352,13 @@ struct gca_h2_s {
     int64_t n_products = 0;
     bool events = false;
     bool timed = false;              // phase events hold a recorded product
+    // touching values are computed on a side stream (non-blocking, default
+    // priority) forked at the start of a product and joined before the gather;
+    // ev_side[slot] times them there (side_used[slot]: that product did)
+    hipStream_t s_side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_side[RING][2] = {};
+    bool side_used[RING] = {};
     gca_stats_t st{};
 };
 
@@ -364,6 +371,9 @@ constexpr int NEAR_CW = 64;          // column chunk of the nearfield block rows
 // A rule on the reference triangle {0 <= s2 <= s1 <= 1}: point
 // P0 + s1 (P1 - P0) + s2 (P2 - P1), weight w times |(P1 - P0) x (P2 - P1)|;
 // the weights sum to 1/2.
+// index of the touching phase in the phase times
+constexpr int TOUCH_PHASE = 7;
+
 struct TriRule {
     int np;
     double s1[64], s2[64], w[64];
