@@ -113,7 +113,10 @@ typedef struct {
                                             2 coupling-block quadrature, 3 coupling reduction,
                                             4 backward transform, 5 nearfield-block quadrature,
                                             6 near-regular list, 7 touching lists (both only for
-                                            the first right-hand side), 8 gather, 9 total */
+                                            the first right-hand side; 7 is timed on the handle's
+                                            side stream, where the touching lists run beside the
+                                            other phases, so 0-8 need not add up to 9), 8 gather,
+                                            9 total (wall time of the product) */
     int64_t store_entries_far;           /* entries of the stored coupling block rows */
     int64_t store_entries_near;          /* entries of the stored nearfield block rows (masked pairs as zeros) */
     int32_t stored_mask;                 /* precisions with stored block rows (gca_store_blocks) */
@@ -176,7 +179,9 @@ gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p,
  * coupling with entries G|t~ x s~ recomputed, backward transform, and
  * nearfield blocks G|t^ x s^ recomputed).  x, y: device, FP64, nt x nrhs,
  * column-major with leading dimension ld >= nt; y is overwritten; x and y
- * must not overlap.  precision: gca_precision.
+ * must not overlap.  precision: gca_precision.  The touching-pair values run
+ * on a side stream owned by the handle, forked from and joined back into
+ * `stream` within the call's work, so `stream` orders the whole product.
  * Errors: GCA_EINVAL (null handle or pointers, nrhs < 1, ld < nt, aliasing,
  * unknown precision), GCA_EHIP. */
 gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t ld,
@@ -270,8 +275,9 @@ gca_status gca_stats(gca_h2 h, gca_stats_t *out);
 
 /* Phase times (ms, HIP events on the stream of each product) of the last
  * min(max_products, 64, products so far) single-right-hand-side products,
- * oldest first: out[q * (GCA_NPHASE + 1) + k], k as in gca_stats_t.phase_ms.
- * out may be NULL to query *count.  Synchronises with the last product. */
+ * oldest first: out[q * (GCA_NPHASE + 1) + k], k as in gca_stats_t.phase_ms
+ * (the touching phase timed on the side stream).  out may be NULL to query
+ * *count.  Synchronises with the last product. */
 gca_status gca_phase_times(gca_h2 h, int64_t max_products, double *out, int64_t *count);
 
 void gca_destroy(gca_h2 h);
