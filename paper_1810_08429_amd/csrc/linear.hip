@@ -9,14 +9,17 @@
 // the mergesort with combination of Section 5 defines (rows ascending by
 // triangle, one row per triangle).
 //
-// Blocks (one workgroup per block): the row subset's merged triangles are
-// staged in LDS; the column subset's are taken in chunks.  For every pair
-// (t, s) of a chunk one thread evaluates the kernel at the P x P point pairs
-// once and forms all nine corner moments
+// Blocks (one 512-thread workgroup per block): every merged triangle of the
+// row and the column subset is staged once in LDS, and the corners with a
+// local vertex are numbered (row corners rho, column corners kappa).  The
+// column triangles are taken in chunks whose corners fit the LDS buffer; for
+// every pair (t, s) of a chunk one thread evaluates the kernel at the P x P
+// point pairs once and forms the nine corner moments
 //     M_ab = |J_t| |J_s| / (4 pi) sum_p sum_q w_p lambda_a(x_p) g(x_p, y_q) w_q lambda_b(y_q),
-// kept in LDS; every block entry (i, j) then adds M[t][s][a][b] over the rows
-// t of its vertex i (corner a) and the rows s of its vertex j (corner b) in a
-// fixed order, so the block is reproducible bit for bit without atomics.
+// keeping those whose two corners are local at (rho, kappa).  Every block
+// entry (i, j) then adds them over the corners rho of its vertex i and kappa
+// of its vertex j in ascending order, so the block is reproducible bit for
+// bit without atomics.
 #include <hip/hip_runtime.h>
 
 #include <climits>
