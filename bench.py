@@ -12,7 +12,10 @@ measured on the same H^2 approximation alongside.  Setup seconds cover tree
 construction and gca_build (synchronised wall time).  The adjoint of the
 energy with respect to the vertex coordinates is timed in both precisions
 after the products (`energy_gradient`), and so is the stored-block mode
-(`stored_blocks`: block rows computed once, products read them).
+(`stored_blocks`: block rows computed once, products read them).  The
+piecewise-linear nodal basis (`linear_basis`) is measured on the same mesh:
+the merge of vertex-subset triangle lists and FP64 Galerkin blocks assembled
+triangle pair by triangle pair, against its own FP64 ceiling.
 
 The roofline object describes the dominant kernel of the mixed product, timed
 with the library's per-product HIP events over the timed steps.  The CPU
