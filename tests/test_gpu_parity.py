@@ -282,3 +282,36 @@ def test_symmetric_rule_h2_matches_oracle_step_by_step(torch, gca, orc):
     H.store_blocks(fp64=True, mixed=True)
     ys = H.matvec(xt).cpu().numpy()
     assert np.linalg.norm(ys - y) / np.linalg.norm(y) < 1e-13
+
+
+def test_side_stream_orders_products_and_geometry_updates(torch, gca):
+    """The touching values run on the handle's side stream, forked from and
+    joined back into the caller's stream: products and a geometry update
+    queued back to back on a non-default stream equal, bit for bit, the same
+    calls separated by device synchronisations."""
+    base = synth.icosphere(3)
+    m = synth.jitter(base, 0.02 * synth.mean_edge_length(base), seed=8)
+    moved = m.verts * 1.02 + np.array([1e-3, 0.0, -2e-3])
+    x = torch.tensor(synth.rhs_normal(m.nt, 1, seed=9), device="cuda")
+    torch.cuda.synchronize()
+    res = []
+    for asynchronous in (True, False):
+        H = build(gca, m, 32, eta=2.0, eps=1e-6)
+        s = torch.cuda.Stream() if asynchronous else torch.cuda.current_stream()
+        sync = (lambda: None) if asynchronous else torch.cuda.synchronize
+        ys = []
+        with torch.cuda.stream(s):
+            for prec in (gca.MIXED, gca.FP64, gca.MIXED):
+                ys.append(H.matvec(x, precision=prec))
+                sync()
+            H.update_geometry(moved)
+            sync()
+            for prec in (gca.MIXED, gca.FP64):
+                ys.append(H.matvec(x, precision=prec))
+                sync()
+        torch.cuda.synchronize()
+        res.append([y.cpu().numpy() for y in ys])
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res[0][0], res[0][2])
+    assert not np.array_equal(res[0][0], res[0][3])
