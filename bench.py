@@ -40,7 +40,7 @@ if ROOT not in sys.path:
 METRIC = "H² matvec DoF/s + setup s at 1e-4 rel err: mixed vs FP64 plain, % roofline"
 
 # ALU ceiling of one FP32 kernel evaluation w / |x - y| accumulated into a sum
-# (derivation in the design doc): with the squared distance expanded around
+# with the squared distance expanded around
 # reference points, 5 VALU lane-ops (1 add + 3 fma for |x - y|^2, 1 fma to
 # accumulate) + 1 v_rsq_f32.  The published FP32 vector peak, 157.3 TFLOP/s =
 # 256 CUs x 2.4 GHz x 128 FMA lanes per clock, gives 7.86e13 lane-ops/s;
