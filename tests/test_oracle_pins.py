@@ -492,6 +492,115 @@ def test_cluster_tree_invariants(orc):
             assert nd.end - nd.begin <= 32
 
 
+# Hand-built boxes whose diameters and distance are exact in binary floating
+# point (sides 3, 4, 0 give a diagonal of exactly 5).  Each case is
+# (lo_a, hi_a, lo_b, hi_b, eta, admissible?) for Section 2's condition
+# max{diam tau, diam sigma} <= 2 eta dist(tau, sigma), dist the Euclidean
+# distance of the boxes, diam the length of a box's diagonal; equality is
+# admissible, overlapping or touching boxes never are.
+ADMISSIBILITY_CASES = [
+    # gap 1.25 along x, both diameters 5: 2 eta dist = 5 at eta = 2 (equality)
+    ((0, 0, 0), (3, 4, 0), (4.25, 0, 0), (7.25, 4, 0), 2.0, True),
+    ((0, 0, 0), (3, 4, 0), (4.25, 0, 0), (7.25, 4, 0), 1.96875, False),
+    ((0, 0, 0), (3, 4, 0), (4.25, 0, 0), (7.25, 4, 0), 1.0, False),
+    # diagonal gaps (0.75, 1, 0): Euclidean 1.25, Chebyshev 1, Manhattan 1.75
+    ((0, 0, 0), (3, 4, 0), (3.75, 5, 0), (6.75, 9, 0), 2.0, True),
+    ((0, 0, 0), (3, 4, 0), (3.75, 5, 0), (6.75, 9, 0), 1.875, False),
+    # gaps along y and z only, (0, 0.75, 1): Euclidean 1.25
+    ((0, 0, 0), (3, 4, 0), (0, 4.75, 1), (3, 8.75, 1), 2.0, True),
+    ((0, 0, 0), (3, 4, 0), (0, 4.75, 1), (3, 8.75, 1), 1.9375, False),
+    # sigma smaller (diagonal 1): the larger diameter decides
+    ((0, 0, 0), (3, 4, 0), (4.25, 0, 0), (4.85, 0.8, 0), 2.0, True),
+    ((0, 0, 0), (3, 4, 0), (4.25, 0, 0), (4.85, 0.8, 0), 1.0, False),
+    ((4.25, 0, 0), (4.85, 0.8, 0), (0, 0, 0), (3, 4, 0), 1.0, False),
+    # touching faces and overlapping boxes: distance zero
+    ((0, 0, 0), (3, 4, 0), (3, 0, 0), (6, 4, 0), 1e9, False),
+    ((0, 0, 0), (3, 4, 0), (1, 1, 0), (4, 5, 0), 1e9, False),
+    # far apart: gap 20 along z, eta 1/8 gives 2 eta dist = 5
+    ((0, 0, 0), (3, 4, 0), (0, 0, 20), (3, 4, 20), 0.125, True),
+    ((0, 0, 0), (3, 4, 0), (0, 0, 20), (3, 4, 20), 0.12, False),
+]
+
+
+def _box(orc, lo, hi):
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    e = hi - lo
+    return orc.Cluster(0, 1, 0, lo=lo, hi=hi, diam=math.sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]))
+
+
+def _admissibility_failures(orc, admissible):
+    bad = []
+    for k, (la, ha, lb, hb, eta, want) in enumerate(ADMISSIBILITY_CASES):
+        if bool(admissible(_box(orc, la, ha), _box(orc, lb, hb), eta)) != want:
+            bad.append(k)
+    return bad
+
+
+def test_admissibility_condition_on_boxes_with_exact_distances(orc):
+    """Section 2's admissibility condition on hand-built boxes: the flip
+    happens exactly at max{diam} = 2 eta dist, with equality admissible, dist
+    Euclidean, the larger diameter deciding, boxes at distance zero never
+    admissible."""
+    assert _box(orc, (0, 0, 0), (3, 4, 0)).diam == 5.0
+    assert orc.box_dist(_box(orc, (0, 0, 0), (3, 4, 0)), _box(orc, (3.75, 5, 0), (6.75, 9, 0))) == 1.25
+    assert orc.box_dist(_box(orc, (0, 0, 0), (3, 4, 0)), _box(orc, (1, 1, 0), (4, 5, 0))) == 0.0
+    assert _admissibility_failures(orc, orc.admissible) == []
+
+
+def test_admissibility_cases_reject_plausible_misreadings(orc):
+    """The cases above are strong enough: a factor eta instead of 2 eta, a
+    strict inequality, the smaller diameter, or a Chebyshev or Manhattan box
+    distance each fail at least one of them."""
+    def gaps(a, b):
+        return [max(0.0, max(b.lo[d] - a.hi[d], a.lo[d] - b.hi[d])) for d in range(3)]
+
+    eucl = lambda a, b: math.sqrt(sum(g * g for g in gaps(a, b)))
+    mutants = {
+        "eta": lambda a, b, eta: eucl(a, b) > 0 and max(a.diam, b.diam) <= eta * eucl(a, b),
+        "strict": lambda a, b, eta: eucl(a, b) > 0 and max(a.diam, b.diam) < 2 * eta * eucl(a, b),
+        "min_diam": lambda a, b, eta: eucl(a, b) > 0 and min(a.diam, b.diam) <= 2 * eta * eucl(a, b),
+        "chebyshev": lambda a, b, eta: max(gaps(a, b)) > 0 and max(a.diam, b.diam) <= 2 * eta * max(gaps(a, b)),
+        "manhattan": lambda a, b, eta: sum(gaps(a, b)) > 0 and max(a.diam, b.diam) <= 2 * eta * sum(gaps(a, b)),
+        "4eta": lambda a, b, eta: eucl(a, b) > 0 and max(a.diam, b.diam) <= 4 * eta * eucl(a, b),
+    }
+    for name, fn in mutants.items():
+        assert _admissibility_failures(orc, fn), name
+
+
+@pytest.mark.parametrize("level,leaf", [(3, 32), (5, 64)])
+def test_admissible_blocks_keep_sigma_outside_omega(orc, level, leaf):
+    """Section 2 needs every admissible sigma outside the closure of omega:
+    with the default margin delta = diam(tau) / (4 eta) per side,
+    sqrt(3) delta < diam / (2 eta) <= dist(tau, sigma), so the box of sigma
+    keeps a positive distance from omega_tau (and omega_sigma from tau)."""
+    m = synth.icosphere(level)
+    tree = orc.cluster_tree(m.verts, m.tris, leaf)
+    eta = 2.0
+    far, _ = orc.block_tree(tree, eta)
+    assert far
+    for (t, s) in far:
+        a, b = tree.nodes[t], tree.nodes[s]
+        assert max(a.diam, b.diam) <= 2 * eta * orc.box_dist(a, b)
+        for u, v in ((a, b), (b, a)):
+            d = 0.25 * u.diam / eta
+            om = orc.Cluster(0, 1, 0, lo=u.lo - d, hi=u.hi + d, diam=0.0)
+            assert orc.box_dist(om, v) > 0, (t, s)
+            # the points of omega's faces (the Green points) stay away from sigma
+            z, _, _ = orc.green_points(u, 3, eta, omega_scale=0.25)
+            inside = np.all((z >= v.lo) & (z <= v.hi), axis=1)
+            assert not inside.any()
+
+
+def test_cluster_diameter_is_the_box_diagonal(orc):
+    """Reading s5: d_tau is the Euclidean length of the bounding box's
+    diagonal (the same value the admissibility condition uses)."""
+    verts, tris = _mesh3()
+    tree = orc.cluster_tree(verts, tris, 32)
+    for nd in tree.nodes:
+        assert nd.diam == pytest.approx(float(np.linalg.norm(nd.hi - nd.lo)), rel=1e-15)
+
+
 def test_block_tree_tiles_index_square_once(orc):
     """P10: admissible and near blocks cover I x I exactly once; no admissible
     block holds a touching or near-regular pair."""
