@@ -79,18 +79,7 @@ def build(verbose: bool = False, jobs: int = 4, out: str = None, defines=()) -> 
     os.replace(tmp, out)
     if verbose:
         print("built", out, flush=True)
-    if out != OUT:
-        return out
-    # ALU probe used to check the roofline ceiling of the quadrature kernels
-    probe_src = os.path.join(HERE, "probe", "alu_probe.hip")
-    probe_bin = os.path.join(HERE, "probe", "alu_probe")
-    r = subprocess.run([hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",
-                        "-Xclang", "-packed-fp32-ops", *MFMA_FLAGS, probe_src, "-o", probe_bin + ".tmp"],
-                       capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"building the ALU probe failed:\n{r.stderr}")
-    os.replace(probe_bin + ".tmp", probe_bin)
-    return OUT
+    return out
 
 
 if __name__ == "__main__":
