@@ -7,8 +7,10 @@ One step = one H^2 product y = G~ x (forward transform, coupling blocks and
 nearfield blocks recomputed by pair quadrature, backward transform, touching
 pairs) for one right-hand side, inputs resident in HBM.  `value` is
 DoF/s = n / (seconds per product) of the mixed-precision path (FP32
-regular-pair quadrature and transfers, FP32 Sauter-Schwab loops); the FP64 path is
-measured on the same H^2 approximation alongside.  Setup seconds cover tree
+regular-pair quadrature and transfers, FP64 Sauter-Schwab touching pairs); the
+FP64 path is measured on the same H^2 approximation alongside, and so is the
+opt-in variant with FP32 Sauter-Schwab Gauss loops (a second handle built with
+ss_fp32 = 1).  Setup seconds cover tree
 construction and gca_build (synchronised wall time).  The adjoint of the
 energy with respect to the vertex coordinates is timed in both precisions
 after the products (`energy_gradient`), and so is the stored-block mode
@@ -18,9 +20,14 @@ the merge of vertex-subset triangle lists and FP64 Galerkin blocks assembled
 triangle pair by triangle pair, against its own FP64 ceiling.
 
 The roofline object describes the dominant kernel of the mixed product, timed
-with the library's per-product HIP events over the timed steps.  The CPU
+with the library's per-product HIP events over the timed steps: `frac` is
+against the published FP32 vector peak (157.3 TFLOP/s, 10 flops per kernel
+evaluation), `issue_ceiling_frac` against the instruction-mix ceiling of an
+evaluation (5 full-rate VALU lane-ops and one quarter-rate rsqrt).  The CPU
 baseline is the plain FP64 oracle computing sampled rows of G x on the host
-cores; the same rows give the relative error of both GPU paths.
+cores; the same rows give the relative error of both GPU paths for three
+vectors (x ~ N(0,1), the all-ones vector and the centroid x3 coordinates), and
+the reported error is the largest of the three.
 """
 from __future__ import annotations
 
@@ -50,7 +57,10 @@ VALU_LANE_OPS_PER_S = 256 * 128 * 2.4e9
 TRANS_LANE_OPS_PER_S = VALU_LANE_OPS_PER_S / 4
 FLOPS_PER_EVAL = 10
 EVALS_PER_S_F32 = 1.0 / (5.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
-ALU_PEAK_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
+ISSUE_CEILING_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
+# the published FP32 vector peak of the chip (packed FP32 FMA: 256 CUs x
+# 2.4 GHz x 128 lanes x 2 flops)
+PUBLISHED_F32_TFLOPS = 157.3
 
 
 # FP64 ceiling of one dimension-reduced Sauter-Schwab evaluation (the
@@ -76,7 +86,7 @@ def lin_evals_per_s(P):
     return FP64_LANE_OPS_PER_S / (13.0 + 4.0 + 27.0 / P)
 
 
-def phase_rooflines(st, params, P, Pc, ms):
+def phase_rooflines(st, params, P, Pc, ms, ss_fp32=False):
     """Fraction of its bound for every phase of the mixed product (per
     product): the quadrature phases against the FP32 ALU ceiling (10 flops
     per evaluation), the touching lists against the FP32 evaluation ceiling,
@@ -89,12 +99,14 @@ def phase_rooflines(st, params, P, Pc, ms):
     for ph, flops in (("near_blocks", st["near_regular_pairs"] * P * P * FLOPS_PER_EVAL),
                       ("coupling_blocks", st["coupling_entries"] * Pc * Pc * FLOPS_PER_EVAL)):
         a = flops / (ms[ph] * 1e-3) / 1e12
-        out[ph] = {"bound": "alu", "achieved": a, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
-                   "frac": a / ALU_PEAK_F32_TFLOPS}
+        out[ph] = {"bound": "alu", "achieved": a, "peak": PUBLISHED_F32_TFLOPS, "unit": "TFLOP/s",
+                   "frac": a / PUBLISHED_F32_TFLOPS, "issue_ceiling": ISSUE_CEILING_F32_TFLOPS,
+                   "issue_ceiling_frac": a / ISSUE_CEILING_F32_TFLOPS}
     ev = st["n_ident"] * 3 * q + st["n_edge"] * 5 * q * q + st["n_vert"] * 2 * q ** 3
     a = ev / (ms["touching"] * 1e-3)
-    out["touching"] = {"bound": "alu", "achieved": a, "peak": SS_EVALS_PER_S_F32, "unit": "evaluations/s",
-                       "frac": a / SS_EVALS_PER_S_F32}
+    peak = SS_EVALS_PER_S_F32 if ss_fp32 else SS_EVALS_PER_S
+    out["touching"] = {"bound": "alu", "achieved": a, "peak": peak, "unit": "evaluations/s",
+                       "frac": a / peak, "arithmetic": "FP32 Gauss loops" if ss_fp32 else "FP64"}
     for ph, byts in (("forward", 4 * (nv_ + ne_) + 4 * n),
                      ("backward", 4 * ne_),
                      ("gather", 4 * nv_ + 2 * (st["n_edge"] + st["n_vert"]) * 12 + st["n_ident"] * 12 + 8 * n)):
@@ -150,6 +162,10 @@ def parse():
                     help="timed calls of the energy gradient per precision (0 disables it)")
     ap.add_argument("--lin-blocks", type=int, default=16384,
                     help="linear-basis blocks (32 x 32 vertices) in the piecewise-linear leg (0 disables it)")
+    ap.add_argument("--omega", type=float, default=None, help="override the workload's omega margin")
+    ap.add_argument("--green-m", type=int, default=None, help="override the workload's Green order")
+    ap.add_argument("--ss32-steps", type=int, default=10,
+                    help="timed mixed products of a handle built with FP32 Sauter-Schwab loops (0 disables it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
@@ -238,6 +254,15 @@ def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
     return res
 
 
+def error_vectors(mesh, x_host):
+    """The vectors of the error metric: the benchmark's x ~ N(0,1), the
+    all-ones vector and the centroid x3 coordinate of every triangle (columns
+    of an n x 3 array).  The smooth two load the far field, where the
+    compression error lives."""
+    c = mesh.verts[mesh.tris].mean(axis=1)
+    return np.stack([x_host, np.ones(mesh.nt), c[:, 2]], axis=1)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -252,10 +277,14 @@ def main():
 
     mesh, cfg = synth.workload(a.workload)
     n = mesh.nt
-    print(f"[bench] workload {a.workload}: n={n} leaf={cfg['leaf']} eta={cfg['eta']} eps={cfg['eps']}",
-          file=sys.stderr, flush=True)
     if a.eps is not None:
         cfg["eps"] = a.eps
+    if a.omega is not None:
+        cfg["omega_scale"] = a.omega
+    if a.green_m is not None:
+        cfg["green_m"] = a.green_m
+    print(f"[bench] workload {a.workload}: n={n} leaf={cfg['leaf']} eta={cfg['eta']} eps={cfg['eps']} "
+          f"green_m={cfg['green_m']} omega={cfg.get('omega_scale', 0.25)}", file=sys.stderr, flush=True)
     params = gca.Params(eta=cfg["eta"], eps=cfg["eps"], green_m=cfg["green_m"],
                         omega_scale=cfg.get("omega_scale", 0.25))
     if a.q_c is not None:
@@ -278,17 +307,18 @@ def main():
     x_host = synth.rhs_normal(n, 1, seed=0)
     x = torch.tensor(x_host, device=dev)
     y = torch.empty_like(x)
+    Xerr = torch.tensor(error_vectors(mesh, x_host), device=dev)
 
-    def run(prec, steps, warmup):
+    def run(Hh, prec, steps, warmup):
         for _ in range(warmup):
-            H.matvec_into(x, y, precision=prec)
+            Hh.matvec_into(x, y, precision=prec)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            H.matvec_into(x, y, precision=prec)
+            Hh.matvec_into(x, y, precision=prec)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        ph = H.phase_times(steps)
+        ph = Hh.phase_times(steps)
         return dt, ph, y.clone()
 
     if a.copy_probe:
@@ -300,20 +330,24 @@ def main():
         print("[bench] copy probe: 1 GiB read + 1 GiB written", file=sys.stderr, flush=True)
         del src, dst
 
-    dt_mixed, ph_mixed, y_mixed = run(gca.MIXED, a.steps, a.warmup)
+    dt_mixed, ph_mixed, y_mixed = run(H, gca.MIXED, a.steps, a.warmup)
     print(f"[bench] mixed: {dt_mixed * 1e3:.3f} ms/product", file=sys.stderr, flush=True)
     fsteps = a.fp64_steps if a.fp64_steps is not None else max(3, a.steps // 2)
-    dt_fp64, ph_fp64, y_fp64 = run(gca.FP64, fsteps, 1)
+    dt_fp64, ph_fp64, y_fp64 = run(H, gca.FP64, fsteps, 1)
     print(f"[bench] fp64 : {dt_fp64 * 1e3:.3f} ms/product", file=sys.stderr, flush=True)
+    # products of the three error vectors (outside the timed region)
+    Y_err = {"mixed": H.matvec(Xerr, gca.MIXED).cpu().numpy(), "fp64": H.matvec(Xerr, gca.FP64).cpu().numpy()}
 
     # adjoint of the energy E = 1/2 x^T G~ x w.r.t. the vertex coordinates
     # (h2_bilinear_grad, frozen structure), mixed and FP64; the first call of
     # each precision sets up the adjoint's index maps and is not timed
     grad = {}
     if a.grad_steps > 0:
-        dxyz = torch.zeros((mesh.nv, 3), dtype=torch.float64, device=dev)
+        gvec = {}
         for prec, name in ((gca.MIXED, "mixed"), (gca.FP64, "fp64")):
+            dxyz = torch.zeros((mesh.nv, 3), dtype=torch.float64, device=dev)
             H.bilinear_grad(x, x, 0.5, dxyz, prec)
+            gvec[name] = dxyz.clone()
             torch.cuda.synchronize()
             t = time.perf_counter()
             for _ in range(a.grad_steps):
@@ -322,7 +356,34 @@ def main():
             grad[name] = {"ms_per_step": (time.perf_counter() - t) / a.grad_steps * 1e3, "steps": a.grad_steps}
             print(f"[bench] energy gradient {name}: {grad[name]['ms_per_step']:.3f} ms", file=sys.stderr,
                   flush=True)
-        del dxyz
+            del dxyz
+        d = gvec["mixed"] - gvec["fp64"]
+        grad["mixed_vs_fp64"] = {
+            "rel_diff_max": float(d.abs().max() / gvec["fp64"].abs().max()),
+            "rel_diff_2": float(torch.linalg.norm(d) / torch.linalg.norm(gvec["fp64"])),
+            "what": "dE/dX of E = 1/2 x^T G~ x, mixed against FP64, relative to the FP64 gradient"}
+        print(f"[bench] energy gradient mixed vs fp64: {grad['mixed_vs_fp64']['rel_diff_max']:.2e} (max norm)",
+              file=sys.stderr, flush=True)
+        del gvec, d
+
+    # the opt-in FP32 Sauter-Schwab loops (gca_params.ss_fp32 = 1): a second
+    # handle on the same tree and parameters
+    ss32 = None
+    if a.ss32_steps > 0:
+        p32 = gca.Params(**{k: getattr(params, k) for k in params.__dataclass_fields__})
+        p32.ss_fp32 = 1
+        H32 = gca.H2(mesh.verts, mesh.tris, tree, p32)
+        dt32, ph32, _ = run(H32, gca.MIXED, a.ss32_steps, 2)
+        pm32 = dict(zip(gca.PHASES, ph32.mean(axis=0).tolist()))
+        Y_err["mixed_ss_fp32"] = H32.matvec(Xerr, gca.MIXED).cpu().numpy()
+        H32.close()
+        ss32 = {"value": n / dt32, "unit": "DoF/s", "ms_per_step": dt32 * 1e3, "steps": a.ss32_steps,
+                "phases_ms": pm32,
+                "phases_roofline_touching": phase_rooflines(st, params, rule_points(params.q_r, params.sym_rules),
+                                                            rule_points(params.q_c, params.sym_rules), pm32,
+                                                            ss_fp32=True)["touching"]}
+        print(f"[bench] mixed with FP32 Sauter-Schwab loops: {dt32 * 1e3:.3f} ms/product", file=sys.stderr,
+              flush=True)
 
     # stored-block mode: the block rows computed once (gca_store_blocks), then
     # products that read them; reported beside the recomputing product
@@ -338,7 +399,7 @@ def main():
         stored = {"store_s": t_store, "entries": entries,
                   "bytes": {"mixed": 4 * entries, "fp64": 8 * entries}}
         for prec, name, yref in ((gca.MIXED, "mixed", y_mixed), (gca.FP64, "fp64", y_fp64)):
-            dt, ph, ys = run(prec, a.stored_steps, 2)
+            dt, ph, ys = run(H, prec, a.stored_steps, 2)
             pm = dict(zip(gca.PHASES, ph.mean(axis=0).tolist()))
             blk_ms = pm["coupling_blocks"] + pm["near_blocks"]
             stored[name] = {"value": n / dt, "unit": "DoF/s", "ms_per_step": dt * 1e3,
@@ -367,45 +428,49 @@ def main():
     dur = mean_mixed[dom] * 1e-3
     achieved = work[dom] / dur / 1e12
     kname = ("k_far_rows<float,%d>" % Pc) if dom == "coupling_blocks" else ("k_near_rows<float,%d>" % P)
-    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_F32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / ALU_PEAK_F32_TFLOPS, "traffic": measured_traffic(kname),
-                "kernel": kname,
-                "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom]}
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PUBLISHED_F32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PUBLISHED_F32_TFLOPS, "traffic": measured_traffic(kname),
+                "issue_ceiling": ISSUE_CEILING_F32_TFLOPS, "issue_ceiling_frac": achieved / ISSUE_CEILING_F32_TFLOPS,
+                "kernel": kname, "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom]}
 
     # CPU oracle on a bounded sample of rows (also the accuracy check): the
     # first rows of one seeded permutation, err_rows of them unless fewer fit
     # in about twice cpu_seconds, so runs of different configurations compare
-    # on the same rows
+    # on the same rows; the oracle computes the rows for the three error
+    # vectors at once (the entries dominate its time)
     cpu = None
     rel = {}
     if a.cpu_seconds > 0:
         import oracle
         ent = oracle.Entries(mesh.verts, mesh.tris, params.q_r, params.q_nr, params.q_s)
+        Xh = error_vectors(mesh, x_host)
         order = np.random.default_rng(12345).permutation(n)
         k0 = oracle.num_threads()
         rows = order[:k0]
         t = time.perf_counter()
-        ref = ent.matvec_rows(rows, x_host)
+        ref = ent.matvec_rows(rows, Xh)
         t1 = time.perf_counter() - t
         k = int(min(a.err_rows, max(k0, 2 * a.cpu_seconds / max(t1, 1e-6) * k0)))
         if k > k0:
             rows2 = order[k0:k]
             t = time.perf_counter()
-            ref2 = ent.matvec_rows(rows2, x_host)
+            ref2 = ent.matvec_rows(rows2, Xh)
             t1 += time.perf_counter() - t
             rows = order[:k]
             ref = np.concatenate([ref, ref2])
         cpu = {"value": len(rows) / t1, "unit": "DoF/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"{len(rows)} rows of the dense FP64 product G x (collapsed Gauss rules of the stated "
-                         f"orders, Sauter-Schwab touching pairs), "
-                         f"{t1:.1f} s; a full product is n rows, so DoF/s = rows/s"}
-        ym = y_mixed.cpu().numpy()[rows]
-        yd = y_fp64.cpu().numpy()[rows]
-        rel = {"mixed": float(np.linalg.norm(ym - ref) / np.linalg.norm(ref)),
-               "fp64": float(np.linalg.norm(yd - ref) / np.linalg.norm(ref)),
-               "rows": int(len(rows))}
-        print(f"[bench] oracle rows {len(rows)} in {t1:.1f} s; rel err mixed {rel['mixed']:.2e} "
-              f"fp64 {rel['fp64']:.2e}", file=sys.stderr, flush=True)
+               "sample": f"{len(rows)} rows of the dense FP64 product G X for 3 vectors at once (collapsed Gauss "
+                         f"rules of the stated orders, Sauter-Schwab touching pairs), {t1:.1f} s; a full product "
+                         f"is n rows, so DoF/s = rows/s"}
+        names = ["x_normal", "ones", "x3"]
+        for key, Y in Y_err.items():
+            errs = {nm: float(np.linalg.norm(Y[rows, j] - ref[:, j]) / np.linalg.norm(ref[:, j]))
+                    for j, nm in enumerate(names)}
+            rel[key] = max(errs.values())
+            rel[key + "_per_vector"] = errs
+        rel["rows"] = int(len(rows))
+        print(f"[bench] oracle rows {len(rows)} in {t1:.1f} s; rel err (max of x, 1, x3) mixed {rel['mixed']:.2e} "
+              f"fp64 {rel['fp64']:.2e}; per vector mixed {rel['mixed_per_vector']}", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -429,10 +494,11 @@ def main():
                                f"{'symmetric' if params.sym_rules else 'collapsed Gauss'} ({P} points regular, {Pc} coupling), "
                                f"1 RHS x ~ N(0,1) seed 0",
                    "n": n, "nrhs": 1, "precision": "mixed: FP32 regular-pair quadrature + transfers, "
-                                                   "FP32 Sauter-Schwab Gauss loops on FP64 edge vectors"},
+                                                   "FP64 Sauter-Schwab touching pairs"},
         "setup_s": setup_s,
         "setup_ms": {"tree": (setup_s * 1e3 - st["build_ms"]), **st["setup_ms"]},
         "fp64": {"value": n / dt_fp64, "unit": "DoF/s", "ms_per_step": dt_fp64 * 1e3, "steps": fsteps},
+        "mixed_ss_fp32": ss32,
         "energy_gradient": grad,
         "stored_blocks": stored,
         "linear_basis": linear,

@@ -26,6 +26,7 @@
 #ifndef GCA_H
 #define GCA_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -48,10 +49,24 @@ typedef enum {
  * GCA_FP64 : every quadrature, transfer and accumulation in FP64.
  * GCA_MIXED: regular-pair quadrature (nearfield and coupling), kernel
  *            evaluation and basis transfers in FP32 with FP32 accumulation;
- *            touching pairs (Sauter-Schwab): edge vectors and surface
- *            elements in FP64, the Gauss loops of the regularised integrands
- *            in FP32, values kept in FP64. */
+ *            touching pairs (Sauter-Schwab) in FP64 (edge vectors, surface
+ *            elements, Gauss loops and values), unless the handle was built
+ *            with gca_params.ss_fp32 = 1, which runs their Gauss loops in
+ *            FP32 on FP64 edge vectors (values still kept in FP64). */
 typedef enum { GCA_FP64 = 0, GCA_MIXED = 1 } gca_precision;
+
+/* Element type of the vectors of h2_matvec (x and y alike). */
+typedef enum { GCA_F64 = 0, GCA_F32 = 1 } gca_dtype;
+
+/* Device memory callbacks.  alloc returns `bytes` bytes of device memory
+ * (aligned to at least 256 bytes) usable on `stream`, or NULL when it cannot;
+ * free releases a block that alloc returned, once no queued work uses it.
+ * `stream` is the hipStream_t of the call that allocates (build, store,
+ * solve, gradient, energy, entries; NULL = the default stream) and, for free,
+ * NULL: the library synchronises the device before it frees.  ctx is
+ * gca_params.alloc_ctx, passed through unchanged. */
+typedef void *(*gca_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*gca_free_fn)(void *ptr, void *stream, void *ctx);
 
 /* Flat triangle mesh (host memory).  xyz: nv x 3 vertex coordinates (FP64,
  * row-major); tri: nt x 3 vertex indices (0-based, row-major).  Copied during
@@ -82,7 +97,13 @@ typedef struct {
                             same polynomial degree 2q - 2 (q = 2: 3 points, q = 3:
                             6 points), which needs q_r, q_nr, q_c in {2, 3}.  The
                             Green factor keeps the collapsed rule of order q_A. */
-    int32_t reserved;    /* must be zero */
+    int32_t ss_fp32;     /* 0 (default): touching pairs in FP64 in both products;
+                            1: the mixed product runs the Sauter-Schwab Gauss
+                            loops in FP32 (FP64 edge vectors and values)       */
+    gca_alloc_fn alloc;  /* device memory of the handle and of every call on it;
+                            NULL (with free NULL): hipMalloc / hipFree          */
+    gca_free_fn free;    /* NULL exactly when alloc is NULL                      */
+    void *alloc_ctx;     /* passed to alloc and free                             */
 } gca_params;
 
 #define GCA_NPHASE 9
@@ -126,7 +147,8 @@ typedef struct {
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
- * q_r 3, q_nr 3, q_s 4, q_c 3, sym_rules 0.  With q_nr == q_r near-regular pairs are
+ * q_r 3, q_nr 3, q_s 4, q_c 3, sym_rules 0, ss_fp32 0, no allocator
+ * callbacks (hipMalloc / hipFree).  With q_nr == q_r near-regular pairs are
  * integrated by the regular rule inside the nearfield blocks (no separate
  * list). */
 void gca_params_default(gca_params *p);
@@ -177,15 +199,32 @@ gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p,
 
 /* y = G~ x (Section 4's H^2 representation applied by forward transform,
  * coupling with entries G|t~ x s~ recomputed, backward transform, and
- * nearfield blocks G|t^ x s^ recomputed).  x, y: device, FP64, nt x nrhs,
- * column-major with leading dimension ld >= nt; y is overwritten; x and y
- * must not overlap.  precision: gca_precision.  The touching-pair values run
- * on a side stream owned by the handle, forked from and joined back into
- * `stream` within the call's work, so `stream` orders the whole product.
+ * nearfield blocks G|t^ x s^ recomputed).  x, y: device, nt x nrhs,
+ * column-major with leading dimension ld >= nt, elements of type `dtype`
+ * (GCA_F64 double, GCA_F32 float; the product's own arithmetic is set by
+ * `precision`, not by dtype: FP32 vectors are widened on entry and the result
+ * rounded to FP32 on exit); y is overwritten; x and y must not overlap.
+ * precision: gca_precision.  The touching-pair values run on a side stream
+ * owned by the handle, forked from and joined back into `stream` within the
+ * call's work, so `stream` orders the whole product.  Allocates nothing.
  * Errors: GCA_EINVAL (null handle or pointers, nrhs < 1, ld < nt, aliasing,
- * unknown precision), GCA_EHIP. */
-gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t ld,
+ * unknown dtype or precision), GCA_EHIP. */
+gca_status h2_matvec(gca_h2 h, const void *x, void *y, int64_t nrhs, int64_t ld, int32_t dtype,
                      int32_t precision, void *stream);
+
+/* Electrostatic energy of a density u (the single-layer system of Section 1):
+ *     E = 1/2 u^T G~ u,   and optionally   g = scale * G~ u
+ * (g is dE/du, the gradient of the energy with respect to the density, times
+ * scale).  u: device FP64, nt entries, original triangle order.  e: device
+ * FP64 scalar receiving E, or NULL.  g: device FP64, nt entries, or NULL.
+ * scale: device FP64 scalar, or NULL for 1 (the incoming cotangent of E in a
+ * reverse-mode chain).  The product is the one of h2_matvec in `precision`;
+ * the dot product is FP64 in a fixed reduction order.  The first call
+ * allocates a workspace of nt + 1025 doubles held by the handle.
+ * Errors: GCA_EINVAL (null handle or u, both e and g NULL, g overlapping u,
+ * unknown precision), GCA_ENOMEM, GCA_EHIP. */
+gca_status gca_energy(gca_h2 h, const double *u, const double *scale, double *e, double *g, int32_t precision,
+                      void *stream);
 
 /* Stored-block mode (the paper's GPU setup computes and keeps the coupling
  * matrices G|t~ x s~ and the nearfield blocks G|t^ x s^, Section 8's second
@@ -235,7 +274,7 @@ gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, 
 gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream);
 
 /* Adjoint of the product with respect to the vertex coordinates:
- *     dxyz += alpha * d(a^T G~(X) b) / dX
+ *     dxyz += alpha * scale * d(a^T G~(X) b) / dX
  * with the structure frozen (tree, blocks, boxes, Green points, pivot rows I
  * and Green columns J of every cluster; the bases are the functions
  * V^ = A^[:, J] A^[I, J]^{-1} of the vertex positions that gca_update_geometry
@@ -243,18 +282,25 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream);
  * (recomputed, not stored), of the touching pairs' Sauter-Schwab rules, and of
  * the Green factor rows through the interpolation chain of Sections 3-4.
  * For the energy E = 1/2 u^T G~ u pass a = b = u, alpha = 1/2.
- * a, b: device FP64, n entries, original triangle order; dxyz: device FP64,
- * nv x 3 row-major, accumulated.  precision: GCA_FP64, or GCA_MIXED (FP32
- * nearfield / coupling derivatives and transfers; touching pairs and bases in
- * FP64).  Stream-ordered, no synchronisation after the first call.
+ * a, b: device FP64, n entries, original triangle order; scale: device FP64
+ * scalar or NULL for 1 (an incoming cotangent that stays on the device);
+ * dxyz: device FP64, nv x 3 row-major, accumulated.  precision: GCA_FP64, or
+ * GCA_MIXED (FP32 nearfield / coupling derivatives and transfers; touching
+ * pairs and bases in FP64).  The first call allocates the adjoint's
+ * workspaces and index maps (held by the handle).  Stream-ordered, no
+ * synchronisation after the first call.
  * Errors: GCA_EINVAL, GCA_ENOMEM, GCA_EHIP. */
-gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double alpha, double *dxyz,
-                            int32_t precision, void *stream);
+gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double alpha, const double *scale,
+                            double *dxyz, int32_t precision, void *stream);
 
 /* Galerkin entries g_{I[k], J[k]} (Eq. G_def) for m pairs, computed by the
  * same device quadrature the matrix-vector product uses (the pair's Sauter
- * case decides the rule).  I, J: device int32 original triangle ids;
- * out: device FP64, m values.  Errors: GCA_EINVAL, GCA_EHIP. */
+ * case decides the rule; touching pairs follow the handle's ss_fp32 in the
+ * mixed precision).  I, J: device int32 original triangle ids; out: device
+ * FP64, m values.  Classifies the pairs on the host (copies I and J back and
+ * synchronises the stream); the device workspace of 24 bytes per pair is held
+ * by the handle and grown when a call needs more.
+ * Errors: GCA_EINVAL, GCA_ENOMEM, GCA_EHIP. */
 gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m,
                        double *out, int32_t precision, void *stream);
 

@@ -4,18 +4,22 @@ compression and of the matrix-vector product runs in the HIP library).
     import paper_1810_08429_amd as gca
     tree = gca.Tree(verts, tris, leaf=64)
     H = gca.H2(verts, tris, tree, gca.Params(eta=2.0, eps=1e-4))
-    y = H.matvec(x)                       # x: torch cuda float64, original order
+    y = H.matvec(x)                       # x: torch cuda float64 or float32, original order
     y = H.matvec(x, precision=gca.MIXED)
 
-PyTorch supplies device memory (tensors) and the stream
-(torch.cuda.current_stream()).  The library must be built first
-(python -m paper_1810_08429_amd.build); importing never falls back to
-anything else.
+PyTorch supplies device memory and the stream: vectors are tensors, the
+stream is torch.cuda.current_stream(), and the library's own device memory
+comes from torch's caching allocator through the gca_params callbacks
+(Params(allocator=None) selects hipMalloc instead).  The library must be
+built first (python -m paper_1810_08429_amd.build); importing never falls
+back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -24,6 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgca.so")
 
 FP64, MIXED = 0, 1
+F64, F32 = 0, 1          # gca_dtype of the vectors of h2_matvec
 PHASES = ["permute", "forward", "coupling_blocks", "coupling_reduce", "backward", "near_blocks",
           "near_regular", "touching", "gather", "total"]
 STATUS = {0: "GCA_OK", -1: "GCA_EINVAL", -2: "GCA_ENOMEM", -3: "GCA_EHIP", -4: "GCA_EMESH",
@@ -34,7 +39,7 @@ EXPORTED = [
     "gca_block_tree",
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
     "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
-    "h2_bilinear_grad", "gca_store_blocks",
+    "h2_bilinear_grad", "gca_store_blocks", "gca_energy",
     "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
 ]
 
@@ -51,11 +56,32 @@ class _Mesh(ctypes.Structure):
                 ("xyz", ctypes.c_void_p), ("tri", ctypes.c_void_p)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("eps", ctypes.c_double), ("omega_scale", ctypes.c_double),
                 ("green_m", ctypes.c_int32), ("q_A", ctypes.c_int32), ("q_r", ctypes.c_int32),
                 ("q_nr", ctypes.c_int32), ("q_s", ctypes.c_int32), ("q_c", ctypes.c_int32),
-                ("sym_rules", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sym_rules", ctypes.c_int32), ("ss_fp32", ctypes.c_int32),
+                ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    """gca_alloc_fn: a block of torch's caching allocator on the call's stream."""
+    import torch
+    return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+
+
+def _torch_free(ptr, stream, ctx):
+    """gca_free_fn: returns a block to torch's caching allocator."""
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
 
 
 class _Stats(ctypes.Structure):
@@ -92,13 +118,14 @@ def lib():
     L.gca_tree_destroy.argtypes = [P]
     L.gca_tree_destroy.restype = None
     L.gca_build.argtypes = [P, P, P, P, P]
-    L.h2_matvec.argtypes = [P, P, P, I64, I64, I32, P]
+    L.h2_matvec.argtypes = [P, P, P, I64, I64, I32, I32, P]
+    L.gca_energy.argtypes = [P, P, P, P, P, I32, P]
     L.gca_entries.argtypes = [P, P, P, I64, P, I32, P]
     L.gca_basis_sizes.argtypes = [P, P, P]
     L.gca_basis_export.argtypes = [P, P, P, P]
     L.gca_stats.argtypes = [P, P]
     L.gca_update_geometry.argtypes = [P, P, P]
-    L.h2_bilinear_grad.argtypes = [P, P, P, D, P, I32, P]
+    L.h2_bilinear_grad.argtypes = [P, P, P, D, P, P, I32, P]
     L.gca_solve_refined.argtypes = [P, P, P, D, I32, D, I32, P, P, P]
     L.gca_phase_times.argtypes = [P, I64, P, P]
     L.gca_store_blocks.argtypes = [P, I32, P]
@@ -112,7 +139,7 @@ def lib():
     for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
-                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks",
+                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy",
                  "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -136,6 +163,8 @@ class Params:
     q_s: int = 4
     q_c: int = 3
     sym_rules: int = 0   # 1: symmetric triangle rules (3 / 6 points) for the disjoint pairs
+    ss_fp32: int = 0     # 1: FP32 Gauss loops of the Sauter-Schwab rules in the mixed product
+    allocator: str = "torch"   # "torch": torch's caching allocator; None: hipMalloc / hipFree
 
     def _c(self):
         p = _Params()
@@ -143,6 +172,11 @@ class Params:
         p.green_m, p.q_A, p.q_r, p.q_nr, p.q_s = self.green_m, self.q_A, self.q_r, self.q_nr, self.q_s
         p.q_c = self.q_c
         p.sym_rules = self.sym_rules
+        p.ss_fp32 = self.ss_fp32
+        if self.allocator == "torch":
+            p.alloc, p.free = _TORCH_ALLOC, _TORCH_FREE
+        elif self.allocator is not None:
+            raise ValueError("allocator must be 'torch' or None")
         return p
 
 
@@ -199,6 +233,20 @@ class Tree:
         return far, near
 
 
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    # handles whose memory came from torch's allocator go back to it while
+    # torch is still alive
+    for H in list(_live):
+        try:
+            H.close()
+        except Exception:
+            pass
+
+
 class H2:
     """GCA-H^2 approximation (gca_build) on the current HIP device."""
 
@@ -210,6 +258,7 @@ class H2:
         p = self.params._c()
         _check(lib().gca_build(ctypes.byref(self._m.c), tree.h, ctypes.byref(p), _stream_ptr(stream),
                                ctypes.byref(self.h)))
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -223,17 +272,18 @@ class H2:
             pass
 
     def matvec_into(self, x, y, precision=FP64, stream=None):
-        """y = G~ x for torch cuda float64 tensors (n,) or (n, nrhs) column-major
-        (x.T contiguous); raw call of h2_matvec."""
+        """y = G~ x for torch cuda tensors (n,) or (n, nrhs) column-major
+        (x.T contiguous), both float64 or both float32; raw call of h2_matvec."""
         import torch
-        assert x.dtype == torch.float64 and y.dtype == torch.float64 and x.is_cuda and y.is_cuda
+        assert x.dtype == y.dtype and x.dtype in (torch.float64, torch.float32) and x.is_cuda and y.is_cuda
         if x.dim() == 1:
             nrhs, ld = 1, x.shape[0]
         else:
             nrhs, ld = x.shape[1], x.stride(1)
             assert x.stride(0) == 1 and y.stride(0) == 1 and y.stride(1) == ld
+        dt = F32 if x.dtype == torch.float32 else F64
         _check(lib().h2_matvec(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
-                               nrhs, ld, int(precision), _stream_ptr(stream)))
+                               nrhs, ld, dt, int(precision), _stream_ptr(stream)))
         return y
 
     def matvec(self, x, precision=FP64, stream=None):
@@ -245,6 +295,24 @@ class H2:
             xx = x.t().contiguous().t()
             y = torch.empty_like(xx.t()).t()
         return self.matvec_into(xx, y, precision, stream)
+
+    def energy(self, u, precision=FP64, scale=None, want_e=True, want_g=False, stream=None):
+        """gca_energy: (E, g) with E = 1/2 u^T G~ u (0-dim tensor) and
+        g = scale * G~ u (scale: 0-dim device tensor or None for 1); either
+        may be skipped (None returned)."""
+        import torch
+        u = u.contiguous()
+        assert u.dtype == torch.float64 and u.is_cuda and u.shape == (self.n,)
+        e = torch.empty((), dtype=torch.float64, device=u.device) if want_e else None
+        g = torch.empty_like(u) if want_g else None
+        sc = None
+        if scale is not None:
+            sc = scale.detach().to(dtype=torch.float64).contiguous()
+            assert sc.is_cuda and sc.numel() == 1
+        _check(lib().gca_energy(self.h, _vp(u), _vp(sc) if sc is not None else None,
+                                _vp(e) if e is not None else None, _vp(g) if g is not None else None,
+                                int(precision), _stream_ptr(stream)))
+        return e, g
 
     def solve(self, f, rtol=1e-8, max_outer=20, inner_rtol=1e-3, max_inner=500, stream=None):
         """u with ||f - G~ u|| <= rtol ||f|| (mixed CG inside FP64 refinement).
@@ -274,16 +342,21 @@ class H2:
         assert v.shape == self._m.xyz.shape
         _check(lib().gca_update_geometry(self.h, v.ctypes.data, _stream_ptr(stream)))
 
-    def bilinear_grad(self, a, b, alpha=1.0, dxyz=None, precision=FP64, stream=None):
-        """dxyz += alpha * d(a^T G~ b)/dX (frozen structure); returns dxyz (nv, 3)."""
+    def bilinear_grad(self, a, b, alpha=1.0, dxyz=None, precision=FP64, scale=None, stream=None):
+        """dxyz += alpha * scale * d(a^T G~ b)/dX (frozen structure; scale: 0-dim
+        device tensor or None for 1); returns dxyz (nv, 3)."""
         import torch
         a = a.contiguous()
         b = b.contiguous()
         if dxyz is None:
             dxyz = torch.zeros((self._m.xyz.shape[0], 3), dtype=torch.float64, device=a.device)
+        sc = None
+        if scale is not None:
+            sc = scale.detach().to(dtype=torch.float64).contiguous()
+            assert sc.is_cuda and sc.numel() == 1
         _check(lib().h2_bilinear_grad(self.h, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
-                                      float(alpha), ctypes.c_void_p(dxyz.data_ptr()), int(precision),
-                                      _stream_ptr(stream)))
+                                      float(alpha), _vp(sc) if sc is not None else None,
+                                      ctypes.c_void_p(dxyz.data_ptr()), int(precision), _stream_ptr(stream)))
         return dxyz
 
     def entries(self, I, J, precision=FP64, stream=None):
@@ -370,20 +443,20 @@ def _fns():
         @staticmethod
         def forward(ctx, u, verts, H, precision):
             ctx.H, ctx.precision = H, precision
-            gu = H.matvec(u, precision)
-            ctx.save_for_backward(u, gu)
-            return 0.5 * torch.dot(u, gu)
+            ctx.save_for_backward(u)
+            e, _ = H.energy(u, precision)
+            return e
 
         @staticmethod
         def backward(ctx, ge):
-            u, gu = ctx.saved_tensors
+            (u,) = ctx.saved_tensors
             H, prec = ctx.H, ctx.precision
             du = dv = None
             if ctx.needs_input_grad[0]:
-                du = ge * gu
+                _, du = H.energy(u, prec, scale=ge, want_e=False, want_g=True)
             if ctx.needs_input_grad[1]:
                 dv = torch.zeros((H._m.xyz.shape[0], 3), dtype=torch.float64, device=u.device)
-                H.bilinear_grad(u, u, 0.5 * float(ge), dv, prec)
+                H.bilinear_grad(u, u, 0.5, dv, prec, scale=ge)
             return du, dv, None, None
 
     _autograd_fns = (_Matvec, _Energy)

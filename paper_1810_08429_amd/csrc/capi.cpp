@@ -13,16 +13,38 @@ using namespace gca;
 
 namespace {
 
+// Device memory of a handle: the caller's callbacks, or hipMalloc / hipFree.
+void *dev_alloc(gca_h2_s *h, size_t bytes)
+{
+    bytes = std::max<size_t>(bytes, 256);
+    if (h->prm.alloc) return h->prm.alloc(bytes, (void *)h->cur_stream, h->prm.alloc_ctx);
+    void *q = nullptr;
+    return hipMalloc(&q, bytes) == hipSuccess ? q : nullptr;
+}
+
+void dev_free(gca_h2_s *h, void *p)
+{
+    if (!p) return;
+    if (h->prm.free)
+        h->prm.free(p, nullptr, h->prm.alloc_ctx);
+    else
+        (void)hipFree(p);
+}
+
+gca_status alloc_error(size_t bytes, const char *what)
+{
+    return set_error(GCA_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes (" + what +
+                                     ") failed");
+}
+
+// count elements owned by the handle until gca_destroy
 template <typename T>
 gca_status dalloc(gca_h2_s *h, T **p, size_t count)
 {
     *p = nullptr;
     if (count == 0) count = 1;
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T));
-    if (e != hipSuccess)
-        return set_error(GCA_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
-                                         " bytes failed: " + hipGetErrorString(e));
+    void *q = dev_alloc(h, count * sizeof(T));
+    if (!q) return alloc_error(count * sizeof(T), "handle");
     h->allocs.push_back(q);
     *p = static_cast<T *>(q);
     return GCA_OK;
@@ -46,17 +68,22 @@ gca_status upload_new(gca_h2_s *h, T **dst, const std::vector<T> &src, hipStream
 
 void free_stored(gca_h2_s *h)
 {
+    if (h->d_far_g64 || h->d_near_g64 || h->d_far_g32 || h->d_near_g32) (void)hipDeviceSynchronize();
     for (void **p : {(void **)&h->d_far_g64, (void **)&h->d_near_g64, (void **)&h->d_far_g32,
                      (void **)&h->d_near_g32}) {
-        if (*p) (void)hipFree(*p);
+        dev_free(h, *p);
         *p = nullptr;
     }
 }
 
 void free_all(gca_h2_s *h)
 {
+    (void)hipDeviceSynchronize();
     free_stored(h);
-    for (void *p : h->allocs) (void)hipFree(p);
+    dev_free(h, h->d_ent);
+    h->d_ent = nullptr;
+    h->ent_cap = 0;
+    for (void *p : h->allocs) dev_free(h, p);
     h->allocs.clear();
     if (h->events) {
         for (auto &r : h->ev)
@@ -83,7 +110,9 @@ gca_status check_params(const gca_params *p)
     if (p->q_r < 1 || p->q_r > 6) return set_error(GCA_EINVAL, "q_r must be in [1, 6]");
     if (p->q_nr < 1 || p->q_nr > 7) return set_error(GCA_EINVAL, "q_nr must be in [1, 7]");
     if (p->q_s < 2 || p->q_s > 32) return set_error(GCA_EINVAL, "q_s must be in [2, 32]");
-    if (p->reserved) return set_error(GCA_EINVAL, "reserved field must be zero");
+    if (p->ss_fp32 != 0 && p->ss_fp32 != 1) return set_error(GCA_EINVAL, "ss_fp32 must be 0 or 1");
+    if ((p->alloc == nullptr) != (p->free == nullptr))
+        return set_error(GCA_EINVAL, "alloc and free callbacks must be given together");
     if (p->q_c < 0 || p->q_c > 6) return set_error(GCA_EINVAL, "q_c must be in 1..6 (0: same as q_r)");
     if (p->sym_rules != 0 && p->sym_rules != 1) return set_error(GCA_EINVAL, "sym_rules must be 0 or 1");
     if (p->sym_rules) {
@@ -119,14 +148,14 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
     std::vector<LevelWs> lw(h->level_clusters.size());
     std::vector<void *> temp;
     auto tmp_alloc = [&](void **q, size_t bytes) -> gca_status {
-        *q = nullptr;
-        hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 8));
-        if (e != hipSuccess) return set_error(GCA_ENOMEM, "hipMalloc (basis workspace) failed");
+        *q = dev_alloc(h, bytes);
+        if (!*q) return alloc_error(bytes, "basis workspace");
         temp.push_back(*q);
         return GCA_OK;
     };
     auto cleanup = [&]() {
-        for (void *q : temp) (void)hipFree(q);
+        (void)hipStreamSynchronize(s);
+        for (void *q : temp) dev_free(h, q);
         temp.clear();
     };
     // workspaces shared by the levels (the leaf level is the largest): the
@@ -324,6 +353,7 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     const double t0 = now_ms();
     GCA_TRY(check_params(p));
     h->prm = *p;
+    h->cur_stream = s;
     if (h->prm.q_c == 0) h->prm.q_c = h->prm.q_r;
     // the topology checks ran when the tree was built from this same mesh
     GCA_TRY(mesh_copy_validate(mesh, h->mesh, false));
@@ -886,10 +916,14 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     return GCA_OK;
 }
 
+// One product y = G~ x on stream s.  x, y: FP32 when vf32, else FP64.
+// first: the touching (and near-regular list) values are recomputed; later
+// right-hand sides of the same call reuse them.
 template <typename T>
-hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipStream_t s)
+hipError_t matvec_one(gca_h2_s *h, const void *x, void *y, bool vf32, bool first, hipStream_t s)
 {
     const bool f32 = std::is_same<T, float>::value;
+    const bool ss32 = f32 && h->prm.ss_fp32;   // FP32 Gauss loops of the Sauter-Schwab rules
     T *xp = f32 ? (T *)h->d_xpf : (T *)h->d_xp;
     T *xh = f32 ? (T *)h->d_xhf : (T *)h->d_xh;
     T *yh = f32 ? (T *)h->d_yhf : (T *)h->d_yh;
@@ -915,11 +949,11 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
         if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(h->s_side, h->ev_fork, 0)) != hipSuccess) return e;
         (void)hipEventRecord(h->ev_side[slot][0], h->s_side);
-        if ((e = launch_touching(h, h->d_tval, h->s_side, sizeof(T) == 4)) != hipSuccess) return e;
+        if ((e = launch_touching(h, h->d_tval, h->s_side, ss32)) != hipSuccess) return e;
         (void)hipEventRecord(h->ev_side[slot][1], h->s_side);
         if ((e = hipEventRecord(h->ev_join, h->s_side)) != hipSuccess) return e;
     }
-    if ((e = launch_permute_in<T>(x, h->d_perm, h->n, xp, f32 ? h->d_xp : nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_permute_in<T>(x, vf32, h->d_perm, h->n, xp, f32 ? h->d_xp : nullptr, s)) != hipSuccess) return e;
     mark(1);
     if ((e = launch_forward<T>(h, xp, xh, s)) != hipSuccess) return e;
     mark(2);
@@ -944,11 +978,11 @@ hipError_t matvec_one(gca_h2_s *h, const double *x, double *y, bool first, hipSt
     mark(7);
     if (side) {
         if ((e = hipStreamWaitEvent(s, h->ev_join, 0)) != hipSuccess) return e;
-    } else if (first && !stored && (e = launch_touching(h, h->d_tval, s, sizeof(T) == 4)) != hipSuccess) {
+    } else if (first && !stored && (e = launch_touching(h, h->d_tval, s, ss32)) != hipSuccess) {
         return e;
     }
     mark(8);
-    if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, nval, y, s)) != hipSuccess) return e;
+    if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, nval, y, vf32, s)) != hipSuccess) return e;
     mark(9);
     h->timed = h->events;
     h->n_products++;
@@ -1086,7 +1120,8 @@ gca_status grad_setup(gca_h2_s *h, hipStream_t s)
 }
 
 template <typename T>
-hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alpha, double *dxyz, hipStream_t s)
+hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alpha, const double *scale,
+                       double *dxyz, hipStream_t s)
 {
     GradWs &w = h->gw;
     const bool f32 = std::is_same<T, float>::value;
@@ -1099,8 +1134,8 @@ hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alp
         if ((e = launch_frozen_basis(h, s)) != hipSuccess) return e;
         h->fz.basis_current = true;
     }
-    if ((e = launch_permute_in<T>(a, h->d_perm, h->n, ap, f32 ? w.ap : nullptr, s)) != hipSuccess) return e;
-    if ((e = launch_permute_in<T>(b, h->d_perm, h->n, bp, f32 ? w.bp : nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_permute_in<T>(a, false, h->d_perm, h->n, ap, f32 ? w.ap : nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_permute_in<T>(b, false, h->d_perm, h->n, bp, f32 ? w.bp : nullptr, s)) != hipSuccess) return e;
     if ((e = launch_forward<T>(h, ap, xa, s)) != hipSuccess) return e;
     if ((e = launch_forward<T>(h, bp, xb, s)) != hipSuccess) return e;
     if ((e = launch_far_blocks<T>(h, xa, cp, s)) != hipSuccess) return e;
@@ -1110,7 +1145,7 @@ hipError_t grad_device(gca_h2_s *h, const double *a, const double *b, double alp
     if ((e = launch_backward<T>(h, ya, s)) != hipSuccess) return e;
     if ((e = launch_backward<T>(h, yb, s)) != hipSuccess) return e;
     if ((e = launch_bilinear_grad<T>(h, w, s)) != hipSuccess) return e;
-    return launch_vertex_gather(h, w, alpha, dxyz, s);
+    return launch_vertex_gather(h, w, alpha, scale, dxyz, s);
 }
 
 // Computes and stores the coupling and nearfield block rows (and the list
@@ -1120,12 +1155,10 @@ gca_status store_impl(gca_h2_s *h, int32_t which, hipStream_t s)
     free_stored(h);
     if (which == 0) return GCA_OK;
     auto alloc = [&](void **p, size_t bytes) -> gca_status {
-        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
-        if (e != hipSuccess) {
-            *p = nullptr;
+        *p = dev_alloc(h, bytes);
+        if (!*p) {
             free_stored(h);
-            return set_error(GCA_ENOMEM, "hipMalloc of stored blocks (" + std::to_string(bytes) +
-                                             " bytes) failed: " + hipGetErrorString(e));
+            return alloc_error(bytes, "stored blocks");
         }
         return GCA_OK;
     };
@@ -1163,6 +1196,7 @@ gca_status gca_store_blocks(gca_h2 h, int32_t which, void *stream)
     clear_error();
     if (!h) return set_error(GCA_EINVAL, "handle is NULL");
     if (which & ~((1 << GCA_FP64) | (1 << GCA_MIXED))) return set_error(GCA_EINVAL, "unknown precision bits");
+    h->cur_stream = (hipStream_t)stream;
     gca_status st = store_impl(h, which, (hipStream_t)stream);
     h->stored_mask = st == GCA_OK ? which : 0;
     return st;
@@ -1182,6 +1216,10 @@ void gca_params_default(gca_params *p)
     p->q_nr = 3;
     p->q_s = 4;
     p->q_c = 3;
+    p->ss_fp32 = 0;
+    p->alloc = nullptr;
+    p->free = nullptr;
+    p->alloc_ctx = nullptr;
 }
 
 const char *gca_last_error(void) { return last_error_cstr(); }
@@ -1290,7 +1328,7 @@ gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p, v
     return GCA_OK;
 }
 
-gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t ld, int32_t precision,
+gca_status h2_matvec(gca_h2 h, const void *x, void *y, int64_t nrhs, int64_t ld, int32_t dtype, int32_t precision,
                      void *stream)
 {
     clear_error();
@@ -1298,18 +1336,55 @@ gca_status h2_matvec(gca_h2 h, const double *x, double *y, int64_t nrhs, int64_t
     if (!x || !y) return set_error(GCA_EINVAL, "x or y is NULL");
     if (nrhs < 1) return set_error(GCA_EINVAL, "nrhs must be >= 1");
     if (ld < h->n) return set_error(GCA_EINVAL, "ld must be >= n");
+    if (dtype != GCA_F64 && dtype != GCA_F32) return set_error(GCA_EINVAL, "unknown dtype");
     if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
+    const size_t es = dtype == GCA_F32 ? 4 : 8;
     {
-        const char *xb = (const char *)x, *xe = (const char *)(x + (nrhs - 1) * ld + h->n);
-        const char *yb = (const char *)y, *ye = (const char *)(y + (nrhs - 1) * ld + h->n);
+        const char *xb = (const char *)x, *xe = xb + ((nrhs - 1) * ld + h->n) * es;
+        const char *yb = (const char *)y, *ye = yb + ((nrhs - 1) * ld + h->n) * es;
         if (xb < ye && yb < xe) return set_error(GCA_EINVAL, "x and y overlap");
     }
     hipStream_t s = (hipStream_t)stream;
+    const bool vf32 = dtype == GCA_F32;
     for (int64_t k = 0; k < nrhs; ++k) {
-        hipError_t e = precision == GCA_FP64 ? matvec_one<double>(h, x + k * ld, y + k * ld, k == 0, s)
-                                             : matvec_one<float>(h, x + k * ld, y + k * ld, k == 0, s);
+        const void *xk = (const char *)x + k * ld * es;
+        void *yk = (char *)y + k * ld * es;
+        hipError_t e = precision == GCA_FP64 ? matvec_one<double>(h, xk, yk, vf32, k == 0, s)
+                                             : matvec_one<float>(h, xk, yk, vf32, k == 0, s);
         if (e != hipSuccess) return set_error(GCA_EHIP, std::string("matvec launch: ") + hipGetErrorString(e));
     }
+    return GCA_OK;
+}
+
+gca_status gca_energy(gca_h2 h, const double *u, const double *scale, double *e, double *g, int32_t precision,
+                      void *stream)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (!u) return set_error(GCA_EINVAL, "u is NULL");
+    if (!e && !g) return set_error(GCA_EINVAL, "nothing to compute: e and g are both NULL");
+    if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
+    const int64_t n = h->n;
+    if (g) {
+        const char *ub = (const char *)u, *ue = (const char *)(u + n);
+        const char *gb = (const char *)g, *ge = (const char *)(g + n);
+        if (ub < ge && gb < ue) return set_error(GCA_EINVAL, "g and u overlap");
+    }
+    if (e && (const char *)e >= (const char *)u && (const char *)e < (const char *)(u + n))
+        return set_error(GCA_EINVAL, "e lies inside u");
+    hipStream_t s = (hipStream_t)stream;
+    h->cur_stream = s;
+    if (!h->d_dotp) GCA_TRY(dalloc(h, &h->d_dotp, 1025));
+    double *gu = g;
+    if (!gu) {
+        if (!h->d_ews) GCA_TRY(dalloc(h, &h->d_ews, (size_t)n));
+        gu = h->d_ews;
+    }
+    hipError_t err = precision == GCA_FP64 ? matvec_one<double>(h, u, gu, false, true, s)
+                                           : matvec_one<float>(h, u, gu, false, true, s);
+    if (err == hipSuccess && e) err = launch_dot(u, gu, n, h->d_dotp, e, s, 0.5);
+    if (err == hipSuccess && g && scale) err = launch_scale(scale, g, g, n, s);
+    if (err != hipSuccess) return set_error(GCA_EHIP, std::string("energy launch: ") + hipGetErrorString(err));
     return GCA_OK;
 }
 
@@ -1352,19 +1427,26 @@ gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, 
         order.insert(order.end(), idx[c].begin(), idx[c].end());
     }
     j.off[5] = (int64_t)pa.size();
-    int32_t *dpa = nullptr, *dpb = nullptr, *dpc = nullptr;
-    double *t64 = nullptr;
-    float *t32 = nullptr;
+    // workspace held by the handle: pair arrays (3 x int32) and values (FP64 + FP32) per pair
+    if ((size_t)m > h->ent_cap) {
+        GCA_HIP_TRY(hipStreamSynchronize(s));
+        dev_free(h, h->d_ent);
+        h->d_ent = nullptr;
+        h->ent_cap = 0;
+        const size_t cap = std::max<size_t>((size_t)m, 1024);
+        h->cur_stream = s;
+        h->d_ent = dev_alloc(h, cap * 24);
+        if (!h->d_ent) return alloc_error(cap * 24, "entries workspace");
+        h->ent_cap = cap;
+    }
+    double *t64 = (double *)h->d_ent;
+    int32_t *dpa = (int32_t *)(t64 + h->ent_cap), *dpb = dpa + h->ent_cap, *dpc = dpb + h->ent_cap;
+    float *t32 = (float *)(dpc + h->ent_cap);
     gca_status st = GCA_OK;
     auto fail = [&](hipError_t e, const char *what) {
         st = set_error(GCA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
     };
-    hipError_t e = hipMalloc(&dpa, m * 4);
-    if (e == hipSuccess) e = hipMalloc(&dpb, m * 4);
-    if (e == hipSuccess) e = hipMalloc(&dpc, m * 4);
-    if (e == hipSuccess) e = hipMalloc(&t64, m * 8);
-    if (e == hipSuccess) e = hipMalloc(&t32, m * 4);
-    if (e == hipSuccess) e = hipMemcpyAsync(dpa, pa.data(), m * 4, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(dpa, pa.data(), m * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dpb, pb.data(), m * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dpc, pc.data(), m * 4, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) fail(e, "entries setup");
@@ -1390,11 +1472,6 @@ gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, 
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) fail(e, "entries result");
     }
-    (void)hipFree(dpa);
-    (void)hipFree(dpb);
-    (void)hipFree(dpc);
-    (void)hipFree(t64);
-    (void)hipFree(t32);
     return st;
 }
 
@@ -1415,10 +1492,9 @@ gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, 
         if (fb < ue && ub < fe) return set_error(GCA_EINVAL, "f and u overlap");
     }
     hipStream_t s = (hipStream_t)stream;
-    if (!h->d_sv) {
-        GCA_TRY(dalloc(h, &h->d_sv, 5 * (size_t)n));
-        GCA_TRY(dalloc(h, &h->d_dotp, 1025));
-    }
+    h->cur_stream = s;
+    if (!h->d_sv) GCA_TRY(dalloc(h, &h->d_sv, 5 * (size_t)n));
+    if (!h->d_dotp) GCA_TRY(dalloc(h, &h->d_dotp, 1025));
     double *r = h->d_sv, *d = r + n, *res = d + n, *p = res + n, *q = p + n;
     double *dres = h->d_dotp + 1024;
     auto dot = [&](const double *a, const double *b, double *out) -> gca_status {
@@ -1428,7 +1504,8 @@ gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, 
         return GCA_OK;
     };
     auto product = [&](const double *x, double *y, int prec) -> gca_status {
-        hipError_t e = prec == GCA_FP64 ? matvec_one<double>(h, x, y, true, s) : matvec_one<float>(h, x, y, true, s);
+        hipError_t e = prec == GCA_FP64 ? matvec_one<double>(h, x, y, false, true, s)
+                                        : matvec_one<float>(h, x, y, false, true, s);
         if (e != hipSuccess) return set_error(GCA_EHIP, std::string("product in solve: ") + hipGetErrorString(e));
         return GCA_OK;
     };
@@ -1489,6 +1566,7 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
     for (int64_t k = 0; k < 3 * h->nv; ++k)
         if (!std::isfinite(xyz[k])) return set_error(GCA_EINVAL, "non-finite vertex coordinate");
     hipStream_t s = (hipStream_t)stream;
+    h->cur_stream = s;
     GCA_TRY(frozen_setup(h, s));
     std::copy(xyz, xyz + 3 * h->nv, h->mesh.xyz.begin());
     GCA_TRY(upload(h->d_xyz, h->mesh.xyz, s));
@@ -1517,8 +1595,8 @@ gca_status gca_update_geometry(gca_h2 h, const double *xyz, void *stream)
     return GCA_OK;
 }
 
-gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double alpha, double *dxyz,
-                            int32_t precision, void *stream)
+gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double alpha, const double *scale,
+                            double *dxyz, int32_t precision, void *stream)
 {
     clear_error();
     if (!h) return set_error(GCA_EINVAL, "handle is NULL");
@@ -1526,10 +1604,11 @@ gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double a
     if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
     if (!std::isfinite(alpha)) return set_error(GCA_EINVAL, "alpha must be finite");
     hipStream_t s = (hipStream_t)stream;
+    h->cur_stream = s;
     GCA_TRY(frozen_setup(h, s));
     GCA_TRY(grad_setup(h, s));
-    hipError_t e = precision == GCA_FP64 ? grad_device<double>(h, a, b, alpha, dxyz, s)
-                                         : grad_device<float>(h, a, b, alpha, dxyz, s);
+    hipError_t e = precision == GCA_FP64 ? grad_device<double>(h, a, b, alpha, scale, dxyz, s)
+                                         : grad_device<float>(h, a, b, alpha, scale, dxyz, s);
     if (e != hipSuccess) return set_error(GCA_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
     return GCA_OK;
 }

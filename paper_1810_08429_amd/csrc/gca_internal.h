@@ -329,7 +329,11 @@ struct gca_h2_s {
 
     // solver workspaces (allocated by the first solve)
     double *d_sv = nullptr;          // 5 x n: r, d, res, p, q
-    double *d_dotp = nullptr;        // dot partials (1024) + result
+    double *d_dotp = nullptr;        // dot partials (1024) + result (first solve or energy)
+    double *d_ews = nullptr;         // energy: the product G~ u when the caller wants E only
+    void *d_ent = nullptr;           // gca_entries: pair arrays and values, 24 bytes per pair
+    size_t ent_cap = 0;              // pairs d_ent holds
+    hipStream_t cur_stream = nullptr;   // stream of the call in progress (given to the alloc callback)
 
     // per-matvec workspaces
     double *d_xp = nullptr;          // permuted input (FP64) n
@@ -398,8 +402,11 @@ hipError_t launch_aca(double *R, double *U, double *V, const int64_t *a_off, con
 hipError_t launch_copy_jobs(const int64_t *jobs, int njobs, const double *src, double *dr, double *dc, float *fr,
                             float *fc, hipStream_t s);
 
+// xp = x in cluster order (x: FP32 when xf32, else FP64), xp64 (if not NULL)
+// the same values in FP64
 template <typename T>
-hipError_t launch_permute_in(const double *x, const int32_t *perm, int64_t n, T *xp, double *xp64, hipStream_t s);
+hipError_t launch_permute_in(const void *x, bool xf32, const int32_t *perm, int64_t n, T *xp, double *xp64,
+                             hipStream_t s);
 template <typename T>
 hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s);
 template <typename T>
@@ -421,12 +428,17 @@ hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s);
 hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s, bool fp32 = false);
 template <typename T>
 hipError_t launch_nearreg(gca_h2_s *h, T *nval, hipStream_t s);
+// y (FP32 when yf32, else FP64) in the original order
 template <typename T>
 hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *yh, const T *npart,
-                         const T *nval, double *y, hipStream_t s);
+                         const T *nval, void *y, bool yf32, hipStream_t s);
 
 // vector kernels of the solver (solve.hip)
-hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t s);
+// *out = factor * sum a[i] b[i] (fixed reduction order; partial: 1024 doubles)
+hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t s,
+                      double factor = 1.0);
+// y = (scale ? *scale : 1) * x  (scale: device scalar)
+hipError_t launch_scale(const double *scale, const double *x, double *y, int64_t n, hipStream_t s);
 hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
 hipError_t launch_cg_update(double alpha, const double *p, const double *q, double *d, double *r, int64_t n,
                             hipStream_t s);
@@ -440,7 +452,9 @@ hipError_t launch_frozen_adjoint_solve(gca_h2_s *h, hipStream_t s);
 // adjoint (grad.hip)
 template <typename T>
 hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s);
-hipError_t launch_vertex_gather(gca_h2_s *h, const GradWs &w, double alpha, double *dxyz, hipStream_t s);
+// dxyz += alpha * (scale ? *scale : 1) * (vertex sums of the triangle derivatives)
+hipError_t launch_vertex_gather(gca_h2_s *h, const GradWs &w, double alpha, const double *scale, double *dxyz,
+                                hipStream_t s);
 
 // Entries for pairs sorted by class on the host (gca_entries).
 struct EntryJobs {

@@ -676,10 +676,11 @@ __global__ void k_tri_gather(int64_t n, const int32_t *leaf_of, const int32_t *l
 
 // dxyz[v] += alpha * sum over (triangle position, local slot) incident to v
 __global__ void k_vertex_gather(int64_t nv, const int64_t *vptr, const int32_t *vpos, const int32_t *vslot,
-                                const double *dT, double alpha, double *dxyz)
+                                const double *dT, double alpha, const double *scale, double *dxyz)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv) return;
+    if (scale) alpha *= *scale;
     double a0 = 0, a1 = 0, a2 = 0;
     for (int64_t q = vptr[v]; q < vptr[v + 1]; ++q) {
         const double *t = dT + 9 * (int64_t)vpos[q] + 3 * vslot[q];
@@ -851,10 +852,11 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
 template hipError_t launch_bilinear_grad<float>(gca_h2_s *, const GradWs &, hipStream_t);
 template hipError_t launch_bilinear_grad<double>(gca_h2_s *, const GradWs &, hipStream_t);
 
-hipError_t launch_vertex_gather(gca_h2_s *h, const GradWs &w, double alpha, double *dxyz, hipStream_t s)
+hipError_t launch_vertex_gather(gca_h2_s *h, const GradWs &w, double alpha, const double *scale, double *dxyz,
+                                hipStream_t s)
 {
     hipLaunchKernelGGL(k_vertex_gather, dim3((unsigned)((h->nv + 127) / 128)), dim3(128), 0, s, h->nv, w.vptr,
-                       w.vpos, w.vslot, w.dT, alpha, dxyz);
+                       w.vpos, w.vslot, w.dT, alpha, scale, dxyz);
     return hipGetLastError();
 }
 

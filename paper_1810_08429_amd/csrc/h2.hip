@@ -13,25 +13,30 @@
 
 namespace gca {
 
-template <typename T>
-__global__ void k_permute_in(const double *x, const int32_t *perm, int64_t n, T *xp, double *xp64)
+template <typename Tin, typename T>
+__global__ void k_permute_in(const Tin *x, const int32_t *perm, int64_t n, T *xp, double *xp64)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double v = x[perm[i]];
+    const double v = (double)x[perm[i]];
     xp[i] = (T)v;
     if (xp64) xp64[i] = v;
 }
 
 template <typename T>
-hipError_t launch_permute_in(const double *x, const int32_t *perm, int64_t n, T *xp, double *xp64, hipStream_t s)
+hipError_t launch_permute_in(const void *x, bool xf32, const int32_t *perm, int64_t n, T *xp, double *xp64,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_permute_in<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, perm, n, xp, xp64);
+    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    if (xf32)
+        hipLaunchKernelGGL((k_permute_in<float, T>), grid, blk, 0, s, (const float *)x, perm, n, xp, xp64);
+    else
+        hipLaunchKernelGGL((k_permute_in<double, T>), grid, blk, 0, s, (const double *)x, perm, n, xp, xp64);
     return hipGetLastError();
 }
-template hipError_t launch_permute_in<float>(const double *, const int32_t *, int64_t, float *, double *,
+template hipError_t launch_permute_in<float>(const void *, bool, const int32_t *, int64_t, float *, double *,
                                              hipStream_t);
-template hipError_t launch_permute_in<double>(const double *, const int32_t *, int64_t, double *, double *,
+template hipError_t launch_permute_in<double>(const void *, bool, const int32_t *, int64_t, double *, double *,
                                               hipStream_t);
 
 // sum_i M[i * ld + k] v[i] for i < m: rows are fetched sixteen at a time into
@@ -211,7 +216,7 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nb)
     return x * q + min(x, r) + b / 8;
 }
 
-template <typename T>
+template <typename T, typename Tout>
 __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int32_t *node, const int32_t *rank,
                                                const int64_t *piv_off, const int64_t *v_off, const T *Vt,
                                                const T *yh, const int64_t *nslot_ptr, const int64_t *nslot,
@@ -219,7 +224,7 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
                                                const int32_t *tother, const double *tval, const int64_t *nptr,
                                                const int32_t *nother,
                                                const T *nval, const T *xp, const double *xp64,
-                                               const int32_t *perm, double *y)
+                                               const int32_t *perm, Tout *y)
 {
     const int li = xcd_contiguous(blockIdx.x, gridDim.x);
     const int c = leaves[li];
@@ -235,7 +240,7 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
         double acc64 = 0;
         const int64_t t0 = tell_off[li] + i;
         for (int k = 0; k < tell_k[li]; ++k) acc64 += tval[t0 + (int64_t)k * nr] * xp64[tother[t0 + (int64_t)k * nr]];
-        y[perm[pos]] = (double)acc + acc64;
+        y[perm[pos]] = (Tout)((double)acc + acc64);
     }
 }
 
@@ -287,17 +292,24 @@ hipError_t launch_touching_ell(gca_h2_s *h, const int32_t *pos_li, int32_t *qmap
 
 template <typename T>
 hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *yh, const T *npart,
-                         const T *nval, double *y, hipStream_t s)
+                         const T *nval, void *y, bool yf32, hipStream_t s)
 {
     const T *Vt = std::is_same<T, float>::value ? (const T *)h->d_Vtf : (const T *)h->d_Vt;
-    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)h->leaves.size()), dim3(64), 0, s, h->d_leaves, h->d_node,
-                       h->d_rank, h->d_piv_off, h->d_v_off, Vt, yh, h->d_gnslot_ptr, h->d_gnslot, npart, h->d_tell_off,
-                       h->d_tell_k, h->d_tell_other, h->d_tval, h->d_nptr, h->d_nother, nval, xp, xp64, h->d_perm, y);
+    const dim3 grid((unsigned)h->leaves.size()), blk(64);
+#define GATHER(TO)                                                                                               \
+    hipLaunchKernelGGL((k_gather<T, TO>), grid, blk, 0, s, h->d_leaves, h->d_node, h->d_rank, h->d_piv_off,      \
+                       h->d_v_off, Vt, yh, h->d_gnslot_ptr, h->d_gnslot, npart, h->d_tell_off, h->d_tell_k,       \
+                       h->d_tell_other, h->d_tval, h->d_nptr, h->d_nother, nval, xp, xp64, h->d_perm, (TO *)y)
+    if (yf32)
+        GATHER(float);
+    else
+        GATHER(double);
+#undef GATHER
     return hipGetLastError();
 }
 template hipError_t launch_gather<float>(gca_h2_s *, const float *, const double *, const float *, const float *,
-                                         const float *, double *, hipStream_t);
+                                         const float *, void *, bool, hipStream_t);
 template hipError_t launch_gather<double>(gca_h2_s *, const double *, const double *, const double *,
-                                          const double *, const double *, double *, hipStream_t);
+                                          const double *, const double *, void *, bool, hipStream_t);
 
 }  // namespace gca

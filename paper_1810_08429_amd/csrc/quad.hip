@@ -1203,7 +1203,7 @@ hipError_t launch_entry_jobs(gca_h2_s *h, const EntryJobs &j, double *tmp64, flo
                              hipStream_t s)
 {
     GaussQ g = make_gq(h->gs_x, h->gs_w, h->prm.q_s);
-    const bool f32 = precision != GCA_FP64;   // the mixed product's FP32 Gauss loops
+    const bool f32 = precision != GCA_FP64 && h->prm.ss_fp32;   // FP32 Gauss loops (opt-in, mixed only)
     for (int kind = 0; kind < 3; ++kind) {
         int64_t b = j.off[kind], np = j.off[kind + 1] - b;
         if (!np) continue;

@@ -35,21 +35,36 @@ __global__ void __launch_bounds__(DOT_THREADS) k_dot_partial(const double *a, co
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(DOT_THREADS) k_dot_final(const double *partial, int np, double *out)
+__global__ void __launch_bounds__(DOT_THREADS) k_dot_final(const double *partial, int np, double factor,
+                                                           double *out)
 {
     __shared__ double sh[DOT_THREADS / 64];
     double v = 0;
     for (int i = threadIdx.x; i < np; i += DOT_THREADS) v += partial[i];
     double s = block_sum(v, sh);
-    if (threadIdx.x == 0) *out = s;
+    if (threadIdx.x == 0) *out = factor * s;
 }
 
-hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t s)
+hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t s,
+                      double factor)
 {
     int nb = (int)std::min<int64_t>(DOT_BLOCKS, (n + DOT_THREADS - 1) / DOT_THREADS);
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(DOT_THREADS), 0, s, a, b, n, partial);
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(DOT_THREADS), 0, s, partial, nb, out);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(DOT_THREADS), 0, s, partial, nb, factor, out);
+    return hipGetLastError();
+}
+
+// y = (scale ? *scale : 1) * x
+__global__ void k_scale(const double *scale, const double *x, double *y, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (scale ? *scale : 1.0) * x[i];
+}
+
+hipError_t launch_scale(const double *scale, const double *x, double *y, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, scale, x, y, n);
     return hipGetLastError();
 }
 

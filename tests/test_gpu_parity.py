@@ -88,10 +88,29 @@ def test_entries_mixed_match_oracle(torch, gca, orc, c1):
         got = H.entries(I, J, precision=gca.MIXED).cpu().numpy()
         ref = G[I, J]
         err = np.max(np.abs(got - ref) / np.abs(ref))
-        # mixed: the Sauter-Schwab Gauss loops run in FP32 (sums of at most 128
-        # positive terms, relative rounding < 128 x 2^-24 ~ 8e-6)
-        tol = 1e-5 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6
+        # mixed: touching pairs stay FP64 (Sauter-Schwab), the disjoint classes
+        # run in FP32
+        tol = 1e-12 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6
         assert err < tol, (k, err)
+
+
+def test_entries_mixed_fp32_sauter_schwab_loops(torch, gca, orc, c1):
+    """ss_fp32 = 1 (opt-in): the mixed product's Sauter-Schwab Gauss loops run
+    in FP32 on FP64 edge vectors; sums of at most 128 positive terms give a
+    relative rounding below 128 x 2^-24 ~ 8e-6.  The FP64 precision is not
+    affected by the flag."""
+    m, ent, G = c1
+    H = build(gca, m, 32, eta=2.0, eps=1e-6, ss_fp32=1)
+    rng = np.random.default_rng(1)
+    for k, (I, J) in class_samples(orc, ent, m.nt, rng).items():
+        if k not in (orc.IDENT, orc.EDGE, orc.VERT):
+            continue
+        ref = G[I, J]
+        got = H.entries(I, J, precision=gca.MIXED).cpu().numpy()
+        err = np.max(np.abs(got - ref) / np.abs(ref))
+        assert 1e-12 < err < 1e-5, (k, err)
+        got64 = H.entries(I, J, precision=gca.FP64).cpu().numpy()
+        assert np.max(np.abs(got64 - ref) / np.abs(ref)) < 1e-12, k
 
 
 def test_nearfield_only_operator_equals_dense(torch, gca, c1):
@@ -248,7 +267,7 @@ def test_symmetric_rule_entries_and_nearfield_match_oracle(torch, gca, orc, c1_s
         got = H.entries(I, J).cpu().numpy()
         assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-12, k
         gm = H.entries(I, J, precision=gca.MIXED).cpu().numpy()
-        tol = 1e-5 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6   # FP32 Sauter-Schwab loops
+        tol = 1e-12 if k in (orc.IDENT, orc.EDGE, orc.VERT) else 2e-6   # FP64 Sauter-Schwab
         assert np.max(np.abs(gm - ref) / np.abs(ref)) < tol, k
     H0 = build(gca, m, 32, eta=1e-6, eps=1e-6, sym_rules=1)
     X = synth.rhs_normal(m.nt, 2, seed=1)

@@ -117,16 +117,21 @@ def test_invalid_meshes_are_rejected(gca):
 @pytest.mark.parametrize("field,value", [("eta", 0.0), ("eta", float("inf")), ("eps", -1.0), ("eps", 1.0),
                                          ("green_m", 0), ("green_m", 7), ("q_s", 1), ("q_r", 0),
                                          ("q_nr", 8), ("omega_scale", 0.0), ("q_c", 7), ("q_c", -1),
-                                         ("sym_rules", 2), ("reserved", 1)])
+                                         ("sym_rules", 2), ("ss_fp32", 2), ("ss_fp32", -1),
+                                         ("alloc_only", 1), ("free_only", 1)])
 def test_invalid_parameters_are_rejected_before_device_work(gca, field, value):
     m = synth.icosphere(1)
     tree = gca.Tree(m.verts, m.tris, 8)
-    p = gca.Params()
+    p = gca.Params(allocator=None)
     h = ctypes.c_void_p()
     mesh = gca._MeshArrays(m.verts, m.tris)
-    if field == "reserved":
+    if field in ("alloc_only", "free_only"):
+        # the callbacks come as a pair
         pc = p._c()
-        pc.reserved = value
+        if field == "alloc_only":
+            pc.alloc = gca._TORCH_ALLOC
+        else:
+            pc.free = gca._TORCH_FREE
     else:
         setattr(p, field, value)
         pc = p._c()
@@ -164,7 +169,9 @@ def test_build_rejects_other_mesh_and_large_leaves(gca):
 
 def test_null_arguments(gca):
     L = gca.lib()
-    assert L.h2_matvec(None, None, None, 1, 1, 0, None) == -1
+    assert L.h2_matvec(None, None, None, 1, 1, 0, 0, None) == -1
+    assert L.gca_energy(None, None, None, None, None, 0, None) == -1
+    assert L.h2_bilinear_grad(None, None, None, 0.5, None, None, 0, None) == -1
     assert L.gca_entries(None, None, None, 1, None, 0, None) == -1
     assert L.gca_stats(None, None) == -1
     assert L.gca_tree_build(None, 8, None) == -1
