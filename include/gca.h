@@ -226,6 +226,22 @@ gca_status h2_matvec(gca_h2 h, const void *x, void *y, int64_t nrhs, int64_t ld,
 gca_status gca_energy(gca_h2 h, const double *u, const double *scale, double *e, double *g, int32_t precision,
                       void *stream);
 
+/* gca_energy for callers that cannot allocate device memory (work under
+ * stream capture, tight serving or optimisation loops, hosts that forbid
+ * allocation): the same computation, arguments, checks and results as
+ * gca_energy, but its workspace (the dot-product partials and, when g is
+ * NULL, the product G~ u) lies in a fixed device array of the library,
+ * (1025 + GCA_NOALLOC_MAX_N) doubles = 520 KiB per GPU, held until the process
+ * ends.  Allocates nothing (no hipMalloc, no allocator callback).  With g NULL
+ * the handle's n must not exceed GCA_NOALLOC_MAX_N (GCA_EINVAL otherwise; pass
+ * g, which then receives G~ u, for larger n).  All calls on one GPU share the
+ * array: calls that overlap in time on one GPU (different streams, or host
+ * threads without ordering) race on it and must be serialised by the caller.
+ * Errors: those of gca_energy except GCA_ENOMEM. */
+#define GCA_NOALLOC_MAX_N 65536
+gca_status gca_energy_noalloc(gca_h2 h, const double *u, const double *scale, double *e, double *g,
+                              int32_t precision, void *stream);
+
 /* Stored-block mode (the paper's GPU setup computes and keeps the coupling
  * matrices G|t~ x s~ and the nearfield blocks G|t^ x s^, Section 8's second
  * and third task): computes the entries of every coupling and nearfield block

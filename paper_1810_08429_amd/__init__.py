@@ -39,7 +39,7 @@ EXPORTED = [
     "gca_block_tree",
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
     "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
-    "h2_bilinear_grad", "gca_store_blocks", "gca_energy",
+    "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
     "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
 ]
 
@@ -120,6 +120,7 @@ def lib():
     L.gca_build.argtypes = [P, P, P, P, P]
     L.h2_matvec.argtypes = [P, P, P, I64, I64, I32, I32, P]
     L.gca_energy.argtypes = [P, P, P, P, P, I32, P]
+    L.gca_energy_noalloc.argtypes = [P, P, P, P, P, I32, P]
     L.gca_entries.argtypes = [P, P, P, I64, P, I32, P]
     L.gca_basis_sizes.argtypes = [P, P, P]
     L.gca_basis_export.argtypes = [P, P, P, P]
@@ -139,7 +140,7 @@ def lib():
     for name in ("gca_tree_build", "gca_tree_info", "gca_tree_export", "gca_block_tree", "gca_build",
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
-                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy",
+                 "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
                  "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -312,6 +313,24 @@ class H2:
         _check(lib().gca_energy(self.h, _vp(u), _vp(sc) if sc is not None else None,
                                 _vp(e) if e is not None else None, _vp(g) if g is not None else None,
                                 int(precision), _stream_ptr(stream)))
+        return e, g
+
+    def energy_noalloc(self, u, precision=FP64, scale=None, want_e=True, want_g=False, stream=None):
+        """gca_energy_noalloc: as energy(), with the library's fixed device
+        workspace instead of allocated memory (the result tensors are the
+        caller's, allocated here before the call)."""
+        import torch
+        u = u.contiguous()
+        assert u.dtype == torch.float64 and u.is_cuda and u.shape == (self.n,)
+        e = torch.empty((), dtype=torch.float64, device=u.device) if want_e else None
+        g = torch.empty_like(u) if want_g else None
+        sc = None
+        if scale is not None:
+            sc = scale.detach().to(dtype=torch.float64).contiguous()
+            assert sc.is_cuda and sc.numel() == 1
+        _check(lib().gca_energy_noalloc(self.h, _vp(u), _vp(sc) if sc is not None else None,
+                                        _vp(e) if e is not None else None, _vp(g) if g is not None else None,
+                                        int(precision), _stream_ptr(stream)))
         return e, g
 
     def solve(self, f, rtol=1e-8, max_outer=20, inner_rtol=1e-3, max_inner=500, stream=None):

@@ -20,7 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgca.so")
 BUILD = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["quad.hip", "basis.hip", "h2.hip", "solve.hip", "adjoint.hip", "grad.hip", "linear.hip"]
+HIP_SOURCES = ["quad.hip", "basis.hip", "h2.hip", "solve.hip", "adjoint.hip", "grad.hip", "linear.hip",
+               "noalloc.hip"]
 HOST_SOURCES = ["host.cpp", "capi.cpp"]
 
 

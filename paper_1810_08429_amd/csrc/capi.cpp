@@ -1360,32 +1360,12 @@ gca_status gca_energy(gca_h2 h, const double *u, const double *scale, double *e,
                       void *stream)
 {
     clear_error();
-    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
-    if (!u) return set_error(GCA_EINVAL, "u is NULL");
-    if (!e && !g) return set_error(GCA_EINVAL, "nothing to compute: e and g are both NULL");
-    if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
-    const int64_t n = h->n;
-    if (g) {
-        const char *ub = (const char *)u, *ue = (const char *)(u + n);
-        const char *gb = (const char *)g, *ge = (const char *)(g + n);
-        if (ub < ge && gb < ue) return set_error(GCA_EINVAL, "g and u overlap");
-    }
-    if (e && (const char *)e >= (const char *)u && (const char *)e < (const char *)(u + n))
-        return set_error(GCA_EINVAL, "e lies inside u");
+    GCA_TRY(gca::energy_check(h, u, e, g, precision));
     hipStream_t s = (hipStream_t)stream;
     h->cur_stream = s;
-    if (!h->d_dotp) GCA_TRY(dalloc(h, &h->d_dotp, 1025));
-    double *gu = g;
-    if (!gu) {
-        if (!h->d_ews) GCA_TRY(dalloc(h, &h->d_ews, (size_t)n));
-        gu = h->d_ews;
-    }
-    hipError_t err = precision == GCA_FP64 ? matvec_one<double>(h, u, gu, false, true, s)
-                                           : matvec_one<float>(h, u, gu, false, true, s);
-    if (err == hipSuccess && e) err = launch_dot(u, gu, n, h->d_dotp, e, s, 0.5);
-    if (err == hipSuccess && g && scale) err = launch_scale(scale, g, g, n, s);
-    if (err != hipSuccess) return set_error(GCA_EHIP, std::string("energy launch: ") + hipGetErrorString(err));
-    return GCA_OK;
+    if (!h->d_dotp) GCA_TRY(dalloc(h, &h->d_dotp, gca::DOT_PARTIALS));
+    if (!g && !h->d_ews) GCA_TRY(dalloc(h, &h->d_ews, (size_t)h->n));
+    return gca::energy_run(h, u, scale, e, g, precision, s, h->d_dotp, h->d_ews);
 }
 
 gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, double *out, int32_t precision,
@@ -1494,7 +1474,7 @@ gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, 
     hipStream_t s = (hipStream_t)stream;
     h->cur_stream = s;
     if (!h->d_sv) GCA_TRY(dalloc(h, &h->d_sv, 5 * (size_t)n));
-    if (!h->d_dotp) GCA_TRY(dalloc(h, &h->d_dotp, 1025));
+    if (!h->d_dotp) GCA_TRY(dalloc(h, &h->d_dotp, gca::DOT_PARTIALS));
     double *r = h->d_sv, *d = r + n, *res = d + n, *p = res + n, *q = p + n;
     double *dres = h->d_dotp + 1024;
     auto dot = [&](const double *a, const double *b, double *out) -> gca_status {
@@ -1703,6 +1683,36 @@ void gca_destroy(gca_h2 h)
 }  // extern "C"
 
 namespace gca {
+
+gca_status energy_check(const gca_h2_s *h, const double *u, const double *e, const double *g, int32_t precision)
+{
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (!u) return set_error(GCA_EINVAL, "u is NULL");
+    if (!e && !g) return set_error(GCA_EINVAL, "nothing to compute: e and g are both NULL");
+    if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
+    const int64_t n = h->n;
+    if (g) {
+        const char *ub = (const char *)u, *ue = (const char *)(u + n);
+        const char *gb = (const char *)g, *ge = (const char *)(g + n);
+        if (ub < ge && gb < ue) return set_error(GCA_EINVAL, "g and u overlap");
+    }
+    if (e && (const char *)e >= (const char *)u && (const char *)e < (const char *)(u + n))
+        return set_error(GCA_EINVAL, "e lies inside u");
+    return GCA_OK;
+}
+
+gca_status energy_run(gca_h2_s *h, const double *u, const double *scale, double *e, double *g, int32_t precision,
+                      hipStream_t s, double *dotp, double *ews)
+{
+    const int64_t n = h->n;
+    double *gu = g ? g : ews;
+    hipError_t err = precision == GCA_FP64 ? matvec_one<double>(h, u, gu, false, true, s)
+                                           : matvec_one<float>(h, u, gu, false, true, s);
+    if (err == hipSuccess && e) err = launch_dot(u, gu, n, dotp, e, s, 0.5);
+    if (err == hipSuccess && g && scale) err = launch_scale(scale, g, g, n, s);
+    if (err != hipSuccess) return set_error(GCA_EHIP, std::string("energy launch: ") + hipGetErrorString(err));
+    return GCA_OK;
+}
 
 bool tri_rule(int q, bool sym, TriRule &r)
 {

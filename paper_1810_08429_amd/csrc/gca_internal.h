@@ -437,6 +437,15 @@ hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *
 // *out = factor * sum a[i] b[i] (fixed reduction order; partial: 1024 doubles)
 hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t s,
                       double factor = 1.0);
+// doubles of a dot-product workspace: 1024 partials + one result slot
+constexpr size_t DOT_PARTIALS = 1025;
+
+// gca_energy after its workspaces exist: argument checks (GCA_OK or the
+// status already recorded), and the product, dot and scaling on stream s with
+// dotp (DOT_PARTIALS doubles) and ews (n doubles, used only when g is NULL)
+gca_status energy_check(const gca_h2_s *h, const double *u, const double *e, const double *g, int32_t precision);
+gca_status energy_run(gca_h2_s *h, const double *u, const double *scale, double *e, double *g, int32_t precision,
+                      hipStream_t s, double *dotp, double *ews);
 // y = (scale ? *scale : 1) * x  (scale: device scalar)
 hipError_t launch_scale(const double *scale, const double *x, double *y, int64_t n, hipStream_t s);
 hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
