@@ -100,6 +100,13 @@ typedef struct {
     int32_t ss_fp32;     /* 0 (default): touching pairs in FP64 in both products;
                             1: the mixed product runs the Sauter-Schwab Gauss
                             loops in FP32 (FP64 edge vectors and values)       */
+    int32_t serial;      /* 0 (default): a product overlaps its phases on two
+                            side streams of the handle (touching values; the
+                            transform chain with the coupling blocks) beside
+                            the nearfield blocks on the caller's stream;
+                            1: every phase on the caller's stream in order, so
+                            each kernel has the chip to itself (per-kernel
+                            measurement)                                     */
     gca_alloc_fn alloc;  /* device memory of the handle and of every call on it;
                             NULL (with free NULL): hipMalloc / hipFree          */
     gca_free_fn free;    /* NULL exactly when alloc is NULL                      */
@@ -129,15 +136,18 @@ typedef struct {
                                             3 geometry upload + quadrature points,
                                             4 nested basis (Green factor + ACA, all levels),
                                             5 block slots, lists and workspaces, 6-7 unused */
-    double phase_ms[GCA_NPHASE + 1];     /* last product's last right-hand side, HIP events on
-                                            its stream: 0 permute in, 1 forward transform,
+    double phase_ms[GCA_NPHASE + 1];     /* last product's last right-hand side, HIP events
+                                            around each phase on the stream it runs on:
+                                            0 permute in, 1 forward transform,
                                             2 coupling-block quadrature, 3 coupling reduction,
                                             4 backward transform, 5 nearfield-block quadrature,
-                                            6 near-regular list, 7 touching lists (both only for
-                                            the first right-hand side; 7 is timed on the handle's
-                                            side stream, where the touching lists run beside the
-                                            other phases, so 0-8 need not add up to 9), 8 gather,
-                                            9 total (wall time of the product) */
+                                            6 near-regular list, 7 touching lists (6 and 7 only
+                                            for the first right-hand side), 8 gather,
+                                            9 total (wall time of the product on the caller's
+                                            stream).  Unless gca_params.serial, phases 1-4 (one
+                                            side stream) and 7 (another) run beside 5-6, so
+                                            0-8 need not add up to 9 and a phase's time is its
+                                            duration while it shares the chip */
     int64_t store_entries_far;           /* entries of the stored coupling block rows */
     int64_t store_entries_near;          /* entries of the stored nearfield block rows (masked pairs as zeros) */
     int32_t stored_mask;                 /* precisions with stored block rows (gca_store_blocks) */
@@ -147,7 +157,7 @@ typedef struct {
 } gca_stats_t;
 
 /* Default parameters: eta 2, eps 1e-6, omega_scale 0.25, green_m 3, q_A 3,
- * q_r 3, q_nr 3, q_s 4, q_c 3, sym_rules 0, ss_fp32 0, no allocator
+ * q_r 3, q_nr 3, q_s 4, q_c 3, sym_rules 0, ss_fp32 0, serial 0, no allocator
  * callbacks (hipMalloc / hipFree).  With q_nr == q_r near-regular pairs are
  * integrated by the regular rule inside the nearfield blocks (no separate
  * list). */
@@ -204,9 +214,18 @@ gca_status gca_build(const gca_mesh *mesh, gca_tree tree, const gca_params *p,
  * (GCA_F64 double, GCA_F32 float; the product's own arithmetic is set by
  * `precision`, not by dtype: FP32 vectors are widened on entry and the result
  * rounded to FP32 on exit); y is overwritten; x and y must not overlap.
- * precision: gca_precision.  The touching-pair values run on a side stream
- * owned by the handle, forked from and joined back into `stream` within the
- * call's work, so `stream` orders the whole product.  Allocates nothing.
+ * precision: gca_precision.  Unless the handle was built with
+ * gca_params.serial = 1, the touching-pair values and the transform chain
+ * (forward transform, coupling blocks, backward transform) run on two side
+ * streams owned by the handle, forked from and joined back into `stream`
+ * within the call's work, so `stream` orders the whole product.
+ * nrhs > 1: the right-hand sides are taken 16 at a time and every block entry
+ * is evaluated once per 16 (the transfer, coupling and nearfield products of
+ * the 16 columns on the matrix cores); the first such call in a precision
+ * allocates that precision's batched workspaces, held by the handle
+ * (16 x (2 n + 2 sum of ranks + partial slots) values, plus 16 n doubles for
+ * the mixed product).  nrhs = 1, and products of a precision whose blocks are
+ * stored (gca_store_blocks), allocate nothing and go one column at a time.
  * Errors: GCA_EINVAL (null handle or pointers, nrhs < 1, ld < nt, aliasing,
  * unknown dtype or precision), GCA_EHIP. */
 gca_status h2_matvec(gca_h2 h, const void *x, void *y, int64_t nrhs, int64_t ld, int32_t dtype,
@@ -257,6 +276,24 @@ gca_status gca_energy_noalloc(gca_h2 h, const double *u, const double *scale, do
  * Errors: GCA_EINVAL (null handle, unknown bits), GCA_ENOMEM (nothing is
  * stored then), GCA_EHIP. */
 gca_status gca_store_blocks(gca_h2 h, int32_t which, void *stream);
+
+/* The stored block entries of one precision (after gca_store_blocks with
+ * its bit), for inspection and element-wise checks of the block kernels:
+ * kind 0 the coupling blocks G|t~ x s~ of the admissible pairs t < s
+ * (Section 4's coupling matrices, Section 8's second task), kind 1 the
+ * nearfield blocks G|t^ x s^ of the inadmissible leaf pairs t <= s (Section
+ * 8's third task).  Entry k is g(rows[k], cols[k]) with original triangle
+ * ids; nearfield entries that the pair lists own (touching pairs, and
+ * near-regular pairs when q_nr != q_r) and the lower triangle of diagonal
+ * blocks are stored as 0.  rows, cols (int32), vals (FP64; FP32 entries
+ * widened): host arrays of capacity entries, or all three NULL to query
+ * *count (the number of stored entries of that kind; count may be NULL).
+ * Synchronises the stream.
+ * Errors: GCA_EINVAL (null handle, unknown precision or kind, blocks of that
+ * precision not stored, capacity below the count, only some arrays given),
+ * GCA_EHIP. */
+gca_status gca_block_entries(gca_h2 h, int32_t precision, int32_t kind, int64_t capacity, int32_t *rows,
+                             int32_t *cols, double *vals, int64_t *count, void *stream);
 
 /* Solves G~ u = f by conjugate gradients on the mixed-precision product
  * (inner iterations, stopped when the inner residual falls below
@@ -338,7 +375,7 @@ gca_status gca_stats(gca_h2 h, gca_stats_t *out);
 /* Phase times (ms, HIP events on the stream of each product) of the last
  * min(max_products, 64, products so far) single-right-hand-side products,
  * oldest first: out[q * (GCA_NPHASE + 1) + k], k as in gca_stats_t.phase_ms
- * (the touching phase timed on the side stream).  out may be NULL to query
+ * (each phase timed on the stream it ran on).  out may be NULL to query
  * *count.  Synchronises with the last product. */
 gca_status gca_phase_times(gca_h2 h, int64_t max_products, double *out, int64_t *count);
 

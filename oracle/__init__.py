@@ -431,7 +431,8 @@ def gca_h2(verts, tris, leaf=32, eta=2.0, m=3, eps=1e-6, q_A=3, q=(3, 5, 4),
     """Build the GCA-H^2 approximation step by step (Sections 2-4).  q_c: order
     of the regular rule for the coupling entries G|t~ x s~ (default q[0]); the
     coupling matrices are Galerkin entries of well-separated pairs, whose
-    rule order is a parameter of the method like the others."""
+    rule order is a parameter of the method like the others, and it applies
+    to every pivot pair of an admissible block."""
     tree = cluster_tree(verts, tris, leaf)
     far, near = block_tree(tree, eta)
     if ent is None:
@@ -457,9 +458,13 @@ def gca_h2(verts, tris, leaf=32, eta=2.0, m=3, eps=1e-6, q_A=3, q=(3, 5, 4),
                 r = len(pivots[s])
                 E[s] = Vh[o:o + r, :]
                 o += r
+    # the coupling entries are entries of admissible blocks: one regular rule
+    # of order q_c for every pivot pair, also for a pair whose vertices are
+    # joined by an edge (the near-regular order is a nearfield refinement)
+    qc = q[0] if q_c is None else q_c
     ent_c = None
-    if q_c is not None and q_c != q[0]:
-        ent_c = Entries(verts, tris, q_c, q_c if ent.sym else q[1], q[2], sym=ent.sym)
+    if qc != q[0] or q[1] != qc:
+        ent_c = Entries(verts, tris, qc, qc, q[2], sym=ent.sym)
     return H2(tree, far, near, pivots, V, E, ent, ent_c=ent_c)
 
 

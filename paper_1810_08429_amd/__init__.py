@@ -40,6 +40,7 @@ EXPORTED = [
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
     "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
     "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
+    "gca_block_entries",
     "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
 ]
 
@@ -64,7 +65,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("eps", ctypes.c_double), ("omega_scale", ctypes.c_double),
                 ("green_m", ctypes.c_int32), ("q_A", ctypes.c_int32), ("q_r", ctypes.c_int32),
                 ("q_nr", ctypes.c_int32), ("q_s", ctypes.c_int32), ("q_c", ctypes.c_int32),
-                ("sym_rules", ctypes.c_int32), ("ss_fp32", ctypes.c_int32),
+                ("sym_rules", ctypes.c_int32), ("ss_fp32", ctypes.c_int32), ("serial", ctypes.c_int32),
                 ("alloc", _ALLOC_FN), ("free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
 
 
@@ -121,6 +122,7 @@ def lib():
     L.h2_matvec.argtypes = [P, P, P, I64, I64, I32, I32, P]
     L.gca_energy.argtypes = [P, P, P, P, P, I32, P]
     L.gca_energy_noalloc.argtypes = [P, P, P, P, P, I32, P]
+    L.gca_block_entries.argtypes = [P, I32, I32, I64, P, P, P, P, P]
     L.gca_entries.argtypes = [P, P, P, I64, P, I32, P]
     L.gca_basis_sizes.argtypes = [P, P, P]
     L.gca_basis_export.argtypes = [P, P, P, P]
@@ -141,7 +143,7 @@ def lib():
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
                  "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
-                 "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks"):
+                 "gca_block_entries", "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -165,6 +167,7 @@ class Params:
     q_c: int = 3
     sym_rules: int = 0   # 1: symmetric triangle rules (3 / 6 points) for the disjoint pairs
     ss_fp32: int = 0     # 1: FP32 Gauss loops of the Sauter-Schwab rules in the mixed product
+    serial: int = 0      # 1: every phase of a product on the caller's stream in order
     allocator: str = "torch"   # "torch": torch's caching allocator; None: hipMalloc / hipFree
 
     def _c(self):
@@ -174,6 +177,7 @@ class Params:
         p.q_c = self.q_c
         p.sym_rules = self.sym_rules
         p.ss_fp32 = self.ss_fp32
+        p.serial = self.serial
         if self.allocator == "torch":
             p.alloc, p.free = _TORCH_ALLOC, _TORCH_FREE
         elif self.allocator is not None:
@@ -353,6 +357,22 @@ class H2:
         store_blocks(False, False) releases the storage."""
         which = (1 << FP64 if fp64 else 0) | (1 << MIXED if mixed else 0)
         _check(lib().gca_store_blocks(self.h, which, _stream_ptr(stream)))
+
+    def block_entries(self, precision=FP64, kind=0, stream=None):
+        """gca_block_entries: (rows, cols, vals) of the stored coupling
+        (kind 0) or nearfield (kind 1) block entries of one precision, with
+        original triangle ids (numpy arrays; store_blocks first)."""
+        L = lib()
+        cnt = ctypes.c_int64(0)
+        _check(L.gca_block_entries(self.h, int(precision), int(kind), 0, None, None, None, ctypes.byref(cnt),
+                                   _stream_ptr(stream)))
+        k = cnt.value
+        r = np.empty(k, dtype=np.int32)
+        c = np.empty(k, dtype=np.int32)
+        v = np.empty(k, dtype=np.float64)
+        _check(L.gca_block_entries(self.h, int(precision), int(kind), k, r.ctypes.data, c.ctypes.data,
+                                   v.ctypes.data, None, _stream_ptr(stream)))
+        return r, c, v
 
     def update_geometry(self, verts, stream=None):
         """Move the vertices keeping tree, blocks, boxes, Green points and pivots

@@ -87,13 +87,18 @@ void free_all(gca_h2_s *h)
     h->allocs.clear();
     if (h->events) {
         for (auto &r : h->ev)
-            for (auto &e : r) (void)hipEventDestroy(e);
-        for (auto &r : h->ev_side)
+            for (auto &pr : r)
+                for (auto &e : pr) (void)hipEventDestroy(e);
+        for (auto &r : h->ev_tot)
             for (auto &e : r) (void)hipEventDestroy(e);
         (void)hipEventDestroy(h->ev_fork);
         (void)hipEventDestroy(h->ev_join);
+        (void)hipEventDestroy(h->ev_cfork);
+        (void)hipEventDestroy(h->ev_cjoin);
         (void)hipStreamDestroy(h->s_side);
+        (void)hipStreamDestroy(h->s_chain);
         h->s_side = nullptr;
+        h->s_chain = nullptr;
     }
     h->events = false;
 }
@@ -111,6 +116,7 @@ gca_status check_params(const gca_params *p)
     if (p->q_nr < 1 || p->q_nr > 7) return set_error(GCA_EINVAL, "q_nr must be in [1, 7]");
     if (p->q_s < 2 || p->q_s > 32) return set_error(GCA_EINVAL, "q_s must be in [2, 32]");
     if (p->ss_fp32 != 0 && p->ss_fp32 != 1) return set_error(GCA_EINVAL, "ss_fp32 must be 0 or 1");
+    if (p->serial != 0 && p->serial != 1) return set_error(GCA_EINVAL, "serial must be 0 or 1");
     if ((p->alloc == nullptr) != (p->free == nullptr))
         return set_error(GCA_EINVAL, "alloc and free callbacks must be given together");
     if (p->q_c < 0 || p->q_c > 6) return set_error(GCA_EINVAL, "q_c must be in 1..6 (0: same as q_r)");
@@ -379,8 +385,6 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     };
     GCA_TRY(build_adjacency(h->mesh, h->adj));
     lap(0);
-    GCA_TRY(build_pair_lists(h->mesh, h->adj, h->tree, p->q_nr != p->q_r, h->pl));
-    lap(1);
     block_tree(h->tree, p->eta, h->blk);
 
     // clusters by level, leaves, leaf of each position
@@ -397,29 +401,39 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
             h->max_leaf = std::max(h->max_leaf, nodes[c].end - nodes[c].begin);
         }
     }
-    // every non-regular pair must lie in an inadmissible leaf block
+    // the nearfield partners of every leaf (sorted): a pair of positions lies
+    // in an inadmissible leaf block iff its leaves are partners
+    const size_t nl = h->leaves.size();
+    std::vector<int64_t> nptr(nl + 1, 0);
+    for (size_t b = 0; b < h->blk.near_t.size(); ++b) nptr[leaf_index[h->blk.near_t[b]] + 1]++;
+    for (size_t l = 0; l < nl; ++l) nptr[l + 1] += nptr[l];
+    std::vector<int32_t> partner(nptr[nl]);
     {
-        const size_t nl = h->leaves.size();
-        std::vector<int64_t> ptr(nl + 1, 0);
-        for (size_t b = 0; b < h->blk.near_t.size(); ++b) ptr[leaf_index[h->blk.near_t[b]] + 1]++;
-        for (size_t l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
-        std::vector<int32_t> partner(ptr[nl]);
-        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+        std::vector<int64_t> fill(nptr.begin(), nptr.end() - 1);
         for (size_t b = 0; b < h->blk.near_t.size(); ++b)
             partner[fill[leaf_index[h->blk.near_t[b]]]++] = h->blk.near_s[b];
-        for (size_t l = 0; l < nl; ++l) std::sort(partner.begin() + ptr[l], partner.begin() + ptr[l + 1]);
+    }
+    for (size_t l = 0; l < nl; ++l) std::sort(partner.begin() + nptr[l], partner.begin() + nptr[l + 1]);
+    auto in_near = [&](int32_t pa, int32_t pb) {
+        const int32_t la = leaf_of[pa], lb = leaf_of[pb];
+        const int32_t t = std::min(la, lb), u = std::max(la, lb);
+        const int32_t li = leaf_index[t];
+        return std::binary_search(partner.begin() + nptr[li], partner.begin() + nptr[li + 1], u);
+    };
+    lap(2);
+    // near-regular pairs of admissible blocks are left to those blocks
+    GCA_TRY(build_pair_lists(h->mesh, h->adj, h->tree, p->q_nr != p->q_r, h->pl, in_near));
+    lap(1);
+    // every listed pair lies in an inadmissible leaf block: touching pairs
+    // because the boxes of the supports share the common vertex (distance 0,
+    // never admissible), near-regular pairs by the filter above
+    {
         std::atomic<bool> bad{false};
         parallel_for((int64_t)h->pl.a.size(), [&](int64_t q0, int64_t q1) {
-            for (int64_t q = q0; q < q1; ++q) {
-                int32_t la = leaf_of[h->pl.a[q]], lb = leaf_of[h->pl.b[q]];
-                int32_t t = std::min(la, lb), u = std::max(la, lb);
-                const int32_t li = leaf_index[t];
-                if (!std::binary_search(partner.begin() + ptr[li], partner.begin() + ptr[li + 1], u)) bad = true;
-            }
+            for (int64_t q = q0; q < q1; ++q)
+                if (!in_near(h->pl.a[q], h->pl.b[q])) bad = true;
         });
-        if (bad)
-            return set_error(GCA_EINVAL, "a touching or near-regular pair lies in an admissible block "
-                                         "(eta too large for this mesh)");
+        if (bad) return set_error(GCA_EINTERNAL, "a listed pair lies outside the nearfield blocks");
     }
     lap(2);
 
@@ -865,12 +879,16 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
     GCA_TRY(dalloc(h, &h->d_npart, h->n_gnslot_total));
     GCA_TRY(dalloc(h, &h->d_npartf, h->n_gnslot_total));
     for (auto &r : h->ev)
-        for (auto &e : r) GCA_HIP_TRY(hipEventCreate(&e));
-    for (auto &r : h->ev_side)
+        for (auto &pr : r)
+            for (auto &e : pr) GCA_HIP_TRY(hipEventCreate(&e));
+    for (auto &r : h->ev_tot)
         for (auto &e : r) GCA_HIP_TRY(hipEventCreate(&e));
     GCA_HIP_TRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     GCA_HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    GCA_HIP_TRY(hipEventCreateWithFlags(&h->ev_cfork, hipEventDisableTiming));
+    GCA_HIP_TRY(hipEventCreateWithFlags(&h->ev_cjoin, hipEventDisableTiming));
     GCA_HIP_TRY(hipStreamCreateWithFlags(&h->s_side, hipStreamNonBlocking));
+    GCA_HIP_TRY(hipStreamCreateWithFlags(&h->s_chain, hipStreamNonBlocking));
     h->events = true;
     GCA_HIP_TRY(hipStreamSynchronize(s));
     lap(5);
@@ -918,7 +936,10 @@ gca_status build_impl(const gca_mesh *mesh, gca_tree tree, const gca_params *p, 
 
 // One product y = G~ x on stream s.  x, y: FP32 when vf32, else FP64.
 // first: the touching (and near-regular list) values are recomputed; later
-// right-hand sides of the same call reuse them.
+// right-hand sides of the same call reuse them.  Unless prm.serial, the
+// touching values run on s_side and the transform chain on s_chain beside the
+// nearfield blocks (both forked from s and joined into s before the gather);
+// serial keeps every phase on s in order, so each kernel has the chip alone.
 template <typename T>
 hipError_t matvec_one(gca_h2_s *h, const void *x, void *y, bool vf32, bool first, hipStream_t s)
 {
@@ -931,59 +952,189 @@ hipError_t matvec_one(gca_h2_s *h, const void *x, void *y, bool vf32, bool first
     T *npart = f32 ? (T *)h->d_npartf : (T *)h->d_npart;
     T *nval = f32 ? (T *)h->d_nvalf : (T *)h->d_nval;
     hipError_t e;
-    // phase events: ev[slot][k] before phase k, ev[slot][GCA_NPHASE] after the last one
     const int slot = (int)(h->n_products % gca_h2_s::RING);
-    auto mark = [&](int k) {
-        if (h->events) (void)hipEventRecord(h->ev[slot][k], s);
+    // phase k between beg(k) and fin(k) on the stream it runs on
+    auto beg = [&](int k, hipStream_t st) {
+        if (h->events) (void)hipEventRecord(h->ev[slot][k][0], st);
+    };
+    auto fin = [&](int k, hipStream_t st) {
+        if (h->events) (void)hipEventRecord(h->ev[slot][k][1], st);
     };
     const T *far_g = f32 ? (const T *)h->d_far_g32 : (const T *)h->d_far_g64;
     const T *near_g = f32 ? (const T *)h->d_near_g32 : (const T *)h->d_near_g64;
     const bool stored = far_g != nullptr;
-    const bool side = first && !stored && h->events;
-    h->side_used[slot] = side;
-    mark(0);
+    const bool par = h->events && !h->prm.serial;
+    const bool touch = first && !stored;      // stored mode: computed with the blocks
+    const bool side = touch && par;
+    const hipStream_t cs = par ? h->s_chain : s;
+    if (h->events) (void)hipEventRecord(h->ev_tot[slot][0], s);
     if (side) {
-        // touching values depend on the geometry only: they run beside the
-        // transforms and blocks; the fork orders them after earlier products
-        // on s (whose gathers read the same table)
+        // touching values depend on the geometry only; the fork orders them
+        // after earlier products on s (whose gathers read the same table)
         if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(h->s_side, h->ev_fork, 0)) != hipSuccess) return e;
-        (void)hipEventRecord(h->ev_side[slot][0], h->s_side);
+        beg(TOUCH_PHASE, h->s_side);
         if ((e = launch_touching(h, h->d_tval, h->s_side, ss32)) != hipSuccess) return e;
-        (void)hipEventRecord(h->ev_side[slot][1], h->s_side);
+        fin(TOUCH_PHASE, h->s_side);
         if ((e = hipEventRecord(h->ev_join, h->s_side)) != hipSuccess) return e;
     }
+    beg(0, s);
     if ((e = launch_permute_in<T>(x, vf32, h->d_perm, h->n, xp, f32 ? h->d_xp : nullptr, s)) != hipSuccess) return e;
-    mark(1);
-    if ((e = launch_forward<T>(h, xp, xh, s)) != hipSuccess) return e;
-    mark(2);
+    fin(0, s);
+    if (par) {
+        if ((e = hipEventRecord(h->ev_cfork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(h->s_chain, h->ev_cfork, 0)) != hipSuccess) return e;
+    }
+    beg(1, cs);
+    if ((e = launch_forward<T>(h, xp, xh, cs)) != hipSuccess) return e;
+    fin(1, cs);
+    beg(2, cs);
     if (stored) {
-        if ((e = launch_apply_stored<T>(h, false, xh, far_g, cpart, s)) != hipSuccess) return e;
-    } else if ((e = launch_far_blocks<T>(h, xh, cpart, s)) != hipSuccess) {
+        if ((e = launch_apply_stored<T>(h, false, xh, far_g, cpart, cs)) != hipSuccess) return e;
+    } else if ((e = launch_far_blocks<T>(h, xh, cpart, cs)) != hipSuccess) {
         return e;
     }
-    mark(3);
-    if ((e = launch_coupling_reduce<T>(h, h->d_gslot_ptr, h->d_gslot, cpart, yh, s)) != hipSuccess) return e;
-    mark(4);
-    if ((e = launch_backward<T>(h, yh, s)) != hipSuccess) return e;
-    mark(5);
+    fin(2, cs);
+    beg(3, cs);
+    if ((e = launch_coupling_reduce<T>(h, h->d_gslot_ptr, h->d_gslot, cpart, yh, cs)) != hipSuccess) return e;
+    fin(3, cs);
+    beg(4, cs);
+    if ((e = launch_backward<T>(h, yh, cs)) != hipSuccess) return e;
+    fin(4, cs);
+    if (par && (e = hipEventRecord(h->ev_cjoin, h->s_chain)) != hipSuccess) return e;
+    beg(5, s);
     if (stored) {
         if ((e = launch_apply_stored<T>(h, true, xp, near_g, npart, s)) != hipSuccess) return e;
     } else if ((e = launch_near<T>(h, xp, npart, s)) != hipSuccess) {
         return e;
     }
-    mark(6);
-    // stored mode: the list values were computed with the blocks
-    if (first && !stored && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
-    mark(7);
+    fin(5, s);
+    beg(6, s);
+    if (touch && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
+    fin(6, s);
     if (side) {
         if ((e = hipStreamWaitEvent(s, h->ev_join, 0)) != hipSuccess) return e;
-    } else if (first && !stored && (e = launch_touching(h, h->d_tval, s, ss32)) != hipSuccess) {
-        return e;
+    } else {
+        beg(TOUCH_PHASE, s);
+        if (touch && (e = launch_touching(h, h->d_tval, s, ss32)) != hipSuccess) return e;
+        fin(TOUCH_PHASE, s);
     }
-    mark(8);
+    if (par && (e = hipStreamWaitEvent(s, h->ev_cjoin, 0)) != hipSuccess) return e;
+    beg(8, s);
     if ((e = launch_gather<T>(h, xp, h->d_xp, yh, npart, nval, y, vf32, s)) != hipSuccess) return e;
-    mark(9);
+    fin(8, s);
+    if (h->events) (void)hipEventRecord(h->ev_tot[slot][1], s);
+    h->timed = h->events;
+    h->n_products++;
+    return hipSuccess;
+}
+
+// The batched product needs the block kernels' rules to be instantiated
+// for NB right-hand sides (up to 9 points per triangle) and recomputed
+// blocks (stored block rows are applied one right-hand side at a time).
+bool batch_supported(const gca_h2_s *h, bool f32)
+{
+    auto ok = [](int P) { return P == 1 || P == 3 || P == 4 || P == 6 || P == 9; };
+    const bool stored = f32 ? h->d_far_g32 != nullptr : h->d_far_g64 != nullptr;
+    return !stored && ok(h->P_r) && ok(h->P_c) && h->max_leaf <= 64;
+}
+
+// Workspaces of the batched product in precision T, allocated on first use.
+template <typename T>
+gca_status batch_workspace(gca_h2_s *h, gca_h2_s::Batch *&w)
+{
+    const bool f32 = std::is_same<T, float>::value;
+    w = &h->batch[f32 ? 1 : 0];
+    if (w->xb) return GCA_OK;
+    T *xb = nullptr, *xh = nullptr, *yh = nullptr, *cp = nullptr, *np = nullptr;
+    double *x64 = nullptr;
+    GCA_TRY(dalloc(h, &xb, (size_t)h->n * NB));
+    if (f32) GCA_TRY(dalloc(h, &x64, (size_t)h->n * NB));
+    GCA_TRY(dalloc(h, &xh, (size_t)std::max<int64_t>(h->n_piv, 1) * NB));
+    GCA_TRY(dalloc(h, &yh, (size_t)std::max<int64_t>(h->n_piv, 1) * NB));
+    GCA_TRY(dalloc(h, &cp, (size_t)std::max<int64_t>(h->n_gslot_total, 1) * NB));
+    GCA_TRY(dalloc(h, &np, (size_t)std::max<int64_t>(h->n_gnslot_total, 1) * NB));
+    w->xh = xh;
+    w->yh = yh;
+    w->cpart = cp;
+    w->npart = np;
+    w->xb64 = f32 ? x64 : (double *)xb;
+    w->xb = xb;
+    return GCA_OK;
+}
+
+// One product for nrhs <= NB right-hand sides (columns of x and y with
+// leading dimension ld): every block entry is evaluated once and applied to
+// all of them; transfers, coupling and nearfield products on the matrix
+// cores.  Streams and phase events as in matvec_one (one ring slot per call).
+template <typename T>
+hipError_t matvec_batch(gca_h2_s *h, gca_h2_s::Batch &w, const void *x, void *y, int nrhs, int64_t ld, bool vf32,
+                        bool first, hipStream_t s)
+{
+    const bool f32 = std::is_same<T, float>::value;
+    const bool ss32 = f32 && h->prm.ss_fp32;
+    T *xb = (T *)w.xb, *xh = (T *)w.xh, *yh = (T *)w.yh, *cpart = (T *)w.cpart, *npart = (T *)w.npart;
+    T *nval = f32 ? (T *)h->d_nvalf : (T *)h->d_nval;
+    hipError_t e;
+    const int slot = (int)(h->n_products % gca_h2_s::RING);
+    auto beg = [&](int k, hipStream_t st) {
+        if (h->events) (void)hipEventRecord(h->ev[slot][k][0], st);
+    };
+    auto fin = [&](int k, hipStream_t st) {
+        if (h->events) (void)hipEventRecord(h->ev[slot][k][1], st);
+    };
+    const bool par = h->events && !h->prm.serial;
+    const bool side = first && par;
+    const hipStream_t cs = par ? h->s_chain : s;
+    if (h->events) (void)hipEventRecord(h->ev_tot[slot][0], s);
+    if (side) {
+        if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(h->s_side, h->ev_fork, 0)) != hipSuccess) return e;
+        beg(TOUCH_PHASE, h->s_side);
+        if ((e = launch_touching(h, h->d_tval, h->s_side, ss32)) != hipSuccess) return e;
+        fin(TOUCH_PHASE, h->s_side);
+        if ((e = hipEventRecord(h->ev_join, h->s_side)) != hipSuccess) return e;
+    }
+    beg(0, s);
+    if ((e = launch_permute_in_nb<T>(x, vf32, ld, nrhs, h->d_perm, h->n, xb, f32 ? w.xb64 : nullptr, s)) !=
+        hipSuccess)
+        return e;
+    fin(0, s);
+    if (par) {
+        if ((e = hipEventRecord(h->ev_cfork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(h->s_chain, h->ev_cfork, 0)) != hipSuccess) return e;
+    }
+    beg(1, cs);
+    if ((e = launch_forward_nb<T>(h, xb, xh, cs)) != hipSuccess) return e;
+    fin(1, cs);
+    beg(2, cs);
+    if ((e = launch_far_blocks_nb<T>(h, xh, cpart, cs)) != hipSuccess) return e;
+    fin(2, cs);
+    beg(3, cs);
+    if ((e = launch_coupling_reduce_nb<T>(h, cpart, yh, cs)) != hipSuccess) return e;
+    fin(3, cs);
+    beg(4, cs);
+    if ((e = launch_backward_nb<T>(h, yh, cs)) != hipSuccess) return e;
+    fin(4, cs);
+    if (par && (e = hipEventRecord(h->ev_cjoin, h->s_chain)) != hipSuccess) return e;
+    beg(5, s);
+    if ((e = launch_near_nb<T>(h, xb, npart, s)) != hipSuccess) return e;
+    fin(5, s);
+    beg(6, s);
+    if (first && (e = launch_nearreg<T>(h, nval, s)) != hipSuccess) return e;
+    fin(6, s);
+    if (side) {
+        if ((e = hipStreamWaitEvent(s, h->ev_join, 0)) != hipSuccess) return e;
+    } else {
+        beg(TOUCH_PHASE, s);
+        if (first && (e = launch_touching(h, h->d_tval, s, ss32)) != hipSuccess) return e;
+        fin(TOUCH_PHASE, s);
+    }
+    if (par && (e = hipStreamWaitEvent(s, h->ev_cjoin, 0)) != hipSuccess) return e;
+    beg(8, s);
+    if ((e = launch_gather_nb<T>(h, xb, w.xb64, yh, npart, nval, y, vf32, ld, nrhs, s)) != hipSuccess) return e;
+    fin(8, s);
+    if (h->events) (void)hipEventRecord(h->ev_tot[slot][1], s);
     h->timed = h->events;
     h->n_products++;
     return hipSuccess;
@@ -1187,6 +1338,20 @@ gca_status store_impl(gca_h2_s *h, int32_t which, hipStream_t s)
     return GCA_OK;
 }
 
+// Phase times (ms) of the product in ring slot `slot`: out[k] for the
+// phases, out[GCA_NPHASE] the whole product.
+gca_status phase_ms_of(gca_h2_s *h, int slot, double *out)
+{
+    float ms;
+    for (int k = 0; k < GCA_NPHASE; ++k) {
+        GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][k][0], h->ev[slot][k][1]));
+        out[k] = ms;
+    }
+    GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev_tot[slot][0], h->ev_tot[slot][1]));
+    out[GCA_NPHASE] = ms;
+    return GCA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1217,6 +1382,7 @@ void gca_params_default(gca_params *p)
     p->q_s = 4;
     p->q_c = 3;
     p->ss_fp32 = 0;
+    p->serial = 0;
     p->alloc = nullptr;
     p->free = nullptr;
     p->alloc_ctx = nullptr;
@@ -1346,6 +1512,22 @@ gca_status h2_matvec(gca_h2 h, const void *x, void *y, int64_t nrhs, int64_t ld,
     }
     hipStream_t s = (hipStream_t)stream;
     const bool vf32 = dtype == GCA_F32;
+    const bool f32 = precision == GCA_MIXED;
+    if (nrhs > 1 && batch_supported(h, f32)) {
+        // NB right-hand sides per pass, every block entry evaluated once per pass
+        gca_h2_s::Batch *w = nullptr;
+        h->cur_stream = s;
+        GCA_TRY(f32 ? batch_workspace<float>(h, w) : batch_workspace<double>(h, w));
+        for (int64_t k0 = 0; k0 < nrhs; k0 += NB) {
+            const int nb = (int)std::min<int64_t>(NB, nrhs - k0);
+            const void *xk = (const char *)x + k0 * ld * es;
+            void *yk = (char *)y + k0 * ld * es;
+            hipError_t e = f32 ? matvec_batch<float>(h, *w, xk, yk, nb, ld, vf32, k0 == 0, s)
+                               : matvec_batch<double>(h, *w, xk, yk, nb, ld, vf32, k0 == 0, s);
+            if (e != hipSuccess) return set_error(GCA_EHIP, std::string("batched matvec launch: ") + hipGetErrorString(e));
+        }
+        return GCA_OK;
+    }
     for (int64_t k = 0; k < nrhs; ++k) {
         const void *xk = (const char *)x + k * ld * es;
         void *yk = (char *)y + k * ld * es;
@@ -1453,6 +1635,71 @@ gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, 
         if (e != hipSuccess) fail(e, "entries result");
     }
     return st;
+}
+
+gca_status gca_block_entries(gca_h2 h, int32_t precision, int32_t kind, int64_t capacity, int32_t *rows,
+                             int32_t *cols, double *vals, int64_t *count, void *stream)
+{
+    clear_error();
+    if (!h) return set_error(GCA_EINVAL, "handle is NULL");
+    if (precision != GCA_FP64 && precision != GCA_MIXED) return set_error(GCA_EINVAL, "unknown precision");
+    if (kind != 0 && kind != 1) return set_error(GCA_EINVAL, "kind must be 0 (coupling) or 1 (nearfield)");
+    if (!(h->stored_mask & (1 << precision)))
+        return set_error(GCA_EINVAL, "the blocks of this precision are not stored (gca_store_blocks)");
+    const bool far = kind == 0;
+    const int64_t total = far ? h->n_far_store : h->n_near_store;
+    if (count) *count = total;
+    if (!rows && !cols && !vals) return GCA_OK;
+    if (!rows || !cols || !vals) return set_error(GCA_EINVAL, "rows, cols and vals must all be given");
+    if (capacity < total) return set_error(GCA_EINVAL, "capacity below the number of stored entries");
+    hipStream_t s = (hipStream_t)stream;
+    const int ng = far ? h->n_far_groups : h->n_near_groups;
+    std::vector<int32_t> g_t(ng);
+    std::vector<int64_t> g_ptr(ng + 1, 0), g_soff(ng);
+    if (ng > 0) {
+        GCA_HIP_TRY(hipMemcpyAsync(g_t.data(), far ? h->d_fg_t : h->d_ng_t, ng * 4, hipMemcpyDeviceToHost, s));
+        GCA_HIP_TRY(hipMemcpyAsync(g_ptr.data(), far ? h->d_fg_ptr : h->d_ng_ptr, (ng + 1) * 8,
+                                   hipMemcpyDeviceToHost, s));
+        GCA_HIP_TRY(hipMemcpyAsync(g_soff.data(), far ? h->d_fg_soff : h->d_ng_soff, ng * 8,
+                                   hipMemcpyDeviceToHost, s));
+    }
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+    const int64_t ncol = g_ptr[ng];
+    std::vector<int32_t> col(ncol);
+    if (ncol > 0)
+        GCA_HIP_TRY(hipMemcpyAsync(col.data(), far ? h->d_fcol_e : h->d_ncol_pos, ncol * 4, hipMemcpyDeviceToHost, s));
+    std::vector<double> v64;
+    std::vector<float> v32;
+    if (precision == GCA_FP64) {
+        v64.resize(total);
+        if (total > 0)
+            GCA_HIP_TRY(hipMemcpyAsync(v64.data(), far ? h->d_far_g64 : h->d_near_g64, total * 8,
+                                       hipMemcpyDeviceToHost, s));
+    } else {
+        v32.resize(total);
+        if (total > 0)
+            GCA_HIP_TRY(hipMemcpyAsync(v32.data(), far ? h->d_far_g32 : h->d_near_g32, total * 4,
+                                       hipMemcpyDeviceToHost, s));
+    }
+    GCA_HIP_TRY(hipStreamSynchronize(s));
+    const auto &perm = h->tree.perm;
+    const auto &nodes = h->tree.nodes;
+    for (int k = 0; k < ng; ++k) {
+        const int t = g_t[k];
+        const int64_t nc = g_ptr[k + 1] - g_ptr[k];
+        const int nr = far ? h->rank[t] : nodes[t].end - nodes[t].begin;
+        for (int i = 0; i < nr; ++i) {
+            const int rpos = far ? h->pivots[h->piv_off[t] + i] : nodes[t].begin + i;
+            for (int64_t j = 0; j < nc; ++j) {
+                const int64_t o = g_soff[k] + (int64_t)i * nc + j;
+                const int32_t c = col[g_ptr[k] + j];
+                rows[o] = perm[rpos];
+                cols[o] = perm[far ? h->pivots[c] : c];
+                vals[o] = precision == GCA_FP64 ? v64[o] : (double)v32[o];
+            }
+        }
+    }
+    return GCA_OK;
 }
 
 gca_status gca_solve_refined(gca_h2 h, const double *f, double *u, double rtol, int32_t max_outer,
@@ -1630,18 +1877,8 @@ gca_status gca_stats(gca_h2 h, gca_stats_t *out)
     out->basis_entries_transfer = h->n_e;
     if (h->events && h->timed) {
         const int slot = (int)((h->n_products - 1) % gca_h2_s::RING);
-        GCA_HIP_TRY(hipEventSynchronize(h->ev[slot][GCA_NPHASE]));
-        float ms;
-        for (int k = 0; k < GCA_NPHASE; ++k) {
-            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][k], h->ev[slot][k + 1]));
-            out->phase_ms[k] = ms;
-        }
-        if (h->side_used[slot]) {
-            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev_side[slot][0], h->ev_side[slot][1]));
-            out->phase_ms[TOUCH_PHASE] = ms;
-        }
-        GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][0], h->ev[slot][GCA_NPHASE]));
-        out->phase_ms[GCA_NPHASE] = ms;
+        GCA_HIP_TRY(hipEventSynchronize(h->ev_tot[slot][1]));
+        GCA_TRY(phase_ms_of(h, slot, out->phase_ms));
     }
     return GCA_OK;
 }
@@ -1654,20 +1891,10 @@ gca_status gca_phase_times(gca_h2 h, int64_t max_products, double *out, int64_t 
     *count = c;
     if (!c || !out) return GCA_OK;
     const int last = (int)((h->n_products - 1) % gca_h2_s::RING);
-    GCA_HIP_TRY(hipEventSynchronize(h->ev[last][GCA_NPHASE]));
+    GCA_HIP_TRY(hipEventSynchronize(h->ev_tot[last][1]));
     for (int64_t q = 0; q < c; ++q) {
         const int slot = (int)((h->n_products - c + q) % gca_h2_s::RING);
-        float ms;
-        for (int k = 0; k < GCA_NPHASE; ++k) {
-            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][k], h->ev[slot][k + 1]));
-            out[q * (GCA_NPHASE + 1) + k] = ms;
-        }
-        if (h->side_used[slot]) {
-            GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev_side[slot][0], h->ev_side[slot][1]));
-            out[q * (GCA_NPHASE + 1) + TOUCH_PHASE] = ms;
-        }
-        GCA_HIP_TRY(hipEventElapsedTime(&ms, h->ev[slot][0], h->ev[slot][GCA_NPHASE]));
-        out[q * (GCA_NPHASE + 1) + GCA_NPHASE] = ms;
+        GCA_TRY(phase_ms_of(h, slot, out + q * (GCA_NPHASE + 1)));
     }
     return GCA_OK;
 }

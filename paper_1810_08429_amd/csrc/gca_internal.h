@@ -8,6 +8,7 @@
 #include <array>
 #include <atomic>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <thread>
 #include <vector>
@@ -138,9 +139,13 @@ struct PairLists {
     std::vector<int32_t> slot_a, slot_b;
 };
 // with_nearreg = false: near-regular pairs use the regular rule (q_nr == q_r)
-// and stay in the nearfield blocks, so no list is built for them.
+// and stay in the nearfield blocks, so no list is built for them.  With
+// with_nearreg, near_ok(position a, position b) tells whether a near-regular
+// pair lies in a nearfield block (only those are listed; a near-regular pair
+// of an admissible block is represented by that block like every other pair
+// of it); NULL lists them all.
 gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t, bool with_nearreg,
-                            PairLists &pl);
+                            PairLists &pl, const std::function<bool(int32_t, int32_t)> &near_ok = nullptr);
 int classify_pair(const Mesh &m, const Adjacency &adj, int32_t i, int32_t j, int32_t *code);
 const char *last_error_cstr();
 
@@ -327,6 +332,15 @@ struct gca_h2_s {
     float *d_far_g32 = nullptr, *d_near_g32 = nullptr;
     int32_t stored_mask = 0;         // bits GCA_FP64 / GCA_MIXED
 
+    // workspaces of the batched product (h2_matvec with nrhs > 1), one set
+    // per precision (index 0 FP64, 1 FP32), allocated by the first batched
+    // product of that precision: x and its FP64 copy (n x NB), pivot vectors
+    // xh, yh (n_piv x NB), coupling and nearfield partials (slots x NB)
+    struct Batch {
+        void *xb = nullptr, *xh = nullptr, *yh = nullptr, *cpart = nullptr, *npart = nullptr;
+        double *xb64 = nullptr;
+    } batch[2];
+
     // solver workspaces (allocated by the first solve)
     double *d_sv = nullptr;          // 5 x n: r, d, res, p, q
     double *d_dotp = nullptr;        // dot partials (1024) + result (first solve or energy)
@@ -352,23 +366,29 @@ struct gca_h2_s {
     // points per triangle of the regular, near-regular and coupling rules
     int P_r = 0, P_nr = 0, P_c = 0;
     static constexpr int RING = 64;  // products whose phase events are retained
-    hipEvent_t ev[RING][GCA_NPHASE + 1] = {};
+    // ev[slot][k] = (start, end) of phase k on the stream it ran on;
+    // ev_tot[slot] brackets the whole product on the caller's stream
+    hipEvent_t ev[RING][GCA_NPHASE][2] = {};
+    hipEvent_t ev_tot[RING][2] = {};
     int64_t n_products = 0;
     bool events = false;
     bool timed = false;              // phase events hold a recorded product
-    // touching values are computed on a side stream (non-blocking, default
-    // priority) forked at the start of a product and joined before the gather;
-    // ev_side[slot] times them there (side_used[slot]: that product did)
-    hipStream_t s_side = nullptr;
+    // Unless prm.serial, a product runs on three streams (non-blocking,
+    // default priority): the touching values on s_side (forked at the start
+    // of a product, joined before the gather) and the transform chain
+    // (forward transform, coupling blocks and their reduction, backward
+    // transform) on s_chain (forked after the permutation of x, joined before
+    // the gather), beside the nearfield blocks on the caller's stream.
+    hipStream_t s_side = nullptr, s_chain = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_side[RING][2] = {};
-    bool side_used[RING] = {};
+    hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;
     gca_stats_t st{};
 };
 
 namespace gca {
 
 constexpr int NEAR_CW = 64;          // column chunk of the nearfield block rows (one mask word)
+constexpr int NB = 16;               // right-hand sides of a batched product (N of the 16 x 16 MFMA tiles)
 
 // ---------------------------------------------------------- kernel launchers --
 // All launchers enqueue on `s` and return the launch status.
@@ -424,6 +444,26 @@ template <typename T>
 hipError_t launch_apply_stored(gca_h2_s *h, bool nearfield, const T *x, const T *G, T *part, hipStream_t s);
 template <typename T>
 hipError_t launch_near(gca_h2_s *h, const T *xp, T *npart, hipStream_t s);
+
+// batched product (16 right-hand sides; vectors and partials row-major x 16):
+// block rows on the matrix cores (quad.hip) and the transforms, reduction,
+// permutation and gather (multi.hip)
+template <typename T>
+hipError_t launch_near_nb(gca_h2_s *h, const T *xb, T *npart, hipStream_t s);
+template <typename T>
+hipError_t launch_far_blocks_nb(gca_h2_s *h, const T *xhb, T *cpart, hipStream_t s);
+template <typename T>
+hipError_t launch_permute_in_nb(const void *x, bool xf32, int64_t ld, int nrhs, const int32_t *perm, int64_t n,
+                                T *xb, double *xb64, hipStream_t s);
+template <typename T>
+hipError_t launch_forward_nb(gca_h2_s *h, const T *xb, T *xhb, hipStream_t s);
+template <typename T>
+hipError_t launch_coupling_reduce_nb(gca_h2_s *h, const T *cpart, T *yhb, hipStream_t s);
+template <typename T>
+hipError_t launch_backward_nb(gca_h2_s *h, T *yhb, hipStream_t s);
+template <typename T>
+hipError_t launch_gather_nb(gca_h2_s *h, const T *xb, const double *xb64, const T *yhb, const T *npart,
+                            const T *nval, void *y, bool yf32, int64_t ld, int nrhs, hipStream_t s);
 // Touching-pair values (FP64 table); fp32: the Gauss loops in FP32.
 hipError_t launch_touching(gca_h2_s *h, double *tval, hipStream_t s, bool fp32 = false);
 template <typename T>

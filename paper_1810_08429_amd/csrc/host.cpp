@@ -433,7 +433,7 @@ int classify_pair(const Mesh &m, const Adjacency &adj, int32_t i, int32_t j, int
 }
 
 gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_s &t, bool with_nearreg,
-                            PairLists &pl)
+                            PairLists &pl, const std::function<bool(int32_t, int32_t)> &near_ok)
 {
     const int64_t nt = m.nt;
     std::vector<int32_t> iperm(nt);
@@ -496,6 +496,7 @@ gca_status build_pair_lists(const Mesh &m, const Adjacency &adj, const gca_tree_
                             continue;
                         }
                         if (kls > 3 || (kls == 3 && !with_nearreg)) continue;
+                        if (kls == 3 && near_ok && !near_ok((int32_t)r, pj)) continue;
                     }
                     const bool own = pj >= r;
                     row.push_back(E{pj, own ? (kls << 8 | code) : -1});

@@ -23,6 +23,7 @@
 
 #include "gca_internal.h"
 #include "devfn.h"
+#include "mfma.h"
 
 namespace gca {
 
@@ -753,6 +754,343 @@ hipError_t launch_store_blocks(gca_h2_s *h, T *far_store, T *near_store, hipStre
     if (e != hipSuccess) return e;
     return near_rows<T, true>(h, nullptr, nullptr, near_store, s);
 }
+
+// ------------------------------------ block rows, 16 right-hand sides ------
+// The batched product (h2_matvec with nrhs > 1) evaluates every entry once
+// for NB = 16 right-hand sides.  Per chunk of a block row the workgroup
+// writes the entries of the chunk (rows x columns, masked pairs as 0) into
+// an LDS tile with the wavefront tiles of the single-vector kernels, then
+// applies the tile on the matrix cores: wavefront w multiplies the 16 rows
+// 16w.. by the chunk's columns of X (row partials, accumulated over the
+// chunks) and the transposed tile's 16 columns 16w.. by the rows of X (column
+// partials of the chunk).  Vectors and partials hold the NB values of a row
+// or slot contiguously.  Deterministic: fixed chunk and K order, one writer
+// per partial.
+template <typename T>
+constexpr int nb_cw() { return sizeof(T) == 4 ? 64 : 32; }
+
+// LDS layout (16-byte aligned sections): mask[64] (near) | rowp[64][P] |
+// rown[64][P] | colp[CW][P] | coln[CW][P] | xr[64][NB] | xc[CW][NB] |
+// gs[64][CW + 1]
+template <typename T>
+struct NbLayout {
+    size_t mask, rowp, rown, colp, coln, xr, xc, gs, total;
+    int gld;
+    __host__ __device__ NbLayout(int P, int CW, bool near)
+    {
+        mask = 0;
+        rowp = mask + (near ? al16(64 * 8) : 0);
+        rown = rowp + al16((size_t)64 * P * sizeof(Q4<T>));
+        colp = rown + al16((size_t)64 * P * sizeof(T));
+        coln = colp + al16((size_t)CW * P * sizeof(Q4<T>));
+        xr = coln + al16((size_t)CW * P * sizeof(T));
+        xc = xr + al16((size_t)64 * NB * sizeof(T));
+        gs = xc + al16((size_t)CW * NB * sizeof(T));
+        gld = CW + 1;
+        total = gs + al16((size_t)64 * gld * sizeof(T));
+    }
+};
+
+// acc (rows 16w.. of the tile) += gs[16w.., 0..kw) xc[0..kw) (kw: a multiple of 4)
+template <typename T>
+__device__ __forceinline__ void nb_rows(typename Mfma<T>::acc_t &acc, const T *gs, int gld, const T *xc, int w,
+                                        int kw)
+{
+    const int lane = threadIdx.x & 63, i = 16 * w + (lane & 15), k = lane >> 4;
+    for (int k0 = 0; k0 < kw; k0 += 4)
+        acc = Mfma<T>::mma(gs[i * gld + k0 + k], xc[(k0 + k) * NB + (lane & 15)], acc);
+}
+
+// gs[0..kr, 16w..]^T xr[0..kr) (kr: a multiple of 4)
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::acc_t nb_cols(const T *gs, int gld, const T *xr, int w, int kr)
+{
+    const int lane = threadIdx.x & 63, j = 16 * w + (lane & 15), k = lane >> 4;
+    typename Mfma<T>::acc_t acc = mfma_zero<T>();
+    for (int k0 = 0; k0 < kr; k0 += 4)
+        acc = Mfma<T>::mma(gs[(k0 + k) * gld + j], xr[(k0 + k) * NB + (lane & 15)], acc);
+    return acc;
+}
+
+template <typename T>
+constexpr int nb_waves() { return sizeof(T) == 4 ? 4 : 3; }
+
+// Nearfield block rows for NB right-hand sides: xp and part hold NB values
+// per position / slot.
+template <typename T, int P>
+__global__ void __launch_bounds__(BLK_THREADS, (nb_waves<T>())) k_near_rows_nb(NearArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int CW = a.cw;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int t = a.g_t[g];
+    const int64_t kb = a.g_ptr[g];
+    const int nc = (int)(a.g_ptr[g + 1] - kb);
+    const int rb = a.node[5 * t + 0], nr = a.node[5 * t + 1] - rb;
+    const int64_t rslot = a.g_rslot[g];
+    const uint64_t *gm = a.mask + a.g_moff[g];
+    const NbLayout<T> L(P, CW, true);
+    uint64_t *mask = reinterpret_cast<uint64_t *>(smem + L.mask);
+    Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
+    T *rown = reinterpret_cast<T *>(smem + L.rown);
+    Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
+    T *coln = reinterpret_cast<T *>(smem + L.coln);
+    T *xr = reinterpret_cast<T *>(smem + L.xr);
+    T *xc = reinterpret_cast<T *>(smem + L.xc);
+    T *gs = reinterpret_cast<T *>(smem + L.gs);
+    const int gld = L.gld;
+    const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
+    const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
+    const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+    auto point = [&](int pos, int p) {
+        if constexpr (sizeof(T) == 4) {
+            const double *c = a.cent + 4 * (size_t)pos;
+            const float4 v = reinterpret_cast<const float4 *>(a.qloc)[(size_t)pos * P + p];
+            return Q4<T>{(T)(c[0] - cx) + v.x, (T)(c[1] - cy) + v.y, (T)(c[2] - cz) + v.z, v.w};
+        } else {
+            const double *src = a.q + ((size_t)pos * P + p) * 4;
+            return Q4<T>{src[0] - cx, src[1] - cy, src[2] - cz, src[3]};
+        }
+    };
+    for (int e = tid; e < nr * P; e += BLK_THREADS) {
+        const int i = e / P, p = e - i * P;
+        const Q4<T> v = point(rb + i, p);
+        rowp[e] = v;
+        rown[e] = v.x * v.x + v.y * v.y + v.z * v.z;
+    }
+    // rows beyond nr read as zero by the column products
+    for (int e = tid; e < 64 * NB; e += BLK_THREADS) xr[e] = e < nr * NB ? a.xp[(int64_t)rb * NB + e] : (T)0;
+    typename Mfma<T>::acc_t racc = mfma_zero<T>();
+    const int kr = (nr + 3) & ~3;
+    for (int c0 = 0; c0 < nc; c0 += CW) {
+        const int cw = min(CW, nc - c0);
+        const int ch = c0 / NEAR_CW, cb = c0 - ch * NEAR_CW;
+        __syncthreads();
+        for (int e = tid; e < cw * P; e += BLK_THREADS) {
+            const int j = e / P, p = e - j * P;
+            const Q4<T> v = point(a.col_pos[kb + c0 + j], p);
+            colp[e] = Q4<T>{-2 * v.x, -2 * v.y, -2 * v.z, v.w};
+            coln[e] = v.x * v.x + v.y * v.y + v.z * v.z;
+        }
+        for (int e = tid; e < CW * NB; e += BLK_THREADS) {
+            const int j = e / NB;
+            xc[e] = j < cw ? a.xp[(int64_t)a.col_pos[kb + c0 + j] * NB + (e - j * NB)] : (T)0;
+        }
+        for (int i = tid; i < nr; i += BLK_THREADS) mask[i] = gm[(size_t)ch * nr + i];
+        for (int e = tid; e < 64 * gld; e += BLK_THREADS) gs[e] = 0;
+        __syncthreads();
+        tile_pass<T, P, true, true>(nr, cw, cb, rowp, rown, colp, coln, nullptr, nullptr, mask, nullptr, nullptr,
+                                     gs, gld);
+        __syncthreads();
+        if (16 * wv < nr) nb_rows<T>(racc, gs, gld, xc, wv, (cw + 3) & ~3);
+        if (16 * wv < cw) {
+            const typename Mfma<T>::acc_t cacc = nb_cols<T>(gs, gld, xr, wv, kr);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * wv + Mfma<T>::row(lane, v);
+                if (j < cw) a.part[a.col_out[kb + c0 + j] * NB + (lane & 15)] = cacc[v];
+            }
+        }
+    }
+    if (16 * wv < nr) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * wv + Mfma<T>::row(lane, v);
+            if (i < nr) a.part[(rslot + i) * NB + (lane & 15)] = racc[v];
+        }
+    }
+}
+
+// Coupling block rows for NB right-hand sides: xh and part hold NB values
+// per pivot entry / slot; row blocks of 64 pivots.
+template <typename T, int P>
+__global__ void __launch_bounds__(BLK_THREADS, (nb_waves<T>())) k_far_rows_nb(FarArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr bool F32 = sizeof(T) == 4;
+    const int CW = a.cw;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int t = a.g_t[g];
+    const int64_t kb = a.g_ptr[g];
+    const int nc = (int)(a.g_ptr[g + 1] - kb);
+    const int nr = a.rank[t];
+    const int64_t xro = a.piv_off[t];
+    const int64_t rslot = a.g_rslot[g];
+    const NbLayout<T> L(P, CW, false);
+    Q4<T> *rowp = reinterpret_cast<Q4<T> *>(smem + L.rowp);
+    T *rown = reinterpret_cast<T *>(smem + L.rown);
+    Q4<T> *colp = reinterpret_cast<Q4<T> *>(smem + L.colp);
+    T *coln = reinterpret_cast<T *>(smem + L.coln);
+    T *xr = reinterpret_cast<T *>(smem + L.xr);
+    T *xc = reinterpret_cast<T *>(smem + L.xc);
+    T *gs = reinterpret_cast<T *>(smem + L.gs);
+    const int gld = L.gld;
+    const double cx = 0.5 * (a.box[8 * t + 0] + a.box[8 * t + 3]);
+    const double cy = 0.5 * (a.box[8 * t + 1] + a.box[8 * t + 4]);
+    const double cz = 0.5 * (a.box[8 * t + 2] + a.box[8 * t + 5]);
+    for (int r0 = 0; r0 < nr; r0 += 64) {
+        const int rw = min(64, nr - r0);
+        if (r0 > 0) __syncthreads();
+        for (int e = tid; e < rw * P; e += BLK_THREADS) {
+            const int i = e / P, p = e - i * P;
+            if (F32) {
+                const float4 v = reinterpret_cast<const float4 *>(a.pq32)[(size_t)(xro + r0 + i) * P + p];
+                rowp[e] = Q4<T>{(T)v.x, (T)v.y, (T)v.z, (T)v.w};
+                rown[e] = (T)(v.x * v.x + v.y * v.y + v.z * v.z);
+            } else {
+                const double *src = a.q + ((size_t)a.piv[xro + r0 + i] * P + p) * 4;
+                const T x = (T)(src[0] - cx), y = (T)(src[1] - cy), z = (T)(src[2] - cz);
+                rowp[e] = Q4<T>{x, y, z, (T)src[3]};
+                rown[e] = x * x + y * y + z * z;
+            }
+        }
+        for (int e = tid; e < 64 * NB; e += BLK_THREADS)
+            xr[e] = e < rw * NB ? a.xh[(xro + r0) * NB + e] : (T)0;
+        typename Mfma<T>::acc_t racc = mfma_zero<T>();
+        const int kr = (rw + 3) & ~3;
+        for (int c0 = 0; c0 < nc; c0 += CW) {
+            const int cw = min(CW, nc - c0);
+            __syncthreads();
+            for (int e = tid; e < cw * P; e += BLK_THREADS) {
+                const int j = e / P, p = e - j * P;
+                const int64_t k = kb + c0 + j;
+                const int ce = a.col_e[k];
+                if (F32) {
+                    const int cs = a.col_s[k];
+                    const float ox = (float)(0.5 * (a.box[8 * cs + 0] + a.box[8 * cs + 3]) - cx);
+                    const float oy = (float)(0.5 * (a.box[8 * cs + 1] + a.box[8 * cs + 4]) - cy);
+                    const float oz = (float)(0.5 * (a.box[8 * cs + 2] + a.box[8 * cs + 5]) - cz);
+                    const float4 v = reinterpret_cast<const float4 *>(a.pq32)[(size_t)ce * P + p];
+                    const float y0 = v.x + ox, y1 = v.y + oy, y2 = v.z + oz;
+                    colp[e] = Q4<T>{(T)(-2 * y0), (T)(-2 * y1), (T)(-2 * y2), (T)v.w};
+                    coln[e] = (T)(y0 * y0 + y1 * y1 + y2 * y2);
+                } else {
+                    const double *src = a.q + ((size_t)a.piv[ce] * P + p) * 4;
+                    const T y0 = (T)(src[0] - cx), y1 = (T)(src[1] - cy), y2 = (T)(src[2] - cz);
+                    colp[e] = Q4<T>{-2 * y0, -2 * y1, -2 * y2, (T)src[3]};
+                    coln[e] = y0 * y0 + y1 * y1 + y2 * y2;
+                }
+            }
+            for (int e = tid; e < CW * NB; e += BLK_THREADS) {
+                const int j = e / NB;
+                xc[e] = j < cw ? a.xh[(int64_t)a.col_e[kb + c0 + j] * NB + (e - j * NB)] : (T)0;
+            }
+            for (int e = tid; e < 64 * gld; e += BLK_THREADS) gs[e] = 0;
+            __syncthreads();
+            tile_pass<T, P, false, true>(rw, cw, 0, rowp, rown, colp, coln, nullptr, nullptr, nullptr, nullptr,
+                                          nullptr, gs, gld);
+            __syncthreads();
+            if (16 * wv < rw) nb_rows<T>(racc, gs, gld, xc, wv, (cw + 3) & ~3);
+            if (16 * wv < cw) {
+                const typename Mfma<T>::acc_t cacc = nb_cols<T>(gs, gld, xr, wv, kr);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = 16 * wv + Mfma<T>::row(lane, v);
+                    if (j < cw) {
+                        T *o = a.part + a.col_out[kb + c0 + j] * NB + (lane & 15);
+                        *o = r0 == 0 ? cacc[v] : *o + cacc[v];
+                    }
+                }
+            }
+        }
+        if (16 * wv < rw) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * wv + Mfma<T>::row(lane, v);
+                if (i < rw) a.part[(rslot + r0 + i) * NB + (lane & 15)] = racc[v];
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_near_nb(gca_h2_s *h, const T *xp, T *npart, hipStream_t s)
+{
+    const int ng = h->n_near_groups;
+    if (ng == 0) return hipSuccess;
+    if (xp == nullptr || npart == nullptr) return hipErrorInvalidValue;
+    const int P = h->P_r;
+    NearArgs<T> a{};
+    a.g_t = h->d_ng_t;
+    a.g_ptr = h->d_ng_ptr;
+    a.g_rslot = h->d_ng_rslot;
+    a.g_moff = h->d_ng_moff;
+    a.col_pos = h->d_ncol_pos;
+    a.col_out = h->d_ncol_out;
+    a.mask = h->d_nmask;
+    a.node = h->d_node;
+    a.box = h->d_box;
+    a.q = h->d_qr;
+    a.cent = h->d_cent;
+    a.qloc = h->d_qloc32;
+    a.xp = xp;
+    a.part = npart;
+    a.ng = ng;
+    a.rmax = h->max_leaf;
+    if (a.rmax > 64) return hipErrorInvalidValue;
+    a.cw = nb_cw<T>();
+    while (a.cw > 16 && NbLayout<T>(P, a.cw, true).total > 64 * 1024) a.cw /= 2;
+    const size_t sm = NbLayout<T>(P, a.cw, true).total;
+    if (sm > 64 * 1024) return hipErrorInvalidValue;
+    switch (P) {
+#define CASE(PP)                                                                                  \
+    case PP:                                                                                      \
+        hipLaunchKernelGGL((k_near_rows_nb<T, PP>), dim3(ng), dim3(BLK_THREADS), sm, s, a);         \
+        break;
+        CASE(1) CASE(3) CASE(4) CASE(6) CASE(9)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_far_blocks_nb(gca_h2_s *h, const T *xh, T *cpart, hipStream_t s)
+{
+    const int ng = h->n_far_groups;
+    if (ng == 0) return hipSuccess;
+    if (xh == nullptr || cpart == nullptr) return hipErrorInvalidValue;
+    const int P = h->P_c;
+    FarArgs<T> a{};
+    a.g_t = h->d_fg_t;
+    a.g_ptr = h->d_fg_ptr;
+    a.g_rslot = h->d_fg_rslot;
+    a.col_e = h->d_fcol_e;
+    a.col_s = h->d_fcol_s;
+    a.col_out = h->d_fcol_out;
+    a.rank = h->d_rank;
+    a.piv_off = h->d_piv_off;
+    a.piv = h->d_piv;
+    a.box = h->d_box;
+    a.q = h->d_qc;
+    a.pq32 = h->d_pq32;
+    a.xh = xh;
+    a.part = cpart;
+    a.ng = ng;
+    a.rmax = 64;
+    a.cw = nb_cw<T>();
+    while (a.cw > 16 && NbLayout<T>(P, a.cw, false).total > 64 * 1024) a.cw /= 2;
+    const size_t sm = NbLayout<T>(P, a.cw, false).total;
+    if (sm > 64 * 1024) return hipErrorInvalidValue;
+    switch (P) {
+#define CASE(PP)                                                                                 \
+    case PP:                                                                                     \
+        hipLaunchKernelGGL((k_far_rows_nb<T, PP>), dim3(ng), dim3(BLK_THREADS), sm, s, a);         \
+        break;
+        CASE(1) CASE(3) CASE(4) CASE(6) CASE(9)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_near_nb<float>(gca_h2_s *, const float *, float *, hipStream_t);
+template hipError_t launch_near_nb<double>(gca_h2_s *, const double *, double *, hipStream_t);
+template hipError_t launch_far_blocks_nb<float>(gca_h2_s *, const float *, float *, hipStream_t);
+template hipError_t launch_far_blocks_nb<double>(gca_h2_s *, const double *, double *, hipStream_t);
 
 // ----------------------------------------------------- stored block rows ---
 // Product with block rows stored by the STORE kernels: G_g (nr x nc,

@@ -661,9 +661,9 @@ def test_coupling_rule_order_changes_only_admissible_blocks(orc, sphere3_dense):
     m, e, G = sphere3_dense
     h3 = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, eps=1e-6, ent=e)
     hs = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, eps=1e-6, ent=e, q_c=3)
-    assert hs.ent_c is None
     h2 = orc.gca_h2(m.verts, m.tris, leaf=32, eta=2.0, eps=1e-6, ent=e, q_c=2)
     D3, D2 = orc.h2_dense(h3), orc.h2_dense(h2)
+    assert np.array_equal(orc.h2_dense(hs), D3)
     tree = h3.tree
     for (t, s) in h3.near:
         ix = np.ix_(tree.indices(t), tree.indices(s))
