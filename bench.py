@@ -166,6 +166,11 @@ def parse():
     ap.add_argument("--green-m", type=int, default=None, help="override the workload's Green order")
     ap.add_argument("--ss32-steps", type=int, default=10,
                     help="timed mixed products of a handle built with FP32 Sauter-Schwab loops (0 disables it)")
+    ap.add_argument("--serial-steps", type=int, default=10,
+                    help="timed mixed products of a handle built with serial = 1 (every phase alone on the "
+                         "caller's stream: per-kernel rooflines in isolation; 0 disables it)")
+    ap.add_argument("--rhs16-steps", type=int, default=5,
+                    help="timed batched products with 16 right-hand sides per precision (0 disables it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
@@ -385,6 +390,46 @@ def main():
         print(f"[bench] mixed with FP32 Sauter-Schwab loops: {dt32 * 1e3:.3f} ms/product", file=sys.stderr,
               flush=True)
 
+    # the same product with every phase alone on the caller's stream
+    # (gca_params.serial = 1): each kernel's duration without the others
+    serial = None
+    if a.serial_steps > 0:
+        ps = gca.Params(**{k: getattr(params, k) for k in params.__dataclass_fields__})
+        ps.serial = 1
+        Hs = gca.H2(mesh.verts, mesh.tris, tree, ps)
+        dts, phs, ys = run(Hs, gca.MIXED, a.serial_steps, 2)
+        pms = dict(zip(gca.PHASES, phs.mean(axis=0).tolist()))
+        serial = {"ms_per_step": dts * 1e3, "steps": a.serial_steps, "phases_ms": pms,
+                  "bit_equal_to_overlapped": bool(torch.equal(ys, y_mixed))}
+        Hs.close()
+        print(f"[bench] mixed, phases serialised: {dts * 1e3:.3f} ms/product", file=sys.stderr, flush=True)
+
+    # 16 right-hand sides in one call: every block entry evaluated once for
+    # the 16 columns, transfer / coupling / nearfield products as matrix-core
+    # tiles; against 16 single products of the same columns
+    rhs16 = None
+    if a.rhs16_steps > 0:
+        # column-major n x 16 (leading dimension n), as h2_matvec takes them
+        X16 = torch.tensor(synth.rhs_normal(n, 16, seed=1).T.copy(), device=dev).t()
+        Y16 = torch.empty((16, n), dtype=torch.float64, device=dev).t()
+        rhs16 = {"workload": "16 columns x ~ N(0,1) seed 1 in one h2_matvec call (nrhs = 16, ld = n)"}
+        for prec, name, dt1 in ((gca.MIXED, "mixed", dt_mixed), (gca.FP64, "fp64", dt_fp64)):
+            H.matvec_into(X16, Y16, precision=prec)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(a.rhs16_steps):
+                H.matvec_into(X16, Y16, precision=prec)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / a.rhs16_steps
+            ph = dict(zip(gca.PHASES, H.phase_times(a.rhs16_steps).mean(axis=0).tolist()))
+            y0 = H.matvec(X16[:, 0].contiguous(), precision=prec)
+            rhs16[name] = {"value": 16 * n / dt, "unit": "DoF/s", "ms_per_step": dt * 1e3, "steps": a.rhs16_steps,
+                           "speedup_vs_16_single_products": 16 * dt1 / dt, "phases_ms": ph,
+                           "rel_diff_column0_vs_single": float((Y16[:, 0] - y0).abs().max() / y0.abs().max())}
+            print(f"[bench] 16 right-hand sides {name}: {dt * 1e3:.3f} ms ({16 * dt1 / dt:.1f}x 16 single products)",
+                  file=sys.stderr, flush=True)
+        del X16, Y16
+
     # stored-block mode: the block rows computed once (gca_store_blocks), then
     # products that read them; reported beside the recomputing product
     stored = {}
@@ -431,7 +476,15 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": PUBLISHED_F32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PUBLISHED_F32_TFLOPS, "traffic": measured_traffic(kname),
                 "issue_ceiling": ISSUE_CEILING_F32_TFLOPS, "issue_ceiling_frac": achieved / ISSUE_CEILING_F32_TFLOPS,
-                "kernel": kname, "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom]}
+                "kernel": kname, "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom],
+                "timing": "HIP events around the kernel on its stream in the timed products, where the "
+                          "transform chain and the touching lists run beside it on the handle's side streams"}
+    if serial is not None:
+        a_ser = work[dom] / (serial["phases_ms"][dom] * 1e-3) / 1e12
+        roofline["alone"] = {"avg_ms": serial["phases_ms"][dom], "achieved": a_ser,
+                             "frac": a_ser / PUBLISHED_F32_TFLOPS,
+                             "issue_ceiling_frac": a_ser / ISSUE_CEILING_F32_TFLOPS,
+                             "timing": "the same kernel in the serial-phase products (gca_params.serial = 1)"}
 
     # CPU oracle on a bounded sample of rows (also the accuracy check): the
     # first rows of one seeded permutation, err_rows of them unless fewer fit
@@ -511,6 +564,10 @@ def main():
                                          "basis_bytes_fp64")},
         "roofline": roofline,
         "phases_roofline": phase_rooflines(st, params, P, Pc, mean_mixed),
+        "serial_phases": serial,
+        "multi_rhs16": rhs16,
+        "phases_roofline_alone": (phase_rooflines(st, params, P, Pc, serial["phases_ms"])
+                                  if serial is not None else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
