@@ -86,6 +86,13 @@ def lin_evals_per_s(P):
     return FP64_LANE_OPS_PER_S / (13.0 + 4.0 + 27.0 / P)
 
 
+# FP64 ceiling of one collocation evaluation (a rule point of a column
+# triangle against a collocation point): 6 FMAs for the point, 3 subtractions,
+# 3 operations for |x - y|^2, 4 for the refined rsqrt plus the quarter-rate
+# v_rsq_f64 (4 issue slots), 1 FMA for the weighted sum: 17 + 4 slots.
+COLL_EVALS_PER_S = FP64_LANE_OPS_PER_S / 21.0
+
+
 def phase_rooflines(st, params, P, Pc, ms, ss_fp32=False):
     """Fraction of its bound for every phase of the mixed product (per
     product): the quadrature phases against the FP32 ALU ceiling (10 flops
@@ -233,8 +240,22 @@ def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    def coll():
+        gca._check(L.gca_coll_blocks(vp(xyz), vp(tri), vp(set_vtx), vp(m_tri), vp(m_loc), vp(m_cnt), cap,
+                                     vp(set_off), vp(br), vp(bc), nblk, ld, q, int(sym), 8, vp(out), vp(status),
+                                     sp))
+
     merge_ms = timed(merge)
     blocks_ms = timed(blocks)
+    coll_ms = timed(coll)
+    cst = status.cpu().numpy()
+    if (cst != 0).any():
+        raise RuntimeError("collocation workload exceeded a kernel limit")
+    # collocation evaluations: per row point, P per (triangle, local corner) of the column list
+    # (the subsets of a block are at least 0.1 apart: no Duffy case)
+    loc = m_loc.cpu().numpy()
+    corners = np.array([(loc[k, :max(int(c), 0)] >= 0).sum() for k, c in
+                        enumerate(m_cnt.cpu().numpy())], dtype=np.int64)
     cnt = m_cnt.cpu().numpy().astype(np.int64)
     st = status.cpu().numpy()
     if (cnt < 0).any() or (st != 0).any():
@@ -253,9 +274,20 @@ def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
            "roofline": {"bound": "fp64 alu", "achieved": ach, "peak": peak, "unit": "evaluations/s",
                         "frac": ach / peak, "kernel": f"k_lin_blocks<{P}>"},
            "steps": steps}
+    cev = int(32 * corners[1::2].sum()) * P
+    cach = cev / (coll_ms * 1e-3)
+    res["collocation"] = {
+        "what": "the collocation matrix of the same basis (Section 6): rows the 32 vertices of each block's row "
+                "subset as collocation points, columns the nodal functions of its column subset, single integrals "
+                "by the same regular rule (Duffy rule with 8 points where a point is a corner, absent here)",
+        "blocks_ms": coll_ms, "entries_per_s": nblk * ld / (coll_ms * 1e-3), "kernel_evaluations": cev,
+        "galerkin_over_collocation_time": blocks_ms / coll_ms,
+        "roofline": {"bound": "fp64 alu", "achieved": cach, "peak": COLL_EVALS_PER_S, "unit": "evaluations/s",
+                     "frac": cach / COLL_EVALS_PER_S, "kernel": "k_coll_blocks"}}
     print(f"[bench] linear basis: merge {merge_ms:.3f} ms ({ns} subsets), blocks {blocks_ms:.3f} ms "
-          f"({nblk} blocks, {ach:.3e} evals/s = {100 * ach / peak:.1f}% of FP64 ceiling)",
-          file=sys.stderr, flush=True)
+          f"({nblk} blocks, {ach:.3e} evals/s = {100 * ach / peak:.1f}% of FP64 ceiling); collocation blocks "
+          f"{coll_ms:.3f} ms ({cach:.3e} evals/s = {100 * cach / COLL_EVALS_PER_S:.1f}%, "
+          f"Galerkin / collocation time {blocks_ms / coll_ms:.1f})", file=sys.stderr, flush=True)
     return res
 
 

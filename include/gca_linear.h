@@ -96,6 +96,30 @@ gca_status gca_lin_blocks(const double *xyz, const int32_t *tri, const int32_t *
                           int32_t nblk, int64_t ld, int32_t q, int32_t sym, double *out,
                           int32_t *status, void *stream);
 
+/* Dense FP64 blocks of the collocation matrix of the linear nodal basis
+ * (Section 6: g_ij = int g(x_i, y) phi_j(y) dy with x_i a mesh vertex, a single
+ * integral), one workgroup per block.  Rows: the vertices of row subset
+ * blk_row[b] (set_vtx[set_off[r] ..], the collocation points; no merge
+ * needed); columns: the nodal functions of the vertices of column subset
+ * blk_col[b], integrated over that subset's merged triangle list
+ * (gca_lin_merge).  A triangle with the collocation point as a corner takes the
+ * Duffy transformation at that corner with q_s Gauss points (1 .. 32; the
+ * radial variable is integrated exactly); the others the regular rule of order
+ * q (collapsed Gauss q = 1..4, or sym = 1: the symmetric rules q = 2, 3).
+ * Arguments as in gca_lin_blocks; set_vtx: device int32, the subsets' vertex
+ * ids given to gca_lin_merge.  out: block b row-major at out[b ld + i m + j]
+ * (ld >= n m of every block).  status: 0 ok; 2 a subset exceeds
+ * GCA_LIN_MAX_BLOCK_SET vertices, the column list exceeds GCA_LIN_MAX_TRIS
+ * triangles or its merge count is -1, or a column vertex lies in more than
+ * GCA_LIN_MAX_DEGREE of them (block written as zeros).
+ * Errors: GCA_EINVAL (NULL pointers, nblk < 0, ld < 0, unsupported q / sym /
+ * q_s), GCA_EHIP. */
+gca_status gca_coll_blocks(const double *xyz, const int32_t *tri, const int32_t *set_vtx,
+                           const int32_t *m_tri, const int32_t *m_loc, const int32_t *m_count, int32_t cap,
+                           const int32_t *set_off, const int32_t *blk_row, const int32_t *blk_col,
+                           int32_t nblk, int64_t ld, int32_t q, int32_t sym, int32_t q_s, double *out,
+                           int32_t *status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

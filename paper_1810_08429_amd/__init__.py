@@ -41,7 +41,7 @@ EXPORTED = [
     "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
     "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
     "gca_block_entries",
-    "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
+    "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks", "gca_coll_blocks",
 ]
 
 
@@ -135,6 +135,7 @@ def lib():
     L.gca_lin_vertex_triangles.argtypes = [P, I64, I64, P, P]
     L.gca_lin_merge.argtypes = [P, P, P, P, P, I32, I32, P, P, P, P]
     L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, P, P, P]
+    L.gca_coll_blocks.argtypes = [P, P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
     L.gca_last_error.argtypes = []
@@ -143,7 +144,8 @@ def lib():
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
                  "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
-                 "gca_block_entries", "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks"):
+                 "gca_block_entries", "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
+                 "gca_coll_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -570,4 +572,22 @@ def lin_blocks(xyz, tri, merged, set_off, blk_row, blk_col, ld, q, sym=False, st
     _check(lib().gca_lin_blocks(_vp(xyz), _vp(tri), _vp(m_tri), _vp(m_loc), _vp(m_count), cap, _vp(set_off),
                                 _vp(blk_row), _vp(blk_col), nblk, int(ld), int(q), int(bool(sym)),
                                 _vp(out), _vp(status), _stream_ptr(stream)))
+    return out[:nblk], status[:nblk]
+
+
+def coll_blocks(xyz, tri, set_vtx, merged, set_off, blk_row, blk_col, ld, q, sym=False, q_s=8, stream=None):
+    """Dense FP64 collocation blocks of the linear nodal basis (gca_coll_blocks):
+    rows the vertices of the row subsets (collocation points), columns the
+    nodal functions of the column subsets over their merged lists `merged`
+    = (tri, loc, count) of lin_merge.  Returns (out[nblk, ld], status[nblk])
+    as CUDA tensors."""
+    import torch
+    m_tri, m_loc, m_count = merged
+    cap = int(m_tri.shape[1])
+    nblk = int(blk_row.numel())
+    out = torch.empty((max(nblk, 1), ld), dtype=torch.float64, device=xyz.device)
+    status = torch.empty(max(nblk, 1), dtype=torch.int32, device=xyz.device)
+    _check(lib().gca_coll_blocks(_vp(xyz), _vp(tri), _vp(set_vtx), _vp(m_tri), _vp(m_loc), _vp(m_count), cap,
+                                 _vp(set_off), _vp(blk_row), _vp(blk_col), nblk, int(ld), int(q), int(bool(sym)),
+                                 int(q_s), _vp(out), _vp(status), _stream_ptr(stream)))
     return out[:nblk], status[:nblk]
