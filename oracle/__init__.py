@@ -82,6 +82,9 @@ def _load():
     lib.orc_num_threads.argtypes = []
     lib.orc_ss_moment.restype = D
     lib.orc_ss_moment.argtypes = [I32, I32, I32, I32, I32, I32]
+    lib.orc_entry_dl.restype = D
+    lib.orc_entry_dl.argtypes = [P, I64, I64]
+    lib.orc_entries_dl.argtypes = [P, I64, P, P, P]
     _lib = lib
     return lib
 
@@ -165,6 +168,23 @@ class Entries:
         out = np.zeros(I.size)
         self.lib.orc_entries(self.h, I.size, _ptr(I), _ptr(J), _ptr(out))
         return out
+
+    def dl_entries(self, i, j):
+        """Double-layer entries k_ij = int_{t_i} int_{t_j} n_j . (x - y) /
+        (4 pi |x - y|^3) dy dx (n_j the unit normal of t_j), same rules per
+        class as the single-layer entries; identical pairs are 0."""
+        I = np.ascontiguousarray(np.atleast_1d(i), dtype=np.int64)
+        J = np.ascontiguousarray(np.atleast_1d(j), dtype=np.int64)
+        I, J = np.broadcast_arrays(I, J)
+        I, J = np.ascontiguousarray(I).ravel(), np.ascontiguousarray(J).ravel()
+        out = np.zeros(I.size)
+        self.lib.orc_entries_dl(self.h, I.size, _ptr(I), _ptr(J), _ptr(out))
+        return out
+
+    def dl_block(self, rows, cols):
+        rows = np.asarray(rows, dtype=np.int64)
+        cols = np.asarray(cols, dtype=np.int64)
+        return self.dl_entries(np.repeat(rows, cols.size), np.tile(cols, rows.size)).reshape(rows.size, cols.size)
 
     def block(self, rows, cols):
         rows = np.asarray(rows, dtype=np.int64)

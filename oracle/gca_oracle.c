@@ -674,3 +674,94 @@ void orc_energy_grad_vertices(void *p, const double *u, int64_t nsel, const int3
         for (int d = 0; d < 3; ++d) out[3 * s + d] = acc[d];
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Double-layer kernel (Section 1: the second-kind formulation uses the normal
+ * derivative of g at y; Section 6: unit normals of the triangles):
+ *     k_ij = int_{t_i} int_{t_j} dg/dn_y(x, y) dy dx,
+ *     dg/dn_y(x, y) = n_j . (x - y) / (4 pi |x - y|^3),
+ * n_j the unit normal of t_j from its mesh orientation (v1 - v0) x (v2 - v0).
+ * Not symmetric: x runs over t_i, y over t_j.  Identical pairs are 0 (the
+ * two points lie in one plane, n_j . (x - y) = 0); touching pairs use the
+ * same Sauter-Schwab maps as above (the kernel is O(1/r^2) near the common
+ * edge or vertex, which the Jacobian's xi^3 cancels), the others the regular
+ * rules of the single-layer entries. */
+
+static void unit_normal(const orc_ctx *c, int64_t t, double *n)
+{
+    double P[3][3];
+    for (int k = 0; k < 3; ++k) vload(c, c->tri[3 * t + k], P[k]);
+    double a[3], b[3];
+    for (int d = 0; d < 3; ++d) { a[d] = P[1][d] - P[0][d]; b[d] = P[2][d] - P[0][d]; }
+    n[0] = a[1] * b[2] - a[2] * b[1];
+    n[1] = a[2] * b[0] - a[0] * b[2];
+    n[2] = a[0] * b[1] - a[1] * b[0];
+    double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int d = 0; d < 3; ++d) n[d] /= l;
+}
+
+static double entry_regular_dl(const double P[3][3], const double Q[3][3], const double *n, const orc_trirule *r)
+{
+    double Jp = surf_elem(P), Jq = surf_elem(Q);
+    double sum = 0.0;
+    for (int a = 0; a < r->np; ++a) {
+        double x[3];
+        chi_rel(P, r->s1[a], r->s2[a], x);
+        for (int d = 0; d < 3; ++d) x[d] += P[0][d];
+        for (int b = 0; b < r->np; ++b) {
+            double y[3];
+            chi_rel(Q, r->s1[b], r->s2[b], y);
+            for (int d = 0; d < 3; ++d) y[d] += Q[0][d];
+            double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            sum += r->w[a] * r->w[b] * (n[0] * dx + n[1] * dy + n[2] * dz) / (r2 * sqrt(r2));
+        }
+    }
+    return sum * Jp * Jq / (4.0 * ORC_PI);
+}
+
+static double entry_touching_dl(int kase, const double P[3][3], const double Q[3][3], const double *n,
+                                int q, const double *gx, const double *gw)
+{
+    double Jp = surf_elem(P), Jq = surf_elem(Q);
+    int nreg = ss_regions(kase);
+    double sum = 0.0;
+    for (int r = 0; r < nreg; ++r)
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+                for (int e = 0; e < q; ++e)
+                    for (int f = 0; f < q; ++f) {
+                        double x1, x2, y1, y2;
+                        double jac = ss_map(kase, r, gx[a], gx[b], gx[e], gx[f], &x1, &x2, &y1, &y2);
+                        double w = gw[a] * gw[b] * gw[e] * gw[f] * jac;
+                        double X[3], Y[3];
+                        chi_rel(P, x1, x2, X);
+                        chi_rel(Q, y1, y2, Y);
+                        double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        sum += w * (n[0] * dx + n[1] * dy + n[2] * dz) / (r2 * sqrt(r2));
+                    }
+    return sum * Jp * Jq / (4.0 * ORC_PI);
+}
+
+double orc_entry_dl(void *p, int64_t i, int64_t j)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    int kase = orc_classify(p, i < j ? i : j, i < j ? j : i);
+    if (kase == ORC_IDENT) return 0.0;
+    double n[3];
+    unit_normal(c, j, n);
+    double P[3][3], Q[3][3];
+    if (kase == ORC_EDGE || kase == ORC_VERT) {
+        touching_vertices(c, kase, i, j, P, Q, NULL, NULL);
+        return entry_touching_dl(kase, P, Q, n, c->q_s, c->gs_x, c->gs_w);
+    }
+    for (int k = 0; k < 3; ++k) { vload(c, c->tri[3 * i + k], P[k]); vload(c, c->tri[3 * j + k], Q[k]); }
+    return entry_regular_dl(P, Q, n, kase == ORC_NEAR ? &c->rn : &c->rr);
+}
+
+void orc_entries_dl(void *p, int64_t m, const int64_t *I, const int64_t *J, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < m; ++k) out[k] = orc_entry_dl(p, I[k], J[k]);
+}
