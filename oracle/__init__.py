@@ -85,6 +85,7 @@ def _load():
     lib.orc_entry_dl.restype = D
     lib.orc_entry_dl.argtypes = [P, I64, I64]
     lib.orc_entries_dl.argtypes = [P, I64, P, P, P]
+    lib.orc_lin_touch_moments.argtypes = [P, I64, I64, P]
     _lib = lib
     return lib
 
@@ -185,6 +186,14 @@ class Entries:
         rows = np.asarray(rows, dtype=np.int64)
         cols = np.asarray(cols, dtype=np.int64)
         return self.dl_entries(np.repeat(rows, cols.size), np.tile(cols, rows.size)).reshape(rows.size, cols.size)
+
+    def lin_touch_moments(self, t, s):
+        """The nine corner moments int_t int_s lambda_a g lambda_b (a, b in
+        the mesh corner order of t and s) of a touching pair by the
+        Sauter-Schwab maps of order q_s (Section 5's linear nodal basis)."""
+        M = np.zeros(9)
+        self.lib.orc_lin_touch_moments(self.h, int(t), int(s), _ptr(M))
+        return M.reshape(3, 3)
 
     def block(self, rows, cols):
         rows = np.asarray(rows, dtype=np.int64)

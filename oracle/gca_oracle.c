@@ -765,3 +765,53 @@ void orc_entries_dl(void *p, int64_t m, const int64_t *I, const int64_t *J, doub
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < m; ++k) out[k] = orc_entry_dl(p, I[k], J[k]);
 }
+
+/* ------------------------------------------------------------------------
+ * Continuous piecewise-linear nodal basis (Section 5): the nine corner moments
+ * of a touching triangle pair (t, s),
+ *     M[a][b] = int_t int_s lambda_a(x) g(x, y) lambda_b(y) dy dx,
+ * a, b the corners of t and s in mesh order, by the same Sauter-Schwab maps
+ * and q_s-point Gauss rules as the piecewise-constant entries, with the
+ * barycentric weights (1 - s1, s1 - s2, s2) of the maps' reference points
+ * (in the vertex order of the rule) moved back to mesh order.  Sets NaN for a
+ * pair that does not touch. */
+void orc_lin_touch_moments(void *p, int64_t t, int64_t s, double *M)
+{
+    const orc_ctx *c = (const orc_ctx *)p;
+    int kase = orc_classify(p, t < s ? t : s, t < s ? s : t);
+    for (int k = 0; k < 9; ++k) M[k] = 0.0;
+    if (kase != ORC_IDENT && kase != ORC_EDGE && kase != ORC_VERT) {
+        for (int k = 0; k < 9; ++k) M[k] = NAN;
+        return;
+    }
+    double P[3][3], Q[3][3];
+    int32_t pid[3], qid[3];
+    touching_vertices(c, kase, t, s, P, Q, pid, qid);
+    int ca[3], cb[3];
+    for (int k = 0; k < 3; ++k)
+        for (int m = 0; m < 3; ++m) {
+            if (c->tri[3 * t + m] == pid[k]) ca[k] = m;
+            if (c->tri[3 * s + m] == qid[k]) cb[k] = m;
+        }
+    double Jp = surf_elem(P), Jq = surf_elem(Q);
+    int q = c->q_s;
+    for (int r = 0; r < ss_regions(kase); ++r)
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+                for (int e = 0; e < q; ++e)
+                    for (int f = 0; f < q; ++f) {
+                        double x1, x2, y1, y2;
+                        double jac = ss_map(kase, r, c->gs_x[a], c->gs_x[b], c->gs_x[e], c->gs_x[f],
+                                            &x1, &x2, &y1, &y2);
+                        double w = c->gs_w[a] * c->gs_w[b] * c->gs_w[e] * c->gs_w[f] * jac;
+                        double X[3], Y[3];
+                        chi_rel(P, x1, x2, X);
+                        chi_rel(Q, y1, y2, Y);
+                        double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
+                        double g = w / sqrt(dx * dx + dy * dy + dz * dz);
+                        double lp[3] = {1.0 - x1, x1 - x2, x2}, lq[3] = {1.0 - y1, y1 - y2, y2};
+                        for (int k = 0; k < 3; ++k)
+                            for (int m = 0; m < 3; ++m) M[3 * ca[k] + cb[m]] += g * lp[k] * lq[m];
+                    }
+    for (int k = 0; k < 9; ++k) M[k] *= Jp * Jq / (4.0 * ORC_PI);
+}

@@ -16,9 +16,9 @@ never does, and nothing here is shared with it.
 * ``lin_block``: Galerkin entries of the linear nodal basis by their plain
   definition (Section 5): for rows i and columns j, the sum over t in T_i and
   s in T_j of the integral over t of phi_i times the integral over s of
-  g(x, y) phi_j(y), with the regular rule of Section 1 on both triangles.  Only
-  pairs of triangles without a common vertex are defined here; a pair that
-  shares one raises.
+  g(x, y) phi_j(y), with the regular rule of Section 1 on both triangles, and
+  for a pair with a common vertex the Sauter-Schwab rules with the nodal
+  weights (the C oracle's ``orc_lin_touch_moments``).
 """
 from __future__ import annotations
 
@@ -98,15 +98,26 @@ def basis_weights(P, q, sym=False):
     return x, (w * J)[:, None] * lam
 
 
-def lin_block(verts, tris, rows, cols, q, sym=False, T=None):
+def lin_block(verts, tris, rows, cols, q, sym=False, T=None, q_s=None):
     """Dense block (len(rows) x len(cols)) of the linear-basis Galerkin matrix
-    by the plain definition; raises ValueError for a triangle pair with a
-    common vertex."""
+    by the plain definition.  A triangle pair with a common vertex (identical,
+    common edge, common vertex) takes the Sauter-Schwab rules of order q_s with
+    the nodal weights (``Entries.lin_touch_moments``); without q_s such a pair
+    raises ValueError."""
     verts = np.asarray(verts, dtype=np.float64)
     tris = np.asarray(tris)
     if T is None:
         T = vertex_triangles(tris, verts.shape[0])
     cache = {}
+    ss = {}
+
+    def touch(t, s):
+        if "e" not in ss:
+            from . import Entries
+            ss["e"] = Entries(verts, tris, q, q, q_s, sym=sym)
+        if (t, s) not in ss:
+            ss[(t, s)] = ss["e"].lin_touch_moments(t, s)
+        return ss[(t, s)]
 
     def bw(t):
         if t not in cache:
@@ -121,9 +132,12 @@ def lin_block(verts, tris, rows, cols, q, sym=False, T=None):
                 a = list(tris[t]).index(int(i))
                 x, Wt = bw(t)
                 for s in T[int(j)]:
-                    if set(map(int, tris[t])) & set(map(int, tris[s])):
-                        raise ValueError("triangles %d and %d share a vertex" % (t, s))
                     b = list(tris[s]).index(int(j))
+                    if set(map(int, tris[t])) & set(map(int, tris[s])):
+                        if q_s is None:
+                            raise ValueError("triangles %d and %d share a vertex" % (t, s))
+                        acc += 4.0 * math.pi * touch(int(t), int(s))[a, b]
+                        continue
                     y, Ws = bw(s)
                     d = x[:, None, :] - y[None, :, :]
                     g = 1.0 / np.sqrt((d * d).sum(axis=2))

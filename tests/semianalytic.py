@@ -84,16 +84,20 @@ def _graded_both(**kw):
     return np.concatenate([0.5 * x, 1.0 - 0.5 * x]), np.concatenate([0.5 * w, 0.5 * w])
 
 
-def pair_integral(T, S):
+def pair_integral(T, S, corner=None):
     """int_T int_S 1/|x-y|; T = (P0, P1, P2) parametrised as P0 + s1 (P1-P0) +
     s2 (P2-P1), 0 <= s2 <= s1 <= 1, collapsed s2 = s1 v; graded towards s1 in
-    {0, 1} and v in {0, 1} (the vertices and edges of T)."""
+    {0, 1} and v in {0, 1} (the vertices and edges of T).  corner = k weights
+    the outer integral with the barycentric coordinate of T's corner k,
+    (1 - s1, s1 - s2, s2)[k]."""
     T = np.asarray(T, dtype=np.float64)
     u, wu = _graded_both()
     v, wv = _graded_both()
     J = np.linalg.norm(np.cross(T[1] - T[0], T[2] - T[1]))
     U, Vv = np.meshgrid(u, v, indexing="ij")
     W = np.outer(wu, wv) * U
+    if corner is not None:
+        W = W * (1.0 - U, U - U * Vv, U * Vv)[corner]
     p = (T[0][None, None, :] + U[..., None] * (T[1] - T[0])[None, None, :]
          + (U * Vv)[..., None] * (T[2] - T[1])[None, None, :])
     pot = triangle_potential(S, p.reshape(-1, 3)).reshape(U.shape)

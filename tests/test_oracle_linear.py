@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from oracle import linear as L
+import synth
 from synth import icosphere
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "merge_example.json")
@@ -142,3 +143,66 @@ def test_symmetry_and_shared_vertex():
     assert (G > 0).all()
     with pytest.raises(ValueError):
         L.lin_block(m.verts, m.tris, a[:2], a[2:4], 3, T=T)
+
+
+def _touching_partners(orc, ent, t, nt):
+    out = {}
+    for s in range(nt):
+        k = int(ent.classify(t, s)[0])
+        if k in (orc.IDENT, orc.EDGE, orc.VERT):
+            out.setdefault(k, s)
+    return out
+
+
+def test_touching_moments_rows_against_semianalytic(orc):
+    """Sauter-Schwab with the nodal weights (Section 5's basis on touching
+    pairs): the row sums sum_b M_ab = int_t lambda_a(x) int_s g(x, y) dy dx
+    against the analytic inner potential and a graded outer rule weighted by
+    lambda_a (tests/semianalytic.py), for the identical, common-edge and
+    common-vertex case (1e-11); the column sums by the transposition
+    M(s, t) = M(t, s)^T of the same integral with the roles swapped."""
+    import math
+    from tests import semianalytic as SA
+    m = synth.jitter(synth.icosphere(2), 0.01, seed=2)
+    ent = orc.Entries(m.verts, m.tris, 3, 3, 12)
+    for t in (5, 77):
+        parts = _touching_partners(orc, ent, t, m.nt)
+        assert set(parts) == {orc.IDENT, orc.EDGE, orc.VERT}
+        for k, s in parts.items():
+            M = ent.lin_touch_moments(t, s)
+            T, S = m.verts[m.tris[t]], m.verts[m.tris[s]]
+            for a in range(3):
+                ref = SA.pair_integral(T, S, corner=a) / (4 * math.pi)
+                assert abs(M[a].sum() - ref) < 1e-11 * ref, (t, s, k, a)
+            Mt = ent.lin_touch_moments(s, t)
+            assert np.abs(Mt - M.T).max() < 1e-9 * np.abs(M).max(), (t, s, k)
+            if k == orc.IDENT:
+                assert np.abs(M - M.T).max() < 1e-13 * np.abs(M).max()
+
+
+def test_touching_moments_partition_of_unity_and_nan_for_disjoint(orc):
+    m = synth.icosphere(2)
+    ent = orc.Entries(m.verts, m.tris, 3, 3, 5)
+    for k, s in _touching_partners(orc, ent, 0, m.nt).items():
+        M = ent.lin_touch_moments(0, s)
+        g = ent.entries(0, s)[0]
+        assert abs(M.sum() - g) < 1e-14 * g
+        assert np.all(M > 0)
+    far = next(s for s in range(m.nt) if ent.classify(0, s) == orc.REG)
+    assert np.isnan(ent.lin_touch_moments(0, far)).all()
+
+
+def test_lin_block_with_touching_pairs_partition_of_unity(orc):
+    """All vertices against all vertices of one icosahedron (every pair of
+    triangles touches or is near): the sum of the linear-basis block equals
+    the sum of the piecewise-constant oracle's whole matrix with the same
+    rules (the nodal functions sum to one on every triangle)."""
+    m = synth.icosphere(0)
+    T = L.vertex_triangles(m.tris, m.nv)
+    B = L.lin_block(m.verts, m.tris, range(m.nv), range(m.nv), 3, False, T=T, q_s=6)
+    G = orc.Entries(m.verts, m.tris, 3, 3, 6).dense()
+    assert abs(B.sum() - G.sum()) < 1e-13 * G.sum()
+    # symmetric up to the Sauter-Schwab quadrature error (the common-edge maps treat x and y differently)
+    assert np.abs(B - B.T).max() < 1e-8 * np.abs(B).max()
+    with pytest.raises(ValueError):
+        L.lin_block(m.verts, m.tris, [0], [0], 3, False, T=T)
