@@ -178,6 +178,9 @@ def parse():
                          "caller's stream: per-kernel rooflines in isolation; 0 disables it)")
     ap.add_argument("--rhs16-steps", type=int, default=5,
                     help="timed batched products with 16 right-hand sides per precision (0 disables it)")
+    ap.add_argument("--dl-rows", type=int, default=32768,
+                    help="triangles whose touching pairs (and as many random pairs) time the double-layer entries "
+                         "(0 disables it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
@@ -288,6 +291,47 @@ def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
           f"({nblk} blocks, {ach:.3e} evals/s = {100 * ach / peak:.1f}% of FP64 ceiling); collocation blocks "
           f"{coll_ms:.3f} ms ({cach:.3e} evals/s = {100 * cach / COLL_EVALS_PER_S:.1f}%, "
           f"Galerkin / collocation time {blocks_ms / coll_ms:.1f})", file=sys.stderr, flush=True)
+    return res
+
+
+def double_layer(gca, torch, H, mesh, nrows, seed=11):
+    """Double-layer Galerkin entries (gca_dl_entries) on the workload mesh: the
+    touching pairs (common vertex or edge) of nrows random triangles, both
+    orders, and as many random (regular) pairs; wall time of each call, which
+    includes the host classification and the transfers."""
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(mesh.nt, nrows, replace=False)
+    flat = mesh.tris.reshape(-1)
+    order = np.argsort(flat, kind="stable")
+    start = np.searchsorted(flat[order], np.arange(mesh.nv + 1))
+    I, J = [], []
+    for c in range(3):
+        v = mesh.tris[rows, c]
+        cnt = start[v + 1] - start[v]
+        rr = np.repeat(rows, cnt)
+        idx = np.concatenate([order[start[a]:start[a + 1]] for a in v]) // 3
+        I.append(rr)
+        J.append(idx)
+    I, J = np.concatenate(I), np.concatenate(J)
+    pair = np.unique(np.stack([I, J], 1), axis=0)
+    pair = pair[pair[:, 0] != pair[:, 1]]
+    Ti = np.concatenate([pair[:, 0], pair[:, 1]])
+    Tj = np.concatenate([pair[:, 1], pair[:, 0]])
+    Ri = rng.integers(0, mesh.nt, Ti.size)
+    Rj = rng.integers(0, mesh.nt, Ti.size)
+    res = {"workload": f"touching pairs of {nrows} random triangles in both orders and as many random pairs "
+                       f"(seed {seed}); FP64; wall time of one gca_dl_entries call each (host classification, "
+                       f"job upload, kernel, read-back)"}
+    for name, (a, b) in (("touching", (Ti, Tj)), ("random", (Ri, Rj))):
+        H.dl_entries(a[:1000], b[:1000])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        H.dl_entries(a, b)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        res[name] = {"pairs": int(a.size), "s": dt, "entries_per_s": a.size / dt}
+    print(f"[bench] double layer: {res['touching']['pairs']} touching pairs in {res['touching']['s']:.3f} s, "
+          f"{res['random']['pairs']} random pairs in {res['random']['s']:.3f} s", file=sys.stderr, flush=True)
     return res
 
 
@@ -488,6 +532,8 @@ def main():
                   f"{stored[name]['block_rows_GBps']:.0f} GB/s", file=sys.stderr, flush=True)
         H.store_blocks(False, False)
 
+    dl = double_layer(gca, torch, H, mesh, a.dl_rows) if a.dl_rows > 0 else None
+
     linear = None
     if a.lin_blocks > 0:
         linear = linear_basis(gca, torch, mesh, a.lin_blocks, max(a.stored_steps, 3), 2)
@@ -587,6 +633,7 @@ def main():
         "energy_gradient": grad,
         "stored_blocks": stored,
         "linear_basis": linear,
+        "double_layer": dl,
         "mixed_over_fp64": dt_fp64 / dt_mixed,
         "rel_err_sampled_rows": rel,
         "phases_ms": {"mixed": mean_mixed, "fp64": mean_fp64},

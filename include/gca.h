@@ -357,6 +357,22 @@ gca_status h2_bilinear_grad(gca_h2 h, const double *a, const double *b, double a
 gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m,
                        double *out, int32_t precision, void *stream);
 
+/* Galerkin entries of the double-layer operator for m pairs (Section 1: the
+ * second-kind formulation uses the normal derivative of g at y; Section 6:
+ * unit normals of the triangles):
+ *     k_ij = int_{t_i} int_{t_j} n_j . (x - y) / (4 pi |x - y|^3) dy dx,
+ * n_j the unit normal of t_j from its mesh orientation (v1 - v0) x (v2 - v0).
+ * Not symmetric.  The pair's Sauter case decides the rule, as for g_ij:
+ * identical pairs are 0 (x - y lies in the plane of t_j); common edge and
+ * common vertex pairs use the Sauter-Schwab maps with q_s Gauss points in
+ * each of the four variables; the others the regular rules of order q_r /
+ * q_nr of the handle.  FP64.  I, J: device int32 original triangle ids; out:
+ * device FP64, m values.  Classifies the pairs on the host (copies I and J
+ * back and synchronises the stream); the device workspace of 188 bytes per
+ * pair is held by the handle and grown when a call needs more.
+ * Errors: GCA_EINVAL, GCA_ENOMEM, GCA_EHIP. */
+gca_status gca_dl_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, double *out, void *stream);
+
 /* Copies the nested basis to host arrays for inspection (any may be NULL):
  * ranks[nc]                   |tau~| per cluster (pre-order numbering);
  * pivots[sum ranks]           original triangle ids of tau~, clusters in

@@ -40,7 +40,7 @@ EXPORTED = [
     "gca_build", "h2_matvec", "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats",
     "gca_destroy", "gca_last_error", "gca_phase_times", "gca_solve_refined", "gca_update_geometry",
     "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
-    "gca_block_entries",
+    "gca_block_entries", "gca_dl_entries",
     "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks", "gca_coll_blocks",
 ]
 
@@ -123,6 +123,7 @@ def lib():
     L.gca_energy.argtypes = [P, P, P, P, P, I32, P]
     L.gca_energy_noalloc.argtypes = [P, P, P, P, P, I32, P]
     L.gca_block_entries.argtypes = [P, I32, I32, I64, P, P, P, P, P]
+    L.gca_dl_entries.argtypes = [P, P, P, I64, P, P]
     L.gca_entries.argtypes = [P, P, P, I64, P, I32, P]
     L.gca_basis_sizes.argtypes = [P, P, P]
     L.gca_basis_export.argtypes = [P, P, P, P]
@@ -144,7 +145,7 @@ def lib():
                  "h2_matvec",
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
                  "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
-                 "gca_block_entries", "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
+                 "gca_block_entries", "gca_dl_entries", "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
                  "gca_coll_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -359,6 +360,16 @@ class H2:
         store_blocks(False, False) releases the storage."""
         which = (1 << FP64 if fp64 else 0) | (1 << MIXED if mixed else 0)
         _check(lib().gca_store_blocks(self.h, which, _stream_ptr(stream)))
+
+    def dl_entries(self, I, J, stream=None):
+        """gca_dl_entries: double-layer entries k_ij for the pairs (I[k], J[k])
+        (original triangle ids), FP64, as a CUDA tensor."""
+        import torch
+        I = torch.as_tensor(np.ascontiguousarray(I), dtype=torch.int32).cuda()
+        J = torch.as_tensor(np.ascontiguousarray(J), dtype=torch.int32).cuda()
+        out = torch.empty(I.numel(), dtype=torch.float64, device="cuda")
+        _check(lib().gca_dl_entries(self.h, _vp(I), _vp(J), I.numel(), _vp(out), _stream_ptr(stream)))
+        return out
 
     def block_entries(self, precision=FP64, kind=0, stream=None):
         """gca_block_entries: (rows, cols, vals) of the stored coupling

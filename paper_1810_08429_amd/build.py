@@ -21,7 +21,8 @@ OUT = os.path.join(HERE, "libgca.so")
 BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["quad.hip", "basis.hip", "h2.hip", "solve.hip", "adjoint.hip", "grad.hip", "linear.hip",
-               "noalloc.hip", "multi.hip", "colloc.hip"]
+               "noalloc.hip", "multi.hip", "colloc.hip",
+               "dlayer.hip"]
 HOST_SOURCES = ["host.cpp", "capi.cpp"]
 
 
