@@ -229,7 +229,7 @@ def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
 
     def blocks():
         gca._check(L.gca_lin_blocks(vp(xyz), vp(tri), vp(m_tri), vp(m_loc), vp(m_cnt), cap, vp(set_off), vp(br),
-                                    vp(bc), nblk, ld, q, int(sym), vp(out), vp(status), sp))
+                                    vp(bc), nblk, ld, q, int(sym), 4, vp(out), vp(status), sp))
 
     def timed(fn):
         for _ in range(warmup):

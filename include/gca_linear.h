@@ -76,24 +76,28 @@ gca_status gca_lin_merge(const int32_t *vt_off, const int32_t *vt_list, const in
  * triangle-pair assembly (Section 5) over the merged lists of
  * gca_lin_merge, one workgroup per block, the regular rule of order q on both
  * triangles of every pair (collapsed Gauss, q = 1..4; or, sym = 1, the
- * symmetric rules of degree 2 q - 2, q = 2, 3).
+ * symmetric rules of degree 2 q - 2, q = 2, 3).  Pairs of triangles with a
+ * common vertex (identical, common edge, common vertex) take, when q_s > 0,
+ * the Sauter-Schwab rules with q_s Gauss points per variable and the nodal
+ * weights (Sections 6 and 8's touching cases, Section 5's basis).
  * xyz: device FP64, nv x 3 vertex coordinates; tri: device int32, nt x 3.
  * m_tri, m_loc, m_count, cap: the outputs of gca_lin_merge and its cap;
  * set_off: device int32, the subsets given to gca_lin_merge (sizes n, m).
  * blk_row, blk_col: device int32, nblk subset ids: block b is rows subset
  *       blk_row[b] x columns subset blk_col[b].
+ * q_s: 0 .. 32; 0 leaves touching pairs out (see status 1).
  * out: device FP64, nblk x ld: block b row-major at out[b ld + i m + j]
  *       (ld >= n m of every block; the rest of the stride is not written).
- * status: device int32, nblk: 0 ok; 1 a triangle of the row list and one of
- *       the column list share a vertex (the regular rule does not apply; the
- *       block is written as zeros); 2 a limit above is exceeded or a merge
- *       count is -1 (block written as zeros where it fits, else not at all).
- * Errors: GCA_EINVAL (NULL pointers, nblk < 0, ld < 0, unsupported q / sym),
- * GCA_EHIP. */
+ * status: device int32, nblk: 0 ok; 1 (q_s = 0 only) a triangle of the row
+ *       list and one of the column list share a vertex (the block is written
+ *       as zeros); 2 a limit above is exceeded or a merge count is -1 (block
+ *       written as zeros where it fits, else not at all).
+ * Errors: GCA_EINVAL (NULL pointers, nblk < 0, ld < 0, unsupported q / sym /
+ * q_s), GCA_EHIP. */
 gca_status gca_lin_blocks(const double *xyz, const int32_t *tri, const int32_t *m_tri,
                           const int32_t *m_loc, const int32_t *m_count, int32_t cap,
                           const int32_t *set_off, const int32_t *blk_row, const int32_t *blk_col,
-                          int32_t nblk, int64_t ld, int32_t q, int32_t sym, double *out,
+                          int32_t nblk, int64_t ld, int32_t q, int32_t sym, int32_t q_s, double *out,
                           int32_t *status, void *stream);
 
 /* Dense FP64 blocks of the collocation matrix of the linear nodal basis

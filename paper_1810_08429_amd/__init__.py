@@ -135,7 +135,7 @@ def lib():
     L.gca_store_blocks.argtypes = [P, I32, P]
     L.gca_lin_vertex_triangles.argtypes = [P, I64, I64, P, P]
     L.gca_lin_merge.argtypes = [P, P, P, P, P, I32, I32, P, P, P, P]
-    L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, P, P, P]
+    L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
     L.gca_coll_blocks.argtypes = [P, P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
@@ -570,10 +570,11 @@ def lin_merge(vt_off, vt_list, tri, set_off, set_vtx, cap, stream=None):
     return out_tri[:nsets], out_loc[:nsets], out_count[:nsets]
 
 
-def lin_blocks(xyz, tri, merged, set_off, blk_row, blk_col, ld, q, sym=False, stream=None):
+def lin_blocks(xyz, tri, merged, set_off, blk_row, blk_col, ld, q, sym=False, q_s=0, stream=None):
     """Dense FP64 linear-basis blocks (gca_lin_blocks) over the merged lists
-    `merged` = (tri, loc, count) of lin_merge.  Returns (out[nblk, ld],
-    status[nblk]) as CUDA tensors."""
+    `merged` = (tri, loc, count) of lin_merge; q_s > 0 integrates touching
+    pairs by the Sauter-Schwab rules.  Returns (out[nblk, ld], status[nblk])
+    as CUDA tensors."""
     import torch
     m_tri, m_loc, m_count = merged
     cap = int(m_tri.shape[1])
@@ -581,7 +582,7 @@ def lin_blocks(xyz, tri, merged, set_off, blk_row, blk_col, ld, q, sym=False, st
     out = torch.empty((max(nblk, 1), ld), dtype=torch.float64, device=xyz.device)
     status = torch.empty(max(nblk, 1), dtype=torch.int32, device=xyz.device)
     _check(lib().gca_lin_blocks(_vp(xyz), _vp(tri), _vp(m_tri), _vp(m_loc), _vp(m_count), cap, _vp(set_off),
-                                _vp(blk_row), _vp(blk_col), nblk, int(ld), int(q), int(bool(sym)),
+                                _vp(blk_row), _vp(blk_col), nblk, int(ld), int(q), int(bool(sym)), int(q_s),
                                 _vp(out), _vp(status), _stream_ptr(stream)))
     return out[:nblk], status[:nblk]
 

@@ -31,6 +31,7 @@
 #include "devfn.h"
 #include "gca_internal.h"
 #include "gca_linear.h"
+#include "ssmap.h"
 
 namespace gca {
 namespace {
@@ -170,7 +171,111 @@ struct LinArgs {
     double *out;
     int32_t *status;
     LinRule R;
+    double gx[32], gw[32];   // Gauss-Legendre on [0, 1] of order qs (touching pairs)
+    int qs;                  // 0: blocks with a touching pair are reported (status 1)
 };
+
+// The nine corner moments M[3 a + b] (a, b corners of t and s in mesh order,
+// vertex ids V, W) of a touching pair, without the factor 1 / (4 pi), by one
+// wavefront: Sauter-Schwab maps (ssmap.h) with qs Gauss points per variable,
+// the rule's vertex order as for the piecewise-constant entries (identical:
+// mesh order; common edge: the shared vertices by ascending id, then the
+// third; common vertex: the shared one, then the cyclic mesh order), and the
+// barycentric weights of the maps' reference points moved back to mesh order.
+// Lane l takes the (region, xi, e1, e2) points l, l + 64, ... with the whole
+// e3 rule; the lanes' partial moments are summed in a fixed tree, so the
+// result does not depend on timing.  Every lane of the wavefront must call it;
+// every lane receives M.
+__device__ void lin_touch_moments(const LinArgs &A, const int *V, const int *W, double *M)
+{
+    // shared corners (a0, b0), (a1, b1); private arrays below are indexed by
+    // compile-time constants only
+    int nsh = 0, a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            if (V[a] == W[b]) {
+                if (nsh == 0) { a0 = a; b0 = b; }
+                else { a1 = a; b1 = b; }
+                ++nsh;
+            }
+    int kase, pa0, pa1, pb0, pb1;   // mesh corners of rule vertices 0 and 1
+    if (nsh == 3) {
+        kase = SS_IDENT;
+        pa0 = pb0 = 0;
+        pa1 = pb1 = 1;
+    } else if (nsh == 2) {
+        kase = SS_EDGE;
+        const bool lo0 = V[a0] < V[a1];
+        pa0 = lo0 ? a0 : a1;
+        pa1 = lo0 ? a1 : a0;
+        pb0 = lo0 ? b0 : b1;
+        pb1 = lo0 ? b1 : b0;
+    } else {
+        kase = SS_VERT;
+        pa0 = a0;
+        pa1 = a0 == 2 ? 0 : a0 + 1;
+        pb0 = b0;
+        pb1 = b0 == 2 ? 0 : b0 + 1;
+    }
+    const int pa2 = 3 - pa0 - pa1, pb2 = 3 - pb0 - pb1;
+    double P[9], Q[9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        P[d] = A.xyz[3 * V[pa0] + d];
+        P[3 + d] = A.xyz[3 * V[pa1] + d];
+        P[6 + d] = A.xyz[3 * V[pa2] + d];
+        Q[d] = A.xyz[3 * W[pb0] + d];
+        Q[3 + d] = A.xyz[3 * W[pb1] + d];
+        Q[6 + d] = A.xyz[3 * W[pb2] + d];
+    }
+    // rule vertex of mesh corner c
+    int ia[3], ib[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ia[c] = pa0 == c ? 0 : (pa1 == c ? 1 : 2);
+        ib[c] = pb0 == c ? 0 : (pb1 == c ? 1 : 2);
+    }
+    const double u1[3] = {P[3] - P[0], P[4] - P[1], P[5] - P[2]}, u2[3] = {P[6] - P[3], P[7] - P[4], P[8] - P[5]};
+    const double v1[3] = {Q[3] - Q[0], Q[4] - Q[1], Q[5] - Q[2]}, v2[3] = {Q[6] - Q[3], Q[7] - Q[4], Q[8] - Q[5]};
+    double m[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e] = 0.0;
+    const int q = A.qs, q3 = q * q * q;
+    const int lane = threadIdx.x & 63;
+    for (int o = lane; o < ss_nregions(kase) * q3; o += 64) {
+        const int r = o / q3, w = o - r * q3;
+        const int i = w / (q * q), j = (w / q) % q, k = w % q;
+        for (int l = 0; l < q; ++l) {
+            double x1, x2, y1, y2;
+            const double jac = ss_map_full(kase, r, A.gx[i], A.gx[j], A.gx[k], A.gx[l], x1, x2, y1, y2);
+            const double d0 = (x1 * u1[0] + x2 * u2[0]) - (y1 * v1[0] + y2 * v2[0]);
+            const double d1 = (x1 * u1[1] + x2 * u2[1]) - (y1 * v1[1] + y2 * v2[1]);
+            const double d2 = (x1 * u1[2] + x2 * u2[2]) - (y1 * v1[2] + y2 * v2[2]);
+            const double g = A.gw[i] * A.gw[j] * A.gw[k] * A.gw[l] * jac * rsq<double>(d0 * d0 + d1 * d1 + d2 * d2);
+            // barycentric weights of the rule's vertices, then in mesh order
+            const double lp0 = 1.0 - x1, lp1 = x1 - x2, lq0 = 1.0 - y1, lq1 = y1 - y2;
+            double lp[3], lq[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lp[c] = ia[c] == 0 ? lp0 : (ia[c] == 1 ? lp1 : x2);
+                lq[c] = ib[c] == 0 ? lq0 : (ib[c] == 1 ? lq1 : y2);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) m[3 * a + b] += g * lp[a] * lq[b];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        double v = group_sum<16>(m[e]);
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        M[e] = v;
+    }
+}
 
 // Vertex coordinates (9 FP64) and |J| = twice the area of triangle t.
 __device__ __forceinline__ double load_tri(const double *xyz, const int32_t *tri, int t, double *X, int *V)
@@ -267,8 +372,63 @@ __device__ __forceinline__ void point(const LinArgs &A, const double *X, int p, 
     }
 }
 
+// The nine corner moments of a pair without a common vertex by the regular
+// rule of P points on both triangles (staged points or vertices X, Y),
+// without the factor 1 / (4 pi).
+template <int P>
+__device__ __forceinline__ void regular_moments(const LinArgs &A, const double *X, const double *Y, double *M)
+{
+    double y[P][3];
+#pragma unroll
+    for (int q = 0; q < P; ++q) point<P>(A, Y, q, y[q]);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        double x[3];
+        point<P>(A, X, p, x);
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const double dx = x[0] - y[q][0], dy = x[1] - y[q][1], dz = x[2] - y[q][2];
+            // a pair with a common vertex may give inf / NaN here: such a
+            // pair is never stored into a block that is returned
+            const double g = rsq<double>(dx * dx + dy * dy + dz * dz);
+            u0 += g * A.R.wl[q][0];
+            u1 += g * A.R.wl[q][1];
+            u2 += g * A.R.wl[q][2];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            M[3 * a + 0] += A.R.wl[p][a] * u0;
+            M[3 * a + 1] += A.R.wl[p][a] * u1;
+            M[3 * a + 2] += A.R.wl[p][a] * u2;
+        }
+    }
+}
+
+// Moments M times f into the chunk's slots V[rho * kc + kappa - k0] of the
+// row corners rc and column corners cc (-1: not a subset vertex).
+__device__ __forceinline__ void store_moments(const double *M, double f, const int *rc, const int *cc, double *V,
+                                              int kc, int k0)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int rho = rc[a];
+        if (rho < 0) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int kap = cc[c];
+            if (kap >= 0) V[rho * kc + kap - k0] = M[3 * a + c] * f;
+        }
+    }
+}
+
 // EPT block entries per thread (n m <= EPT LB); two workgroups per CU.
-template <int P, int EPT>
+// TOUCH = false: every pair by the regular rule; a block with a pair with a
+// common vertex is written as zeros with status 1.  TOUCH = true (launched
+// after it, on the same stream): only the blocks with status 1, again, the
+// touching pairs queued in LDS round by round and integrated by the
+// Sauter-Schwab rules, one wavefront per pair.
+template <int P, int EPT, bool TOUCH>
 __global__ void __launch_bounds__(LB, 2) k_lin_blocks(LinArgs A)
 {
     __shared__ double px[2][TMAX][9];      // points (P <= 3) or vertices of every row / column triangle
@@ -282,8 +442,11 @@ __global__ void __launch_bounds__(LB, 2) k_lin_blocks(LinArgs A)
     __shared__ int sh[LB];
     __shared__ double V[MV];               // used moments of a chunk: V[rho * kc + kappa - k0]
     __shared__ int bad, touch;
+    __shared__ int qp[TOUCH ? LB : 1];     // queued touching pairs of a round: t << 16 | s
+    __shared__ int qn;
 
     const int b = blockIdx.x, tid = threadIdx.x;
+    if (TOUCH && A.status[b] != 1) return;
     const int rs = A.blk_row[b], cs = A.blk_col[b];
     const int n = A.set_off[rs + 1] - A.set_off[rs], m = A.set_off[cs + 1] - A.set_off[cs];
     const int nT = A.m_count[rs], nS = A.m_count[cs];
@@ -297,6 +460,7 @@ __global__ void __launch_bounds__(LB, 2) k_lin_blocks(LinArgs A)
     if (tid == 0) {
         bad = 0;
         touch = 0;
+        qn = 0;
     }
     const int32_t *rtri = A.m_tri + (int64_t)rs * A.cap, *ctri = A.m_tri + (int64_t)cs * A.cap;
     for (int x = tid; x < nT + nS; x += LB) {
@@ -327,60 +491,61 @@ __global__ void __launch_bounds__(LB, 2) k_lin_blocks(LinArgs A)
         }
         const int s1 = lo, sc = s1 - s0;
         const int k0 = cbase[s0], kc = cbase[s1] - k0;
-        // pair pi = sl * nT + t, advanced by LB without a division per pair
-        const int nt1 = max(nT, 1), dsl = LB / nt1, dt = LB - dsl * nt1;
-        int sl = tid / nt1, t = tid - sl * nt1;
-        for (int pi = tid; pi < sc * nT; pi += LB, t += dt, sl += dsl) {
-            if (t >= nT) {
-                t -= nT;
-                ++sl;
+        if constexpr (!TOUCH) {
+            // pair pi = sl * nT + t, advanced by LB without a division per pair
+            const int nt1 = max(nT, 1), dsl = LB / nt1, dt = LB - dsl * nt1;
+            int sl = tid / nt1, t = tid - sl * nt1;
+            for (int pi = tid; pi < sc * nT; pi += LB, t += dt, sl += dsl) {
+                if (t >= nT) {
+                    t -= nT;
+                    ++sl;
+                }
+                const int s = s0 + sl;
+                bool tch = false;
+#pragma unroll
+                for (int u = 0; u < 3; ++u)
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) tch |= tv[0][t][u] == tv[1][s][v];
+                if (tch) touch = 1;
+                double M[9];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) M[e] = 0.0;
+                regular_moments<P>(A, px[0][t], px[1][s], M);
+                store_moments(M, jac[0][t] * jac[1][s] * inv4pi, cmap[0][t], cmap[1][s], V, kc, k0);
             }
-            const int s = s0 + sl;
-            bool tch = false;
+        } else {
+            const int np = sc * nT, wave = tid >> 6;
+            for (int base = 0; base < np; base += LB) {
+                const int pi = base + tid;
+                if (pi < np) {
+                    const int sl = pi / nT, t = pi - sl * nT, s = s0 + sl;
+                    bool tch = false;
 #pragma unroll
-            for (int u = 0; u < 3; ++u)
+                    for (int u = 0; u < 3; ++u)
 #pragma unroll
-                for (int v = 0; v < 3; ++v) tch |= tv[0][t][u] == tv[1][s][v];
-            if (tch) touch = 1;
-            const double *X = px[0][t], *Y = px[1][s];
-            double y[P][3];
+                        for (int v = 0; v < 3; ++v) tch |= tv[0][t][u] == tv[1][s][v];
+                    if (tch) {
+                        qp[atomicAdd(&qn, 1)] = t << 16 | s;
+                    } else {
+                        double M[9];
 #pragma unroll
-            for (int q = 0; q < P; ++q) point<P>(A, Y, q, y[q]);
-            double M[9];
-#pragma unroll
-            for (int e = 0; e < 9; ++e) M[e] = 0.0;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                double x[3];
-                point<P>(A, X, p, x);
-                double u0 = 0.0, u1 = 0.0, u2 = 0.0;
-#pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    const double dx = x[0] - y[q][0], dy = x[1] - y[q][1], dz = x[2] - y[q][2];
-                    // a pair with a common vertex may give inf / NaN here: its
-                    // block is reported with status 1 and written as zeros
-                    const double g = rsq<double>(dx * dx + dy * dy + dz * dz);
-                    u0 += g * A.R.wl[q][0];
-                    u1 += g * A.R.wl[q][1];
-                    u2 += g * A.R.wl[q][2];
+                        for (int e = 0; e < 9; ++e) M[e] = 0.0;
+                        regular_moments<P>(A, px[0][t], px[1][s], M);
+                        store_moments(M, jac[0][t] * jac[1][s] * inv4pi, cmap[0][t], cmap[1][s], V, kc, k0);
+                    }
                 }
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    M[3 * a + 0] += A.R.wl[p][a] * u0;
-                    M[3 * a + 1] += A.R.wl[p][a] * u1;
-                    M[3 * a + 2] += A.R.wl[p][a] * u2;
+                __syncthreads();
+                const int nq = qn;
+                for (int e = wave; e < nq; e += LB / 64) {
+                    const int t = qp[e] >> 16, s = qp[e] & 0xFFFF;
+                    double M[9];
+                    lin_touch_moments(A, tv[0][t], tv[1][s], M);
+                    if ((tid & 63) == 0)
+                        store_moments(M, jac[0][t] * jac[1][s] * inv4pi, cmap[0][t], cmap[1][s], V, kc, k0);
                 }
-            }
-            const double f = jac[0][t] * jac[1][s] * inv4pi;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int rho = cmap[0][t][a];
-                if (rho < 0) continue;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int kap = cmap[1][s][c];
-                    if (kap >= 0) V[rho * kc + kap - k0] = M[3 * a + c] * f;
-                }
+                __syncthreads();
+                if (tid == 0) qn = 0;
+                __syncthreads();
             }
         }
         __syncthreads();
@@ -461,11 +626,12 @@ gca_status gca_lin_merge(const int32_t *vt_off, const int32_t *vt_list, const in
 
 gca_status gca_lin_blocks(const double *xyz, const int32_t *tri, const int32_t *m_tri, const int32_t *m_loc,
                           const int32_t *m_count, int32_t cap, const int32_t *set_off, const int32_t *blk_row,
-                          const int32_t *blk_col, int32_t nblk, int64_t ld, int32_t q, int32_t sym, double *out,
-                          int32_t *status, void *stream)
+                          const int32_t *blk_col, int32_t nblk, int64_t ld, int32_t q, int32_t sym, int32_t q_s,
+                          double *out, int32_t *status, void *stream)
 {
     clear_error();
     if (nblk < 0 || ld < 0) return set_error(GCA_EINVAL, "nblk and ld must be >= 0");
+    if (q_s < 0 || q_s > 32) return set_error(GCA_EINVAL, "q_s must be in [0, 32]");
     if (cap < 1 || cap > GCA_LIN_MAX_GATHER) return set_error(GCA_EINVAL, "cap out of range");
     if (sym != 0 && sym != 1) return set_error(GCA_EINVAL, "sym must be 0 or 1");
     TriRule r;
@@ -481,13 +647,16 @@ gca_status gca_lin_blocks(const double *xyz, const int32_t *tri, const int32_t *
         a.R.wl[p][1] = r.w[p] * (r.s1[p] - r.s2[p]);
         a.R.wl[p][2] = r.w[p] * r.s2[p];
     }
+    a.qs = q_s;
+    if (q_s > 0) gauss_legendre01(q_s, a.gx, a.gw);
     hipStream_t s = (hipStream_t)stream;
     // entries per thread from the caller's stride (ld >= n m of every block)
     const int ept = ld <= 2 * LB ? 2 : (ld <= 4 * LB ? 4 : 8);
     switch (r.np * 16 + ept) {
-#define CASE(PP, EE)                                                                    \
-    case PP * 16 + EE:                                                                  \
-        hipLaunchKernelGGL((k_lin_blocks<PP, EE>), dim3(nblk), dim3(LB), 0, s, a);      \
+#define CASE(PP, EE)                                                                          \
+    case PP * 16 + EE:                                                                        \
+        hipLaunchKernelGGL((k_lin_blocks<PP, EE, false>), dim3(nblk), dim3(LB), 0, s, a);     \
+        if (q_s > 0) hipLaunchKernelGGL((k_lin_blocks<PP, EE, true>), dim3(nblk), dim3(LB), 0, s, a); \
         break;
 #define CASES(PP) CASE(PP, 2) CASE(PP, 4) CASE(PP, 8)
         CASES(1) CASES(3) CASES(4) CASES(6) CASES(9) CASES(16)

@@ -207,3 +207,56 @@ def test_blocks_sphere_l8_sample(env):
     for b, (r, c) in enumerate(pairs):
         want = L.lin_block(m.verts, m.tris, sets[r], sets[c], 2, True, T=T)
         assert np.abs(out[b].reshape(32, 32) - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("q,sym,q_s", [(3, False, 5), (2, True, 4), (1, False, 3)])
+def test_touching_blocks_equal_oracle(env, q, sym, q_s):
+    # blocks whose row and column triangles share vertices (identical, common
+    # edge, common vertex): the Sauter-Schwab rules with the nodal weights
+    g, torch = env
+    m = synth.icosphere(2)
+    dm = _device_mesh(g, torch, m.verts, m.tris)
+    rng = np.random.default_rng(50 + q + 7 * sym)
+    T = _numpy_T(m.tris, m.nv)
+    c = int(rng.integers(m.nv))
+    far = int(np.argmax(((m.verts - m.verts[c]) ** 2).sum(1)))
+    sets = [_patch(m.verts, c, 24, 24, rng),          # contiguous patch
+            _patch(m.verts, c, 17, 60, rng),          # scattered over a wider neighbourhood
+            np.array([c]),
+            _patch(m.verts, far, 9, 9, rng)]          # far away: regular pairs only
+    pairs = [(0, 0), (0, 1), (1, 0), (2, 2), (2, 0), (1, 1), (0, 3)]
+    so, merged = _merge(g, torch, dm, sets, cap=192)
+    br = torch.tensor([p[0] for p in pairs], dtype=torch.int32).cuda()
+    bc = torch.tensor([p[1] for p in pairs], dtype=torch.int32).cuda()
+    out, st = g.lin_blocks(dm[0], dm[1], merged, so, br, bc, 64 * 64, q, sym, q_s=q_s)
+    out2, _ = g.lin_blocks(dm[0], dm[1], merged, so, br, bc, 64 * 64, q, sym, q_s=q_s)
+    out, out2, st = out.cpu().numpy(), out2.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all()
+    for k, (r, c_) in enumerate(pairs):
+        want = L.lin_block(m.verts, m.tris, sets[r], sets[c_], q, sym, T=T, q_s=q_s)
+        got = out[k, :want.size].reshape(want.shape)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), (k, q, sym, q_s)
+        # the stride beyond n m is not written; the block is the same bit for bit
+        assert np.array_equal(out[k, :want.size], out2[k, :want.size])
+
+
+def test_touching_full_matrix_level1(env):
+    # the whole linear-basis Galerkin matrix of the level-1 sphere as one block:
+    # equal to the oracle, symmetric up to the rules' asymmetry, positive definite
+    g, torch = env
+    m = synth.icosphere(1)
+    dm = _device_mesh(g, torch, m.verts, m.tris)
+    T = _numpy_T(m.tris, m.nv)
+    sets = [np.arange(m.nv)]
+    so, merged = _merge(g, torch, dm, sets, cap=192)
+    z = torch.zeros(1, dtype=torch.int32).cuda()
+    out, st = g.lin_blocks(dm[0], dm[1], merged, so, z, z, 64 * 64, 3, False, q_s=6)
+    G = out.cpu().numpy()[0, :m.nv * m.nv].reshape(m.nv, m.nv)
+    assert st.cpu().numpy()[0] == 0
+    want = L.lin_block(m.verts, m.tris, range(m.nv), range(m.nv), 3, False, T=T, q_s=6)
+    assert np.abs(G - want).max() <= 1e-12 * np.abs(want).max()
+    assert np.abs(G - G.T).max() <= 1e-6 * np.abs(G).max()
+    assert np.linalg.eigvalsh(0.5 * (G + G.T)).min() > 0
+    # without q_s the same block is refused (status 1, zeros)
+    out0, st0 = g.lin_blocks(dm[0], dm[1], merged, so, z, z, 64 * 64, 3, False)
+    assert st0.cpu().numpy()[0] == 1 and (out0[0, :m.nv * m.nv] == 0).all()

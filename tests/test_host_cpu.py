@@ -203,9 +203,9 @@ def test_lin_entry_points_validate_arguments(gca):
     assert L.gca_lin_merge(None, None, None, None, None, 0, 8, None, None, None, None) == 0
     assert L.gca_lin_merge(None, None, None, None, None, 2, 8, None, None, None, None) == -1
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
-    L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, P, P, P]
-    args = lambda nblk, q, sym, cap=8, ld=16: (None, None, None, None, None, cap, None, None, None, nblk, ld, q, sym,
-                                                None, None, None)
+    L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
+    args = lambda nblk, q, sym, cap=8, ld=16, q_s=0: (None, None, None, None, None, cap, None, None, None, nblk, ld, q,
+                                                      sym, q_s, None, None, None)
     assert L.gca_lin_blocks(*args(0, 3, 0)) == 0
     assert L.gca_lin_blocks(*args(1, 3, 0)) == -1       # NULL pointers
     assert L.gca_lin_blocks(*args(0, 5, 0)) == -1       # 25-point rule exceeds 16 points
@@ -213,3 +213,6 @@ def test_lin_entry_points_validate_arguments(gca):
     assert L.gca_lin_blocks(*args(0, 3, 2)) == -1
     assert L.gca_lin_blocks(*args(0, 3, 0, cap=0)) == -1
     assert L.gca_lin_blocks(*args(-1, 3, 0)) == -1
+    assert L.gca_lin_blocks(*args(0, 3, 0, q_s=32)) == 0
+    assert L.gca_lin_blocks(*args(0, 3, 0, q_s=33)) == -1    # more Gauss points than the rule table holds
+    assert L.gca_lin_blocks(*args(0, 3, 0, q_s=-1)) == -1
