@@ -86,6 +86,14 @@ def _load():
     lib.orc_entry_dl.argtypes = [P, I64, I64]
     lib.orc_entries_dl.argtypes = [P, I64, P, P, P]
     lib.orc_lin_touch_moments.argtypes = [P, I64, I64, P]
+    lib.orc_curved_create.restype = P
+    lib.orc_curved_create.argtypes = [I64, I64, P, P, I32, I32, I32]
+    lib.orc_curved_destroy.argtypes = [P]
+    lib.orc_curved_classify.restype = I32
+    lib.orc_curved_classify.argtypes = [P, I64, I64]
+    lib.orc_curved_moments.argtypes = [P, I32, I64, I64, P]
+    lib.orc_curved_moments_many.argtypes = [P, I32, I64, P, P, P]
+    lib.orc_curved_mass.argtypes = [P, I64, I32, P]
     _lib = lib
     return lib
 

@@ -815,3 +815,220 @@ void orc_lin_touch_moments(void *p, int64_t t, int64_t s, double *M)
                     }
     for (int k = 0; k < 9; ++k) M[k] *= Jp * Jq / (4.0 * ORC_PI);
 }
+
+/* ------------------------------------------------------------------------
+ * Curved (quadratic) triangles (Section 6).  Triangle t is the image of the
+ * reference triangle under the quadratic map Phi_t that interpolates its
+ * vertices X0, X1, X2 and the points X3, X4, X5 given for its edges X0-X1,
+ * X1-X2, X2-X0 at the edge midpoints.  With the barycentric coordinates
+ * (l0, l1, l2) = (1 - s1, s1 - s2, s2) of the reference point s (the
+ * parametrisation of the flat code above, whose map is the special case of
+ * straight-edge midpoints):
+ *     Phi(s) = sum_a l_a (2 l_a - 1) X_a + 4 l0 l1 X3 + 4 l1 l2 X4 + 4 l2 l0 X5,
+ * the normal n(s) = dPhi/ds1 x dPhi/ds2 and the Gramian gamma(s) = |n(s)|.
+ * The basis functions are the mapped nodal functions: phi_a o Phi = l_a.
+ * For a pair (t, s) the nine moments
+ *     M[a][b] = int_that int_that l_a(x) k(Phi_t(x), Phi_s(y)) l_b(y)
+ *               gamma_t(x) gamma_s(y) dy dx
+ * are returned (a, b corners in mesh order; the piecewise-constant entry is
+ * their sum) for k the single-layer kernel g (op 0) or the double-layer
+ * kernel n_s(y) . (x - y) / (4 pi |x - y|^3) with the unit normal
+ * n_s = n / gamma of the mesh orientation (op 1).  Touching pairs, decided
+ * by the corner ids, use the Sauter-Schwab maps of the flat entries on the
+ * reference coordinates, with the corners reordered as there (the edge
+ * points follow their edges) and differences Phi_t(x) - Phi_s(y) formed
+ * relative to the shared vertex; the others the regular rule on both
+ * triangles. */
+
+typedef struct {
+    int64_t nn, nt;
+    double *xyz;     /* nn x 3 nodes */
+    int32_t *tri;    /* nt x 6: X0 X1 X2 (corners) and the edge points of X0-X1, X1-X2, X2-X0 */
+    int q_s;
+    orc_trirule rr;
+    double gs_x[ORC_QMAX], gs_w[ORC_QMAX];
+} orc_curved;
+
+void *orc_curved_create(int64_t nn, int64_t nt, const double *xyz, const int32_t *tri6, int q_r, int q_s, int sym)
+{
+    if (q_r < 1 || q_s < 1 || q_r > ORC_QMAX || q_s > ORC_QMAX) return NULL;
+    if (sym && q_r != 2 && q_r != 3) return NULL;
+    orc_curved *c = (orc_curved *)calloc(1, sizeof(orc_curved));
+    if (sym) rule_symmetric(q_r, &c->rr);
+    else rule_collapsed(q_r, &c->rr);
+    c->nn = nn; c->nt = nt; c->q_s = q_s;
+    c->xyz = (double *)malloc(sizeof(double) * 3 * (size_t)nn);
+    c->tri = (int32_t *)malloc(sizeof(int32_t) * 6 * (size_t)nt);
+    memcpy(c->xyz, xyz, sizeof(double) * 3 * (size_t)nn);
+    memcpy(c->tri, tri6, sizeof(int32_t) * 6 * (size_t)nt);
+    orc_gauss01(q_s, c->gs_x, c->gs_w);
+    return c;
+}
+
+void orc_curved_destroy(void *p)
+{
+    orc_curved *c = (orc_curved *)p;
+    if (!c) return;
+    free(c->xyz); free(c->tri); free(c);
+}
+
+/* ORC_IDENT / ORC_EDGE / ORC_VERT by shared corners, else ORC_REG */
+int orc_curved_classify(void *p, int64_t i, int64_t j)
+{
+    const orc_curved *c = (const orc_curved *)p;
+    int shared = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (c->tri[6 * i + a] == c->tri[6 * j + b]) ++shared;
+    return shared == 3 ? ORC_IDENT : (shared == 2 ? ORC_EDGE : (shared == 1 ? ORC_VERT : ORC_REG));
+}
+
+/* node index (3, 4, 5) of the edge between corners a and b */
+static int edge_slot(int a, int b)
+{
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    return lo == 0 ? (hi == 1 ? 3 : 5) : 4;
+}
+
+/* The six nodes of triangle t with its corners taken in the order perm
+ * (new corner k = mesh corner perm[k]). */
+static void curved_nodes(const orc_curved *c, int64_t t, const int *perm, double X[6][3])
+{
+    int src[6] = {perm[0], perm[1], perm[2], edge_slot(perm[0], perm[1]), edge_slot(perm[1], perm[2]),
+                  edge_slot(perm[2], perm[0])};
+    for (int k = 0; k < 6; ++k)
+        for (int d = 0; d < 3; ++d) X[k][d] = c->xyz[3 * (int64_t)c->tri[6 * t + src[k]] + d];
+}
+
+/* Phi(s) - X0 and n(s) */
+static void curved_eval(const double X[6][3], double s1, double s2, double *rel, double *n)
+{
+    double l0 = 1.0 - s1, l1 = s1 - s2, l2 = s2;
+    double N[6] = {l0 * (2 * l0 - 1), l1 * (2 * l1 - 1), l2 * (2 * l2 - 1), 4 * l0 * l1, 4 * l1 * l2, 4 * l2 * l0};
+    /* derivatives of the shape functions with respect to (l0, l1, l2) */
+    double D[6][3] = {{4 * l0 - 1, 0, 0}, {0, 4 * l1 - 1, 0}, {0, 0, 4 * l2 - 1},
+                      {4 * l1, 4 * l0, 0}, {0, 4 * l2, 4 * l1}, {4 * l2, 0, 4 * l0}};
+    double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) {
+        rel[d] = 0.0;
+        for (int k = 0; k < 6; ++k) {
+            rel[d] += N[k] * (X[k][d] - X[0][d]);
+            /* d/ds1 = d/dl1 - d/dl0, d/ds2 = d/dl2 - d/dl1 */
+            a[d] += (D[k][1] - D[k][0]) * X[k][d];
+            b[d] += (D[k][2] - D[k][1]) * X[k][d];
+        }
+    }
+    n[0] = a[1] * b[2] - a[2] * b[1];
+    n[1] = a[2] * b[0] - a[0] * b[2];
+    n[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* kernel value times gamma_t gamma_s: op 0 g gamma_s, op 1 (ns . d) / (4 pi r^3) with
+ * ns = sign * n_s (the unnormalised normal of the mesh orientation) */
+static double curved_kernel(int op, const double *d, const double *ns, double sign)
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (op == 0) return sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]) / (4.0 * ORC_PI * sqrt(r2));
+    return sign * (ns[0] * d[0] + ns[1] * d[1] + ns[2] * d[2]) / (4.0 * ORC_PI * r2 * sqrt(r2));
+}
+
+static double vnorm(const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+/* sign of a permutation of (0, 1, 2) */
+static double perm_sign(const int *p)
+{
+    int inv = (p[0] > p[1]) + (p[0] > p[2]) + (p[1] > p[2]);
+    return (inv & 1) ? -1.0 : 1.0;
+}
+
+void orc_curved_moments(void *p, int op, int64_t t, int64_t s, double *M)
+{
+    const orc_curved *c = (const orc_curved *)p;
+    for (int k = 0; k < 9; ++k) M[k] = 0.0;
+    const int32_t *vt = c->tri + 6 * t, *vs = c->tri + 6 * s;
+    int kase = orc_curved_classify(p, t, s);
+    int pa[3] = {0, 1, 2}, pb[3] = {0, 1, 2};
+    if (kase == ORC_EDGE) {
+        int sa[2], sb[2], ns = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (vt[a] == vs[b]) { sa[ns] = a; sb[ns] = b; ++ns; }
+        int lo0 = vt[sa[0]] < vt[sa[1]];
+        pa[0] = lo0 ? sa[0] : sa[1]; pa[1] = lo0 ? sa[1] : sa[0]; pa[2] = 3 - pa[0] - pa[1];
+        pb[0] = lo0 ? sb[0] : sb[1]; pb[1] = lo0 ? sb[1] : sb[0]; pb[2] = 3 - pb[0] - pb[1];
+    } else if (kase == ORC_VERT) {
+        int ka = 0, kb = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (vt[a] == vs[b]) { ka = a; kb = b; }
+        for (int k = 0; k < 3; ++k) { pa[k] = (ka + k) % 3; pb[k] = (kb + k) % 3; }
+    }
+    double X[6][3], Y[6][3];
+    curved_nodes(c, t, pa, X);
+    curved_nodes(c, s, pb, Y);
+    double sgn = perm_sign(pb);
+    if (kase == ORC_REG) {
+        const orc_trirule *r = &c->rr;
+        for (int a = 0; a < r->np; ++a) {
+            double xr[3], nx[3];
+            curved_eval(X, r->s1[a], r->s2[a], xr, nx);
+            double lp[3] = {1.0 - r->s1[a], r->s1[a] - r->s2[a], r->s2[a]};
+            double wx = r->w[a] * vnorm(nx);
+            for (int b = 0; b < r->np; ++b) {
+                double yr[3], ny[3], d[3];
+                curved_eval(Y, r->s1[b], r->s2[b], yr, ny);
+                for (int k = 0; k < 3; ++k) d[k] = (X[0][k] + xr[k]) - (Y[0][k] + yr[k]);
+                double g = wx * r->w[b] * curved_kernel(op, d, ny, sgn);
+                double lq[3] = {1.0 - r->s1[b], r->s1[b] - r->s2[b], r->s2[b]};
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) M[3 * pa[i] + pb[j]] += g * lp[i] * lq[j];
+            }
+        }
+        return;
+    }
+    int q = c->q_s;
+    for (int r = 0; r < ss_regions(kase); ++r)
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+                for (int e = 0; e < q; ++e)
+                    for (int f = 0; f < q; ++f) {
+                        double x1, x2, y1, y2;
+                        double jac = ss_map(kase, r, c->gs_x[a], c->gs_x[b], c->gs_x[e], c->gs_x[f], &x1, &x2, &y1, &y2);
+                        double w = c->gs_w[a] * c->gs_w[b] * c->gs_w[e] * c->gs_w[f] * jac;
+                        double xr[3], nx[3], yr[3], ny[3], d[3];
+                        curved_eval(X, x1, x2, xr, nx);
+                        curved_eval(Y, y1, y2, yr, ny);
+                        /* X0 = Y0: the shared vertex */
+                        for (int k = 0; k < 3; ++k) d[k] = xr[k] - yr[k];
+                        double g = w * vnorm(nx) * curved_kernel(op, d, ny, sgn);
+                        double lp[3] = {1.0 - x1, x1 - x2, x2}, lq[3] = {1.0 - y1, y1 - y2, y2};
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j) M[3 * pa[i] + pb[j]] += g * lp[i] * lq[j];
+                    }
+}
+
+void orc_curved_moments_many(void *p, int op, int64_t m, const int64_t *I, const int64_t *J, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < m; ++k) orc_curved_moments(p, op, I[k], J[k], out + 9 * k);
+}
+
+/* int_t phi_a = int_that l_a gamma by the collapsed rule of order q (area: the sum) */
+void orc_curved_mass(void *p, int64_t t, int q, double *m3)
+{
+    const orc_curved *c = (const orc_curved *)p;
+    orc_trirule r;
+    rule_collapsed(q, &r);
+    int id[3] = {0, 1, 2};
+    double X[6][3];
+    curved_nodes(c, t, id, X);
+    m3[0] = m3[1] = m3[2] = 0.0;
+    for (int a = 0; a < r.np; ++a) {
+        double xr[3], n[3];
+        curved_eval(X, r.s1[a], r.s2[a], xr, n);
+        double w = r.w[a] * vnorm(n);
+        m3[0] += w * (1.0 - r.s1[a]);
+        m3[1] += w * (r.s1[a] - r.s2[a]);
+        m3[2] += w * r.s2[a];
+    }
+}

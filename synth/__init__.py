@@ -25,7 +25,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "Mesh", "icosphere", "ellipsoid", "jitter", "mean_edge_length",
+    "Mesh", "QuadMesh", "icosphere", "ellipsoid", "quadratic", "jitter", "mean_edge_length",
     "rhs_normal", "workload",
 ]
 
@@ -108,6 +108,58 @@ def ellipsoid(level: int, axes=(1.0, 0.7, 0.4)) -> Mesh:
     m = icosphere(level)
     m.verts = m.verts * np.asarray(axes, dtype=np.float64)[None, :]
     return m
+
+
+@dataclass
+class QuadMesh:
+    """Quadratic (curved) triangles on the vertices of a flat mesh.
+
+    nodes: (nv + ne, 3) float64: the nv vertices, then one node per edge.
+    tris:  (nt, 6) int32: vertices v0, v1, v2 (the flat mesh's order), then the
+           nodes of the edges v0-v1, v1-v2, v2-v0.
+    """
+    nodes: np.ndarray
+    tris: np.ndarray
+    nv: int
+
+    @property
+    def nt(self) -> int:
+        return int(self.tris.shape[0])
+
+    @property
+    def nn(self) -> int:
+        return int(self.nodes.shape[0])
+
+
+def quadratic(mesh: Mesh, surface: str = "sphere", axes=(1.0, 1.0, 1.0)) -> QuadMesh:
+    """Edge nodes for curved triangles: the midpoint of every edge, moved onto
+    the surface the mesh approximates -- "sphere" (radial projection onto the
+    sphere of the vertices' radius), "ellipsoid" (the semi-axes `axes`: the
+    midpoint mapped to the unit sphere, projected, mapped back) or "flat" (kept
+    on the straight edge).  Edges are numbered in order of first appearance
+    in (triangle, edge) order."""
+    t = mesh.tris.astype(np.int64)
+    e = np.stack([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]], axis=1).reshape(-1, 2)
+    key = np.sort(e, axis=1)
+    _, first, inv = np.unique(key[:, 0] * (mesh.nv + 1) + key[:, 1], return_index=True, return_inverse=True)
+    order = np.argsort(first, kind="stable")            # renumber by first appearance
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    eid = rank[inv.reshape(-1)]
+    ends = key[first[order]]
+    mid = 0.5 * (mesh.verts[ends[:, 0]] + mesh.verts[ends[:, 1]])
+    if surface == "sphere":
+        r = np.linalg.norm(mesh.verts[ends[:, 0]], axis=1)
+        mid = mid / np.linalg.norm(mid, axis=1, keepdims=True) * r[:, None]
+    elif surface == "ellipsoid":
+        a = np.asarray(axes, dtype=np.float64)[None, :]
+        u = mid / a
+        mid = u / np.linalg.norm(u, axis=1, keepdims=True) * a
+    elif surface != "flat":
+        raise ValueError("surface must be sphere, ellipsoid or flat")
+    nodes = np.concatenate([mesh.verts, mid])
+    tri6 = np.concatenate([mesh.tris.astype(np.int64), mesh.nv + eid.reshape(-1, 3)], axis=1).astype(np.int32)
+    return QuadMesh(nodes, tri6, mesh.nv)
 
 
 def mean_edge_length(mesh: Mesh) -> float:
