@@ -42,6 +42,7 @@ EXPORTED = [
     "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
     "gca_block_entries", "gca_dl_entries",
     "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks", "gca_coll_blocks",
+    "gca_curved_entries",
 ]
 
 
@@ -137,6 +138,7 @@ def lib():
     L.gca_lin_merge.argtypes = [P, P, P, P, P, I32, I32, P, P, P, P]
     L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
     L.gca_coll_blocks.argtypes = [P, P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
+    L.gca_curved_entries.argtypes = [P, P, I64, P, P, I64, I32, I32, I32, I32, I32, P, P]
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
     L.gca_last_error.argtypes = []
@@ -146,7 +148,7 @@ def lib():
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
                  "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
                  "gca_block_entries", "gca_dl_entries", "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
-                 "gca_coll_blocks"):
+                 "gca_coll_blocks", "gca_curved_entries"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -603,3 +605,20 @@ def coll_blocks(xyz, tri, set_vtx, merged, set_off, blk_row, blk_col, ld, q, sym
                                  _vp(set_off), _vp(blk_row), _vp(blk_col), nblk, int(ld), int(q), int(bool(sym)),
                                  int(q_s), _vp(out), _vp(status), _stream_ptr(stream)))
     return out[:nblk], status[:nblk]
+
+
+def curved_entries(nodes, tri6, I, J, op=0, basis=0, q=3, sym=False, q_s=4, stream=None):
+    """Galerkin moments of curved (quadratic) triangle pairs (gca_curved_entries):
+    nodes (nn, 3) FP64 and tri6 (nt, 6) int32 CUDA tensors, I and J int32 CUDA
+    tensors of triangle ids; op 0 single layer, 1 double layer; basis 0 the
+    piecewise-constant entries (m,), basis 1 the nine nodal moments (m, 3, 3).
+    Returns a CUDA FP64 tensor."""
+    import torch
+    m = int(I.numel())
+    assert int(J.numel()) == m and I.dtype == torch.int32 and J.dtype == torch.int32
+    assert nodes.dtype == torch.float64 and tri6.dtype == torch.int32 and tri6.shape[1] == 6
+    assert nodes.is_contiguous() and tri6.is_contiguous() and I.is_contiguous() and J.is_contiguous()
+    out = torch.empty(max(m, 1) * (9 if basis else 1), dtype=torch.float64, device=nodes.device)
+    _check(lib().gca_curved_entries(_vp(nodes), _vp(tri6), int(tri6.shape[0]), _vp(I), _vp(J), m, int(op),
+                                    int(basis), int(q), int(bool(sym)), int(q_s), _vp(out), _stream_ptr(stream)))
+    return out[:m * 9].view(m, 3, 3) if basis else out[:m]

@@ -22,7 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["quad.hip", "basis.hip", "h2.hip", "solve.hip", "adjoint.hip", "grad.hip", "linear.hip",
                "noalloc.hip", "multi.hip", "colloc.hip",
-               "dlayer.hip"]
+               "dlayer.hip", "curved.hip"]
 HOST_SOURCES = ["host.cpp", "capi.cpp"]
 
 

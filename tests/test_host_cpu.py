@@ -193,6 +193,19 @@ def test_lin_vertex_triangles_host(gca):
     assert list(off) == [0] * 5 and lst.size == 0
 
 
+def test_curved_entry_point_validates_arguments(gca):
+    L = ctypes.CDLL(gca.LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.gca_curved_entries.argtypes = [P, P, I64, P, P, I64, I32, I32, I32, I32, I32, P, P]
+    ok = dict(nt=20, m=0, op=0, basis=0, q=3, sym=0, q_s=4)
+    call = lambda **kw: L.gca_curved_entries(None, None, kw["nt"], None, None, kw["m"], kw["op"], kw["basis"],
+                                             kw["q"], kw["sym"], kw["q_s"], None, None)
+    assert call(**ok) == 0
+    for bad in (dict(m=-1), dict(nt=0), dict(op=2), dict(basis=2), dict(q=5), dict(q=4, sym=1), dict(sym=2),
+                dict(q_s=0), dict(q_s=33), dict(m=4)):   # the last: NULL pointers with work to do
+        assert call(**{**ok, **bad}) == -1, bad
+
+
 def test_lin_entry_points_validate_arguments(gca):
     # argument checks run before any device work (NULL device pointers are fine here)
     L = ctypes.CDLL(gca.LIB_PATH)
