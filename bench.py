@@ -34,6 +34,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -91,6 +92,22 @@ def lin_evals_per_s(P):
 # 3 operations for |x - y|^2, 4 for the refined rsqrt plus the quarter-rate
 # v_rsq_f64 (4 issue slots), 1 FMA for the weighted sum: 17 + 4 slots.
 COLL_EVALS_PER_S = FP64_LANE_OPS_PER_S / 21.0
+
+
+# FP64 ceilings of the curved-triangle kernels (quadratic maps, normals
+# interpolated from their six nodal values).  Regular pairs: per kernel
+# evaluation 3 subtractions, 3 for |x - y|^2, the refined rsqrt (4 slots)
+# with its quarter-rate v_rsq_f64 (4), the Gramian factor and the weighted
+# sum (2): 16 slots; per rule point (2 P per pair) the shape functions (11),
+# the point and the normal (33 FMAs), |n|^2 and the square root (about 11):
+# 55 slots.  Touching pairs, per 4D point: the map and its weight (12), two
+# points with their normals (88), the differences, norms, refined rsqrt and
+# weight (25), the sum (1): 126 slots.
+def curved_pairs_per_s(P):
+    return FP64_LANE_OPS_PER_S / (16.0 * P * P + 55.0 * 2 * P)
+
+
+CURVED_SS_EVALS_PER_S = FP64_LANE_OPS_PER_S / 126.0
 
 
 def phase_rooflines(st, params, P, Pc, ms, ss_fp32=False):
@@ -178,6 +195,8 @@ def parse():
                          "caller's stream: per-kernel rooflines in isolation; 0 disables it)")
     ap.add_argument("--rhs16-steps", type=int, default=5,
                     help="timed batched products with 16 right-hand sides per precision (0 disables it)")
+    ap.add_argument("--curved-rows", type=int, default=32768,
+                    help="random triangles whose touching pairs the curved-triangle leg integrates (0: skip)")
     ap.add_argument("--dl-rows", type=int, default=32768,
                     help="triangles whose touching pairs (and as many random pairs) time the double-layer entries "
                          "(0 disables it)")
@@ -294,13 +313,9 @@ def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
     return res
 
 
-def double_layer(gca, torch, H, mesh, nrows, seed=11):
-    """Double-layer Galerkin entries (gca_dl_entries) on the workload mesh: the
-    touching pairs (common vertex or edge) of nrows random triangles, both
-    orders, and as many random (regular) pairs; wall time of each call, which
-    includes the host classification and the transfers."""
-    rng = np.random.default_rng(seed)
-    rows = rng.choice(mesh.nt, nrows, replace=False)
+def touching_pairs(mesh, rows):
+    """Every pair (t, s), t in rows, s != t sharing a vertex with t, in both
+    orders (unique)."""
     flat = mesh.tris.reshape(-1)
     order = np.argsort(flat, kind="stable")
     start = np.searchsorted(flat[order], np.arange(mesh.nv + 1))
@@ -308,15 +323,99 @@ def double_layer(gca, torch, H, mesh, nrows, seed=11):
     for c in range(3):
         v = mesh.tris[rows, c]
         cnt = start[v + 1] - start[v]
-        rr = np.repeat(rows, cnt)
-        idx = np.concatenate([order[start[a]:start[a + 1]] for a in v]) // 3
-        I.append(rr)
-        J.append(idx)
+        I.append(np.repeat(rows, cnt))
+        J.append(np.concatenate([order[start[a]:start[a + 1]] for a in v]) // 3)
     I, J = np.concatenate(I), np.concatenate(J)
     pair = np.unique(np.stack([I, J], 1), axis=0)
     pair = pair[pair[:, 0] != pair[:, 1]]
-    Ti = np.concatenate([pair[:, 0], pair[:, 1]])
-    Tj = np.concatenate([pair[:, 1], pair[:, 0]])
+    return np.concatenate([pair[:, 0], pair[:, 1]]), np.concatenate([pair[:, 1], pair[:, 0]])
+
+
+def curved(gca, torch, mesh, nrows, steps=3, seed=13):
+    """Curved (quadratic) triangles on the workload mesh (Section 6): edge
+    points on the sphere, gca_curved_entries for the touching pairs of nrows
+    random triangles (both orders; identical pairs added) and as many random
+    pairs; single layer with the piecewise-constant basis (and the nodal
+    moments, and the double layer), symmetric 6-point rule, q_s = 4; HIP events
+    on the current stream around each call (no host work inside)."""
+    import synth
+    q = synth.quadratic(mesh, "sphere")
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(mesh.nt, nrows, replace=False)
+    Ti, Tj = touching_pairs(mesh, rows)
+    Ti, Tj = np.concatenate([Ti, rows]), np.concatenate([Tj, rows])
+    # regular pairs in blocks, as a block of the matrix presents them: 32 x 32
+    # triangles of two patches (32 consecutive ids of the hierarchical mesh
+    # numbering) whose centroids are at least 0.1 apart
+    nb = Ti.size // 1024
+    cen = mesh.verts[mesh.tris].mean(axis=1)
+    pa = rng.integers(0, mesh.nt // 32, nb)
+    pb = rng.integers(0, mesh.nt // 32, nb)
+    far = np.linalg.norm(cen[32 * pa] - cen[32 * pb], axis=1) > 0.1
+    pa, pb = pa[far], pb[far]
+    loc = np.arange(32)
+    Ri = (32 * pa[:, None, None] + loc[None, :, None] + 0 * loc[None, None, :]).reshape(-1)
+    Rj = (32 * pb[:, None, None] + 0 * loc[None, :, None] + loc[None, None, :]).reshape(-1)
+    shared = (mesh.tris[Ti][:, :, None] == mesh.tris[Tj][:, None, :]).sum(axis=(1, 2))
+    qs, P = 4, 6
+    regions = {1: 2, 2: 5, 3: 6}
+    ss_evals = int(sum(regions[k] * np.count_nonzero(shared == k) for k in (1, 2, 3))) * qs ** 4
+    nodes = torch.as_tensor(q.nodes, dtype=torch.float64).cuda()
+    tri6 = torch.as_tensor(q.tris, dtype=torch.int32).cuda()
+    dev = lambda a: torch.as_tensor(a.astype(np.int32)).cuda()
+    sets = {"touching": (dev(Ti), dev(Tj)), "regular": (dev(Ri), dev(Rj))}
+    res = {"workload": f"curved level-{int(round(math.log(mesh.nt / 20, 4)))} sphere ({q.nt} quadratic triangles, "
+                       f"{q.nn} nodes, edge points projected onto the sphere); the touching pairs of {nrows} random "
+                       f"triangles in both orders plus the identical pairs, and about as many regular pairs in 32 x 32 "
+                       f"blocks of two patches of consecutive triangles at least 0.1 apart (seed {seed}); "
+                       f"symmetric {P}-point rule, q_s = {qs}, FP64",
+           "touching_classes": {"vertex": int(np.count_nonzero(shared == 1)),
+                                "edge": int(np.count_nonzero(shared == 2)),
+                                "identical": int(np.count_nonzero(shared == 3))}}
+    for name, (I, J) in sets.items():
+        out = {}
+        for op, basis, key in ((0, 0, "single_constant"), (0, 1, "single_nodal"), (1, 0, "double_constant")):
+            gca.curved_entries(nodes, tri6, I, J, op=op, basis=basis, q=3, sym=True, q_s=qs)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                gca.curved_entries(nodes, tri6, I, J, op=op, basis=basis, q=3, sym=True, q_s=qs)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            out[key] = {"ms": ms, "pairs_per_s": I.numel() / (ms * 1e-3)}
+        out["pairs"] = int(I.numel())
+        res[name] = out
+    ms = res["regular"]["single_constant"]["ms"]
+    ach = res["regular"]["pairs"] / (ms * 1e-3)
+    res["regular"]["roofline"] = {"bound": "fp64 alu", "achieved": ach, "peak": curved_pairs_per_s(P),
+                                  "unit": "pairs/s", "frac": ach / curved_pairs_per_s(P),
+                                  "kernel": f"k_curved_regular<{P},0,0>"}
+    ms = res["touching"]["single_constant"]["ms"]
+    ach = ss_evals / (ms * 1e-3)
+    res["touching"]["roofline"] = {"bound": "fp64 alu", "achieved": ach, "peak": CURVED_SS_EVALS_PER_S,
+                                   "unit": "evaluations/s", "frac": ach / CURVED_SS_EVALS_PER_S,
+                                   "evaluations": ss_evals, "kernel": "k_curved_touch<0,0>"}
+    print(f"[bench] curved: {res['regular']['pairs']} regular pairs {ms_fmt(res['regular'])}; "
+          f"{res['touching']['pairs']} touching pairs {ms_fmt(res['touching'])}; regular "
+          f"{res['regular']['roofline']['frac']:.1%}, touching {res['touching']['roofline']['frac']:.1%} of the FP64 ceiling",
+          file=sys.stderr, flush=True)
+    return res
+
+
+def ms_fmt(r):
+    return ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in r.items() if isinstance(v, dict) and "ms" in v)
+
+
+def double_layer(gca, torch, H, mesh, nrows, seed=11):
+    """Double-layer Galerkin entries (gca_dl_entries) on the workload mesh: the
+    touching pairs (common vertex or edge) of nrows random triangles, both
+    orders, and as many random (regular) pairs; wall time of each call, which
+    includes the host classification and the transfers."""
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(mesh.nt, nrows, replace=False)
+    Ti, Tj = touching_pairs(mesh, rows)
     Ri = rng.integers(0, mesh.nt, Ti.size)
     Rj = rng.integers(0, mesh.nt, Ti.size)
     res = {"workload": f"touching pairs of {nrows} random triangles in both orders and as many random pairs "
@@ -533,6 +632,7 @@ def main():
         H.store_blocks(False, False)
 
     dl = double_layer(gca, torch, H, mesh, a.dl_rows) if a.dl_rows > 0 else None
+    curv = curved(gca, torch, mesh, a.curved_rows) if a.curved_rows > 0 else None
 
     linear = None
     if a.lin_blocks > 0:
@@ -634,6 +734,7 @@ def main():
         "stored_blocks": stored,
         "linear_basis": linear,
         "double_layer": dl,
+        "curved": curv,
         "mixed_over_fp64": dt_fp64 / dt_mixed,
         "rel_err_sampled_rows": rel,
         "phases_ms": {"mixed": mean_mixed, "fp64": mean_fp64},

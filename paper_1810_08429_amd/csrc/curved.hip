@@ -9,15 +9,13 @@
 // evaluation the paper proposes): 18 FMAs per point instead of the 36 of the
 // two derivatives and the cross product.  gamma = |n|.
 //
-// Two kernels on the caller's stream, each pair written by exactly one:
-//   - k_curved_regular: one thread per pair without a common corner, the
-//     regular rule of P points on both triangles (the column points kept in
-//     registers);
-//   - k_curved_touch: one wavefront per 64 pairs; the touching ones (ballot)
-//     are integrated one after the other by the whole wavefront: the 4D
-//     Sauter-Schwab maps (ssmap.h), lanes over (region, xi, e1, e2) and e3
-//     inside, differences formed relative to the shared corner, the lanes'
-//     partial sums combined in a fixed order.
+// One kernel, one thread per pair, every pair written once:
+//   - a pair without a common corner: the regular rule of P points on both
+//     triangles in its own lane (the column points kept in registers);
+//   - then the touching pairs of the wavefront (ballot), one after the other
+//     by the whole wavefront: the 4D Sauter-Schwab maps (ssmap.h), lanes over
+//     (region, xi, e1, e2) and e3 inside, differences formed relative to the
+//     shared corner, the lanes' partial sums combined in a fixed order.
 // FP64 throughout.
 #include <hip/hip_runtime.h>
 
@@ -126,23 +124,10 @@ __device__ __forceinline__ double dot3(const double *a, const double *b)
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// A pair without a common corner, by one thread.
 template <int P, int OP, int BASIS>
-__global__ void __launch_bounds__(128) k_curved_regular(CurvArgs A)
+__device__ void regular_pair(const CurvArgs &A, int64_t t, int64_t s, double *out)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.m) return;
-    const int64_t t = A.I[k], s = A.J[k];
-    double *out = A.out + (BASIS ? 9 * k : k);
-    if (t < 0 || t >= A.nt || s < 0 || s >= A.nt) {
-        for (int e = 0; e < (BASIS ? 9 : 1); ++e) out[e] = __builtin_nan("");
-        return;
-    }
-    bool tch = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) tch |= A.tri[6 * t + a] == A.tri[6 * s + b];
-    if (tch) return;   // k_curved_touch writes it
     const CurvRule &R = A.R;
     double yy[P][3], yk[P][3];   // column points minus the row triangle's X0; gamma (OP 0) or n (OP 1)
     double s0[3];
@@ -223,20 +208,26 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int OP, int BASIS>
-__global__ void __launch_bounds__(256) k_curved_touch(CurvArgs A)
+// The pairs of a wavefront: pair base + lane is (t, s); invalid ids give NaN,
+// pairs without a common corner take regular_pair in their own lane, then the
+// touching ones (ballot) are integrated one after the other by the whole
+// wavefront.  Every lane of the wavefront must call it.
+template <int P, int OP, int BASIS>
+__device__ void wave_pairs(const CurvArgs &A, int64_t base, int t, int s, bool live)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
-    const int64_t k = base + lane;
-    int t = -1, s = -1;
     bool tch = false;
-    if (k < A.m) {
-        t = A.I[k];
-        s = A.J[k];
-        if (t >= 0 && t < A.nt && s >= 0 && s < A.nt)
+    if (live) {
+        double *out = A.out + (BASIS ? 9 * (base + lane) : base + lane);
+        if (t < 0 || t >= A.nt || s < 0 || s >= A.nt) {
+            for (int e = 0; e < (BASIS ? 9 : 1); ++e) out[e] = __builtin_nan("");
+        } else {
+#pragma unroll
             for (int a = 0; a < 3; ++a)
+#pragma unroll
                 for (int b = 0; b < 3; ++b) tch |= A.tri[6 * (int64_t)t + a] == A.tri[6 * (int64_t)s + b];
+            if (!tch) regular_pair<P, OP, BASIS>(A, t, s, out);
+        }
     }
     uint64_t mask = __ballot(tch);
     const CurvRule &R = A.R;
@@ -343,21 +334,30 @@ __global__ void __launch_bounds__(256) k_curved_touch(CurvArgs A)
     }
 }
 
+// One thread per pair (64 pairs per wavefront, 256 per workgroup).
+template <int P, int OP, int BASIS>
+__global__ void __launch_bounds__(256) k_curved(CurvArgs A)
+{
+    const int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
+    const int64_t k = base + (threadIdx.x & 63);
+    const bool live = k < A.m;
+    wave_pairs<P, OP, BASIS>(A, base, live ? A.I[k] : -1, live ? A.J[k] : -1, live);
+}
+
 template <int OP, int BASIS>
 hipError_t launch_curved(const CurvArgs &a, int np, hipStream_t s)
 {
-    const unsigned g1 = (unsigned)((a.m + 127) / 128), g2 = (unsigned)((a.m + 255) / 256);
+    const unsigned g = (unsigned)((a.m + 255) / 256);
     switch (np) {
-#define CASE(PP)                                                                                 \
-    case PP:                                                                                     \
-        hipLaunchKernelGGL((k_curved_regular<PP, OP, BASIS>), dim3(g1), dim3(128), 0, s, a);     \
+#define CASE(PP)                                                                         \
+    case PP:                                                                             \
+        hipLaunchKernelGGL((k_curved<PP, OP, BASIS>), dim3(g), dim3(256), 0, s, a);      \
         break;
         CASE(1) CASE(3) CASE(4) CASE(6) CASE(9) CASE(16)
 #undef CASE
     default:
         return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_curved_touch<OP, BASIS>), dim3(g2), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
