@@ -124,6 +124,51 @@ gca_status gca_coll_blocks(const double *xyz, const int32_t *tri, const int32_t 
                            int32_t nblk, int64_t ld, int32_t q, int32_t sym, int32_t q_s, double *out,
                            int32_t *status, void *stream);
 
+/* ---- GCA-H^2 with the nodal basis (Sections 2-5 over the vertices) ----
+ *
+ * The index set is the vertices (one nodal function each).  The cluster tree
+ * splits the vertex positions at the median of the longest extent of their
+ * bounding box (ties by vertex id); a cluster's box, used by the
+ * admissibility condition max(diam t, diam s) <= 2 eta dist(t, s) and by the
+ * Green points of Section 2, encloses the supports of its functions (every
+ * triangle of T_i).  The Green factor A of a cluster has one row per vertex:
+ * the integrals of g(x, z_nu) and of the normal derivative against phi_i over
+ * its support (collapsed Gauss of order q_A on every triangle, the nodal
+ * weight); full-pivot ACA and the nested bases follow Sections 3-4 as for the
+ * piecewise-constant basis.  The coupling matrices G|t~ x s~ (the rule of
+ * order q_c on both triangles) and the nearfield blocks (order q_r, touching
+ * pairs by Sauter-Schwab with q_s points per variable) are assembled once by
+ * the pair-wise kernels above and stored; the product is FP64. */
+typedef struct gca_lin_h2_s *gca_lin_h2;
+
+/* Builds the approximation.  mesh: host arrays (copied).  leaf: vertices per
+ * leaf cluster, 1..64.  p: eta, eps, omega_scale, green_m, q_A, q_r, q_s,
+ * q_c (0: q_r), sym_rules, alloc / free / alloc_ctx as for gca_build (q_nr,
+ * ss_fp32 and serial are not used; q_r and q_c: 1..4, or 2, 3 with
+ * sym_rules).  Synchronises the stream.  *out: a handle, gca_lin_destroy.
+ * Errors: GCA_EINVAL, GCA_EMESH, GCA_ENOMEM, GCA_EHIP, GCA_EINTERNAL (a pivot
+ * or leaf chunk outside the pair-wise kernels' limits). */
+gca_status gca_lin_build(const gca_mesh *mesh, int32_t leaf, const gca_params *p, void *stream, gca_lin_h2 *out);
+
+/* y = G~ x for the nodal basis: x, y device FP64 vectors of n_v entries in the
+ * original vertex order (y may not alias x); queued on the stream.  Calls
+ * on one handle share its work vectors: do not overlap them.
+ * Errors: GCA_EINVAL, GCA_EHIP. */
+gca_status gca_lin_matvec(gca_lin_h2 h, const double *x, double *y, void *stream);
+
+/* info[8] = {n_v, clusters, coupling blocks, nearfield blocks (both
+ * orientations), largest rank, sum of the ranks, stored coupling entries,
+ * stored nearfield entries}.  Errors: GCA_EINVAL. */
+gca_status gca_lin_info(gca_lin_h2 h, int64_t *info);
+
+/* Host arrays: perm[n_v] (cluster position -> vertex id), ranks[clusters]
+ * (pre-order), pivots[sum of ranks] (vertex ids, cluster by cluster in
+ * pre-order, each in pivot order).  Errors: GCA_EINVAL. */
+gca_status gca_lin_export(gca_lin_h2 h, int32_t *perm, int32_t *ranks, int32_t *pivots);
+
+/* Frees the handle and its device memory (synchronises the device). */
+void gca_lin_destroy(gca_lin_h2 h);
+
 #ifdef __cplusplus
 }
 #endif

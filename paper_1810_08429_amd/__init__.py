@@ -42,7 +42,7 @@ EXPORTED = [
     "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
     "gca_block_entries", "gca_dl_entries",
     "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks", "gca_coll_blocks",
-    "gca_curved_entries",
+    "gca_curved_entries", "gca_lin_build", "gca_lin_matvec", "gca_lin_info", "gca_lin_export", "gca_lin_destroy",
 ]
 
 
@@ -139,6 +139,12 @@ def lib():
     L.gca_lin_blocks.argtypes = [P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
     L.gca_coll_blocks.argtypes = [P, P, P, P, P, P, I32, P, P, P, I32, I64, I32, I32, I32, P, P, P]
     L.gca_curved_entries.argtypes = [P, P, I64, P, P, I64, I32, I32, I32, I32, I32, P, P]
+    L.gca_lin_build.argtypes = [P, I32, P, P, P]
+    L.gca_lin_matvec.argtypes = [P, P, P, P]
+    L.gca_lin_info.argtypes = [P, P]
+    L.gca_lin_export.argtypes = [P, P, P, P]
+    L.gca_lin_destroy.argtypes = [P]
+    L.gca_lin_destroy.restype = None
     L.gca_destroy.argtypes = [P]
     L.gca_destroy.restype = None
     L.gca_last_error.argtypes = []
@@ -148,7 +154,8 @@ def lib():
                  "gca_entries", "gca_basis_sizes", "gca_basis_export", "gca_stats", "gca_phase_times",
                  "gca_solve_refined", "gca_update_geometry", "h2_bilinear_grad", "gca_store_blocks", "gca_energy", "gca_energy_noalloc",
                  "gca_block_entries", "gca_dl_entries", "gca_lin_vertex_triangles", "gca_lin_merge", "gca_lin_blocks",
-                 "gca_coll_blocks", "gca_curved_entries"):
+                 "gca_coll_blocks", "gca_curved_entries", "gca_lin_build", "gca_lin_matvec", "gca_lin_info",
+                 "gca_lin_export"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -255,6 +262,60 @@ def _close_live_handles():
             H.close()
         except Exception:
             pass
+
+
+class LinH2:
+    """GCA-H^2 approximation of the nodal-basis matrix (gca_lin_build): one
+    basis function per vertex; q_r / q_c / q_s / sym_rules of `params` are
+    the rules of the stored nearfield and coupling blocks."""
+
+    INFO = ("n", "clusters", "far_blocks", "near_blocks", "max_rank", "sum_rank", "far_entries", "near_entries")
+
+    def __init__(self, verts, tris, leaf=16, params: Params = None, stream=None):
+        self._m = _MeshArrays(verts, tris)
+        self.params = params or Params()
+        self.n = self._m.xyz.shape[0]
+        self.h = ctypes.c_void_p()
+        p = self.params._c()
+        _check(lib().gca_lin_build(ctypes.byref(self._m.c), int(leaf), ctypes.byref(p), _stream_ptr(stream),
+                                   ctypes.byref(self.h)))
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gca_lin_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matvec(self, x, stream=None):
+        """y = G~ x (FP64 cuda tensors of n_v entries, original vertex order)."""
+        import torch
+        assert x.dtype == torch.float64 and x.is_cuda and x.dim() == 1 and x.shape[0] == self.n
+        x = x.contiguous()
+        y = torch.empty_like(x)
+        _check(lib().gca_lin_matvec(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                    _stream_ptr(stream)))
+        return y
+
+    def info(self):
+        a = np.zeros(8, dtype=np.int64)
+        _check(lib().gca_lin_info(self.h, a.ctypes.data))
+        return dict(zip(self.INFO, (int(v) for v in a)))
+
+    def export(self):
+        """(perm, ranks, pivots per cluster as a list of vertex-id arrays)."""
+        inf = self.info()
+        perm = np.zeros(self.n, dtype=np.int32)
+        ranks = np.zeros(inf["clusters"], dtype=np.int32)
+        piv = np.zeros(max(inf["sum_rank"], 1), dtype=np.int32)
+        _check(lib().gca_lin_export(self.h, perm.ctypes.data, ranks.ctypes.data, piv.ctypes.data))
+        off = np.concatenate([[0], np.cumsum(ranks)])
+        return perm, ranks, [piv[off[c]:off[c + 1]] for c in range(len(ranks))]
 
 
 class H2:

@@ -22,8 +22,8 @@ BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["quad.hip", "basis.hip", "h2.hip", "solve.hip", "adjoint.hip", "grad.hip", "linear.hip",
                "noalloc.hip", "multi.hip", "colloc.hip",
-               "dlayer.hip", "curved.hip"]
-HOST_SOURCES = ["host.cpp", "capi.cpp"]
+               "dlayer.hip", "curved.hip", "lin_h2.hip"]
+HOST_SOURCES = ["host.cpp", "capi.cpp", "lin_h2.cpp"]
 
 
 def _hipcc():

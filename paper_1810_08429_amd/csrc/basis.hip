@@ -129,7 +129,7 @@ hipError_t launch_green_A(const double *qA, int PA, const double *box, const int
         hipLaunchKernelGGL((k_green_A<PP>), grid, blk, 0, s, qA, box, row_tri, row_cl, row_out, nrows, m, \
                            g, eta, omega_scale, A);                                                  \
         break;
-        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
+        CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36) CASE(64) CASE(100) CASE(144)
 #undef CASE
     default:
         return hipErrorInvalidValue;

@@ -142,7 +142,7 @@ gca_status build_basis(gca_h2_s *h, hipStream_t s)
 {
     const gca_params &p = h->prm;
     const int k = 6 * p.green_m * p.green_m, cols = 2 * k;
-    const int PA = p.q_A * p.q_A;
+    const int PA = h->PA_rows > 0 ? h->PA_rows : p.q_A * p.q_A;
     const auto &nodes = h->tree.nodes;
     const int nc = (int)h->nc;
     std::vector<std::vector<int32_t>> piv(nc);   // pivot positions per cluster
@@ -2014,6 +2014,19 @@ void gca_destroy(gca_h2 h)
 }  // extern "C"
 
 namespace gca {
+
+// Shared with the nodal-basis handle (lin_h2.cpp): the handle's device
+// memory, the parameter checks and the level-wise basis construction.
+gca_status handle_alloc(gca_h2_s *h, void **p, size_t bytes)
+{
+    char *q = nullptr;
+    GCA_TRY(dalloc(h, &q, bytes));
+    *p = q;
+    return GCA_OK;
+}
+void handle_free_all(gca_h2_s *h) { free_all(h); }
+gca_status params_check(const gca_params *p) { return check_params(p); }
+gca_status basis_build(gca_h2_s *h, hipStream_t s) { return build_basis(h, s); }
 
 gca_status energy_check(const gca_h2_s *h, const double *u, const double *e, const double *g, int32_t precision)
 {

@@ -111,6 +111,11 @@ struct gca_tree_s {
 namespace gca {
 
 gca_status tree_build(const Mesh &m, int32_t leaf, gca_tree_s &t);
+// The tree over the vertices (the nodal basis of Section 5): points the
+// vertices, boxes those of the supports (every triangle of T_v, given as the
+// CSR vt_ptr / vt); perm maps positions to vertex ids.
+gca_status tree_build_vertices(const Mesh &m, const std::vector<int64_t> &vt_ptr, const std::vector<int32_t> &vt,
+                               int32_t leaf, gca_tree_s &t);
 
 // Block partition (Section 2 admissibility) as symmetric halves.
 struct Blocks {
@@ -214,6 +219,8 @@ struct gca_h2_s {
     gca::Adjacency adj;
     gca::Blocks blk;
     gca::PairLists pl;
+
+    int32_t PA_rows = 0;             // Green-factor points per row if not q_A^2 (the nodal basis)
 
     // host copies of the basis structure
     std::vector<int32_t> rank;       // per cluster
@@ -520,5 +527,34 @@ struct EntryJobs {
 };
 hipError_t launch_entry_jobs(gca_h2_s *h, const EntryJobs &j, double *tmp64, float *tmp32, int precision,
                              hipStream_t s);
+
+// Shared with the nodal-basis handle (capi.cpp): device memory owned by the
+// handle until it is freed, the parameter checks, the level-wise basis
+// construction (rows per cluster from the tree, Green points from d_box,
+// PA_rows points per row in d_qA).
+gca_status handle_alloc(gca_h2_s *h, void **p, size_t bytes);
+void handle_free_all(gca_h2_s *h);
+gca_status params_check(const gca_params *p);
+gca_status basis_build(gca_h2_s *h, hipStream_t s);
+
+// Stored sub-blocks of the nodal-basis handle applied per target (lin_h2.hip):
+// target g (cluster tgt[g]) sums its sub-blocks sub_ptr[g] .. sub_ptr[g+1];
+// sub-block b: rows [row0, row0 + nr) of the target, G row-major nr x nc at
+// goff[b], columns src[srcoff[b] + j].  FAR: yh[piv_off[t] + i] = sum; else
+// the sum is added into y[perm[begin + i]] after V_t yh_t (the gather).
+struct LinApply {
+    int32_t ntarget = 0;
+    int32_t *tgt = nullptr;
+    int64_t *sub_ptr = nullptr;
+    int32_t *sub_meta = nullptr;   // 3 per sub-block: nr, nc, row0
+    int64_t *goff = nullptr, *srcoff = nullptr;
+    double *G = nullptr;
+};
+hipError_t launch_lin_far_apply(const gca_h2_s *h, const LinApply &a, const double *xh, double *yh, hipStream_t s);
+hipError_t launch_lin_gather(const gca_h2_s *h, const LinApply &a, const double *xp, const double *yh, double *y,
+                             hipStream_t s);
+// out[goff[b] + i nc + j] = in[b ld + i nc + j] for the nb sub-blocks of a batch
+hipError_t launch_lin_compact(const double *in, int64_t ld, int32_t nb, const int32_t *meta, const int64_t *goff,
+                              double *out, hipStream_t s);
 
 }  // namespace gca

@@ -161,12 +161,14 @@ gca_status build_adjacency(const Mesh &m, Adjacency &adj)
 
 namespace {
 
+// Items (triangles, or the vertices of the nodal basis) with a point each
+// (cent, the splitting coordinate) and the box of their support (sup: lo,
+// hi per item).
 struct TreeBuilder {
-    const Mesh &m;
     int32_t leaf;
     gca_tree_s &t;
-    std::vector<double> cent;   // nt x 3
-    std::vector<int32_t> tmp;
+    const std::vector<double> &cent;   // n x 3
+    const std::vector<double> &sup;    // n x 6
 
     void box_of(int32_t b, int32_t e, Node &nd)
     {
@@ -175,13 +177,10 @@ struct TreeBuilder {
             nd.hi[d] = -INFINITY;
         }
         for (int32_t p = b; p < e; ++p) {
-            int32_t tri = t.perm[p];
-            for (int k = 0; k < 3; ++k) {
-                const double *v = &m.xyz[3 * (int64_t)m.tri[3 * (int64_t)tri + k]];
-                for (int d = 0; d < 3; ++d) {
-                    nd.lo[d] = std::min(nd.lo[d], v[d]);
-                    nd.hi[d] = std::max(nd.hi[d], v[d]);
-                }
+            const double *bx = &sup[6 * (int64_t)t.perm[p]];
+            for (int d = 0; d < 3; ++d) {
+                nd.lo[d] = std::min(nd.lo[d], bx[d]);
+                nd.hi[d] = std::max(nd.hi[d], bx[3 + d]);
             }
         }
         double e0 = nd.hi[0] - nd.lo[0], e1 = nd.hi[1] - nd.lo[1], e2 = nd.hi[2] - nd.lo[2];
@@ -265,52 +264,91 @@ struct TreeBuilder {
 
 }  // namespace
 
-gca_status tree_build(const Mesh &m, int32_t leaf, gca_tree_s &t)
+// The tree over n items: median splits of the points, boxes of the supports
+// (leaves from their items' boxes, parents as the union of their sons' boxes;
+// min / max are exact, so this equals a direct scan).
+static void build_items(const std::vector<double> &cent, const std::vector<double> &sup, int64_t n, int32_t leaf,
+                        gca_tree_s &t)
 {
-    if (leaf < 1) return set_error(GCA_EINVAL, "leaf_size must be >= 1");
-    t.nt = m.nt;
-    t.nv = m.nv;
-    t.leaf = leaf;
-    t.perm.resize(m.nt);
+    t.perm.resize(n);
     std::iota(t.perm.begin(), t.perm.end(), 0);
     t.nodes.clear();
-    t.nodes.reserve(4 * (m.nt / std::max(1, leaf / 2) + 1));
+    t.nodes.reserve(4 * (n / std::max(1, leaf / 2) + 1));
     t.depth = 0;
-    TreeBuilder tb{m, leaf, t, {}, {}};
-    tb.cent.resize(3 * m.nt);
-    parallel_for(m.nt, [&](int64_t i0, int64_t i1) {
-        for (int64_t i = i0; i < i1; ++i)
-            for (int d = 0; d < 3; ++d) {
-                double v0 = m.xyz[3 * (int64_t)m.tri[3 * i] + d];
-                double v1 = m.xyz[3 * (int64_t)m.tri[3 * i + 1] + d];
-                double v2 = m.xyz[3 * (int64_t)m.tri[3 * i + 2] + d];
-                tb.cent[3 * i + d] = ((v0 + v1) + v2) / 3.0;
-            }
-    });
+    TreeBuilder tb{leaf, t, cent, sup};
     int par = 0;
-    while (par < 4 && (1 << (par + 1)) <= host_threads() && (m.nt >> par) > 8 * (int64_t)leaf) ++par;
-    tb.rec(0, (int32_t)m.nt, 0, -1, par, t.nodes);
+    while (par < 4 && (1 << (par + 1)) <= host_threads() && (n >> par) > 8 * (int64_t)leaf) ++par;
+    tb.rec(0, (int32_t)n, 0, -1, par, t.nodes);
     for (const Node &nd : t.nodes) t.depth = std::max(t.depth, nd.level);
-    // boxes of the supports: leaves from their vertices, parents as the union of
-    // their sons' boxes (min / max are exact, so this equals a direct scan)
     parallel_for((int64_t)t.nodes.size(), [&](int64_t c0, int64_t c1) {
         for (int64_t c = c0; c < c1; ++c)
             if (t.nodes[c].son[0] < 0) tb.box_of(t.nodes[c].begin, t.nodes[c].end, t.nodes[c]);
     });
     for (int64_t c = (int64_t)t.nodes.size() - 1; c >= 0; --c) {
         Node &nd = t.nodes[c];
-        if (nd.son[0] < 0) {
-            continue;
-        } else {
-            const Node &a = t.nodes[nd.son[0]], &b = t.nodes[nd.son[1]];
-            for (int d = 0; d < 3; ++d) {
-                nd.lo[d] = std::min(a.lo[d], b.lo[d]);
-                nd.hi[d] = std::max(a.hi[d], b.hi[d]);
-            }
-            double e0 = nd.hi[0] - nd.lo[0], e1 = nd.hi[1] - nd.lo[1], e2 = nd.hi[2] - nd.lo[2];
-            nd.diam = std::sqrt((e0 * e0 + e1 * e1) + e2 * e2);
+        if (nd.son[0] < 0) continue;
+        const Node &a = t.nodes[nd.son[0]], &b = t.nodes[nd.son[1]];
+        for (int d = 0; d < 3; ++d) {
+            nd.lo[d] = std::min(a.lo[d], b.lo[d]);
+            nd.hi[d] = std::max(a.hi[d], b.hi[d]);
         }
+        double e0 = nd.hi[0] - nd.lo[0], e1 = nd.hi[1] - nd.lo[1], e2 = nd.hi[2] - nd.lo[2];
+        nd.diam = std::sqrt((e0 * e0 + e1 * e1) + e2 * e2);
     }
+}
+
+gca_status tree_build(const Mesh &m, int32_t leaf, gca_tree_s &t)
+{
+    if (leaf < 1) return set_error(GCA_EINVAL, "leaf_size must be >= 1");
+    t.nt = m.nt;
+    t.nv = m.nv;
+    t.leaf = leaf;
+    // triangle centroids ((v0 + v1) + v2) / 3 and the boxes of the triangles
+    std::vector<double> cent(3 * m.nt), sup(6 * m.nt);
+    parallel_for(m.nt, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double v0 = m.xyz[3 * (int64_t)m.tri[3 * i] + d];
+                double v1 = m.xyz[3 * (int64_t)m.tri[3 * i + 1] + d];
+                double v2 = m.xyz[3 * (int64_t)m.tri[3 * i + 2] + d];
+                cent[3 * i + d] = ((v0 + v1) + v2) / 3.0;
+                sup[6 * i + d] = std::min(v0, std::min(v1, v2));
+                sup[6 * i + 3 + d] = std::max(v0, std::max(v1, v2));
+            }
+    });
+    build_items(cent, sup, m.nt, leaf, t);
+    t.mesh_xyz = m.xyz;
+    t.mesh_tri = m.tri;
+    return GCA_OK;
+}
+
+gca_status tree_build_vertices(const Mesh &m, const std::vector<int64_t> &vt_ptr, const std::vector<int32_t> &vt,
+                               int32_t leaf, gca_tree_s &t)
+{
+    if (leaf < 1) return set_error(GCA_EINVAL, "leaf_size must be >= 1");
+    t.nt = m.nt;
+    t.nv = m.nv;
+    t.leaf = leaf;
+    // the vertex itself, and the box of every triangle of its support
+    std::vector<double> sup(6 * m.nv);
+    parallel_for(m.nv, [&](int64_t v0, int64_t v1) {
+        for (int64_t v = v0; v < v1; ++v) {
+            double *bx = &sup[6 * v];
+            for (int d = 0; d < 3; ++d) {
+                bx[d] = INFINITY;
+                bx[3 + d] = -INFINITY;
+            }
+            for (int64_t q = vt_ptr[v]; q < vt_ptr[v + 1]; ++q)
+                for (int k = 0; k < 3; ++k) {
+                    const double *x = &m.xyz[3 * (int64_t)m.tri[3 * (int64_t)vt[q] + k]];
+                    for (int d = 0; d < 3; ++d) {
+                        bx[d] = std::min(bx[d], x[d]);
+                        bx[3 + d] = std::max(bx[3 + d], x[d]);
+                    }
+                }
+        }
+    });
+    build_items(m.xyz, sup, m.nv, leaf, t);
     t.mesh_xyz = m.xyz;
     t.mesh_tri = m.tri;
     return GCA_OK;
