@@ -184,6 +184,8 @@ def parse():
                     help="timed products per precision in stored-block mode (0 disables it)")
     ap.add_argument("--grad-steps", type=int, default=3,
                     help="timed calls of the energy gradient per precision (0 disables it)")
+    ap.add_argument("--nodal-level", type=int, default=7,
+                    help="sphere level of the nodal-basis H2 timing leg (0: skip)")
     ap.add_argument("--lin-blocks", type=int, default=16384,
                     help="linear-basis blocks (32 x 32 vertices) in the piecewise-linear leg (0 disables it)")
     ap.add_argument("--omega", type=float, default=None, help="override the workload's omega margin")
@@ -203,6 +205,71 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
+
+
+def lin_h2(gca, torch, level_time, level_err=5, steps=10, leaf=32):
+    """GCA-H^2 with the nodal basis (gca_lin_build / gca_lin_matvec): the
+    approximation error of the product at level `level_err` against the same
+    handle built with eta -> 0 (every block stored as nearfield: the nodal
+    Galerkin matrix itself), for x ~ N(0,1), the all-ones vector and x3; then
+    build time, storage and the product time (HIP events) at level
+    `level_time`."""
+    import synth
+    prm = dict(eta=2.0, eps=1e-5, omega_scale=0.25, green_m=4, q_A=2, q_r=3, q_nr=3, q_s=4, q_c=2, sym_rules=1)
+    res = {"workload": f"unit icosphere, nodal basis (one function per vertex), leaf {leaf}, eta 2, Green order 4, "
+                       f"ACA eps 1e-5, Green factor rule q_A 2, symmetric 6-point rule for the nearfield pairs and "
+                       f"3-point rule for the coupling entries, Sauter-Schwab q_s 4 for touching pairs; FP64",
+           "params": prm}
+    m = synth.icosphere(level_err)
+    P = gca.Params(**prm)
+    H = gca.LinH2(m.verts, m.tris, leaf=leaf, params=P)
+    D = gca.LinH2(m.verts, m.tris, leaf=leaf, params=gca.Params(**{**prm, "eta": 1e-9}))
+    X = error_vectors_nodal(m, synth.rhs_normal(m.nv, seed=0))
+    errs = {}
+    for k, name in enumerate(("x_normal", "ones", "x3")):
+        x = torch.as_tensor(np.ascontiguousarray(X[:, k])).cuda()
+        y, yd = H.matvec(x), D.matvec(x)
+        errs[name] = float((y - yd).abs().max() / yd.abs().max())
+    res["error"] = {"level": level_err, "n": m.nv, "reference": "the same handle with eta -> 0 (all blocks stored "
+                    "dense: the nodal Galerkin matrix with the same rules)", "max_rel": max(errs.values()),
+                    "per_vector": errs, "info": H.info()}
+    del D
+    torch.cuda.empty_cache()
+    m = synth.icosphere(level_time)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = gca.LinH2(m.verts, m.tris, leaf=leaf, params=P)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    x = torch.as_tensor(synth.rhs_normal(m.nv, seed=0)).cuda()
+    for _ in range(2):
+        H.matvec(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        H.matvec(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    inf = H.info()
+    # algorithmic bytes of a product: the stored entries once, the vectors and bases around them
+    nbytes = 8 * (inf["far_entries"] + inf["near_entries"])
+    res["time"] = {"level": level_time, "n": m.nv, "build_s": build_s, "ms_per_product": ms, "DoF_per_s": m.nv / (ms * 1e-3),
+                   "info": inf, "stored_bytes": nbytes,
+                   "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_BYTES_PER_S / 1e9,
+                                "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / HBM_BYTES_PER_S,
+                                "what": "stored coupling and nearfield entries read once per product (FP64)"}}
+    print(f"[bench] nodal H2: error {res['error']['max_rel']:.2e} at level {level_err}; level {level_time} "
+          f"(n = {m.nv}): build {build_s:.2f} s, product {ms:.3f} ms, {nbytes / 1e9:.2f} GB stored, "
+          f"{res['time']['roofline']['frac']:.1%} of HBM", file=sys.stderr, flush=True)
+    return res
+
+
+def error_vectors_nodal(mesh, x_host):
+    """The error metric's vectors for the nodal basis: x ~ N(0,1), the all-ones
+    vector and the vertex x3 coordinate."""
+    return np.stack([x_host, np.ones(mesh.nv), mesh.verts[:, 2]], axis=1)
 
 
 def linear_basis(gca, torch, mesh, nblk, steps, warmup, q=2, sym=True, seed=7):
@@ -637,6 +704,7 @@ def main():
     linear = None
     if a.lin_blocks > 0:
         linear = linear_basis(gca, torch, mesh, a.lin_blocks, max(a.stored_steps, 3), 2)
+    nodal = lin_h2(gca, torch, a.nodal_level) if a.nodal_level > 0 else None
 
     phases = gca.PHASES
     mean_mixed = dict(zip(phases, ph_mixed.mean(axis=0).tolist()))
@@ -733,6 +801,7 @@ def main():
         "energy_gradient": grad,
         "stored_blocks": stored,
         "linear_basis": linear,
+        "nodal_h2": nodal,
         "double_layer": dl,
         "curved": curv,
         "mixed_over_fp64": dt_fp64 / dt_mixed,

@@ -537,23 +537,26 @@ void handle_free_all(gca_h2_s *h);
 gca_status params_check(const gca_params *p);
 gca_status basis_build(gca_h2_s *h, hipStream_t s);
 
-// Stored sub-blocks of the nodal-basis handle applied per target (lin_h2.hip):
-// target g (cluster tgt[g]) sums its sub-blocks sub_ptr[g] .. sub_ptr[g+1];
-// sub-block b: rows [row0, row0 + nr) of the target, G row-major nr x nc at
-// goff[b], columns src[srcoff[b] + j].  FAR: yh[piv_off[t] + i] = sum; else
-// the sum is added into y[perm[begin + i]] after V_t yh_t (the gather).
+// Stored sub-blocks of the nodal-basis handle (lin_h2.hip): sub-block b has
+// rows [row0, row0 + nr) of its target, G column-major nr x nc at goff[b],
+// columns src[srcoff[b] + j]; its row sums go to part[poff[b] + i].  Target g
+// (cluster tgt[g]) then adds those of its sub-blocks sub_ptr[g] ..
+// sub_ptr[g+1] in order.  FAR: yh[piv_off[t] + i] = sum; else y[perm[begin +
+// i]] = V_t yh_t + sum (the gather).
 struct LinApply {
     int32_t ntarget = 0;
+    int64_t nsub = 0;
     int32_t *tgt = nullptr;
     int64_t *sub_ptr = nullptr;
     int32_t *sub_meta = nullptr;   // 3 per sub-block: nr, nc, row0
     int64_t *goff = nullptr, *srcoff = nullptr;
-    double *G = nullptr;
+    int64_t *poff = nullptr;       // per sub-block: its rows' partial sums in part
+    double *G = nullptr, *part = nullptr;
 };
-hipError_t launch_lin_far_apply(const gca_h2_s *h, const LinApply &a, const double *xh, double *yh, hipStream_t s);
-hipError_t launch_lin_gather(const gca_h2_s *h, const LinApply &a, const double *xp, const double *yh, double *y,
-                             hipStream_t s);
-// out[goff[b] + i nc + j] = in[b ld + i nc + j] for the nb sub-blocks of a batch
+// the row sums of every sub-block (one wavefront each), then per target
+hipError_t launch_lin_sub(const LinApply &a, const double *src, hipStream_t s);
+hipError_t launch_lin_reduce(const gca_h2_s *h, const LinApply &a, bool far, double *yh, double *y, hipStream_t s);
+// out[goff[b] + j nr + i] = in[b ld + i nc + j] for the nb sub-blocks of a batch (transposed)
 hipError_t launch_lin_compact(const double *in, int64_t ld, int32_t nb, const int32_t *meta, const int64_t *goff,
                               double *out, hipStream_t s);
 

@@ -27,6 +27,10 @@ struct gca_lin_h2_s {
     LinApply far, near;
     int64_t n_far_store = 0, n_near_store = 0;
     double *d_xp = nullptr, *d_xh = nullptr, *d_yh = nullptr;
+    // the transform chain and the coupling blocks run on s_side beside the
+    // nearfield blocks on the caller's stream
+    hipStream_t s_side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -271,9 +275,9 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
         for (size_t g = 0; g < tg.size(); ++g) tpos[tg[g]] = (int32_t)g;
         std::vector<std::vector<int32_t>> per(tg.size());
         for (size_t b = 0; b < bt.size(); ++b) per[tpos[bt[b]]].push_back(bs[b]);
-        std::vector<int64_t> sub_ptr{0}, goff, srcoff;
+        std::vector<int64_t> sub_ptr{0}, goff, srcoff, poff;
         std::vector<int32_t> meta, br, bc;
-        int64_t off = 0;
+        int64_t off = 0, prow = 0;
         for (size_t g = 0; g < tg.size(); ++g) {
             const int t = tg[g];
             std::sort(per[g].begin(), per[g].end());
@@ -285,14 +289,19 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
                         br.push_back(set0[t] + (int32_t)rb);
                         bc.push_back(set0[u] + (int32_t)cb);
                         goff.push_back(off);
+                        poff.push_back(prow);
                         srcoff.push_back((farb ? h->piv_off[u] : nodes[u].begin) + ch[u][cb]);
                         off += (int64_t)nr * ncol;
+                        prow += nr;
                     }
             sub_ptr.push_back((int64_t)goff.size());
         }
         nstore = off;
         A.ntarget = (int32_t)tg.size();
+        A.nsub = (int64_t)goff.size();
         GCA_TRY(put(h, &A.tgt, tg, s));
+        GCA_TRY(put(h, &A.poff, poff, s));
+        GCA_TRY(alloc_n(h, &A.part, (size_t)prow));
         GCA_TRY(put(h, &A.sub_ptr, sub_ptr, s));
         GCA_TRY(put(h, &A.sub_meta, meta, s));
         GCA_TRY(put(h, &A.goff, goff, s));
@@ -324,8 +333,21 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
     GCA_TRY(alloc_n(h, &L->d_xp, (size_t)nv));
     GCA_TRY(alloc_n(h, &L->d_xh, (size_t)std::max<int64_t>(h->n_piv, 1)));
     GCA_TRY(alloc_n(h, &L->d_yh, (size_t)std::max<int64_t>(h->n_piv, 1)));
+    GCA_HIP_TRY(hipStreamCreateWithFlags(&L->s_side, hipStreamNonBlocking));
+    GCA_HIP_TRY(hipEventCreateWithFlags(&L->ev_fork, hipEventDisableTiming));
+    GCA_HIP_TRY(hipEventCreateWithFlags(&L->ev_join, hipEventDisableTiming));
     GCA_HIP_TRY(hipStreamSynchronize(s));
     return GCA_OK;
+}
+
+void destroy_lin(gca_lin_h2_s *L)
+{
+    (void)hipDeviceSynchronize();
+    if (L->ev_fork) (void)hipEventDestroy(L->ev_fork);
+    if (L->ev_join) (void)hipEventDestroy(L->ev_join);
+    if (L->s_side) (void)hipStreamDestroy(L->s_side);
+    handle_free_all(&L->h);
+    delete L;
 }
 
 }  // namespace
@@ -342,8 +364,7 @@ gca_status gca_lin_build(const gca_mesh *mesh, int32_t leaf, const gca_params *p
     if (!L) return set_error(GCA_ENOMEM, "out of host memory");
     const gca_status st = build_lin(mesh, leaf, p, (hipStream_t)stream, L);
     if (st != GCA_OK) {
-        handle_free_all(&L->h);
-        delete L;
+        destroy_lin(L);
         return st;
     }
     *out = L;
@@ -356,11 +377,18 @@ gca_status gca_lin_matvec(gca_lin_h2 L, const double *x, double *y, void *stream
     if (!L || !x || !y) return set_error(GCA_EINVAL, "NULL pointer");
     gca_h2_s *h = &L->h;
     const hipStream_t s = (hipStream_t)stream;
+    const hipStream_t c = L->s_side;
     GCA_HIP_TRY(launch_permute_in<double>(x, false, h->d_perm, h->n, L->d_xp, nullptr, s));
-    GCA_HIP_TRY(launch_forward<double>(h, L->d_xp, L->d_xh, s));
-    GCA_HIP_TRY(launch_lin_far_apply(h, L->far, L->d_xh, L->d_yh, s));
-    GCA_HIP_TRY(launch_backward<double>(h, L->d_yh, s));
-    GCA_HIP_TRY(launch_lin_gather(h, L->near, L->d_xp, L->d_yh, y, s));
+    GCA_HIP_TRY(hipEventRecord(L->ev_fork, s));
+    GCA_HIP_TRY(hipStreamWaitEvent(c, L->ev_fork, 0));
+    GCA_HIP_TRY(launch_forward<double>(h, L->d_xp, L->d_xh, c));
+    GCA_HIP_TRY(launch_lin_sub(L->far, L->d_xh, c));
+    GCA_HIP_TRY(launch_lin_reduce(h, L->far, true, L->d_yh, nullptr, c));
+    GCA_HIP_TRY(launch_backward<double>(h, L->d_yh, c));
+    GCA_HIP_TRY(hipEventRecord(L->ev_join, c));
+    GCA_HIP_TRY(launch_lin_sub(L->near, L->d_xp, s));
+    GCA_HIP_TRY(hipStreamWaitEvent(s, L->ev_join, 0));
+    GCA_HIP_TRY(launch_lin_reduce(h, L->near, false, L->d_yh, y, s));
     return GCA_OK;
 }
 
@@ -390,9 +418,7 @@ gca_status gca_lin_export(gca_lin_h2 L, int32_t *perm, int32_t *ranks, int32_t *
 
 void gca_lin_destroy(gca_lin_h2 L)
 {
-    if (!L) return;
-    handle_free_all(&L->h);
-    delete L;
+    if (L) destroy_lin(L);
 }
 
 }  // extern "C"

@@ -10,73 +10,98 @@
 namespace gca {
 namespace {
 
-// sum over the target's sub-blocks (stored order) that cover row i
-__device__ __forceinline__ double sub_rows(const LinApply &a, int64_t b0, int64_t b1, int i, const double *src)
+constexpr int AW = 4;          // wavefronts per workgroup: one sub-block each
+
+// Row sums of one sub-block per wavefront: entries column-major (G[j nr + i]:
+// a column is one coalesced load); up to 32 rows, the two half-wavefronts
+// take the even and the odd columns, four columns per lane in flight.
+__global__ void __launch_bounds__(64 * AW) k_lin_sub(LinApply a, const double *src)
 {
-    double acc = 0.0;
-    for (int64_t b = b0; b < b1; ++b) {
-        const int nr = a.sub_meta[3 * b], nc = a.sub_meta[3 * b + 1], row0 = a.sub_meta[3 * b + 2];
-        if (i < row0 || i >= row0 + nr) continue;
-        const double *G = a.G + a.goff[b] + (int64_t)(i - row0) * nc;
-        const double *x = src + a.srcoff[b];
-        for (int j = 0; j < nc; ++j) acc += G[j] * x[j];
+    const int64_t b = (int64_t)blockIdx.x * AW + (threadIdx.x >> 6);
+    if (b >= a.nsub) return;
+    const int lane = threadIdx.x & 63;
+    const int nr = a.sub_meta[3 * b], nc = a.sub_meta[3 * b + 1];
+    const double *G = a.G + a.goff[b];
+    const double *x = src + a.srcoff[b];
+    const int hs = nr <= 32 ? 2 : 1;
+    const int r = hs == 2 ? (lane & 31) : lane, h = hs == 2 ? (lane >> 5) : 0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (r < nr) {
+        int j = h;
+        for (; j + 3 * hs < nc; j += 4 * hs) {
+            a0 += G[(int64_t)j * nr + r] * x[j];
+            a1 += G[(int64_t)(j + hs) * nr + r] * x[j + hs];
+            a2 += G[(int64_t)(j + 2 * hs) * nr + r] * x[j + 2 * hs];
+            a3 += G[(int64_t)(j + 3 * hs) * nr + r] * x[j + 3 * hs];
+        }
+        for (; j < nc; j += hs) a0 += G[(int64_t)j * nr + r] * x[j];
     }
-    return acc;
+    double v = (a0 + a1) + (a2 + a3);
+    if (hs == 2) v += __shfl_xor(v, 32);
+    if (r < nr && h == 0) a.part[a.poff[b] + r] = v;
 }
 
-// one workgroup per cluster, thread per pivot: yh_t = sum_s G|t~ x s~ xh_s
-__global__ void __launch_bounds__(128) k_lin_far_apply(LinApply a, const int32_t *rank, const int64_t *piv_off,
-                                                       const double *xh, double *yh)
+// One workgroup per target, thread per row: the partial sums of the target's
+// sub-blocks that cover the row, in stored order.  FAR: yh_t = the sum; else
+// y|t = V_t yh_t + the sum, written in the original vertex order.
+template <bool FAR>
+__global__ void __launch_bounds__(128) k_lin_reduce(LinApply a, const int32_t *node, const int32_t *rank,
+                                                    const int64_t *piv_off, const int64_t *v_off, const double *Vt,
+                                                    const int32_t *perm, double *yh, double *y)
 {
     const int g = blockIdx.x;
     const int t = a.tgt[g];
-    const int r = rank[t];
-    for (int i = threadIdx.x; i < r; i += blockDim.x)
-        yh[piv_off[t] + i] = sub_rows(a, a.sub_ptr[g], a.sub_ptr[g + 1], i, xh);
-}
-
-// one workgroup per leaf, thread per row: y = V_t yh_t + the nearfield blocks,
-// written in the original vertex order
-__global__ void __launch_bounds__(64) k_lin_gather(LinApply a, const int32_t *node, const int32_t *rank,
-                                                   const int64_t *piv_off, const int64_t *v_off, const double *Vt,
-                                                   const int32_t *perm, const double *xp, const double *yh,
-                                                   double *y)
-{
-    const int g = blockIdx.x;
-    const int t = a.tgt[g];
-    const int b = node[5 * t], nr = node[5 * t + 1] - b, r = rank[t];
-    const double *Vc = Vt + v_off[t];
-    const double *yc = yh + piv_off[t];
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+    const int b0 = node[5 * t];
+    const int nrow = FAR ? rank[t] : node[5 * t + 1] - b0;
+    const int64_t s0 = a.sub_ptr[g], s1 = a.sub_ptr[g + 1];
+    for (int i = threadIdx.x; i < nrow; i += blockDim.x) {
         double acc = 0.0;
-        for (int k = 0; k < r; ++k) acc += Vc[(int64_t)k * nr + i] * yc[k];
-        acc += sub_rows(a, a.sub_ptr[g], a.sub_ptr[g + 1], i, xp);
-        y[perm[b + i]] = acc;
+        for (int64_t b = s0; b < s1; ++b) {
+            const int nr = a.sub_meta[3 * b], row0 = a.sub_meta[3 * b + 2];
+            if (i >= row0 && i < row0 + nr) acc += a.part[a.poff[b] + i - row0];
+        }
+        if (FAR) {
+            yh[piv_off[t] + i] = acc;
+        } else {
+            const double *Vc = Vt + v_off[t];
+            const double *yc = yh + piv_off[t];
+            double v = 0.0;
+            for (int k = 0; k < rank[t]; ++k) v += Vc[(int64_t)k * nrow + i] * yc[k];
+            y[perm[b0 + i]] = v + acc;
+        }
     }
 }
 
+// sub-block b of a batch (row-major nr x nc at in + b ld) into the store,
+// column-major at out + goff[b]
 __global__ void k_lin_compact(const double *in, int64_t ld, const int32_t *meta, const int64_t *goff, double *out)
 {
     const int b = blockIdx.x;
-    const int n = meta[3 * b] * meta[3 * b + 1];
-    for (int e = threadIdx.x; e < n; e += blockDim.x) out[goff[b] + e] = in[(int64_t)b * ld + e];
+    const int nr = meta[3 * b], nc = meta[3 * b + 1];
+    for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
+        const int i = e / nc, j = e - i * nc;
+        out[goff[b] + (int64_t)j * nr + i] = in[(int64_t)b * ld + e];
+    }
 }
 
 }  // namespace
 
-hipError_t launch_lin_far_apply(const gca_h2_s *h, const LinApply &a, const double *xh, double *yh, hipStream_t s)
+hipError_t launch_lin_sub(const LinApply &a, const double *src, hipStream_t s)
 {
-    if (a.ntarget == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lin_far_apply, dim3(a.ntarget), dim3(128), 0, s, a, h->d_rank, h->d_piv_off, xh, yh);
+    if (a.nsub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lin_sub, dim3((unsigned)((a.nsub + AW - 1) / AW)), dim3(64 * AW), 0, s, a, src);
     return hipGetLastError();
 }
 
-hipError_t launch_lin_gather(const gca_h2_s *h, const LinApply &a, const double *xp, const double *yh, double *y,
-                             hipStream_t s)
+hipError_t launch_lin_reduce(const gca_h2_s *h, const LinApply &a, bool far, double *yh, double *y, hipStream_t s)
 {
     if (a.ntarget == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lin_gather, dim3(a.ntarget), dim3(64), 0, s, a, h->d_node, h->d_rank, h->d_piv_off,
-                       h->d_v_off, h->d_Vt, h->d_perm, xp, yh, y);
+    if (far)
+        hipLaunchKernelGGL(k_lin_reduce<true>, dim3(a.ntarget), dim3(128), 0, s, a, h->d_node, h->d_rank,
+                           h->d_piv_off, h->d_v_off, h->d_Vt, h->d_perm, yh, y);
+    else
+        hipLaunchKernelGGL(k_lin_reduce<false>, dim3(a.ntarget), dim3(128), 0, s, a, h->d_node, h->d_rank,
+                           h->d_piv_off, h->d_v_off, h->d_Vt, h->d_perm, yh, y);
     return hipGetLastError();
 }
 
