@@ -193,6 +193,27 @@ def test_lin_vertex_triangles_host(gca):
     assert list(off) == [0] * 5 and lst.size == 0
 
 
+def test_nodal_h2_build_validates_arguments(gca):
+    # every check below runs on the host before any device memory is touched
+    import synth
+    m = synth.icosphere(1)
+    L = ctypes.CDLL(gca.LIB_PATH)
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    L.gca_lin_build.argtypes = [P, I32, P, P, P]
+    mesh = gca._MeshArrays(m.verts, m.tris)
+    out = ctypes.c_void_p()
+    ok = gca.Params(allocator=None)
+    call = lambda leaf, prm, o=ctypes.byref(out), me=ctypes.byref(mesh.c): L.gca_lin_build(
+        me, leaf, ctypes.byref(prm._c()), None, o)
+    assert call(0, ok) == -1                                   # leaf below 1
+    assert call(65, ok) == -1                                  # leaf above the 64-vertex chunks
+    assert call(16, gca.Params(q_r=5, allocator=None)) == -1   # 25-point rule: beyond the block kernels
+    assert call(16, gca.Params(q_c=3, sym_rules=1, q_r=4, q_nr=3, allocator=None)) == -1
+    assert call(16, ok, o=None) == -1                          # NULL out
+    assert call(16, ok, me=None) == -1                         # NULL mesh
+    assert not out.value
+
+
 def test_curved_entry_point_validates_arguments(gca):
     L = ctypes.CDLL(gca.LIB_PATH)
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
