@@ -475,30 +475,57 @@ def ms_fmt(r):
     return ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in r.items() if isinstance(v, dict) and "ms" in v)
 
 
-def double_layer(gca, torch, H, mesh, nrows, seed=11):
+# FP64 ceiling of one 4D Sauter-Schwab point of the double-layer touching
+# pairs: the map and its weight (14 slots), the point difference (9), the
+# kernel n . d |d|^-3 with the refined rsqrt and its quarter-rate v_rsq_f64
+# (15), the weighted sum (1): 39 slots.
+DL_SS_EVALS_PER_S = FP64_LANE_OPS_PER_S / 39.0
+
+
+def double_layer(gca, torch, H, mesh, nrows, seed=11, steps=3):
     """Double-layer Galerkin entries (gca_dl_entries) on the workload mesh: the
     touching pairs (common vertex or edge) of nrows random triangles, both
-    orders, and as many random (regular) pairs; wall time of each call, which
-    includes the host classification and the transfers."""
+    orders, and as many random pairs; HIP events on the current stream around
+    each call (classification and integration on the device)."""
     rng = np.random.default_rng(seed)
     rows = rng.choice(mesh.nt, nrows, replace=False)
     Ti, Tj = touching_pairs(mesh, rows)
     Ri = rng.integers(0, mesh.nt, Ti.size)
     Rj = rng.integers(0, mesh.nt, Ti.size)
+    shared = (mesh.tris[Ti][:, :, None] == mesh.tris[Tj][:, None, :]).sum(axis=(1, 2))
+    qs = H.params.q_s
+    evals = int(5 * np.count_nonzero(shared == 2) + 2 * np.count_nonzero(shared == 1)) * qs ** 4
     res = {"workload": f"touching pairs of {nrows} random triangles in both orders and as many random pairs "
-                       f"(seed {seed}); FP64; wall time of one gca_dl_entries call each (host classification, "
-                       f"job upload, kernel, read-back)"}
+                       f"(seed {seed}); FP64; HIP events around one gca_dl_entries call each"}
     for name, (a, b) in (("touching", (Ti, Tj)), ("random", (Ri, Rj))):
-        H.dl_entries(a[:1000], b[:1000])
+        I = torch.as_tensor(a.astype(np.int32)).cuda()
+        J = torch.as_tensor(b.astype(np.int32)).cuda()
+        out = torch.empty(I.numel(), dtype=torch.float64, device="cuda")
+        call = lambda: gca._check(gca.lib().gca_dl_entries(H.h, ctypes_vp(I), ctypes_vp(J), I.numel(),
+                                                           ctypes_vp(out), gca._stream_ptr(None)))
+        call()
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        H.dl_entries(a, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            call()
+        e1.record()
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        res[name] = {"pairs": int(a.size), "s": dt, "entries_per_s": a.size / dt}
-    print(f"[bench] double layer: {res['touching']['pairs']} touching pairs in {res['touching']['s']:.3f} s, "
-          f"{res['random']['pairs']} random pairs in {res['random']['s']:.3f} s", file=sys.stderr, flush=True)
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"pairs": int(a.size), "ms": ms, "entries_per_s": a.size / (ms * 1e-3)}
+    ach = evals / (res["touching"]["ms"] * 1e-3)
+    res["touching"]["roofline"] = {"bound": "fp64 alu", "achieved": ach, "peak": DL_SS_EVALS_PER_S,
+                                   "unit": "evaluations/s", "frac": ach / DL_SS_EVALS_PER_S, "evaluations": evals,
+                                   "kernel": "k_dl_pairs"}
+    print(f"[bench] double layer: {res['touching']['pairs']} touching pairs in {res['touching']['ms']:.3f} ms "
+          f"({res['touching']['roofline']['frac']:.1%} of the FP64 ceiling), {res['random']['pairs']} random pairs "
+          f"in {res['random']['ms']:.3f} ms", file=sys.stderr, flush=True)
     return res
+
+
+def ctypes_vp(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def error_vectors(mesh, x_host):

@@ -366,10 +366,11 @@ gca_status gca_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m,
  * identical pairs are 0 (x - y lies in the plane of t_j); common edge and
  * common vertex pairs use the Sauter-Schwab maps with q_s Gauss points in
  * each of the four variables; the others the regular rules of order q_r /
- * q_nr of the handle.  FP64.  I, J: device int32 original triangle ids; out:
- * device FP64, m values.  Classifies the pairs on the host (copies I and J
- * back and synchronises the stream); the device workspace of 188 bytes per
- * pair is held by the handle and grown when a call needs more.
+ * q_nr of the handle.  FP64.  I, J: device int32 original triangle ids (an id
+ * outside [0, n) gives NaN); out: device FP64, m values.  The pairs are
+ * classified on the device and the work is queued on the stream without
+ * synchronisation; the first call uploads the mesh's vertex adjacency (for
+ * the near-regular class), held by the handle.
  * Errors: GCA_EINVAL, GCA_ENOMEM, GCA_EHIP. */
 gca_status gca_dl_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t m, double *out, void *stream);
 

@@ -83,9 +83,6 @@ void free_all(gca_h2_s *h)
     dev_free(h, h->d_ent);
     h->d_ent = nullptr;
     h->ent_cap = 0;
-    dev_free(h, h->d_dl);
-    h->d_dl = nullptr;
-    h->dl_cap = 0;
     for (void *p : h->allocs) dev_free(h, p);
     h->allocs.clear();
     if (h->events) {
@@ -1648,96 +1645,14 @@ gca_status gca_dl_entries(gca_h2 h, const int32_t *I, const int32_t *J, int64_t 
     if (m == 0) return GCA_OK;
     if (!I || !J || !out) return set_error(GCA_EINVAL, "NULL pointer");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<int32_t> hi(m), hj(m);
-    GCA_HIP_TRY(hipMemcpyAsync(hi.data(), I, m * 4, hipMemcpyDeviceToHost, s));
-    GCA_HIP_TRY(hipMemcpyAsync(hj.data(), J, m * 4, hipMemcpyDeviceToHost, s));
-    GCA_HIP_TRY(hipStreamSynchronize(s));
-    const Mesh &M = h->mesh;
-    auto vtx = [&](int32_t v, double *o) {
-        for (int d = 0; d < 3; ++d) o[d] = M.xyz[3 * (int64_t)v + d];
-    };
-    // jobs grouped by class: common vertex, common edge, near-regular, regular
-    std::vector<int64_t> order[4];
-    std::vector<int32_t> jkind(m, -1);
-    for (int64_t k = 0; k < m; ++k) {
-        const int32_t a = hi[k], b = hj[k];
-        if (a < 0 || a >= h->n || b < 0 || b >= h->n) return set_error(GCA_EINVAL, "triangle id out of range");
-        int32_t code = 0;
-        const int kls = classify_pair(M, h->adj, std::min(a, b), std::max(a, b), &code);
-        const int kind = kls == 2 ? 2 : (kls == 1 ? 3 : (kls == 3 ? 1 : (kls == 4 ? 0 : -1)));
-        jkind[k] = kind;
-        if (kind >= 0) order[kind == 2 ? 0 : (kind == 3 ? 1 : (kind == 1 ? 2 : 3))].push_back(k);
-    }
-    std::vector<int64_t> jobs;
-    for (auto &o : order) jobs.insert(jobs.end(), o.begin(), o.end());
-    const int64_t nj = (int64_t)jobs.size();
-    std::vector<double> jb((size_t)std::max<int64_t>(nj, 1) * 21);
-    std::vector<int32_t> kd(std::max<int64_t>(nj, 1));
-    for (int64_t q = 0; q < nj; ++q) {
-        const int64_t k = jobs[q];
-        const int32_t a = hi[k], b = hj[k];
-        const int32_t *ta = &M.tri[3 * (int64_t)a], *tb = &M.tri[3 * (int64_t)b];
-        int32_t pa[3] = {ta[0], ta[1], ta[2]}, pb[3] = {tb[0], tb[1], tb[2]};
-        if (jkind[k] == 3) {   // common edge: shared vertices (lower id first), then the third
-            int32_t sh[2], ns = 0;
-            for (int x = 0; x < 3; ++x)
-                for (int y = 0; y < 3; ++y)
-                    if (ta[x] == tb[y] && ns < 2) sh[ns++] = ta[x];
-            const int32_t lo = std::min(sh[0], sh[1]), hi2 = std::max(sh[0], sh[1]);
-            int32_t oa = -1, ob = -1;
-            for (int x = 0; x < 3; ++x) {
-                if (ta[x] != lo && ta[x] != hi2) oa = ta[x];
-                if (tb[x] != lo && tb[x] != hi2) ob = tb[x];
-            }
-            pa[0] = lo; pa[1] = hi2; pa[2] = oa;
-            pb[0] = lo; pb[1] = hi2; pb[2] = ob;
-        } else if (jkind[k] == 2) {   // common vertex first, then cyclic mesh order
-            int ka = 0, kb = 0;
-            for (int x = 0; x < 3; ++x)
-                for (int y = 0; y < 3; ++y)
-                    if (ta[x] == tb[y]) { ka = x; kb = y; }
-            for (int x = 0; x < 3; ++x) { pa[x] = ta[(ka + x) % 3]; pb[x] = tb[(kb + x) % 3]; }
-        }
-        double *o = &jb[21 * q];
-        for (int x = 0; x < 3; ++x) { vtx(pa[x], o + 3 * x); vtx(pb[x], o + 9 + 3 * x); }
-        // unit normal of t_b from its mesh orientation
-        double v0[3], v1[3], v2[3];
-        vtx(tb[0], v0); vtx(tb[1], v1); vtx(tb[2], v2);
-        const double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
-        const double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
-        double nn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-        const double l = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
-        for (int d = 0; d < 3; ++d) o[18 + d] = nn[d] / l;
-        kd[q] = jkind[k];
-    }
-    // workspace held by the handle: jobs, kinds and values
-    const size_t need = (size_t)std::max<int64_t>(nj, 1) * (21 * 8 + 4 + 8);
-    if (need > h->dl_cap) {
-        GCA_HIP_TRY(hipStreamSynchronize(s));
-        dev_free(h, h->d_dl);
-        h->d_dl = nullptr;
-        h->dl_cap = 0;
+    // the vertex adjacency of the near-regular class, uploaded by the first call
+    if (!h->d_vv_ptr) {
         h->cur_stream = s;
-        h->d_dl = dev_alloc(h, need);
-        if (!h->d_dl) return alloc_error(need, "double-layer entries workspace");
-        h->dl_cap = need;
+        GCA_TRY(upload_new(h, &h->d_vv_ptr, h->adj.vv_ptr, s));
+        GCA_TRY(upload_new(h, &h->d_vv, h->adj.vv, s));
     }
-    double *djob = (double *)h->d_dl;
-    double *dval = djob + 21 * std::max<int64_t>(nj, 1);
-    int32_t *dkind = (int32_t *)(dval + std::max<int64_t>(nj, 1));
-    std::vector<double> val(std::max<int64_t>(nj, 1));
-    if (nj > 0) {
-        GCA_HIP_TRY(hipMemcpyAsync(djob, jb.data(), nj * 21 * 8, hipMemcpyHostToDevice, s));
-        GCA_HIP_TRY(hipMemcpyAsync(dkind, kd.data(), nj * 4, hipMemcpyHostToDevice, s));
-        GCA_HIP_TRY(launch_dl_entries(djob, dkind, nj, h->prm.q_r, h->prm.q_nr, h->prm.q_s, h->prm.sym_rules != 0,
-                                      dval, s));
-        GCA_HIP_TRY(hipMemcpyAsync(val.data(), dval, nj * 8, hipMemcpyDeviceToHost, s));
-        GCA_HIP_TRY(hipStreamSynchronize(s));
-    }
-    std::vector<double> res(m, 0.0);   // identical pairs: 0
-    for (int64_t q = 0; q < nj; ++q) res[jobs[q]] = val[q];
-    GCA_HIP_TRY(hipMemcpyAsync(out, res.data(), m * 8, hipMemcpyHostToDevice, s));
-    GCA_HIP_TRY(hipStreamSynchronize(s));
+    GCA_HIP_TRY(launch_dl_pairs(h->d_xyz, h->d_tv, h->d_iperm, h->d_vv_ptr, h->d_vv, h->n, I, J, m, h->prm.q_r,
+                                h->prm.q_nr, h->prm.q_s, h->prm.sym_rules != 0, out, s));
     return GCA_OK;
 }
 

@@ -354,8 +354,8 @@ struct gca_h2_s {
     double *d_ews = nullptr;         // energy: the product G~ u when the caller wants E only
     void *d_ent = nullptr;           // gca_entries: pair arrays and values, 24 bytes per pair
     size_t ent_cap = 0;              // pairs d_ent holds
-    void *d_dl = nullptr;            // gca_dl_entries: jobs, kinds and values
-    size_t dl_cap = 0;               // bytes d_dl holds
+    int64_t *d_vv_ptr = nullptr;     // gca_dl_entries: the vertex adjacency (first call)
+    int32_t *d_vv = nullptr;
     hipStream_t cur_stream = nullptr;   // stream of the call in progress (given to the alloc callback)
 
     // per-matvec workspaces
@@ -486,11 +486,12 @@ hipError_t launch_gather(gca_h2_s *h, const T *xp, const double *xp64, const T *
 // *out = factor * sum a[i] b[i] (fixed reduction order; partial: 1024 doubles)
 hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t s,
                       double factor = 1.0);
-// double-layer entries (dlayer.hip): job k = 21 doubles (P, Q vertices in the
-// order of its rule, unit normal of the second triangle), kind 0 regular,
-// 1 near-regular, 2 common vertex, 3 common edge
-hipError_t launch_dl_entries(const double *job, const int32_t *kind, int64_t m, int q_r, int q_nr, int q_s, bool sym,
-                             double *out, hipStream_t s);
+// Double-layer entries (dlayer.hip) of m pairs (original triangle ids I, J) classified on
+// the device: tv / iperm the handle's position tables, vv_ptr / vv the vertex
+// adjacency (near-regular class); ids out of range give NaN.
+hipError_t launch_dl_pairs(const double *xyz, const int32_t *tv, const int32_t *iperm, const int64_t *vv_ptr,
+                           const int32_t *vv, int64_t n, const int32_t *I, const int32_t *J, int64_t m, int q_r,
+                           int q_nr, int q_s, bool sym, double *out, hipStream_t s);
 
 // doubles of a dot-product workspace: 1024 partials + one result slot
 constexpr size_t DOT_PARTIALS = 1025;
