@@ -538,12 +538,12 @@ void handle_free_all(gca_h2_s *h);
 gca_status params_check(const gca_params *p);
 gca_status basis_build(gca_h2_s *h, hipStream_t s);
 
-// Stored sub-blocks of the nodal-basis handle (lin_h2.hip): sub-block b has
-// rows [row0, row0 + nr) of its target, G column-major nr x nc at goff[b],
-// columns src[srcoff[b] + j]; its row sums go to part[poff[b] + i].  Target g
-// (cluster tgt[g]) then adds those of its sub-blocks sub_ptr[g] ..
-// sub_ptr[g+1] in order.  FAR: yh[piv_off[t] + i] = sum; else y[perm[begin +
-// i]] = V_t yh_t + sum (the gather).
+// Stored blocks of the nodal-basis handle (lin_h2.hip): block b has rows
+// [row0, row0 + nr) of its target (row0 = 0: whole blocks), G column-major
+// nr x nc at goff[b], columns src[srcoff[b] + j]; its row sums go to
+// part[poff[b] + i].  Target g (cluster tgt[g]) then adds those of its blocks
+// sub_ptr[g] .. sub_ptr[g+1] in order.  FAR: yh[piv_off[t] + i] = sum; else
+// y[perm[begin + i]] = V_t yh_t + sum (the gather).
 struct LinApply {
     int32_t ntarget = 0;
     int64_t nsub = 0;
@@ -557,7 +557,8 @@ struct LinApply {
 // the row sums of every sub-block (one wavefront each), then per target
 hipError_t launch_lin_sub(const LinApply &a, const double *src, hipStream_t s);
 hipError_t launch_lin_reduce(const gca_h2_s *h, const LinApply &a, bool far, double *yh, double *y, hipStream_t s);
-// out[goff[b] + j nr + i] = in[b ld + i nc + j] for the nb sub-blocks of a batch (transposed)
+// out[dst[b] + j ldo + i] = in[b ld + i nc + j] for the nb sub-blocks of a batch
+// (meta: nr, nc, ldo per sub-block; transposed into their blocks)
 hipError_t launch_lin_compact(const double *in, int64_t ld, int32_t nb, const int32_t *meta, const int64_t *goff,
                               double *out, hipStream_t s);
 

@@ -275,25 +275,33 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
         for (size_t g = 0; g < tg.size(); ++g) tpos[tg[g]] = (int32_t)g;
         std::vector<std::vector<int32_t>> per(tg.size());
         for (size_t b = 0; b < bt.size(); ++b) per[tpos[bt[b]]].push_back(bs[b]);
-        std::vector<int64_t> sub_ptr{0}, goff, srcoff, poff;
-        std::vector<int32_t> meta, br, bc;
+        // stored blocks: every block (t, u) whole, column-major with leading
+        // dimension the rows of t; assembled in chunk sub-blocks (the pair-wise
+        // kernels' limits) that the compaction puts in place
+        std::vector<int64_t> sub_ptr{0}, goff, srcoff, poff, dst;
+        std::vector<int32_t> meta, smeta, br, bc;
         int64_t off = 0, prow = 0;
         for (size_t g = 0; g < tg.size(); ++g) {
             const int t = tg[g];
+            const int nrt = ch[t].back();
             std::sort(per[g].begin(), per[g].end());
-            for (int u : per[g])
+            for (int u : per[g]) {
+                const int ncu = ch[u].back();
+                meta.insert(meta.end(), {nrt, ncu, 0});
+                goff.push_back(off);
+                poff.push_back(prow);
+                srcoff.push_back(farb ? h->piv_off[u] : nodes[u].begin);
                 for (size_t cb = 0; cb + 1 < ch[u].size(); ++cb)
                     for (size_t rb = 0; rb + 1 < ch[t].size(); ++rb) {
                         const int nr = ch[t][rb + 1] - ch[t][rb], ncol = ch[u][cb + 1] - ch[u][cb];
-                        meta.insert(meta.end(), {nr, ncol, ch[t][rb]});
+                        smeta.insert(smeta.end(), {nr, ncol, nrt});
+                        dst.push_back(off + (int64_t)ch[u][cb] * nrt + ch[t][rb]);
                         br.push_back(set0[t] + (int32_t)rb);
                         bc.push_back(set0[u] + (int32_t)cb);
-                        goff.push_back(off);
-                        poff.push_back(prow);
-                        srcoff.push_back((farb ? h->piv_off[u] : nodes[u].begin) + ch[u][cb]);
-                        off += (int64_t)nr * ncol;
-                        prow += nr;
                     }
+                off += (int64_t)nrt * ncu;
+                prow += nrt;
+            }
             sub_ptr.push_back((int64_t)goff.size());
         }
         nstore = off;
@@ -309,12 +317,12 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
         GCA_TRY(alloc_n(h, &A.G, (size_t)off));
         const int q = farb ? prm.q_c : prm.q_r;
         std::vector<int32_t> st(BATCH);
-        for (size_t b0 = 0; b0 < goff.size(); b0 += BATCH) {
-            const int32_t nb = (int32_t)std::min<size_t>(BATCH, goff.size() - b0);
+        for (size_t b0 = 0; b0 < dst.size(); b0 += BATCH) {
+            const int32_t nb = (int32_t)std::min<size_t>(BATCH, dst.size() - b0);
             GCA_HIP_TRY(hipMemcpyAsync(d_br, br.data() + b0, 4 * (size_t)nb, hipMemcpyHostToDevice, s));
             GCA_HIP_TRY(hipMemcpyAsync(d_bc, bc.data() + b0, 4 * (size_t)nb, hipMemcpyHostToDevice, s));
-            GCA_HIP_TRY(hipMemcpyAsync(d_meta, meta.data() + 3 * b0, 12 * (size_t)nb, hipMemcpyHostToDevice, s));
-            GCA_HIP_TRY(hipMemcpyAsync(d_goff, goff.data() + b0, 8 * (size_t)nb, hipMemcpyHostToDevice, s));
+            GCA_HIP_TRY(hipMemcpyAsync(d_meta, smeta.data() + 3 * b0, 12 * (size_t)nb, hipMemcpyHostToDevice, s));
+            GCA_HIP_TRY(hipMemcpyAsync(d_goff, dst.data() + b0, 8 * (size_t)nb, hipMemcpyHostToDevice, s));
             GCA_TRY(gca_lin_blocks(d_xyz, d_tri, d_mtri, d_mloc, d_mcnt, CHUNK_T, d_set_off, d_br, d_bc, nb,
                                    (int64_t)CHUNK_V * CHUNK_V, q, prm.sym_rules != 0, farb ? 0 : prm.q_s, d_tmp,
                                    d_status, s));

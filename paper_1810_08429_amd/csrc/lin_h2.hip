@@ -12,9 +12,10 @@ namespace {
 
 constexpr int AW = 4;          // wavefronts per workgroup: one sub-block each
 
-// Row sums of one sub-block per wavefront: entries column-major (G[j nr + i]:
-// a column is one coalesced load); up to 32 rows, the two half-wavefronts
-// take the even and the odd columns, four columns per lane in flight.
+// Row sums of one stored block per wavefront: entries column-major (G[j nr +
+// i]: a column is one coalesced load per 64 rows); blocks of up to 32 rows
+// let the two half-wavefronts take the even and the odd columns; four
+// columns per lane in flight.
 __global__ void __launch_bounds__(64 * AW) k_lin_sub(LinApply a, const double *src)
 {
     const int64_t b = (int64_t)blockIdx.x * AW + (threadIdx.x >> 6);
@@ -23,22 +24,27 @@ __global__ void __launch_bounds__(64 * AW) k_lin_sub(LinApply a, const double *s
     const int nr = a.sub_meta[3 * b], nc = a.sub_meta[3 * b + 1];
     const double *G = a.G + a.goff[b];
     const double *x = src + a.srcoff[b];
+    double *out = a.part + a.poff[b];
     const int hs = nr <= 32 ? 2 : 1;
-    const int r = hs == 2 ? (lane & 31) : lane, h = hs == 2 ? (lane >> 5) : 0;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    if (r < nr) {
-        int j = h;
-        for (; j + 3 * hs < nc; j += 4 * hs) {
-            a0 += G[(int64_t)j * nr + r] * x[j];
-            a1 += G[(int64_t)(j + hs) * nr + r] * x[j + hs];
-            a2 += G[(int64_t)(j + 2 * hs) * nr + r] * x[j + 2 * hs];
-            a3 += G[(int64_t)(j + 3 * hs) * nr + r] * x[j + 3 * hs];
+    const int rp = 64 / hs;
+    const int h = hs == 2 ? (lane >> 5) : 0, rl = lane & (rp - 1);
+    for (int r0 = 0; r0 < nr; r0 += rp) {
+        const int r = r0 + rl;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (r < nr) {
+            int j = h;
+            for (; j + 3 * hs < nc; j += 4 * hs) {
+                a0 += G[(int64_t)j * nr + r] * x[j];
+                a1 += G[(int64_t)(j + hs) * nr + r] * x[j + hs];
+                a2 += G[(int64_t)(j + 2 * hs) * nr + r] * x[j + 2 * hs];
+                a3 += G[(int64_t)(j + 3 * hs) * nr + r] * x[j + 3 * hs];
+            }
+            for (; j < nc; j += hs) a0 += G[(int64_t)j * nr + r] * x[j];
         }
-        for (; j < nc; j += hs) a0 += G[(int64_t)j * nr + r] * x[j];
+        double v = (a0 + a1) + (a2 + a3);
+        if (hs == 2) v += __shfl_xor(v, 32);
+        if (r < nr && h == 0) out[r] = v;
     }
-    double v = (a0 + a1) + (a2 + a3);
-    if (hs == 2) v += __shfl_xor(v, 32);
-    if (r < nr && h == 0) a.part[a.poff[b] + r] = v;
 }
 
 // One workgroup per target, thread per row: the partial sums of the target's
@@ -72,15 +78,15 @@ __global__ void __launch_bounds__(128) k_lin_reduce(LinApply a, const int32_t *n
     }
 }
 
-// sub-block b of a batch (row-major nr x nc at in + b ld) into the store,
-// column-major at out + goff[b]
-__global__ void k_lin_compact(const double *in, int64_t ld, const int32_t *meta, const int64_t *goff, double *out)
+// sub-block b of a batch (row-major nr x nc at in + b ld) into the store:
+// column-major with leading dimension ldo at out + dst[b] (meta: nr, nc, ldo)
+__global__ void k_lin_compact(const double *in, int64_t ld, const int32_t *meta, const int64_t *dst, double *out)
 {
     const int b = blockIdx.x;
-    const int nr = meta[3 * b], nc = meta[3 * b + 1];
+    const int nr = meta[3 * b], nc = meta[3 * b + 1], ldo = meta[3 * b + 2];
     for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
         const int i = e / nc, j = e - i * nc;
-        out[goff[b] + (int64_t)j * nr + i] = in[(int64_t)b * ld + e];
+        out[dst[b] + (int64_t)j * ldo + i] = in[(int64_t)b * ld + e];
     }
 }
 
