@@ -113,6 +113,69 @@ __global__ void __launch_bounds__(64) k_forward(const int32_t *clusters, const i
     }
 }
 
+// The levels with few clusters (the upper tree, where ranks are largest):
+// a workgroup of four wavefronts per cluster, each wavefront a quarter of the
+// rows (leaf: the rows of V; parent: the rows of E_son0 then E_son1), lanes
+// over the basis columns, the quarters added in LDS in a fixed order.
+constexpr int WIDE_LEVEL = 1024;   // clusters of a level below which it runs wide
+constexpr int WIDE_MINR = 64;      // ... when some rank exceeds a wavefront (measured: slower below)
+constexpr int WIDE_MAXR = 512;     // ranks (at most the 2k <= 512 Green columns)
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_forward_wide(const int32_t *clusters, const int32_t *node,
+                                                      const int32_t *rank, const int64_t *piv_off,
+                                                      const int64_t *v_off, const int64_t *e_off, const T *V,
+                                                      const T *E, const T *xp, T *xh)
+{
+    __shared__ T part[4][WIDE_MAXR];
+    const int c = clusters[blockIdx.x];
+    const int r = rank[c];
+    const int s0 = node[5 * c + 2], s1 = node[5 * c + 3];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool leaf = s0 < 0;
+    const int b = node[5 * c];
+    const int r0 = leaf ? node[5 * c + 1] - b : rank[s0];
+    const int nrow = leaf ? r0 : r0 + rank[s1];
+    const int i0 = (w * nrow) / 4, i1 = ((w + 1) * nrow) / 4;
+    for (int k = lane; k < r; k += 64) {
+        T acc = 0;
+        if (leaf) {
+            acc = col_dot_range(V + v_off[c], r, i0, i1, xp + b, k);
+        } else {
+            // rows [i0, i1) of E_son0 (i < r0) and E_son1 (i >= r0)
+            const int a0 = min(i0, r0), a1 = min(i1, r0);
+            if (a1 > a0) acc += col_dot_range(E + e_off[s0], r, a0, a1, xh + piv_off[s0], k);
+            const int b0 = max(i0, r0) - r0, b1 = max(i1, r0) - r0;
+            if (b1 > b0) acc += col_dot_range(E + e_off[s1], r, b0, b1, xh + piv_off[s1], k);
+        }
+        part[w][k] = acc;
+    }
+    __syncthreads();
+    T *out = xh + piv_off[c];
+    for (int k = threadIdx.x; k < r; k += 256) out[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
+}
+
+// yh_c += E_c yh_parent for the clusters of a level with few clusters: the
+// parent's rows in quarters over the four wavefronts, lanes over the columns
+template <typename T>
+__global__ void __launch_bounds__(256) k_backward_wide(const int32_t *clusters, const int32_t *node,
+                                                       const int32_t *rank, const int64_t *piv_off,
+                                                       const int64_t *e_off, const T *Et, T *yh)
+{
+    __shared__ T part[4][WIDE_MAXR];
+    const int c = clusters[blockIdx.x];
+    const int par = node[5 * c + 4];
+    const int rc = rank[c], rp = rank[par];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i0 = (w * rp) / 4, i1 = ((w + 1) * rp) / 4;
+    const T *Ec = Et + e_off[c];
+    const T *yp = yh + piv_off[par];
+    for (int j = lane; j < rc; j += 64) part[w][j] = col_dot_range(Ec, rc, i0, i1, yp, j);
+    __syncthreads();
+    T *yc = yh + piv_off[c];
+    for (int j = threadIdx.x; j < rc; j += 256) yc[j] += (part[0][j] + part[1][j]) + (part[2][j] + part[3][j]);
+}
+
 template <typename T>
 hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s)
 {
@@ -121,8 +184,12 @@ hipError_t launch_forward(gca_h2_s *h, const T *xp, T *xh, hipStream_t s)
     for (int l = (int)h->level_clusters.size() - 1; l >= 0; --l) {
         int nc = (int)h->level_clusters[l].size();
         if (!nc) continue;
-        hipLaunchKernelGGL(k_forward<T>, dim3(nc), dim3(64), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
-                           h->d_piv_off, h->d_v_off, h->d_e_off, V, E, xp, xh);
+        if (nc < WIDE_LEVEL && h->max_rank > WIDE_MINR && h->max_rank <= WIDE_MAXR)
+            hipLaunchKernelGGL(k_forward_wide<T>, dim3(nc), dim3(256), 0, s, h->d_level_clusters[l], h->d_node,
+                               h->d_rank, h->d_piv_off, h->d_v_off, h->d_e_off, V, E, xp, xh);
+        else
+            hipLaunchKernelGGL(k_forward<T>, dim3(nc), dim3(64), 0, s, h->d_level_clusters[l], h->d_node,
+                               h->d_rank, h->d_piv_off, h->d_v_off, h->d_e_off, V, E, xp, xh);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -192,8 +259,12 @@ hipError_t launch_backward(gca_h2_s *h, T *yh, hipStream_t s)
     for (int l = 1; l < (int)h->level_clusters.size(); ++l) {
         int nc = (int)h->level_clusters[l].size();
         if (!nc) continue;
-        hipLaunchKernelGGL(k_backward<T>, dim3(nc), dim3(64), 0, s, h->d_level_clusters[l], h->d_node, h->d_rank,
-                           h->d_piv_off, h->d_e_off, Et, yh);
+        if (nc < WIDE_LEVEL && h->max_rank > WIDE_MINR && h->max_rank <= WIDE_MAXR)
+            hipLaunchKernelGGL(k_backward_wide<T>, dim3(nc), dim3(256), 0, s, h->d_level_clusters[l], h->d_node,
+                               h->d_rank, h->d_piv_off, h->d_e_off, Et, yh);
+        else
+            hipLaunchKernelGGL(k_backward<T>, dim3(nc), dim3(64), 0, s, h->d_level_clusters[l], h->d_node,
+                               h->d_rank, h->d_piv_off, h->d_e_off, Et, yh);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
