@@ -1,5 +1,6 @@
-// Device helpers shared by the kernels: reciprocal square roots and
-// cross-lane sums inside a wavefront by DPP (no LDS round trip).
+// Device helpers shared by the kernels: reciprocal square roots, cross-lane
+// sums inside a wavefront by DPP (no LDS round trip) and an XCD-aware
+// workgroup order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,6 +49,15 @@ __device__ __forceinline__ T group_sum(T v)
     if constexpr (N >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
     if constexpr (N >= 16) v += dpp_mov<0x140>(v);  // row_mirror
     return v;
+}
+
+// Workgroups are dealt to the 8 XCDs of the chip round-robin by id; this
+// bijection of [0, nb) gives each XCD a contiguous range of work items, so
+// the neighbouring data that adjacent items read stays in that XCD's L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int nb)
+{
+    const int q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + min(x, r) + b / 8;
 }
 
 }  // namespace gca

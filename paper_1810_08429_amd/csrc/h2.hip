@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
+#include "devfn.h"
 
 namespace gca {
 
@@ -278,14 +279,8 @@ template hipError_t launch_backward<double>(gca_h2_s *, double *, hipStream_t);
 // are stored per leaf in ELL form (partner k of row i at k * nr + i, so the
 // rows of a leaf read consecutive addresses), the near-regular values (T) in
 // a row CSR aligned with their column indices.
-// Workgroups are dealt to the 8 XCDs of the chip round-robin by id; this
-// bijection gives each XCD a contiguous range of leaves, so the neighbouring
-// positions a leaf's touching pairs read stay in that XCD's L2.
-__device__ __forceinline__ int xcd_contiguous(int b, int nb)
-{
-    const int q = nb / 8, r = nb % 8, x = b % 8;
-    return x * q + min(x, r) + b / 8;
-}
+// Leaves are taken in XCD-contiguous order, so the neighbouring positions a
+// leaf's touching pairs read stay in one XCD's L2.
 
 template <typename T, typename Tout>
 __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int32_t *node, const int32_t *rank,

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
+#include "devfn.h"
 #include "mfma.h"
 
 namespace gca {
@@ -181,7 +182,7 @@ __global__ void __launch_bounds__(64) k_gather_nb(const int32_t *leaves, const i
                                                   const double *xb64, const int32_t *perm, Tout *y, int64_t ld,
                                                   int nrhs)
 {
-    const int li = blockIdx.x;
+    const int li = xcd_contiguous(blockIdx.x, gridDim.x);  // XCD-local neighbours
     const int c = leaves[li];
     const int b = node[5 * c], nr = node[5 * c + 1] - b;
     const int r = rank[c];
@@ -205,12 +206,25 @@ __global__ void __launch_bounds__(64) k_gather_nb(const int32_t *leaves, const i
             for (int64_t q = nslot_ptr[li]; q < nslot_ptr[li + 1]; ++q) sum += npart[(nslot[q] + ii) * NB + n];
             const int pos = b + ii;
             for (int64_t q = nptr[pos]; q < nptr[pos + 1]; ++q) sum += nval[q] * xb[(int64_t)nother[q] * NB + n];
-            double s64 = 0;
+            // touching partners four at a time on four partial sums, so that
+            // their dependent loads (partner, then its x) are in flight together
+            double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
             const int64_t t0 = tell_off[li] + ii;
-            for (int k = 0; k < tell_k[li]; ++k) {
-                const int64_t e = t0 + (int64_t)k * nr;
-                s64 += tval[e] * xb64[(int64_t)tother[e] * NB + n];
+            const int kt = tell_k[li];
+            int k = 0;
+            for (; k + 3 < kt; k += 4) {
+                const int64_t e0 = t0 + (int64_t)k * nr, e1 = e0 + nr, e2 = e1 + nr, e3 = e2 + nr;
+                const int64_t o0 = tother[e0], o1 = tother[e1], o2 = tother[e2], o3 = tother[e3];
+                s0 += tval[e0] * xb64[o0 * NB + n];
+                s1 += tval[e1] * xb64[o1 * NB + n];
+                s2 += tval[e2] * xb64[o2 * NB + n];
+                s3 += tval[e3] * xb64[o3 * NB + n];
             }
+            for (; k < kt; ++k) {
+                const int64_t e = t0 + (int64_t)k * nr;
+                s0 += tval[e] * xb64[(int64_t)tother[e] * NB + n];
+            }
+            const double s64 = (s0 + s1) + (s2 + s3);
             if (n < nrhs) y[(int64_t)n * ld + perm[pos]] = (Tout)((double)sum + s64);
         }
     }
