@@ -1096,7 +1096,7 @@ hipError_t matvec_batch(gca_h2_s *h, gca_h2_s::Batch &w, const void *x, void *y,
         if ((e = hipEventRecord(h->ev_join, h->s_side)) != hipSuccess) return e;
     }
     beg(0, s);
-    if ((e = launch_permute_in_nb<T>(x, vf32, ld, nrhs, h->d_perm, h->n, xb, f32 ? w.xb64 : nullptr, s)) !=
+    if ((e = launch_permute_in_nb<T>(x, vf32, ld, nrhs, h->d_iperm, h->n, xb, f32 ? w.xb64 : nullptr, s)) !=
         hipSuccess)
         return e;
     fin(0, s);

@@ -462,7 +462,7 @@ hipError_t launch_near_nb(gca_h2_s *h, const T *xb, T *npart, hipStream_t s);
 template <typename T>
 hipError_t launch_far_blocks_nb(gca_h2_s *h, const T *xhb, T *cpart, hipStream_t s);
 template <typename T>
-hipError_t launch_permute_in_nb(const void *x, bool xf32, int64_t ld, int nrhs, const int32_t *perm, int64_t n,
+hipError_t launch_permute_in_nb(const void *x, bool xf32, int64_t ld, int nrhs, const int32_t *iperm, int64_t n,
                                 T *xb, double *xb64, hipStream_t s);
 template <typename T>
 hipError_t launch_forward_nb(gca_h2_s *h, const T *xb, T *xhb, hipStream_t s);

@@ -14,31 +14,56 @@
 namespace gca {
 
 // xb[pos][k] = x[k * ld + perm[pos]] for k < nrhs, 0 for the padding columns;
-// xb64 (if not null) the same in FP64 (the touching values are FP64)
-template <typename Tin, typename T>
-__global__ void k_permute_in_nb(const Tin *x, int64_t ld, int nrhs, const int32_t *perm, int64_t n, T *xb,
-                                double *xb64)
+// xb64 (if not null) the same in FP64 (the touching values are FP64).  A
+// workgroup takes 64 consecutive original ids o: every column's 64 values
+// are read coalesced and transposed in LDS, then the NB values of each row
+// are written contiguously at position iperm[o] (four per thread).
+template <typename T>
+__device__ __forceinline__ void store4(T *dst, const double *v);
+template <>
+__device__ __forceinline__ void store4<float>(float *dst, const double *v)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * NB) return;
-    const int64_t pos = e / NB;
-    const int k = (int)(e - pos * NB);
-    const double v = k < nrhs ? (double)x[k * ld + perm[pos]] : 0.0;
-    xb[e] = (T)v;
-    if (xb64) xb64[e] = v;
+    *reinterpret_cast<float4 *>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+}
+template <>
+__device__ __forceinline__ void store4<double>(double *dst, const double *v)
+{
+    reinterpret_cast<double2 *>(dst)[0] = double2{v[0], v[1]};
+    reinterpret_cast<double2 *>(dst)[1] = double2{v[2], v[3]};
+}
+
+template <typename Tin, typename T>
+__global__ void __launch_bounds__(256) k_permute_in_nb(const Tin *x, int64_t ld, int nrhs, const int32_t *iperm,
+                                                       int64_t n, T *xb, double *xb64)
+{
+    __shared__ double tile[64][NB + 1];
+    const int64_t o0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x, oo = t & 63;
+    for (int k = t >> 6; k < NB; k += 4) {
+        const int64_t o = o0 + oo;
+        tile[oo][k] = (k < nrhs && o < n) ? (double)x[k * ld + o] : 0.0;
+    }
+    __syncthreads();
+    const int r = t >> 2, kq = (t & 3) * 4;
+    const int64_t o = o0 + r;
+    if (o >= n) return;
+    const int64_t pos = iperm[o];
+    const double v[4] = {tile[r][kq], tile[r][kq + 1], tile[r][kq + 2], tile[r][kq + 3]};
+    store4<T>(xb + pos * NB + kq, v);
+    if (xb64) store4<double>(xb64 + pos * NB + kq, v);
 }
 
 template <typename T>
-hipError_t launch_permute_in_nb(const void *x, bool xf32, int64_t ld, int nrhs, const int32_t *perm, int64_t n,
+hipError_t launch_permute_in_nb(const void *x, bool xf32, int64_t ld, int nrhs, const int32_t *iperm, int64_t n,
                                 T *xb, double *xb64, hipStream_t s)
 {
-    const dim3 grid((unsigned)((n * NB + 255) / 256)), blk(256);
+    const dim3 grid((unsigned)((n + 63) / 64)), blk(256);
     if (xf32)
-        hipLaunchKernelGGL((k_permute_in_nb<float, T>), grid, blk, 0, s, (const float *)x, ld, nrhs, perm, n, xb,
+        hipLaunchKernelGGL((k_permute_in_nb<float, T>), grid, blk, 0, s, (const float *)x, ld, nrhs, iperm, n, xb,
                            xb64);
     else
-        hipLaunchKernelGGL((k_permute_in_nb<double, T>), grid, blk, 0, s, (const double *)x, ld, nrhs, perm, n, xb,
-                           xb64);
+        hipLaunchKernelGGL((k_permute_in_nb<double, T>), grid, blk, 0, s, (const double *)x, ld, nrhs, iperm, n,
+                           xb, xb64);
     return hipGetLastError();
 }
 

@@ -5,10 +5,10 @@ and nearfield products of the 16 columns as 16 x 16 matrix-core tiles.
 Against the single products column by column (FP64 1e-13, mixed 2e-6 of the
 column's max norm: only the summation order differs), against the oracle's
 step-by-step GCA-H^2 (FP64 1e-10), for 3, 16 and 20 columns (one partial and
-two passes), ld > n, FP32 vectors, ranks above 64 (several row blocks in the
-coupling kernel and several tiles per transfer), the collapsed and the
-symmetric rules; serial and overlapped phases bit-equal; the stored-block mode
-(column by column) agrees."""
+two passes), a mesh size that is not a multiple of 64, ld > n, FP32 vectors,
+ranks above 64 (several row blocks in the coupling kernel and several tiles
+per transfer), the collapsed and the symmetric rules; serial and overlapped
+phases bit-equal; the stored-block mode (column by column) agrees."""
 import numpy as np
 import pytest
 
@@ -54,6 +54,21 @@ def test_batched_equals_single_products(torch, gca, nrhs, sym):
     for prec, tol in ((gca.FP64, 1e-13), (gca.MIXED, 2e-6)):
         Y = H.matvec(X, precision=prec)
         assert torch.equal(Y, H.matvec(X, precision=prec))
+        columns_match(torch, H, X, Y, prec, tol)
+    H.close()
+
+
+def test_batched_ragged_patch(torch, gca):
+    """An open patch of n = 1243 triangles (the level-3 sphere without its
+    last 37): the last 64-id group of the input permutation and the last
+    leaves are partial."""
+    base = synth.icosphere(3)
+    tris = np.ascontiguousarray(base.tris[:1243])
+    H = gca.H2(base.verts, tris, gca.Tree(base.verts, tris, 64), gca.Params(eta=2.0, eps=1e-6))
+    X = torch.tensor(synth.rhs_normal(1243, 16, seed=31), device="cuda")
+    print("[multi-rhs] ragged n 1243", flush=True)
+    for prec, tol in ((gca.FP64, 1e-13), (gca.MIXED, 2e-6)):
+        Y = H.matvec(X, precision=prec)
         columns_match(torch, H, X, Y, prec, tol)
     H.close()
 
