@@ -51,6 +51,51 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// sum_{q in [b, e)} part[slots[q] * stride + x] on four partial sums (slots
+// b + 4k + j on sum j, then (s0 + s1) + (s2 + s3)), so that four loads are in
+// flight together; the order is fixed, the result reproducible.
+template <typename T>
+__device__ __forceinline__ T slot_sum(const T *part, const int64_t *slots, int64_t b, int64_t e, int64_t stride,
+                                      int64_t x)
+{
+    T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int64_t q = b;
+    for (; q + 3 < e; q += 4) {
+        s0 += part[slots[q] * stride + x];
+        s1 += part[slots[q + 1] * stride + x];
+        s2 += part[slots[q + 2] * stride + x];
+        s3 += part[slots[q + 3] * stride + x];
+    }
+    if (q < e) s0 += part[slots[q] * stride + x];
+    if (q + 1 < e) s1 += part[slots[q + 1] * stride + x];
+    if (q + 2 < e) s2 += part[slots[q + 2] * stride + x];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// sum_{k < kt} val[e_k] x[oth[e_k] * stride + n] with e_k = e0 + k ld (a row
+// of an ELL table whose entry k lies ld apart): four partners on four
+// partial sums, so that their dependent loads (partner, then its x) are in
+// flight together; fixed order.
+__device__ __forceinline__ double ell_sum(const double *val, const int32_t *oth, const double *x, int64_t e0,
+                                          int64_t ld, int kt, int64_t stride, int n)
+{
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int k = 0;
+    for (; k + 3 < kt; k += 4) {
+        const int64_t e = e0 + (int64_t)k * ld;
+        const int64_t o0 = oth[e], o1 = oth[e + ld], o2 = oth[e + 2 * ld], o3 = oth[e + 3 * ld];
+        s0 += val[e] * x[o0 * stride + n];
+        s1 += val[e + ld] * x[o1 * stride + n];
+        s2 += val[e + 2 * ld] * x[o2 * stride + n];
+        s3 += val[e + 3 * ld] * x[o3 * stride + n];
+    }
+    for (; k < kt; ++k) {
+        const int64_t e = e0 + (int64_t)k * ld;
+        s0 += val[e] * x[(int64_t)oth[e] * stride + n];
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Workgroups are dealt to the 8 XCDs of the chip round-robin by id; this
 // bijection of [0, nb) gives each XCD a contiguous range of work items, so
 // the neighbouring data that adjacent items read stays in that XCD's L2.

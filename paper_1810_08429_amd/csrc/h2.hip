@@ -207,11 +207,7 @@ __global__ void k_coupling_reduce(const int32_t *rank, const int64_t *piv_off, c
     const int c = blockIdx.x;
     const int r = rank[c];
     const int64_t b = slot_ptr[c], e = slot_ptr[c + 1];
-    for (int k = threadIdx.x; k < r; k += blockDim.x) {
-        T acc = 0;
-        for (int64_t q = b; q < e; ++q) acc += part[slots[q] + k];
-        yh[piv_off[c] + k] = acc;
-    }
+    for (int k = threadIdx.x; k < r; k += blockDim.x) yh[piv_off[c] + k] = slot_sum(part, slots, b, e, 1, k);
 }
 
 template <typename T>
@@ -299,13 +295,10 @@ __global__ void __launch_bounds__(64) k_gather(const int32_t *leaves, const int3
     const T *Vc = Vt + v_off[c];
     const T *yc = yh + piv_off[c];
     for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-        T acc = col_dot(Vc, nr, r, yc, i);
-        for (int64_t q = nslot_ptr[li]; q < nslot_ptr[li + 1]; ++q) acc += npart[nslot[q] + i];
+        T acc = col_dot(Vc, nr, r, yc, i) + slot_sum(npart, nslot, nslot_ptr[li], nslot_ptr[li + 1], 1, i);
         const int pos = b + i;
         for (int64_t q = nptr[pos]; q < nptr[pos + 1]; ++q) acc += nval[q] * xp[nother[q]];
-        double acc64 = 0;
-        const int64_t t0 = tell_off[li] + i;
-        for (int k = 0; k < tell_k[li]; ++k) acc64 += tval[t0 + (int64_t)k * nr] * xp64[tother[t0 + (int64_t)k * nr]];
+        const double acc64 = ell_sum(tval, tother, xp64, tell_off[li] + i, nr, tell_k[li], 1, 0);
         y[perm[pos]] = (Tout)((double)acc + acc64);
     }
 }

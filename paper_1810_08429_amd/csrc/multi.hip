@@ -132,11 +132,7 @@ __global__ void k_coupling_reduce_nb(const int32_t *rank, const int64_t *piv_off
     const int c = blockIdx.x;
     const int m = rank[c] * NB;
     const int64_t b = slot_ptr[c], e = slot_ptr[c + 1];
-    for (int x = threadIdx.x; x < m; x += blockDim.x) {
-        T acc = 0;
-        for (int64_t q = b; q < e; ++q) acc += part[slots[q] * NB + x];
-        yhb[piv_off[c] * NB + x] = acc;
-    }
+    for (int x = threadIdx.x; x < m; x += blockDim.x) yhb[piv_off[c] * NB + x] = slot_sum(part, slots, b, e, NB, x);
 }
 
 template <typename T>
@@ -227,29 +223,10 @@ __global__ void __launch_bounds__(64) k_gather_nb(const int32_t *leaves, const i
         for (int v = 0; v < 4; ++v) {
             const int ii = i0 + Mfma<T>::row(lane, v);
             if (ii >= nr) continue;
-            T sum = acc[v];
-            for (int64_t q = nslot_ptr[li]; q < nslot_ptr[li + 1]; ++q) sum += npart[(nslot[q] + ii) * NB + n];
+            T sum = acc[v] + slot_sum(npart, nslot, nslot_ptr[li], nslot_ptr[li + 1], NB, (int64_t)ii * NB + n);
             const int pos = b + ii;
             for (int64_t q = nptr[pos]; q < nptr[pos + 1]; ++q) sum += nval[q] * xb[(int64_t)nother[q] * NB + n];
-            // touching partners four at a time on four partial sums, so that
-            // their dependent loads (partner, then its x) are in flight together
-            double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-            const int64_t t0 = tell_off[li] + ii;
-            const int kt = tell_k[li];
-            int k = 0;
-            for (; k + 3 < kt; k += 4) {
-                const int64_t e0 = t0 + (int64_t)k * nr, e1 = e0 + nr, e2 = e1 + nr, e3 = e2 + nr;
-                const int64_t o0 = tother[e0], o1 = tother[e1], o2 = tother[e2], o3 = tother[e3];
-                s0 += tval[e0] * xb64[o0 * NB + n];
-                s1 += tval[e1] * xb64[o1 * NB + n];
-                s2 += tval[e2] * xb64[o2 * NB + n];
-                s3 += tval[e3] * xb64[o3 * NB + n];
-            }
-            for (; k < kt; ++k) {
-                const int64_t e = t0 + (int64_t)k * nr;
-                s0 += tval[e] * xb64[(int64_t)tother[e] * NB + n];
-            }
-            const double s64 = (s0 + s1) + (s2 + s3);
+            const double s64 = ell_sum(tval, tother, xb64, tell_off[li] + ii, nr, tell_k[li], NB, n);
             if (n < nrhs) y[(int64_t)n * ld + perm[pos]] = (Tout)((double)sum + s64);
         }
     }
