@@ -14,6 +14,7 @@
 
 #include "gca_internal.h"
 #include "devfn.h"
+#include "mfma.h"
 
 namespace gca {
 
@@ -164,13 +165,13 @@ __global__ void __launch_bounds__(256) k_lu(ClusterArgs ca, const double *AJ, do
     }
 }
 
-// Row solves with P C = L U (P: perm, L unit lower, U upper, both in LU).
-// mode 0: v C = a     (V^ rows from A^[:, J] rows), written to out
-// mode 1: C z = vbar  (z = rows of Z = V^bar C^{-T}), written to out
-// rows of `in` and `out`: m x r row-major at aj_off[b]; `tmp` the same size.
+// Row solves v C = a with P C = L U (P: perm, L unit lower, U upper, both in
+// LU): the rows of V^ from those of A^[:, J], and the rows of C^{-1} from
+// those of the identity.  Rows of `in` and `out`: m x r row-major at
+// aj_off[b]; `tmp` the same size.
 __global__ void __launch_bounds__(256) k_row_solve(ClusterArgs ca, const double *LU, const int32_t *perm,
                                                    const int64_t *perm_off, const double *in, double *out,
-                                                   double *tmp, int mode)
+                                                   double *tmp)
 {
     const int b = blockIdx.x;
     const int c = ca.clusters[b];
@@ -182,37 +183,23 @@ __global__ void __launch_bounds__(256) k_row_solve(ClusterArgs ca, const double 
         const double *a = in + ca.aj_off[b] + (int64_t)i * r;
         double *t = tmp + ca.aj_off[b] + (int64_t)i * r;
         double *v = out + ca.aj_off[b] + (int64_t)i * r;
-        if (mode == 0) {
-            // v P^T L U = a: t U = a (forward over columns), w L = t (backward), v = w P
-            for (int j = 0; j < r; ++j) {
-                double s = a[j];
-                for (int q = 0; q < j; ++q) s -= t[q] * A[(int64_t)q * r + j];
-                t[j] = s / A[(int64_t)j * r + j];
-            }
-            for (int j = r - 1; j >= 0; --j) {
-                double s = t[j];
-                for (int q = j + 1; q < r; ++q) s -= t[q] * A[(int64_t)q * r + j];
-                t[j] = s;   // w_j (unit diagonal of L)
-            }
-            for (int j = 0; j < r; ++j) v[pm[j]] = t[j];
-        } else {
-            // P^T L U z = vbar: L y = P vbar (forward), U z = y (backward)
-            for (int j = 0; j < r; ++j) {
-                double s = a[pm[j]];
-                for (int q = 0; q < j; ++q) s -= A[(int64_t)j * r + q] * t[q];
-                t[j] = s;
-            }
-            for (int j = r - 1; j >= 0; --j) {
-                double s = t[j];
-                for (int q = j + 1; q < r; ++q) s -= A[(int64_t)j * r + q] * v[q];
-                v[j] = s / A[(int64_t)j * r + j];
-            }
+        // v P^T L U = a: t U = a (forward over columns), w L = t (backward), v = w P
+        for (int j = 0; j < r; ++j) {
+            double s = a[j];
+            for (int q = 0; q < j; ++q) s -= t[q] * A[(int64_t)q * r + j];
+            t[j] = s / A[(int64_t)j * r + j];
         }
+        for (int j = r - 1; j >= 0; --j) {
+            double s = t[j];
+            for (int q = j + 1; q < r; ++q) s -= t[q] * A[(int64_t)q * r + j];
+            t[j] = s;   // w_j (unit diagonal of L)
+        }
+        for (int j = 0; j < r; ++j) v[pm[j]] = t[j];
     }
 }
 
-// The same factorisation and solves with C staged in LDS, for ranks up to
-// FZ_MAXR: k_lu_lds factors in LDS (one workgroup per cluster); in
+// The same factorisation and row solves with C staged in LDS, for ranks up
+// to FZ_MAXR: k_lu_lds factors in LDS (one workgroup per cluster); in
 // k_row_solve_lds eight threads share a row and hold its entries q = t + 8 s
 // in registers, the sums over q are split over the eight and combined by
 // shuffles.  Same operations as k_lu / k_row_solve, different summation order.
@@ -297,8 +284,7 @@ __global__ void __launch_bounds__(256) k_lu_lds(ClusterArgs ca, const double *AJ
 }
 
 __global__ void __launch_bounds__(256) k_row_solve_lds(ClusterArgs ca, const double *LU, const int32_t *perm,
-                                                       const int64_t *perm_off, const double *in, double *out,
-                                                       int mode)
+                                                       const int64_t *perm_off, const double *in, double *out)
 {
     constexpr int NS = FZ_MAXR / 8;
     __shared__ double A[FZ_MAXR * FZ_MAXR];
@@ -320,82 +306,93 @@ __global__ void __launch_bounds__(256) k_row_solve_lds(ClusterArgs ca, const dou
 #pragma unroll
         for (int sl = 0; sl < NS; ++sl) {
             const int q = t8 + 8 * sl;
-            av[sl] = q < r ? a[mode == 0 ? q : pmv[q]] : 0.0;
+            av[sl] = q < r ? a[q] : 0.0;
         }
-        if (mode == 0) {
-            // v P^T L U = a: t U = a (forward over columns), w L = t (backward), v = w P
+        // v P^T L U = a: t U = a (forward over columns), w L = t (backward), v = w P
 #pragma unroll
-            for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
-            for (int j = 0; j < r; ++j) {
-                double acc = 0.0;
-#pragma unroll
-                for (int sl = 0; sl < NS; ++sl) {
-                    const int q = t8 + 8 * sl;
-                    if (q < j) acc += t[sl] * A[q * r + j];
-                }
-                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
-                if (t8 == (j & 7)) {
-#pragma unroll
-                    for (int sl = 0; sl < NS; ++sl)
-                        if (sl == (j >> 3)) t[sl] = (av[sl] - acc) / A[j * r + j];
-                }
-            }
-            for (int j = r - 1; j >= 0; --j) {
-                double acc = 0.0;
-#pragma unroll
-                for (int sl = 0; sl < NS; ++sl) {
-                    const int q = t8 + 8 * sl;
-                    if (q > j && q < r) acc += t[sl] * A[q * r + j];
-                }
-                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
-                if (t8 == (j & 7)) {
-#pragma unroll
-                    for (int sl = 0; sl < NS; ++sl)
-                        if (sl == (j >> 3)) t[sl] -= acc;
-                }
-            }
+        for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
+        for (int j = 0; j < r; ++j) {
+            double acc = 0.0;
 #pragma unroll
             for (int sl = 0; sl < NS; ++sl) {
                 const int q = t8 + 8 * sl;
-                if (q < r) v[pmv[q]] = t[sl];
+                if (q < j) acc += t[sl] * A[q * r + j];
             }
-        } else {
-            // P^T L U z = vbar: L y = P vbar (forward), U z = y (backward)
+            acc = group_sum<8>(acc);   // the row's eight lanes, DPP
+            if (t8 == (j & 7)) {
 #pragma unroll
-            for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
-            for (int j = 0; j < r; ++j) {
-                double acc = 0.0;
-#pragma unroll
-                for (int sl = 0; sl < NS; ++sl) {
-                    const int q = t8 + 8 * sl;
-                    if (q < j) acc += A[j * r + q] * t[sl];
-                }
-                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
-                if (t8 == (j & 7)) {
-#pragma unroll
-                    for (int sl = 0; sl < NS; ++sl)
-                        if (sl == (j >> 3)) t[sl] = av[sl] - acc;
-                }
+                for (int sl = 0; sl < NS; ++sl)
+                    if (sl == (j >> 3)) t[sl] = (av[sl] - acc) / A[j * r + j];
             }
-            for (int j = r - 1; j >= 0; --j) {
-                double acc = 0.0;
-#pragma unroll
-                for (int sl = 0; sl < NS; ++sl) {
-                    const int q = t8 + 8 * sl;
-                    if (q > j && q < r) acc += A[j * r + q] * t[sl];
-                }
-                acc = group_sum<8>(acc);   // the row's eight lanes, DPP
-                if (t8 == (j & 7)) {
-#pragma unroll
-                    for (int sl = 0; sl < NS; ++sl)
-                        if (sl == (j >> 3)) t[sl] = (t[sl] - acc) / A[j * r + j];
-                }
-            }
+        }
+        for (int j = r - 1; j >= 0; --j) {
+            double acc = 0.0;
 #pragma unroll
             for (int sl = 0; sl < NS; ++sl) {
                 const int q = t8 + 8 * sl;
-                if (q < r) v[q] = t[sl];
+                if (q > j && q < r) acc += t[sl] * A[q * r + j];
             }
+            acc = group_sum<8>(acc);   // the row's eight lanes, DPP
+            if (t8 == (j & 7)) {
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl)
+                    if (sl == (j >> 3)) t[sl] -= acc;
+            }
+        }
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const int q = t8 + 8 * sl;
+            if (q < r) v[pmv[q]] = t[sl];
+        }
+    }
+}
+
+// identity r x r blocks at aj_off[b] (the right-hand sides of C^{-1})
+__global__ void k_eye(ClusterArgs ca, double *out)
+{
+    const int b = blockIdx.x;
+    const int r = ca.rank[ca.clusters[b]];
+    double *o = out + ca.aj_off[b];
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) o[e] = (e / r == e % r) ? 1.0 : 0.0;
+}
+
+// Z = Vbar C^{-T} per cluster (row i of Z solves C z = Vbar[i, :]^T) as a
+// product with the stored C^{-1}: 16 x 16 tiles over (row of Vbar, column of
+// Z) on the matrix cores (v_mfma_f64_16x16x4, mfma.h), the sum over the r
+// columns of Vbar in steps of four; the four wavefronts take every fourth
+// tile.
+__global__ void __launch_bounds__(256) k_cinv_apply(ClusterArgs ca, const double *Cinv, const double *Vbar,
+                                                    double *Z)
+{
+    const int b = blockIdx.x;
+    const int c = ca.clusters[b];
+    const int r = ca.rank[c];
+    const int m = (int)(ca.arow_off[c + 1] - ca.arow_off[c]);
+    const double *Ci = Cinv + ca.c_off[b];
+    const double *Vb = Vbar + ca.aj_off[b];
+    double *Zb = Z + ca.aj_off[b];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4;
+    const int ntc = (r + 15) >> 4, nt = ((m + 15) >> 4) * ntc;
+    for (int tile = wv; tile < nt; tile += 4) {
+        const int i0 = (tile / ntc) * 16, l0 = (tile % ntc) * 16;
+        const int i = i0 + q, l = l0 + q;
+        Mfma<double>::acc_t acc = mfma_zero<double>();
+        for (int k0 = 0; k0 < r; k0 += 16) {
+            // the operands of four steps loaded before their products
+            double a[4], bb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + 4 * u + kq;
+                a[u] = (i < m && k < r) ? Vb[(int64_t)i * r + k] : 0.0;
+                bb[u] = (l < r && k < r) ? Ci[(int64_t)l * r + k] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = Mfma<double>::mma(a[u], bb[u], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = i0 + Mfma<double>::row(lane, v);
+            if (ii < m && l < r) Zb[(int64_t)ii * r + l] = acc[v];
         }
     }
 }
@@ -461,15 +458,25 @@ hipError_t launch_frozen_basis(gca_h2_s *h, hipStream_t s)
     default:
         return hipErrorInvalidValue;
     }
+    // C^{-1} from the identity's rows (Z serves as their buffer: r x r
+    // blocks at c_off, as many rows as the rank)
+    ClusterArgs ci = ca;
+    ci.arow_off = h->fz.d_roff;
+    ci.aj_off = h->fz.d_c_off;
+    hipLaunchKernelGGL(k_eye, dim3(nc), dim3(256), 0, s, ci, h->fz.d_Z);
     if (h->max_rank <= FZ_MAXR) {
         hipLaunchKernelGGL(k_lu_lds, dim3(nc), dim3(256), 0, s, ca, h->fz.d_AJ, h->fz.d_LU, h->fz.d_perm,
                            h->d_piv_off);
         hipLaunchKernelGGL(k_row_solve_lds, dim3(nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm, h->d_piv_off,
-                           h->fz.d_AJ, h->fz.d_Vh, 0);
+                           h->fz.d_AJ, h->fz.d_Vh);
+        hipLaunchKernelGGL(k_row_solve_lds, dim3(nc), dim3(256), 0, s, ci, h->fz.d_LU, h->fz.d_perm, h->d_piv_off,
+                           h->fz.d_Z, h->fz.d_Cinv);
     } else {
         hipLaunchKernelGGL(k_lu, dim3(nc), dim3(256), 0, s, ca, h->fz.d_AJ, h->fz.d_LU, h->fz.d_perm, h->d_piv_off);
         hipLaunchKernelGGL(k_row_solve, dim3(nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm, h->d_piv_off,
-                           h->fz.d_AJ, h->fz.d_Vh, h->fz.d_tmp, 0);
+                           h->fz.d_AJ, h->fz.d_Vh, h->fz.d_tmp);
+        hipLaunchKernelGGL(k_row_solve, dim3(nc), dim3(256), 0, s, ci, h->fz.d_LU, h->fz.d_perm, h->d_piv_off,
+                           h->fz.d_Z, h->fz.d_Cinv, h->fz.d_tmp);
     }
     hipLaunchKernelGGL(k_unit_rows, dim3(nc), dim3(256), 0, s, ca, h->fz.d_Vh);
     return hipGetLastError();
@@ -479,12 +486,8 @@ hipError_t launch_frozen_basis(gca_h2_s *h, hipStream_t s)
 hipError_t launch_frozen_adjoint_solve(gca_h2_s *h, hipStream_t s)
 {
     ClusterArgs ca = cluster_args(h);
-    if (h->max_rank <= FZ_MAXR)
-        hipLaunchKernelGGL(k_row_solve_lds, dim3((unsigned)h->nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm,
-                           h->d_piv_off, h->fz.d_Vbar, h->fz.d_Z, 1);
-    else
-        hipLaunchKernelGGL(k_row_solve, dim3((unsigned)h->nc), dim3(256), 0, s, ca, h->fz.d_LU, h->fz.d_perm,
-                           h->d_piv_off, h->fz.d_Vbar, h->fz.d_Z, h->fz.d_tmp, 1);
+    hipLaunchKernelGGL(k_cinv_apply, dim3((unsigned)h->nc), dim3(256), 0, s, ca, h->fz.d_Cinv, h->fz.d_Vbar,
+                       h->fz.d_Z);
     return hipGetLastError();
 }
 

@@ -1150,6 +1150,7 @@ gca_status frozen_setup(gca_h2_s *h, hipStream_t s)
     for (int c = 0; c < nc; ++c) batch[c] = c;
     fz.aj_off.assign(nc, 0);
     fz.c_off.assign(nc, 0);
+    std::vector<int64_t> roff(nc + 1, 0);
     int64_t aj = 0, cc = 0;
     for (int c = 0; c < nc; ++c) {
         const int64_t m = h->arow_off[c + 1] - h->arow_off[c];
@@ -1157,6 +1158,7 @@ gca_status frozen_setup(gca_h2_s *h, hipStream_t s)
         fz.c_off[c] = cc;
         aj += m * h->rank[c];
         cc += (int64_t)h->rank[c] * h->rank[c];
+        roff[c + 1] = roff[c] + h->rank[c];
     }
     fz.n_aj = aj;
     fz.n_c = cc;
@@ -1167,12 +1169,14 @@ gca_status frozen_setup(gca_h2_s *h, hipStream_t s)
     GCA_TRY(upload_new(h, &fz.d_arows, h->arows, s));
     GCA_TRY(upload_new(h, &fz.d_aj_off, fz.aj_off, s));
     GCA_TRY(upload_new(h, &fz.d_c_off, fz.c_off, s));
+    GCA_TRY(upload_new(h, &fz.d_roff, roff, s));
     GCA_TRY(dalloc(h, &fz.d_AJ, aj));
     GCA_TRY(dalloc(h, &fz.d_Vh, aj));
     GCA_TRY(dalloc(h, &fz.d_tmp, aj));
     GCA_TRY(dalloc(h, &fz.d_Vbar, aj));
     GCA_TRY(dalloc(h, &fz.d_Z, aj));
     GCA_TRY(dalloc(h, &fz.d_LU, cc));
+    GCA_TRY(dalloc(h, &fz.d_Cinv, cc));
     GCA_TRY(dalloc(h, &fz.d_perm, h->n_piv));
     // copies of V^ into the leaf bases and transfer matrices
     std::vector<int64_t> vj, ej;

@@ -176,10 +176,12 @@ struct Frozen {
     int64_t *d_arow_off = nullptr;
     int32_t *d_arows = nullptr;
     int64_t *d_aj_off = nullptr, *d_c_off = nullptr;
+    int64_t *d_roff = nullptr;       // nc + 1: prefix sums of the ranks (cluster order)
     std::vector<int64_t> aj_off, c_off;
     int64_t n_aj = 0, n_c = 0;
     double *d_AJ = nullptr, *d_Vh = nullptr, *d_tmp = nullptr, *d_LU = nullptr;
     double *d_Vbar = nullptr, *d_Z = nullptr;
+    double *d_Cinv = nullptr;        // C^{-1} = A^[I, J]^{-1} per cluster (r x r at c_off)
     int32_t *d_perm = nullptr;
     int64_t *d_copy_jobs = nullptr;  // V / E copies from d_Vh
     int32_t n_vjobs = 0, n_ejobs = 0;

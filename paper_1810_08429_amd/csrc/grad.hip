@@ -20,6 +20,7 @@
 
 #include "gca_internal.h"
 #include "devfn.h"
+#include "mfma.h"
 
 namespace gca {
 
@@ -493,9 +494,13 @@ __global__ void k_vbar(const int32_t *node, const int32_t *rank, const int64_t *
     }
 }
 
-// Abar = Z, minus (V^T Z)[k, :] on pivot row I_k (W kept in tmp)
-__global__ void k_abar(const int32_t *rank, const int64_t *piv_off, const int32_t *pivrow, const int64_t *arow_off,
-                       const int64_t *aj_off, const double *Vh, double *Z, double *tmp)
+// Abar = Z, minus (V^T Z)[k, :] on pivot row I_k (W kept in tmp).  W = V^T Z
+// in 16 x 16 tiles on the matrix cores (v_mfma_f64_16x16x4, mfma.h): the
+// four wavefronts take every fourth tile, each a sum over the m rows in
+// steps of four.
+__global__ void __launch_bounds__(256) k_abar(const int32_t *rank, const int64_t *piv_off, const int32_t *pivrow,
+                                              const int64_t *arow_off, const int64_t *aj_off, const double *Vh,
+                                              double *Z, double *tmp)
 {
     const int c = blockIdx.x;
     const int r = rank[c];
@@ -503,11 +508,29 @@ __global__ void k_abar(const int32_t *rank, const int64_t *piv_off, const int32_
     const double *V = Vh + aj_off[c];
     double *Zc = Z + aj_off[c];
     double *W = tmp + aj_off[c];
-    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
-        const int k = e / r, l = e - k * r;
-        double s = 0;
-        for (int i = 0; i < m; ++i) s += V[(int64_t)i * r + k] * Zc[(int64_t)i * r + l];
-        W[e] = s;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4;
+    const int nt = (r + 15) >> 4;
+    for (int tile = wv; tile < nt * nt; tile += 4) {
+        const int k0 = (tile / nt) * 16, l0 = (tile % nt) * 16;
+        const int k = k0 + q, l = l0 + q;
+        Mfma<double>::acc_t acc = mfma_zero<double>();
+        for (int i0 = 0; i0 < m; i0 += 16) {
+            // the operands of four steps loaded before their products
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 4 * u + kq;
+                a[u] = (i < m && k < r) ? V[(int64_t)i * r + k] : 0.0;
+                b[u] = (i < m && l < r) ? Zc[(int64_t)i * r + l] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = Mfma<double>::mma(a[u], b[u], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = k0 + Mfma<double>::row(lane, v);
+            if (kk < r && l < r) W[(int64_t)kk * r + l] = acc[v];
+        }
     }
     __syncthreads();
     const int32_t *I = pivrow + piv_off[c];
@@ -519,7 +542,7 @@ __global__ void k_abar(const int32_t *rank, const int64_t *piv_off, const int32_
 
 // derivative of sum_l Abar[i, l] A^[i, J_l] w.r.t. the row triangle's vertices
 template <int PA>
-__global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const int64_t *piv_off,
+__global__ void __launch_bounds__(128, 4) k_abar_grad(const int32_t *rank, const int64_t *piv_off,
                                                    const int32_t *pivcol, const int64_t *arow_off,
                                                    const int32_t *arows, const int64_t *aj_off, const double *box,
                                                    const double *qA, const double *xyz, const int32_t *tv, int m_green,
@@ -562,9 +585,12 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
         for (int l = threadIdx.x; l < r; l += blockDim.x) column(l, colz + 7 * l);
     __syncthreads();
     // rows of at most 32 (64): 4 (2) threads per row take every 4th (2nd)
-    // Green column; their sums are added in LDS in a fixed order
+    // Green column; their sums are added in LDS in a fixed order.  Per row
+    // point p (outer loop, its coordinates loaded once) the sum over the
+    // thread's Green columns H_p = sum_l grad_x(...) is folded at once into
+    // the three vertex gradients with the point's barycentric weights.
     constexpr int MAXG = PA <= 9 ? 4 : 1;
-    constexpr int NV = 1 + 3 * PA;
+    constexpr int NV = 10;                 // S and the three vertex gradients
     __shared__ double red[(MAXG == 1 ? 1 : 96) * NV];
     const int G = (MAXG >= 4 && m <= 32) ? 4 : (MAXG >= 2 && m <= 64) ? 2 : 1;
     const int RW = (int)blockDim.x / G, gq = threadIdx.x / RW, rt = threadIdx.x - gq * RW;
@@ -574,42 +600,58 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
         const int pos = active ? arows[ro + i] : 0;
         const double *pts = qA + (size_t)pos * PA * 4;
         double S = 0;          // sum_p W_p f_p weighted (for the d ln J term)
-        D3 Hp[PA];
-        for (int p = 0; p < PA; ++p) Hp[p] = {0, 0, 0};
+        D3 gk[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         const double *ab = Abar + aj_off[c] + (int64_t)(active ? i : 0) * r;
-        for (int l = gq; active && l < r; l += G) {
-            const double om = ab[l];
-            if (om == 0.0) continue;
-            double own[7];
-            if (!staged) column(l, own);
-            const double *cz = staged ? colz + 7 * l : own;
-            const double z[3] = {cz[0], cz[1], cz[2]};
-            const double scale = cz[6];
-            const bool single = scale > 0;
-            const D3 nn = {cz[3], cz[4], cz[5]};
-            for (int p = 0; p < PA; ++p) {
-                const D3 d = D3{pts[4 * p] - z[0], pts[4 * p + 1] - z[1], pts[4 * p + 2] - z[2]};
+#pragma unroll 1
+        for (int p = 0; active && p < PA; ++p) {
+            const double px = pts[4 * p], py = pts[4 * p + 1], pz = pts[4 * p + 2], pw = pts[4 * p + 3];
+            D3 Hs = {0, 0, 0};
+            // column l's point z, normal n and scale (single layer > 0)
+            auto term = [&](double om, D3 z, D3 nn, double scale) {
+                const D3 d = D3{px - z.x, py - z.y, pz - z.z};
                 const double ri = rsq<double>(dot(d, d)), ri3 = ri * ri * ri;
-                const double wq = pts[4 * p + 3] * om * scale;
-                if (single) {
+                const double wq = pw * om * scale;
+                if (scale > 0) {
                     S += wq * ri;                               // g = ri / 4 pi
-                    Hp[p] = Hp[p] + (-wq * ri3) * d;            // grad_x ri = -d ri^3
+                    Hs = Hs + (-wq * ri3) * d;                  // grad_x ri = -d ri^3
                 } else {
                     const double nd = dot(nn, d);
                     S += wq * nd * ri3;                         // dg/dn = n.d ri^3 / 4 pi
-                    Hp[p] = Hp[p] + wq * ri3 * (nn - (3.0 * nd * ri * ri) * d);
+                    Hs = Hs + wq * ri3 * (nn - (3.0 * nd * ri * ri) * d);
+                }
+            };
+            if (staged) {
+                // the next column's weight loaded while this one is evaluated
+                double om_next = gq < r ? ab[gq] : 0.0;
+                for (int l = gq; l < r; l += G) {
+                    const double om = om_next;
+                    if (l + G < r) om_next = ab[l + G];
+                    if (om == 0.0) continue;
+                    const double *cz = colz + 7 * l;
+                    term(om, D3{cz[0], cz[1], cz[2]}, D3{cz[3], cz[4], cz[5]}, cz[6]);
+                }
+            } else {
+                for (int l = gq; l < r; l += G) {
+                    const double om = ab[l];
+                    if (om == 0.0) continue;
+                    double cz[7];
+                    column(l, cz);
+                    term(om, D3{cz[0], cz[1], cz[2]}, D3{cz[3], cz[4], cz[5]}, cz[6]);
                 }
             }
+            double beta[3];
+            rule_beta(RA, p, beta);
+            for (int kk = 0; kk < 3; ++kk) gk[kk] = gk[kk] + beta[kk] * Hs;
         }
         if (G > 1) {
             __syncthreads();
             if (gq > 0 && active) {
                 double *o = red + ((size_t)(gq - 1) * RW + rt) * NV;
                 o[0] = S;
-                for (int p = 0; p < PA; ++p) {
-                    o[1 + 3 * p] = Hp[p].x;
-                    o[2 + 3 * p] = Hp[p].y;
-                    o[3 + 3 * p] = Hp[p].z;
+                for (int kk = 0; kk < 3; ++kk) {
+                    o[1 + 3 * kk] = gk[kk].x;
+                    o[2 + 3 * kk] = gk[kk].y;
+                    o[3 + 3 * kk] = gk[kk].z;
                 }
             }
             __syncthreads();
@@ -617,7 +659,8 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
                 for (int q = 1; q < G; ++q) {
                     const double *o = red + ((size_t)(q - 1) * RW + rt) * NV;
                     S += o[0];
-                    for (int p = 0; p < PA; ++p) Hp[p] = Hp[p] + D3{o[1 + 3 * p], o[2 + 3 * p], o[3 + 3 * p]};
+                    for (int kk = 0; kk < 3; ++kk)
+                        gk[kk] = gk[kk] + D3{o[1 + 3 * kk], o[2 + 3 * kk], o[3 + 3 * kk]};
                 }
         }
         if (gq != 0 || !active) continue;
@@ -626,15 +669,10 @@ __global__ void __launch_bounds__(128) k_abar_grad(const int32_t *rank, const in
         dlnJ(ldv3(xyz, v[0]), ldv3(xyz, v[1]), ldv3(xyz, v[2]), lj);
         double *out = gout + 9 * (ro + i);
         for (int kk = 0; kk < 3; ++kk) {
-            D3 gk = S * lj[kk];
-            for (int p = 0; p < PA; ++p) {
-                double beta[3];
-                rule_beta(RA, p, beta);
-                gk = gk + beta[kk] * Hp[p];
-            }
-            out[3 * kk] = gk.x;
-            out[3 * kk + 1] = gk.y;
-            out[3 * kk + 2] = gk.z;
+            const D3 g = S * lj[kk] + gk[kk];
+            out[3 * kk] = g.x;
+            out[3 * kk + 1] = g.y;
+            out[3 * kk + 2] = g.z;
         }
     }
 }

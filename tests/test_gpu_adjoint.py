@@ -88,6 +88,34 @@ def test_adjoint_matches_central_differences(torch, gca):
     H.update_geometry(m.verts)
 
 
+def test_adjoint_with_ranks_above_64_matches_central_differences(torch, gca):
+    """Green order 5 and eps 1e-9 on the level-4 sphere: cluster ranks above
+    64, so the factors of C = A^[I, J] and C^{-1} come from the global-memory
+    factorisation and row solves, and the products with C^{-1} span several
+    16-column tiles; checked against central differences as above."""
+    m = jittered(4, seed=19)
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, 64), gca.Params(eta=2.0, eps=1e-9, green_m=5))
+    assert H.stats()["rank_max"] > 64
+    u = torch.tensor(synth.rhs_normal(m.nt, 1, seed=8), device="cuda")
+    g = H.bilinear_grad(u, u, alpha=0.5).cpu().numpy()
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    scale = np.abs(g).max()
+    for v in rng.choice(m.nv, 4, replace=False):
+        for d in range(3):
+            xp, xm = m.verts.copy(), m.verts.copy()
+            xp[v, d] += h
+            xm[v, d] -= h
+            H.update_geometry(xp)
+            ep = frozen_energy(H, torch, u)
+            H.update_geometry(xm)
+            em = frozen_energy(H, torch, u)
+            fd = (ep - em) / (2 * h)
+            assert abs(fd - g[v, d]) <= 1e-6 * abs(g[v, d]) + 1e-7 * scale, (v, d, fd, g[v, d])
+    H.update_geometry(m.verts)
+    H.close()
+
+
 def test_adjoint_close_to_dense_gradient(torch, gca, orc):
     """The frozen-structure H^2 gradient approximates the gradient of the exact
     Galerkin energy (oracle, all pairs) to the compression tolerance."""
