@@ -494,13 +494,15 @@ __global__ void k_vbar(const int32_t *node, const int32_t *rank, const int64_t *
     }
 }
 
-// Abar = Z, minus (V^T Z)[k, :] on pivot row I_k (W kept in tmp).  W = V^T Z
-// in 16 x 16 tiles on the matrix cores (v_mfma_f64_16x16x4, mfma.h): the
-// four wavefronts take every fourth tile, each a sum over the m rows in
-// steps of four.
+// Abar = Z, minus (V^T Z)[k, :] on pivot row I_k (W kept in tmp), all m x r
+// row-major; then Abar is written column-major to At (At[l m + i]) through
+// LDS tiles, so that the Green-factor derivative kernel reads a column's
+// entries of consecutive rows together.  W = V^T Z in 16 x 16 tiles on the
+// matrix cores (v_mfma_f64_16x16x4, mfma.h): the four wavefronts take every
+// fourth tile, each a sum over the m rows in steps of four.
 __global__ void __launch_bounds__(256) k_abar(const int32_t *rank, const int64_t *piv_off, const int32_t *pivrow,
                                               const int64_t *arow_off, const int64_t *aj_off, const double *Vh,
-                                              double *Z, double *tmp)
+                                              double *Z, double *tmp, double *At)
 {
     const int c = blockIdx.x;
     const int r = rank[c];
@@ -538,9 +540,26 @@ __global__ void __launch_bounds__(256) k_abar(const int32_t *rank, const int64_t
         const int k = e / r, l = e - k * r;
         Zc[(int64_t)I[k] * r + l] -= W[e];
     }
+    __syncthreads();
+    __shared__ double tl[32][65];
+    double *Ac = At + aj_off[c];
+    for (int i0 = 0; i0 < m; i0 += 32)
+        for (int l0 = 0; l0 < r; l0 += 64) {
+            for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+                const int ii = e >> 6, ll = e & 63;
+                tl[ii][ll] = (i0 + ii < m && l0 + ll < r) ? Zc[(int64_t)(i0 + ii) * r + l0 + ll] : 0.0;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+                const int ll = e >> 5, ii = e & 31;
+                if (i0 + ii < m && l0 + ll < r) Ac[(int64_t)(l0 + ll) * m + i0 + ii] = tl[ii][ll];
+            }
+            __syncthreads();
+        }
 }
 
 // derivative of sum_l Abar[i, l] A^[i, J_l] w.r.t. the row triangle's vertices
+// (Abar column-major per cluster: Abar[l m + i])
 template <int PA>
 __global__ void __launch_bounds__(128, 4) k_abar_grad(const int32_t *rank, const int64_t *piv_off,
                                                    const int32_t *pivcol, const int64_t *arow_off,
@@ -601,7 +620,7 @@ __global__ void __launch_bounds__(128, 4) k_abar_grad(const int32_t *rank, const
         const double *pts = qA + (size_t)pos * PA * 4;
         double S = 0;          // sum_p W_p f_p weighted (for the d ln J term)
         D3 gk[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        const double *ab = Abar + aj_off[c] + (int64_t)(active ? i : 0) * r;
+        const double *ab = Abar + aj_off[c] + (active ? i : 0);   // column l at ab[l m]
 #pragma unroll 1
         for (int p = 0; active && p < PA; ++p) {
             const double px = pts[4 * p], py = pts[4 * p + 1], pz = pts[4 * p + 2], pw = pts[4 * p + 3];
@@ -622,17 +641,17 @@ __global__ void __launch_bounds__(128, 4) k_abar_grad(const int32_t *rank, const
             };
             if (staged) {
                 // the next column's weight loaded while this one is evaluated
-                double om_next = gq < r ? ab[gq] : 0.0;
+                double om_next = gq < r ? ab[(int64_t)gq * m] : 0.0;
                 for (int l = gq; l < r; l += G) {
                     const double om = om_next;
-                    if (l + G < r) om_next = ab[l + G];
+                    if (l + G < r) om_next = ab[(int64_t)(l + G) * m];
                     if (om == 0.0) continue;
                     const double *cz = colz + 7 * l;
                     term(om, D3{cz[0], cz[1], cz[2]}, D3{cz[3], cz[4], cz[5]}, cz[6]);
                 }
             } else {
                 for (int l = gq; l < r; l += G) {
-                    const double om = ab[l];
+                    const double om = ab[(int64_t)l * m];
                     if (om == 0.0) continue;
                     double cz[7];
                     column(l, cz);
@@ -865,15 +884,16 @@ hipError_t launch_bilinear_grad(gca_h2_s *h, const GradWs &w, hipStream_t s)
     hipLaunchKernelGGL(k_vbar<T>, dim3(nc), dim3(256), 0, s, h->d_node, h->d_rank, h->d_piv_off, h->fz.d_aj_off, ap,
                        bp, xa, xb, ya, yb, h->fz.d_Vbar);
     if ((e = launch_frozen_adjoint_solve(h, s)) != hipSuccess) return e;
+    // Abar column-major into the Vbar buffer (Vbar is consumed by now)
     hipLaunchKernelGGL(k_abar, dim3(nc), dim3(256), 0, s, h->d_rank, h->d_piv_off, h->fz.d_pivrow,
-                       h->fz.d_arow_off, h->fz.d_aj_off, h->fz.d_Vh, h->fz.d_Z, h->fz.d_tmp);
+                       h->fz.d_arow_off, h->fz.d_aj_off, h->fz.d_Vh, h->fz.d_Z, h->fz.d_tmp, h->fz.d_Vbar);
     const int PA = h->prm.q_A * h->prm.q_A;
     switch (PA) {
 #define CASE(PP)                                                                                              \
     case PP:                                                                                                  \
         hipLaunchKernelGGL((k_abar_grad<PP>), dim3(nc), dim3(128), 0, s, h->d_rank, h->d_piv_off, h->fz.d_pivcol, \
                            h->fz.d_arow_off, h->fz.d_arows, h->fz.d_aj_off, h->d_box, h->d_qA, h->d_xyz, h->d_tv, \
-                           h->prm.green_m, h->prm.eta, h->prm.omega_scale, Rg, RA, h->fz.d_Z, w.gb);            \
+                           h->prm.green_m, h->prm.eta, h->prm.omega_scale, Rg, RA, h->fz.d_Vbar, w.gb);            \
         break;
         CASE(1) CASE(4) CASE(9) CASE(16) CASE(25) CASE(36)
 #undef CASE
