@@ -581,8 +581,7 @@ __global__ void __launch_bounds__(128, 4) k_abar_grad(const int32_t *rank, const
         H[d] = bx[3 + d] + delta;
     }
     // Green column l of the cluster: point z, outward normal n, and the scale
-    // of the single-layer (> 0) or double-layer (< 0) column; staged in LDS
-    // once per cluster when the rank allows
+    // of the single-layer (> 0) or double-layer (< 0) column
     auto column = [&](int l, double *o) {
         const int col = pivcol[piv_off[c] + l];
         const int nu = col < k ? col : col - k;
@@ -597,17 +596,15 @@ __global__ void __launch_bounds__(128, 4) k_abar_grad(const int32_t *rank, const
         const double w = G_.w[gi] * G_.w[gj] * (H[b1] - L[b1]) * (H[b2] - L[b2]);
         o[6] = col < k ? sqrt(w) * INV4PI_G : -diam * sqrt(w) * INV4PI_G;
     };
-    constexpr int CMAX = 64;
+    // Green columns staged in LDS 64 at a time
+    constexpr int CMAX = 64, CH = 4;
     __shared__ double colz[CMAX * 7];
-    const bool staged = r <= CMAX;
-    if (staged)
-        for (int l = threadIdx.x; l < r; l += blockDim.x) column(l, colz + 7 * l);
-    __syncthreads();
     // rows of at most 32 (64): 4 (2) threads per row take every 4th (2nd)
-    // Green column; their sums are added in LDS in a fixed order.  Per row
-    // point p (outer loop, its coordinates loaded once) the sum over the
-    // thread's Green columns H_p = sum_l grad_x(...) is folded at once into
-    // the three vertex gradients with the point's barycentric weights.
+    // Green column; their sums are added in LDS in a fixed order.  A thread
+    // takes its columns CH at a time: their weights Abar[i, l] are loaded
+    // once, then per row point p (coordinates loaded once per chunk) the sum
+    // over the chunk H_p = sum_l grad_x(...) is folded at once into the three
+    // vertex gradients with the point's barycentric weights.
     constexpr int MAXG = PA <= 9 ? 4 : 1;
     constexpr int NV = 10;                 // S and the three vertex gradients
     __shared__ double red[(MAXG == 1 ? 1 : 96) * NV];
@@ -621,46 +618,49 @@ __global__ void __launch_bounds__(128, 4) k_abar_grad(const int32_t *rank, const
         double S = 0;          // sum_p W_p f_p weighted (for the d ln J term)
         D3 gk[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         const double *ab = Abar + aj_off[c] + (active ? i : 0);   // column l at ab[l m]
+        for (int lb = 0; lb < r; lb += CMAX) {
+            const int le = min(r, lb + CMAX);
+            __syncthreads();   // the previous block's columns are no longer read
+            for (int l = lb + (int)threadIdx.x; l < le; l += blockDim.x) column(l, colz + 7 * (l - lb));
+            __syncthreads();
+            for (int l0 = lb + gq; l0 < le; l0 += CH * G) {
+                // weights of the chunk's columns (0 past the block: those
+                // read the block's last column and add exactly 0)
+                double om[CH];
+                int lz[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int l = l0 + u * G;
+                    om[u] = (active && l < le) ? ab[(int64_t)l * m] : 0.0;
+                    lz[u] = 7 * (min(l, le - 1) - lb);
+                }
 #pragma unroll 1
-        for (int p = 0; active && p < PA; ++p) {
-            const double px = pts[4 * p], py = pts[4 * p + 1], pz = pts[4 * p + 2], pw = pts[4 * p + 3];
-            D3 Hs = {0, 0, 0};
-            // column l's point z, normal n and scale (single layer > 0)
-            auto term = [&](double om, D3 z, D3 nn, double scale) {
-                const D3 d = D3{px - z.x, py - z.y, pz - z.z};
-                const double ri = rsq<double>(dot(d, d)), ri3 = ri * ri * ri;
-                const double wq = pw * om * scale;
-                if (scale > 0) {
-                    S += wq * ri;                               // g = ri / 4 pi
-                    Hs = Hs + (-wq * ri3) * d;                  // grad_x ri = -d ri^3
-                } else {
-                    const double nd = dot(nn, d);
-                    S += wq * nd * ri3;                         // dg/dn = n.d ri^3 / 4 pi
-                    Hs = Hs + wq * ri3 * (nn - (3.0 * nd * ri * ri) * d);
-                }
-            };
-            if (staged) {
-                // the next column's weight loaded while this one is evaluated
-                double om_next = gq < r ? ab[(int64_t)gq * m] : 0.0;
-                for (int l = gq; l < r; l += G) {
-                    const double om = om_next;
-                    if (l + G < r) om_next = ab[(int64_t)(l + G) * m];
-                    if (om == 0.0) continue;
-                    const double *cz = colz + 7 * l;
-                    term(om, D3{cz[0], cz[1], cz[2]}, D3{cz[3], cz[4], cz[5]}, cz[6]);
-                }
-            } else {
-                for (int l = gq; l < r; l += G) {
-                    const double om = ab[(int64_t)l * m];
-                    if (om == 0.0) continue;
-                    double cz[7];
-                    column(l, cz);
-                    term(om, D3{cz[0], cz[1], cz[2]}, D3{cz[3], cz[4], cz[5]}, cz[6]);
+                for (int p = 0; active && p < PA; ++p) {
+                    const double px = pts[4 * p], py = pts[4 * p + 1], pz = pts[4 * p + 2], pw = pts[4 * p + 3];
+                    D3 Hs = {0, 0, 0};
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        // column point z, normal n and scale (single layer > 0)
+                        const double *cz = colz + lz[u];
+                        const double scale = cz[6];
+                        const D3 d = D3{px - cz[0], py - cz[1], pz - cz[2]};
+                        const double ri = rsq<double>(dot(d, d)), ri3 = ri * ri * ri;
+                        const double wq = pw * om[u] * scale;
+                        if (scale > 0) {
+                            S += wq * ri;                               // g = ri / 4 pi
+                            Hs = Hs + (-wq * ri3) * d;                  // grad_x ri = -d ri^3
+                        } else {
+                            const D3 nn = {cz[3], cz[4], cz[5]};
+                            const double nd = dot(nn, d);
+                            S += wq * nd * ri3;                         // dg/dn = n.d ri^3 / 4 pi
+                            Hs = Hs + wq * ri3 * (nn - (3.0 * nd * ri * ri) * d);
+                        }
+                    }
+                    double beta[3];
+                    rule_beta(RA, p, beta);
+                    for (int kk = 0; kk < 3; ++kk) gk[kk] = gk[kk] + beta[kk] * Hs;
                 }
             }
-            double beta[3];
-            rule_beta(RA, p, beta);
-            for (int kk = 0; kk < 3; ++kk) gk[kk] = gk[kk] + beta[kk] * Hs;
         }
         if (G > 1) {
             __syncthreads();
