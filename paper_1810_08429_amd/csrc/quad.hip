@@ -1106,7 +1106,8 @@ template hipError_t launch_far_blocks_nb<double>(gca_h2_s *, const double *, dou
 // row-major at g_soff) gives the row partials G_g x_cols and the column
 // partials G_g^T x_rows from one read of every entry.  Wavefront w streams
 // the rows i = w mod 4 (each a contiguous run of nc entries, lanes over
-// columns): the row sum is reduced across the wavefront by shuffles, the
+// columns): the row sum is reduced across the wavefront (DPP, then two
+// cross-row moves), the
 // column sums stay in registers (up to APPLY_CB columns at a time) and are
 // combined over the four wavefronts in LDS.  One writer per partial slot.
 constexpr int APPLY_K = 4;                 // column registers per lane
@@ -1184,7 +1185,7 @@ __global__ void __launch_bounds__(BLK_THREADS) k_rows_apply(ApplyArgs<T> a)
                     v += gr[q][k] * xc[k];
                     ca[k] += gr[q][k] * xi[q];
                 }
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                v = class_sum<1>(v, lane);   // DPP within rows of 16, then lane ^ 16, lane ^ 32
                 const int i = i0 + q * BLK_WAVES;
                 if (lane == 0 && i < nr) {
                     if (cb == 0)
