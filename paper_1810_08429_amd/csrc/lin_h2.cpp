@@ -38,6 +38,10 @@ namespace {
 constexpr int CHUNK_V = GCA_LIN_MAX_BLOCK_SET;   // vertices of a chunk at most
 constexpr int CHUNK_T = GCA_LIN_MAX_TRIS;        // sum of |T_v| over a chunk at most (merged rows)
 constexpr int BATCH = 2048;                      // sub-blocks per assembly launch
+// product sub-blocks: a stored block is applied in column pieces of about
+// PIECE entries (at least 8 columns), one wavefront each, so that the large
+// coupling blocks are shared by several wavefronts
+constexpr int64_t PIECE = 4096;
 
 template <typename T>
 gca_status alloc_n(gca_h2_s *h, T **p, size_t n)
@@ -277,7 +281,8 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
         for (size_t b = 0; b < bt.size(); ++b) per[tpos[bt[b]]].push_back(bs[b]);
         // stored blocks: every block (t, u) whole, column-major with leading
         // dimension the rows of t; assembled in chunk sub-blocks (the pair-wise
-        // kernels' limits) that the compaction puts in place
+        // kernels' limits) that the compaction puts in place, and applied in
+        // column pieces with a partial-sum slot each
         std::vector<int64_t> sub_ptr{0}, goff, srcoff, poff, dst;
         std::vector<int32_t> meta, smeta, br, bc;
         int64_t off = 0, prow = 0;
@@ -287,10 +292,14 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
             std::sort(per[g].begin(), per[g].end());
             for (int u : per[g]) {
                 const int ncu = ch[u].back();
-                meta.insert(meta.end(), {nrt, ncu, 0});
-                goff.push_back(off);
-                poff.push_back(prow);
-                srcoff.push_back(farb ? h->piv_off[u] : nodes[u].begin);
+                const int wmax = (int)std::max<int64_t>(8, PIECE / std::max(nrt, 1));
+                for (int c0 = 0; c0 < ncu; c0 += wmax) {
+                    meta.insert(meta.end(), {nrt, std::min(wmax, ncu - c0), 0});
+                    goff.push_back(off + (int64_t)c0 * nrt);
+                    poff.push_back(prow);
+                    srcoff.push_back((farb ? h->piv_off[u] : nodes[u].begin) + c0);
+                    prow += nrt;
+                }
                 for (size_t cb = 0; cb + 1 < ch[u].size(); ++cb)
                     for (size_t rb = 0; rb + 1 < ch[t].size(); ++rb) {
                         const int nr = ch[t][rb + 1] - ch[t][rb], ncol = ch[u][cb + 1] - ch[u][cb];
@@ -300,7 +309,6 @@ gca_status build_lin(const gca_mesh *mesh, int32_t leaf, const gca_params *p, hi
                         bc.push_back(set0[u] + (int32_t)cb);
                     }
                 off += (int64_t)nrt * ncu;
-                prow += nrt;
             }
             sub_ptr.push_back((int64_t)goff.size());
         }

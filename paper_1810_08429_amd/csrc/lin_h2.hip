@@ -1,8 +1,9 @@
 // Product kernels of the nodal-basis GCA-H^2 handle (Sections 2-5 with one
 // basis function per vertex, Section 5): the coupling matrices G|t~ x s~ and
-// the nearfield blocks are stored at build time as sub-blocks (pivot or leaf
-// chunks small enough for the pair-wise assembly); the forward and backward
-// transforms are those of the piecewise-constant handle (h2.hip).  FP64.
+// the nearfield blocks are stored whole at build time (column-major) and
+// applied in column pieces, one wavefront each, whose partial row sums are
+// added per target; the forward and backward transforms are those of the
+// piecewise-constant handle (h2.hip).  FP64.
 #include <hip/hip_runtime.h>
 
 #include "gca_internal.h"
@@ -10,12 +11,12 @@
 namespace gca {
 namespace {
 
-constexpr int AW = 4;          // wavefronts per workgroup: one sub-block each
+constexpr int AW = 4;          // wavefronts per workgroup: one piece each
 
-// Row sums of one stored block per wavefront: entries column-major (G[j nr +
-// i]: a column is one coalesced load per 64 rows); blocks of up to 32 rows
-// let the two half-wavefronts take the even and the odd columns; four
-// columns per lane in flight.
+// Row sums of one column piece of a stored block per wavefront: entries
+// column-major (G[j nr + i]: a column is one coalesced load per 64 rows);
+// blocks of up to 32 rows let the two half-wavefronts take the even and the
+// odd columns; four columns per lane in flight.
 __global__ void __launch_bounds__(64 * AW) k_lin_sub(LinApply a, const double *src)
 {
     const int64_t b = (int64_t)blockIdx.x * AW + (threadIdx.x >> 6);
