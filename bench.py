@@ -57,6 +57,7 @@ METRIC = "H² matvec DoF/s + setup s at 1e-4 rel err: mixed vs FP64 plain, % roo
 VALU_LANE_OPS_PER_S = 256 * 128 * 2.4e9
 TRANS_LANE_OPS_PER_S = VALU_LANE_OPS_PER_S / 4
 FLOPS_PER_EVAL = 10
+GRAD_FLOPS_PER_EVAL = 18
 EVALS_PER_S_F32 = 1.0 / (5.0 / VALU_LANE_OPS_PER_S + 1.0 / TRANS_LANE_OPS_PER_S)
 ISSUE_CEILING_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
 # the published FP32 vector peak of the chip (packed FP32 FMA: 256 CUs x
@@ -752,6 +753,21 @@ def main():
                 "kernel": kname, "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom],
                 "timing": "HIP events around the kernel on its stream in the timed products, where the "
                           "transform chain and the touching lists run beside it on the handle's side streams"}
+    if a.grad_steps > 0:
+        # block derivatives of the adjoint: every ordered pair of the
+        # nearfield and coupling blocks (both orientations), per evaluation
+        # 18 flops (difference, |d|^2, w/r, its sum, w/r^3 and the 3-vector
+        # accumulation; the rsqrt not counted)
+        gev = 2 * (st["near_regular_pairs"] * P * P + st["coupling_entries"] * Pc * Pc)
+        gfl = gev * GRAD_FLOPS_PER_EVAL
+        ag = gfl / (grad["mixed"]["ms_per_step"] * 1e-3) / 1e12
+        grad["roofline"] = {
+            "bound": "alu", "achieved": ag, "peak": PUBLISHED_F32_TFLOPS, "unit": "TFLOP/s",
+            "frac": ag / PUBLISHED_F32_TFLOPS, "evaluations": gev, "flops": gfl,
+            "kernel": "k_grad_blocks<float,%d,true> and k_grad_blocks<float,%d,false>" % (P, Pc),
+            "timing": "the whole mixed h2_bilinear_grad call (basis terms, pair lists and transforms "
+                      "included), so a lower bound of the block kernels' own rate; their own times are "
+                      "in the committed kernel trace of the gradient"}
     if serial is not None:
         a_ser = work[dom] / (serial["phases_ms"][dom] * 1e-3) / 1e12
         roofline["alone"] = {"avg_ms": serial["phases_ms"][dom], "achieved": a_ser,
