@@ -312,7 +312,7 @@ constexpr size_t grad_blk_smem(int cw)
 }
 
 template <typename T, int P, bool NEAR>
-__global__ void __launch_bounds__(128) k_grad_blocks(GradBlkArgs<T> g)
+__global__ void __launch_bounds__(128, (sizeof(T) == 4 && P <= 6 ? 4 : 1)) k_grad_blocks(GradBlkArgs<T> g)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = blockIdx.x, tid = threadIdx.x;
