@@ -17,7 +17,9 @@ after the products (`energy_gradient`), and so is the stored-block mode
 (`stored_blocks`: block rows computed once, products read them).  The
 piecewise-linear nodal basis (`linear_basis`) is measured on the same mesh:
 the merge of vertex-subset triangle lists and FP64 Galerkin blocks assembled
-triangle pair by triangle pair, against its own FP64 ceiling.
+triangle pair by triangle pair, against its own FP64 ceiling.  The refined
+solve of G u = f (mixed CG inside FP64 refinement to 1e-8) is timed on the
+level-7 sphere (`solve_level7`).
 
 The roofline object describes the dominant kernel of the mixed product, timed
 with the library's per-product HIP events over the timed steps: `frac` is
@@ -185,6 +187,8 @@ def parse():
                     help="timed products per precision in stored-block mode (0 disables it)")
     ap.add_argument("--grad-steps", type=int, default=3,
                     help="timed calls of the energy gradient per precision (0 disables it)")
+    ap.add_argument("--solve-steps", type=int, default=1,
+                    help="timed refined solves on the level-7 sphere (0: skip)")
     ap.add_argument("--nodal-level", type=int, default=7,
                     help="sphere level of the nodal-basis H2 timing leg (0: skip)")
     ap.add_argument("--lin-blocks", type=int, default=16384,
@@ -206,6 +210,52 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (calibrates the PMC byte counters)")
     return ap.parse_args()
+
+
+def solve_leg(gca, torch, steps):
+    """The level-7 sphere (327,680 triangles) with the settings of the
+    level-8 operating point (leaf 64, eta 2, Green order 5, omega margin 1.5,
+    eps 1e-5, coupling order 2, symmetric rules): G u = f with
+    f_i = int_{t_i} x_3 solved by CG on the mixed product inside FP64
+    refinement to a relative residual of 1e-8 (gca_solve_refined).  Setup and
+    solve wall times, the iteration counts, and the L2 distance of u to the
+    exact density 3 x_3 of the unit sphere (the best piecewise-constant
+    approximation is itself O(h) away)."""
+    import synth
+    m = synth.icosphere(7)
+    _, prm = synth.workload("sphere_l8")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = gca.Params(eta=prm["eta"], eps=prm["eps"], green_m=prm["green_m"], omega_scale=prm["omega_scale"])
+    p.q_c = prm["q_c"]
+    p.sym_rules = prm["sym_rules"]
+    H = gca.H2(m.verts, m.tris, gca.Tree(m.verts, m.tris, prm["leaf"]), p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    T = m.verts[m.tris]
+    area = 0.5 * np.linalg.norm(np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]), axis=1)
+    c = T.mean(axis=1)
+    f = torch.tensor(area * c[:, 2], device="cuda")
+    H.solve(f, rtol=1e-8, max_inner=2000)   # untimed: the solver's workspaces
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        u, outer, inner, rel = H.solve(f, rtol=1e-8, max_inner=2000)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    uu = u.cpu().numpy()
+    exact = 3.0 * c[:, 2]
+    err = float(np.sqrt(np.sum(area * (uu - exact) ** 2) / np.sum(area * exact ** 2)))
+    H.close()
+    res = {"workload": "unit icosphere level 7, 327680 flat triangles, the level-8 operating point's settings "
+                       "(leaf 64, eta 2, Green order 5, omega margin 1.5, ACA eps 1e-5, coupling order 2, symmetric "
+                       "rules); f_i = int_{t_i} x_3; mixed-precision CG inside FP64 refinement to 1e-8",
+           "n": int(m.nt), "setup_s": t_setup, "solve_ms": dt * 1e3, "steps": steps, "outer": int(outer),
+           "inner": int(inner), "relres": float(rel), "density_rel_err_l2": err}
+    print(f"[bench] solve level 7 (n = {m.nt}): setup {t_setup:.2f} s, solve {dt * 1e3:.1f} ms "
+          f"({outer} refinement steps, {inner} CG iterations, residual {rel:.1e}), |u - 3 x3| {err:.2e}",
+          file=sys.stderr, flush=True)
+    return res
 
 
 def lin_h2(gca, torch, level_time, level_err=5, steps=10, leaf=32):
@@ -733,6 +783,7 @@ def main():
     if a.lin_blocks > 0:
         linear = linear_basis(gca, torch, mesh, a.lin_blocks, max(a.stored_steps, 3), 2)
     nodal = lin_h2(gca, torch, a.nodal_level) if a.nodal_level > 0 else None
+    solve = solve_leg(gca, torch, a.solve_steps) if a.solve_steps > 0 else None
 
     phases = gca.PHASES
     mean_mixed = dict(zip(phases, ph_mixed.mean(axis=0).tolist()))
@@ -845,6 +896,7 @@ def main():
         "stored_blocks": stored,
         "linear_basis": linear,
         "nodal_h2": nodal,
+        "solve_level7": solve,
         "double_layer": dl,
         "curved": curv,
         "mixed_over_fp64": dt_fp64 / dt_mixed,
