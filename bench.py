@@ -65,6 +65,7 @@ ISSUE_CEILING_F32_TFLOPS = EVALS_PER_S_F32 * FLOPS_PER_EVAL / 1e12
 # the published FP32 vector peak of the chip (packed FP32 FMA: 256 CUs x
 # 2.4 GHz x 128 lanes x 2 flops)
 PUBLISHED_F32_TFLOPS = 157.3
+PUBLISHED_F64_TFLOPS = 78.6     # FP64 vector and FP64 matrix peak
 
 
 # FP64 ceiling of one dimension-reduced Sauter-Schwab evaluation (the
@@ -772,6 +773,13 @@ def main():
                             "block_rows_GBps": stored["bytes"][name] / (blk_ms * 1e-3) / 1e9,
                             "rel_diff_vs_recomputed": float(torch.linalg.norm(ys - yref) / torch.linalg.norm(yref)),
                             "phases_ms": pm}
+            gbps = stored["bytes"][name] / (blk_ms * 1e-3) / 1e9
+            stored[name]["roofline"] = {
+                "bound": "hbm", "achieved": gbps, "peak": HBM_BYTES_PER_S / 1e9, "unit": "GB/s",
+                "frac": gbps * 1e9 / HBM_BYTES_PER_S,
+                "bytes": stored["bytes"][name], "kernel": "k_rows_apply",
+                "timing": "the coupling and nearfield block-row launches (HIP events per phase), their times "
+                          "added although they run on two streams at once, so a lower bound"}
             print(f"[bench] stored blocks {name}: {dt * 1e3:.3f} ms/product, block rows "
                   f"{stored[name]['block_rows_GBps']:.0f} GB/s", file=sys.stderr, flush=True)
         H.store_blocks(False, False)
@@ -804,6 +812,20 @@ def main():
                 "kernel": kname, "phase": dom, "avg_ms": mean_mixed[dom], "flops_per_launch": work[dom],
                 "timing": "HIP events around the kernel on its stream in the timed products, where the "
                           "transform chain and the touching lists run beside it on the handle's side streams"}
+    if rhs16 is not None:
+        # dominant kernel of the batched product: the nearfield block rows,
+        # per unordered regular pair P^2 evaluations (10 flops each) and the
+        # two 16-column products of the entry on the matrix cores (64 flops)
+        for name in ("mixed", "fp64"):
+            ms16 = rhs16[name]["phases_ms"]["near_blocks"]
+            fl = st["near_regular_pairs"] * (P * P * FLOPS_PER_EVAL + 64)
+            ach = fl / (ms16 * 1e-3) / 1e12
+            pk = PUBLISHED_F32_TFLOPS if name == "mixed" else PUBLISHED_F64_TFLOPS
+            rhs16[name]["roofline"] = {
+                "bound": "alu", "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk, "flops": fl,
+                "kernel": "k_near_rows_nb<%s,%d>" % ("float" if name == "mixed" else "double", P), "avg_ms": ms16,
+                "timing": "HIP events around the kernel in the timed batched products (the transform chain and "
+                          "the touching lists run beside it)"}
     if a.grad_steps > 0:
         # block derivatives of the adjoint: every ordered pair of the
         # nearfield and coupling blocks (both orientations), per evaluation
