@@ -1,6 +1,7 @@
 // Device helpers shared by the kernels: reciprocal square roots, cross-lane
-// sums inside a wavefront by DPP (no LDS round trip) and an XCD-aware
-// workgroup order.
+// sums inside a wavefront by DPP (no LDS round trip) and the moves between
+// its rows of 16 lanes, sums over slot lists, and an XCD-aware workgroup
+// order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,6 +50,31 @@ __device__ __forceinline__ T group_sum(T v)
     if constexpr (N >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
     if constexpr (N >= 16) v += dpp_mov<0x140>(v);  // row_mirror
     return v;
+}
+
+// Cross-lane moves for the tile reductions: DPP (above) within a row of 16
+// lanes, an LDS swizzle for lane ^ 16 and a permute for lane ^ 32 (64-bit
+// values move as two 32-bit halves).  Every lane of the wavefront must be
+// active.
+__device__ __forceinline__ float xor16_mov(float v)
+{   // ds_swizzle bit mode within 32 lanes: and 0x1f, or 0, xor 0x10
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+__device__ __forceinline__ double xor16_mov(double v)
+{
+    const int2 h = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, int2{__builtin_amdgcn_ds_swizzle(h.x, 0x401F),
+                                           __builtin_amdgcn_ds_swizzle(h.y, 0x401F)});
+}
+__device__ __forceinline__ float xor32_mov(float v, int addr)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double xor32_mov(double v, int addr)
+{
+    const int2 h = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, int2{__builtin_amdgcn_ds_bpermute(addr, h.x),
+                                           __builtin_amdgcn_ds_bpermute(addr, h.y)});
 }
 
 // sum_{q in [b, e)} part[slots[q] * stride + x] on four partial sums (slots

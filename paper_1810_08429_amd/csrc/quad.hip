@@ -127,31 +127,6 @@ __device__ __forceinline__ T block_entry(const Q4<T> (&rp)[P], const T (&rn)[P],
     return acc;
 }
 
-// Cross-lane moves for the tile reductions: DPP (devfn.h) within a row of 16
-// lanes, an LDS swizzle for lane ^ 16 and a permute for lane ^ 32 (64-bit
-// values move as two 32-bit halves).  Every lane of the wavefront must be
-// active.
-__device__ __forceinline__ float xor16_mov(float v)
-{   // ds_swizzle bit mode within 32 lanes: and 0x1f, or 0, xor 0x10
-    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
-}
-__device__ __forceinline__ double xor16_mov(double v)
-{
-    const int2 h = __builtin_bit_cast(int2, v);
-    return __builtin_bit_cast(double, int2{__builtin_amdgcn_ds_swizzle(h.x, 0x401F),
-                                           __builtin_amdgcn_ds_swizzle(h.y, 0x401F)});
-}
-__device__ __forceinline__ float xor32_mov(float v, int addr)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double xor32_mov(double v, int addr)
-{
-    const int2 h = __builtin_bit_cast(int2, v);
-    return __builtin_bit_cast(double, int2{__builtin_amdgcn_ds_bpermute(addr, h.x),
-                                           __builtin_amdgcn_ds_bpermute(addr, h.y)});
-}
-
 // Sum over the lanes congruent modulo S (S = 1 .. 32); every lane receives
 // the sum of its class.  Within a row of 16 the class is rotated through
 // (row_ror by 8, 4, .., S), then lane ^ 16 and lane ^ 32 join the rows.
