@@ -58,7 +58,10 @@ struct CollArgs {
 
 __global__ void __launch_bounds__(CT) k_coll_blocks(CollArgs A)
 {
-    __shared__ double px[TMAX][9];           // vertices of the column triangles (mesh order)
+    // per column triangle: its vertices (mesh order), or with rules of up to
+    // three points the rule's points (the Duffy case then reads the vertices
+    // from xyz)
+    __shared__ double px[TMAX][9];
     __shared__ double jac[TMAX];             // 2 |t| / (4 pi)
     __shared__ int tv[TMAX][3];              // their vertex ids
     __shared__ int lst[BSET][DEG];           // (triangle << 2 | corner) of column vertex j, ascending
@@ -82,9 +85,10 @@ __global__ void __launch_bounds__(CT) k_coll_blocks(CollArgs A)
     const int32_t *ctri = A.m_tri + (int64_t)cs * A.cap;
     const int32_t *cloc = A.m_loc + (int64_t)cs * A.cap * 3;
     constexpr double inv4pi = 0.07957747154594767;
+    const bool pts = A.R.np <= 3;
     for (int t = tid; t < nS; t += CT) {
         const int tr = ctri[t];
-        double *X = px[t];
+        double X[9];
         for (int c = 0; c < 3; ++c) {
             const int v = A.tri[3 * tr + c];
             tv[t][c] = v;
@@ -94,6 +98,13 @@ __global__ void __launch_bounds__(CT) k_coll_blocks(CollArgs A)
         const double bx = X[6] - X[0], by = X[7] - X[1], bz = X[8] - X[2];
         const double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
         jac[t] = sqrt(cx * cx + cy * cy + cz * cz) * inv4pi;
+        if (pts) {
+            for (int p = 0; p < A.R.np; ++p)
+                for (int d = 0; d < 3; ++d)
+                    px[t][3 * p + d] = X[d] + A.R.s1[p] * (X[3 + d] - X[d]) + A.R.s2[p] * (X[6 + d] - X[3 + d]);
+        } else {
+            for (int e = 0; e < 9; ++e) px[t][e] = X[e];
+        }
     }
     for (int i = tid; i < n; i += CT) {
         const int v = A.set_vtx[A.set_off[rs] + i];
@@ -124,16 +135,15 @@ __global__ void __launch_bounds__(CT) k_coll_blocks(CollArgs A)
         double acc = 0.0;
         for (int l = 0; l < lc[j]; ++l) {
             const int t = lst[j][l] >> 2, c = lst[j][l] & 3;
-            const double *X = px[t];
             const int ks = tv[t][0] == vi ? 0 : (tv[t][1] == vi ? 1 : (tv[t][2] == vi ? 2 : -1));
             double s = 0.0;
             if (ks >= 0) {
                 // Duffy at corner ks: d(v) = (P_a - P_k) + v (P_b - P_a)
                 const int ka = ks == 2 ? 0 : ks + 1, kb = ka == 2 ? 0 : ka + 1;
-                const double e0 = X[3 * ka + 0] - X[3 * ks + 0], e1 = X[3 * ka + 1] - X[3 * ks + 1],
-                             e2 = X[3 * ka + 2] - X[3 * ks + 2];
-                const double f0 = X[3 * kb + 0] - X[3 * ka + 0], f1 = X[3 * kb + 1] - X[3 * ka + 1],
-                             f2 = X[3 * kb + 2] - X[3 * ka + 2];
+                auto vtx = [&](int k) { return pts ? A.xyz + 3 * (size_t)tv[t][k] : (const double *)px[t] + 3 * k; };
+                const double *Pk = vtx(ks), *Pa = vtx(ka), *Pb = vtx(kb);
+                const double e0 = Pa[0] - Pk[0], e1 = Pa[1] - Pk[1], e2 = Pa[2] - Pk[2];
+                const double f0 = Pb[0] - Pa[0], f1 = Pb[1] - Pa[1], f2 = Pb[2] - Pa[2];
                 const int role = c == ks ? 0 : (c == ka ? 1 : 2);
                 for (int q = 0; q < R.nq; ++q) {
                     const double v = R.v[q];
@@ -141,7 +151,13 @@ __global__ void __launch_bounds__(CT) k_coll_blocks(CollArgs A)
                     const double om = role == 0 ? 0.5 : (role == 1 ? 0.5 * (1.0 - v) : 0.5 * v);
                     s += R.wv[q] * om * rsq<double>(d0 * d0 + d1 * d1 + d2 * d2);
                 }
+            } else if (pts) {
+                for (int p = 0; p < R.np; ++p) {
+                    const double d0 = x0 - px[t][3 * p], d1 = x1 - px[t][3 * p + 1], d2 = x2 - px[t][3 * p + 2];
+                    s += R.wl[p][c] * rsq<double>(d0 * d0 + d1 * d1 + d2 * d2);
+                }
             } else {
+                const double *X = px[t];
                 for (int p = 0; p < R.np; ++p) {
                     const double a1 = R.s1[p], a2 = R.s2[p];
                     const double y0 = X[0] + a1 * (X[3] - X[0]) + a2 * (X[6] - X[3]);
